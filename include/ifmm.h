@@ -1,0 +1,144 @@
+/*
+ * ifmm.h -- C-ABI of the MI355X (gfx950) Inverse Fast Multipole Method.
+ *
+ * The library factors and solves A x = b where A is an FMM matrix on 2D
+ * points: A_ij = K(|x_i - x_j|) for i != j, with the far field represented
+ * through nested Chebyshev interpolation (the "FMM matrix" of Ambikasaran &
+ * Darve, Section 2.2), and a diagonal chosen by a rule below.  The problem
+ * statement follows Section 1 (solve A x = b to a tolerance eps, A an FMM
+ * matrix) and the benchmark equation of Section 5 (sigma_i + sum_{j != i}
+ * K sigma_j = f_i is the special case diag_mode = CONST, c0 = 1).
+ *
+ * The factorisation is Algorithm 1 (elimination of the extended sparse system
+ * level by level, with fill between well-separated clusters recompressed into
+ * the M2L / P2M / L2P operators) and the solve is Algorithm 2 (back
+ * substitution in reverse order); factor and solve are decoupled (end of
+ * Section 4.2.2), so one factor serves many right-hand sides.
+ *
+ * Conventions
+ *  - All arrays passed in or out are DEVICE pointers on the current HIP
+ *    device; the caller owns them (the library never frees them).
+ *  - points: [n][2] row-major (x0, y0, x1, y1, ...), FP64.
+ *  - b, x, y: [nrhs][n] column-major (leading dimension n), FP64, in the
+ *    caller's point order.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *    ifmm_factor and ifmm_solve synchronise that stream before returning.
+ *  - Every call returns a status; no exception crosses the ABI.  On error the
+ *    outputs are left untouched except where stated.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef IFMM_H_
+#define IFMM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifmm_plan* ifmm_t;
+
+typedef enum {
+  IFMM_OK = 0,
+  IFMM_EINVAL = 1,     /* invalid argument (sizes, NaN/Inf, points outside the box, duplicates) */
+  IFMM_ENOMEM = 2,     /* device or pinned-host allocation failed */
+  IFMM_ESINGULAR = 3,  /* a pivot block was exactly singular */
+  IFMM_ENOTCONV = 4,   /* refinement did not reach refine_tol (x holds the best iterate) */
+  IFMM_EDEVICE = 5     /* a HIP runtime error */
+} ifmm_status;
+
+typedef enum {
+  IFMM_K_INV_R = 0, /* K(r) = 1/r   (Section 1, Green's functions table) */
+  IFMM_K_EXP = 1    /* K(r) = exp(-r/ell) (Section 1, covariance functions table) */
+} ifmm_kernel_kind;
+
+typedef enum {
+  IFMM_DIAG_ROWSUM = 0, /* A_ii = c0 + sum_{j != i} A_ij over the FMM matrix */
+  IFMM_DIAG_CONST = 1   /* A_ii = c0 (e.g. K(0) + sigma^2 for exp, 1 for Section 5) */
+} ifmm_diag_mode;
+
+typedef struct {
+  int kind;       /* ifmm_kernel_kind */
+  double ell;     /* length scale of IFMM_K_EXP (> 0) */
+  int diag_mode;  /* ifmm_diag_mode */
+  double c0;
+} ifmm_kernel;
+
+typedef struct {
+  int r_max;           /* rank cap of the compressed bases; 0 = 2 p^2; must be >= p^2, <= 128 */
+  double refine_tol;   /* 0: plain solve; > 0: FP64 iterative refinement with the FMM product
+                          until ||b - A x|| / ||b|| <= refine_tol for every column */
+  int refine_maxit;    /* refinement sweeps (0 = 30) */
+  double box_lo[2];    /* root box [lo, lo + size]^2 containing every point */
+  double box_size;     /* 0 = unit square [0,1]^2 */
+} ifmm_options;
+
+typedef struct {
+  int iterations;          /* refinement sweeps done (0 = plain solve) */
+  double residual;         /* final max over columns of ||b - A x|| / ||b|| (when refining) */
+  double history[32];      /* residual after the direct solve and after each sweep */
+  double solve_ms;         /* wall time of this call */
+} ifmm_solve_info;
+
+typedef struct {
+  int64_t n;
+  int kappa;               /* leaf level (levels 2..kappa are eliminated) */
+  int p;                   /* Chebyshev nodes per dimension */
+  int max_rank;            /* largest rank met (r_m of Section 5) */
+  int level_max_rank[16];
+  double level_mean_rank[16];
+  int top_size;            /* size of the dense level-2 multipole system */
+  double assembly_ms;      /* t_a: tree, operators, near field, weights */
+  double factor_ms;        /* t_f: Algorithm 1 */
+  double last_solve_ms;    /* t_s of the last ifmm_solve (including refinement) */
+  double factor_bytes;     /* device bytes held by the factor */
+  double factor_flops;     /* counted FP64 flops of the factorisation */
+} ifmm_stats_t;
+
+/*
+ * Factor the FMM matrix of `n` points (Algorithm 1).
+ *   points     device [n][2], inside the root box (default [0,1]^2)
+ *   k          kernel and diagonal rule
+ *   eps        relative truncation tolerance of the fill compression (>= 0;
+ *              eps = 0 keeps every direction up to the rank cap)
+ *   leaf_size  mean leaf occupancy bound: depth = max(2, ceil(log4(n / leaf_size)))
+ *   rank       p^2, the Chebyshev interpolation rank, 1 <= p <= 8
+ *   opt        NULL for defaults
+ *   out        receives the handle (owns all factor memory; free with ifmm_destroy)
+ * Errors: EINVAL (n < 16, rank not a perfect square, p > 8, leaf_size < 1,
+ * eps < 0 or NaN, kernel parameters, non-finite or out-of-box or duplicate
+ * points), ENOMEM, ESINGULAR, EDEVICE.
+ */
+ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, double eps,
+                        int leaf_size, int rank, const ifmm_options* opt, void* stream,
+                        ifmm_t* out);
+
+/*
+ * Solve A x = b for nrhs columns (Algorithm 2, optionally refined).
+ *   b, x  device [nrhs][n]; x may not alias b.
+ *   info  optional (host), filled on OK and on ENOTCONV.
+ * Errors: EINVAL (null handle/pointers, nrhs < 1 or > 64), ENOTCONV (x holds
+ * the best iterate), ENOMEM, EDEVICE.
+ */
+ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* stream,
+                       ifmm_solve_info* info);
+
+/* y = A x with the FMM product in FP64 (the matrix that is factored). */
+ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* stream);
+
+/* Copy the diagonal of A (caller's point order) into device array d[n]. */
+ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream);
+
+/* Statistics of the factorisation (host struct). */
+ifmm_status ifmm_stats(ifmm_t h, ifmm_stats_t* s);
+
+/* Final rank of every cluster of `level` (Morton order) into host out[4^level]. */
+ifmm_status ifmm_ranks(ifmm_t h, int level, int* out, int count);
+
+void ifmm_destroy(ifmm_t h);
+const char* ifmm_status_string(ifmm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFMM_H_ */

@@ -1,0 +1,315 @@
+// Kernel-function and Chebyshev operators of the FMM matrix on gfx950 (FP64):
+// leaf interpolation matrices (L2P / P2M), near-field blocks (P2P), the M2L
+// node-to-node kernel tables, and the passes of the FMM product used for the
+// row-sum diagonal and for refinement residuals.  Points are in tree order.
+#include "ifmm_internal.h"
+
+namespace ifmm {
+
+namespace {
+
+__device__ inline double kval(KernelFn kf, double r) {
+  return kf.kind == 0 ? 1.0 / r : exp(-r / kf.ell);
+}
+
+__device__ inline double cheb_node(int p, int m) {
+  return cos((2.0 * m + 1.0) * M_PI / (2.0 * p));  // m = 0..p-1
+}
+
+// l_m(s) for all m = 0..p-1.
+__device__ inline void lagrange_all(int p, double s, double* out) {
+  double t[kMaxP];
+  for (int m = 0; m < p; ++m) t[m] = cheb_node(p, m);
+  for (int m = 0; m < p; ++m) {
+    double v = 1.0;
+    for (int k = 0; k < p; ++k)
+      if (k != m) v *= (s - t[k]) / (t[m] - t[k]);
+    out[m] = v;
+  }
+}
+
+__device__ inline void leaf_box(int i, int kappa, double lox, double loy, double size,
+                                double& cx, double& cy, double& h) {
+  const double w = size / (double)(1 << kappa);
+  cx = lox + (demorton_x(i) + 0.5) * w;
+  cy = loy + (demorton_y(i) + 0.5) * w;
+  h = 0.5 * w;
+}
+
+__global__ void k_leaf_interp(const double* __restrict__ pts, const int* __restrict__ start,
+                              const int* __restrict__ cnt, int kappa, double lox, double loy,
+                              double size, int p, double* dst, size_t stride, int ld) {
+  const int i = blockIdx.x;
+  const int n = cnt[i];
+  double cx, cy, h;
+  leaf_box(i, kappa, lox, loy, size, cx, cy, h);
+  double* S = dst + (size_t)i * stride;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    const double x = pts[2 * (start[i] + a)], y = pts[2 * (start[i] + a) + 1];
+    double lx[kMaxP], ly[kMaxP];
+    lagrange_all(p, (x - cx) / h, lx);
+    lagrange_all(p, (y - cy) / h, ly);
+    for (int mx = 0; mx < p; ++mx)
+      for (int my = 0; my < p; ++my) S[a + (size_t)(mx * p + my) * ld] = lx[mx] * ly[my];
+  }
+}
+
+__global__ void k_near(const double* __restrict__ pts, const int* __restrict__ start,
+                       const int* __restrict__ cnt, const int* __restrict__ nbr9, KernelFn kf,
+                       const double* __restrict__ d, double* P, size_t slot_stride, int ld) {
+  const int i = blockIdx.x, s = blockIdx.y;
+  const int j = nbr9[i * 9 + s];
+  if (j < 0) return;
+  const int ni = cnt[i], nj = cnt[j];
+  double* B = P + ((size_t)i * 9 + s) * slot_stride;
+  const int si = start[i], sj = start[j];
+  for (int e = threadIdx.x; e < ni * nj; e += blockDim.x) {
+    const int a = e % ni, b = e / ni;
+    double v;
+    if (s == 4 && a == b) {
+      v = d[si + a];
+    } else {
+      const double dx = pts[2 * (si + a)] - pts[2 * (sj + b)];
+      const double dy = pts[2 * (si + a) + 1] - pts[2 * (sj + b) + 1];
+      v = kval(kf, sqrt(dx * dx + dy * dy));
+    }
+    B[a + (size_t)b * ld] = v;
+  }
+}
+
+__global__ void k_m2l_table(KernelFn kf, int p, double h, double* dst) {
+  const int off = blockIdx.x;  // 0..48
+  const int dx = off / 7 - 3, dy = off % 7 - 3;
+  const int p2 = p * p;
+  double* T = dst + (size_t)off * p2 * p2;
+  for (int e = threadIdx.x; e < p2 * p2; e += blockDim.x) {
+    const int m = e % p2, n = e / p2;
+    const double xm = h * cheb_node(p, m / p), ym = h * cheb_node(p, m % p);
+    const double xn = 2.0 * h * dx + h * cheb_node(p, n / p), yn = 2.0 * h * dy + h * cheb_node(p, n % p);
+    const double ex = xm - xn, ey = ym - yn;
+    T[m + (size_t)n * p2] = (dx == 0 && dy == 0 && m == n) ? 0.0 : kval(kf, sqrt(ex * ex + ey * ey));
+  }
+}
+
+// ---------------------------------------------------------------- FMM passes
+// Multipole/local node values are stored [cluster][rhs][p^2].
+__global__ void k_p2m(const double* __restrict__ pts, const int* __restrict__ start,
+                      const int* __restrict__ cnt, int kappa, double lox, double loy, double size,
+                      int p, const double* __restrict__ x, int ldx, int nrhs, double* W) {
+  const int i = blockIdx.x;
+  const int p2 = p * p;
+  const int n = cnt[i];
+  double cx, cy, h;
+  leaf_box(i, kappa, lox, loy, size, cx, cy, h);
+  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
+    const int m = e % p2, r = e / p2;
+    const int mx = m / p, my = m % p;
+    double acc = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const int g = start[i] + a;
+      double lx[kMaxP], ly[kMaxP];
+      lagrange_all(p, (pts[2 * g] - cx) / h, lx);
+      lagrange_all(p, (pts[2 * g + 1] - cy) / h, ly);
+      acc = fma(lx[mx] * ly[my], x[g + (size_t)r * ldx], acc);
+    }
+    W[((size_t)i * nrhs + r) * p2 + m] = acc;
+  }
+}
+
+__global__ void k_m2m(const double* __restrict__ E, int p, const double* __restrict__ Wc,
+                      double* Wp, int nrhs) {
+  const int P = blockIdx.x;
+  const int p2 = p * p;
+  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
+    const int m = e % p2, r = e / p2;
+    double acc = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const double* Ec = E + (size_t)c * p2 * p2;
+      const double* w = Wc + ((size_t)(4 * P + c) * nrhs + r) * p2;
+      for (int mm = 0; mm < p2; ++mm) acc = fma(Ec[mm + (size_t)m * p2], w[mm], acc);
+    }
+    Wp[((size_t)P * nrhs + r) * p2 + m] = acc;
+  }
+}
+
+__global__ void k_m2l(int p, int k, const double* __restrict__ table, const double* __restrict__ W,
+                      double* G, int nrhs) {
+  const int i = blockIdx.x;
+  const int p2 = p * p;
+  const int ix = demorton_x(i), iy = demorton_y(i);
+  const int nside = 1 << k;
+  const int x0 = 2 * (ix >> 1) - 2, y0 = 2 * (iy >> 1) - 2;
+  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
+    const int m = e % p2, r = e / p2;
+    double acc = 0.0;
+    for (int sx = 0; sx < 6; ++sx)
+      for (int sy = 0; sy < 6; ++sy) {
+        const int jx = x0 + sx, jy = y0 + sy;
+        if (jx < 0 || jy < 0 || jx >= nside || jy >= nside) continue;
+        const int dx = jx - ix, dy = jy - iy;
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+        const int l = morton2(jx, jy);
+        const double* T = table + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
+        const double* w = W + ((size_t)l * nrhs + r) * p2;
+        for (int n = 0; n < p2; ++n) acc = fma(T[m + (size_t)n * p2], w[n], acc);
+      }
+    G[((size_t)i * nrhs + r) * p2 + m] = acc;
+  }
+}
+
+__global__ void k_l2l(const double* __restrict__ E, int p, const double* __restrict__ Gp, double* Gc,
+                      int nrhs) {
+  const int c = blockIdx.x;  // child index
+  const int P = c >> 2, q = c & 3;
+  const int p2 = p * p;
+  const double* Ec = E + (size_t)q * p2 * p2;
+  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
+    const int mm = e % p2, r = e / p2;
+    const double* g = Gp + ((size_t)P * nrhs + r) * p2;
+    double acc = 0.0;
+    for (int m = 0; m < p2; ++m) acc = fma(Ec[mm + (size_t)m * p2], g[m], acc);
+    Gc[((size_t)c * nrhs + r) * p2 + mm] += acc;
+  }
+}
+
+__global__ void k_l2p_p2p(const double* __restrict__ pts, const int* __restrict__ start,
+                          const int* __restrict__ cnt, const int* __restrict__ nbr9, int kappa,
+                          double lox, double loy, double size, int p, KernelFn kf,
+                          const double* __restrict__ G, const double* __restrict__ x, int ldx,
+                          const double* __restrict__ d, double* y, int ldy, int nrhs) {
+  const int i = blockIdx.x;
+  const int p2 = p * p;
+  const int n = cnt[i];
+  double cx, cy, h;
+  leaf_box(i, kappa, lox, loy, size, cx, cy, h);
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    const int g = start[i] + a;
+    const double xa = pts[2 * g], ya = pts[2 * g + 1];
+    double lx[kMaxP], ly[kMaxP];
+    lagrange_all(p, (xa - cx) / h, lx);
+    lagrange_all(p, (ya - cy) / h, ly);
+    for (int r = 0; r < nrhs; ++r) {
+      const double* gl = G + ((size_t)i * nrhs + r) * p2;
+      double acc = 0.0;
+      for (int m = 0; m < p2; ++m) acc = fma(lx[m / p] * ly[m % p], gl[m], acc);
+      for (int s = 0; s < 9; ++s) {
+        const int j = nbr9[i * 9 + s];
+        if (j < 0) continue;
+        for (int b = 0; b < cnt[j]; ++b) {
+          const int gb = start[j] + b;
+          if (gb == g) continue;
+          const double dx = xa - pts[2 * gb], dy = ya - pts[2 * gb + 1];
+          acc = fma(kval(kf, sqrt(dx * dx + dy * dy)), x[gb + (size_t)r * ldx], acc);
+        }
+      }
+      if (d) acc = fma(d[g], x[g + (size_t)r * ldx], acc);
+      y[g + (size_t)r * ldy] = acc;
+    }
+  }
+}
+
+__global__ void k_gather_rows(const double* __restrict__ src, int ld_src, const int* __restrict__ idx,
+                              int n, int nrhs, double* dst, int ld_dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * nrhs) return;
+  const int i = (int)(e % n), r = (int)(e / n);
+  dst[i + (size_t)r * ld_dst] = src[idx[i] + (size_t)r * ld_src];
+}
+
+__global__ void k_scatter_rows(const double* __restrict__ src, int ld_src, const int* __restrict__ idx,
+                               int n, int nrhs, double* dst, int ld_dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * nrhs) return;
+  const int i = (int)(e % n), r = (int)(e / n);
+  dst[idx[i] + (size_t)r * ld_dst] = src[i + (size_t)r * ld_src];
+}
+
+__global__ void k_colnorm2(const double* __restrict__ x, int n, int nrhs, int ld, double* out) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = x[i + (size_t)r * ld];
+    s += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out + r, red[0] + red[1] + red[2] + red[3]);
+}
+
+}  // namespace
+
+void launch_colnorm2(const double* x, int n, int nrhs, int ld, double* out, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_colnorm2, dim3(nb, nrhs), dim3(256), 0, s, x, n, nrhs, ld, out);
+}
+
+void launch_leaf_interp(const double* pts, const int* leaf_start, const int* leaf_n, int nleaf,
+                        int kappa, double lox, double loy, double size, int p, double* dst,
+                        size_t stride, int ld, int max_n, hipStream_t s) {
+  (void)max_n;
+  hipLaunchKernelGGL(k_leaf_interp, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, kappa,
+                     lox, loy, size, p, dst, stride, ld);
+}
+
+void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
+                       const int* nbr9, int nleaf, KernelFn kf, const double* d, double* P,
+                       size_t slot_stride, int ld, int max_n, hipStream_t s) {
+  (void)max_n;
+  hipLaunchKernelGGL(k_near, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
+                     d, P, slot_stride, ld);
+}
+
+void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_m2l_table, dim3(49), dim3(256), 0, s, kf, p, h, dst);
+}
+
+void launch_p2m(const double* pts, const int* leaf_start, const int* leaf_n, int nleaf, int kappa,
+                double lox, double loy, double size, int p, const double* x, int ldx, int nrhs,
+                double* W, hipStream_t s) {
+  hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, kappa, lox, loy,
+                     size, p, x, ldx, nrhs, W);
+}
+
+void launch_m2m(const double* E, int p, int nc_parent, const double* Wc, double* Wp, int nrhs,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_m2m, dim3(nc_parent), dim3(64), 0, s, E, p, Wc, Wp, nrhs);
+}
+
+void launch_m2l(int p, int k, const double* table, const double* W, double* G, int nrhs,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_m2l, dim3(1 << (2 * k)), dim3(64), 0, s, p, k, table, W, G, nrhs);
+}
+
+void launch_l2l(const double* E, int p, int nc_parent, const double* Gp, double* Gc, int nrhs,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_l2l, dim3(4 * nc_parent), dim3(64), 0, s, E, p, Gp, Gc, nrhs);
+}
+
+void launch_l2p_p2p(const double* pts, const int* leaf_start, const int* leaf_n, const int* nbr9,
+                    int nleaf, int kappa, double lox, double loy, double size, int p, KernelFn kf,
+                    const double* G, const double* x, int ldx, const double* d, double* y,
+                    int ldy, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_l2p_p2p, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, nbr9, kappa,
+                     lox, loy, size, p, kf, G, x, ldx, d, y, ldy, nrhs);
+}
+
+void launch_gather_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
+                        double* dst, int ld_dst, hipStream_t s) {
+  const size_t tot = (size_t)n * nrhs;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src,
+                     ld_src, idx, n, nrhs, dst, ld_dst);
+}
+
+void launch_scatter_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
+                         double* dst, int ld_dst, hipStream_t s) {
+  const size_t tot = (size_t)n * nrhs;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src,
+                     ld_src, idx, n, nrhs, dst, ld_dst);
+}
+
+}  // namespace ifmm

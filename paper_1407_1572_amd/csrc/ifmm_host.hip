@@ -1,0 +1,1533 @@
+// Host orchestration of the IFMM on one MI355X: tree and cluster lists,
+// assembly of the extended sparse system, Algorithm 1 (elimination with
+// compression of well-separated fill), Algorithm 2 (back substitution), the
+// FMM product and FP64 iterative refinement, behind the C-ABI of ifmm.h.
+//
+// The host plans integer work only (which block feeds which batched kernel);
+// every floating-point step runs in the gfx950 kernels.  Per colour phase the
+// host reads back the new ranks once (they decide the block shapes of the
+// next steps) -- that is the only synchronisation inside the factorisation.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ifmm.h"
+#include "ifmm_internal.h"
+
+using namespace ifmm;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+};
+struct NoMem {};
+struct BadArg {};
+
+#define HIP_OK(x)                                      \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) throw HipError{e_};          \
+  } while (0)
+
+template <class T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw NoMem{};
+  }
+  return static_cast<T*>(p);
+}
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+inline int rup(int a, int b) { return (a + b - 1) / b * b; }
+
+// ------------------------------------------------------------ descriptor stages
+enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_INV };
+struct Op {
+  OpType t;
+  size_t off, off2;
+  int count, a, b;
+};
+
+struct Stage {
+  std::vector<char> blob;
+  std::vector<Op> ops;
+  double flops = 0.0;
+  size_t push(const void* p, size_t n) {
+    size_t off = (blob.size() + 63) & ~size_t(63);
+    blob.resize(off + n);
+    std::memcpy(blob.data() + off, p, n);
+    return off;
+  }
+  void gemm(const std::vector<GemmDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0, nn = 0;
+    for (const auto& d : v) {
+      mm = std::max(mm, d.M);
+      nn = std::max(nn, d.N);
+      flops += 2.0 * d.M * d.N * d.K;
+    }
+    ops.push_back({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn});
+  }
+  void add(const std::vector<AddDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0, nn = 0;
+    for (const auto& d : v) {
+      mm = std::max(mm, d.M);
+      nn = std::max(nn, d.N);
+    }
+    ops.push_back({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn});
+  }
+  void xform(const std::vector<XformDesc>& v) {
+    if (v.empty()) return;
+    for (const auto& d : v)
+      flops += 2.0 * (d.T ? d.r_new * d.r_old * d.c_old : 0) +
+               2.0 * (d.S ? (d.T ? d.r_new : d.r_old) * d.c_old * d.c_new : 0);
+    ops.push_back({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0});
+  }
+  void qr(const std::vector<QrDesc>& v) {
+    if (v.empty()) return;
+    for (const auto& d : v) flops += 4.0 * d.n * d.m * std::min(d.n, d.m);
+    ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0});
+  }
+  void rrqr(const std::vector<RrqrDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0;
+    for (const auto& d : v) {
+      mm = std::max(mm, d.m);
+      flops += 4.0 * d.n * d.m * std::min(std::min(d.n, d.m), d.kmax);
+    }
+    ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), 0, (int)v.size(), mm, 0});
+  }
+  void formq(const std::vector<FormQDesc>& v) {
+    if (v.empty()) return;
+    for (const auto& d : v) flops += 4.0 * d.n * d.r * d.kk;
+    ops.push_back({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0});
+  }
+  void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
+    if (v.empty()) return;
+    int rr = 0;
+    for (const auto& d : v) rr = std::max(rr, d.r);
+    for (const auto& x : b) flops += 2.0 * x.rows * rr * rr;
+    size_t o1 = push(v.data(), v.size() * sizeof(StackQrDesc));
+    size_t o2 = push(b.data(), std::max<size_t>(1, b.size()) * sizeof(BlkRef));
+    ops.push_back({OP_STACKQR, o1, o2, (int)v.size(), rr, 0});
+  }
+  void inv(const std::vector<InvDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0;
+    for (const auto& d : v) {
+      mm = std::max(mm, d.m);
+      flops += 2.0 * d.m * d.m * (double)d.m;
+    }
+    ops.push_back({OP_INV, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0});
+  }
+  bool empty() const { return ops.empty(); }
+  void clear() {
+    blob.clear();
+    ops.clear();
+    flops = 0.0;
+  }
+};
+
+// Pinned host + device buffers for descriptor upload, double-buffered.
+struct Arena {
+  char* h[2] = {nullptr, nullptr};
+  char* d[2] = {nullptr, nullptr};
+  size_t cap[2] = {0, 0};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int cur = 0;
+  void init() {
+    for (int i = 0; i < 2; ++i) HIP_OK(hipEventCreate(&ev[i]));
+  }
+  void release() {
+    for (int i = 0; i < 2; ++i) {
+      if (h[i]) (void)hipHostFree(h[i]);
+      if (d[i]) (void)hipFree(d[i]);
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      h[i] = d[i] = nullptr;
+      ev[i] = nullptr;
+    }
+  }
+  char* upload(const std::vector<char>& blob, hipStream_t s) {
+    cur ^= 1;
+    const size_t need = blob.size();
+    if (need > cap[cur]) {
+      HIP_OK(hipStreamSynchronize(s));
+      if (h[cur]) (void)hipHostFree(h[cur]);
+      if (d[cur]) (void)hipFree(d[cur]);
+      h[cur] = nullptr;
+      d[cur] = nullptr;
+      size_t c = std::max(need, 2 * cap[cur]);
+      c = std::max<size_t>(c, 1 << 20);
+      if (hipHostMalloc(reinterpret_cast<void**>(&h[cur]), c) != hipSuccess) {
+        (void)hipGetLastError();
+        cap[cur] = 0;
+        throw NoMem{};
+      }
+      d[cur] = dalloc<char>(c);
+      cap[cur] = c;
+    } else {
+      HIP_OK(hipEventSynchronize(ev[cur]));
+    }
+    std::memcpy(h[cur], blob.data(), need);
+    HIP_OK(hipMemcpyAsync(d[cur], h[cur], need, hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(ev[cur], s));
+    return d[cur];
+  }
+};
+
+// Grow-only device workspace.
+struct Buf {
+  double* p = nullptr;
+  size_t n = 0;
+  double* need(size_t m, hipStream_t s) {
+    if (m > n) {
+      HIP_OK(hipStreamSynchronize(s));
+      dfree(p);
+      p = dalloc<double>(m);
+      n = m;
+    }
+    return p;
+  }
+  void release() {
+    dfree(p);
+    n = 0;
+  }
+};
+
+// ------------------------------------------------------------ geometry helpers
+inline int s9_dx(int s) { return s / 3 - 1; }
+inline int s9_dy(int s) { return s % 3 - 1; }
+inline int s9_of(int dx, int dy) { return (dx + 1) * 3 + (dy + 1); }
+inline bool pos_adjacent(int sa, int sb) {
+  return std::abs(s9_dx(sa) - s9_dx(sb)) <= 1 && std::abs(s9_dy(sa) - s9_dy(sb)) <= 1;
+}
+inline int slot36(int a, int b) {
+  return win_slot(demorton_x(a), demorton_y(a), demorton_x(b), demorton_y(b));
+}
+inline bool in_ilist(int a, int b) {
+  const int ax = demorton_x(a), ay = demorton_y(a), bx = demorton_x(b), by = demorton_y(b);
+  if (win_slot(ax, ay, bx, by) < 0) return false;
+  return std::abs(ax - bx) > 1 || std::abs(ay - by) > 1;
+}
+// compact index of an ordered pair of 3x3 positions at Chebyshev distance 2
+struct PairTable {
+  int idx[9][9];
+  int count = 0;
+  PairTable() {
+    for (int a = 0; a < 9; ++a)
+      for (int b = 0; b < 9; ++b) {
+        const int d = std::max(std::abs(s9_dx(a) - s9_dx(b)), std::abs(s9_dy(a) - s9_dy(b)));
+        idx[a][b] = d == 2 ? count++ : -1;
+      }
+  }
+};
+const PairTable kPairs;
+
+// ------------------------------------------------------------ Chebyshev (host)
+double cheb_t(int p, int m) { return std::cos((2.0 * m + 1.0) * M_PI / (2.0 * p)); }
+double lagr(int p, int m, double s) {
+  double v = 1.0;
+  for (int k = 0; k < p; ++k)
+    if (k != m) v *= (s - cheb_t(p, k)) / (cheb_t(p, m) - cheb_t(p, k));
+  return v;
+}
+// E_c: rows child nodes, columns parent nodes (p^2 x p^2, column-major).
+std::vector<double> transfer_host(int p) {
+  const int p2 = p * p;
+  std::vector<double> E(4 * p2 * p2);
+  for (int c = 0; c < 4; ++c) {
+    const double ox = (c & 1) ? 0.5 : -0.5, oy = (c >> 1) ? 0.5 : -0.5;
+    for (int mc = 0; mc < p2; ++mc) {
+      const double sx = ox + 0.5 * cheb_t(p, mc / p), sy = oy + 0.5 * cheb_t(p, mc % p);
+      for (int mp = 0; mp < p2; ++mp)
+        E[(size_t)c * p2 * p2 + mc + (size_t)mp * p2] = lagr(p, mp / p, sx) * lagr(p, mp % p, sy);
+    }
+  }
+  return E;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// ------------------------------------------------------------------- levels
+struct Level {
+  int k = 0, nside = 0, nc = 0;
+  std::vector<int> n, r, colour, nbr9, choff;  // choff: [nc*4] offsets of children's multipoles
+  int npad = 0, rpad = 0, mpad = 0;
+  size_t sP = 0, sQ = 0, sL = 0, sM = 0, sU = 0, sUP = 0, sD = 0;
+  double *P = nullptr, *Qm = nullptr, *L = nullptr, *M = nullptr, *U = nullptr, *V = nullptr,
+         *UP = nullptr, *VP = nullptr, *Dinv = nullptr, *Om = nullptr, *Omp = nullptr;
+  double* Pb(int i, int s) const { return P + ((size_t)i * 9 + s) * sP; }
+  double* Qb(int i, int s) const { return Qm + ((size_t)i * 9 + s) * sQ; }
+  double* Lb(int i, int s) const { return L + ((size_t)i * 9 + s) * sL; }
+  double* Mb(int i, int s) const { return M + ((size_t)i * 36 + s) * sM; }
+  double* Ub(int i) const { return U + (size_t)i * sU; }
+  double* Vb(int i) const { return V + (size_t)i * sU; }
+  double* UPb(int i) const { return UP + (size_t)i * sUP; }
+  double* VPb(int i) const { return VP + (size_t)i * sUP; }
+  double* Db(int i) const { return Dinv + (size_t)i * sD; }
+  double* Omb(int i) const { return Om + (size_t)i * sUP; }
+  double* Ompb(int i) const { return Omp + (size_t)i * sUP; }
+  void set_pads(int np) {
+    npad = np;
+    mpad = npad + rpad;
+    sP = (size_t)npad * npad;
+    sQ = (size_t)npad * rpad;
+    sL = (size_t)rpad * npad;
+    sM = (size_t)rpad * rpad;
+    sU = (size_t)npad * rpad;
+    sUP = (size_t)rpad * rpad;
+    sD = (size_t)mpad * mpad;
+  }
+  void free_work() {
+    dfree(M);
+    dfree(U);
+    dfree(V);
+    dfree(UP);
+    dfree(VP);
+    dfree(Om);
+    dfree(Omp);
+  }
+  void free_all() {
+    free_work();
+    dfree(P);
+    dfree(Qm);
+    dfree(L);
+    dfree(Dinv);
+  }
+};
+
+// A unit of the 3x3 neighbourhood of an eliminated cluster.
+struct UnitH {
+  int cl = -1, kind = 0, size = 0, off = 0;  // kind 1: particles, 2: multipoles
+};
+struct Elim {
+  int i, ni, ri, m;
+  std::array<UnitH, 9> u;
+};
+
+}  // namespace
+
+struct ifmm_plan {
+  hipStream_t s = nullptr;
+  int64_t N = 0;
+  int kappa = 0, p = 0, p2 = 0, leaf = 0, r_cap = 0, rpad = 0;
+  KernelFn kf{};
+  int diag_mode = 0;
+  double c0 = 0.0, eps = 0.0;
+  double lox = 0.0, loy = 0.0, size = 1.0;
+  double refine_tol = 0.0;
+  int refine_maxit = 30;
+  std::vector<int> perm, leaf_start, leaf_n;
+  double* d_pts = nullptr;
+  int *d_perm = nullptr, *d_leaf_start = nullptr, *d_leaf_n = nullptr, *d_nbr9_leaf = nullptr;
+  double* d_diag = nullptr;
+  double* d_E = nullptr;
+  std::vector<double*> d_table;
+  std::vector<Level> lv;
+  std::vector<std::vector<std::vector<Elim>>> plan;  // [k][colour] eliminations in order
+  // top
+  std::vector<int> top_ids, top_off;
+  int top_m = 0;
+  double* d_top = nullptr;
+  Status* d_status = nullptr;
+  Arena arena;
+  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsXf, wsS1, wsS2, wsVec;
+  int* d_rank = nullptr;
+  size_t rank_cap = 0;
+  // stats
+  double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
+  int max_rank = 0;
+
+  void run(Stage& st) {
+    if (st.empty()) return;
+    factor_flops += st.flops;
+    char* d = arena.upload(st.blob, s);
+    for (const Op& op : st.ops) {
+      switch (op.t) {
+        case OP_GEMM: launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, s); break;
+        case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, s); break;
+        case OP_XFORM: {
+          const int nwg = 2048;
+          double* z = wsXf.need((size_t)nwg * kMaxRank * kMaxRank, s);
+          launch_xform(reinterpret_cast<XformDesc*>(d + op.off), op.count, z, nwg, kMaxRank, s);
+          break;
+        }
+        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, s); break;
+        case OP_RRQR: launch_rrqr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, s); break;
+        case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, s); break;
+        case OP_STACKQR:
+          launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
+                         op.count, op.a, s);
+          break;
+        case OP_INV: launch_inverse(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
+      }
+      HIP_OK(hipGetLastError());
+    }
+    st.clear();
+  }
+
+  // ---------------------------------------------------------------- tree
+  void build_tree(const std::vector<double>& pts) {
+    kappa = 2;
+    while ((int64_t)leaf * (1LL << (2 * kappa)) < N) ++kappa;
+    if (kappa > 12) throw BadArg{};
+    const int nb = 1 << kappa;
+    const int nleaf = nb * nb;
+    std::vector<int> key(N);
+    for (int64_t a = 0; a < N; ++a) {
+      const double x = pts[2 * a], y = pts[2 * a + 1];
+      if (!std::isfinite(x) || !std::isfinite(y)) throw BadArg{};
+      if (x < lox || y < loy || x > lox + size || y > loy + size) throw BadArg{};
+      int ix = (int)std::floor((x - lox) / size * nb), iy = (int)std::floor((y - loy) / size * nb);
+      ix = std::min(std::max(ix, 0), nb - 1);
+      iy = std::min(std::max(iy, 0), nb - 1);
+      key[a] = morton2(ix, iy);
+    }
+    leaf_n.assign(nleaf, 0);
+    for (int64_t a = 0; a < N; ++a) leaf_n[key[a]]++;
+    leaf_start.assign(nleaf, 0);
+    for (int i = 1; i < nleaf; ++i) leaf_start[i] = leaf_start[i - 1] + leaf_n[i - 1];
+    perm.assign(N, 0);
+    std::vector<int> fillp(leaf_start);
+    for (int64_t a = 0; a < N; ++a) perm[fillp[key[a]]++] = (int)a;  // stable
+    if (kf.kind == 0) {  // 1/r needs distinct points
+      for (int i = 0; i < nleaf; ++i) {
+        std::vector<std::pair<double, double>> v;
+        for (int a = 0; a < leaf_n[i]; ++a) {
+          const int g = perm[leaf_start[i] + a];
+          v.emplace_back(pts[2 * g], pts[2 * g + 1]);
+        }
+        std::sort(v.begin(), v.end());
+        for (size_t a = 1; a < v.size(); ++a)
+          if (v[a] == v[a - 1]) throw BadArg{};
+      }
+    }
+    lv.assign(kappa + 1, Level());
+    for (int k = 2; k <= kappa; ++k) {
+      Level& L = lv[k];
+      L.k = k;
+      L.nside = 1 << k;
+      L.nc = L.nside * L.nside;
+      L.n.assign(L.nc, 0);
+      L.r.assign(L.nc, 0);
+      L.colour.assign(L.nc, 0);
+      L.nbr9.assign((size_t)L.nc * 9, -1);
+      for (int i = 0; i < L.nc; ++i) {
+        const int ix = demorton_x(i), iy = demorton_y(i);
+        L.colour[i] = 3 * (ix % 3) + (iy % 3);
+        for (int s = 0; s < 9; ++s) {
+          const int jx = ix + s9_dx(s), jy = iy + s9_dy(s);
+          if (jx >= 0 && jy >= 0 && jx < L.nside && jy < L.nside) L.nbr9[(size_t)i * 9 + s] = morton2(jx, jy);
+        }
+      }
+      L.rpad = rpad;
+    }
+    for (int i = 0; i < nleaf; ++i) lv[kappa].n[i] = leaf_n[i];
+  }
+
+  // ------------------------------------------------------------- FMM product
+  // y = A x (tree order, column-major ld N); diag null = off-diagonal part only.
+  void fmm_apply_tree(const double* xs, double* ys, int nrhs, const double* diag) {
+    const int nleaf = 1 << (2 * kappa);
+    std::vector<double*> W(kappa + 1, nullptr), G(kappa + 1, nullptr);
+    size_t tot = 0;
+    for (int k = 2; k <= kappa; ++k) tot += (size_t)(1 << (2 * k)) * p2 * nrhs;
+    double* base = wsVec.need(2 * tot, s);
+    size_t off = 0;
+    for (int k = 2; k <= kappa; ++k) {
+      W[k] = base + off;
+      off += (size_t)(1 << (2 * k)) * p2 * nrhs;
+    }
+    for (int k = 2; k <= kappa; ++k) {
+      G[k] = base + off;
+      off += (size_t)(1 << (2 * k)) * p2 * nrhs;
+    }
+    launch_p2m(d_pts, d_leaf_start, d_leaf_n, nleaf, kappa, lox, loy, size, p, xs, (int)N, nrhs, W[kappa], s);
+    for (int k = kappa - 1; k >= 2; --k) launch_m2m(d_E, p, 1 << (2 * k), W[k + 1], W[k], nrhs, s);
+    for (int k = 2; k <= kappa; ++k) launch_m2l(p, k, d_table[k], W[k], G[k], nrhs, s);
+    for (int k = 2; k < kappa; ++k) launch_l2l(d_E, p, 1 << (2 * k), G[k], G[k + 1], nrhs, s);
+    launch_l2p_p2p(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, kf,
+                   G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
+    HIP_OK(hipGetLastError());
+  }
+
+  // --------------------------------------------------------------- assembly
+  void assemble(const double* d_points_in) {
+    const double t0 = now_ms();
+    std::vector<double> pts(2 * N);
+    HIP_OK(hipMemcpyAsync(pts.data(), d_points_in, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    build_tree(pts);
+    const int nleaf = 1 << (2 * kappa);
+    std::vector<double> spts(2 * N);
+    for (int64_t a = 0; a < N; ++a) {
+      spts[2 * a] = pts[2 * perm[a]];
+      spts[2 * a + 1] = pts[2 * perm[a] + 1];
+    }
+    d_pts = dalloc<double>(2 * N);
+    d_perm = dalloc<int>(N);
+    d_leaf_start = dalloc<int>(nleaf);
+    d_leaf_n = dalloc<int>(nleaf);
+    d_nbr9_leaf = dalloc<int>((size_t)nleaf * 9);
+    d_diag = dalloc<double>(N);
+    d_status = dalloc<Status>(1);
+    HIP_OK(hipMemsetAsync(d_status, 0, sizeof(Status), s));
+    HIP_OK(hipMemcpyAsync(d_pts, spts.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * N, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_leaf_start, leaf_start.data(), sizeof(int) * nleaf, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_leaf_n, leaf_n.data(), sizeof(int) * nleaf, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_nbr9_leaf, lv[kappa].nbr9.data(), sizeof(int) * nleaf * 9, hipMemcpyHostToDevice, s));
+    std::vector<double> E = transfer_host(p);
+    d_E = dalloc<double>(E.size());
+    HIP_OK(hipMemcpyAsync(d_E, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, s));
+    d_table.assign(kappa + 1, nullptr);
+    for (int k = 2; k <= kappa; ++k) {
+      d_table[k] = dalloc<double>((size_t)49 * p2 * p2);
+      launch_m2l_table(kf, p, 0.5 * size / (1 << k), d_table[k], s);
+    }
+    // diagonal
+    if (diag_mode == IFMM_DIAG_ROWSUM) {
+      double* ones = wsS1.need(N, s);
+      std::vector<double> h1(N, 1.0);
+      HIP_OK(hipMemcpyAsync(ones, h1.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+      fmm_apply_tree(ones, d_diag, 1, nullptr);
+      std::vector<double> hd(N);
+      HIP_OK(hipMemcpyAsync(hd.data(), d_diag, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      for (auto& v : hd) v += c0;
+      HIP_OK(hipMemcpyAsync(d_diag, hd.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+      HIP_OK(hipStreamSynchronize(s));
+    } else {
+      std::vector<double> hd(N, c0);
+      HIP_OK(hipMemcpyAsync(d_diag, hd.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    }
+
+    // ---- leaf level: interpolation, orthonormal bases, near field
+    Level& Lf = lv[kappa];
+    int nmax = 0;
+    for (int i = 0; i < nleaf; ++i) {
+      nmax = std::max(nmax, Lf.n[i]);
+      Lf.r[i] = std::min(Lf.n[i], p2);
+    }
+    Lf.set_pads(rup(std::max(nmax, 1), 8));
+    Lf.P = dalloc<double>(Lf.sP * 9 * Lf.nc);
+    Lf.Qm = dalloc<double>(Lf.sQ * 9 * Lf.nc);
+    Lf.L = dalloc<double>(Lf.sL * 9 * Lf.nc);
+    Lf.U = dalloc<double>(Lf.sU * Lf.nc);
+    Lf.V = dalloc<double>(Lf.sU * Lf.nc);
+    Lf.Dinv = dalloc<double>(Lf.sD * Lf.nc);
+    HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(double) * Lf.sQ * 9 * Lf.nc, s));
+    HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(double) * Lf.sL * 9 * Lf.nc, s));
+    launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, Lf.sP,
+                      Lf.npad, nmax, s);
+    launch_leaf_interp(d_pts, d_leaf_start, d_leaf_n, nleaf, kappa, lox, loy, size, p, Lf.U, Lf.sU,
+                       Lf.npad, nmax, s);
+    // R factors of every level at assembly (r x p^2), kept until M2L is built
+    std::vector<double*> Ra(kappa + 1, nullptr);
+    for (int k = 2; k <= kappa; ++k) Ra[k] = dalloc<double>((size_t)lv[k].nc * rpad * p2);
+    {
+      Stage st;
+      std::vector<QrDesc> q;
+      for (int i = 0; i < nleaf; ++i)
+        if (Lf.n[i] > 0) q.push_back({Lf.Ub(i), Ra[kappa] + (size_t)i * rpad * p2, Lf.n[i], p2, Lf.npad, rpad});
+      st.qr(q);
+      std::vector<AddDesc> cp;
+      for (int i = 0; i < nleaf; ++i)
+        if (Lf.n[i] > 0) cp.push_back({Lf.Ub(i), Lf.Vb(i), Lf.n[i], Lf.r[i], Lf.npad, Lf.npad, 0, 1.0, 0.0});
+      st.add(cp);
+      run(st);
+    }
+    // ---- non-leaf levels at assembly: S_P = [R_c E_c], QR, transfer blocks
+    for (int k = kappa; k >= 2; --k) {
+      Level& L = lv[k];
+      L.UP = dalloc<double>(L.sUP == 0 ? (size_t)rpad * rpad * L.nc : L.sUP * L.nc);
+    }
+    for (int k = kappa - 1; k >= 2; --k) {
+      Level& L = lv[k];
+      Level& C = lv[k + 1];
+      L.choff.assign((size_t)L.nc * 4, 0);
+      int nm = 0;
+      for (int P = 0; P < L.nc; ++P) {
+        int o = 0;
+        for (int c = 0; c < 4; ++c) {
+          L.choff[(size_t)P * 4 + c] = o;
+          o += C.r[4 * P + c];
+        }
+        L.n[P] = o;
+        L.r[P] = std::min(o, p2);
+        nm = std::max(nm, o);
+      }
+      const int npA = rup(std::max(nm, 1), 8);
+      double* SP = wsA.need((size_t)L.nc * npA * p2, s);
+      Stage st;
+      std::vector<GemmDesc> g;
+      for (int P = 0; P < L.nc; ++P)
+        for (int c = 0; c < 4; ++c) {
+          const int ch = 4 * P + c;
+          if (C.r[ch] == 0) continue;
+          g.push_back({Ra[k + 1] + (size_t)ch * rpad * p2, d_E + (size_t)c * p2 * p2,
+                       SP + (size_t)P * npA * p2 + L.choff[(size_t)P * 4 + c], C.r[ch], p2, p2, rpad, p2,
+                       npA, 0, 0, 1.0, 0.0});
+        }
+      st.gemm(g);
+      std::vector<QrDesc> q;
+      for (int P = 0; P < L.nc; ++P)
+        if (L.n[P] > 0) q.push_back({SP + (size_t)P * npA * p2, Ra[k] + (size_t)P * rpad * p2, L.n[P], p2, npA, rpad});
+      st.qr(q);
+      C.sUP = (size_t)rpad * rpad;
+      std::vector<AddDesc> cp;
+      for (int P = 0; P < L.nc; ++P)
+        for (int c = 0; c < 4; ++c) {
+          const int ch = 4 * P + c;
+          if (C.r[ch] == 0) continue;
+          cp.push_back({SP + (size_t)P * npA * p2 + L.choff[(size_t)P * 4 + c], C.UPb(ch), C.r[ch], L.r[P],
+                        npA, rpad, 0, 1.0, 0.0});
+        }
+      st.add(cp);
+      run(st);
+    }
+    for (int k = 2; k <= kappa; ++k) {
+      Level& L = lv[k];
+      L.sUP = (size_t)rpad * rpad;
+      L.sM = (size_t)rpad * rpad;
+      L.VP = dalloc<double>(L.sUP * L.nc);
+      HIP_OK(hipMemcpyAsync(L.VP, L.UP, sizeof(double) * L.sUP * L.nc, hipMemcpyDeviceToDevice, s));
+    }
+    // ---- M2L in orthonormal coordinates: M_il = R_i K(dx,dy) R_l^T
+    for (int k = 2; k <= kappa; ++k) {
+      Level& L = lv[k];
+      L.M = dalloc<double>(L.sM * 36 * L.nc);
+      HIP_OK(hipMemsetAsync(L.M, 0, sizeof(double) * L.sM * 36 * L.nc, s));
+      double* tmp = wsA.need((size_t)L.nc * rpad * p2, s);
+      for (int dx = -3; dx <= 3; ++dx)
+        for (int dy = -3; dy <= 3; ++dy) {
+          if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+          const double* T = d_table[k] + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
+          std::vector<GemmDesc> g1, g2;
+          for (int i = 0; i < L.nc; ++i) {
+            if (L.r[i] == 0) continue;
+            const int jx = demorton_x(i) + dx, jy = demorton_y(i) + dy;
+            if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+            const int l = morton2(jx, jy);
+            if (L.r[l] == 0 || !in_ilist(i, l)) continue;
+            double* ti = tmp + (size_t)i * rpad * p2;
+            g1.push_back({Ra[k] + (size_t)i * rpad * p2, T, ti, L.r[i], p2, p2, rpad, p2, rpad, 0, 0, 1.0, 0.0});
+            g2.push_back({ti, Ra[k] + (size_t)l * rpad * p2, L.Mb(i, slot36(i, l)), L.r[i], L.r[l], p2, rpad,
+                          rpad, rpad, 0, 1, 1.0, 0.0});
+          }
+          Stage st;
+          st.gemm(g1);
+          st.gemm(g2);
+          run(st);
+        }
+    }
+    for (int k = 2; k <= kappa; ++k) dfree(Ra[k]);
+    // ---- far-field weights of the parent levels, top-down
+    for (int k = 2; k < kappa; ++k) {
+      Level& L = lv[k];
+      L.Om = dalloc<double>(L.sUP * L.nc);
+      L.Omp = dalloc<double>(L.sUP * L.nc);
+      std::vector<int> ids;
+      for (int i = 0; i < L.nc; ++i)
+        if (L.r[i] > 0) ids.push_back(i);
+      weights(k, ids, [&](int t, int side) { return side == 0 ? L.Omb(ids[t]) : L.Ompb(ids[t]); });
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    t_assembly = now_ms() - t0;
+  }
+
+  // Omega (side 0) / Omega' (side 1) of the clusters `ids` at level k: R
+  // factor of the stacked far-field row / column (+ parent chain).
+  template <class OutFn>
+  void weights(int k, const std::vector<int>& ids, OutFn out) {
+    Level& L = lv[k];
+    const int nt = (int)ids.size();
+    if (nt == 0) return;
+    double* Z = nullptr;
+    if (k > 2) Z = wsZ.need((size_t)nt * 2 * rpad * rpad, s);
+    Stage st;
+    std::vector<GemmDesc> g;
+    std::vector<StackQrDesc> sd;
+    std::vector<BlkRef> br;
+    for (int t = 0; t < nt; ++t) {
+      const int q = ids[t];
+      const int rq = L.r[q];
+      for (int side = 0; side < 2; ++side) {
+        StackQrDesc d{out(t, side), rq, rpad, (int)br.size(), 0};
+        const int qx = demorton_x(q), qy = demorton_y(q);
+        for (int sl = 0; sl < 36; ++sl) {
+          const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+          if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+          if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+          const int l = morton2(jx, jy);
+          if (L.r[l] == 0) continue;
+          if (side == 0) br.push_back({L.Mb(q, sl), rpad, L.r[l], 1});
+          else br.push_back({L.Mb(l, slot36(l, q)), rpad, L.r[l], 0});
+          d.nblk++;
+        }
+        if (k > 2) {
+          Level& Pl = lv[k - 1];
+          const int P = q >> 2;
+          const int rP = Pl.r[P];
+          if (rP > 0) {
+            double* z = Z + ((size_t)t * 2 + side) * rpad * rpad;
+            const double* om = side == 0 ? Pl.Omb(P) : Pl.Ompb(P);
+            const double* up = side == 0 ? L.UPb(q) : L.VPb(q);
+            g.push_back({om, up, z, rP, rq, rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
+            br.push_back({z, rpad, rP, 0});
+            d.nblk++;
+          }
+        }
+        sd.push_back(d);
+      }
+    }
+    st.gemm(g);
+    st.stackqr(sd, br);
+    run(st);
+  }
+
+  // ------------------------------------------------------------ factorisation
+  void factor() {
+    const double t0 = now_ms();
+    plan.assign(kappa + 1, std::vector<std::vector<Elim>>(9));
+    for (int k = kappa; k >= 2; --k) {
+      for (int c = 0; c < 9; ++c) phase(k, c);
+      Level& L = lv[k];
+      for (int i = 0; i < L.nc; ++i) max_rank = std::max(max_rank, L.r[i]);
+      if (k > 2) transition(k);
+    }
+    top();
+    HIP_OK(hipStreamSynchronize(s));
+    Status hs{};
+    HIP_OK(hipMemcpy(&hs, d_status, sizeof(Status), hipMemcpyDeviceToHost));
+    if (hs.singular) throw 3;
+    t_factor = now_ms() - t0;
+  }
+
+  void phase(int k, int c) {
+    Level& L = lv[k];
+    std::vector<Elim>& E = plan[k][c];
+    for (int i = 0; i < L.nc; ++i) {
+      if (L.colour[i] != c || L.n[i] == 0) continue;
+      Elim e;
+      e.i = i;
+      e.ni = L.n[i];
+      e.ri = L.r[i];
+      e.m = e.ni + e.ri;
+      int off = 0;
+      for (int sp = 0; sp < 9; ++sp) {
+        UnitH u;
+        if (sp == 4) {
+          u = {i, 2, e.ri, 0};
+        } else {
+          const int j = L.nbr9[(size_t)i * 9 + sp];
+          if (j >= 0 && L.n[j] > 0) {
+            if (L.colour[j] > c) u = {j, 1, L.n[j], 0};
+            else if (L.r[j] > 0) u = {j, 2, L.r[j], 0};
+          }
+        }
+        if (u.kind) {
+          u.off = off;
+          off += u.size;
+        }
+        e.u[sp] = u;
+      }
+      E.push_back(e);
+    }
+    const int nb = (int)E.size();
+    if (nb == 0) return;
+    const int fpad = std::max(L.npad, rpad);
+    const int wpad = 8 * fpad + rpad;
+    double* X = wsX.need((size_t)nb * L.mpad * wpad, s);
+    double* F = wsF.need((size_t)nb * kPairs.count * fpad * fpad, s);
+    auto Xp = [&](int b) { return X + (size_t)b * L.mpad * wpad; };
+    auto Fp = [&](int b, int sa, int sb) {
+      return F + ((size_t)b * kPairs.count + kPairs.idx[sa][sb]) * fpad * fpad;
+    };
+    // ---- eliminate the batch: pivot inverse, X = D^-1 B, Schur updates
+    {
+      Stage st;
+      std::vector<AddDesc> dbuild;
+      std::vector<InvDesc> inv;
+      for (const Elim& e : E) {
+        double* D = L.Db(e.i);
+        dbuild.push_back({L.Pb(e.i, 4), D, e.ni, e.ni, L.npad, L.mpad, 0, 1.0, 0.0});
+        dbuild.push_back({L.Ub(e.i), D + (size_t)e.ni * L.mpad, e.ni, e.ri, L.npad, L.mpad, 0, 1.0, 0.0});
+        dbuild.push_back({L.Vb(e.i), D + e.ni, e.ri, e.ni, L.npad, L.mpad, 1, 1.0, 0.0});
+        dbuild.push_back({nullptr, D + e.ni + (size_t)e.ni * L.mpad, e.ri, e.ri, 0, L.mpad, 0, 0.0, 0.0});
+        inv.push_back({D, e.m, L.mpad});
+      }
+      st.add(dbuild);
+      st.inv(inv);
+      std::vector<GemmDesc> gx;
+      std::vector<AddDesc> ax;
+      for (int b = 0; b < nb; ++b) {
+        const Elim& e = E[b];
+        const double* D = L.Db(e.i);
+        for (int sp = 0; sp < 9; ++sp) {
+          const UnitH& u = e.u[sp];
+          if (!u.kind) continue;
+          double* Xc = Xp(b) + (size_t)u.off * L.mpad;
+          if (sp == 4) {
+            ax.push_back({D + (size_t)e.ni * L.mpad, Xc, e.m, e.ri, L.mpad, L.mpad, 0, -1.0, 0.0});
+          } else {
+            const double* Bsrc = u.kind == 1 ? L.Pb(e.i, sp) : L.Qb(e.i, sp);
+            gx.push_back({D, Bsrc, Xc, e.m, u.size, e.ni, L.mpad, L.npad, L.mpad, 0, 0, 1.0, 0.0});
+          }
+        }
+      }
+      st.gemm(gx);
+      st.add(ax);
+      std::vector<GemmDesc> gs;
+      std::vector<AddDesc> am;
+      for (int b = 0; b < nb; ++b) {
+        const Elim& e = E[b];
+        for (int sa = 0; sa < 9; ++sa) {
+          const UnitH& ua = e.u[sa];
+          if (!ua.kind || sa == 4) continue;
+          const double* Ca = ua.kind == 1 ? L.Pb(ua.cl, 8 - sa) : L.Lb(ua.cl, 8 - sa);
+          const int lda = ua.kind == 1 ? L.npad : rpad;
+          for (int sb = 0; sb < 9; ++sb) {
+            const UnitH& ub = e.u[sb];
+            if (!ub.kind) continue;
+            const double* Xb = Xp(b) + (size_t)ub.off * L.mpad;
+            double* C;
+            int ldc;
+            double beta = 1.0;
+            const bool adj = pos_adjacent(sa, sb);
+            if (ua.kind == 2 && ub.kind == 2) {
+              C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
+              ldc = rpad;
+            } else if (!adj) {
+              C = Fp(b, sa, sb);
+              ldc = fpad;
+              beta = 0.0;
+            } else {
+              const int st9 = s9_of(s9_dx(sb) - s9_dx(sa), s9_dy(sb) - s9_dy(sa));
+              if (ua.kind == 1 && ub.kind == 1) { C = L.Pb(ua.cl, st9); ldc = L.npad; }
+              else if (ua.kind == 1) { C = L.Qb(ua.cl, st9); ldc = L.npad; }
+              else { C = L.Lb(ua.cl, st9); ldc = rpad; }
+            }
+            gs.push_back({Ca, Xb, C, ua.size, ub.size, e.ni, lda, L.mpad, ldc, 0, 0, -1.0, beta});
+          }
+        }
+        // row M2L(i) of the pivot: += X^z
+        for (int sb = 0; sb < 9; ++sb) {
+          const UnitH& ub = e.u[sb];
+          if (!ub.kind) continue;
+          const double* Xz = Xp(b) + e.ni + (size_t)ub.off * L.mpad;
+          if (ub.kind == 1) am.push_back({Xz, L.Lb(e.i, sb), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
+          else am.push_back({Xz, L.Mb(e.i, slot36(e.i, ub.cl)), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
+        }
+      }
+      st.gemm(gs);
+      st.add(am);
+      run(st);
+    }
+    compress(k, E, fpad, Fp);
+  }
+
+  template <class FpFn>
+  void compress(int k, const std::vector<Elim>& E, int fpad, FpFn Fp) {
+    Level& L = lv[k];
+    struct Touch {
+      int q, b, sq, cu, cv;
+    };
+    std::vector<Touch> T;
+    std::vector<int> tidx(L.nc, -1);
+    for (int b = 0; b < (int)E.size(); ++b)
+      for (int sq = 0; sq < 9; ++sq) {
+        const UnitH& u = E[b].u[sq];
+        if (u.kind != 1) continue;
+        int cu = 0, cv = 0;
+        for (int s2 = 0; s2 < 9; ++s2) {
+          if (kPairs.idx[sq][s2] < 0 || !E[b].u[s2].kind) continue;
+          cu += E[b].u[s2].size;
+          cv += E[b].u[s2].size;
+        }
+        if (cu == 0) continue;
+        tidx[u.cl] = (int)T.size();
+        T.push_back({u.cl, b, sq, cu, cv});
+      }
+    const int nt = (int)T.size();
+    if (nt == 0) return;
+    // Omega, Omega' from the current state (before any basis change)
+    double* Om = wsB.need((size_t)nt * 2 * rpad * rpad, s);
+    std::vector<int> ids(nt);
+    for (int t = 0; t < nt; ++t) ids[t] = T[t].q;
+    weights(k, ids, [&](int t, int side) { return Om + ((size_t)t * 2 + side) * rpad * rpad; });
+    // new bases, chunk by chunk
+    const int cmax = rpad + 5 * fpad;
+    double* Uh = wsQ.need((size_t)nt * 2 * L.sU, s);
+    double* TS = wsR.need((size_t)nt * 2 * rpad * rpad, s);
+    size_t per = (size_t)2 * L.npad * cmax;
+    int chunk = (int)std::min<size_t>(nt, std::max<size_t>(64, ((size_t)12 << 30) / (per * sizeof(double))));
+    double* A = wsT.need(per * chunk + (size_t)chunk * 2 * 2 * kMaxRank, s);
+    double* tauA = A + per * chunk;
+    if (rank_cap < (size_t)4 * nt) {
+      HIP_OK(hipStreamSynchronize(s));
+      if (d_rank) (void)hipFree(d_rank);
+      rank_cap = (size_t)4 * nt;
+      d_rank = dalloc<int>(rank_cap);
+    }
+    std::vector<int> hr(4 * nt), rnew(nt);
+    for (int t0 = 0; t0 < nt; t0 += chunk) {
+      const int t1 = std::min(nt, t0 + chunk);
+      Stage st;
+      std::vector<GemmDesc> g;
+      std::vector<AddDesc> a;
+      std::vector<RrqrDesc> rq;
+      for (int t = t0; t < t1; ++t) {
+        const Touch& tc = T[t];
+        const int q = tc.q, nq = L.n[q], rq0 = L.r[q];
+        for (int side = 0; side < 2; ++side) {
+          double* Aw = A + ((size_t)(t - t0) * 2 + side) * L.npad * cmax;
+          const double* base = side == 0 ? L.Ub(q) : L.Vb(q);
+          g.push_back({base, Om + ((size_t)t * 2 + side) * rpad * rpad, Aw, nq, rq0, rq0, L.npad, rpad, L.npad,
+                       0, 1, 1.0, 0.0});
+          int col = rq0;
+          for (int s2 = 0; s2 < 9; ++s2) {
+            if (kPairs.idx[tc.sq][s2] < 0 || !E[tc.b].u[s2].kind) continue;
+            const int w = E[tc.b].u[s2].size;
+            if (side == 0) a.push_back({Fp(tc.b, tc.sq, s2), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 0, 1.0, 0.0});
+            else a.push_back({Fp(tc.b, s2, tc.sq), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 1, 1.0, 0.0});
+            col += w;
+          }
+          double* tb = tauA + ((size_t)(t - t0) * 2 + side) * 2 * kMaxRank;
+          rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 4 * t + side, d_rank + 4 * t + 2 + side, nq, col, L.npad,
+                        std::min(nq, r_cap), eps});
+        }
+      }
+      st.gemm(g);
+      st.add(a);
+      st.rrqr(rq);
+      run(st);
+      HIP_OK(hipMemcpyAsync(hr.data() + 4 * t0, d_rank + 4 * t0, sizeof(int) * 4 * (t1 - t0), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      std::vector<FormQDesc> fq;
+      for (int t = t0; t < t1; ++t) {
+        const int q = T[t].q, nq = L.n[q];
+        rnew[t] = std::min(std::min(std::max(hr[4 * t], hr[4 * t + 1]), nq), r_cap);
+        for (int side = 0; side < 2; ++side) {
+          double* Aw = A + ((size_t)(t - t0) * 2 + side) * L.npad * cmax;
+          double* tb = tauA + ((size_t)(t - t0) * 2 + side) * 2 * kMaxRank;
+          const int steps = hr[4 * t + 2 + side];
+          fq.push_back({Aw, tb, tb + kMaxRank, Uh + ((size_t)t * 2 + side) * L.sU, nq, rnew[t],
+                        std::min(rnew[t], steps), L.npad, L.npad});
+        }
+      }
+      st.formq(fq);
+      run(st);
+    }
+    // basis changes: T = Uh^T U, St = Vh^T V
+    Stage st;
+    std::vector<GemmDesc> g;
+    for (int t = 0; t < nt; ++t) {
+      const int q = T[t].q, nq = L.n[q];
+      g.push_back({Uh + ((size_t)t * 2) * L.sU, L.Ub(q), TS + ((size_t)t * 2) * rpad * rpad, rnew[t], L.r[q], nq,
+                   L.npad, L.npad, rpad, 1, 0, 1.0, 0.0});
+      g.push_back({Uh + ((size_t)t * 2 + 1) * L.sU, L.Vb(q), TS + ((size_t)t * 2 + 1) * rpad * rpad, rnew[t], L.r[q],
+                   nq, L.npad, L.npad, rpad, 1, 0, 1.0, 0.0});
+    }
+    st.gemm(g);
+    auto Tm = [&](int t) { return TS + ((size_t)t * 2) * rpad * rpad; };
+    auto Sm = [&](int t) { return TS + ((size_t)t * 2 + 1) * rpad * rpad; };
+    std::vector<XformDesc> xf;
+    for (int t = 0; t < nt; ++t) {
+      const int q = T[t].q;
+      const int qx = demorton_x(q), qy = demorton_y(q);
+      for (int sl = 0; sl < 36; ++sl) {
+        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+        const int l = morton2(jx, jy);
+        if (L.r[l] == 0) continue;
+        const int tl = tidx[l];
+        // row block (q, l): T_q M S_l
+        xf.push_back({L.Mb(q, sl), Tm(t), tl >= 0 ? Sm(tl) : nullptr, L.r[q], L.r[l], rnew[t],
+                      tl >= 0 ? rnew[tl] : L.r[l], rpad, rpad, rpad, 1});
+        // column block (l, q) when l is not itself touched
+        if (tl < 0)
+          xf.push_back({L.Mb(l, slot36(l, q)), nullptr, Sm(t), L.r[l], L.r[q], L.r[l], rnew[t], rpad, rpad, rpad, 1});
+      }
+      if (k > 2 && lv[k - 1].r[q >> 2] > 0) {
+        const int rP = lv[k - 1].r[q >> 2];
+        xf.push_back({L.UPb(q), Tm(t), nullptr, L.r[q], rP, rnew[t], rP, rpad, rpad, rpad, 0});
+        xf.push_back({L.VPb(q), Sm(t), nullptr, L.r[q], rP, rnew[t], rP, rpad, rpad, rpad, 0});
+      }
+    }
+    st.xform(xf);
+    std::vector<AddDesc> cp;
+    for (int t = 0; t < nt; ++t) {
+      const int q = T[t].q, nq = L.n[q];
+      cp.push_back({Uh + ((size_t)t * 2) * L.sU, L.Ub(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
+      cp.push_back({Uh + ((size_t)t * 2 + 1) * L.sU, L.Vb(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
+    }
+    st.add(cp);
+    for (int t = 0; t < nt; ++t) L.r[T[t].q] = rnew[t];
+    // project the compressed fill into M2L
+    std::vector<GemmDesc> g1, g2;
+    double* tmp = wsS2.need((size_t)E.size() * kPairs.count * rpad * fpad, s);
+    for (int b = 0; b < (int)E.size(); ++b) {
+      const Elim& e = E[b];
+      for (int sa = 0; sa < 9; ++sa)
+        for (int sb = 0; sb < 9; ++sb) {
+          const int pi = kPairs.idx[sa][sb];
+          if (pi < 0) continue;
+          const UnitH& ua = e.u[sa];
+          const UnitH& ub = e.u[sb];
+          if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
+          const double* Fb = Fp(b, sa, sb);
+          double* C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
+          if (ua.kind == 1 && ub.kind == 1) {
+            double* tm = tmp + ((size_t)b * kPairs.count + pi) * rpad * fpad;
+            g1.push_back({L.Ub(ua.cl), Fb, tm, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 0.0});
+            g2.push_back({tm, L.Vb(ub.cl), C, L.r[ua.cl], L.r[ub.cl], ub.size, rpad, L.npad, rpad, 0, 0, 1.0, 1.0});
+          } else if (ua.kind == 1) {
+            g2.push_back({L.Ub(ua.cl), Fb, C, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 1.0});
+          } else {
+            g2.push_back({Fb, L.Vb(ub.cl), C, ua.size, L.r[ub.cl], ub.size, fpad, L.npad, rpad, 0, 0, 1.0, 1.0});
+          }
+        }
+    }
+    st.gemm(g1);
+    st.gemm(g2);
+    run(st);
+  }
+
+  // Level k -> k-1: particles are the children's multipoles; P2P from their
+  // M2L; parent bases re-orthonormalised (z_P -> Ru z_P, y_P = Rv^T y^_P).
+  void transition(int k) {
+    Level& C = lv[k];
+    Level& L = lv[k - 1];
+    int nm = 0;
+    std::vector<int> rold(L.r);
+    for (int P = 0; P < L.nc; ++P) {
+      int o = 0;
+      for (int c = 0; c < 4; ++c) {
+        L.choff[(size_t)P * 4 + c] = o;
+        o += C.r[4 * P + c];
+      }
+      L.n[P] = o;
+      nm = std::max(nm, o);
+    }
+    L.set_pads(rup(std::max(nm, 1), 8));
+    L.P = dalloc<double>(L.sP * 9 * L.nc);
+    L.Qm = dalloc<double>(L.sQ * 9 * L.nc);
+    L.L = dalloc<double>(L.sL * 9 * L.nc);
+    L.U = dalloc<double>(L.sU * L.nc);
+    L.V = dalloc<double>(L.sU * L.nc);
+    L.Dinv = dalloc<double>(L.sD * L.nc);
+    HIP_OK(hipMemsetAsync(L.Qm, 0, sizeof(double) * L.sQ * 9 * L.nc, s));
+    HIP_OK(hipMemsetAsync(L.L, 0, sizeof(double) * L.sL * 9 * L.nc, s));
+    double* Ru = wsA.need((size_t)L.nc * 2 * rpad * rpad, s);
+    auto Rub = [&](int P) { return Ru + (size_t)P * 2 * rpad * rpad; };
+    auto Rvb = [&](int P) { return Ru + ((size_t)P * 2 + 1) * rpad * rpad; };
+    Stage st;
+    std::vector<AddDesc> a;
+    for (int P = 0; P < L.nc; ++P) {
+      if (L.n[P] == 0) continue;
+      for (int sp = 0; sp < 9; ++sp) {
+        const int Q = L.nbr9[(size_t)P * 9 + sp];
+        if (Q < 0 || L.n[Q] == 0) continue;
+        double* B = L.Pb(P, sp);
+        for (int c = 0; c < 4; ++c) {
+          const int ch = 4 * P + c;
+          if (C.r[ch] == 0) continue;
+          for (int c2 = 0; c2 < 4; ++c2) {
+            const int ch2 = 4 * Q + c2;
+            if (C.r[ch2] == 0) continue;
+            a.push_back({C.Mb(ch, slot36(ch, ch2)), B + L.choff[(size_t)P * 4 + c] + (size_t)L.choff[(size_t)Q * 4 + c2] * L.npad,
+                         C.r[ch], C.r[ch2], rpad, L.npad, 0, 1.0, 0.0});
+          }
+        }
+      }
+      for (int c = 0; c < 4; ++c) {
+        const int ch = 4 * P + c;
+        if (C.r[ch] == 0) continue;
+        a.push_back({C.UPb(ch), L.Ub(P) + L.choff[(size_t)P * 4 + c], C.r[ch], rold[P], rpad, L.npad, 0, 1.0, 0.0});
+        a.push_back({C.VPb(ch), L.Vb(P) + L.choff[(size_t)P * 4 + c], C.r[ch], rold[P], rpad, L.npad, 0, 1.0, 0.0});
+      }
+    }
+    st.add(a);
+    std::vector<QrDesc> q;
+    std::vector<AddDesc> z;
+    for (int P = 0; P < L.nc; ++P) {
+      if (L.n[P] > 0) {
+        q.push_back({L.Ub(P), Rub(P), L.n[P], rold[P], L.npad, rpad});
+        q.push_back({L.Vb(P), Rvb(P), L.n[P], rold[P], L.npad, rpad});
+      }
+      L.r[P] = std::min(L.n[P], rold[P]);
+    }
+    st.qr(q);
+    std::vector<XformDesc> xf;
+    for (int P = 0; P < L.nc; ++P) {
+      if (rold[P] == 0) continue;
+      const int px = demorton_x(P), py = demorton_y(P);
+      for (int sl = 0; sl < 36; ++sl) {
+        const int jx = 2 * (px >> 1) - 2 + sl / 6, jy = 2 * (py >> 1) - 2 + sl % 6;
+        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+        if (std::abs(jx - px) <= 1 && std::abs(jy - py) <= 1) continue;
+        const int l = morton2(jx, jy);
+        if (rold[l] == 0) continue;
+        xf.push_back({L.Mb(P, sl), Rub(P), Rvb(l), rold[P], rold[l], L.r[P], L.r[l], rpad, rpad, rpad, 1});
+      }
+      if (k - 1 > 2 && lv[k - 2].r[P >> 2] > 0) {
+        const int rG = lv[k - 2].r[P >> 2];
+        xf.push_back({L.UPb(P), Rub(P), nullptr, rold[P], rG, L.r[P], rG, rpad, rpad, rpad, 0});
+        xf.push_back({L.VPb(P), Rvb(P), nullptr, rold[P], rG, L.r[P], rG, rpad, rpad, rpad, 0});
+      }
+    }
+    st.xform(xf);
+    run(st);
+    HIP_OK(hipStreamSynchronize(s));
+    C.free_work();
+  }
+
+  void top() {
+    Level& L = lv[2];
+    top_ids.clear();
+    top_off.assign(1, 0);
+    for (int c = 0; c < 16; ++c)
+      if (L.r[c] > 0) {
+        top_ids.push_back(c);
+        top_off.push_back(top_off.back() + L.r[c]);
+      }
+    top_m = top_off.back();
+    if (top_m == 0) return;
+    d_top = dalloc<double>((size_t)top_m * top_m);
+    Stage st;
+    std::vector<AddDesc> a;
+    for (size_t x = 0; x < top_ids.size(); ++x)
+      for (size_t y = 0; y < top_ids.size(); ++y) {
+        const int ca = top_ids[x], cb = top_ids[y];
+        a.push_back({L.Mb(ca, slot36(ca, cb)), d_top + top_off[x] + (size_t)top_off[y] * top_m, L.r[ca], L.r[cb], rpad,
+                     top_m, 0, 1.0, 0.0});
+      }
+    st.add(a);
+    st.inv({InvDesc{d_top, top_m, top_m}});
+    run(st);
+    L.free_work();
+  }
+
+  // ------------------------------------------------------------------ solve
+  struct SolveBufs {
+    std::vector<double*> b, c, sn, x, y;
+  };
+  // x (tree order, ld N) = A^-1 b (tree order, ld N)
+  void solve_tree(const double* bt, double* xt, int nrhs) {
+    std::vector<size_t> ob(kappa + 1), oc(kappa + 1);
+    size_t tot = 0;
+    for (int k = 2; k <= kappa; ++k) {
+      const Level& L = lv[k];
+      ob[k] = tot;
+      tot += (size_t)3 * L.nc * L.npad * nrhs;
+      oc[k] = tot;
+      tot += (size_t)2 * L.nc * rpad * nrhs;
+    }
+    int nbmax = 0, mmax = 0;
+    for (int k = 2; k <= kappa; ++k)
+      for (int c = 0; c < 9; ++c) {
+        nbmax = std::max(nbmax, (int)plan[k][c].size());
+        mmax = std::max(mmax, lv[k].mpad);
+      }
+    const size_t wsz = (size_t)nbmax * mmax * nrhs;
+    double* base = wsS1.need(tot + 2 * wsz + 2 * (size_t)std::max(top_m, 1) * nrhs, s);
+    double* wv = base + tot;
+    double* rv = wv + wsz;
+    double* tv = rv + wsz;
+    auto bvec = [&](int k, int i) { return base + ob[k] + (size_t)i * lv[k].npad * nrhs; };
+    auto snap = [&](int k, int i) { return base + ob[k] + ((size_t)lv[k].nc + i) * lv[k].npad * nrhs; };
+    auto xvec = [&](int k, int i) { return base + ob[k] + ((size_t)2 * lv[k].nc + i) * lv[k].npad * nrhs; };
+    auto cvec = [&](int k, int i) { return base + oc[k] + (size_t)i * rpad * nrhs; };
+    auto yvec = [&](int k, int i) { return base + oc[k] + ((size_t)lv[k].nc + i) * rpad * nrhs; };
+    HIP_OK(hipMemsetAsync(base, 0, sizeof(double) * tot, s));
+    Stage st;
+    {
+      std::vector<AddDesc> a;
+      const Level& Lf = lv[kappa];
+      for (int i = 0; i < Lf.nc; ++i)
+        if (Lf.n[i]) a.push_back({bt + leaf_start[i], bvec(kappa, i), Lf.n[i], nrhs, (int)N, Lf.npad, 0, 1.0, 0.0});
+      st.add(a);
+      run(st);
+    }
+    for (int k = kappa; k >= 2; --k) {
+      const Level& L = lv[k];
+      for (int c = 0; c < 9; ++c) {
+        const std::vector<Elim>& E = plan[k][c];
+        if (E.empty()) continue;
+        std::vector<AddDesc> a1, a2;
+        std::vector<GemmDesc> g1, g2;
+        for (int b = 0; b < (int)E.size(); ++b) {
+          const Elim& e = E[b];
+          double* w = wv + (size_t)b * L.mpad * nrhs;
+          a1.push_back({bvec(k, e.i), snap(k, e.i), e.ni, nrhs, L.npad, L.npad, 0, 1.0, 0.0});
+          g1.push_back({L.Db(e.i), bvec(k, e.i), w, e.m, nrhs, e.ni, L.mpad, L.npad, L.mpad, 0, 0, 1.0, 0.0});
+          for (int sp = 0; sp < 9; ++sp) {
+            const UnitH& u = e.u[sp];
+            if (!u.kind || sp == 4) continue;
+            if (u.kind == 1)
+              g2.push_back({L.Pb(u.cl, 8 - sp), w, bvec(k, u.cl), u.size, nrhs, e.ni, L.npad, L.mpad, L.npad, 0, 0, -1.0, 1.0});
+            else
+              g2.push_back({L.Lb(u.cl, 8 - sp), w, cvec(k, u.cl), u.size, nrhs, e.ni, rpad, L.mpad, rpad, 0, 0, -1.0, 1.0});
+          }
+          a2.push_back({w + e.ni, cvec(k, e.i), e.ri, nrhs, L.mpad, rpad, 0, 1.0, 1.0});
+        }
+        st.add(a1);
+        st.gemm(g1);
+        st.gemm(g2);
+        st.add(a2);
+        run(st);
+      }
+      if (k > 2) {
+        const Level& Lp = lv[k - 1];
+        std::vector<AddDesc> a;
+        for (int P = 0; P < Lp.nc; ++P)
+          for (int c = 0; c < 4; ++c) {
+            const int ch = 4 * P + c;
+            if (L.r[ch]) a.push_back({cvec(k, ch), bvec(k - 1, P) + Lp.choff[(size_t)P * 4 + c], L.r[ch], nrhs, rpad, Lp.npad, 0, 1.0, 0.0});
+          }
+        st.add(a);
+        run(st);
+      }
+    }
+    if (top_m > 0) {
+      std::vector<AddDesc> a, a2;
+      for (size_t x = 0; x < top_ids.size(); ++x)
+        a.push_back({cvec(2, top_ids[x]), tv + top_off[x], lv[2].r[top_ids[x]], nrhs, rpad, top_m, 0, 1.0, 0.0});
+      st.add(a);
+      double* yt = tv + (size_t)top_m * nrhs;
+      st.gemm({GemmDesc{d_top, tv, yt, top_m, nrhs, top_m, top_m, top_m, top_m, 0, 0, 1.0, 0.0}});
+      for (size_t x = 0; x < top_ids.size(); ++x)
+        a2.push_back({yt + top_off[x], yvec(2, top_ids[x]), lv[2].r[top_ids[x]], nrhs, top_m, rpad, 0, 1.0, 0.0});
+      st.add(a2);
+      run(st);
+    }
+    for (int k = 2; k <= kappa; ++k) {
+      const Level& L = lv[k];
+      for (int c = 8; c >= 0; --c) {
+        const std::vector<Elim>& E = plan[k][c];
+        if (E.empty()) continue;
+        std::vector<AddDesc> a;
+        for (int b = 0; b < (int)E.size(); ++b) {
+          const Elim& e = E[b];
+          double* r = rv + (size_t)b * L.mpad * nrhs;
+          a.push_back({snap(k, e.i), r, e.ni, nrhs, L.npad, L.mpad, 0, 1.0, 0.0});
+          a.push_back({yvec(k, e.i), r + e.ni, e.ri, nrhs, rpad, L.mpad, 0, 1.0, 0.0});
+        }
+        st.add(a);
+        for (int sp = 0; sp < 9; ++sp) {
+          if (sp == 4) continue;
+          std::vector<GemmDesc> g;
+          for (int b = 0; b < (int)E.size(); ++b) {
+            const Elim& e = E[b];
+            const UnitH& u = e.u[sp];
+            if (!u.kind) continue;
+            double* r = rv + (size_t)b * L.mpad * nrhs;
+            if (u.kind == 1)
+              g.push_back({L.Pb(e.i, sp), xvec(k, u.cl), r, e.ni, nrhs, u.size, L.npad, L.npad, L.mpad, 0, 0, -1.0, 1.0});
+            else
+              g.push_back({L.Qb(e.i, sp), yvec(k, u.cl), r, e.ni, nrhs, u.size, L.npad, rpad, L.mpad, 0, 0, -1.0, 1.0});
+          }
+          st.gemm(g);
+        }
+        std::vector<GemmDesc> gx;
+        for (int b = 0; b < (int)E.size(); ++b) {
+          const Elim& e = E[b];
+          gx.push_back({L.Db(e.i), rv + (size_t)b * L.mpad * nrhs, xvec(k, e.i), e.ni, nrhs, e.m, L.mpad, L.mpad,
+                        L.npad, 0, 0, 1.0, 0.0});
+        }
+        st.gemm(gx);
+        run(st);
+      }
+      if (k < kappa) {
+        const Level& Lc = lv[k + 1];
+        std::vector<AddDesc> a;
+        for (int P = 0; P < L.nc; ++P)
+          for (int c = 0; c < 4; ++c) {
+            const int ch = 4 * P + c;
+            if (Lc.r[ch]) a.push_back({xvec(k, P) + L.choff[(size_t)P * 4 + c], yvec(k + 1, ch), Lc.r[ch], nrhs, L.npad, rpad, 0, 1.0, 0.0});
+          }
+        st.add(a);
+        run(st);
+      }
+    }
+    std::vector<AddDesc> a;
+    const Level& Lf = lv[kappa];
+    for (int i = 0; i < Lf.nc; ++i)
+      if (Lf.n[i]) a.push_back({xvec(kappa, i), xt + leaf_start[i], Lf.n[i], nrhs, Lf.npad, (int)N, 0, 1.0, 0.0});
+    st.add(a);
+    run(st);
+  }
+
+  void release() {
+    for (auto& L : lv) L.free_all();
+    for (auto& t : d_table) dfree(t);
+    dfree(d_pts);
+    dfree(d_perm);
+    dfree(d_leaf_start);
+    dfree(d_leaf_n);
+    dfree(d_nbr9_leaf);
+    dfree(d_diag);
+    dfree(d_E);
+    dfree(d_top);
+    dfree(d_status);
+    if (d_rank) (void)hipFree(d_rank);
+    d_rank = nullptr;
+    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec}) b->release();
+    arena.release();
+  }
+};
+
+namespace {
+
+ifmm_status map_exc() {
+  try {
+    throw;
+  } catch (const HipError&) {
+    return IFMM_EDEVICE;
+  } catch (const NoMem&) {
+    return IFMM_ENOMEM;
+  } catch (const BadArg&) {
+    return IFMM_EINVAL;
+  } catch (int code) {
+    return (ifmm_status)code;
+  } catch (const std::bad_alloc&) {
+    return IFMM_ENOMEM;
+  } catch (...) {
+    return IFMM_EDEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, double eps, int leaf_size,
+                        int rank, const ifmm_options* opt, void* stream, ifmm_t* out) {
+  if (!out || !points || !k) return IFMM_EINVAL;
+  if (n < 16 || n > (int64_t)1 << 30 || leaf_size < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return IFMM_EINVAL;
+  int p = (int)std::lround(std::sqrt((double)rank));
+  if (rank < 1 || p * p != rank || p > kMaxP) return IFMM_EINVAL;
+  if (k->kind != IFMM_K_INV_R && k->kind != IFMM_K_EXP) return IFMM_EINVAL;
+  if (k->kind == IFMM_K_EXP && !(k->ell > 0.0)) return IFMM_EINVAL;
+  if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST) return IFMM_EINVAL;
+  if (!std::isfinite(k->c0)) return IFMM_EINVAL;
+  int r_cap = opt && opt->r_max > 0 ? opt->r_max : 2 * rank;
+  if (r_cap > kMaxRank) r_cap = opt && opt->r_max > 0 ? -1 : kMaxRank;
+  if (r_cap < rank || r_cap > kMaxRank) return IFMM_EINVAL;
+  ifmm_plan* h = new (std::nothrow) ifmm_plan();
+  if (!h) return IFMM_ENOMEM;
+  h->s = static_cast<hipStream_t>(stream);
+  h->N = n;
+  h->p = p;
+  h->p2 = rank;
+  h->leaf = leaf_size;
+  h->r_cap = r_cap;
+  h->rpad = rup(r_cap, 8);
+  h->kf = KernelFn{k->kind, k->ell};
+  h->diag_mode = k->diag_mode;
+  h->c0 = k->c0;
+  h->eps = eps;
+  if (opt && opt->box_size > 0.0) {
+    h->lox = opt->box_lo[0];
+    h->loy = opt->box_lo[1];
+    h->size = opt->box_size;
+  }
+  if (opt) {
+    h->refine_tol = opt->refine_tol;
+    h->refine_maxit = opt->refine_maxit > 0 ? opt->refine_maxit : 30;
+  }
+  try {
+    h->arena.init();
+    h->assemble(points);
+    h->factor();
+  } catch (...) {
+    ifmm_status st = map_exc();
+    (void)hipStreamSynchronize(h->s);
+    h->release();
+    delete h;
+    return st;
+  }
+  *out = h;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* stream) {
+  if (!h || !x || !y || nrhs < 1 || nrhs > 64) return IFMM_EINVAL;
+  try {
+    h->s = static_cast<hipStream_t>(stream);
+    const int N = (int)h->N;
+    double* buf = h->wsS2.need((size_t)2 * N * nrhs, h->s);
+    launch_gather_rows(x, N, h->d_perm, N, nrhs, buf, N, h->s);
+    h->fmm_apply_tree(buf, buf + (size_t)N * nrhs, nrhs, h->d_diag);
+    launch_scatter_rows(buf + (size_t)N * nrhs, N, h->d_perm, N, nrhs, y, N, h->s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(h->s));
+  } catch (...) {
+    return map_exc();
+  }
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream) {
+  if (!h || !d) return IFMM_EINVAL;
+  try {
+    h->s = static_cast<hipStream_t>(stream);
+    launch_scatter_rows(h->d_diag, (int)h->N, h->d_perm, (int)h->N, 1, d, (int)h->N, h->s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(h->s));
+  } catch (...) {
+    return map_exc();
+  }
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* stream, ifmm_solve_info* info) {
+  if (!h || !b || !x || nrhs < 1 || nrhs > 64 || b == x) return IFMM_EINVAL;
+  ifmm_status result = IFMM_OK;
+  try {
+    h->s = static_cast<hipStream_t>(stream);
+    const double t0 = now_ms();
+    const int N = (int)h->N;
+    const size_t sz = (size_t)N * nrhs;
+    Buf& wb = h->wsB;  // tree-order vectors: b, x, r, dx, y
+    double* base = wb.need(5 * sz + 2 * (size_t)nrhs, h->s);
+    double* bt = base;
+    double* xt = base + sz;
+    double* rt = base + 2 * sz;
+    double* dx = base + 3 * sz;
+    double* yt = base + 4 * sz;
+    double* nrm = base + 5 * sz;
+    launch_gather_rows(b, N, h->d_perm, N, nrhs, bt, N, h->s);
+    h->solve_tree(bt, xt, nrhs);
+    int it = 0;
+    std::vector<double> hist;
+    if (h->refine_tol > 0.0) {
+      std::vector<double> bn(nrhs), rn(nrhs);
+      HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, h->s));
+      launch_colnorm2(bt, N, nrhs, N, nrm, h->s);
+      HIP_OK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->s));
+      HIP_OK(hipStreamSynchronize(h->s));
+      std::vector<double> best_res(nrhs, 1e300);
+      while (true) {
+        h->fmm_apply_tree(xt, yt, nrhs, h->d_diag);
+        Stage st;
+        st.add({AddDesc{bt, rt, N, nrhs, N, N, 0, 1.0, 0.0}});
+        st.add({AddDesc{yt, rt, N, nrhs, N, N, 0, -1.0, 1.0}});
+        h->run(st);
+        HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, h->s));
+        launch_colnorm2(rt, N, nrhs, N, nrm, h->s);
+        HIP_OK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->s));
+        HIP_OK(hipStreamSynchronize(h->s));
+        double worst = 0.0;
+        for (int r = 0; r < nrhs; ++r) worst = std::max(worst, std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300));
+        hist.push_back(worst);
+        if (worst <= h->refine_tol) break;
+        if (it >= h->refine_maxit || (hist.size() >= 3 && worst > 0.9 * hist[hist.size() - 2] && worst > hist[0])) {
+          result = IFMM_ENOTCONV;
+          break;
+        }
+        h->solve_tree(rt, dx, nrhs);
+        Stage s2;
+        s2.add({AddDesc{dx, xt, N, nrhs, N, N, 0, 1.0, 1.0}});
+        h->run(s2);
+        ++it;
+      }
+    }
+    launch_scatter_rows(xt, N, h->d_perm, N, nrhs, x, N, h->s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(h->s));
+    h->t_solve = now_ms() - t0;
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = it;
+      info->residual = hist.empty() ? 0.0 : hist.back();
+      for (size_t i = 0; i < hist.size() && i < 32; ++i) info->history[i] = hist[i];
+      info->solve_ms = h->t_solve;
+    }
+  } catch (...) {
+    return map_exc();
+  }
+  return result;
+}
+
+ifmm_status ifmm_stats(ifmm_t h, ifmm_stats_t* s) {
+  if (!h || !s) return IFMM_EINVAL;
+  std::memset(s, 0, sizeof(*s));
+  s->n = h->N;
+  s->kappa = h->kappa;
+  s->p = h->p;
+  s->max_rank = h->max_rank;
+  double bytes = 0;
+  for (int k = 2; k <= h->kappa && k < 16; ++k) {
+    const Level& L = h->lv[k];
+    int mx = 0;
+    double sum = 0;
+    int cnt = 0;
+    for (int i = 0; i < L.nc; ++i)
+      if (L.n[i] > 0) {
+        mx = std::max(mx, L.r[i]);
+        sum += L.r[i];
+        ++cnt;
+      }
+    s->level_max_rank[k] = mx;
+    s->level_mean_rank[k] = cnt ? sum / cnt : 0.0;
+    bytes += 8.0 * L.nc * (9.0 * (L.sP + L.sQ + L.sL) + L.sD);
+  }
+  s->top_size = h->top_m;
+  s->assembly_ms = h->t_assembly;
+  s->factor_ms = h->t_factor;
+  s->last_solve_ms = h->t_solve;
+  s->factor_bytes = bytes;
+  s->factor_flops = h->factor_flops;
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_ranks(ifmm_t h, int level, int* out, int count) {
+  if (!h || !out || level < 2 || level > h->kappa) return IFMM_EINVAL;
+  const Level& L = h->lv[level];
+  if (count < L.nc) return IFMM_EINVAL;
+  for (int i = 0; i < L.nc; ++i) out[i] = L.r[i];
+  return IFMM_OK;
+}
+
+void ifmm_destroy(ifmm_t h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->s);
+  h->release();
+  delete h;
+}
+
+const char* ifmm_status_string(ifmm_status s) {
+  switch (s) {
+    case IFMM_OK: return "ok";
+    case IFMM_EINVAL: return "invalid argument";
+    case IFMM_ENOMEM: return "out of memory";
+    case IFMM_ESINGULAR: return "singular pivot block";
+    case IFMM_ENOTCONV: return "refinement did not converge";
+    case IFMM_EDEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Internal interface between the host orchestrator (ifmm_host.hip) and the
+// device kernels (ifmm_kernels.hip).  Everything is FP64, column-major.
+// Every batched kernel reads an array of descriptors planned on the host;
+// an entry whose sizes are zero is a no-op.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ifmm {
+
+constexpr int kMaxRank = 128;   // largest multipole/local rank supported
+constexpr int kMaxP = 8;        // largest Chebyshev order per dimension
+
+// C = alpha * op(A) op(B) + beta * C; beta == 0 never reads C.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int opA, opB;  // 0: as stored, 1: transposed
+  double alpha, beta;
+};
+
+// C = alpha * op(A) + beta * C (M x N); beta == 0 never reads C.
+struct AddDesc {
+  const double* A;
+  double* C;
+  int M, N, lda, ldc, trans;
+  double alpha, beta;
+};
+
+// X <- T * X * S in place, X is r_old x c_old (ldx); T is r_new x r_old (ldt)
+// or null; S is c_old x c_new (lds), or its transpose when transS, or null.
+struct XformDesc {
+  double* X;
+  const double* T;
+  const double* S;
+  int r_old, c_old, r_new, c_new;
+  int ldx, ldt, lds, transS;
+};
+
+// Householder QR in place: Q (n x K, K = min(n, m)) overwrites A, R (K x m)
+// is written to R; sign-normalised so that R_jj >= 0.
+struct QrDesc {
+  double* A;
+  double* R;
+  int n, m, lda, ldr;
+};
+
+// Column-pivoted Householder QR for up to kmax steps, in place.  Reflector j
+// is u_j (u_j[0] = 1 implicit) stored below the diagonal of column j, with
+// tau[j] and alpha[j] (the signed diagonal).  rank = number of leading steps
+// whose pivot norm exceeds eps * first pivot norm.
+struct RrqrDesc {
+  double* A;
+  double* tau;
+  double* alpha;
+  int* rank;
+  int* steps;
+  int n, m, lda, kmax;
+  double eps;
+};
+
+// Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with
+// column j negated where alpha[j] < 0.
+struct FormQDesc {
+  const double* A;
+  const double* tau;
+  const double* alpha;
+  double* Q;
+  int n, r, kk, lda, ldq;
+};
+
+// One block of a vertical stack whose R factor is wanted.
+struct BlkRef {
+  const double* p;
+  int ld, rows, trans;  // the stacked block is p (rows x cols) or p^T
+};
+// R (r x r, upper triangular, R_jj >= 0) of the QR of the stack of nblk
+// blocks starting at blocks[first]; each block has r columns.
+struct StackQrDesc {
+  double* R;
+  int r, ldr, first, nblk;
+};
+
+// Inverse of a square matrix in place (Gauss-Jordan, partial pivoting).
+struct InvDesc {
+  double* A;
+  int m, lda;
+};
+
+__host__ __device__ inline int demorton_x(int key) {
+  int x = 0;
+  for (int b = 0; b < 15; ++b) x |= ((key >> (2 * b)) & 1) << b;
+  return x;
+}
+__host__ __device__ inline int demorton_y(int key) {
+  int y = 0;
+  for (int b = 0; b < 15; ++b) y |= ((key >> (2 * b + 1)) & 1) << b;
+  return y;
+}
+__host__ __device__ inline int morton2(int x, int y) {
+  int key = 0;
+  for (int b = 0; b < 15; ++b) {
+    key |= ((x >> b) & 1) << (2 * b);
+    key |= ((y >> b) & 1) << (2 * b + 1);
+  }
+  return key;
+}
+// Slot of cluster (jx, jy) in the 6 x 6 window of cluster (ix, iy) -- the
+// children of the parent's 3 x 3 neighbourhood, which holds N_i and I_i --
+// or -1 outside it.
+__host__ __device__ inline int win_slot(int ix, int iy, int jx, int jy) {
+  const int sx = jx - (2 * (ix >> 1) - 2), sy = jy - (2 * (iy >> 1) - 2);
+  if (sx < 0 || sx > 5 || sy < 0 || sy > 5) return -1;
+  return sx * 6 + sy;
+}
+
+struct Status {
+  int singular;     // a zero pivot met
+  int bad_cluster;  // first descriptor index that met it
+};
+
+// ---------------------------------------------------------------- launchers
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, hipStream_t s);
+void launch_add(const AddDesc* d, int nd, int max_m, int max_n, hipStream_t s);
+void launch_xform(const XformDesc* d, int nd, double* scratch, int nwg, int ld_scratch,
+                  hipStream_t s);
+void launch_qr(const QrDesc* d, int nd, hipStream_t s);
+void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s);
+void launch_formq(const FormQDesc* d, int nd, hipStream_t s);
+void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s);
+void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
+
+// ---------------------------------------------------------- problem kernels
+struct KernelFn {
+  int kind;   // 0: 1/r, 1: exp(-r/ell)
+  double ell;
+};
+
+// Chebyshev L2P at the points of each leaf: S (n_i x p^2) into dst + i*stride.
+void launch_leaf_interp(const double* pts, const int* leaf_start, const int* leaf_n,
+                        int nleaf, int kappa, double lox, double loy, double size, int p,
+                        double* dst, size_t stride, int ld, int max_n, hipStream_t s);
+// Near-field blocks of the leaves: dst[i][slot] = K(x_i, x_j), diagonal of the
+// self block replaced by d.
+void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
+                       const int* nbr9, int nleaf, KernelFn kf, const double* d,
+                       double* P, size_t slot_stride, int ld, int max_n, hipStream_t s);
+// Kernel between the Chebyshev nodes of two boxes of half-width h whose
+// centres differ by (dx, dy) * 2h, for the 49 offsets dx, dy in [-3, 3].
+void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s);
+
+// FMM product passes (Chebyshev coordinates, tree order).
+struct FmmLevel {
+  int k, nc;
+  double* W;  // multipole node values [nc][p2][nrhs]
+  double* G;  // local node values     [nc][p2][nrhs]
+  const double* table;  // 49 x p2 x p2
+};
+void launch_p2m(const double* pts, const int* leaf_start, const int* leaf_n, int nleaf,
+                int kappa, double lox, double loy, double size, int p, const double* x, int ldx,
+                int nrhs, double* W, hipStream_t s);
+void launch_m2m(const double* E, int p, int nc_parent, const double* Wc, double* Wp, int nrhs,
+                hipStream_t s);
+void launch_m2l(int p, int k, const double* table, const double* W, double* G, int nrhs,
+                hipStream_t s);
+void launch_l2l(const double* E, int p, int nc_parent, const double* Gp, double* Gc, int nrhs,
+                hipStream_t s);
+void launch_l2p_p2p(const double* pts, const int* leaf_start, const int* leaf_n, const int* nbr9,
+                    int nleaf, int kappa, double lox, double loy, double size, int p,
+                    KernelFn kf, const double* G, const double* x, int ldx, const double* d,
+                    double* y, int ldy, int nrhs, hipStream_t s);
+// out[r] += sum_i x[i + r*ld]^2 (out must be zeroed first).
+void launch_colnorm2(const double* x, int n, int nrhs, int ld, double* out, hipStream_t s);
+void launch_gather_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
+                        double* dst, int ld_dst, hipStream_t s);
+void launch_scatter_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
+                         double* dst, int ld_dst, hipStream_t s);
+
+}  // namespace ifmm

@@ -1,0 +1,536 @@
+// Batched dense linear algebra for the IFMM on gfx950 (FP64).
+//
+// Every kernel consumes an array of descriptors planned on the host, one
+// independent small problem per descriptor (the clusters of one colour batch
+// never share a block, so their problems run concurrently).  Wave size 64,
+// 256-thread workgroups; matrices are column-major.
+#include "ifmm_internal.h"
+
+namespace ifmm {
+
+namespace {
+
+constexpr int WG = 256;
+constexpr int WAVE = 64;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Block-wide sum; every thread gets the result.  red must hold WG/WAVE doubles.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < WG / WAVE; ++i) t += red[i];
+  return t;
+}
+
+// Block-wide argmax of (value, index): largest value, smallest index on ties.
+__device__ inline void block_argmax(double v, int idx, double* rv, int* ri, double& bv, int& bi) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    double ov = __shfl_xor(v, o, WAVE);
+    int oi = __shfl_xor(idx, o, WAVE);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) { rv[w] = v; ri[w] = idx; }
+  __syncthreads();
+  bv = rv[0];
+  bi = ri[0];
+  for (int i = 1; i < WG / WAVE; ++i)
+    if (rv[i] > bv || (rv[i] == bv && ri[i] < bi)) { bv = rv[i]; bi = ri[i]; }
+}
+
+// ------------------------------------------------------------------- GEMM
+// 64 x 64 output tile per workgroup, 4 x 4 per thread, K staged by 16 in LDS.
+__global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs, int tiles_m) {
+  const GemmDesc d = descs[blockIdx.x];
+  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
+  const int m0 = tm * 64, n0 = tn * 64;
+  if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += WG) {
+      int mm, kk;
+      if (d.opA == 0) { mm = e % 64; kk = e / 64; } else { kk = e % 16; mm = e / 16; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < d.M && gk < d.K)
+        v = d.opA == 0 ? d.A[gm + (size_t)gk * d.lda] : d.A[gk + (size_t)gm * d.lda];
+      As[kk][mm] = v;
+      int nn;
+      if (d.opB == 0) { kk = e % 16; nn = e / 16; } else { nn = e % 64; kk = e / 64; }
+      const int gn = n0 + nn;
+      const int gk2 = k0 + kk;
+      double w = 0.0;
+      if (gn < d.N && gk2 < d.K)
+        w = d.opB == 0 ? d.B[gk2 + (size_t)gn * d.ldb] : d.B[gn + (size_t)gk2 * d.ldb];
+      Bs[kk][nn] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gm = m0 + tx + 16 * i, gn = n0 + ty + 16 * j;
+      if (gm < d.M && gn < d.N) {
+        double* c = d.C + gm + (size_t)gn * d.ldc;
+        *c = d.beta == 0.0 ? d.alpha * acc[i][j] : fma(d.alpha, acc[i][j], d.beta * *c);
+      }
+    }
+}
+
+// -------------------------------------------------------------------- ADD
+__global__ __launch_bounds__(WG) void k_add(const AddDesc* __restrict__ descs, int tiles_m) {
+  const AddDesc d = descs[blockIdx.x];
+  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
+  const int m0 = tm * 64, n0 = tn * 64;
+  if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += WG) {
+    const int i = m0 + e % 64, j = n0 + e / 64;
+    if (i < d.M && j < d.N) {
+      const double a = d.A == nullptr ? 0.0
+                       : (d.trans ? d.A[j + (size_t)i * d.lda] : d.A[i + (size_t)j * d.lda]);
+      double* c = d.C + i + (size_t)j * d.ldc;
+      *c = d.beta == 0.0 ? d.alpha * a : fma(d.alpha, a, d.beta * *c);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ XFORM
+// X <- T X S with Z = T X staged in a per-workgroup global scratch.
+__global__ __launch_bounds__(WG) void k_xform(const XformDesc* __restrict__ descs, int nd,
+                                              double* scratch, int ldz) {
+  double* Z = scratch + (size_t)blockIdx.x * ldz * kMaxRank;
+  for (int di = blockIdx.x; di < nd; di += gridDim.x) {
+    const XformDesc d = descs[di];
+    if (d.X == nullptr || (d.T == nullptr && d.S == nullptr)) continue;
+    const int rz = d.T ? d.r_new : d.r_old;  // rows of Z
+    for (int e = threadIdx.x; e < rz * d.c_old; e += WG) {
+      const int i = e % rz, j = e / rz;
+      double v;
+      if (d.T) {
+        v = 0.0;
+        for (int k = 0; k < d.r_old; ++k)
+          v = fma(d.T[i + (size_t)k * d.ldt], d.X[k + (size_t)j * d.ldx], v);
+      } else {
+        v = d.X[i + (size_t)j * d.ldx];
+      }
+      Z[i + (size_t)j * ldz] = v;
+    }
+    __syncthreads();
+    const int cn = d.S ? d.c_new : d.c_old;
+    for (int e = threadIdx.x; e < rz * cn; e += WG) {
+      const int i = e % rz, j = e / rz;
+      double v;
+      if (d.S) {
+        v = 0.0;
+        for (int k = 0; k < d.c_old; ++k) {
+          const double s = d.transS ? d.S[j + (size_t)k * d.lds] : d.S[k + (size_t)j * d.lds];
+          v = fma(Z[i + (size_t)k * ldz], s, v);
+        }
+      } else {
+        v = Z[i + (size_t)j * ldz];
+      }
+      d.X[i + (size_t)j * d.ldx] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------- QR
+__global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m, K = min(n, m);
+  if (d.A == nullptr || K == 0 || K > kMaxRank) return;
+  double* A = d.A;
+  const size_t lda = d.lda;
+  __shared__ double red[WG / WAVE];
+  __shared__ double tau_s[kMaxRank], alpha_s[kMaxRank];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
+  for (int j = 0; j < K; ++j) {
+    double part = 0.0;
+    for (int i = j + threadIdx.x; i < n; i += WG) part += A[i + j * lda] * A[i + j * lda];
+    const double nrm = sqrt(block_sum(part, red));
+    const double x0 = A[j + j * lda];
+    double alpha = 0.0, tau = 0.0, v0 = 1.0;
+    if (nrm > 0.0) {
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tau = -v0 / alpha;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = nrm > 0.0 ? A[i + j * lda] / v0 : 0.0;
+    if (threadIdx.x == 0) { tau_s[j] = tau; alpha_s[j] = alpha; }
+    __syncthreads();
+    for (int c = j + 1 + w; c < m; c += nw) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
+      s = wave_sum(s) + A[j + c * lda];
+      const double ts = tau * s;
+      for (int i = j + 1 + lane; i < n; i += WAVE) A[i + c * lda] -= ts * A[i + j * lda];
+      if (lane == 0) A[j + c * lda] -= ts;
+    }
+    __syncthreads();
+    // row j of R is final now
+    for (int c = threadIdx.x; c < m; c += WG)
+      d.R[j + (size_t)c * d.ldr] = c < j ? 0.0 : (c == j ? alpha : A[j + c * lda]);
+    __syncthreads();
+  }
+  // form Q in place (backward accumulation)
+  for (int j = K - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    for (int c = j + 1 + w; c < K; c += nw) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
+      s = wave_sum(s) + A[j + c * lda];
+      const double ts = tau * s;
+      for (int i = j + 1 + lane; i < n; i += WAVE) A[i + c * lda] -= ts * A[i + j * lda];
+      if (lane == 0) A[j + c * lda] -= ts;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG) {
+      double v;
+      if (i < j) v = 0.0;
+      else if (i == j) v = 1.0 - tau;
+      else v = -tau * A[i + j * lda];
+      A[i + j * lda] = v;
+    }
+    __syncthreads();
+  }
+  // sign normalisation: R_jj >= 0
+  for (int j = 0; j < K; ++j) {
+    if (alpha_s[j] < 0.0) {
+      for (int i = threadIdx.x; i < n; i += WG) A[i + j * lda] = -A[i + j * lda];
+      for (int c = j + threadIdx.x; c < m; c += WG) d.R[j + (size_t)c * d.ldr] = -d.R[j + (size_t)c * d.ldr];
+    }
+  }
+}
+
+// ------------------------------------------------------------------- RRQR
+__global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs) {
+  extern __shared__ double nrm[];  // m entries
+  const RrqrDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int K = min(min(n, m), d.kmax);
+  if (d.A == nullptr) return;
+  double* A = d.A;
+  const size_t lda = d.lda;
+  __shared__ double red[WG / WAVE];
+  __shared__ double rv[WG / WAVE];
+  __shared__ int ri[WG / WAVE];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
+  for (int c = w; c < m; c += nw) {
+    double s = 0.0;
+    for (int i = lane; i < n; i += WAVE) s += A[i + c * lda] * A[i + c * lda];
+    s = wave_sum(s);
+    if (lane == 0) nrm[c] = sqrt(s);
+  }
+  __syncthreads();
+  int rank = 0;
+  bool counting = true;
+  double first = 0.0;
+  for (int j = 0; j < K; ++j) {
+    double bv = -1.0;
+    int bi = m;
+    for (int c = j + threadIdx.x; c < m; c += WG)
+      if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
+    double piv;
+    int cp;
+    block_argmax(bv, bi, rv, ri, piv, cp);
+    if (j == 0) first = piv;
+    if (counting && first > 0.0 && piv > d.eps * first) rank = j + 1;
+    else counting = false;
+    __syncthreads();
+    if (cp != j) {
+      for (int i = threadIdx.x; i < n; i += WG) {
+        const double t = A[i + j * lda];
+        A[i + j * lda] = A[i + cp * lda];
+        A[i + cp * lda] = t;
+      }
+      if (threadIdx.x == 0) { const double t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int i = j + threadIdx.x; i < n; i += WG) part += A[i + j * lda] * A[i + j * lda];
+    const double xn = sqrt(block_sum(part, red));
+    const double x0 = A[j + j * lda];
+    double alpha = 0.0, tau = 0.0, v0 = 1.0;
+    if (xn > 0.0) {
+      alpha = x0 >= 0.0 ? -xn : xn;
+      v0 = x0 - alpha;
+      tau = -v0 / alpha;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0.0 ? A[i + j * lda] / v0 : 0.0;
+    if (threadIdx.x == 0) { d.tau[j] = tau; d.alpha[j] = alpha; A[j + j * lda] = alpha; }
+    __syncthreads();
+    for (int c = j + 1 + w; c < m; c += nw) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
+      s = wave_sum(s) + A[j + c * lda];
+      const double ts = tau * s;
+      double q = 0.0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) {
+        const double v = A[i + c * lda] - ts * A[i + j * lda];
+        A[i + c * lda] = v;
+        q += v * v;
+      }
+      q = wave_sum(q);
+      if (lane == 0) { A[j + c * lda] -= ts; nrm[c] = sqrt(q); }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
+}
+
+// ------------------------------------------------------------------ FORMQ
+__global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ descs) {
+  const FormQDesc d = descs[blockIdx.x];
+  if (d.Q == nullptr || d.r == 0) return;
+  const int n = d.n, r = d.r;
+  const size_t lda = d.lda, ldq = d.ldq;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
+  for (int e = threadIdx.x; e < n * r; e += WG) {
+    const int i = e % n, j = e / n;
+    d.Q[i + j * ldq] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = d.kk - 1; j >= 0; --j) {
+    const double tau = d.tau[j];
+    for (int c = j + w; c < r; c += nw) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) s += d.A[i + j * lda] * d.Q[i + c * ldq];
+      s = wave_sum(s) + d.Q[j + c * ldq];
+      const double ts = tau * s;
+      for (int i = j + 1 + lane; i < n; i += WAVE) d.Q[i + c * ldq] -= ts * d.A[i + j * lda];
+      if (lane == 0) d.Q[j + c * ldq] -= ts;
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < d.kk && j < r; ++j)
+    if (d.alpha[j] < 0.0)
+      for (int i = threadIdx.x; i < n; i += WG) d.Q[i + j * ldq] = -d.Q[i + j * ldq];
+}
+
+// --------------------------------------------------------------- STACK QR
+// R of a tall stack [B_0; B_1; ...] processed block by block: the running R
+// (r x r) and a chunk of the current block live in LDS; each Householder
+// step only touches row j of R and the chunk rows.
+__global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
+                                                const BlkRef* __restrict__ blocks, int chunk) {
+  extern __shared__ double lds[];
+  const StackQrDesc d = descs[blockIdx.x];
+  const int r = d.r;
+  if (d.R == nullptr || r == 0) return;
+  double* R = lds;               // r x r, ld r
+  double* C = lds + r * r;       // chunk x r, ld chunk
+  __shared__ double sv[kMaxRank];  // 2 s / vtv per column
+  for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0.0;
+  __syncthreads();
+  for (int b = 0; b < d.nblk; ++b) {
+    const BlkRef B = blocks[d.first + b];
+    for (int r0 = 0; r0 < B.rows; r0 += chunk) {
+      const int cr = min(chunk, B.rows - r0);
+      for (int e = threadIdx.x; e < cr * r; e += WG) {
+        const int i = e % cr, j = e / cr;
+        const int gi = r0 + i;
+        C[i + j * chunk] = B.trans ? B.p[j + (size_t)gi * B.ld] : B.p[gi + (size_t)j * B.ld];
+      }
+      __syncthreads();
+      for (int j = 0; j < r; ++j) {
+        // reflector of x = [R_jj; C[:, j]]
+        double s2 = 0.0;
+        for (int i = 0; i < cr; ++i) s2 += C[i + j * chunk] * C[i + j * chunk];
+        const double rjj = R[j + j * r];
+        const double nrm = sqrt(rjj * rjj + s2);
+        if (s2 == 0.0 || nrm == 0.0) continue;  // nothing below the diagonal: H = I
+        const double alpha = rjj >= 0.0 ? -nrm : nrm;
+        const double v0 = rjj - alpha;
+        const double vtv = -2.0 * alpha * v0;
+        for (int c = j + 1 + (int)threadIdx.x; c < r; c += WG) {
+          double s = v0 * R[j + c * r];
+          for (int i = 0; i < cr; ++i) s += C[i + j * chunk] * C[i + c * chunk];
+          sv[c] = 2.0 * s / vtv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < (r - j - 1) * (cr + 1); e += WG) {
+          const int c = j + 1 + e / (cr + 1), i = e % (cr + 1);
+          if (i == cr) R[j + c * r] -= sv[c] * v0;
+          else C[i + c * chunk] -= sv[c] * C[i + j * chunk];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) R[j + j * r] = alpha;
+        for (int i = threadIdx.x; i < cr; i += WG) C[i + j * chunk] = 0.0;
+        __syncthreads();
+      }
+    }
+  }
+  for (int e = threadIdx.x; e < r * r; e += WG) {
+    const int i = e % r, j = e / r;
+    double v = j < i ? 0.0 : R[i + j * r];
+    if (R[i + i * r] < 0.0) v = -v;
+    d.R[i + (size_t)j * d.ldr] = v;
+  }
+}
+
+// ---------------------------------------------------------------- INVERSE
+// Gauss-Jordan with partial pivoting (first largest |a| wins ties), in place.
+__global__ __launch_bounds__(WG) void k_inverse(const InvDesc* __restrict__ descs, Status* st) {
+  extern __shared__ double sh[];  // f[m], row[m]
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr || m == 0) return;
+  double* A = d.A;
+  const size_t lda = d.lda;
+  double* f = sh;
+  double* rowj = sh + m;
+  int* piv = reinterpret_cast<int*>(sh + 2 * m);
+  __shared__ double rv[WG / WAVE];
+  __shared__ int ri[WG / WAVE];
+  bool bad = false;
+  for (int j = 0; j < m; ++j) {
+    double bv = -1.0;
+    int bi = m;
+    for (int i = j + threadIdx.x; i < m; i += WG) {
+      const double a = fabs(A[i + j * lda]);
+      if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
+    }
+    double pv;
+    int p;
+    block_argmax(bv, bi, rv, ri, pv, p);
+    if (threadIdx.x == 0) piv[j] = p;
+    if (p != j)
+      for (int c = threadIdx.x; c < m; c += WG) {
+        const double t = A[j + c * lda];
+        A[j + c * lda] = A[p + c * lda];
+        A[p + c * lda] = t;
+      }
+    __syncthreads();
+    const double djj = A[j + j * lda];
+    if (djj == 0.0) bad = true;
+    const double inv = 1.0 / djj;
+    for (int i = threadIdx.x; i < m; i += WG) f[i] = A[i + j * lda];
+    for (int c = threadIdx.x; c < m; c += WG) rowj[c] = c == j ? inv : A[j + c * lda] * inv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += WG) {
+      const int i = e % m, c = e / m;
+      if (i == j) {
+        A[i + c * lda] = rowj[c];
+      } else if (c == j) {
+        A[i + c * lda] = -f[i] * inv;
+      } else {
+        A[i + c * lda] -= f[i] * rowj[c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const int p = piv[j];
+    if (p != j)
+      for (int i = threadIdx.x; i < m; i += WG) {
+        const double t = A[i + j * lda];
+        A[i + j * lda] = A[i + p * lda];
+        A[i + p * lda] = t;
+      }
+    __syncthreads();
+  }
+  if (bad && threadIdx.x == 0 && st) {
+    if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
+  }
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  hipLaunchKernelGGL(k_gemm, dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
+}
+
+void launch_add(const AddDesc* d, int nd, int max_m, int max_n, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  hipLaunchKernelGGL(k_add, dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
+}
+
+void launch_xform(const XformDesc* d, int nd, double* scratch, int nwg, int ld_scratch,
+                  hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_xform, dim3(nd < nwg ? nd : nwg), dim3(WG), 0, s, d, nd, scratch,
+                     ld_scratch);
+}
+
+void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_qr, dim3(nd), dim3(WG), 0, s, d);
+}
+
+void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_rrqr, dim3(nd), dim3(WG), sizeof(double) * (max_m > 0 ? max_m : 1), s, d);
+}
+
+void launch_formq(const FormQDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_formq, dim3(nd), dim3(WG), 0, s, d);
+}
+
+void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
+  if (nd <= 0 || max_r <= 0) return;
+  const size_t rr = (size_t)max_r * max_r * sizeof(double);
+  const size_t row = sizeof(double) * max_r;
+  // stay within 64 KiB when a 16-row chunk fits, else use up to 150 KiB of
+  // the 160 KiB LDS of a gfx950 CU
+  const size_t budget = rr + 16 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
+  int chunk = (int)((budget - rr) / row);
+  if (chunk > kMaxRank) chunk = kMaxRank;
+  if (chunk < 1) chunk = 1;
+  const size_t lds = rr + (size_t)chunk * row;
+  if (lds > 64 * 1024) {
+    static bool raised = false;
+    if (!raised) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_stackqr),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      raised = true;
+    }
+  }
+  hipLaunchKernelGGL(k_stackqr, dim3(nd), dim3(WG), lds, s, d, b, chunk);
+}
+
+void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0) return;
+  const size_t lds = sizeof(double) * 2 * max_m + sizeof(int) * max_m;
+  hipLaunchKernelGGL(k_inverse, dim3(nd), dim3(WG), lds, s, d, st);
+}
+
+}  // namespace ifmm

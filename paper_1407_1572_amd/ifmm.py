@@ -1,0 +1,194 @@
+"""Thin Python binding of the IFMM C-ABI (include/ifmm.h).
+
+Argument marshalling only: every step of the factorisation and solve runs in
+the gfx950 library ``libifmm.so`` built in this package directory.  Importing
+this module does not load the library; constructing a solver does, and fails
+loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libifmm.so")
+
+KERNELS = {"inv_r": 0, "exp": 1}
+DIAG = {"rowsum": 0, "const": 1}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "singular pivot block",
+          4: "refinement did not converge", 5: "HIP device error"}
+
+
+class IFMMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)} (status {code})")
+        self.code = code
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("ell", C.c_double), ("diag_mode", C.c_int), ("c0", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("r_max", C.c_int), ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
+                ("box_lo", C.c_double * 2), ("box_size", C.c_double)]
+
+
+class _SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("residual", C.c_double), ("history", C.c_double * 32),
+                ("solve_ms", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("kappa", C.c_int), ("p", C.c_int), ("max_rank", C.c_int),
+                ("level_max_rank", C.c_int * 16), ("level_mean_rank", C.c_double * 16),
+                ("top_size", C.c_int), ("assembly_ms", C.c_double), ("factor_ms", C.c_double),
+                ("last_solve_ms", C.c_double), ("factor_bytes", C.c_double),
+                ("factor_flops", C.c_double)]
+
+
+_LIBS: dict = {}
+
+
+def load(path: str | None = None):
+    """Load (once) and type the C-ABI library; raises if it is missing."""
+    path = path or LIB_PATH
+    if path in _LIBS:
+        return _LIBS[path]
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"IFMM library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.ifmm_factor.argtypes = [P, C.c_int64, C.POINTER(_Kernel), C.c_double, C.c_int, C.c_int,
+                                C.POINTER(_Options), P, C.POINTER(P)]
+    lib.ifmm_factor.restype = C.c_int
+    lib.ifmm_solve.argtypes = [P, P, P, C.c_int, P, C.POINTER(_SolveInfo)]
+    lib.ifmm_solve.restype = C.c_int
+    lib.ifmm_matvec.argtypes = [P, P, P, C.c_int, P]
+    lib.ifmm_matvec.restype = C.c_int
+    lib.ifmm_diagonal.argtypes = [P, P, P]
+    lib.ifmm_diagonal.restype = C.c_int
+    lib.ifmm_stats.argtypes = [P, C.POINTER(_Stats)]
+    lib.ifmm_stats.restype = C.c_int
+    lib.ifmm_ranks.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_int]
+    lib.ifmm_ranks.restype = C.c_int
+    lib.ifmm_destroy.argtypes = [P]
+    lib.ifmm_destroy.restype = None
+    lib.ifmm_status_string.argtypes = [C.c_int]
+    lib.ifmm_status_string.restype = C.c_char_p
+    _LIBS[path] = lib
+    return lib
+
+
+def _stream_handle(t):
+    import torch
+    if t.is_cuda:
+        return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+    return C.c_void_p(0)
+
+
+class IFMMSolver:
+    """ifmm_factor(points, kernel, eps, leaf_size, rank) / ifmm_solve(b).
+
+    points: torch float64 tensor [N, 2] on the GPU.  b for ``solve`` is [N]
+    or [N, nrhs] on the same device.
+    """
+
+    def __init__(self, points, kernel: str = "inv_r", ell: float = 0.0, diag: str = "rowsum",
+                 c0: float = 1.0, eps: float = 1e-8, leaf_size: int = 64, rank: int = 36,
+                 r_max: int = 0, refine_tol: float = 0.0, refine_maxit: int = 30,
+                 box=None, lib_path: str | None = None):
+        import torch
+        self._lib = load(lib_path)
+        if lib_path is None and not points.is_cuda:
+            raise ValueError("points must be a GPU tensor")
+        pts = points.to(torch.float64).contiguous()
+        self.n = int(pts.shape[0])
+        self.device = pts.device
+        k = _Kernel(KERNELS[kernel], float(ell), DIAG[diag], float(c0))
+        o = _Options()
+        o.r_max = int(r_max)
+        o.refine_tol = float(refine_tol)
+        o.refine_maxit = int(refine_maxit)
+        if box is not None:
+            o.box_lo[0], o.box_lo[1], o.box_size = float(box[0]), float(box[1]), float(box[2])
+        h = C.c_void_p()
+        st = self._lib.ifmm_factor(C.c_void_p(pts.data_ptr()), self.n, C.byref(k), float(eps),
+                                   int(leaf_size), int(rank), C.byref(o), _stream_handle(pts),
+                                   C.byref(h))
+        if st != 0:
+            raise IFMMError(st, "ifmm_factor")
+        self._h = h
+        self.last_info = None
+
+    def _cols(self, v):
+        import torch
+        v = v.to(device=self.device, dtype=torch.float64)
+        one = v.dim() == 1
+        vt = (v.reshape(1, -1) if one else v.t()).contiguous()  # [nrhs][N]
+        return vt, one
+
+    def solve(self, b, check: bool = True):
+        import torch
+        bt, one = self._cols(b)
+        xt = torch.empty_like(bt)
+        info = _SolveInfo()
+        st = self._lib.ifmm_solve(self._h, C.c_void_p(bt.data_ptr()), C.c_void_p(xt.data_ptr()),
+                                  int(bt.shape[0]), _stream_handle(bt), C.byref(info))
+        self.last_info = {"iterations": info.iterations, "residual": info.residual,
+                          "history": list(info.history[:max(1, info.iterations + 1)]),
+                          "solve_ms": info.solve_ms, "status": st}
+        if st != 0 and (check or st != 4):
+            raise IFMMError(st, "ifmm_solve")
+        return xt[0] if one else xt.t()
+
+    def matvec(self, x):
+        import torch
+        xt, one = self._cols(x)
+        yt = torch.empty_like(xt)
+        st = self._lib.ifmm_matvec(self._h, C.c_void_p(xt.data_ptr()), C.c_void_p(yt.data_ptr()),
+                                   int(xt.shape[0]), _stream_handle(xt))
+        if st != 0:
+            raise IFMMError(st, "ifmm_matvec")
+        return yt[0] if one else yt.t()
+
+    def diagonal(self):
+        import torch
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        st = self._lib.ifmm_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_handle(d))
+        if st != 0:
+            raise IFMMError(st, "ifmm_diagonal")
+        return d
+
+    def stats(self) -> dict:
+        s = _Stats()
+        st = self._lib.ifmm_stats(self._h, C.byref(s))
+        if st != 0:
+            raise IFMMError(st, "ifmm_stats")
+        k = s.kappa
+        return {"n": s.n, "kappa": k, "p": s.p, "max_rank": s.max_rank,
+                "level_max_rank": {l: s.level_max_rank[l] for l in range(2, k + 1)},
+                "level_mean_rank": {l: s.level_mean_rank[l] for l in range(2, k + 1)},
+                "top_size": s.top_size, "assembly_ms": s.assembly_ms, "factor_ms": s.factor_ms,
+                "last_solve_ms": s.last_solve_ms, "factor_bytes": s.factor_bytes,
+                "factor_flops": s.factor_flops}
+
+    def ranks(self, level: int) -> np.ndarray:
+        out = (C.c_int * (4 ** level))()
+        st = self._lib.ifmm_ranks(self._h, int(level), out, 4 ** level)
+        if st != 0:
+            raise IFMMError(st, "ifmm_ranks")
+        return np.frombuffer(out, dtype=np.int32).copy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ifmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
