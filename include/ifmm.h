@@ -71,6 +71,7 @@ typedef struct {
   int refine_maxit;    /* refinement sweeps (0 = 30) */
   double box_lo[2];    /* root box [lo, lo + size]^2 containing every point */
   double box_size;     /* 0 = unit square [0,1]^2 */
+  int profile;         /* 1: time every batched kernel launch with HIP events (ifmm_stats) */
 } ifmm_options;
 
 typedef struct {
@@ -93,6 +94,14 @@ typedef struct {
   double last_solve_ms;    /* t_s of the last ifmm_solve (including refinement) */
   double factor_bytes;     /* device bytes held by the factor */
   double factor_flops;     /* counted FP64 flops of the factorisation */
+  /* With ifmm_options.profile: per batched-kernel family, accumulated over the
+     handle's life -- 0 gemm, 1 add/copy, 2 basis transform, 3 Householder QR,
+     4 column-pivoted QR, 5 basis formation, 6 stacked R factor, 7 pivot inverse.
+     flops / bytes are the algorithmic counts of the launches. */
+  int64_t kernel_launches[8];
+  double kernel_ms[8];
+  double kernel_flops[8];
+  double kernel_bytes[8];
 } ifmm_stats_t;
 
 /*

@@ -57,10 +57,12 @@ inline int rup(int a, int b) { return (a + b - 1) / b * b; }
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_INV };
+constexpr int kOpTypes = 8;
 struct Op {
   OpType t;
   size_t off, off2;
   int count, a, b;
+  double flops, bytes;  // algorithmic work of the launch
 };
 
 struct Stage {
@@ -73,68 +75,107 @@ struct Stage {
     std::memcpy(blob.data() + off, p, n);
     return off;
   }
+  // Algorithmic counts: flops of the operation as defined, bytes = every
+  // operand read once and every output written once (8-byte words).
   void gemm(const std::vector<GemmDesc>& v) {
     if (v.empty()) return;
     int mm = 0, nn = 0;
+    double f = 0, by = 0;
     for (const auto& d : v) {
       mm = std::max(mm, d.M);
       nn = std::max(nn, d.N);
-      flops += 2.0 * d.M * d.N * d.K;
+      f += 2.0 * d.M * d.N * d.K;
+      by += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     }
-    ops.push_back({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn});
+    flops += f;
+    ops.push_back({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn, f, by});
   }
   void add(const std::vector<AddDesc>& v) {
     if (v.empty()) return;
     int mm = 0, nn = 0;
+    double by = 0;
     for (const auto& d : v) {
       mm = std::max(mm, d.M);
       nn = std::max(nn, d.N);
+      by += 8.0 * d.M * d.N * ((d.A ? 1.0 : 0.0) + (d.beta != 0.0 ? 2.0 : 1.0));
     }
-    ops.push_back({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn});
+    ops.push_back({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn, 0.0, by});
   }
   void xform(const std::vector<XformDesc>& v) {
     if (v.empty()) return;
-    for (const auto& d : v)
-      flops += 2.0 * (d.T ? d.r_new * d.r_old * d.c_old : 0) +
-               2.0 * (d.S ? (d.T ? d.r_new : d.r_old) * d.c_old * d.c_new : 0);
-    ops.push_back({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0});
+    double f = 0, by = 0;
+    for (const auto& d : v) {
+      const int rz = d.T ? d.r_new : d.r_old, cn = d.S ? d.c_new : d.c_old;
+      f += 2.0 * (d.T ? (double)d.r_new * d.r_old * d.c_old : 0) + 2.0 * (d.S ? (double)rz * d.c_old * d.c_new : 0);
+      by += 8.0 * ((double)d.r_old * d.c_old + (d.T ? (double)d.r_new * d.r_old : 0) +
+                   (d.S ? (double)d.c_old * d.c_new : 0) + (double)rz * cn);
+    }
+    flops += f;
+    ops.push_back({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0, f, by});
   }
   void qr(const std::vector<QrDesc>& v) {
     if (v.empty()) return;
-    for (const auto& d : v) flops += 4.0 * d.n * d.m * std::min(d.n, d.m);
-    ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0});
+    double f = 0, by = 0;
+    for (const auto& d : v) {
+      const double K = std::min(d.n, d.m);
+      f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
+           + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
+      by += 8.0 * (2.0 * d.n * d.m + K * d.m);
+    }
+    flops += f;
+    ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by});
   }
   void rrqr(const std::vector<RrqrDesc>& v) {
     if (v.empty()) return;
     int mm = 0;
+    double f = 0, by = 0;
     for (const auto& d : v) {
       mm = std::max(mm, d.m);
-      flops += 4.0 * d.n * d.m * std::min(std::min(d.n, d.m), d.kmax);
+      const int K = std::min(std::min(d.n, d.m), d.kmax);
+      for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
+      by += 16.0 * d.n * (double)d.m;
     }
-    ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), 0, (int)v.size(), mm, 0});
+    flops += f;
+    ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), 0, (int)v.size(), mm, 0, f, by});
   }
   void formq(const std::vector<FormQDesc>& v) {
     if (v.empty()) return;
-    for (const auto& d : v) flops += 4.0 * d.n * d.r * d.kk;
-    ops.push_back({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0});
+    double f = 0, by = 0;
+    for (const auto& d : v) {
+      for (int j = 0; j < d.kk; ++j) f += 4.0 * (d.n - j) * (double)(d.r - j);
+      by += 8.0 * ((double)d.n * d.kk + (double)d.n * d.r);
+    }
+    flops += f;
+    ops.push_back({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0, f, by});
   }
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
     if (v.empty()) return;
     int rr = 0;
-    for (const auto& d : v) rr = std::max(rr, d.r);
-    for (const auto& x : b) flops += 2.0 * x.rows * rr * rr;
+    double f = 0, by = 0;
+    for (const auto& d : v) {
+      rr = std::max(rr, d.r);
+      for (int t = 0; t < d.nblk; ++t) {
+        f += 2.0 * b[d.first + t].rows * (double)d.r * d.r;
+        by += 8.0 * b[d.first + t].rows * (double)d.r;
+      }
+      by += 8.0 * d.r * d.r;
+    }
+    flops += f;
     size_t o1 = push(v.data(), v.size() * sizeof(StackQrDesc));
     size_t o2 = push(b.data(), std::max<size_t>(1, b.size()) * sizeof(BlkRef));
-    ops.push_back({OP_STACKQR, o1, o2, (int)v.size(), rr, 0});
+    ops.push_back({OP_STACKQR, o1, o2, (int)v.size(), rr, 0, f, by});
   }
   void inv(const std::vector<InvDesc>& v) {
     if (v.empty()) return;
     int mm = 0;
+    double f = 0, by = 0;
     for (const auto& d : v) {
       mm = std::max(mm, d.m);
-      flops += 2.0 * d.m * d.m * (double)d.m;
+      f += 2.0 * d.m * d.m * (double)d.m;
+      by += 16.0 * d.m * (double)d.m;
     }
-    ops.push_back({OP_INV, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0});
+    flops += f;
+    ops.push_back({OP_INV, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by});
   }
   bool empty() const { return ops.empty(); }
   void clear() {
@@ -356,12 +397,54 @@ struct ifmm_plan {
   // stats
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
   int max_rank = 0;
+  // per-kernel profile (HIP events around each batched launch)
+  bool profile = false;
+  struct Pending {
+    int t;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pend;
+  std::vector<hipEvent_t> evpool;
+  double prof_ms[kOpTypes] = {}, prof_flops[kOpTypes] = {}, prof_bytes[kOpTypes] = {};
+  long prof_launch[kOpTypes] = {};
+  hipEvent_t get_event() {
+    if (!evpool.empty()) {
+      hipEvent_t e = evpool.back();
+      evpool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    return e;
+  }
+  void resolve_profile() {
+    if (pend.empty()) return;
+    HIP_OK(hipStreamSynchronize(s));
+    for (const Pending& p : pend) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, p.a, p.b));
+      prof_ms[p.t] += ms;
+      prof_flops[p.t] += p.flops;
+      prof_bytes[p.t] += p.bytes;
+      prof_launch[p.t] += 1;
+      evpool.push_back(p.a);
+      evpool.push_back(p.b);
+    }
+    pend.clear();
+  }
 
   void run(Stage& st) {
     if (st.empty()) return;
     factor_flops += st.flops;
     char* d = arena.upload(st.blob, s);
     for (const Op& op : st.ops) {
+      hipEvent_t ea = nullptr, eb = nullptr;
+      if (profile) {
+        ea = get_event();
+        eb = get_event();
+        HIP_OK(hipEventRecord(ea, s));
+      }
       switch (op.t) {
         case OP_GEMM: launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, s); break;
         case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, s); break;
@@ -381,6 +464,11 @@ struct ifmm_plan {
         case OP_INV: launch_inverse(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
       }
       HIP_OK(hipGetLastError());
+      if (profile) {
+        HIP_OK(hipEventRecord(eb, s));
+        pend.push_back({(int)op.t, ea, eb, op.flops, op.bytes});
+        if (pend.size() > 4096) resolve_profile();
+      }
     }
     st.clear();
   }
@@ -717,6 +805,7 @@ struct ifmm_plan {
     }
     top();
     HIP_OK(hipStreamSynchronize(s));
+    resolve_profile();
     Status hs{};
     HIP_OK(hipMemcpy(&hs, d_status, sizeof(Status), hipMemcpyDeviceToHost));
     if (hs.singular) throw 3;
@@ -1295,6 +1384,13 @@ struct ifmm_plan {
     d_rank = nullptr;
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec}) b->release();
     arena.release();
+    for (const Pending& p : pend) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    pend.clear();
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    evpool.clear();
   }
 };
 
@@ -1354,6 +1450,7 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
     h->size = opt->box_size;
   }
   if (opt) {
+    h->profile = opt->profile != 0;
     h->refine_tol = opt->refine_tol;
     h->refine_maxit = opt->refine_maxit > 0 ? opt->refine_maxit : 30;
   }
@@ -1458,6 +1555,7 @@ ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* str
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(h->s));
     h->t_solve = now_ms() - t0;
+    h->resolve_profile();
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->iterations = it;
@@ -1500,6 +1598,12 @@ ifmm_status ifmm_stats(ifmm_t h, ifmm_stats_t* s) {
   s->last_solve_ms = h->t_solve;
   s->factor_bytes = bytes;
   s->factor_flops = h->factor_flops;
+  for (int t = 0; t < kOpTypes; ++t) {
+    s->kernel_launches[t] = h->prof_launch[t];
+    s->kernel_ms[t] = h->prof_ms[t];
+    s->kernel_flops[t] = h->prof_flops[t];
+    s->kernel_bytes[t] = h->prof_bytes[t];
+  }
   return IFMM_OK;
 }
 
