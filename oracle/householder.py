@@ -95,3 +95,4 @@ def basis_from_reflectors(n: int, vs, alphas, r: int) -> np.ndarray:
         if alphas[j] < 0:
             Q[:, j] = -Q[:, j]
     return Q
+

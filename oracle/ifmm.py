@@ -40,6 +40,9 @@ Readings where the paper is silent (all listed in the design doc):
   Omega_q weights the existing far field: R factor of the QR of the
   transposed M2L row of q joined with the parent chain UP[q] Omega_parent^T
   (precomputed top-down from the assembled operators);
+* symmetric kernels: the reordered extended system is symmetric (P2M is the
+  transpose of L2P), so the column basis equals the row basis -- only the row
+  side is compressed and V^ = U^;
 * level transition re-orthonormalises the parent bases by Householder QR.
 """
 from __future__ import annotations
@@ -63,8 +66,9 @@ def _z(a, b):
 class IFMM:
     def __init__(self, points, kernel: Kernel, eps: float, leaf_size: int, p: int,
                  diag_mode: str = "rowsum", c0: float = 1.0, r_cap: int | None = None,
-                 lo=(0.0, 0.0), size: float = 1.0):
+                 lo=(0.0, 0.0), size: float = 1.0, symmetric: bool | None = None):
         self.tree = Tree(points, leaf_size, lo, size)
+        self.symmetric = (kernel.kind != "callable") if symmetric is None else bool(symmetric)
         self.kernel = kernel
         self.eps = float(eps)
         self.p = int(p)
@@ -290,13 +294,18 @@ class IFMM:
         for q in touched:
             Om, Omp = self._weights(k, q)
             AU = np.hstack([self.U[k][q] @ Om.T] + rowf[q])
-            AV = np.hstack([self.V[k][q] @ Omp.T] + colf[q])
             kmax = min(int(n[q]), self.r_cap)
             kU, vU, aU = hh.pivoted_qr(AU, self.eps, kmax)
-            kV, vV, aV = hh.pivoted_qr(AV, self.eps, kmax)
-            rh = min(max(kU, kV), int(n[q]), self.r_cap)
-            Uh = hh.basis_from_reflectors(int(n[q]), vU, aU, rh)
-            Vh = hh.basis_from_reflectors(int(n[q]), vV, aV, rh)
+            if self.symmetric:
+                rh = min(kU, int(n[q]), self.r_cap)
+                Uh = hh.basis_from_reflectors(int(n[q]), vU, aU, rh)
+                Vh = Uh
+            else:
+                AV = np.hstack([self.V[k][q] @ Omp.T] + colf[q])
+                kV, vV, aV = hh.pivoted_qr(AV, self.eps, kmax)
+                rh = min(max(kU, kV), int(n[q]), self.r_cap)
+                Uh = hh.basis_from_reflectors(int(n[q]), vU, aU, rh)
+                Vh = hh.basis_from_reflectors(int(n[q]), vV, aV, rh)
             Tq[q] = Uh.T @ self.U[k][q]
             Sq[q] = self.V[k][q].T @ Vh
             new[q] = (Uh, Vh, rh)

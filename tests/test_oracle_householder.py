@@ -49,3 +49,4 @@ def test_pivoted_qr_first_pivot_is_largest_column_and_threshold_is_relative():
     B = rng.standard_normal((30, 4)) @ np.diag([1, 1e-3, 1e-7, 1e-12]) @ rng.standard_normal((4, 30))
     for s in (1e-8, 1.0, 1e8):
         assert hh.pivoted_qr(s * B, 1e-9, 30)[0] == 3
+

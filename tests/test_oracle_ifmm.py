@@ -207,3 +207,14 @@ def test_planted_mistakes_break_the_eps0_pin(monkeypatch):
 
     monkeypatch.setattr(IFMM, "_compress", skip_parent_update)
     assert err() > 1e-6
+
+
+def test_symmetric_mode_agrees_with_two_sided_compression():
+    # for a symmetric kernel the row and column compressions coincide, so the
+    # one-sided (symmetric) variant must reproduce the general one
+    pts = workloads.points_for("c1_invr_2k", 1024)
+    b = workloads.rhs(1024, 1, 4)[:, 0]
+    xs = IFMM(pts, Kernel("inv_r"), 1e-7, 16, 4, "rowsum", 1.0, symmetric=True).factor().solve(b)
+    og = IFMM(pts, Kernel("inv_r"), 1e-7, 16, 4, "rowsum", 1.0, symmetric=False).factor()
+    xg = og.solve(b)
+    assert np.linalg.norm(xs - xg) / np.linalg.norm(xg) < 1e-7
