@@ -3,6 +3,10 @@
 // compression of well-separated fill), Algorithm 2 (back substitution), the
 // FMM product and FP64 iterative refinement, behind the C-ABI of ifmm.h.
 //
+// The kernels of the C-ABI are radial, hence symmetric: the reordered extended
+// system is symmetric (P2M = L2P^T), so every cluster carries one basis
+// (V = U, VP = UP) and fill is compressed from the row side only.
+//
 // The host plans integer work only (which block feeds which batched kernel);
 // every floating-point step runs in the gfx950 kernels.  Per colour phase the
 // host reads back the new ranks once (they decide the block shapes of the
@@ -54,15 +58,18 @@ void dfree(T*& p) {
 }
 
 inline int rup(int a, int b) { return (a + b - 1) / b * b; }
+constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
 
 // ------------------------------------------------------------ descriptor stages
-enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_INV };
-constexpr int kOpTypes = 8;
+enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_INV, OP_GJPANEL, OP_GJREST, OP_GJUNPERM };
+constexpr int kOpTypes = 8;  // profile families; the three blocked-inverse pieces count as 7
+inline int family(int t) { return t >= 8 ? 7 : t; }
 struct Op {
   OpType t;
   size_t off, off2;
   int count, a, b;
   double flops, bytes;  // algorithmic work of the launch
+  size_t off2b = 0;
 };
 
 struct Stage {
@@ -125,18 +132,30 @@ struct Stage {
     flops += f;
     ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by});
   }
-  void rrqr(const std::vector<RrqrDesc>& v) {
-    if (v.empty()) return;
-    int mm = 0;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      mm = std::max(mm, d.m);
-      const int K = std::min(std::min(d.n, d.m), d.kmax);
-      for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
-      by += 16.0 * d.n * (double)d.m;
+  void rrqr(const std::vector<RrqrDesc>& all) {
+    if (all.empty()) return;
+    // matrices that fit in LDS go to the LDS kernel (b = 1), the rest stream
+    std::vector<RrqrDesc> grp[2];
+    for (const auto& d : all) {
+      const size_t need = sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m);
+      grp[need <= kRrqrLdsBytes ? 1 : 0].push_back(d);
     }
-    flops += f;
-    ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), 0, (int)v.size(), mm, 0, f, by});
+    for (int g = 0; g < 2; ++g) {
+      const auto& v = grp[g];
+      if (v.empty()) continue;
+      int mm = 0;
+      size_t lds = 0;
+      double f = 0, by = 0;
+      for (const auto& d : v) {
+        mm = std::max(mm, d.m);
+        lds = std::max(lds, sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m));
+        const int K = std::min(std::min(d.n, d.m), d.kmax);
+        for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
+        by += 16.0 * d.n * (double)d.m;
+      }
+      flops += f;
+      ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), (size_t)lds, (int)v.size(), mm, g, f, by});
+    }
   }
   void formq(const std::vector<FormQDesc>& v) {
     if (v.empty()) return;
@@ -176,6 +195,50 @@ struct Stage {
     }
     flops += f;
     ops.push_back({OP_INV, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by});
+  }
+  // Blocked Gauss-Jordan inverse of every matrix in v (panels of nb columns);
+  // piv (nd x maxm ints) and tmp (nd x nb x maxm doubles) are device workspace.
+  void inv_blocked(const std::vector<InvDesc>& v, int* piv, double* tmp, int nb) {
+    if (v.empty()) return;
+    int mm = 0;
+    for (const auto& d : v) mm = std::max(mm, d.m);
+    const size_t o = push(v.data(), v.size() * sizeof(InvDesc));
+    const int nd = (int)v.size();
+    const size_t ldt = (size_t)nb * mm;
+    for (int j0 = 0; j0 < mm; j0 += nb) {
+      double fp = 0, bp = 0;
+      for (const auto& d : v)
+        if (d.m > j0) {
+          const int nbe = std::min(nb, d.m - j0);
+          fp += 3.0 * d.m * nbe * nbe;
+          bp += 16.0 * d.m * nbe;
+        }
+      ops.push_back({OP_GJPANEL, o, (size_t)(uintptr_t)piv, nd, mm, j0, fp, bp});
+      ops.push_back({OP_GJREST, o, (size_t)(uintptr_t)tmp, nd, mm, j0, 0.0, 0.0});
+      ops.back().off2b = (size_t)(uintptr_t)piv;
+      std::vector<GemmDesc> g;
+      for (int b = 0; b < nd; ++b) {
+        const InvDesc& d = v[b];
+        if (d.m <= j0) continue;
+        const int nbe = std::min(nb, d.m - j0);
+        double* A = d.A;
+        const size_t lda = d.lda;
+        double* tb = tmp + (size_t)b * ldt;
+        const int cr[2][2] = {{0, j0}, {j0 + nbe, d.m}};
+        for (const auto& c : cr) {
+          if (c[1] <= c[0]) continue;
+          g.push_back({A + j0 + j0 * lda, tb + (size_t)c[0] * nb, A + j0 + (size_t)c[0] * lda, nbe, c[1] - c[0],
+                       nbe, (int)lda, nb, (int)lda, 0, 0, 1.0, 0.0});
+          for (const auto& r : cr) {
+            if (r[1] <= r[0]) continue;
+            g.push_back({A + r[0] + j0 * lda, tb + (size_t)c[0] * nb, A + r[0] + (size_t)c[0] * lda, r[1] - r[0],
+                         c[1] - c[0], nbe, (int)lda, nb, (int)lda, 0, 0, 1.0, 1.0});
+          }
+        }
+      }
+      gemm(g);
+    }
+    ops.push_back({OP_GJUNPERM, o, (size_t)(uintptr_t)piv, nd, mm, 0, 0.0, 0.0});
   }
   bool empty() const { return ops.empty(); }
   void clear() {
@@ -314,19 +377,18 @@ struct Level {
   std::vector<int> n, r, colour, nbr9, choff;  // choff: [nc*4] offsets of children's multipoles
   int npad = 0, rpad = 0, mpad = 0;
   size_t sP = 0, sQ = 0, sL = 0, sM = 0, sU = 0, sUP = 0, sD = 0;
-  double *P = nullptr, *Qm = nullptr, *L = nullptr, *M = nullptr, *U = nullptr, *V = nullptr,
-         *UP = nullptr, *VP = nullptr, *Dinv = nullptr, *Om = nullptr, *Omp = nullptr;
+  // one basis per cluster (symmetric system): U is both L2P and P2M^T, UP the
+  // parent's transfer block of this child, Om the precomputed far-field weight
+  double *P = nullptr, *Qm = nullptr, *L = nullptr, *M = nullptr, *U = nullptr, *UP = nullptr,
+         *Dinv = nullptr, *Om = nullptr;
   double* Pb(int i, int s) const { return P + ((size_t)i * 9 + s) * sP; }
   double* Qb(int i, int s) const { return Qm + ((size_t)i * 9 + s) * sQ; }
   double* Lb(int i, int s) const { return L + ((size_t)i * 9 + s) * sL; }
   double* Mb(int i, int s) const { return M + ((size_t)i * 36 + s) * sM; }
   double* Ub(int i) const { return U + (size_t)i * sU; }
-  double* Vb(int i) const { return V + (size_t)i * sU; }
   double* UPb(int i) const { return UP + (size_t)i * sUP; }
-  double* VPb(int i) const { return VP + (size_t)i * sUP; }
   double* Db(int i) const { return Dinv + (size_t)i * sD; }
   double* Omb(int i) const { return Om + (size_t)i * sUP; }
-  double* Ompb(int i) const { return Omp + (size_t)i * sUP; }
   void set_pads(int np) {
     npad = np;
     mpad = npad + rpad;
@@ -341,11 +403,8 @@ struct Level {
   void free_work() {
     dfree(M);
     dfree(U);
-    dfree(V);
     dfree(UP);
-    dfree(VP);
     dfree(Om);
-    dfree(Omp);
   }
   void free_all() {
     free_work();
@@ -455,22 +514,49 @@ struct ifmm_plan {
           break;
         }
         case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, s); break;
-        case OP_RRQR: launch_rrqr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, s); break;
+        case OP_RRQR:
+          if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, s);
+          else launch_rrqr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, s);
+          break;
         case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, s); break;
         case OP_STACKQR:
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
                          op.count, op.a, s);
           break;
         case OP_INV: launch_inverse(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
+        case OP_GJPANEL:
+          launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
+                          reinterpret_cast<int*>(op.off2), op.a, d_status, s);
+          break;
+        case OP_GJREST:
+          launch_gj_rest(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
+                         reinterpret_cast<int*>(op.off2b), op.a, reinterpret_cast<double*>(op.off2),
+                         (size_t)kInvNb * op.a, s);
+          break;
+        case OP_GJUNPERM:
+          launch_gj_unpermute(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a,
+                              reinterpret_cast<int*>(op.off2), op.a, s);
+          break;
       }
       HIP_OK(hipGetLastError());
       if (profile) {
         HIP_OK(hipEventRecord(eb, s));
-        pend.push_back({(int)op.t, ea, eb, op.flops, op.bytes});
+        pend.push_back({family(op.t), ea, eb, op.flops, op.bytes});
         if (pend.size() > 4096) resolve_profile();
       }
     }
     st.clear();
+  }
+
+  // Inverse of the pivot blocks: blocked Gauss-Jordan.
+  Buf wsInvT, wsInvP;
+  void plan_inverse(Stage& st, const std::vector<InvDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0;
+    for (const auto& d : v) mm = std::max(mm, d.m);
+    double* tmp = wsInvT.need((size_t)v.size() * kInvNb * mm, s);
+    int* piv = reinterpret_cast<int*>(wsInvP.need(((size_t)v.size() * mm + 1) / 2 + 1, s));
+    st.inv_blocked(v, piv, tmp, kInvNb);
   }
 
   // ---------------------------------------------------------------- tree
@@ -621,7 +707,6 @@ struct ifmm_plan {
     Lf.Qm = dalloc<double>(Lf.sQ * 9 * Lf.nc);
     Lf.L = dalloc<double>(Lf.sL * 9 * Lf.nc);
     Lf.U = dalloc<double>(Lf.sU * Lf.nc);
-    Lf.V = dalloc<double>(Lf.sU * Lf.nc);
     Lf.Dinv = dalloc<double>(Lf.sD * Lf.nc);
     HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(double) * Lf.sQ * 9 * Lf.nc, s));
     HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(double) * Lf.sL * 9 * Lf.nc, s));
@@ -638,10 +723,6 @@ struct ifmm_plan {
       for (int i = 0; i < nleaf; ++i)
         if (Lf.n[i] > 0) q.push_back({Lf.Ub(i), Ra[kappa] + (size_t)i * rpad * p2, Lf.n[i], p2, Lf.npad, rpad});
       st.qr(q);
-      std::vector<AddDesc> cp;
-      for (int i = 0; i < nleaf; ++i)
-        if (Lf.n[i] > 0) cp.push_back({Lf.Ub(i), Lf.Vb(i), Lf.n[i], Lf.r[i], Lf.npad, Lf.npad, 0, 1.0, 0.0});
-      st.add(cp);
       run(st);
     }
     // ---- non-leaf levels at assembly: S_P = [R_c E_c], QR, transfer blocks
@@ -697,8 +778,7 @@ struct ifmm_plan {
       Level& L = lv[k];
       L.sUP = (size_t)rpad * rpad;
       L.sM = (size_t)rpad * rpad;
-      L.VP = dalloc<double>(L.sUP * L.nc);
-      HIP_OK(hipMemcpyAsync(L.VP, L.UP, sizeof(double) * L.sUP * L.nc, hipMemcpyDeviceToDevice, s));
+
     }
     // ---- M2L in orthonormal coordinates: M_il = R_i K(dx,dy) R_l^T
     for (int k = 2; k <= kappa; ++k) {
@@ -733,25 +813,24 @@ struct ifmm_plan {
     for (int k = 2; k < kappa; ++k) {
       Level& L = lv[k];
       L.Om = dalloc<double>(L.sUP * L.nc);
-      L.Omp = dalloc<double>(L.sUP * L.nc);
       std::vector<int> ids;
       for (int i = 0; i < L.nc; ++i)
         if (L.r[i] > 0) ids.push_back(i);
-      weights(k, ids, [&](int t, int side) { return side == 0 ? L.Omb(ids[t]) : L.Ompb(ids[t]); });
+      weights(k, ids, [&](int t) { return L.Omb(ids[t]); });
     }
     HIP_OK(hipStreamSynchronize(s));
     t_assembly = now_ms() - t0;
   }
 
-  // Omega (side 0) / Omega' (side 1) of the clusters `ids` at level k: R
-  // factor of the stacked far-field row / column (+ parent chain).
+  // Omega of the clusters `ids` at level k: R factor of the stacked
+  // transposed far-field row (+ the parent chain UP Omega_parent^T).
   template <class OutFn>
   void weights(int k, const std::vector<int>& ids, OutFn out) {
     Level& L = lv[k];
     const int nt = (int)ids.size();
     if (nt == 0) return;
     double* Z = nullptr;
-    if (k > 2) Z = wsZ.need((size_t)nt * 2 * rpad * rpad, s);
+    if (k > 2) Z = wsZ.need((size_t)nt * rpad * rpad, s);
     Stage st;
     std::vector<GemmDesc> g;
     std::vector<StackQrDesc> sd;
@@ -759,34 +838,29 @@ struct ifmm_plan {
     for (int t = 0; t < nt; ++t) {
       const int q = ids[t];
       const int rq = L.r[q];
-      for (int side = 0; side < 2; ++side) {
-        StackQrDesc d{out(t, side), rq, rpad, (int)br.size(), 0};
-        const int qx = demorton_x(q), qy = demorton_y(q);
-        for (int sl = 0; sl < 36; ++sl) {
-          const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-          if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
-          if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
-          const int l = morton2(jx, jy);
-          if (L.r[l] == 0) continue;
-          if (side == 0) br.push_back({L.Mb(q, sl), rpad, L.r[l], 1});
-          else br.push_back({L.Mb(l, slot36(l, q)), rpad, L.r[l], 0});
+      StackQrDesc d{out(t), rq, rpad, (int)br.size(), 0};
+      const int qx = demorton_x(q), qy = demorton_y(q);
+      for (int sl = 0; sl < 36; ++sl) {
+        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+        const int l = morton2(jx, jy);
+        if (L.r[l] == 0) continue;
+        br.push_back({L.Mb(q, sl), rpad, L.r[l], 1});
+        d.nblk++;
+      }
+      if (k > 2) {
+        Level& Pl = lv[k - 1];
+        const int P = q >> 2;
+        const int rP = Pl.r[P];
+        if (rP > 0) {
+          double* z = Z + (size_t)t * rpad * rpad;
+          g.push_back({Pl.Omb(P), L.UPb(q), z, rP, rq, rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
+          br.push_back({z, rpad, rP, 0});
           d.nblk++;
         }
-        if (k > 2) {
-          Level& Pl = lv[k - 1];
-          const int P = q >> 2;
-          const int rP = Pl.r[P];
-          if (rP > 0) {
-            double* z = Z + ((size_t)t * 2 + side) * rpad * rpad;
-            const double* om = side == 0 ? Pl.Omb(P) : Pl.Ompb(P);
-            const double* up = side == 0 ? L.UPb(q) : L.VPb(q);
-            g.push_back({om, up, z, rP, rq, rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
-            br.push_back({z, rpad, rP, 0});
-            d.nblk++;
-          }
-        }
-        sd.push_back(d);
       }
+      sd.push_back(d);
     }
     st.gemm(g);
     st.stackqr(sd, br);
@@ -861,12 +935,12 @@ struct ifmm_plan {
         double* D = L.Db(e.i);
         dbuild.push_back({L.Pb(e.i, 4), D, e.ni, e.ni, L.npad, L.mpad, 0, 1.0, 0.0});
         dbuild.push_back({L.Ub(e.i), D + (size_t)e.ni * L.mpad, e.ni, e.ri, L.npad, L.mpad, 0, 1.0, 0.0});
-        dbuild.push_back({L.Vb(e.i), D + e.ni, e.ri, e.ni, L.npad, L.mpad, 1, 1.0, 0.0});
+        dbuild.push_back({L.Ub(e.i), D + e.ni, e.ri, e.ni, L.npad, L.mpad, 1, 1.0, 0.0});
         dbuild.push_back({nullptr, D + e.ni + (size_t)e.ni * L.mpad, e.ri, e.ri, 0, L.mpad, 0, 0.0, 0.0});
         inv.push_back({D, e.m, L.mpad});
       }
       st.add(dbuild);
-      st.inv(inv);
+      plan_inverse(st, inv);
       std::vector<GemmDesc> gx;
       std::vector<AddDesc> ax;
       for (int b = 0; b < nb; ++b) {
@@ -939,7 +1013,7 @@ struct ifmm_plan {
   void compress(int k, const std::vector<Elim>& E, int fpad, FpFn Fp) {
     Level& L = lv[k];
     struct Touch {
-      int q, b, sq, cu, cv;
+      int q, b, sq;
     };
     std::vector<Touch> T;
     std::vector<int> tidx(L.nc, -1);
@@ -947,38 +1021,37 @@ struct ifmm_plan {
       for (int sq = 0; sq < 9; ++sq) {
         const UnitH& u = E[b].u[sq];
         if (u.kind != 1) continue;
-        int cu = 0, cv = 0;
+        int cu = 0;
         for (int s2 = 0; s2 < 9; ++s2) {
           if (kPairs.idx[sq][s2] < 0 || !E[b].u[s2].kind) continue;
           cu += E[b].u[s2].size;
-          cv += E[b].u[s2].size;
         }
         if (cu == 0) continue;
         tidx[u.cl] = (int)T.size();
-        T.push_back({u.cl, b, sq, cu, cv});
+        T.push_back({u.cl, b, sq});
       }
     const int nt = (int)T.size();
     if (nt == 0) return;
-    // Omega, Omega' from the current state (before any basis change)
-    double* Om = wsB.need((size_t)nt * 2 * rpad * rpad, s);
+    // Omega from the current state (before any basis change)
+    double* Om = wsB.need((size_t)nt * rpad * rpad, s);
     std::vector<int> ids(nt);
     for (int t = 0; t < nt; ++t) ids[t] = T[t].q;
-    weights(k, ids, [&](int t, int side) { return Om + ((size_t)t * 2 + side) * rpad * rpad; });
-    // new bases, chunk by chunk
+    weights(k, ids, [&](int t) { return Om + (size_t)t * rpad * rpad; });
+    // new bases, chunk by chunk: pivoted QR of [U Omega^T | fill of the row]
     const int cmax = rpad + 5 * fpad;
-    double* Uh = wsQ.need((size_t)nt * 2 * L.sU, s);
-    double* TS = wsR.need((size_t)nt * 2 * rpad * rpad, s);
-    size_t per = (size_t)2 * L.npad * cmax;
+    double* Uh = wsQ.need((size_t)nt * L.sU, s);
+    double* Tt = wsR.need((size_t)nt * rpad * rpad, s);
+    const size_t per = (size_t)L.npad * cmax;
     int chunk = (int)std::min<size_t>(nt, std::max<size_t>(64, ((size_t)12 << 30) / (per * sizeof(double))));
-    double* A = wsT.need(per * chunk + (size_t)chunk * 2 * 2 * kMaxRank, s);
+    double* A = wsT.need(per * chunk + (size_t)chunk * 2 * kMaxRank, s);
     double* tauA = A + per * chunk;
-    if (rank_cap < (size_t)4 * nt) {
+    if (rank_cap < (size_t)2 * nt) {
       HIP_OK(hipStreamSynchronize(s));
       if (d_rank) (void)hipFree(d_rank);
-      rank_cap = (size_t)4 * nt;
+      rank_cap = (size_t)2 * nt;
       d_rank = dalloc<int>(rank_cap);
     }
-    std::vector<int> hr(4 * nt), rnew(nt);
+    std::vector<int> hr(2 * nt), rnew(nt);
     for (int t0 = 0; t0 < nt; t0 += chunk) {
       const int t1 = std::min(nt, t0 + chunk);
       Stage st;
@@ -988,58 +1061,47 @@ struct ifmm_plan {
       for (int t = t0; t < t1; ++t) {
         const Touch& tc = T[t];
         const int q = tc.q, nq = L.n[q], rq0 = L.r[q];
-        for (int side = 0; side < 2; ++side) {
-          double* Aw = A + ((size_t)(t - t0) * 2 + side) * L.npad * cmax;
-          const double* base = side == 0 ? L.Ub(q) : L.Vb(q);
-          g.push_back({base, Om + ((size_t)t * 2 + side) * rpad * rpad, Aw, nq, rq0, rq0, L.npad, rpad, L.npad,
-                       0, 1, 1.0, 0.0});
-          int col = rq0;
-          for (int s2 = 0; s2 < 9; ++s2) {
-            if (kPairs.idx[tc.sq][s2] < 0 || !E[tc.b].u[s2].kind) continue;
-            const int w = E[tc.b].u[s2].size;
-            if (side == 0) a.push_back({Fp(tc.b, tc.sq, s2), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 0, 1.0, 0.0});
-            else a.push_back({Fp(tc.b, s2, tc.sq), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 1, 1.0, 0.0});
-            col += w;
-          }
-          double* tb = tauA + ((size_t)(t - t0) * 2 + side) * 2 * kMaxRank;
-          rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 4 * t + side, d_rank + 4 * t + 2 + side, nq, col, L.npad,
-                        std::min(nq, r_cap), eps});
+        double* Aw = A + (size_t)(t - t0) * per;
+        g.push_back({L.Ub(q), Om + (size_t)t * rpad * rpad, Aw, nq, rq0, rq0, L.npad, rpad, L.npad, 0, 1, 1.0, 0.0});
+        int col = rq0;
+        for (int s2 = 0; s2 < 9; ++s2) {
+          if (kPairs.idx[tc.sq][s2] < 0 || !E[tc.b].u[s2].kind) continue;
+          const int w = E[tc.b].u[s2].size;
+          a.push_back({Fp(tc.b, tc.sq, s2), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 0, 1.0, 0.0});
+          col += w;
         }
+        double* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
+        rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
+                      std::min(nq, r_cap), eps});
       }
       st.gemm(g);
       st.add(a);
       st.rrqr(rq);
       run(st);
-      HIP_OK(hipMemcpyAsync(hr.data() + 4 * t0, d_rank + 4 * t0, sizeof(int) * 4 * (t1 - t0), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
       std::vector<FormQDesc> fq;
       for (int t = t0; t < t1; ++t) {
         const int q = T[t].q, nq = L.n[q];
-        rnew[t] = std::min(std::min(std::max(hr[4 * t], hr[4 * t + 1]), nq), r_cap);
-        for (int side = 0; side < 2; ++side) {
-          double* Aw = A + ((size_t)(t - t0) * 2 + side) * L.npad * cmax;
-          double* tb = tauA + ((size_t)(t - t0) * 2 + side) * 2 * kMaxRank;
-          const int steps = hr[4 * t + 2 + side];
-          fq.push_back({Aw, tb, tb + kMaxRank, Uh + ((size_t)t * 2 + side) * L.sU, nq, rnew[t],
-                        std::min(rnew[t], steps), L.npad, L.npad});
-        }
+        rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
+        double* Aw = A + (size_t)(t - t0) * per;
+        double* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
+        fq.push_back({Aw, tb, tb + kMaxRank, Uh + (size_t)t * L.sU, nq, rnew[t], std::min(rnew[t], hr[2 * t + 1]),
+                      L.npad, L.npad});
       }
       st.formq(fq);
       run(st);
     }
-    // basis changes: T = Uh^T U, St = Vh^T V
+    // basis change T = U^^T U (the column side uses S = T^T)
     Stage st;
     std::vector<GemmDesc> g;
     for (int t = 0; t < nt; ++t) {
       const int q = T[t].q, nq = L.n[q];
-      g.push_back({Uh + ((size_t)t * 2) * L.sU, L.Ub(q), TS + ((size_t)t * 2) * rpad * rpad, rnew[t], L.r[q], nq,
-                   L.npad, L.npad, rpad, 1, 0, 1.0, 0.0});
-      g.push_back({Uh + ((size_t)t * 2 + 1) * L.sU, L.Vb(q), TS + ((size_t)t * 2 + 1) * rpad * rpad, rnew[t], L.r[q],
-                   nq, L.npad, L.npad, rpad, 1, 0, 1.0, 0.0});
+      g.push_back({Uh + (size_t)t * L.sU, L.Ub(q), Tt + (size_t)t * rpad * rpad, rnew[t], L.r[q], nq, L.npad, L.npad,
+                   rpad, 1, 0, 1.0, 0.0});
     }
     st.gemm(g);
-    auto Tm = [&](int t) { return TS + ((size_t)t * 2) * rpad * rpad; };
-    auto Sm = [&](int t) { return TS + ((size_t)t * 2 + 1) * rpad * rpad; };
+    auto Tm = [&](int t) { return Tt + (size_t)t * rpad * rpad; };
     std::vector<XformDesc> xf;
     for (int t = 0; t < nt; ++t) {
       const int q = T[t].q;
@@ -1051,25 +1113,23 @@ struct ifmm_plan {
         const int l = morton2(jx, jy);
         if (L.r[l] == 0) continue;
         const int tl = tidx[l];
-        // row block (q, l): T_q M S_l
-        xf.push_back({L.Mb(q, sl), Tm(t), tl >= 0 ? Sm(tl) : nullptr, L.r[q], L.r[l], rnew[t],
+        // row block (q, l): T_q M T_l^T
+        xf.push_back({L.Mb(q, sl), Tm(t), tl >= 0 ? Tm(tl) : nullptr, L.r[q], L.r[l], rnew[t],
                       tl >= 0 ? rnew[tl] : L.r[l], rpad, rpad, rpad, 1});
         // column block (l, q) when l is not itself touched
         if (tl < 0)
-          xf.push_back({L.Mb(l, slot36(l, q)), nullptr, Sm(t), L.r[l], L.r[q], L.r[l], rnew[t], rpad, rpad, rpad, 1});
+          xf.push_back({L.Mb(l, slot36(l, q)), nullptr, Tm(t), L.r[l], L.r[q], L.r[l], rnew[t], rpad, rpad, rpad, 1});
       }
       if (k > 2 && lv[k - 1].r[q >> 2] > 0) {
         const int rP = lv[k - 1].r[q >> 2];
         xf.push_back({L.UPb(q), Tm(t), nullptr, L.r[q], rP, rnew[t], rP, rpad, rpad, rpad, 0});
-        xf.push_back({L.VPb(q), Sm(t), nullptr, L.r[q], rP, rnew[t], rP, rpad, rpad, rpad, 0});
       }
     }
     st.xform(xf);
     std::vector<AddDesc> cp;
     for (int t = 0; t < nt; ++t) {
       const int q = T[t].q, nq = L.n[q];
-      cp.push_back({Uh + ((size_t)t * 2) * L.sU, L.Ub(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
-      cp.push_back({Uh + ((size_t)t * 2 + 1) * L.sU, L.Vb(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
+      cp.push_back({Uh + (size_t)t * L.sU, L.Ub(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
     }
     st.add(cp);
     for (int t = 0; t < nt; ++t) L.r[T[t].q] = rnew[t];
@@ -1090,11 +1150,11 @@ struct ifmm_plan {
           if (ua.kind == 1 && ub.kind == 1) {
             double* tm = tmp + ((size_t)b * kPairs.count + pi) * rpad * fpad;
             g1.push_back({L.Ub(ua.cl), Fb, tm, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 0.0});
-            g2.push_back({tm, L.Vb(ub.cl), C, L.r[ua.cl], L.r[ub.cl], ub.size, rpad, L.npad, rpad, 0, 0, 1.0, 1.0});
+            g2.push_back({tm, L.Ub(ub.cl), C, L.r[ua.cl], L.r[ub.cl], ub.size, rpad, L.npad, rpad, 0, 0, 1.0, 1.0});
           } else if (ua.kind == 1) {
             g2.push_back({L.Ub(ua.cl), Fb, C, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 1.0});
           } else {
-            g2.push_back({Fb, L.Vb(ub.cl), C, ua.size, L.r[ub.cl], ub.size, fpad, L.npad, rpad, 0, 0, 1.0, 1.0});
+            g2.push_back({Fb, L.Ub(ub.cl), C, ua.size, L.r[ub.cl], ub.size, fpad, L.npad, rpad, 0, 0, 1.0, 1.0});
           }
         }
     }
@@ -1124,13 +1184,11 @@ struct ifmm_plan {
     L.Qm = dalloc<double>(L.sQ * 9 * L.nc);
     L.L = dalloc<double>(L.sL * 9 * L.nc);
     L.U = dalloc<double>(L.sU * L.nc);
-    L.V = dalloc<double>(L.sU * L.nc);
     L.Dinv = dalloc<double>(L.sD * L.nc);
     HIP_OK(hipMemsetAsync(L.Qm, 0, sizeof(double) * L.sQ * 9 * L.nc, s));
     HIP_OK(hipMemsetAsync(L.L, 0, sizeof(double) * L.sL * 9 * L.nc, s));
-    double* Ru = wsA.need((size_t)L.nc * 2 * rpad * rpad, s);
-    auto Rub = [&](int P) { return Ru + (size_t)P * 2 * rpad * rpad; };
-    auto Rvb = [&](int P) { return Ru + ((size_t)P * 2 + 1) * rpad * rpad; };
+    double* Ru = wsA.need((size_t)L.nc * rpad * rpad, s);
+    auto Rub = [&](int P) { return Ru + (size_t)P * rpad * rpad; };
     Stage st;
     std::vector<AddDesc> a;
     for (int P = 0; P < L.nc; ++P) {
@@ -1154,17 +1212,13 @@ struct ifmm_plan {
         const int ch = 4 * P + c;
         if (C.r[ch] == 0) continue;
         a.push_back({C.UPb(ch), L.Ub(P) + L.choff[(size_t)P * 4 + c], C.r[ch], rold[P], rpad, L.npad, 0, 1.0, 0.0});
-        a.push_back({C.VPb(ch), L.Vb(P) + L.choff[(size_t)P * 4 + c], C.r[ch], rold[P], rpad, L.npad, 0, 1.0, 0.0});
       }
     }
     st.add(a);
     std::vector<QrDesc> q;
     std::vector<AddDesc> z;
     for (int P = 0; P < L.nc; ++P) {
-      if (L.n[P] > 0) {
-        q.push_back({L.Ub(P), Rub(P), L.n[P], rold[P], L.npad, rpad});
-        q.push_back({L.Vb(P), Rvb(P), L.n[P], rold[P], L.npad, rpad});
-      }
+      if (L.n[P] > 0) q.push_back({L.Ub(P), Rub(P), L.n[P], rold[P], L.npad, rpad});
       L.r[P] = std::min(L.n[P], rold[P]);
     }
     st.qr(q);
@@ -1178,12 +1232,11 @@ struct ifmm_plan {
         if (std::abs(jx - px) <= 1 && std::abs(jy - py) <= 1) continue;
         const int l = morton2(jx, jy);
         if (rold[l] == 0) continue;
-        xf.push_back({L.Mb(P, sl), Rub(P), Rvb(l), rold[P], rold[l], L.r[P], L.r[l], rpad, rpad, rpad, 1});
+        xf.push_back({L.Mb(P, sl), Rub(P), Rub(l), rold[P], rold[l], L.r[P], L.r[l], rpad, rpad, rpad, 1});
       }
       if (k - 1 > 2 && lv[k - 2].r[P >> 2] > 0) {
         const int rG = lv[k - 2].r[P >> 2];
         xf.push_back({L.UPb(P), Rub(P), nullptr, rold[P], rG, L.r[P], rG, rpad, rpad, rpad, 0});
-        xf.push_back({L.VPb(P), Rvb(P), nullptr, rold[P], rG, L.r[P], rG, rpad, rpad, rpad, 0});
       }
     }
     st.xform(xf);
@@ -1213,7 +1266,7 @@ struct ifmm_plan {
                      top_m, 0, 1.0, 0.0});
       }
     st.add(a);
-    st.inv({InvDesc{d_top, top_m, top_m}});
+    plan_inverse(st, {InvDesc{d_top, top_m, top_m}});
     run(st);
     L.free_work();
   }
@@ -1382,7 +1435,8 @@ struct ifmm_plan {
     dfree(d_status);
     if (d_rank) (void)hipFree(d_rank);
     d_rank = nullptr;
-    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec}) b->release();
+    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP})
+      b->release();
     arena.release();
     for (const Pending& p : pend) {
       (void)hipEventDestroy(p.a);

@@ -130,9 +130,19 @@ void launch_xform(const XformDesc* d, int nd, double* scratch, int nwg, int ld_s
                   hipStream_t s);
 void launch_qr(const QrDesc* d, int nd, hipStream_t s);
 void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s);
+// Same, with the whole matrix staged in LDS: (n + 1) * m + m doubles must fit
+// in `lds` <= kRrqrLdsBytes.
+constexpr size_t kRrqrLdsBytes = 150 * 1024;
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s);
 void launch_formq(const FormQDesc* d, int nd, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s);
 void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
+// Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
+void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
+                     Status* st, hipStream_t s);
+void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const int* piv, int ldp,
+                    double* tmp, size_t ldt, hipStream_t s);
+void launch_gj_unpermute(const InvDesc* d, int nd, int max_m, const int* piv, int ldp, hipStream_t s);
 
 // ---------------------------------------------------------- problem kernels
 struct KernelFn {

@@ -235,23 +235,57 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
 }
 
 // ------------------------------------------------------------------- RRQR
+// Each column of the trailing matrix is handled by a group of 16 lanes (16
+// consecutive rows per access, one 128-byte line), so a workgroup has 16
+// columns in flight; dot products and norms reduce with shuffles inside the
+// group.  The matrix lives in LDS (stride n + 1) when it fits, else it is
+// streamed from global memory.  Norms are recomputed exactly every step.
+constexpr int GRP = 16;
+
+__device__ inline double grp_sum(double v) {
+  v += __shfl_xor(v, 1, WAVE);
+  v += __shfl_xor(v, 2, WAVE);
+  v += __shfl_xor(v, 4, WAVE);
+  v += __shfl_xor(v, 8, WAVE);
+  return v;
+}
+
+template <bool kLds>
 __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs) {
-  extern __shared__ double nrm[];  // m entries
+  extern __shared__ double sh[];
   const RrqrDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
   const int K = min(min(n, m), d.kmax);
   if (d.A == nullptr) return;
-  double* A = d.A;
-  const size_t lda = d.lda;
-  __shared__ double red[WG / WAVE];
+  double* A;
+  size_t lda;
+  double* nrm;
+  if (kLds) {
+    lda = n + 1;
+    A = sh;
+    nrm = sh + lda * m;
+    for (int e = threadIdx.x; e < n * m; e += WG) {
+      const int i = e % n, c = e / n;
+      A[i + c * lda] = d.A[i + (size_t)c * d.lda];
+    }
+  } else {
+    A = d.A;
+    lda = d.lda;
+    nrm = sh;
+  }
   __shared__ double rv[WG / WAVE];
   __shared__ int ri[WG / WAVE];
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
-  for (int c = w; c < m; c += nw) {
-    double s = 0.0;
-    for (int i = lane; i < n; i += WAVE) s += A[i + c * lda] * A[i + c * lda];
-    s = wave_sum(s);
-    if (lane == 0) nrm[c] = sqrt(s);
+  __shared__ double red[WG / WAVE];
+  const int rl = threadIdx.x % GRP;         // row lane inside the group
+  const int slot = threadIdx.x / GRP;       // 0..15: column slot of the group
+  constexpr int NSLOT = WG / GRP;
+  __syncthreads();
+  for (int c = slot; c < m; c += NSLOT) {
+    const double* col = A + c * lda;
+    double q = 0.0;
+    for (int i = rl; i < n; i += GRP) q = fma(col[i], col[i], q);
+    q = grp_sum(q);
+    if (rl == 0) nrm[c] = sqrt(q);
   }
   __syncthreads();
   int rank = 0;
@@ -279,7 +313,7 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
     double part = 0.0;
-    for (int i = j + threadIdx.x; i < n; i += WG) part += A[i + j * lda] * A[i + j * lda];
+    for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
     const double xn = sqrt(block_sum(part, red));
     const double x0 = A[j + j * lda];
     double alpha = 0.0, tau = 0.0, v0 = 1.0;
@@ -292,21 +326,32 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0.0 ? A[i + j * lda] / v0 : 0.0;
     if (threadIdx.x == 0) { d.tau[j] = tau; d.alpha[j] = alpha; A[j + j * lda] = alpha; }
     __syncthreads();
-    for (int c = j + 1 + w; c < m; c += nw) {
+    const double* u = A + j * lda;
+    for (int c = j + 1 + slot; c < m; c += NSLOT) {
+      double* col = A + c * lda;
       double s = 0.0;
-      for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
-      s = wave_sum(s) + A[j + c * lda];
+      for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
+      s = grp_sum(s) + col[j];
       const double ts = tau * s;
       double q = 0.0;
-      for (int i = j + 1 + lane; i < n; i += WAVE) {
-        const double v = A[i + c * lda] - ts * A[i + j * lda];
-        A[i + c * lda] = v;
-        q += v * v;
+      for (int i = j + 1 + rl; i < n; i += GRP) {
+        const double v = fma(-ts, u[i], col[i]);
+        col[i] = v;
+        q = fma(v, v, q);
       }
-      q = wave_sum(q);
-      if (lane == 0) { A[j + c * lda] -= ts; nrm[c] = sqrt(q); }
+      q = grp_sum(q);
+      if (rl == 0) {
+        col[j] -= ts;
+        nrm[c] = sqrt(q);
+      }
     }
     __syncthreads();
+  }
+  if (kLds) {
+    for (int e = threadIdx.x; e < n * K; e += WG) {
+      const int i = e % n, c = e / n;
+      d.A[i + (size_t)c * d.lda] = A[i + c * lda];
+    }
   }
   if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
 }
@@ -342,17 +387,20 @@ __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ desc
 
 // --------------------------------------------------------------- STACK QR
 // R of a tall stack [B_0; B_1; ...] processed block by block: the running R
-// (r x r) and a chunk of the current block live in LDS; each Householder
-// step only touches row j of R and the chunk rows.
+// (r x r) and a chunk of the current block live in LDS.  Each Householder
+// step only touches row j of R and the chunk rows; thread t owns column t
+// (every thread forms the reflector of column j itself from broadcast reads),
+// so a step needs one barrier.
 __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
                                                 const BlkRef* __restrict__ blocks, int chunk) {
   extern __shared__ double lds[];
   const StackQrDesc d = descs[blockIdx.x];
   const int r = d.r;
   if (d.R == nullptr || r == 0) return;
-  double* R = lds;               // r x r, ld r
-  double* C = lds + r * r;       // chunk x r, ld chunk
-  __shared__ double sv[kMaxRank];  // 2 s / vtv per column
+  const int ldc = chunk + 1;
+  double* R = lds;                 // r x r, ld r
+  double* C = lds + r * r;         // chunk x r, ld chunk + 1
+  const int c = threadIdx.x;       // owned column (r <= kMaxRank < WG)
   for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0.0;
   __syncthreads();
   for (int b = 0; b < d.nblk; ++b) {
@@ -362,33 +410,34 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
       for (int e = threadIdx.x; e < cr * r; e += WG) {
         const int i = e % cr, j = e / cr;
         const int gi = r0 + i;
-        C[i + j * chunk] = B.trans ? B.p[j + (size_t)gi * B.ld] : B.p[gi + (size_t)j * B.ld];
+        C[i + j * ldc] = B.trans ? B.p[j + (size_t)gi * B.ld] : B.p[gi + (size_t)j * B.ld];
       }
       __syncthreads();
       for (int j = 0; j < r; ++j) {
-        // reflector of x = [R_jj; C[:, j]]
+        const double* cj = C + j * ldc;
         double s2 = 0.0;
-        for (int i = 0; i < cr; ++i) s2 += C[i + j * chunk] * C[i + j * chunk];
+        for (int i = 0; i < cr; ++i) s2 = fma(cj[i], cj[i], s2);
         const double rjj = R[j + j * r];
         const double nrm = sqrt(rjj * rjj + s2);
         if (s2 == 0.0 || nrm == 0.0) continue;  // nothing below the diagonal: H = I
         const double alpha = rjj >= 0.0 ? -nrm : nrm;
         const double v0 = rjj - alpha;
-        const double vtv = -2.0 * alpha * v0;
-        for (int c = j + 1 + (int)threadIdx.x; c < r; c += WG) {
-          double s = v0 * R[j + c * r];
-          for (int i = 0; i < cr; ++i) s += C[i + j * chunk] * C[i + c * chunk];
-          sv[c] = 2.0 * s / vtv;
+        const double f2 = 2.0 / (-2.0 * alpha * v0);
+        double rjc = 0.0, sc = 0.0;
+        if (c > j && c < r) {
+          double* cc = C + c * ldc;
+          rjc = R[j + c * r];
+          sc = v0 * rjc;
+          for (int i = 0; i < cr; ++i) sc = fma(cj[i], cc[i], sc);
+          sc *= f2;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < (r - j - 1) * (cr + 1); e += WG) {
-          const int c = j + 1 + e / (cr + 1), i = e % (cr + 1);
-          if (i == cr) R[j + c * r] -= sv[c] * v0;
-          else C[i + c * chunk] -= sv[c] * C[i + j * chunk];
+        __syncthreads();  // every thread has read column j and R_jj
+        if (c > j && c < r) {
+          double* cc = C + c * ldc;
+          for (int i = 0; i < cr; ++i) cc[i] = fma(-sc, cj[i], cc[i]);
+          R[j + c * r] = rjc - sc * v0;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) R[j + j * r] = alpha;
-        for (int i = threadIdx.x; i < cr; i += WG) C[i + j * chunk] = 0.0;
+        if (c == j) R[j + j * r] = alpha;
         __syncthreads();
       }
     }
@@ -467,6 +516,115 @@ __global__ __launch_bounds__(WG) void k_inverse(const InvDesc* __restrict__ desc
   }
 }
 
+// ------------------------------------------------------- BLOCKED INVERSE
+// Gauss-Jordan by panels of nb columns.  The panel kernel runs the nb
+// unblocked steps restricted to the panel columns (pivot search over the
+// rows not yet used, row swap, scaling, elimination of every other row), so
+// the panel ends as [A11^-1 on the pivot rows; -A21 A11^-1 elsewhere].  The
+// remaining columns receive the same row swaps and then one rank-nb update
+// (two GEMM shapes planned on the host).  A final pass undoes the column
+// permutation.
+__global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ descs, int j0, int nb,
+                                                 int* __restrict__ piv_all, int ldp, Status* st) {
+  extern __shared__ double f[];  // m entries
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr || j0 >= m) return;
+  const int nbe = min(nb, m - j0);
+  double* A = d.A;
+  const size_t lda = d.lda;
+  int* piv = piv_all + (size_t)blockIdx.x * ldp;
+  __shared__ double rowj[64];
+  __shared__ double rv[WG / WAVE];
+  __shared__ int ri[WG / WAVE];
+  bool bad = false;
+  for (int t = 0; t < nbe; ++t) {
+    const int j = j0 + t;
+    double bv = -1.0;
+    int bi = m;
+    for (int i = j + threadIdx.x; i < m; i += WG) {
+      const double a = fabs(A[i + j * lda]);
+      if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
+    }
+    double pv;
+    int p;
+    block_argmax(bv, bi, rv, ri, pv, p);
+    if (threadIdx.x == 0) piv[j] = p;
+    if (p != j && threadIdx.x < nbe) {
+      const int c = j0 + threadIdx.x;
+      const double tmp = A[j + c * lda];
+      A[j + c * lda] = A[p + c * lda];
+      A[p + c * lda] = tmp;
+    }
+    __syncthreads();
+    const double djj = A[j + j * lda];
+    if (djj == 0.0) bad = true;
+    const double inv = 1.0 / djj;
+    for (int i = threadIdx.x; i < m; i += WG) f[i] = A[i + j * lda];
+    if (threadIdx.x < nbe) {
+      const int c = j0 + threadIdx.x;
+      rowj[threadIdx.x] = c == j ? inv : A[j + c * lda] * inv;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * nbe; e += WG) {
+      const int i = e % m, tc = e / m, c = j0 + tc;
+      if (i == j) A[i + c * lda] = rowj[tc];
+      else if (c == j) A[i + c * lda] = -f[i] * inv;
+      else A[i + c * lda] -= f[i] * rowj[tc];
+    }
+    __syncthreads();
+  }
+  if (bad && threadIdx.x == 0 && st) {
+    if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
+  }
+}
+
+// Row swaps of the panel applied to every other column, and rows j0..j0+nb-1
+// of those columns copied to tmp (nb x m, ld nb).
+__global__ __launch_bounds__(WG) void k_gj_rest(const InvDesc* __restrict__ descs, int j0, int nb,
+                                                const int* __restrict__ piv_all, int ldp,
+                                                double* __restrict__ tmp_all, size_t ldt) {
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr || j0 >= m) return;
+  const int nbe = min(nb, m - j0);
+  const int* piv = piv_all + (size_t)blockIdx.x * ldp;
+  double* tmp = tmp_all + (size_t)blockIdx.x * ldt;
+  const size_t lda = d.lda;
+  for (int c = blockIdx.y * WG + threadIdx.x; c < m; c += gridDim.y * WG) {
+    if (c >= j0 && c < j0 + nbe) continue;
+    double* col = d.A + c * lda;
+    for (int t = 0; t < nbe; ++t) {
+      const int j = j0 + t, p = piv[j];
+      if (p != j) {
+        const double x = col[j];
+        col[j] = col[p];
+        col[p] = x;
+      }
+    }
+    for (int t = 0; t < nbe; ++t) tmp[t + (size_t)c * nb] = col[j0 + t];
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_gj_unpermute(const InvDesc* __restrict__ descs,
+                                                     const int* __restrict__ piv_all, int ldp) {
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr) return;
+  const int* piv = piv_all + (size_t)blockIdx.x * ldp;
+  const size_t lda = d.lda;
+  for (int i = blockIdx.y * WG + threadIdx.x; i < m; i += gridDim.y * WG) {
+    for (int j = m - 1; j >= 0; --j) {
+      const int p = piv[j];
+      if (p != j) {
+        const double x = d.A[i + j * lda];
+        d.A[i + j * lda] = d.A[i + p * lda];
+        d.A[i + p * lda] = x;
+      }
+    }
+  }
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -497,7 +655,18 @@ void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
 
 void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(k_rrqr, dim3(nd), dim3(WG), sizeof(double) * (max_m > 0 ? max_m : 1), s, d);
+  hipLaunchKernelGGL(k_rrqr<false>, dim3(nd), dim3(WG), sizeof(double) * (max_m > 0 ? max_m : 1), s, d);
+}
+
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s) {
+  if (nd <= 0) return;
+  static bool raised = false;
+  if (!raised) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_rrqr<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRrqrLdsBytes);
+    raised = true;
+  }
+  hipLaunchKernelGGL(k_rrqr<true>, dim3(nd), dim3(WG), lds, s, d);
 }
 
 void launch_formq(const FormQDesc* d, int nd, hipStream_t s) {
@@ -515,7 +684,8 @@ void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hi
   int chunk = (int)((budget - rr) / row);
   if (chunk > kMaxRank) chunk = kMaxRank;
   if (chunk < 1) chunk = 1;
-  const size_t lds = rr + (size_t)chunk * row;
+  if (chunk > 1 && rr + (size_t)(chunk + 1) * row > budget) --chunk;
+  const size_t lds = rr + (size_t)(chunk + 1) * row;
   if (lds > 64 * 1024) {
     static bool raised = false;
     if (!raised) {
@@ -525,6 +695,23 @@ void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hi
     }
   }
   hipLaunchKernelGGL(k_stackqr, dim3(nd), dim3(WG), lds, s, d, b, chunk);
+}
+
+void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
+                     Status* st, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv, ldp, st);
+}
+
+void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const int* piv, int ldp,
+                    double* tmp, size_t ldt, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_gj_rest, dim3(nd, cdiv(max_m, WG)), dim3(WG), 0, s, d, j0, nb, piv, ldp, tmp, ldt);
+}
+
+void launch_gj_unpermute(const InvDesc* d, int nd, int max_m, const int* piv, int ldp, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_gj_unpermute, dim3(nd, cdiv(max_m, WG)), dim3(WG), 0, s, d, piv, ldp);
 }
 
 void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
