@@ -1072,7 +1072,7 @@ struct ifmm_plan {
         }
         double* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
-                      std::min(nq, r_cap), eps});
+                      std::min(nq, r_cap), eps, 1});
       }
       st.gemm(g);
       st.add(a);

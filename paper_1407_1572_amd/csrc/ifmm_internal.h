@@ -52,7 +52,8 @@ struct QrDesc {
 // Column-pivoted Householder QR for up to kmax steps, in place.  Reflector j
 // is u_j (u_j[0] = 1 implicit) stored below the diagonal of column j, with
 // tau[j] and alpha[j] (the signed diagonal).  rank = number of leading steps
-// whose pivot norm exceeds eps * first pivot norm.
+// whose pivot norm exceeds eps * first pivot norm; with stop_at_rank the
+// factorisation stops at the first pivot at or below that threshold.
 struct RrqrDesc {
   double* A;
   double* tau;
@@ -61,6 +62,7 @@ struct RrqrDesc {
   int* steps;
   int n, m, lda, kmax;
   double eps;
+  int stop_at_rank;
 };
 
 // Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with

@@ -302,6 +302,17 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     if (j == 0) first = piv;
     if (counting && first > 0.0 && piv > d.eps * first) rank = j + 1;
     else counting = false;
+    if (!counting && d.stop_at_rank) {  // uniform: every thread holds the same pivot
+      if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; }
+      if (kLds) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * j; e += WG) {
+          const int i = e % n, c = e / n;
+          d.A[i + (size_t)c * d.lda] = A[i + c * lda];
+        }
+      }
+      return;
+    }
     __syncthreads();
     if (cp != j) {
       for (int i = threadIdx.x; i < n; i += WG) {
@@ -387,10 +398,10 @@ __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ desc
 
 // --------------------------------------------------------------- STACK QR
 // R of a tall stack [B_0; B_1; ...] processed block by block: the running R
-// (r x r) and a chunk of the current block live in LDS.  Each Householder
-// step only touches row j of R and the chunk rows; thread t owns column t
-// (every thread forms the reflector of column j itself from broadcast reads),
-// so a step needs one barrier.
+// (r x r) and a chunk of the current block live in LDS.  A Householder step
+// only touches row j of R and the chunk rows.  Each trailing column is handled
+// by a 16-lane group (lanes over chunk rows, shuffle reductions), every group
+// forms the reflector of column j itself, so a step costs one barrier.
 __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
                                                 const BlkRef* __restrict__ blocks, int chunk) {
   extern __shared__ double lds[];
@@ -400,7 +411,8 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
   const int ldc = chunk + 1;
   double* R = lds;                 // r x r, ld r
   double* C = lds + r * r;         // chunk x r, ld chunk + 1
-  const int c = threadIdx.x;       // owned column (r <= kMaxRank < WG)
+  const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
+  constexpr int NSLOT = WG / GRP;
   for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0.0;
   __syncthreads();
   for (int b = 0; b < d.nblk; ++b) {
@@ -408,7 +420,8 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
     for (int r0 = 0; r0 < B.rows; r0 += chunk) {
       const int cr = min(chunk, B.rows - r0);
       for (int e = threadIdx.x; e < cr * r; e += WG) {
-        const int i = e % cr, j = e / cr;
+        int i, j;
+        if (B.trans) { j = e % r; i = e / r; } else { i = e % cr; j = e / cr; }
         const int gi = r0 + i;
         C[i + j * ldc] = B.trans ? B.p[j + (size_t)gi * B.ld] : B.p[gi + (size_t)j * B.ld];
       }
@@ -416,30 +429,27 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
       for (int j = 0; j < r; ++j) {
         const double* cj = C + j * ldc;
         double s2 = 0.0;
-        for (int i = 0; i < cr; ++i) s2 = fma(cj[i], cj[i], s2);
+        for (int i = rl; i < cr; i += GRP) s2 = fma(cj[i], cj[i], s2);
+        s2 = grp_sum(s2);
         const double rjj = R[j + j * r];
         const double nrm = sqrt(rjj * rjj + s2);
         if (s2 == 0.0 || nrm == 0.0) continue;  // nothing below the diagonal: H = I
         const double alpha = rjj >= 0.0 ? -nrm : nrm;
         const double v0 = rjj - alpha;
         const double f2 = 2.0 / (-2.0 * alpha * v0);
-        double rjc = 0.0, sc = 0.0;
-        if (c > j && c < r) {
+        for (int c = j + 1 + slot; c < r; c += NSLOT) {
           double* cc = C + c * ldc;
-          rjc = R[j + c * r];
-          sc = v0 * rjc;
-          for (int i = 0; i < cr; ++i) sc = fma(cj[i], cc[i], sc);
-          sc *= f2;
+          double sc = 0.0;
+          for (int i = rl; i < cr; i += GRP) sc = fma(cj[i], cc[i], sc);
+          const double rjc = R[j + c * r];
+          sc = (grp_sum(sc) + v0 * rjc) * f2;
+          for (int i = rl; i < cr; i += GRP) cc[i] = fma(-sc, cj[i], cc[i]);
+          if (rl == 0) R[j + c * r] = rjc - sc * v0;
         }
-        __syncthreads();  // every thread has read column j and R_jj
-        if (c > j && c < r) {
-          double* cc = C + c * ldc;
-          for (int i = 0; i < cr; ++i) cc[i] = fma(-sc, cj[i], cc[i]);
-          R[j + c * r] = rjc - sc * v0;
-        }
-        if (c == j) R[j + j * r] = alpha;
-        __syncthreads();
+        __syncthreads();  // trailing columns final; R_jj and column j no longer read
+        if (threadIdx.x == 0) R[j + j * r] = alpha;
       }
+      __syncthreads();
     }
   }
   for (int e = threadIdx.x; e < r * r; e += WG) {
