@@ -132,9 +132,11 @@ struct Stage {
     flops += f;
     ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by});
   }
-  void rrqr(const std::vector<RrqrDesc>& all) {
+  // Pivoted QRs: matrices that fit in LDS go to the LDS kernel (b = 1); the
+  // rest run the multi-workgroup version (b = 0) with per-matrix norms in
+  // nrm_ws (sum of m doubles).
+  void rrqr(const std::vector<RrqrDesc>& all, double* nrm_ws) {
     if (all.empty()) return;
-    // matrices that fit in LDS go to the LDS kernel (b = 1), the rest stream
     std::vector<RrqrDesc> grp[2];
     for (const auto& d : all) {
       const size_t need = sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m);
@@ -143,18 +145,33 @@ struct Stage {
     for (int g = 0; g < 2; ++g) {
       const auto& v = grp[g];
       if (v.empty()) continue;
-      int mm = 0;
+      int mm = 0, kk = 0;
       size_t lds = 0;
       double f = 0, by = 0;
       for (const auto& d : v) {
         mm = std::max(mm, d.m);
         lds = std::max(lds, sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m));
         const int K = std::min(std::min(d.n, d.m), d.kmax);
+        kk = std::max(kk, K);
         for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
         by += 16.0 * d.n * (double)d.m;
       }
       flops += f;
-      ops.push_back({OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), (size_t)lds, (int)v.size(), mm, g, f, by});
+      const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
+      if (g == 1) {
+        ops.push_back({OP_RRQR, o, (size_t)lds, (int)v.size(), mm, 1, f, by});
+      } else {
+        std::vector<RrqrState> st(v.size());
+        size_t off = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+          st[i] = RrqrState{nrm_ws + off, 0.0, 0, 1, 0, 0};
+          off += v[i].m;
+        }
+        const size_t o2 = push(st.data(), st.size() * sizeof(RrqrState));
+        Op op{OP_RRQR, o, o2, (int)v.size(), mm, 0, f, by};
+        op.off2b = (size_t)kk;
+        ops.push_back(op);
+      }
     }
   }
   void formq(const std::vector<FormQDesc>& v) {
@@ -450,7 +467,7 @@ struct ifmm_plan {
   double* d_top = nullptr;
   Status* d_status = nullptr;
   Arena arena;
-  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsXf, wsS1, wsS2, wsVec;
+  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsXf, wsS1, wsS2, wsVec, wsNrm, wsSeg;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
   // stats
@@ -516,7 +533,9 @@ struct ifmm_plan {
         case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, s); break;
         case OP_RRQR:
           if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, s);
-          else launch_rrqr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, s);
+          else
+            launch_rrqr_multi(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2b,
+                              reinterpret_cast<RrqrState*>(d + op.off2), s);
           break;
         case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, s); break;
         case OP_STACKQR:
@@ -863,7 +882,36 @@ struct ifmm_plan {
       sd.push_back(d);
     }
     st.gemm(g);
-    st.stackqr(sd, br);
+    // Few clusters (coarse levels): split each stack into segments handled by
+    // separate workgroups, then take the R factor of the stacked partial R's
+    // (the same R up to rounding).
+    const int S = std::max(1, std::min(8, (3072 + nt - 1) / nt));
+    if (S == 1) {
+      st.stackqr(sd, br);
+    } else {
+      double* part = wsSeg.need((size_t)nt * S * rpad * rpad, s);
+      std::vector<StackQrDesc> s1, s2;
+      std::vector<BlkRef> b1, b2;
+      for (int t = 0; t < nt; ++t) {
+        const StackQrDesc& d = sd[t];
+        StackQrDesc fin{d.R, d.r, d.ldr, (int)b2.size(), 0};
+        const int per = (d.nblk + S - 1) / S;
+        for (int g0 = 0; g0 < d.nblk; g0 += per) {
+          double* pr = part + ((size_t)t * S + g0 / per) * rpad * rpad;
+          StackQrDesc ps{pr, d.r, rpad, (int)b1.size(), 0};
+          for (int x = g0; x < std::min(d.nblk, g0 + per); ++x) {
+            b1.push_back(br[d.first + x]);
+            ps.nblk++;
+          }
+          s1.push_back(ps);
+          b2.push_back({pr, rpad, d.r, 0});
+          fin.nblk++;
+        }
+        s2.push_back(fin);
+      }
+      st.stackqr(s1, b1);
+      st.stackqr(s2, b2);
+    }
     run(st);
   }
 
@@ -1076,7 +1124,9 @@ struct ifmm_plan {
       }
       st.gemm(g);
       st.add(a);
-      st.rrqr(rq);
+      size_t msum = 0;
+      for (const auto& d : rq) msum += d.m;
+      st.rrqr(rq, wsNrm.need(msum + 1, s));
       run(st);
       HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
@@ -1435,7 +1485,8 @@ struct ifmm_plan {
     dfree(d_status);
     if (d_rank) (void)hipFree(d_rank);
     d_rank = nullptr;
-    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP})
+    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
+                   &wsNrm, &wsSeg})
       b->release();
     arena.release();
     for (const Pending& p : pend) {

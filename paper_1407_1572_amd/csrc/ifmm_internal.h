@@ -65,6 +65,13 @@ struct RrqrDesc {
   int stop_at_rank;
 };
 
+// Per-matrix state of the multi-workgroup pivoted QR (nrm: m doubles).
+struct RrqrState {
+  double* nrm;
+  double first;
+  int rank, counting, done, apply;
+};
+
 // Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with
 // column j negated where alpha[j] < 0.
 struct FormQDesc {
@@ -136,6 +143,10 @@ void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s);
 // in `lds` <= kRrqrLdsBytes.
 constexpr size_t kRrqrLdsBytes = 150 * 1024;
 void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s);
+// Same arithmetic with every step split in a pivot launch and a column-tiled
+// update launch (many workgroups per matrix); max_k = largest step count.
+void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st,
+                       hipStream_t s);
 void launch_formq(const FormQDesc* d, int nd, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s);
 void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);

@@ -367,6 +367,134 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
   if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
 }
 
+// ------------------------------------------------ multi-workgroup RRQR
+// For large matrices (few per launch at the coarse levels) one Householder
+// step is two launches: k_rrqr_pivot (one workgroup per matrix: pivot choice,
+// column swap, reflector) and k_rrqr_update (column tiles of the trailing
+// matrix spread over many workgroups, 16-lane groups per column, exact norms).
+// Per-matrix state lives in RrqrState; same arithmetic as k_rrqr.
+__global__ __launch_bounds__(WG) void k_rrqr_init(const RrqrDesc* __restrict__ descs,
+                                                  RrqrState* __restrict__ st) {
+  const RrqrDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m;
+  RrqrState& S = st[blockIdx.x];
+  const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
+  constexpr int NSLOT = WG / GRP;
+  for (int c = blockIdx.y * NSLOT + slot; c < m; c += gridDim.y * NSLOT) {
+    const double* col = d.A + (size_t)c * d.lda;
+    double q = 0.0;
+    for (int i = rl; i < n; i += GRP) q = fma(col[i], col[i], q);
+    q = grp_sum(q);
+    if (rl == 0) S.nrm[c] = sqrt(q);
+  }
+  if (blockIdx.y == 0 && threadIdx.x == 0) {
+    S.done = d.A == nullptr ? 1 : 0;
+    S.apply = 0;
+    S.rank = 0;
+    S.counting = 1;
+    S.first = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ descs,
+                                                   RrqrState* __restrict__ st, int j) {
+  const RrqrDesc d = descs[blockIdx.x];
+  RrqrState& S = st[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int K = min(min(n, m), d.kmax);
+  if (S.done) {
+    if (threadIdx.x == 0) S.apply = 0;
+    return;
+  }
+  if (j >= K) {
+    if (threadIdx.x == 0) { *d.rank = S.rank; *d.steps = K; S.done = 1; S.apply = 0; }
+    return;
+  }
+  __shared__ double rv[WG / WAVE];
+  __shared__ int ri[WG / WAVE];
+  __shared__ double red[WG / WAVE];
+  double* A = d.A;
+  const size_t lda = d.lda;
+  double* nrm = S.nrm;
+  double bv = -1.0;
+  int bi = m;
+  for (int c = j + threadIdx.x; c < m; c += WG)
+    if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
+  double piv;
+  int cp;
+  block_argmax(bv, bi, rv, ri, piv, cp);
+  const double first = j == 0 ? piv : S.first;
+  int rank = S.rank;
+  bool counting = S.counting != 0;
+  if (counting && first > 0.0 && piv > d.eps * first) rank = j + 1;
+  else counting = false;
+  __syncthreads();
+  if (threadIdx.x == 0) { S.first = first; S.rank = rank; S.counting = counting ? 1 : 0; }
+  if (!counting && d.stop_at_rank) {
+    if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; S.done = 1; S.apply = 0; }
+    return;
+  }
+  if (cp != j) {
+    for (int i = threadIdx.x; i < n; i += WG) {
+      const double t = A[i + j * lda];
+      A[i + j * lda] = A[i + cp * lda];
+      A[i + cp * lda] = t;
+    }
+    if (threadIdx.x == 0) { const double t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
+  const double xn = sqrt(block_sum(part, red));
+  const double x0 = A[j + j * lda];
+  double alpha = 0.0, tau = 0.0, v0 = 1.0;
+  if (xn > 0.0) {
+    alpha = x0 >= 0.0 ? -xn : xn;
+    v0 = x0 - alpha;
+    tau = -v0 / alpha;
+  }
+  __syncthreads();
+  for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0.0 ? A[i + j * lda] / v0 : 0.0;
+  if (threadIdx.x == 0) {
+    d.tau[j] = tau;
+    d.alpha[j] = alpha;
+    A[j + j * lda] = alpha;
+    // the trailing update of the last reflector is never read: skip it
+    if (j + 1 == K) { *d.rank = rank; *d.steps = K; S.done = 1; S.apply = 0; }
+    else S.apply = 1;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_rrqr_update(const RrqrDesc* __restrict__ descs,
+                                                    const RrqrState* __restrict__ st, int j) {
+  const RrqrDesc d = descs[blockIdx.x];
+  const RrqrState& S = st[blockIdx.x];
+  const int n = d.n, m = d.m;
+  if (!S.apply) return;  // no reflector formed at this step
+  const double tau = d.tau[j];
+  const double* u = d.A + (size_t)j * d.lda;
+  const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
+  constexpr int NSLOT = WG / GRP;
+  for (int c = j + 1 + blockIdx.y * NSLOT + slot; c < m; c += gridDim.y * NSLOT) {
+    double* col = d.A + (size_t)c * d.lda;
+    double s = 0.0;
+    for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
+    s = grp_sum(s) + col[j];
+    const double ts = tau * s;
+    double q = 0.0;
+    for (int i = j + 1 + rl; i < n; i += GRP) {
+      const double v = fma(-ts, u[i], col[i]);
+      col[i] = v;
+      q = fma(v, v, q);
+    }
+    q = grp_sum(q);
+    if (rl == 0) {
+      col[j] -= ts;
+      S.nrm[c] = sqrt(q);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ FORMQ
 __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ descs) {
   const FormQDesc d = descs[blockIdx.x];
@@ -434,17 +562,21 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
         const double rjj = R[j + j * r];
         const double nrm = sqrt(rjj * rjj + s2);
         if (s2 == 0.0 || nrm == 0.0) continue;  // nothing below the diagonal: H = I
+        // H = I - tau u u^T with u = [1; C_j / v0], tau = -v0 / alpha in [1, 2]:
+        // no product of two small quantities is formed, so repeated stacking of
+        // nearly annihilated columns cannot overflow the scale.
         const double alpha = rjj >= 0.0 ? -nrm : nrm;
         const double v0 = rjj - alpha;
-        const double f2 = 2.0 / (-2.0 * alpha * v0);
+        const double tau = -v0 / alpha;
+        const double iv0 = 1.0 / v0;
         for (int c = j + 1 + slot; c < r; c += NSLOT) {
           double* cc = C + c * ldc;
           double sc = 0.0;
-          for (int i = rl; i < cr; i += GRP) sc = fma(cj[i], cc[i], sc);
+          for (int i = rl; i < cr; i += GRP) sc = fma(cj[i] * iv0, cc[i], sc);
           const double rjc = R[j + c * r];
-          sc = (grp_sum(sc) + v0 * rjc) * f2;
-          for (int i = rl; i < cr; i += GRP) cc[i] = fma(-sc, cj[i], cc[i]);
-          if (rl == 0) R[j + c * r] = rjc - sc * v0;
+          sc = tau * (grp_sum(sc) + rjc);
+          for (int i = rl; i < cr; i += GRP) cc[i] = fma(-sc, cj[i] * iv0, cc[i]);
+          if (rl == 0) R[j + c * r] = rjc - sc;
         }
         __syncthreads();  // trailing columns final; R_jj and column j no longer read
         if (threadIdx.x == 0) R[j + j * r] = alpha;
@@ -534,26 +666,43 @@ __global__ __launch_bounds__(WG) void k_inverse(const InvDesc* __restrict__ desc
 // remaining columns receive the same row swaps and then one rank-nb update
 // (two GEMM shapes planned on the host).  A final pass undoes the column
 // permutation.
+template <bool kLds>
 __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ descs, int j0, int nb,
                                                  int* __restrict__ piv_all, int ldp, Status* st) {
-  extern __shared__ double f[];  // m entries
+  extern __shared__ double f[];  // m entries (+ the m x nb panel when kLds)
   const InvDesc d = descs[blockIdx.x];
   const int m = d.m;
   if (d.A == nullptr || j0 >= m) return;
   const int nbe = min(nb, m - j0);
-  double* A = d.A;
-  const size_t lda = d.lda;
+  double* A;
+  size_t lda;
+  int c0;  // column index of panel column 0 inside A
+  if (kLds) {
+    A = f + m;
+    lda = m;
+    c0 = 0;
+    for (int e = threadIdx.x; e < m * nbe; e += WG) {
+      const int i = e % m, t = e / m;
+      A[i + t * lda] = d.A[i + (size_t)(j0 + t) * d.lda];
+    }
+    __syncthreads();
+  } else {
+    A = d.A + (size_t)j0 * d.lda;
+    lda = d.lda;
+    c0 = 0;
+  }
+  (void)c0;
   int* piv = piv_all + (size_t)blockIdx.x * ldp;
   __shared__ double rowj[64];
   __shared__ double rv[WG / WAVE];
   __shared__ int ri[WG / WAVE];
   bool bad = false;
   for (int t = 0; t < nbe; ++t) {
-    const int j = j0 + t;
+    const int j = j0 + t;  // global row / column index of the pivot
     double bv = -1.0;
     int bi = m;
     for (int i = j + threadIdx.x; i < m; i += WG) {
-      const double a = fabs(A[i + j * lda]);
+      const double a = fabs(A[i + t * lda]);
       if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
     }
     double pv;
@@ -561,28 +710,42 @@ __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ des
     block_argmax(bv, bi, rv, ri, pv, p);
     if (threadIdx.x == 0) piv[j] = p;
     if (p != j && threadIdx.x < nbe) {
-      const int c = j0 + threadIdx.x;
+      const int c = threadIdx.x;
       const double tmp = A[j + c * lda];
       A[j + c * lda] = A[p + c * lda];
       A[p + c * lda] = tmp;
     }
     __syncthreads();
-    const double djj = A[j + j * lda];
+    const double djj = A[j + t * lda];
     if (djj == 0.0) bad = true;
     const double inv = 1.0 / djj;
-    for (int i = threadIdx.x; i < m; i += WG) f[i] = A[i + j * lda];
+    double* fcol = kLds ? f : nullptr;
+    __shared__ double fbuf_small[1];
+    (void)fbuf_small;
+    if (kLds) {
+      for (int i = threadIdx.x; i < m; i += WG) fcol[i] = A[i + t * lda];
+    } else {
+      for (int i = threadIdx.x; i < m; i += WG) f[i] = A[i + t * lda];
+      fcol = f;
+    }
     if (threadIdx.x < nbe) {
-      const int c = j0 + threadIdx.x;
-      rowj[threadIdx.x] = c == j ? inv : A[j + c * lda] * inv;
+      const int c = threadIdx.x;
+      rowj[c] = c == t ? inv : A[j + c * lda] * inv;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m * nbe; e += WG) {
-      const int i = e % m, tc = e / m, c = j0 + tc;
-      if (i == j) A[i + c * lda] = rowj[tc];
-      else if (c == j) A[i + c * lda] = -f[i] * inv;
-      else A[i + c * lda] -= f[i] * rowj[tc];
+      const int i = e % m, tc = e / m;
+      if (i == j) A[i + tc * lda] = rowj[tc];
+      else if (tc == t) A[i + tc * lda] = -fcol[i] * inv;
+      else A[i + tc * lda] -= fcol[i] * rowj[tc];
     }
     __syncthreads();
+  }
+  if (kLds) {
+    for (int e = threadIdx.x; e < m * nbe; e += WG) {
+      const int i = e % m, t = e / m;
+      d.A[i + (size_t)(j0 + t) * d.lda] = A[i + t * lda];
+    }
   }
   if (bad && threadIdx.x == 0 && st) {
     if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
@@ -679,6 +842,17 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k_rrqr<true>, dim3(nd), dim3(WG), lds, s, d);
 }
 
+void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st,
+                       hipStream_t s) {
+  if (nd <= 0) return;
+  const int tiles = cdiv(max_m, 4 * (WG / GRP));  // ~64 columns per workgroup
+  hipLaunchKernelGGL(k_rrqr_init, dim3(nd, tiles), dim3(WG), 0, s, d, st);
+  for (int j = 0; j < max_k; ++j) {
+    hipLaunchKernelGGL(k_rrqr_pivot, dim3(nd), dim3(WG), 0, s, d, st, j);
+    hipLaunchKernelGGL(k_rrqr_update, dim3(nd, tiles), dim3(WG), 0, s, d, st, j);
+  }
+}
+
 void launch_formq(const FormQDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
   hipLaunchKernelGGL(k_formq, dim3(nd), dim3(WG), 0, s, d);
@@ -710,7 +884,19 @@ void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hi
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(k_gj_panel, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv, ldp, st);
+  const size_t lds = sizeof(double) * (size_t)max_m * (nb + 1);
+  if (lds <= 150 * 1024) {
+    static bool raised = false;
+    if (!raised && lds > 64 * 1024) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      raised = true;
+    }
+    hipLaunchKernelGGL(k_gj_panel<true>, dim3(nd), dim3(WG), lds, s, d, j0, nb, piv, ldp, st);
+  } else {
+    hipLaunchKernelGGL(k_gj_panel<false>, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv,
+                       ldp, st);
+  }
 }
 
 void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const int* piv, int ldp,
