@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns/s IFMM factor+solve at N=1M, rel resid 1e-8: mixed vs FP64 GPU"
 PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6}
+SINGLE_KERNEL = {"gemm": "k_gemm", "add": "k_add", "xform": "k_xform", "qr": "k_qr",
+                 "formq": "k_formq", "stackqr": "k_stackqr"}
 WORKLOAD = ("1,048,576 uniform points in [0,1]^2, exp(-r/0.1) + 1e-2 I, leaf 64, "
             "p=6 (rank 36), eps 1e-8, 1 rhs, FP64 factor+solve with FP64 refinement to 1e-8")
 
@@ -82,10 +84,15 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        t0 = time.perf_counter()
         s = IFMMSolver(pts, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, refine_tol=1e-8, profile=True)
+        t1 = time.perf_counter()
         s.solve(b)
         st, info = s.stats(), s.last_info
+        t2 = time.perf_counter()
         s.close()
+        t3 = time.perf_counter()
+        st["wall_ms"] = {"factor_call": (t1 - t0) * 1e3, "solve_call": (t2 - t1) * 1e3, "destroy": (t3 - t2) * 1e3}
         return st, info
 
     for w in range(args.warmup):
@@ -97,7 +104,8 @@ def main():
     recs = []
     for k in range(args.steps):
         recs.append(step())
-        print(f"step {k}: t_f {recs[-1][0]['factor_ms']:.0f} ms", file=sys.stderr, flush=True)
+        print(f"step {k}: t_f {recs[-1][0]['factor_ms']:.0f} ms  wall {recs[-1][0]['wall_ms']}", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) / args.steps * 1e3
@@ -109,7 +117,10 @@ def main():
             a = fam.setdefault(name, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
             for key in a:
                 a[key] += kv[key]
-    dom = max(fam, key=lambda k: fam[k]["ms"])
+    # The roofline is taken for one kernel: families whose ops are a single
+    # kernel each (the pivoted QR and the blocked inverse span several).
+    single = [k for k in fam if k in SINGLE_KERNEL]
+    dom = max(single, key=lambda k: fam[k]["ms"])
     d = fam[dom]
     t_s = d["ms"] / 1e3
     flops_rate = d["flops"] / t_s / 1e12 if t_s > 0 else 0.0
@@ -121,10 +132,11 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": flops_rate, "peak": PEAK["fp64_TFs"], "unit": "TFLOP/s",
                 "frac": flops_rate / PEAK["fp64_TFs"], "traffic": None}
-    roof.update({"kernel": dom, "launches_per_step": d["launches"] / len(recs),
+    roof.update({"kernel": SINGLE_KERNEL[dom], "launches_per_step": d["launches"] / len(recs),
                  "avg_launch_ms": d["ms"] / max(1, d["launches"]),
                  "algorithmic_flops_per_launch": d["flops"] / max(1, d["launches"]),
-                 "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"])})
+                 "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"]),
+                 "hbm_GBs": bw, "fp64_TFs": flops_rate})
     st0, info0 = recs[-1]
     out = {
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
@@ -132,11 +144,13 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N, "precision": "fp64",
                    "t_assembly_ms": st0["assembly_ms"], "t_factor_ms": st0["factor_ms"],
-                   "t_solve_ms": st0["last_solve_ms"], "refine_iterations": info0["iterations"],
+                   "t_solve_ms": st0["last_solve_ms"], "wall_ms": st0["wall_ms"], "refine_iterations": info0["iterations"],
                    "final_residual": info0["residual"], "residual_history": info0["history"],
                    "max_rank": st0["max_rank"], "level_max_rank": st0["level_max_rank"],
                    "factor_bytes": st0["factor_bytes"], "factor_flops": st0["factor_flops"],
-                   "kernel_ms_per_step": {k: v["ms"] / len(recs) for k, v in fam.items()}},
+                   "kernels_per_step": {k: {"ms": v["ms"] / len(recs), "launches": v["launches"] / len(recs),
+                                            "gflop": v["flops"] / len(recs) / 1e9,
+                                            "gbyte": v["bytes"] / len(recs) / 1e9} for k, v in fam.items()}},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
