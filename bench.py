@@ -1,4 +1,5 @@
-"""Benchmark: IFMM factor + solve on one MI355X at N = 1,048,576.
+"""Benchmark: IFMM factor + solve on one MI355X at N = 1,048,576, mixed
+precision against FP64.
 
 Workload (one step = the whole hot path on one batch of synthetic input):
   1,048,576 i.i.d. uniform points in [0,1]^2, K(r) = exp(-r/0.1) with
@@ -6,8 +7,11 @@ Workload (one step = the whole hot path on one batch of synthetic input):
   (rank 36), compression eps = 1e-8, one N(0,1) right-hand side; factor
   (assembly + Algorithm 1) then solve (Algorithm 2) with FP64 refinement
   until ||b - A x|| / ||b|| <= 1e-8 against the FMM matrix.
-Inputs are resident in HBM before the timed region; the timed region covers
-K complete steps (ifmm_factor + ifmm_solve + ifmm_destroy).
+The headline runs the mixed-precision factor (FP32 blocks, Schur updates and
+recompression; FP64 pivot inverses, top solve, FMM product, residuals and
+vectors); the same steps with the FP64 factor are timed after it for the
+speedup.  Inputs are resident in HBM before the timed regions; a timed
+region covers K complete steps (ifmm_factor + ifmm_solve + ifmm_destroy).
 
 Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
 """
@@ -21,11 +25,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "unknowns/s IFMM factor+solve at N=1M, rel resid 1e-8: mixed vs FP64 GPU"
-PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6}
-SINGLE_KERNEL = {"gemm": "k_gemm", "add": "k_add", "xform": "k_xform", "qr": "k_qr",
-                 "formq": "k_formq", "stackqr": "k_stackqr"}
+# MI355X peaks: HBM3E, FP64 and FP32 (vector and matrix alike) dense rates.
+PEAK = {"hbm_GBs": 8000.0, "fp64_TFs": 78.6, "fp32_TFs": 157.3}
 WORKLOAD = ("1,048,576 uniform points in [0,1]^2, exp(-r/0.1) + 1e-2 I, leaf 64, "
-            "p=6 (rank 36), eps 1e-8, 1 rhs, FP64 factor+solve with FP64 refinement to 1e-8")
+            "p=6 (rank 36), eps 1e-8, 1 rhs, factor+solve with FP64 refinement to 1e-8; "
+            "value: mixed-precision factor (FP32 blocks), fp64 figures alongside")
+# Profile slots whose launches are all one kernel instantiation, per factor
+# precision (the pivoted QR and the blocked inverse span several kernels).
+SINGLE_KERNEL = {
+    "fp64": {"gemm": "k_gemm<double, double, double>", "add": "k_add<double, double>",
+             "xform": "k_xform<double>", "formq": "k_formq<double>", "stackqr": "k_stackqr<double>"},
+    "fp32": {"gemm_f32": "k_gemm<float, float, float>", "xform_f32": "k_xform<float>",
+             "qr_f32": "k_qr<float>", "formq_f32": "k_formq<float>", "stackqr_f32": "k_stackqr<float>"},
+}
 
 
 def cpu_baseline(n_full):
@@ -57,35 +69,40 @@ def cpu_baseline(n_full):
     return {"value": tot_n / tot_t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(subs)} sub-squares of side 1/16 of the same 1M point set "
                       f"({tot_n} points, leaf boxes of the full problem's width), same kernel, "
-                      f"p, eps, refinement; {tot_t:.1f} s on 1 thread"}
+                      f"p, eps, FP64, refinement to 1e-8; {tot_t:.1f} s on 1 thread"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the IFMM factor+solve of one problem runs on a "
-              "single MI355X here (multi-GPU sharding is a design note, not built).", file=sys.stderr)
-        sys.exit(2)
+def roofline(fam, nrec, prec):
+    single = [k for k in fam if k in SINGLE_KERNEL[prec] and fam[k]["launches"] > 0]
+    dom = max(single, key=lambda k: fam[k]["ms"])
+    d = fam[dom]
+    t_s = d["ms"] / 1e3
+    flops_rate = d["flops"] / t_s / 1e12 if t_s > 0 else 0.0
+    bw = d["bytes"] / t_s / 1e9 if t_s > 0 else 0.0
+    peak_f = PEAK["fp32_TFs"] if dom.endswith("_f32") else PEAK["fp64_TFs"]
+    if d["bytes"] / (PEAK["hbm_GBs"] * 1e9) > d["flops"] / (peak_f * 1e12):
+        roof = {"bound": "hbm", "achieved": bw, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                "frac": bw / PEAK["hbm_GBs"], "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": flops_rate, "peak": peak_f, "unit": "TFLOP/s",
+                "frac": flops_rate / peak_f, "traffic": None}
+    roof.update({"kernel": SINGLE_KERNEL[prec][dom], "launches_per_step": d["launches"] / nrec,
+                 "avg_launch_ms": d["ms"] / max(1, d["launches"]),
+                 "algorithmic_flops_per_launch": d["flops"] / max(1, d["launches"]),
+                 "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"]),
+                 "achieved_GBs": bw, "achieved_TFs": flops_rate})
+    return roof
+
+
+def run(prec, pts, b, steps, warmup, N):
     import torch
 
-    import workloads
     from paper_1407_1572_amd import IFMMSolver
-
-    dev = torch.device("cuda:0")
-    N = args.n
-    pts = torch.from_numpy(workloads.points_for("c3_exp_1m", N)).to(dev)
-    b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", N)[:, 0].copy()).to(dev)
-    torch.cuda.synchronize()
 
     def step():
         t0 = time.perf_counter()
-        s = IFMMSolver(pts, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, refine_tol=1e-8, profile=True)
+        s = IFMMSolver(pts, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, refine_tol=1e-8, profile=True,
+                       precision=prec)
         t1 = time.perf_counter()
         s.solve(b)
         st, info = s.stats(), s.last_info
@@ -95,62 +112,75 @@ def main():
         st["wall_ms"] = {"factor_call": (t1 - t0) * 1e3, "solve_call": (t2 - t1) * 1e3, "destroy": (t3 - t2) * 1e3}
         return st, info
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         st, info = step()
-        print(f"warmup {w}: t_a {st['assembly_ms']:.0f} ms  t_f {st['factor_ms']:.0f} ms  "
-              f"t_s {st['last_solve_ms']:.0f} ms  resid {info['residual']:.2e}", file=sys.stderr, flush=True)
+        print(f"{prec} warmup {w}: t_a {st['assembly_ms']:.0f} ms  t_f {st['factor_ms']:.0f} ms  "
+              f"t_s {st['last_solve_ms']:.0f} ms  resid {info['residual']:.2e} ({info['iterations']} sweeps)",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     recs = []
-    for k in range(args.steps):
+    for k in range(steps):
         recs.append(step())
-        print(f"step {k}: t_f {recs[-1][0]['factor_ms']:.0f} ms  wall {recs[-1][0]['wall_ms']}", file=sys.stderr,
-              flush=True)
+        print(f"{prec} step {k}: t_f {recs[-1][0]['factor_ms']:.0f} ms  wall {recs[-1][0]['wall_ms']}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
-    value = N / (ms / 1e3)
-
+    ms = (time.perf_counter() - t0) / steps * 1e3
     fam = {}
     for st, _ in recs:
         for name, kv in st["kernels"].items():
             a = fam.setdefault(name, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
             for key in a:
                 a[key] += kv[key]
-    # The roofline is taken for one kernel: families whose ops are a single
-    # kernel each (the pivoted QR and the blocked inverse span several).
-    single = [k for k in fam if k in SINGLE_KERNEL]
-    dom = max(single, key=lambda k: fam[k]["ms"])
-    d = fam[dom]
-    t_s = d["ms"] / 1e3
-    flops_rate = d["flops"] / t_s / 1e12 if t_s > 0 else 0.0
-    bw = d["bytes"] / t_s / 1e9 if t_s > 0 else 0.0
-    hbm_bound = d["bytes"] / (PEAK["hbm_GBs"] * 1e9) > d["flops"] / (PEAK["fp64_TFs"] * 1e12)
-    if hbm_bound:
-        roof = {"bound": "hbm", "achieved": bw, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                "frac": bw / PEAK["hbm_GBs"], "traffic": None}
-    else:
-        roof = {"bound": "alu", "achieved": flops_rate, "peak": PEAK["fp64_TFs"], "unit": "TFLOP/s",
-                "frac": flops_rate / PEAK["fp64_TFs"], "traffic": None}
-    roof.update({"kernel": SINGLE_KERNEL[dom], "launches_per_step": d["launches"] / len(recs),
-                 "avg_launch_ms": d["ms"] / max(1, d["launches"]),
-                 "algorithmic_flops_per_launch": d["flops"] / max(1, d["launches"]),
-                 "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"]),
-                 "hbm_GBs": bw, "fp64_TFs": flops_rate})
     st0, info0 = recs[-1]
+    summary = {"unknowns_per_s": N / (ms / 1e3), "ms_per_step": ms,
+               "t_assembly_ms": st0["assembly_ms"], "t_factor_ms": st0["factor_ms"],
+               "t_solve_ms": st0["last_solve_ms"], "wall_ms": st0["wall_ms"],
+               "refine_status": max(info["status"] for _, info in recs),
+               "refine_iterations": info0["iterations"], "final_residual": info0["residual"],
+               "residual_history": info0["history"], "max_rank": st0["max_rank"],
+               "level_max_rank": st0["level_max_rank"], "level_mean_rank": st0["level_mean_rank"],
+               "factor_bytes": st0["factor_bytes"], "factor_flops": st0["factor_flops"],
+               "kernels_per_step": {k: {"ms": v["ms"] / len(recs), "launches": v["launches"] / len(recs),
+                                        "gflop": v["flops"] / len(recs) / 1e9,
+                                        "gbyte": v["bytes"] / len(recs) / 1e9}
+                                    for k, v in fam.items() if v["launches"] > 0}}
+    return summary, roofline(fam, len(recs), prec)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the IFMM factor+solve of one problem runs on a "
+              "single MI355X here (multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads
+
+    dev = torch.device("cuda:0")
+    N = args.n
+    pts = torch.from_numpy(workloads.points_for("c3_exp_1m", N)).to(dev)
+    b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", N)[:, 0].copy()).to(dev)
+    torch.cuda.synchronize()
+
+    mixed, roof = run("fp32", pts, b, args.steps, args.warmup, N)
+    fp64, roof64 = (None, None) if args.no_fp64 else run("fp64", pts, b, args.steps, args.warmup, N)
     out = {
-        "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": N, "precision": "fp64",
-                   "t_assembly_ms": st0["assembly_ms"], "t_factor_ms": st0["factor_ms"],
-                   "t_solve_ms": st0["last_solve_ms"], "wall_ms": st0["wall_ms"], "refine_iterations": info0["iterations"],
-                   "final_residual": info0["residual"], "residual_history": info0["history"],
-                   "max_rank": st0["max_rank"], "level_max_rank": st0["level_max_rank"],
-                   "factor_bytes": st0["factor_bytes"], "factor_flops": st0["factor_flops"],
-                   "kernels_per_step": {k: {"ms": v["ms"] / len(recs), "launches": v["launches"] / len(recs),
-                                            "gflop": v["flops"] / len(recs) / 1e9,
-                                            "gbyte": v["bytes"] / len(recs) / 1e9} for k, v in fam.items()}},
+        "metric": METRIC, "value": mixed["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": N, "mixed": mixed, "fp64": fp64,
+                   "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
+                   "roofline_fp64": roof64},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -64,6 +64,20 @@ typedef struct {
   double c0;
 } ifmm_kernel;
 
+/*
+ * Scalar type of the factor's stored blocks (the off-pivot blocks, bases,
+ * M2L operators and fill).  With IFMM_FP32 (the mixed-precision factor) the
+ * Schur updates and the fill recompression run in FP32 with FP32
+ * accumulation; the pivot-block inverses, the top system, the FMM product,
+ * the residuals and every solution vector stay FP64, so refinement recovers
+ * an FP64-accurate solution.  The relative compression threshold of an FP32
+ * factor is max(eps, 2.5e-7): pivot norms below that are FP32 rounding noise.
+ */
+typedef enum {
+  IFMM_FP64 = 0,
+  IFMM_FP32 = 1
+} ifmm_precision;
+
 typedef struct {
   int r_max;           /* rank cap of the compressed bases; 0 = 2 p^2; must be >= p^2, <= 128 */
   double refine_tol;   /* 0: plain solve; > 0: FP64 iterative refinement with the FMM product
@@ -72,6 +86,7 @@ typedef struct {
   double box_lo[2];    /* root box [lo, lo + size]^2 containing every point */
   double box_size;     /* 0 = unit square [0,1]^2 */
   int profile;         /* 1: time every batched kernel launch with HIP events (ifmm_stats) */
+  int precision;       /* ifmm_precision of the factor (0 = FP64) */
 } ifmm_options;
 
 typedef struct {
@@ -95,13 +110,16 @@ typedef struct {
   double factor_bytes;     /* device bytes held by the factor */
   double factor_flops;     /* counted FP64 flops of the factorisation */
   /* With ifmm_options.profile: per batched-kernel family, accumulated over the
-     handle's life -- 0 gemm, 1 add/copy, 2 basis transform, 3 Householder QR,
-     4 column-pivoted QR, 5 basis formation, 6 stacked R factor, 7 pivot inverse.
-     flops / bytes are the algorithmic counts of the launches. */
-  int64_t kernel_launches[8];
-  double kernel_ms[8];
-  double kernel_flops[8];
-  double kernel_bytes[8];
+     handle's life.  Slot f + 8 q: family f -- 0 gemm, 1 add/copy, 2 basis
+     transform, 3 Householder QR, 4 column-pivoted QR, 5 basis formation,
+     6 stacked R factor, 7 pivot inverse -- with q = 1 for launches computing
+     in FP32 (gemm: both operands FP32; add: FP32 destination).  flops / bytes
+     are the algorithmic counts of the launches (bytes at storage size). */
+  int64_t kernel_launches[16];
+  double kernel_ms[16];
+  double kernel_flops[16];
+  double kernel_bytes[16];
+  int precision;           /* ifmm_precision of the factor */
 } ifmm_stats_t;
 
 /*
@@ -115,8 +133,8 @@ typedef struct {
  *   opt        NULL for defaults
  *   out        receives the handle (owns all factor memory; free with ifmm_destroy)
  * Errors: EINVAL (n < 16, rank not a perfect square, p > 8, leaf_size < 1,
- * eps < 0 or NaN, kernel parameters, non-finite or out-of-box or duplicate
- * points), ENOMEM, ESINGULAR, EDEVICE.
+ * eps < 0 or NaN, kernel parameters, unknown precision, non-finite or
+ * out-of-box or duplicate points), ENOMEM, ESINGULAR, EDEVICE.
  */
 ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, double eps,
                         int leaf_size, int rank, const ifmm_options* opt, void* stream,

@@ -54,14 +54,15 @@ __global__ void k_leaf_interp(const double* __restrict__ pts, const int* __restr
   }
 }
 
+template <class T>
 __global__ void k_near(const double* __restrict__ pts, const int* __restrict__ start,
                        const int* __restrict__ cnt, const int* __restrict__ nbr9, KernelFn kf,
-                       const double* __restrict__ d, double* P, size_t slot_stride, int ld) {
+                       const double* __restrict__ d, T* P, size_t slot_stride, int ld) {
   const int i = blockIdx.x, s = blockIdx.y;
   const int j = nbr9[i * 9 + s];
   if (j < 0) return;
   const int ni = cnt[i], nj = cnt[j];
-  double* B = P + ((size_t)i * 9 + s) * slot_stride;
+  T* B = P + ((size_t)i * 9 + s) * slot_stride;
   const int si = start[i], sj = start[j];
   for (int e = threadIdx.x; e < ni * nj; e += blockDim.x) {
     const int a = e % ni, b = e / ni;
@@ -73,7 +74,7 @@ __global__ void k_near(const double* __restrict__ pts, const int* __restrict__ s
       const double dy = pts[2 * (si + a) + 1] - pts[2 * (sj + b) + 1];
       v = kval(kf, sqrt(dx * dx + dy * dy));
     }
-    B[a + (size_t)b * ld] = v;
+    B[a + (size_t)b * ld] = (T)v;
   }
 }
 
@@ -255,11 +256,15 @@ void launch_leaf_interp(const double* pts, const int* leaf_start, const int* lea
 }
 
 void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
-                       const int* nbr9, int nleaf, KernelFn kf, const double* d, double* P,
+                       const int* nbr9, int nleaf, KernelFn kf, const double* d, void* P, int f32,
                        size_t slot_stride, int ld, int max_n, hipStream_t s) {
   (void)max_n;
-  hipLaunchKernelGGL(k_near, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
-                     d, P, slot_stride, ld);
+  if (f32)
+    hipLaunchKernelGGL(k_near<float>, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
+                       d, static_cast<float*>(P), slot_stride, ld);
+  else
+    hipLaunchKernelGGL(k_near<double>, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
+                       d, static_cast<double*>(P), slot_stride, ld);
 }
 
 void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s) {

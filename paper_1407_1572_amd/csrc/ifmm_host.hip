@@ -59,18 +59,47 @@ void dfree(T*& p) {
 
 inline int rup(int a, int b) { return (a + b - 1) / b * b; }
 constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
+// Relative threshold floor of the fill compression in an FP32 factor: pivot
+// norms below a few FP32 rounding units of the first are rounding noise
+// there, so a smaller eps would only keep noise directions up to the cap.
+constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
-enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_INV, OP_GJPANEL, OP_GJREST, OP_GJUNPERM };
+enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM };
 constexpr int kOpTypes = 8;  // profile families; the three blocked-inverse pieces count as 7
-inline int family(int t) { return t >= 8 ? 7 : t; }
+inline int family(int t) { return t >= OP_GJPANEL ? 7 : t; }
 struct Op {
   OpType t;
   size_t off, off2;
   int count, a, b;
   double flops, bytes;  // algorithmic work of the launch
   size_t off2b = 0;
+  int ty = 0;  // scalar type code of the descriptors
 };
+
+inline double esz(int f32) { return f32 ? 4.0 : 8.0; }
+
+// Splits v into runs of equal type code (first-seen order) and calls
+// f(run, ty) for each: one launch per type combination.
+template <class D, class F>
+void by_type(const std::vector<D>& v, F f) {
+  if (v.empty()) return;
+  bool mixed = false;
+  for (const D& d : v) mixed |= d.ty != v[0].ty;
+  if (!mixed) {
+    f(v, v[0].ty);
+    return;
+  }
+  std::vector<int> seen;
+  for (const D& d : v)
+    if (std::find(seen.begin(), seen.end(), d.ty) == seen.end()) seen.push_back(d.ty);
+  for (int t : seen) {
+    std::vector<D> g;
+    for (const D& d : v)
+      if (d.ty == t) g.push_back(d);
+    f(g, t);
+  }
+}
 
 struct Stage {
   std::vector<char> blob;
@@ -82,139 +111,144 @@ struct Stage {
     std::memcpy(blob.data() + off, p, n);
     return off;
   }
+  void op(Op o, int ty) {
+    o.ty = ty;
+    ops.push_back(o);
+  }
   // Algorithmic counts: flops of the operation as defined, bytes = every
-  // operand read once and every output written once (8-byte words).
-  void gemm(const std::vector<GemmDesc>& v) {
-    if (v.empty()) return;
-    int mm = 0, nn = 0;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      mm = std::max(mm, d.M);
-      nn = std::max(nn, d.N);
-      f += 2.0 * d.M * d.N * d.K;
-      by += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
-    }
-    flops += f;
-    ops.push_back({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn, f, by});
+  // operand read once and every output written once, at its storage size.
+  void gemm(const std::vector<GemmDesc>& all) {
+    by_type(all, [&](const std::vector<GemmDesc>& v, int ty) {
+      int mm = 0, nn = 0;
+      double f = 0, by = 0;
+      const double sa = esz(ty & 1), sb = esz(ty & 2), sc = esz(ty & 4);
+      for (const auto& d : v) {
+        mm = std::max(mm, d.M);
+        nn = std::max(nn, d.N);
+        f += 2.0 * d.M * d.N * d.K;
+        by += sa * d.M * d.K + sb * (double)d.K * d.N + sc * (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N;
+      }
+      flops += f;
+      op({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn, f, by}, ty);
+    });
   }
-  void add(const std::vector<AddDesc>& v) {
-    if (v.empty()) return;
-    int mm = 0, nn = 0;
-    double by = 0;
-    for (const auto& d : v) {
-      mm = std::max(mm, d.M);
-      nn = std::max(nn, d.N);
-      by += 8.0 * d.M * d.N * ((d.A ? 1.0 : 0.0) + (d.beta != 0.0 ? 2.0 : 1.0));
-    }
-    ops.push_back({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn, 0.0, by});
+  void add(const std::vector<AddDesc>& all) {
+    by_type(all, [&](const std::vector<AddDesc>& v, int ty) {
+      int mm = 0, nn = 0;
+      double by = 0;
+      for (const auto& d : v) {
+        mm = std::max(mm, d.M);
+        nn = std::max(nn, d.N);
+        by += (double)d.M * d.N * ((d.A ? esz(ty & 1) : 0.0) + esz(ty & 2) * (d.beta != 0.0 ? 2.0 : 1.0));
+      }
+      op({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn, 0.0, by}, ty);
+    });
   }
-  void xform(const std::vector<XformDesc>& v) {
-    if (v.empty()) return;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      const int rz = d.T ? d.r_new : d.r_old, cn = d.S ? d.c_new : d.c_old;
-      f += 2.0 * (d.T ? (double)d.r_new * d.r_old * d.c_old : 0) + 2.0 * (d.S ? (double)rz * d.c_old * d.c_new : 0);
-      by += 8.0 * ((double)d.r_old * d.c_old + (d.T ? (double)d.r_new * d.r_old : 0) +
-                   (d.S ? (double)d.c_old * d.c_new : 0) + (double)rz * cn);
-    }
-    flops += f;
-    ops.push_back({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0, f, by});
+  void xform(const std::vector<XformDesc>& all) {
+    by_type(all, [&](const std::vector<XformDesc>& v, int ty) {
+      double f = 0, by = 0;
+      for (const auto& d : v) {
+        const int rz = d.T ? d.r_new : d.r_old, cn = d.S ? d.c_new : d.c_old;
+        f += 2.0 * (d.T ? (double)d.r_new * d.r_old * d.c_old : 0) + 2.0 * (d.S ? (double)rz * d.c_old * d.c_new : 0);
+        by += esz(ty) * ((double)d.r_old * d.c_old + (d.T ? (double)d.r_new * d.r_old : 0) +
+                         (d.S ? (double)d.c_old * d.c_new : 0) + (double)rz * cn);
+      }
+      flops += f;
+      op({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
+    });
   }
-  void qr(const std::vector<QrDesc>& v) {
-    if (v.empty()) return;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      const double K = std::min(d.n, d.m);
-      f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
-           + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
-      by += 8.0 * (2.0 * d.n * d.m + K * d.m);
-    }
-    flops += f;
-    ops.push_back({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by});
+  void qr(const std::vector<QrDesc>& all) {
+    by_type(all, [&](const std::vector<QrDesc>& v, int ty) {
+      double f = 0, by = 0;
+      for (const auto& d : v) {
+        const double K = std::min(d.n, d.m);
+        f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
+             + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
+        by += esz(ty) * (2.0 * d.n * d.m + K * d.m);
+      }
+      flops += f;
+      op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
+    });
   }
   // Pivoted QRs: matrices that fit in LDS go to the LDS kernel (b = 1); the
   // rest run the multi-workgroup version (b = 0) with per-matrix norms in
   // nrm_ws (sum of m doubles).
   void rrqr(const std::vector<RrqrDesc>& all, double* nrm_ws) {
-    if (all.empty()) return;
-    std::vector<RrqrDesc> grp[2];
-    for (const auto& d : all) {
-      const size_t need = sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m);
-      grp[need <= kRrqrLdsBytes ? 1 : 0].push_back(d);
-    }
-    for (int g = 0; g < 2; ++g) {
-      const auto& v = grp[g];
-      if (v.empty()) continue;
-      int mm = 0, kk = 0;
-      size_t lds = 0;
+    size_t nrm_off = 0;
+    by_type(all, [&](const std::vector<RrqrDesc>& byt, int ty) {
+      const size_t es = ty ? sizeof(float) : sizeof(double);
+      std::vector<RrqrDesc> grp[2];
+      for (const auto& d : byt) {
+        const size_t need = es * ((size_t)(d.n + 1) * d.m + d.m);
+        grp[need <= kRrqrLdsBytes ? 1 : 0].push_back(d);
+      }
+      for (int g = 0; g < 2; ++g) {
+        const auto& v = grp[g];
+        if (v.empty()) continue;
+        int mm = 0, kk = 0;
+        size_t lds = 0;
+        double f = 0, by = 0;
+        for (const auto& d : v) {
+          mm = std::max(mm, d.m);
+          lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
+          const int K = std::min(std::min(d.n, d.m), d.kmax);
+          kk = std::max(kk, K);
+          for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
+          by += 2.0 * es * d.n * (double)d.m;
+        }
+        flops += f;
+        const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
+        if (g == 1) {
+          op({OP_RRQR, o, (size_t)lds, (int)v.size(), mm, 1, f, by}, ty);
+        } else {
+          std::vector<RrqrState> st(v.size());
+          for (size_t i = 0; i < v.size(); ++i) {
+            st[i] = RrqrState{nrm_ws + nrm_off, 0.0, 0, 1, 0, 0};
+            nrm_off += v[i].m;
+          }
+          const size_t o2 = push(st.data(), st.size() * sizeof(RrqrState));
+          Op x{OP_RRQR, o, o2, (int)v.size(), mm, 0, f, by};
+          x.off2b = (size_t)kk;
+          op(x, ty);
+        }
+      }
+    });
+  }
+  void formq(const std::vector<FormQDesc>& all) {
+    by_type(all, [&](const std::vector<FormQDesc>& v, int ty) {
       double f = 0, by = 0;
       for (const auto& d : v) {
-        mm = std::max(mm, d.m);
-        lds = std::max(lds, sizeof(double) * ((size_t)(d.n + 1) * d.m + d.m));
-        const int K = std::min(std::min(d.n, d.m), d.kmax);
-        kk = std::max(kk, K);
-        for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
-        by += 16.0 * d.n * (double)d.m;
+        for (int j = 0; j < d.kk; ++j) f += 4.0 * (d.n - j) * (double)(d.r - j);
+        by += esz(ty) * ((double)d.n * d.kk + (double)d.n * d.r);
       }
       flops += f;
-      const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
-      if (g == 1) {
-        ops.push_back({OP_RRQR, o, (size_t)lds, (int)v.size(), mm, 1, f, by});
-      } else {
-        std::vector<RrqrState> st(v.size());
-        size_t off = 0;
-        for (size_t i = 0; i < v.size(); ++i) {
-          st[i] = RrqrState{nrm_ws + off, 0.0, 0, 1, 0, 0};
-          off += v[i].m;
-        }
-        const size_t o2 = push(st.data(), st.size() * sizeof(RrqrState));
-        Op op{OP_RRQR, o, o2, (int)v.size(), mm, 0, f, by};
-        op.off2b = (size_t)kk;
-        ops.push_back(op);
-      }
-    }
+      op({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
+    });
   }
-  void formq(const std::vector<FormQDesc>& v) {
-    if (v.empty()) return;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      for (int j = 0; j < d.kk; ++j) f += 4.0 * (d.n - j) * (double)(d.r - j);
-      by += 8.0 * ((double)d.n * d.kk + (double)d.n * d.r);
-    }
-    flops += f;
-    ops.push_back({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0, f, by});
-  }
+  // All blocks of a stack have the type of its R.
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
     if (v.empty()) return;
+    const int ty = v[0].ty;
+    for (const auto& d : v)
+      if (d.ty != ty) throw BadArg{};
     int rr = 0;
     double f = 0, by = 0;
     for (const auto& d : v) {
       rr = std::max(rr, d.r);
       for (int t = 0; t < d.nblk; ++t) {
         f += 2.0 * b[d.first + t].rows * (double)d.r * d.r;
-        by += 8.0 * b[d.first + t].rows * (double)d.r;
+        by += esz(ty) * b[d.first + t].rows * (double)d.r;
       }
-      by += 8.0 * d.r * d.r;
+      by += esz(ty) * d.r * d.r;
     }
     flops += f;
     size_t o1 = push(v.data(), v.size() * sizeof(StackQrDesc));
     size_t o2 = push(b.data(), std::max<size_t>(1, b.size()) * sizeof(BlkRef));
-    ops.push_back({OP_STACKQR, o1, o2, (int)v.size(), rr, 0, f, by});
+    op({OP_STACKQR, o1, o2, (int)v.size(), rr, 0, f, by}, ty);
   }
-  void inv(const std::vector<InvDesc>& v) {
-    if (v.empty()) return;
-    int mm = 0;
-    double f = 0, by = 0;
-    for (const auto& d : v) {
-      mm = std::max(mm, d.m);
-      f += 2.0 * d.m * d.m * (double)d.m;
-      by += 16.0 * d.m * (double)d.m;
-    }
-    flops += f;
-    ops.push_back({OP_INV, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by});
-  }
-  // Blocked Gauss-Jordan inverse of every matrix in v (panels of nb columns);
-  // piv (nd x maxm ints) and tmp (nd x nb x maxm doubles) are device workspace.
+  // Blocked Gauss-Jordan inverse (FP64) of every matrix in v (panels of nb
+  // columns); piv (nd x maxm ints) and tmp (nd x nb x maxm doubles) are
+  // device workspace.
   void inv_blocked(const std::vector<InvDesc>& v, int* piv, double* tmp, int nb) {
     if (v.empty()) return;
     int mm = 0;
@@ -230,8 +264,9 @@ struct Stage {
           fp += 3.0 * d.m * nbe * nbe;
           bp += 16.0 * d.m * nbe;
         }
-      ops.push_back({OP_GJPANEL, o, (size_t)(uintptr_t)piv, nd, mm, j0, fp, bp});
-      ops.push_back({OP_GJREST, o, (size_t)(uintptr_t)tmp, nd, mm, j0, 0.0, 0.0});
+      flops += fp;
+      op({OP_GJPANEL, o, (size_t)(uintptr_t)piv, nd, mm, j0, fp, bp}, 0);
+      op({OP_GJREST, o, (size_t)(uintptr_t)tmp, nd, mm, j0, 0.0, 0.0}, 0);
       ops.back().off2b = (size_t)(uintptr_t)piv;
       std::vector<GemmDesc> g;
       for (int b = 0; b < nd; ++b) {
@@ -255,7 +290,7 @@ struct Stage {
       }
       gemm(g);
     }
-    ops.push_back({OP_GJUNPERM, o, (size_t)(uintptr_t)piv, nd, mm, 0, 0.0, 0.0});
+    op({OP_GJUNPERM, o, (size_t)(uintptr_t)piv, nd, mm, 0, 0.0, 0.0}, 0);
   }
   bool empty() const { return ops.empty(); }
   void clear() {
@@ -312,22 +347,24 @@ struct Arena {
   }
 };
 
-// Grow-only device workspace.
+// Grow-only device workspace (typed views of one allocation).
 struct Buf {
-  double* p = nullptr;
-  size_t n = 0;
-  double* need(size_t m, hipStream_t s) {
-    if (m > n) {
+  char* p = nullptr;
+  size_t bytes = 0;
+  template <class U = double>
+  U* need(size_t m, hipStream_t s) {
+    const size_t b = std::max<size_t>(m, 1) * sizeof(U);
+    if (b > bytes) {
       HIP_OK(hipStreamSynchronize(s));
       dfree(p);
-      p = dalloc<double>(m);
-      n = m;
+      p = dalloc<char>(b);
+      bytes = b;
     }
-    return p;
+    return reinterpret_cast<U*>(p);
   }
   void release() {
     dfree(p);
-    n = 0;
+    bytes = 0;
   }
 };
 
@@ -389,6 +426,9 @@ double now_ms() {
 }
 
 // ------------------------------------------------------------------- levels
+// Blocks of one level, in the factor's scalar type T, except the pivot
+// inverses (always FP64).
+template <class T>
 struct Level {
   int k = 0, nside = 0, nc = 0;
   std::vector<int> n, r, colour, nbr9, choff;  // choff: [nc*4] offsets of children's multipoles
@@ -396,16 +436,16 @@ struct Level {
   size_t sP = 0, sQ = 0, sL = 0, sM = 0, sU = 0, sUP = 0, sD = 0;
   // one basis per cluster (symmetric system): U is both L2P and P2M^T, UP the
   // parent's transfer block of this child, Om the precomputed far-field weight
-  double *P = nullptr, *Qm = nullptr, *L = nullptr, *M = nullptr, *U = nullptr, *UP = nullptr,
-         *Dinv = nullptr, *Om = nullptr;
-  double* Pb(int i, int s) const { return P + ((size_t)i * 9 + s) * sP; }
-  double* Qb(int i, int s) const { return Qm + ((size_t)i * 9 + s) * sQ; }
-  double* Lb(int i, int s) const { return L + ((size_t)i * 9 + s) * sL; }
-  double* Mb(int i, int s) const { return M + ((size_t)i * 36 + s) * sM; }
-  double* Ub(int i) const { return U + (size_t)i * sU; }
-  double* UPb(int i) const { return UP + (size_t)i * sUP; }
+  T *P = nullptr, *Qm = nullptr, *L = nullptr, *M = nullptr, *U = nullptr, *UP = nullptr, *Om = nullptr;
+  double* Dinv = nullptr;
+  T* Pb(int i, int s) const { return P + ((size_t)i * 9 + s) * sP; }
+  T* Qb(int i, int s) const { return Qm + ((size_t)i * 9 + s) * sQ; }
+  T* Lb(int i, int s) const { return L + ((size_t)i * 9 + s) * sL; }
+  T* Mb(int i, int s) const { return M + ((size_t)i * 36 + s) * sM; }
+  T* Ub(int i) const { return U + (size_t)i * sU; }
+  T* UPb(int i) const { return UP + (size_t)i * sUP; }
   double* Db(int i) const { return Dinv + (size_t)i * sD; }
-  double* Omb(int i) const { return Om + (size_t)i * sUP; }
+  T* Omb(int i) const { return Om + (size_t)i * sUP; }
   void set_pads(int np) {
     npad = np;
     mpad = npad + rpad;
@@ -443,6 +483,8 @@ struct Elim {
 
 }  // namespace
 
+// Opaque handle of the C-ABI: the problem parameters, and the interface of
+// the factor engine, whose block scalar type is its template parameter.
 struct ifmm_plan {
   hipStream_t s = nullptr;
   int64_t N = 0;
@@ -453,13 +495,29 @@ struct ifmm_plan {
   double lox = 0.0, loy = 0.0, size = 1.0;
   double refine_tol = 0.0;
   int refine_maxit = 30;
+  bool profile = false;
+  virtual ~ifmm_plan() = default;
+  virtual void build(const double* points) = 0;  // assembly + Algorithm 1
+  virtual ifmm_status solve(const double* b, double* x, int nrhs, ifmm_solve_info* info) = 0;
+  virtual void matvec(const double* x, double* y, int nrhs) = 0;
+  virtual void diagonal(double* d) = 0;
+  virtual void stats(ifmm_stats_t* st) = 0;
+  virtual int ranks(int level, int* out, int count) = 0;
+  virtual void release() = 0;
+};
+
+namespace {
+
+template <class T>
+struct Plan final : ifmm_plan {
+  static constexpr bool kF32 = std::is_same<T, float>::value;
   std::vector<int> perm, leaf_start, leaf_n;
   double* d_pts = nullptr;
   int *d_perm = nullptr, *d_leaf_start = nullptr, *d_leaf_n = nullptr, *d_nbr9_leaf = nullptr;
   double* d_diag = nullptr;
   double* d_E = nullptr;
   std::vector<double*> d_table;
-  std::vector<Level> lv;
+  std::vector<Level<T>> lv;
   std::vector<std::vector<std::vector<Elim>>> plan;  // [k][colour] eliminations in order
   // top
   std::vector<int> top_ids, top_off;
@@ -474,7 +532,6 @@ struct ifmm_plan {
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
   int max_rank = 0;
   // per-kernel profile (HIP events around each batched launch)
-  bool profile = false;
   struct Pending {
     int t;
     hipEvent_t a, b;
@@ -482,8 +539,9 @@ struct ifmm_plan {
   };
   std::vector<Pending> pend;
   std::vector<hipEvent_t> evpool;
-  double prof_ms[kOpTypes] = {}, prof_flops[kOpTypes] = {}, prof_bytes[kOpTypes] = {};
-  long prof_launch[kOpTypes] = {};
+  // slot = family + kOpTypes * (1 if the launch computes in FP32)
+  double prof_ms[2 * kOpTypes] = {}, prof_flops[2 * kOpTypes] = {}, prof_bytes[2 * kOpTypes] = {};
+  long prof_launch[2 * kOpTypes] = {};
   hipEvent_t get_event() {
     if (!evpool.empty()) {
       hipEvent_t e = evpool.back();
@@ -522,27 +580,26 @@ struct ifmm_plan {
         HIP_OK(hipEventRecord(ea, s));
       }
       switch (op.t) {
-        case OP_GEMM: launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, s); break;
-        case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, s); break;
+        case OP_GEMM: launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
+        case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
         case OP_XFORM: {
           const int nwg = 2048;
-          double* z = wsXf.need((size_t)nwg * kMaxRank * kMaxRank, s);
-          launch_xform(reinterpret_cast<XformDesc*>(d + op.off), op.count, z, nwg, kMaxRank, s);
+          double* z = wsXf.need<double>((size_t)nwg * kMaxRank * kMaxRank, s);
+          launch_xform(reinterpret_cast<XformDesc*>(d + op.off), op.count, z, nwg, kMaxRank, op.ty, s);
           break;
         }
-        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, s); break;
+        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_RRQR:
-          if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, s);
+          if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
           else
             launch_rrqr_multi(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2b,
-                              reinterpret_cast<RrqrState*>(d + op.off2), s);
+                              reinterpret_cast<RrqrState*>(d + op.off2), op.ty, s);
           break;
-        case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, s); break;
+        case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_STACKQR:
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
-                         op.count, op.a, s);
+                         op.count, op.a, op.ty, s);
           break;
-        case OP_INV: launch_inverse(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
         case OP_GJPANEL:
           launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
@@ -560,7 +617,8 @@ struct ifmm_plan {
       HIP_OK(hipGetLastError());
       if (profile) {
         HIP_OK(hipEventRecord(eb, s));
-        pend.push_back({family(op.t), ea, eb, op.flops, op.bytes});
+        const bool f32 = op.t == OP_GEMM ? (op.ty & 3) == 3 : op.t == OP_ADD ? (op.ty & 2) != 0 : op.ty != 0;
+        pend.push_back({family(op.t) + (f32 ? kOpTypes : 0), ea, eb, op.flops, op.bytes});
         if (pend.size() > 4096) resolve_profile();
       }
     }
@@ -574,7 +632,7 @@ struct ifmm_plan {
     int mm = 0;
     for (const auto& d : v) mm = std::max(mm, d.m);
     double* tmp = wsInvT.need((size_t)v.size() * kInvNb * mm, s);
-    int* piv = reinterpret_cast<int*>(wsInvP.need(((size_t)v.size() * mm + 1) / 2 + 1, s));
+    int* piv = wsInvP.need<int>((size_t)v.size() * mm + 1, s);
     st.inv_blocked(v, piv, tmp, kInvNb);
   }
 
@@ -614,9 +672,9 @@ struct ifmm_plan {
           if (v[a] == v[a - 1]) throw BadArg{};
       }
     }
-    lv.assign(kappa + 1, Level());
+    lv.assign(kappa + 1, Level<T>());
     for (int k = 2; k <= kappa; ++k) {
-      Level& L = lv[k];
+      Level<T>& L = lv[k];
       L.k = k;
       L.nside = 1 << k;
       L.nc = L.nside * L.nside;
@@ -715,23 +773,28 @@ struct ifmm_plan {
     }
 
     // ---- leaf level: interpolation, orthonormal bases, near field
-    Level& Lf = lv[kappa];
+    Level<T>& Lf = lv[kappa];
     int nmax = 0;
     for (int i = 0; i < nleaf; ++i) {
       nmax = std::max(nmax, Lf.n[i]);
       Lf.r[i] = std::min(Lf.n[i], p2);
     }
     Lf.set_pads(rup(std::max(nmax, 1), 8));
-    Lf.P = dalloc<double>(Lf.sP * 9 * Lf.nc);
-    Lf.Qm = dalloc<double>(Lf.sQ * 9 * Lf.nc);
-    Lf.L = dalloc<double>(Lf.sL * 9 * Lf.nc);
-    Lf.U = dalloc<double>(Lf.sU * Lf.nc);
+    Lf.P = dalloc<T>(Lf.sP * 9 * Lf.nc);
+    Lf.Qm = dalloc<T>(Lf.sQ * 9 * Lf.nc);
+    Lf.L = dalloc<T>(Lf.sL * 9 * Lf.nc);
+    Lf.U = dalloc<T>(Lf.sU * Lf.nc);
     Lf.Dinv = dalloc<double>(Lf.sD * Lf.nc);
-    HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(double) * Lf.sQ * 9 * Lf.nc, s));
-    HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(double) * Lf.sL * 9 * Lf.nc, s));
-    launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, Lf.sP,
-                      Lf.npad, nmax, s);
-    launch_leaf_interp(d_pts, d_leaf_start, d_leaf_n, nleaf, kappa, lox, loy, size, p, Lf.U, Lf.sU,
+    HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, s));
+    HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, s));
+    launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
+                      Lf.sP, Lf.npad, nmax, s);
+    // Interpolation and orthonormalisation in FP64; an FP32 factor takes the
+    // rounded bases.
+    double* U64;
+    if constexpr (kF32) U64 = wsS2.need<double>(Lf.sU * Lf.nc, s);
+    else U64 = Lf.U;
+    launch_leaf_interp(d_pts, d_leaf_start, d_leaf_n, nleaf, kappa, lox, loy, size, p, U64, Lf.sU,
                        Lf.npad, nmax, s);
     // R factors of every level at assembly (r x p^2), kept until M2L is built
     std::vector<double*> Ra(kappa + 1, nullptr);
@@ -740,18 +803,24 @@ struct ifmm_plan {
       Stage st;
       std::vector<QrDesc> q;
       for (int i = 0; i < nleaf; ++i)
-        if (Lf.n[i] > 0) q.push_back({Lf.Ub(i), Ra[kappa] + (size_t)i * rpad * p2, Lf.n[i], p2, Lf.npad, rpad});
+        if (Lf.n[i] > 0) q.push_back({U64 + (size_t)i * Lf.sU, Ra[kappa] + (size_t)i * rpad * p2, Lf.n[i], p2, Lf.npad, rpad});
       st.qr(q);
+      if constexpr (kF32) {
+        std::vector<AddDesc> cv;
+        for (int i = 0; i < nleaf; ++i)
+          if (Lf.n[i] > 0) cv.push_back({U64 + (size_t)i * Lf.sU, Lf.Ub(i), Lf.n[i], Lf.r[i], Lf.npad, Lf.npad, 0, 1.0, 0.0});
+        st.add(cv);
+      }
       run(st);
     }
     // ---- non-leaf levels at assembly: S_P = [R_c E_c], QR, transfer blocks
     for (int k = kappa; k >= 2; --k) {
-      Level& L = lv[k];
-      L.UP = dalloc<double>(L.sUP == 0 ? (size_t)rpad * rpad * L.nc : L.sUP * L.nc);
+      Level<T>& L = lv[k];
+      L.UP = dalloc<T>(L.sUP == 0 ? (size_t)rpad * rpad * L.nc : L.sUP * L.nc);
     }
     for (int k = kappa - 1; k >= 2; --k) {
-      Level& L = lv[k];
-      Level& C = lv[k + 1];
+      Level<T>& L = lv[k];
+      Level<T>& C = lv[k + 1];
       L.choff.assign((size_t)L.nc * 4, 0);
       int nm = 0;
       for (int P = 0; P < L.nc; ++P) {
@@ -794,21 +863,21 @@ struct ifmm_plan {
       run(st);
     }
     for (int k = 2; k <= kappa; ++k) {
-      Level& L = lv[k];
+      Level<T>& L = lv[k];
       L.sUP = (size_t)rpad * rpad;
       L.sM = (size_t)rpad * rpad;
 
     }
     // ---- M2L in orthonormal coordinates: M_il = R_i K(dx,dy) R_l^T
     for (int k = 2; k <= kappa; ++k) {
-      Level& L = lv[k];
-      L.M = dalloc<double>(L.sM * 36 * L.nc);
-      HIP_OK(hipMemsetAsync(L.M, 0, sizeof(double) * L.sM * 36 * L.nc, s));
+      Level<T>& L = lv[k];
+      L.M = dalloc<T>(L.sM * 36 * L.nc);
+      HIP_OK(hipMemsetAsync(L.M, 0, sizeof(T) * L.sM * 36 * L.nc, s));
       double* tmp = wsA.need((size_t)L.nc * rpad * p2, s);
       for (int dx = -3; dx <= 3; ++dx)
         for (int dy = -3; dy <= 3; ++dy) {
           if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-          const double* T = d_table[k] + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
+          const double* Kt = d_table[k] + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
           std::vector<GemmDesc> g1, g2;
           for (int i = 0; i < L.nc; ++i) {
             if (L.r[i] == 0) continue;
@@ -817,7 +886,7 @@ struct ifmm_plan {
             const int l = morton2(jx, jy);
             if (L.r[l] == 0 || !in_ilist(i, l)) continue;
             double* ti = tmp + (size_t)i * rpad * p2;
-            g1.push_back({Ra[k] + (size_t)i * rpad * p2, T, ti, L.r[i], p2, p2, rpad, p2, rpad, 0, 0, 1.0, 0.0});
+            g1.push_back({Ra[k] + (size_t)i * rpad * p2, Kt, ti, L.r[i], p2, p2, rpad, p2, rpad, 0, 0, 1.0, 0.0});
             g2.push_back({ti, Ra[k] + (size_t)l * rpad * p2, L.Mb(i, slot36(i, l)), L.r[i], L.r[l], p2, rpad,
                           rpad, rpad, 0, 1, 1.0, 0.0});
           }
@@ -830,8 +899,8 @@ struct ifmm_plan {
     for (int k = 2; k <= kappa; ++k) dfree(Ra[k]);
     // ---- far-field weights of the parent levels, top-down
     for (int k = 2; k < kappa; ++k) {
-      Level& L = lv[k];
-      L.Om = dalloc<double>(L.sUP * L.nc);
+      Level<T>& L = lv[k];
+      L.Om = dalloc<T>(L.sUP * L.nc);
       std::vector<int> ids;
       for (int i = 0; i < L.nc; ++i)
         if (L.r[i] > 0) ids.push_back(i);
@@ -845,11 +914,11 @@ struct ifmm_plan {
   // transposed far-field row (+ the parent chain UP Omega_parent^T).
   template <class OutFn>
   void weights(int k, const std::vector<int>& ids, OutFn out) {
-    Level& L = lv[k];
+    Level<T>& L = lv[k];
     const int nt = (int)ids.size();
     if (nt == 0) return;
-    double* Z = nullptr;
-    if (k > 2) Z = wsZ.need((size_t)nt * rpad * rpad, s);
+    T* Z = nullptr;
+    if (k > 2) Z = wsZ.need<T>((size_t)nt * rpad * rpad, s);
     Stage st;
     std::vector<GemmDesc> g;
     std::vector<StackQrDesc> sd;
@@ -869,11 +938,11 @@ struct ifmm_plan {
         d.nblk++;
       }
       if (k > 2) {
-        Level& Pl = lv[k - 1];
+        Level<T>& Pl = lv[k - 1];
         const int P = q >> 2;
         const int rP = Pl.r[P];
         if (rP > 0) {
-          double* z = Z + (size_t)t * rpad * rpad;
+          T* z = Z + (size_t)t * rpad * rpad;
           g.push_back({Pl.Omb(P), L.UPb(q), z, rP, rq, rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
           br.push_back({z, rpad, rP, 0});
           d.nblk++;
@@ -889,15 +958,15 @@ struct ifmm_plan {
     if (S == 1) {
       st.stackqr(sd, br);
     } else {
-      double* part = wsSeg.need((size_t)nt * S * rpad * rpad, s);
+      T* part = wsSeg.need<T>((size_t)nt * S * rpad * rpad, s);
       std::vector<StackQrDesc> s1, s2;
       std::vector<BlkRef> b1, b2;
       for (int t = 0; t < nt; ++t) {
         const StackQrDesc& d = sd[t];
-        StackQrDesc fin{d.R, d.r, d.ldr, (int)b2.size(), 0};
+        StackQrDesc fin{static_cast<T*>(d.R), d.r, d.ldr, (int)b2.size(), 0};
         const int per = (d.nblk + S - 1) / S;
         for (int g0 = 0; g0 < d.nblk; g0 += per) {
-          double* pr = part + ((size_t)t * S + g0 / per) * rpad * rpad;
+          T* pr = part + ((size_t)t * S + g0 / per) * rpad * rpad;
           StackQrDesc ps{pr, d.r, rpad, (int)b1.size(), 0};
           for (int x = g0; x < std::min(d.nblk, g0 + per); ++x) {
             b1.push_back(br[d.first + x]);
@@ -921,7 +990,7 @@ struct ifmm_plan {
     plan.assign(kappa + 1, std::vector<std::vector<Elim>>(9));
     for (int k = kappa; k >= 2; --k) {
       for (int c = 0; c < 9; ++c) phase(k, c);
-      Level& L = lv[k];
+      Level<T>& L = lv[k];
       for (int i = 0; i < L.nc; ++i) max_rank = std::max(max_rank, L.r[i]);
       if (k > 2) transition(k);
     }
@@ -935,7 +1004,7 @@ struct ifmm_plan {
   }
 
   void phase(int k, int c) {
-    Level& L = lv[k];
+    Level<T>& L = lv[k];
     std::vector<Elim>& E = plan[k][c];
     for (int i = 0; i < L.nc; ++i) {
       if (L.colour[i] != c || L.n[i] == 0) continue;
@@ -968,8 +1037,8 @@ struct ifmm_plan {
     if (nb == 0) return;
     const int fpad = std::max(L.npad, rpad);
     const int wpad = 8 * fpad + rpad;
-    double* X = wsX.need((size_t)nb * L.mpad * wpad, s);
-    double* F = wsF.need((size_t)nb * kPairs.count * fpad * fpad, s);
+    T* X = wsX.need<T>((size_t)nb * L.mpad * wpad, s);
+    T* F = wsF.need<T>((size_t)nb * kPairs.count * fpad * fpad, s);
     auto Xp = [&](int b) { return X + (size_t)b * L.mpad * wpad; };
     auto Fp = [&](int b, int sa, int sb) {
       return F + ((size_t)b * kPairs.count + kPairs.idx[sa][sb]) * fpad * fpad;
@@ -997,11 +1066,11 @@ struct ifmm_plan {
         for (int sp = 0; sp < 9; ++sp) {
           const UnitH& u = e.u[sp];
           if (!u.kind) continue;
-          double* Xc = Xp(b) + (size_t)u.off * L.mpad;
+          T* Xc = Xp(b) + (size_t)u.off * L.mpad;
           if (sp == 4) {
             ax.push_back({D + (size_t)e.ni * L.mpad, Xc, e.m, e.ri, L.mpad, L.mpad, 0, -1.0, 0.0});
           } else {
-            const double* Bsrc = u.kind == 1 ? L.Pb(e.i, sp) : L.Qb(e.i, sp);
+            const T* Bsrc = u.kind == 1 ? L.Pb(e.i, sp) : L.Qb(e.i, sp);
             gx.push_back({D, Bsrc, Xc, e.m, u.size, e.ni, L.mpad, L.npad, L.mpad, 0, 0, 1.0, 0.0});
           }
         }
@@ -1015,13 +1084,13 @@ struct ifmm_plan {
         for (int sa = 0; sa < 9; ++sa) {
           const UnitH& ua = e.u[sa];
           if (!ua.kind || sa == 4) continue;
-          const double* Ca = ua.kind == 1 ? L.Pb(ua.cl, 8 - sa) : L.Lb(ua.cl, 8 - sa);
+          const T* Ca = ua.kind == 1 ? L.Pb(ua.cl, 8 - sa) : L.Lb(ua.cl, 8 - sa);
           const int lda = ua.kind == 1 ? L.npad : rpad;
           for (int sb = 0; sb < 9; ++sb) {
             const UnitH& ub = e.u[sb];
             if (!ub.kind) continue;
-            const double* Xb = Xp(b) + (size_t)ub.off * L.mpad;
-            double* C;
+            const T* Xb = Xp(b) + (size_t)ub.off * L.mpad;
+            T* C;
             int ldc;
             double beta = 1.0;
             const bool adj = pos_adjacent(sa, sb);
@@ -1045,7 +1114,7 @@ struct ifmm_plan {
         for (int sb = 0; sb < 9; ++sb) {
           const UnitH& ub = e.u[sb];
           if (!ub.kind) continue;
-          const double* Xz = Xp(b) + e.ni + (size_t)ub.off * L.mpad;
+          const T* Xz = Xp(b) + e.ni + (size_t)ub.off * L.mpad;
           if (ub.kind == 1) am.push_back({Xz, L.Lb(e.i, sb), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
           else am.push_back({Xz, L.Mb(e.i, slot36(e.i, ub.cl)), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
         }
@@ -1059,11 +1128,11 @@ struct ifmm_plan {
 
   template <class FpFn>
   void compress(int k, const std::vector<Elim>& E, int fpad, FpFn Fp) {
-    Level& L = lv[k];
+    Level<T>& L = lv[k];
     struct Touch {
       int q, b, sq;
     };
-    std::vector<Touch> T;
+    std::vector<Touch> touch;
     std::vector<int> tidx(L.nc, -1);
     for (int b = 0; b < (int)E.size(); ++b)
       for (int sq = 0; sq < 9; ++sq) {
@@ -1075,24 +1144,25 @@ struct ifmm_plan {
           cu += E[b].u[s2].size;
         }
         if (cu == 0) continue;
-        tidx[u.cl] = (int)T.size();
-        T.push_back({u.cl, b, sq});
+        tidx[u.cl] = (int)touch.size();
+        touch.push_back({u.cl, b, sq});
       }
-    const int nt = (int)T.size();
+    const int nt = (int)touch.size();
     if (nt == 0) return;
+    const double eps_c = kF32 ? std::max(eps, kF32EpsFloor) : eps;
     // Omega from the current state (before any basis change)
-    double* Om = wsB.need((size_t)nt * rpad * rpad, s);
+    T* Om = wsB.need<T>((size_t)nt * rpad * rpad, s);
     std::vector<int> ids(nt);
-    for (int t = 0; t < nt; ++t) ids[t] = T[t].q;
+    for (int t = 0; t < nt; ++t) ids[t] = touch[t].q;
     weights(k, ids, [&](int t) { return Om + (size_t)t * rpad * rpad; });
     // new bases, chunk by chunk: pivoted QR of [U Omega^T | fill of the row]
     const int cmax = rpad + 5 * fpad;
-    double* Uh = wsQ.need((size_t)nt * L.sU, s);
-    double* Tt = wsR.need((size_t)nt * rpad * rpad, s);
+    T* Uh = wsQ.need<T>((size_t)nt * L.sU, s);
+    T* Tt = wsR.need<T>((size_t)nt * rpad * rpad, s);
     const size_t per = (size_t)L.npad * cmax;
-    int chunk = (int)std::min<size_t>(nt, std::max<size_t>(64, ((size_t)12 << 30) / (per * sizeof(double))));
-    double* A = wsT.need(per * chunk + (size_t)chunk * 2 * kMaxRank, s);
-    double* tauA = A + per * chunk;
+    int chunk = (int)std::min<size_t>(nt, std::max<size_t>(64, ((size_t)12 << 30) / (per * sizeof(T))));
+    T* A = wsT.need<T>(per * chunk + (size_t)chunk * 2 * kMaxRank, s);
+    T* tauA = A + per * chunk;
     if (rank_cap < (size_t)2 * nt) {
       HIP_OK(hipStreamSynchronize(s));
       if (d_rank) (void)hipFree(d_rank);
@@ -1107,9 +1177,9 @@ struct ifmm_plan {
       std::vector<AddDesc> a;
       std::vector<RrqrDesc> rq;
       for (int t = t0; t < t1; ++t) {
-        const Touch& tc = T[t];
+        const Touch& tc = touch[t];
         const int q = tc.q, nq = L.n[q], rq0 = L.r[q];
-        double* Aw = A + (size_t)(t - t0) * per;
+        T* Aw = A + (size_t)(t - t0) * per;
         g.push_back({L.Ub(q), Om + (size_t)t * rpad * rpad, Aw, nq, rq0, rq0, L.npad, rpad, L.npad, 0, 1, 1.0, 0.0});
         int col = rq0;
         for (int s2 = 0; s2 < 9; ++s2) {
@@ -1118,9 +1188,9 @@ struct ifmm_plan {
           a.push_back({Fp(tc.b, tc.sq, s2), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 0, 1.0, 0.0});
           col += w;
         }
-        double* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
+        T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
-                      std::min(nq, r_cap), eps, 1});
+                      std::min(nq, r_cap), eps_c, 1});
       }
       st.gemm(g);
       st.add(a);
@@ -1132,10 +1202,10 @@ struct ifmm_plan {
       HIP_OK(hipStreamSynchronize(s));
       std::vector<FormQDesc> fq;
       for (int t = t0; t < t1; ++t) {
-        const int q = T[t].q, nq = L.n[q];
+        const int q = touch[t].q, nq = L.n[q];
         rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
-        double* Aw = A + (size_t)(t - t0) * per;
-        double* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
+        T* Aw = A + (size_t)(t - t0) * per;
+        T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         fq.push_back({Aw, tb, tb + kMaxRank, Uh + (size_t)t * L.sU, nq, rnew[t], std::min(rnew[t], hr[2 * t + 1]),
                       L.npad, L.npad});
       }
@@ -1146,7 +1216,7 @@ struct ifmm_plan {
     Stage st;
     std::vector<GemmDesc> g;
     for (int t = 0; t < nt; ++t) {
-      const int q = T[t].q, nq = L.n[q];
+      const int q = touch[t].q, nq = L.n[q];
       g.push_back({Uh + (size_t)t * L.sU, L.Ub(q), Tt + (size_t)t * rpad * rpad, rnew[t], L.r[q], nq, L.npad, L.npad,
                    rpad, 1, 0, 1.0, 0.0});
     }
@@ -1154,7 +1224,7 @@ struct ifmm_plan {
     auto Tm = [&](int t) { return Tt + (size_t)t * rpad * rpad; };
     std::vector<XformDesc> xf;
     for (int t = 0; t < nt; ++t) {
-      const int q = T[t].q;
+      const int q = touch[t].q;
       const int qx = demorton_x(q), qy = demorton_y(q);
       for (int sl = 0; sl < 36; ++sl) {
         const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
@@ -1178,14 +1248,14 @@ struct ifmm_plan {
     st.xform(xf);
     std::vector<AddDesc> cp;
     for (int t = 0; t < nt; ++t) {
-      const int q = T[t].q, nq = L.n[q];
+      const int q = touch[t].q, nq = L.n[q];
       cp.push_back({Uh + (size_t)t * L.sU, L.Ub(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
     }
     st.add(cp);
-    for (int t = 0; t < nt; ++t) L.r[T[t].q] = rnew[t];
+    for (int t = 0; t < nt; ++t) L.r[touch[t].q] = rnew[t];
     // project the compressed fill into M2L
     std::vector<GemmDesc> g1, g2;
-    double* tmp = wsS2.need((size_t)E.size() * kPairs.count * rpad * fpad, s);
+    T* tmp = wsS2.need<T>((size_t)E.size() * kPairs.count * rpad * fpad, s);
     for (int b = 0; b < (int)E.size(); ++b) {
       const Elim& e = E[b];
       for (int sa = 0; sa < 9; ++sa)
@@ -1195,10 +1265,10 @@ struct ifmm_plan {
           const UnitH& ua = e.u[sa];
           const UnitH& ub = e.u[sb];
           if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
-          const double* Fb = Fp(b, sa, sb);
-          double* C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
+          const T* Fb = Fp(b, sa, sb);
+          T* C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
           if (ua.kind == 1 && ub.kind == 1) {
-            double* tm = tmp + ((size_t)b * kPairs.count + pi) * rpad * fpad;
+            T* tm = tmp + ((size_t)b * kPairs.count + pi) * rpad * fpad;
             g1.push_back({L.Ub(ua.cl), Fb, tm, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 0.0});
             g2.push_back({tm, L.Ub(ub.cl), C, L.r[ua.cl], L.r[ub.cl], ub.size, rpad, L.npad, rpad, 0, 0, 1.0, 1.0});
           } else if (ua.kind == 1) {
@@ -1216,8 +1286,8 @@ struct ifmm_plan {
   // Level k -> k-1: particles are the children's multipoles; P2P from their
   // M2L; parent bases re-orthonormalised (z_P -> Ru z_P, y_P = Rv^T y^_P).
   void transition(int k) {
-    Level& C = lv[k];
-    Level& L = lv[k - 1];
+    Level<T>& C = lv[k];
+    Level<T>& L = lv[k - 1];
     int nm = 0;
     std::vector<int> rold(L.r);
     for (int P = 0; P < L.nc; ++P) {
@@ -1230,14 +1300,14 @@ struct ifmm_plan {
       nm = std::max(nm, o);
     }
     L.set_pads(rup(std::max(nm, 1), 8));
-    L.P = dalloc<double>(L.sP * 9 * L.nc);
-    L.Qm = dalloc<double>(L.sQ * 9 * L.nc);
-    L.L = dalloc<double>(L.sL * 9 * L.nc);
-    L.U = dalloc<double>(L.sU * L.nc);
+    L.P = dalloc<T>(L.sP * 9 * L.nc);
+    L.Qm = dalloc<T>(L.sQ * 9 * L.nc);
+    L.L = dalloc<T>(L.sL * 9 * L.nc);
+    L.U = dalloc<T>(L.sU * L.nc);
     L.Dinv = dalloc<double>(L.sD * L.nc);
-    HIP_OK(hipMemsetAsync(L.Qm, 0, sizeof(double) * L.sQ * 9 * L.nc, s));
-    HIP_OK(hipMemsetAsync(L.L, 0, sizeof(double) * L.sL * 9 * L.nc, s));
-    double* Ru = wsA.need((size_t)L.nc * rpad * rpad, s);
+    HIP_OK(hipMemsetAsync(L.Qm, 0, sizeof(T) * L.sQ * 9 * L.nc, s));
+    HIP_OK(hipMemsetAsync(L.L, 0, sizeof(T) * L.sL * 9 * L.nc, s));
+    T* Ru = wsA.need<T>((size_t)L.nc * rpad * rpad, s);
     auto Rub = [&](int P) { return Ru + (size_t)P * rpad * rpad; };
     Stage st;
     std::vector<AddDesc> a;
@@ -1246,7 +1316,7 @@ struct ifmm_plan {
       for (int sp = 0; sp < 9; ++sp) {
         const int Q = L.nbr9[(size_t)P * 9 + sp];
         if (Q < 0 || L.n[Q] == 0) continue;
-        double* B = L.Pb(P, sp);
+        T* B = L.Pb(P, sp);
         for (int c = 0; c < 4; ++c) {
           const int ch = 4 * P + c;
           if (C.r[ch] == 0) continue;
@@ -1296,7 +1366,7 @@ struct ifmm_plan {
   }
 
   void top() {
-    Level& L = lv[2];
+    Level<T>& L = lv[2];
     top_ids.clear();
     top_off.assign(1, 0);
     for (int c = 0; c < 16; ++c)
@@ -1330,7 +1400,7 @@ struct ifmm_plan {
     std::vector<size_t> ob(kappa + 1), oc(kappa + 1);
     size_t tot = 0;
     for (int k = 2; k <= kappa; ++k) {
-      const Level& L = lv[k];
+      const Level<T>& L = lv[k];
       ob[k] = tot;
       tot += (size_t)3 * L.nc * L.npad * nrhs;
       oc[k] = tot;
@@ -1343,7 +1413,7 @@ struct ifmm_plan {
         mmax = std::max(mmax, lv[k].mpad);
       }
     const size_t wsz = (size_t)nbmax * mmax * nrhs;
-    double* base = wsS1.need(tot + 2 * wsz + 2 * (size_t)std::max(top_m, 1) * nrhs, s);
+    double* base = wsS1.need<double>(tot + 2 * wsz + 2 * (size_t)std::max(top_m, 1) * nrhs, s);
     double* wv = base + tot;
     double* rv = wv + wsz;
     double* tv = rv + wsz;
@@ -1356,14 +1426,14 @@ struct ifmm_plan {
     Stage st;
     {
       std::vector<AddDesc> a;
-      const Level& Lf = lv[kappa];
+      const Level<T>& Lf = lv[kappa];
       for (int i = 0; i < Lf.nc; ++i)
         if (Lf.n[i]) a.push_back({bt + leaf_start[i], bvec(kappa, i), Lf.n[i], nrhs, (int)N, Lf.npad, 0, 1.0, 0.0});
       st.add(a);
       run(st);
     }
     for (int k = kappa; k >= 2; --k) {
-      const Level& L = lv[k];
+      const Level<T>& L = lv[k];
       for (int c = 0; c < 9; ++c) {
         const std::vector<Elim>& E = plan[k][c];
         if (E.empty()) continue;
@@ -1391,7 +1461,7 @@ struct ifmm_plan {
         run(st);
       }
       if (k > 2) {
-        const Level& Lp = lv[k - 1];
+        const Level<T>& Lp = lv[k - 1];
         std::vector<AddDesc> a;
         for (int P = 0; P < Lp.nc; ++P)
           for (int c = 0; c < 4; ++c) {
@@ -1415,7 +1485,7 @@ struct ifmm_plan {
       run(st);
     }
     for (int k = 2; k <= kappa; ++k) {
-      const Level& L = lv[k];
+      const Level<T>& L = lv[k];
       for (int c = 8; c >= 0; --c) {
         const std::vector<Elim>& E = plan[k][c];
         if (E.empty()) continue;
@@ -1452,7 +1522,7 @@ struct ifmm_plan {
         run(st);
       }
       if (k < kappa) {
-        const Level& Lc = lv[k + 1];
+        const Level<T>& Lc = lv[k + 1];
         std::vector<AddDesc> a;
         for (int P = 0; P < L.nc; ++P)
           for (int c = 0; c < 4; ++c) {
@@ -1464,14 +1534,160 @@ struct ifmm_plan {
       }
     }
     std::vector<AddDesc> a;
-    const Level& Lf = lv[kappa];
+    const Level<T>& Lf = lv[kappa];
     for (int i = 0; i < Lf.nc; ++i)
       if (Lf.n[i]) a.push_back({xvec(kappa, i), xt + leaf_start[i], Lf.n[i], nrhs, Lf.npad, (int)N, 0, 1.0, 0.0});
     st.add(a);
     run(st);
   }
 
-  void release() {
+  // ---------------------------------------------------------- entry points
+  void build(const double* points) override {
+    arena.init();
+    assemble(points);
+    factor();
+  }
+
+  void matvec(const double* x, double* y, int nrhs) override {
+    const int n = (int)N;
+    double* buf = wsS2.need<double>((size_t)2 * n * nrhs, s);
+    launch_gather_rows(x, n, d_perm, n, nrhs, buf, n, s);
+    fmm_apply_tree(buf, buf + (size_t)n * nrhs, nrhs, d_diag);
+    launch_scatter_rows(buf + (size_t)n * nrhs, n, d_perm, n, nrhs, y, n, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+  }
+
+  void diagonal(double* d) override {
+    launch_scatter_rows(d_diag, (int)N, d_perm, (int)N, 1, d, (int)N, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+  }
+
+  // Algorithm 2, then FP64 iterative refinement against the FMM product:
+  // x += A_f^-1 (b - A x) until every column meets refine_tol.
+  ifmm_status solve(const double* b, double* x, int nrhs, ifmm_solve_info* info) override {
+    ifmm_status result = IFMM_OK;
+    const double t0 = now_ms();
+    const int n = (int)N;
+    const size_t sz = (size_t)n * nrhs;
+    // tree-order vectors: b, x, r, dx, y, best x
+    double* base = wsB.need<double>(6 * sz + 2 * (size_t)nrhs, s);
+    double* bt = base;
+    double* xt = base + sz;
+    double* rt = base + 2 * sz;
+    double* dx = base + 3 * sz;
+    double* yt = base + 4 * sz;
+    double* xbest = base + 5 * sz;
+    double* nrm = base + 6 * sz;
+    launch_gather_rows(b, n, d_perm, n, nrhs, bt, n, s);
+    solve_tree(bt, xt, nrhs);
+    int it = 0;
+    std::vector<double> hist;
+    const double* xout = xt;
+    if (refine_tol > 0.0) {
+      std::vector<double> bn(nrhs), rn(nrhs);
+      HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
+      launch_colnorm2(bt, n, nrhs, n, nrm, s);
+      HIP_OK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      double best = 1e300;
+      while (true) {
+        fmm_apply_tree(xt, yt, nrhs, d_diag);
+        Stage st;
+        st.add({AddDesc{bt, rt, n, nrhs, n, n, 0, 1.0, 0.0}});
+        st.add({AddDesc{yt, rt, n, nrhs, n, n, 0, -1.0, 1.0}});
+        run(st);
+        HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
+        launch_colnorm2(rt, n, nrhs, n, nrm, s);
+        HIP_OK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        double worst = 0.0;
+        for (int r = 0; r < nrhs; ++r) worst = std::max(worst, std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300));
+        hist.push_back(worst);
+        if (worst <= refine_tol) {
+          xout = xt;
+          break;
+        }
+        if (worst < best) {  // keep the best iterate for a non-converged return
+          best = worst;
+          Stage sb;
+          sb.add({AddDesc{xt, xbest, n, nrhs, n, n, 0, 1.0, 0.0}});
+          run(sb);
+        }
+        if (it >= refine_maxit || (hist.size() >= 3 && worst > 0.9 * hist[hist.size() - 2] && worst > hist[0])) {
+          result = IFMM_ENOTCONV;
+          xout = xbest;
+          break;
+        }
+        solve_tree(rt, dx, nrhs);
+        Stage s2;
+        s2.add({AddDesc{dx, xt, n, nrhs, n, n, 0, 1.0, 1.0}});
+        run(s2);
+        ++it;
+      }
+    }
+    launch_scatter_rows(xout, n, d_perm, n, nrhs, x, n, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    t_solve = now_ms() - t0;
+    resolve_profile();
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = it;
+      info->residual = hist.empty() ? 0.0 : (result == IFMM_OK ? hist.back() : *std::min_element(hist.begin(), hist.end()));
+      for (size_t i = 0; i < hist.size() && i < 32; ++i) info->history[i] = hist[i];
+      info->solve_ms = t_solve;
+    }
+    return result;
+  }
+
+  void stats(ifmm_stats_t* st) override {
+    std::memset(st, 0, sizeof(*st));
+    st->n = N;
+    st->kappa = kappa;
+    st->p = p;
+    st->max_rank = max_rank;
+    double bytes = 0;
+    for (int k = 2; k <= kappa && k < 16; ++k) {
+      const Level<T>& L = lv[k];
+      int mx = 0;
+      double sum = 0;
+      int cnt = 0;
+      for (int i = 0; i < L.nc; ++i)
+        if (L.n[i] > 0) {
+          mx = std::max(mx, L.r[i]);
+          sum += L.r[i];
+          ++cnt;
+        }
+      st->level_max_rank[k] = mx;
+      st->level_mean_rank[k] = cnt ? sum / cnt : 0.0;
+      bytes += (double)L.nc * (sizeof(T) * 9.0 * (L.sP + L.sQ + L.sL) + sizeof(double) * L.sD);
+    }
+    st->top_size = top_m;
+    st->assembly_ms = t_assembly;
+    st->factor_ms = t_factor;
+    st->last_solve_ms = t_solve;
+    st->factor_bytes = bytes;
+    st->factor_flops = factor_flops;
+    st->precision = kF32 ? IFMM_FP32 : IFMM_FP64;
+    for (int t = 0; t < 2 * kOpTypes; ++t) {
+      st->kernel_launches[t] = prof_launch[t];
+      st->kernel_ms[t] = prof_ms[t];
+      st->kernel_flops[t] = prof_flops[t];
+      st->kernel_bytes[t] = prof_bytes[t];
+    }
+  }
+
+  int ranks(int level, int* out, int count) override {
+    if (level < 2 || level > kappa) return IFMM_EINVAL;
+    const Level<T>& L = lv[level];
+    if (count < L.nc) return IFMM_EINVAL;
+    for (int i = 0; i < L.nc; ++i) out[i] = L.r[i];
+    return IFMM_OK;
+  }
+
+  void release() override {
     for (auto& L : lv) L.free_all();
     for (auto& t : d_table) dfree(t);
     dfree(d_pts);
@@ -1498,8 +1714,6 @@ struct ifmm_plan {
     evpool.clear();
   }
 };
-
-namespace {
 
 ifmm_status map_exc() {
   try {
@@ -1536,7 +1750,11 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
   int r_cap = opt && opt->r_max > 0 ? opt->r_max : 2 * rank;
   if (r_cap > kMaxRank) r_cap = opt && opt->r_max > 0 ? -1 : kMaxRank;
   if (r_cap < rank || r_cap > kMaxRank) return IFMM_EINVAL;
-  ifmm_plan* h = new (std::nothrow) ifmm_plan();
+  const int prec = opt ? opt->precision : IFMM_FP64;
+  if (prec != IFMM_FP64 && prec != IFMM_FP32) return IFMM_EINVAL;
+  ifmm_plan* h = nullptr;
+  if (prec == IFMM_FP32) h = new (std::nothrow) Plan<float>();
+  else h = new (std::nothrow) Plan<double>();
   if (!h) return IFMM_ENOMEM;
   h->s = static_cast<hipStream_t>(stream);
   h->N = n;
@@ -1560,9 +1778,7 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
     h->refine_maxit = opt->refine_maxit > 0 ? opt->refine_maxit : 30;
   }
   try {
-    h->arena.init();
-    h->assemble(points);
-    h->factor();
+    h->build(points);
   } catch (...) {
     ifmm_status st = map_exc();
     (void)hipStreamSynchronize(h->s);
@@ -1578,13 +1794,7 @@ ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* st
   if (!h || !x || !y || nrhs < 1 || nrhs > 64) return IFMM_EINVAL;
   try {
     h->s = static_cast<hipStream_t>(stream);
-    const int N = (int)h->N;
-    double* buf = h->wsS2.need((size_t)2 * N * nrhs, h->s);
-    launch_gather_rows(x, N, h->d_perm, N, nrhs, buf, N, h->s);
-    h->fmm_apply_tree(buf, buf + (size_t)N * nrhs, nrhs, h->d_diag);
-    launch_scatter_rows(buf + (size_t)N * nrhs, N, h->d_perm, N, nrhs, y, N, h->s);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(h->s));
+    h->matvec(x, y, nrhs);
   } catch (...) {
     return map_exc();
   }
@@ -1595,9 +1805,7 @@ ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream) {
   if (!h || !d) return IFMM_EINVAL;
   try {
     h->s = static_cast<hipStream_t>(stream);
-    launch_scatter_rows(h->d_diag, (int)h->N, h->d_perm, (int)h->N, 1, d, (int)h->N, h->s);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(h->s));
+    h->diagonal(d);
   } catch (...) {
     return map_exc();
   }
@@ -1606,118 +1814,23 @@ ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream) {
 
 ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* stream, ifmm_solve_info* info) {
   if (!h || !b || !x || nrhs < 1 || nrhs > 64 || b == x) return IFMM_EINVAL;
-  ifmm_status result = IFMM_OK;
   try {
     h->s = static_cast<hipStream_t>(stream);
-    const double t0 = now_ms();
-    const int N = (int)h->N;
-    const size_t sz = (size_t)N * nrhs;
-    Buf& wb = h->wsB;  // tree-order vectors: b, x, r, dx, y
-    double* base = wb.need(5 * sz + 2 * (size_t)nrhs, h->s);
-    double* bt = base;
-    double* xt = base + sz;
-    double* rt = base + 2 * sz;
-    double* dx = base + 3 * sz;
-    double* yt = base + 4 * sz;
-    double* nrm = base + 5 * sz;
-    launch_gather_rows(b, N, h->d_perm, N, nrhs, bt, N, h->s);
-    h->solve_tree(bt, xt, nrhs);
-    int it = 0;
-    std::vector<double> hist;
-    if (h->refine_tol > 0.0) {
-      std::vector<double> bn(nrhs), rn(nrhs);
-      HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, h->s));
-      launch_colnorm2(bt, N, nrhs, N, nrm, h->s);
-      HIP_OK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->s));
-      HIP_OK(hipStreamSynchronize(h->s));
-      std::vector<double> best_res(nrhs, 1e300);
-      while (true) {
-        h->fmm_apply_tree(xt, yt, nrhs, h->d_diag);
-        Stage st;
-        st.add({AddDesc{bt, rt, N, nrhs, N, N, 0, 1.0, 0.0}});
-        st.add({AddDesc{yt, rt, N, nrhs, N, N, 0, -1.0, 1.0}});
-        h->run(st);
-        HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, h->s));
-        launch_colnorm2(rt, N, nrhs, N, nrm, h->s);
-        HIP_OK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, h->s));
-        HIP_OK(hipStreamSynchronize(h->s));
-        double worst = 0.0;
-        for (int r = 0; r < nrhs; ++r) worst = std::max(worst, std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300));
-        hist.push_back(worst);
-        if (worst <= h->refine_tol) break;
-        if (it >= h->refine_maxit || (hist.size() >= 3 && worst > 0.9 * hist[hist.size() - 2] && worst > hist[0])) {
-          result = IFMM_ENOTCONV;
-          break;
-        }
-        h->solve_tree(rt, dx, nrhs);
-        Stage s2;
-        s2.add({AddDesc{dx, xt, N, nrhs, N, N, 0, 1.0, 1.0}});
-        h->run(s2);
-        ++it;
-      }
-    }
-    launch_scatter_rows(xt, N, h->d_perm, N, nrhs, x, N, h->s);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(h->s));
-    h->t_solve = now_ms() - t0;
-    h->resolve_profile();
-    if (info) {
-      std::memset(info, 0, sizeof(*info));
-      info->iterations = it;
-      info->residual = hist.empty() ? 0.0 : hist.back();
-      for (size_t i = 0; i < hist.size() && i < 32; ++i) info->history[i] = hist[i];
-      info->solve_ms = h->t_solve;
-    }
+    return h->solve(b, x, nrhs, info);
   } catch (...) {
     return map_exc();
   }
-  return result;
 }
 
 ifmm_status ifmm_stats(ifmm_t h, ifmm_stats_t* s) {
   if (!h || !s) return IFMM_EINVAL;
-  std::memset(s, 0, sizeof(*s));
-  s->n = h->N;
-  s->kappa = h->kappa;
-  s->p = h->p;
-  s->max_rank = h->max_rank;
-  double bytes = 0;
-  for (int k = 2; k <= h->kappa && k < 16; ++k) {
-    const Level& L = h->lv[k];
-    int mx = 0;
-    double sum = 0;
-    int cnt = 0;
-    for (int i = 0; i < L.nc; ++i)
-      if (L.n[i] > 0) {
-        mx = std::max(mx, L.r[i]);
-        sum += L.r[i];
-        ++cnt;
-      }
-    s->level_max_rank[k] = mx;
-    s->level_mean_rank[k] = cnt ? sum / cnt : 0.0;
-    bytes += 8.0 * L.nc * (9.0 * (L.sP + L.sQ + L.sL) + L.sD);
-  }
-  s->top_size = h->top_m;
-  s->assembly_ms = h->t_assembly;
-  s->factor_ms = h->t_factor;
-  s->last_solve_ms = h->t_solve;
-  s->factor_bytes = bytes;
-  s->factor_flops = h->factor_flops;
-  for (int t = 0; t < kOpTypes; ++t) {
-    s->kernel_launches[t] = h->prof_launch[t];
-    s->kernel_ms[t] = h->prof_ms[t];
-    s->kernel_flops[t] = h->prof_flops[t];
-    s->kernel_bytes[t] = h->prof_bytes[t];
-  }
+  h->stats(s);
   return IFMM_OK;
 }
 
 ifmm_status ifmm_ranks(ifmm_t h, int level, int* out, int count) {
-  if (!h || !out || level < 2 || level > h->kappa) return IFMM_EINVAL;
-  const Level& L = h->lv[level];
-  if (count < L.nc) return IFMM_EINVAL;
-  for (int i = 0; i < L.nc; ++i) out[i] = L.r[i];
-  return IFMM_OK;
+  if (!h || !out) return IFMM_EINVAL;
+  return (ifmm_status)h->ranks(level, out, count);
 }
 
 void ifmm_destroy(ifmm_t h) {

@@ -1,52 +1,104 @@
 // Internal interface between the host orchestrator (ifmm_host.hip) and the
-// device kernels (ifmm_kernels.hip).  Everything is FP64, column-major.
+// device kernels (ifmm_linalg.hip, ifmm_fmm.hip).  Matrices are column-major.
 // Every batched kernel reads an array of descriptors planned on the host;
 // an entry whose sizes are zero is a no-op.
+//
+// Scalar types: the factor's blocks are FP64 or FP32 (the mixed-precision
+// factor); pivot inverses, the top system, the FMM product and all solution
+// vectors are FP64.  A descriptor records the scalar type of each operand in
+// `ty`, set by its constructor from the pointer types it is given, and a
+// launch runs the kernel instantiation for that type combination (all
+// descriptors of one launch share it).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace ifmm {
 
 constexpr int kMaxRank = 128;   // largest multipole/local rank supported
 constexpr int kMaxP = 8;        // largest Chebyshev order per dimension
 
+// 0 for double, 1 for float.
+template <class T>
+constexpr int tcode() {
+  static_assert(std::is_same<T, double>::value || std::is_same<T, float>::value, "FP64 or FP32 only");
+  return std::is_same<T, float>::value ? 1 : 0;
+}
+// Keeps a parameter out of template argument deduction.
+template <class X>
+struct nodeduce {
+  using type = X;
+};
+
 // C = alpha * op(A) op(B) + beta * C; beta == 0 never reads C.
+// ty: bit 0 A is FP32, bit 1 B is FP32, bit 2 C is FP32.  The products are
+// accumulated in FP64 when A or B is FP64, else in FP32.
 struct GemmDesc {
-  const double* A;
-  const double* B;
-  double* C;
+  const void* A;
+  const void* B;
+  void* C;
   int M, N, K;
   int lda, ldb, ldc;
   int opA, opB;  // 0: as stored, 1: transposed
   double alpha, beta;
+  int ty;
+  GemmDesc() = default;
+  template <class TA, class TB, class TC>
+  __host__ GemmDesc(const TA* a, const TB* b, TC* c, int M_, int N_, int K_, int lda_, int ldb_, int ldc_,
+                    int opA_, int opB_, double al, double be)
+      : A(a), B(b), C(c), M(M_), N(N_), K(K_), lda(lda_), ldb(ldb_), ldc(ldc_), opA(opA_), opB(opB_),
+        alpha(al), beta(be), ty(tcode<TA>() | tcode<TB>() << 1 | tcode<TC>() << 2) {}
 };
 
-// C = alpha * op(A) + beta * C (M x N); beta == 0 never reads C.
+// C = alpha * op(A) + beta * C (M x N); beta == 0 never reads C; A null
+// reads as zero.  ty: bit 0 A is FP32, bit 1 C is FP32.
 struct AddDesc {
-  const double* A;
-  double* C;
+  const void* A;
+  void* C;
   int M, N, lda, ldc, trans;
   double alpha, beta;
+  int ty;
+  AddDesc() = default;
+  template <class TA, class TC>
+  __host__ AddDesc(const TA* a, TC* c, int M_, int N_, int lda_, int ldc_, int tr, double al, double be)
+      : A(a), C(c), M(M_), N(N_), lda(lda_), ldc(ldc_), trans(tr), alpha(al), beta(be),
+        ty(tcode<TA>() | tcode<TC>() << 1) {}
+  template <class TC>
+  __host__ AddDesc(std::nullptr_t, TC* c, int M_, int N_, int lda_, int ldc_, int tr, double al, double be)
+      : A(nullptr), C(c), M(M_), N(N_), lda(lda_), ldc(ldc_), trans(tr), alpha(al), beta(be),
+        ty(tcode<TC>() | tcode<TC>() << 1) {}
 };
 
 // X <- T * X * S in place, X is r_old x c_old (ldx); T is r_new x r_old (ldt)
 // or null; S is c_old x c_new (lds), or its transpose when transS, or null.
 struct XformDesc {
-  double* X;
-  const double* T;
-  const double* S;
+  void* X;
+  const void* T;
+  const void* S;
   int r_old, c_old, r_new, c_new;
   int ldx, ldt, lds, transS;
+  int ty;
+  XformDesc() = default;
+  template <class U>
+  __host__ XformDesc(U* x, typename nodeduce<const U*>::type t, typename nodeduce<const U*>::type s_, int ro,
+                     int co, int rn, int cn, int ldx_, int ldt_, int lds_, int ts)
+      : X(x), T(t), S(s_), r_old(ro), c_old(co), r_new(rn), c_new(cn), ldx(ldx_), ldt(ldt_), lds(lds_),
+        transS(ts), ty(tcode<U>()) {}
 };
 
 // Householder QR in place: Q (n x K, K = min(n, m)) overwrites A, R (K x m)
 // is written to R; sign-normalised so that R_jj >= 0.
 struct QrDesc {
-  double* A;
-  double* R;
+  void* A;
+  void* R;
   int n, m, lda, ldr;
+  int ty;
+  QrDesc() = default;
+  template <class U>
+  __host__ QrDesc(U* a, typename nodeduce<U*>::type r, int n_, int m_, int lda_, int ldr_)
+      : A(a), R(r), n(n_), m(m_), lda(lda_), ldr(ldr_), ty(tcode<U>()) {}
 };
 
 // Column-pivoted Householder QR for up to kmax steps, in place.  Reflector j
@@ -55,14 +107,21 @@ struct QrDesc {
 // whose pivot norm exceeds eps * first pivot norm; with stop_at_rank the
 // factorisation stops at the first pivot at or below that threshold.
 struct RrqrDesc {
-  double* A;
-  double* tau;
-  double* alpha;
+  void* A;
+  void* tau;
+  void* alpha;
   int* rank;
   int* steps;
   int n, m, lda, kmax;
   double eps;
   int stop_at_rank;
+  int ty;
+  RrqrDesc() = default;
+  template <class U>
+  __host__ RrqrDesc(U* a, typename nodeduce<U*>::type tau_, typename nodeduce<U*>::type alpha_, int* rank_,
+                    int* steps_, int n_, int m_, int lda_, int kmax_, double eps_, int stop)
+      : A(a), tau(tau_), alpha(alpha_), rank(rank_), steps(steps_), n(n_), m(m_), lda(lda_), kmax(kmax_),
+        eps(eps_), stop_at_rank(stop), ty(tcode<U>()) {}
 };
 
 // Per-matrix state of the multi-workgroup pivoted QR (nrm: m doubles).
@@ -75,26 +134,37 @@ struct RrqrState {
 // Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with
 // column j negated where alpha[j] < 0.
 struct FormQDesc {
-  const double* A;
-  const double* tau;
-  const double* alpha;
-  double* Q;
+  const void* A;
+  const void* tau;
+  const void* alpha;
+  void* Q;
   int n, r, kk, lda, ldq;
+  int ty;
+  FormQDesc() = default;
+  template <class U>
+  __host__ FormQDesc(typename nodeduce<const U*>::type a, typename nodeduce<const U*>::type tau_,
+                     typename nodeduce<const U*>::type alpha_, U* q, int n_, int r_, int kk_, int lda_, int ldq_)
+      : A(a), tau(tau_), alpha(alpha_), Q(q), n(n_), r(r_), kk(kk_), lda(lda_), ldq(ldq_), ty(tcode<U>()) {}
 };
 
 // One block of a vertical stack whose R factor is wanted.
 struct BlkRef {
-  const double* p;
+  const void* p;
   int ld, rows, trans;  // the stacked block is p (rows x cols) or p^T
 };
 // R (r x r, upper triangular, R_jj >= 0) of the QR of the stack of nblk
-// blocks starting at blocks[first]; each block has r columns.
+// blocks starting at blocks[first]; each block has r columns, of R's type.
 struct StackQrDesc {
-  double* R;
+  void* R;
   int r, ldr, first, nblk;
+  int ty;
+  StackQrDesc() = default;
+  template <class U>
+  __host__ StackQrDesc(U* R_, int r_, int ldr_, int first_, int nblk_)
+      : R(R_), r(r_), ldr(ldr_), first(first_), nblk(nblk_), ty(tcode<U>()) {}
 };
 
-// Inverse of a square matrix in place (Gauss-Jordan, partial pivoting).
+// Inverse of a square FP64 matrix in place (Gauss-Jordan, partial pivoting).
 struct InvDesc {
   double* A;
   int m, lda;
@@ -133,23 +203,23 @@ struct Status {
 };
 
 // ---------------------------------------------------------------- launchers
-void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, hipStream_t s);
-void launch_add(const AddDesc* d, int nd, int max_m, int max_n, hipStream_t s);
-void launch_xform(const XformDesc* d, int nd, double* scratch, int nwg, int ld_scratch,
+// `ty` is the type code shared by the descriptors of the launch.
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
+void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
+// scratch: nwg * ld_scratch * kMaxRank elements of the descriptors' type.
+void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
                   hipStream_t s);
-void launch_qr(const QrDesc* d, int nd, hipStream_t s);
-void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s);
-// Same, with the whole matrix staged in LDS: (n + 1) * m + m doubles must fit
-// in `lds` <= kRrqrLdsBytes.
+void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
+// Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
+// must fit in `lds` <= kRrqrLdsBytes.
 constexpr size_t kRrqrLdsBytes = 150 * 1024;
-void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s);
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
 // Same arithmetic with every step split in a pivot launch and a column-tiled
 // update launch (many workgroups per matrix); max_k = largest step count.
-void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st,
+void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st, int ty,
                        hipStream_t s);
-void launch_formq(const FormQDesc* d, int nd, hipStream_t s);
-void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s);
-void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
+void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
+void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 // Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s);
@@ -168,10 +238,10 @@ void launch_leaf_interp(const double* pts, const int* leaf_start, const int* lea
                         int nleaf, int kappa, double lox, double loy, double size, int p,
                         double* dst, size_t stride, int ld, int max_n, hipStream_t s);
 // Near-field blocks of the leaves: dst[i][slot] = K(x_i, x_j), diagonal of the
-// self block replaced by d.
+// self block replaced by d; P is FP64 (f32 = 0) or FP32 (f32 = 1).
 void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
                        const int* nbr9, int nleaf, KernelFn kf, const double* d,
-                       double* P, size_t slot_stride, int ld, int max_n, hipStream_t s);
+                       void* P, int f32, size_t slot_stride, int ld, int max_n, hipStream_t s);
 // Kernel between the Chebyshev nodes of two boxes of half-width h whose
 // centres differ by (dx, dy) * 2h, for the 49 offsets dx, dy in [-3, 3].
 void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s);

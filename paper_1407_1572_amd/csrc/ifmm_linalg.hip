@@ -1,9 +1,10 @@
-// Batched dense linear algebra for the IFMM on gfx950 (FP64).
+// Batched dense linear algebra for the IFMM on gfx950 (FP64 and FP32).
 //
 // Every kernel consumes an array of descriptors planned on the host, one
 // independent small problem per descriptor (the clusters of one colour batch
 // never share a block, so their problems run concurrently).  Wave size 64,
-// 256-thread workgroups; matrices are column-major.
+// 256-thread workgroups; matrices are column-major.  Kernels are templates
+// over the scalar type of their operands; the pivot inverse is FP64 only.
 #include "ifmm_internal.h"
 
 namespace ifmm {
@@ -13,27 +14,30 @@ namespace {
 constexpr int WG = 256;
 constexpr int WAVE = 64;
 
-__device__ inline double wave_sum(double v) {
+template <class T>
+__device__ inline T wave_sum(T v) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
   return v;
 }
 
-// Block-wide sum; every thread gets the result.  red must hold WG/WAVE doubles.
-__device__ inline double block_sum(double v, double* red) {
+// Block-wide sum; every thread gets the result.  red must hold WG/WAVE values.
+template <class T>
+__device__ inline T block_sum(T v, T* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   __syncthreads();
   if (lane == 0) red[w] = v;
   __syncthreads();
-  double t = 0.0;
+  T t = 0;
   for (int i = 0; i < WG / WAVE; ++i) t += red[i];
   return t;
 }
 
 // Block-wide argmax of (value, index): largest value, smallest index on ties.
-__device__ inline void block_argmax(double v, int idx, double* rv, int* ri, double& bv, int& bi) {
+template <class T>
+__device__ inline void block_argmax(T v, int idx, T* rv, int* ri, T& bv, int& bi) {
   for (int o = WAVE / 2; o > 0; o >>= 1) {
-    double ov = __shfl_xor(v, o, WAVE);
+    T ov = __shfl_xor(v, o, WAVE);
     int oi = __shfl_xor(idx, o, WAVE);
     if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
   }
@@ -47,43 +51,60 @@ __device__ inline void block_argmax(double v, int idx, double* rv, int* ri, doub
     if (rv[i] > bv || (rv[i] == bv && ri[i] < bi)) { bv = rv[i]; bi = ri[i]; }
 }
 
+// Sum over the 16 lanes of a lane group (lanes 16g .. 16g+15 of a wave).
+constexpr int GRP = 16;
+template <class T>
+__device__ inline T grp_sum(T v) {
+  v += __shfl_xor(v, 1, WAVE);
+  v += __shfl_xor(v, 2, WAVE);
+  v += __shfl_xor(v, 4, WAVE);
+  v += __shfl_xor(v, 8, WAVE);
+  return v;
+}
+
 // ------------------------------------------------------------------- GEMM
 // 64 x 64 output tile per workgroup, 4 x 4 per thread, K staged by 16 in LDS.
+template <class TA, class TB, class TC>
 __global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs, int tiles_m) {
+  using Acc = typename std::conditional<std::is_same<TA, float>::value && std::is_same<TB, float>::value,
+                                        float, double>::type;
   const GemmDesc d = descs[blockIdx.x];
   const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
   const int m0 = tm * 64, n0 = tn * 64;
   if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  const TA* __restrict__ Ap = static_cast<const TA*>(d.A);
+  const TB* __restrict__ Bp = static_cast<const TB*>(d.B);
+  TC* Cp = static_cast<TC*>(d.C);
+  __shared__ Acc As[16][65];
+  __shared__ Acc Bs[16][65];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  Acc acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
   for (int k0 = 0; k0 < d.K; k0 += 16) {
     for (int e = threadIdx.x; e < 1024; e += WG) {
       int mm, kk;
       if (d.opA == 0) { mm = e % 64; kk = e / 64; } else { kk = e % 16; mm = e / 16; }
       const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
+      Acc v = 0;
       if (gm < d.M && gk < d.K)
-        v = d.opA == 0 ? d.A[gm + (size_t)gk * d.lda] : d.A[gk + (size_t)gm * d.lda];
+        v = (Acc)(d.opA == 0 ? Ap[gm + (size_t)gk * d.lda] : Ap[gk + (size_t)gm * d.lda]);
       As[kk][mm] = v;
       int nn;
       if (d.opB == 0) { kk = e % 16; nn = e / 16; } else { nn = e % 64; kk = e / 64; }
       const int gn = n0 + nn;
       const int gk2 = k0 + kk;
-      double w = 0.0;
+      Acc w = 0;
       if (gn < d.N && gk2 < d.K)
-        w = d.opB == 0 ? d.B[gk2 + (size_t)gn * d.ldb] : d.B[gn + (size_t)gk2 * d.ldb];
+        w = (Acc)(d.opB == 0 ? Bp[gk2 + (size_t)gn * d.ldb] : Bp[gn + (size_t)gk2 * d.ldb]);
       Bs[kk][nn] = w;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+      Acc a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
 #pragma unroll
@@ -95,131 +116,141 @@ __global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs,
     }
     __syncthreads();
   }
+  const Acc al = (Acc)d.alpha, be = (Acc)d.beta;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int gm = m0 + tx + 16 * i, gn = n0 + ty + 16 * j;
       if (gm < d.M && gn < d.N) {
-        double* c = d.C + gm + (size_t)gn * d.ldc;
-        *c = d.beta == 0.0 ? d.alpha * acc[i][j] : fma(d.alpha, acc[i][j], d.beta * *c);
+        TC* c = Cp + gm + (size_t)gn * d.ldc;
+        *c = (TC)(d.beta == 0.0 ? al * acc[i][j] : fma(al, acc[i][j], be * (Acc)*c));
       }
     }
 }
 
 // -------------------------------------------------------------------- ADD
+// Computed in FP64, stored in C's type.
+template <class TA, class TC>
 __global__ __launch_bounds__(WG) void k_add(const AddDesc* __restrict__ descs, int tiles_m) {
   const AddDesc d = descs[blockIdx.x];
   const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
   const int m0 = tm * 64, n0 = tn * 64;
   if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
+  const TA* Ap = static_cast<const TA*>(d.A);
+  TC* Cp = static_cast<TC*>(d.C);
   for (int e = threadIdx.x; e < 64 * 64; e += WG) {
     const int i = m0 + e % 64, j = n0 + e / 64;
     if (i < d.M && j < d.N) {
-      const double a = d.A == nullptr ? 0.0
-                       : (d.trans ? d.A[j + (size_t)i * d.lda] : d.A[i + (size_t)j * d.lda]);
-      double* c = d.C + i + (size_t)j * d.ldc;
-      *c = d.beta == 0.0 ? d.alpha * a : fma(d.alpha, a, d.beta * *c);
+      const double a = Ap == nullptr ? 0.0
+                       : (double)(d.trans ? Ap[j + (size_t)i * d.lda] : Ap[i + (size_t)j * d.lda]);
+      TC* c = Cp + i + (size_t)j * d.ldc;
+      *c = (TC)(d.beta == 0.0 ? d.alpha * a : fma(d.alpha, a, d.beta * (double)*c));
     }
   }
 }
 
 // ------------------------------------------------------------------ XFORM
 // X <- T X S with Z = T X staged in a per-workgroup global scratch.
-__global__ __launch_bounds__(WG) void k_xform(const XformDesc* __restrict__ descs, int nd,
-                                              double* scratch, int ldz) {
-  double* Z = scratch + (size_t)blockIdx.x * ldz * kMaxRank;
+template <class T>
+__global__ __launch_bounds__(WG) void k_xform(const XformDesc* __restrict__ descs, int nd, T* scratch,
+                                              int ldz) {
+  T* Z = scratch + (size_t)blockIdx.x * ldz * kMaxRank;
   for (int di = blockIdx.x; di < nd; di += gridDim.x) {
     const XformDesc d = descs[di];
     if (d.X == nullptr || (d.T == nullptr && d.S == nullptr)) continue;
-    const int rz = d.T ? d.r_new : d.r_old;  // rows of Z
+    T* X = static_cast<T*>(d.X);
+    const T* Tm = static_cast<const T*>(d.T);
+    const T* Sm = static_cast<const T*>(d.S);
+    const int rz = Tm ? d.r_new : d.r_old;  // rows of Z
     for (int e = threadIdx.x; e < rz * d.c_old; e += WG) {
       const int i = e % rz, j = e / rz;
-      double v;
-      if (d.T) {
-        v = 0.0;
-        for (int k = 0; k < d.r_old; ++k)
-          v = fma(d.T[i + (size_t)k * d.ldt], d.X[k + (size_t)j * d.ldx], v);
+      T v;
+      if (Tm) {
+        v = 0;
+        for (int k = 0; k < d.r_old; ++k) v = fma(Tm[i + (size_t)k * d.ldt], X[k + (size_t)j * d.ldx], v);
       } else {
-        v = d.X[i + (size_t)j * d.ldx];
+        v = X[i + (size_t)j * d.ldx];
       }
       Z[i + (size_t)j * ldz] = v;
     }
     __syncthreads();
-    const int cn = d.S ? d.c_new : d.c_old;
+    const int cn = Sm ? d.c_new : d.c_old;
     for (int e = threadIdx.x; e < rz * cn; e += WG) {
       const int i = e % rz, j = e / rz;
-      double v;
-      if (d.S) {
-        v = 0.0;
+      T v;
+      if (Sm) {
+        v = 0;
         for (int k = 0; k < d.c_old; ++k) {
-          const double s = d.transS ? d.S[j + (size_t)k * d.lds] : d.S[k + (size_t)j * d.lds];
+          const T s = d.transS ? Sm[j + (size_t)k * d.lds] : Sm[k + (size_t)j * d.lds];
           v = fma(Z[i + (size_t)k * ldz], s, v);
         }
       } else {
         v = Z[i + (size_t)j * ldz];
       }
-      d.X[i + (size_t)j * d.ldx] = v;
+      X[i + (size_t)j * d.ldx] = v;
     }
     __syncthreads();
   }
 }
 
 // --------------------------------------------------------------------- QR
+template <class T>
 __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
   const QrDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m, K = min(n, m);
   if (d.A == nullptr || K == 0 || K > kMaxRank) return;
-  double* A = d.A;
+  T* A = static_cast<T*>(d.A);
+  T* R = static_cast<T*>(d.R);
   const size_t lda = d.lda;
-  __shared__ double red[WG / WAVE];
-  __shared__ double tau_s[kMaxRank], alpha_s[kMaxRank];
+  __shared__ T red[WG / WAVE];
+  __shared__ T tau_s[kMaxRank], alpha_s[kMaxRank];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
   for (int j = 0; j < K; ++j) {
-    double part = 0.0;
+    T part = 0;
     for (int i = j + threadIdx.x; i < n; i += WG) part += A[i + j * lda] * A[i + j * lda];
-    const double nrm = sqrt(block_sum(part, red));
-    const double x0 = A[j + j * lda];
-    double alpha = 0.0, tau = 0.0, v0 = 1.0;
-    if (nrm > 0.0) {
-      alpha = x0 >= 0.0 ? -nrm : nrm;
+    const T nrm = sqrt(block_sum(part, red));
+    const T x0 = A[j + j * lda];
+    T alpha = 0, tau = 0, v0 = 1;
+    if (nrm > 0) {
+      alpha = x0 >= 0 ? -nrm : nrm;
       v0 = x0 - alpha;
       tau = -v0 / alpha;
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = nrm > 0.0 ? A[i + j * lda] / v0 : 0.0;
+    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = nrm > 0 ? A[i + j * lda] / v0 : T(0);
     if (threadIdx.x == 0) { tau_s[j] = tau; alpha_s[j] = alpha; }
     __syncthreads();
     for (int c = j + 1 + w; c < m; c += nw) {
-      double s = 0.0;
+      T s = 0;
       for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
       s = wave_sum(s) + A[j + c * lda];
-      const double ts = tau * s;
+      const T ts = tau * s;
       for (int i = j + 1 + lane; i < n; i += WAVE) A[i + c * lda] -= ts * A[i + j * lda];
       if (lane == 0) A[j + c * lda] -= ts;
     }
     __syncthreads();
     // row j of R is final now
     for (int c = threadIdx.x; c < m; c += WG)
-      d.R[j + (size_t)c * d.ldr] = c < j ? 0.0 : (c == j ? alpha : A[j + c * lda]);
+      R[j + (size_t)c * d.ldr] = c < j ? T(0) : (c == j ? alpha : A[j + c * lda]);
     __syncthreads();
   }
   // form Q in place (backward accumulation)
   for (int j = K - 1; j >= 0; --j) {
-    const double tau = tau_s[j];
+    const T tau = tau_s[j];
     for (int c = j + 1 + w; c < K; c += nw) {
-      double s = 0.0;
+      T s = 0;
       for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * A[i + c * lda];
       s = wave_sum(s) + A[j + c * lda];
-      const double ts = tau * s;
+      const T ts = tau * s;
       for (int i = j + 1 + lane; i < n; i += WAVE) A[i + c * lda] -= ts * A[i + j * lda];
       if (lane == 0) A[j + c * lda] -= ts;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += WG) {
-      double v;
-      if (i < j) v = 0.0;
-      else if (i == j) v = 1.0 - tau;
+      T v;
+      if (i < j) v = 0;
+      else if (i == j) v = 1 - tau;
       else v = -tau * A[i + j * lda];
       A[i + j * lda] = v;
     }
@@ -227,62 +258,46 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
   }
   // sign normalisation: R_jj >= 0
   for (int j = 0; j < K; ++j) {
-    if (alpha_s[j] < 0.0) {
+    if (alpha_s[j] < 0) {
       for (int i = threadIdx.x; i < n; i += WG) A[i + j * lda] = -A[i + j * lda];
-      for (int c = j + threadIdx.x; c < m; c += WG) d.R[j + (size_t)c * d.ldr] = -d.R[j + (size_t)c * d.ldr];
+      for (int c = j + threadIdx.x; c < m; c += WG) R[j + (size_t)c * d.ldr] = -R[j + (size_t)c * d.ldr];
     }
   }
 }
 
 // ------------------------------------------------------------------- RRQR
-// Each column of the trailing matrix is handled by a group of 16 lanes (16
-// consecutive rows per access, one 128-byte line), so a workgroup has 16
-// columns in flight; dot products and norms reduce with shuffles inside the
-// group.  The matrix lives in LDS (stride n + 1) when it fits, else it is
-// streamed from global memory.  Norms are recomputed exactly every step.
-constexpr int GRP = 16;
-
-__device__ inline double grp_sum(double v) {
-  v += __shfl_xor(v, 1, WAVE);
-  v += __shfl_xor(v, 2, WAVE);
-  v += __shfl_xor(v, 4, WAVE);
-  v += __shfl_xor(v, 8, WAVE);
-  return v;
-}
-
-template <bool kLds>
+// The whole matrix is staged in LDS (stride n + 1).  Each column of the
+// trailing matrix is handled by a group of 16 lanes (16 consecutive rows per
+// access), so a workgroup has 16 columns in flight; dot products and norms
+// reduce with shuffles inside the group.  Norms are recomputed exactly every
+// step.
+template <class T>
 __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs) {
-  extern __shared__ double sh[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const RrqrDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
   const int K = min(min(n, m), d.kmax);
   if (d.A == nullptr) return;
-  double* A;
-  size_t lda;
-  double* nrm;
-  if (kLds) {
-    lda = n + 1;
-    A = sh;
-    nrm = sh + lda * m;
-    for (int e = threadIdx.x; e < n * m; e += WG) {
-      const int i = e % n, c = e / n;
-      A[i + c * lda] = d.A[i + (size_t)c * d.lda];
-    }
-  } else {
-    A = d.A;
-    lda = d.lda;
-    nrm = sh;
+  T* gA = static_cast<T*>(d.A);
+  T* gtau = static_cast<T*>(d.tau);
+  T* galpha = static_cast<T*>(d.alpha);
+  const size_t lda = n + 1;
+  T* A = reinterpret_cast<T*>(smem);
+  T* nrm = A + lda * m;
+  for (int e = threadIdx.x; e < n * m; e += WG) {
+    const int i = e % n, c = e / n;
+    A[i + c * lda] = gA[i + (size_t)c * d.lda];
   }
-  __shared__ double rv[WG / WAVE];
+  __shared__ T rv[WG / WAVE];
   __shared__ int ri[WG / WAVE];
-  __shared__ double red[WG / WAVE];
+  __shared__ T red[WG / WAVE];
   const int rl = threadIdx.x % GRP;         // row lane inside the group
   const int slot = threadIdx.x / GRP;       // 0..15: column slot of the group
   constexpr int NSLOT = WG / GRP;
   __syncthreads();
   for (int c = slot; c < m; c += NSLOT) {
-    const double* col = A + c * lda;
-    double q = 0.0;
+    const T* col = A + c * lda;
+    T q = 0;
     for (int i = rl; i < n; i += GRP) q = fma(col[i], col[i], q);
     q = grp_sum(q);
     if (rl == 0) nrm[c] = sqrt(q);
@@ -290,63 +305,61 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
   __syncthreads();
   int rank = 0;
   bool counting = true;
-  double first = 0.0;
+  T first = 0;
   for (int j = 0; j < K; ++j) {
-    double bv = -1.0;
+    T bv = -1;
     int bi = m;
     for (int c = j + threadIdx.x; c < m; c += WG)
       if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
-    double piv;
+    T piv;
     int cp;
     block_argmax(bv, bi, rv, ri, piv, cp);
     if (j == 0) first = piv;
-    if (counting && first > 0.0 && piv > d.eps * first) rank = j + 1;
+    if (counting && first > 0 && (double)piv > d.eps * (double)first) rank = j + 1;
     else counting = false;
     if (!counting && d.stop_at_rank) {  // uniform: every thread holds the same pivot
       if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; }
-      if (kLds) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * j; e += WG) {
-          const int i = e % n, c = e / n;
-          d.A[i + (size_t)c * d.lda] = A[i + c * lda];
-        }
+      __syncthreads();
+      for (int e = threadIdx.x; e < n * j; e += WG) {
+        const int i = e % n, c = e / n;
+        gA[i + (size_t)c * d.lda] = A[i + c * lda];
       }
       return;
     }
     __syncthreads();
     if (cp != j) {
       for (int i = threadIdx.x; i < n; i += WG) {
-        const double t = A[i + j * lda];
+        const T t = A[i + j * lda];
         A[i + j * lda] = A[i + cp * lda];
         A[i + cp * lda] = t;
       }
-      if (threadIdx.x == 0) { const double t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
+      if (threadIdx.x == 0) { const T t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
     }
     __syncthreads();
-    double part = 0.0;
+    T part = 0;
     for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
-    const double xn = sqrt(block_sum(part, red));
-    const double x0 = A[j + j * lda];
-    double alpha = 0.0, tau = 0.0, v0 = 1.0;
-    if (xn > 0.0) {
-      alpha = x0 >= 0.0 ? -xn : xn;
+    const T xn = sqrt(block_sum(part, red));
+    const T x0 = A[j + j * lda];
+    T alpha = 0, tau = 0, v0 = 1;
+    if (xn > 0) {
+      alpha = x0 >= 0 ? -xn : xn;
       v0 = x0 - alpha;
       tau = -v0 / alpha;
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0.0 ? A[i + j * lda] / v0 : 0.0;
-    if (threadIdx.x == 0) { d.tau[j] = tau; d.alpha[j] = alpha; A[j + j * lda] = alpha; }
+    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
+    if (threadIdx.x == 0) { gtau[j] = tau; galpha[j] = alpha; A[j + j * lda] = alpha; }
     __syncthreads();
-    const double* u = A + j * lda;
+    const T* u = A + j * lda;
     for (int c = j + 1 + slot; c < m; c += NSLOT) {
-      double* col = A + c * lda;
-      double s = 0.0;
+      T* col = A + c * lda;
+      T s = 0;
       for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
       s = grp_sum(s) + col[j];
-      const double ts = tau * s;
-      double q = 0.0;
+      const T ts = tau * s;
+      T q = 0;
       for (int i = j + 1 + rl; i < n; i += GRP) {
-        const double v = fma(-ts, u[i], col[i]);
+        const T v = fma(-ts, u[i], col[i]);
         col[i] = v;
         q = fma(v, v, q);
       }
@@ -358,11 +371,9 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
   }
-  if (kLds) {
-    for (int e = threadIdx.x; e < n * K; e += WG) {
-      const int i = e % n, c = e / n;
-      d.A[i + (size_t)c * d.lda] = A[i + c * lda];
-    }
+  for (int e = threadIdx.x; e < n * K; e += WG) {
+    const int i = e % n, c = e / n;
+    gA[i + (size_t)c * d.lda] = A[i + c * lda];
   }
   if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
 }
@@ -372,7 +383,9 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
 // step is two launches: k_rrqr_pivot (one workgroup per matrix: pivot choice,
 // column swap, reflector) and k_rrqr_update (column tiles of the trailing
 // matrix spread over many workgroups, 16-lane groups per column, exact norms).
-// Per-matrix state lives in RrqrState; same arithmetic as k_rrqr.
+// Per-matrix state lives in RrqrState (norms kept in FP64); same arithmetic
+// as k_rrqr.
+template <class T>
 __global__ __launch_bounds__(WG) void k_rrqr_init(const RrqrDesc* __restrict__ descs,
                                                   RrqrState* __restrict__ st) {
   const RrqrDesc d = descs[blockIdx.x];
@@ -380,12 +393,13 @@ __global__ __launch_bounds__(WG) void k_rrqr_init(const RrqrDesc* __restrict__ d
   RrqrState& S = st[blockIdx.x];
   const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
   constexpr int NSLOT = WG / GRP;
-  for (int c = blockIdx.y * NSLOT + slot; c < m; c += gridDim.y * NSLOT) {
-    const double* col = d.A + (size_t)c * d.lda;
-    double q = 0.0;
+  const T* A = static_cast<const T*>(d.A);
+  for (int c = blockIdx.y * NSLOT + slot; A != nullptr && c < m; c += gridDim.y * NSLOT) {
+    const T* col = A + (size_t)c * d.lda;
+    T q = 0;
     for (int i = rl; i < n; i += GRP) q = fma(col[i], col[i], q);
     q = grp_sum(q);
-    if (rl == 0) S.nrm[c] = sqrt(q);
+    if (rl == 0) S.nrm[c] = (double)sqrt(q);
   }
   if (blockIdx.y == 0 && threadIdx.x == 0) {
     S.done = d.A == nullptr ? 1 : 0;
@@ -396,6 +410,7 @@ __global__ __launch_bounds__(WG) void k_rrqr_init(const RrqrDesc* __restrict__ d
   }
 }
 
+template <class T>
 __global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ descs,
                                                    RrqrState* __restrict__ st, int j) {
   const RrqrDesc d = descs[blockIdx.x];
@@ -412,8 +427,8 @@ __global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ 
   }
   __shared__ double rv[WG / WAVE];
   __shared__ int ri[WG / WAVE];
-  __shared__ double red[WG / WAVE];
-  double* A = d.A;
+  __shared__ T red[WG / WAVE];
+  T* A = static_cast<T*>(d.A);
   const size_t lda = d.lda;
   double* nrm = S.nrm;
   double bv = -1.0;
@@ -436,28 +451,28 @@ __global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ 
   }
   if (cp != j) {
     for (int i = threadIdx.x; i < n; i += WG) {
-      const double t = A[i + j * lda];
+      const T t = A[i + j * lda];
       A[i + j * lda] = A[i + cp * lda];
       A[i + cp * lda] = t;
     }
     if (threadIdx.x == 0) { const double t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
   }
   __syncthreads();
-  double part = 0.0;
+  T part = 0;
   for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
-  const double xn = sqrt(block_sum(part, red));
-  const double x0 = A[j + j * lda];
-  double alpha = 0.0, tau = 0.0, v0 = 1.0;
-  if (xn > 0.0) {
-    alpha = x0 >= 0.0 ? -xn : xn;
+  const T xn = sqrt(block_sum(part, red));
+  const T x0 = A[j + j * lda];
+  T alpha = 0, tau = 0, v0 = 1;
+  if (xn > 0) {
+    alpha = x0 >= 0 ? -xn : xn;
     v0 = x0 - alpha;
     tau = -v0 / alpha;
   }
   __syncthreads();
-  for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0.0 ? A[i + j * lda] / v0 : 0.0;
+  for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
   if (threadIdx.x == 0) {
-    d.tau[j] = tau;
-    d.alpha[j] = alpha;
+    static_cast<T*>(d.tau)[j] = tau;
+    static_cast<T*>(d.alpha)[j] = alpha;
     A[j + j * lda] = alpha;
     // the trailing update of the last reflector is never read: skip it
     if (j + 1 == K) { *d.rank = rank; *d.steps = K; S.done = 1; S.apply = 0; }
@@ -465,63 +480,70 @@ __global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ 
   }
 }
 
+template <class T>
 __global__ __launch_bounds__(WG) void k_rrqr_update(const RrqrDesc* __restrict__ descs,
                                                     const RrqrState* __restrict__ st, int j) {
   const RrqrDesc d = descs[blockIdx.x];
   const RrqrState& S = st[blockIdx.x];
   const int n = d.n, m = d.m;
   if (!S.apply) return;  // no reflector formed at this step
-  const double tau = d.tau[j];
-  const double* u = d.A + (size_t)j * d.lda;
+  T* A = static_cast<T*>(d.A);
+  const T tau = static_cast<const T*>(d.tau)[j];
+  const T* u = A + (size_t)j * d.lda;
   const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
   constexpr int NSLOT = WG / GRP;
   for (int c = j + 1 + blockIdx.y * NSLOT + slot; c < m; c += gridDim.y * NSLOT) {
-    double* col = d.A + (size_t)c * d.lda;
-    double s = 0.0;
+    T* col = A + (size_t)c * d.lda;
+    T s = 0;
     for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
     s = grp_sum(s) + col[j];
-    const double ts = tau * s;
-    double q = 0.0;
+    const T ts = tau * s;
+    T q = 0;
     for (int i = j + 1 + rl; i < n; i += GRP) {
-      const double v = fma(-ts, u[i], col[i]);
+      const T v = fma(-ts, u[i], col[i]);
       col[i] = v;
       q = fma(v, v, q);
     }
     q = grp_sum(q);
     if (rl == 0) {
       col[j] -= ts;
-      S.nrm[c] = sqrt(q);
+      S.nrm[c] = (double)sqrt(q);
     }
   }
 }
 
 // ------------------------------------------------------------------ FORMQ
+template <class T>
 __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ descs) {
   const FormQDesc d = descs[blockIdx.x];
   if (d.Q == nullptr || d.r == 0) return;
   const int n = d.n, r = d.r;
   const size_t lda = d.lda, ldq = d.ldq;
+  const T* A = static_cast<const T*>(d.A);
+  const T* tauv = static_cast<const T*>(d.tau);
+  const T* alphav = static_cast<const T*>(d.alpha);
+  T* Q = static_cast<T*>(d.Q);
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
   for (int e = threadIdx.x; e < n * r; e += WG) {
     const int i = e % n, j = e / n;
-    d.Q[i + j * ldq] = i == j ? 1.0 : 0.0;
+    Q[i + j * ldq] = i == j ? T(1) : T(0);
   }
   __syncthreads();
   for (int j = d.kk - 1; j >= 0; --j) {
-    const double tau = d.tau[j];
+    const T tau = tauv[j];
     for (int c = j + w; c < r; c += nw) {
-      double s = 0.0;
-      for (int i = j + 1 + lane; i < n; i += WAVE) s += d.A[i + j * lda] * d.Q[i + c * ldq];
-      s = wave_sum(s) + d.Q[j + c * ldq];
-      const double ts = tau * s;
-      for (int i = j + 1 + lane; i < n; i += WAVE) d.Q[i + c * ldq] -= ts * d.A[i + j * lda];
-      if (lane == 0) d.Q[j + c * ldq] -= ts;
+      T s = 0;
+      for (int i = j + 1 + lane; i < n; i += WAVE) s += A[i + j * lda] * Q[i + c * ldq];
+      s = wave_sum(s) + Q[j + c * ldq];
+      const T ts = tau * s;
+      for (int i = j + 1 + lane; i < n; i += WAVE) Q[i + c * ldq] -= ts * A[i + j * lda];
+      if (lane == 0) Q[j + c * ldq] -= ts;
     }
     __syncthreads();
   }
   for (int j = 0; j < d.kk && j < r; ++j)
-    if (d.alpha[j] < 0.0)
-      for (int i = threadIdx.x; i < n; i += WG) d.Q[i + j * ldq] = -d.Q[i + j * ldq];
+    if (alphav[j] < 0)
+      for (int i = threadIdx.x; i < n; i += WG) Q[i + j * ldq] = -Q[i + j * ldq];
 }
 
 // --------------------------------------------------------------- STACK QR
@@ -530,50 +552,52 @@ __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ desc
 // only touches row j of R and the chunk rows.  Each trailing column is handled
 // by a 16-lane group (lanes over chunk rows, shuffle reductions), every group
 // forms the reflector of column j itself, so a step costs one barrier.
+template <class T>
 __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
                                                 const BlkRef* __restrict__ blocks, int chunk) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const StackQrDesc d = descs[blockIdx.x];
   const int r = d.r;
   if (d.R == nullptr || r == 0) return;
   const int ldc = chunk + 1;
-  double* R = lds;                 // r x r, ld r
-  double* C = lds + r * r;         // chunk x r, ld chunk + 1
+  T* R = reinterpret_cast<T*>(smem);  // r x r, ld r
+  T* C = R + r * r;                    // chunk x r, ld chunk + 1
   const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
   constexpr int NSLOT = WG / GRP;
-  for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0.0;
+  for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0;
   __syncthreads();
   for (int b = 0; b < d.nblk; ++b) {
     const BlkRef B = blocks[d.first + b];
+    const T* Bp = static_cast<const T*>(B.p);
     for (int r0 = 0; r0 < B.rows; r0 += chunk) {
       const int cr = min(chunk, B.rows - r0);
       for (int e = threadIdx.x; e < cr * r; e += WG) {
         int i, j;
         if (B.trans) { j = e % r; i = e / r; } else { i = e % cr; j = e / cr; }
         const int gi = r0 + i;
-        C[i + j * ldc] = B.trans ? B.p[j + (size_t)gi * B.ld] : B.p[gi + (size_t)j * B.ld];
+        C[i + j * ldc] = B.trans ? Bp[j + (size_t)gi * B.ld] : Bp[gi + (size_t)j * B.ld];
       }
       __syncthreads();
       for (int j = 0; j < r; ++j) {
-        const double* cj = C + j * ldc;
-        double s2 = 0.0;
+        const T* cj = C + j * ldc;
+        T s2 = 0;
         for (int i = rl; i < cr; i += GRP) s2 = fma(cj[i], cj[i], s2);
         s2 = grp_sum(s2);
-        const double rjj = R[j + j * r];
-        const double nrm = sqrt(rjj * rjj + s2);
-        if (s2 == 0.0 || nrm == 0.0) continue;  // nothing below the diagonal: H = I
+        const T rjj = R[j + j * r];
+        const T nrm = sqrt(rjj * rjj + s2);
+        if (s2 == 0 || nrm == 0) continue;  // nothing below the diagonal: H = I
         // H = I - tau u u^T with u = [1; C_j / v0], tau = -v0 / alpha in [1, 2]:
         // no product of two small quantities is formed, so repeated stacking of
         // nearly annihilated columns cannot overflow the scale.
-        const double alpha = rjj >= 0.0 ? -nrm : nrm;
-        const double v0 = rjj - alpha;
-        const double tau = -v0 / alpha;
-        const double iv0 = 1.0 / v0;
+        const T alpha = rjj >= 0 ? -nrm : nrm;
+        const T v0 = rjj - alpha;
+        const T tau = -v0 / alpha;
+        const T iv0 = T(1) / v0;
         for (int c = j + 1 + slot; c < r; c += NSLOT) {
-          double* cc = C + c * ldc;
-          double sc = 0.0;
+          T* cc = C + c * ldc;
+          T sc = 0;
           for (int i = rl; i < cr; i += GRP) sc = fma(cj[i] * iv0, cc[i], sc);
-          const double rjc = R[j + c * r];
+          const T rjc = R[j + c * r];
           sc = tau * (grp_sum(sc) + rjc);
           for (int i = rl; i < cr; i += GRP) cc[i] = fma(-sc, cj[i] * iv0, cc[i]);
           if (rl == 0) R[j + c * r] = rjc - sc;
@@ -584,77 +608,12 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
       __syncthreads();
     }
   }
+  T* Rout = static_cast<T*>(d.R);
   for (int e = threadIdx.x; e < r * r; e += WG) {
     const int i = e % r, j = e / r;
-    double v = j < i ? 0.0 : R[i + j * r];
-    if (R[i + i * r] < 0.0) v = -v;
-    d.R[i + (size_t)j * d.ldr] = v;
-  }
-}
-
-// ---------------------------------------------------------------- INVERSE
-// Gauss-Jordan with partial pivoting (first largest |a| wins ties), in place.
-__global__ __launch_bounds__(WG) void k_inverse(const InvDesc* __restrict__ descs, Status* st) {
-  extern __shared__ double sh[];  // f[m], row[m]
-  const InvDesc d = descs[blockIdx.x];
-  const int m = d.m;
-  if (d.A == nullptr || m == 0) return;
-  double* A = d.A;
-  const size_t lda = d.lda;
-  double* f = sh;
-  double* rowj = sh + m;
-  int* piv = reinterpret_cast<int*>(sh + 2 * m);
-  __shared__ double rv[WG / WAVE];
-  __shared__ int ri[WG / WAVE];
-  bool bad = false;
-  for (int j = 0; j < m; ++j) {
-    double bv = -1.0;
-    int bi = m;
-    for (int i = j + threadIdx.x; i < m; i += WG) {
-      const double a = fabs(A[i + j * lda]);
-      if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
-    }
-    double pv;
-    int p;
-    block_argmax(bv, bi, rv, ri, pv, p);
-    if (threadIdx.x == 0) piv[j] = p;
-    if (p != j)
-      for (int c = threadIdx.x; c < m; c += WG) {
-        const double t = A[j + c * lda];
-        A[j + c * lda] = A[p + c * lda];
-        A[p + c * lda] = t;
-      }
-    __syncthreads();
-    const double djj = A[j + j * lda];
-    if (djj == 0.0) bad = true;
-    const double inv = 1.0 / djj;
-    for (int i = threadIdx.x; i < m; i += WG) f[i] = A[i + j * lda];
-    for (int c = threadIdx.x; c < m; c += WG) rowj[c] = c == j ? inv : A[j + c * lda] * inv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += WG) {
-      const int i = e % m, c = e / m;
-      if (i == j) {
-        A[i + c * lda] = rowj[c];
-      } else if (c == j) {
-        A[i + c * lda] = -f[i] * inv;
-      } else {
-        A[i + c * lda] -= f[i] * rowj[c];
-      }
-    }
-    __syncthreads();
-  }
-  for (int j = m - 1; j >= 0; --j) {
-    const int p = piv[j];
-    if (p != j)
-      for (int i = threadIdx.x; i < m; i += WG) {
-        const double t = A[i + j * lda];
-        A[i + j * lda] = A[i + p * lda];
-        A[i + p * lda] = t;
-      }
-    __syncthreads();
-  }
-  if (bad && threadIdx.x == 0 && st) {
-    if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
+    T v = j < i ? T(0) : R[i + j * r];
+    if (R[i + i * r] < 0) v = -v;
+    Rout[i + (size_t)j * d.ldr] = v;
   }
 }
 
@@ -669,7 +628,8 @@ __global__ __launch_bounds__(WG) void k_inverse(const InvDesc* __restrict__ desc
 template <bool kLds>
 __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ descs, int j0, int nb,
                                                  int* __restrict__ piv_all, int ldp, Status* st) {
-  extern __shared__ double f[];  // m entries (+ the m x nb panel when kLds)
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* f = reinterpret_cast<double*>(smem);  // m entries (+ the m x nb panel when kLds)
   const InvDesc d = descs[blockIdx.x];
   const int m = d.m;
   if (d.A == nullptr || j0 >= m) return;
@@ -800,68 +760,36 @@ __global__ __launch_bounds__(WG) void k_gj_unpermute(const InvDesc* __restrict__
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-}  // namespace
-
-void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, hipStream_t s) {
-  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
-  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
-  hipLaunchKernelGGL(k_gemm, dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
+template <class TA, class TB, class TC>
+void gemm_go(const GemmDesc* d, int nd, int tm, int tn, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
 }
 
-void launch_add(const AddDesc* d, int nd, int max_m, int max_n, hipStream_t s) {
-  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
-  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
-  hipLaunchKernelGGL(k_add, dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
+template <class TA, class TC>
+void add_go(const AddDesc* d, int nd, int tm, int tn, hipStream_t s) {
+  hipLaunchKernelGGL((k_add<TA, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
 }
 
-void launch_xform(const XformDesc* d, int nd, double* scratch, int nwg, int ld_scratch,
-                  hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL(k_xform, dim3(nd < nwg ? nd : nwg), dim3(WG), 0, s, d, nd, scratch,
-                     ld_scratch);
-}
-
-void launch_qr(const QrDesc* d, int nd, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL(k_qr, dim3(nd), dim3(WG), 0, s, d);
-}
-
-void launch_rrqr(const RrqrDesc* d, int nd, int max_m, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL(k_rrqr<false>, dim3(nd), dim3(WG), sizeof(double) * (max_m > 0 ? max_m : 1), s, d);
-}
-
-void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, hipStream_t s) {
-  if (nd <= 0) return;
-  static bool raised = false;
-  if (!raised) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_rrqr<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRrqrLdsBytes);
-    raised = true;
-  }
-  hipLaunchKernelGGL(k_rrqr<true>, dim3(nd), dim3(WG), lds, s, d);
-}
-
-void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st,
-                       hipStream_t s) {
-  if (nd <= 0) return;
-  const int tiles = cdiv(max_m, 4 * (WG / GRP));  // ~64 columns per workgroup
-  hipLaunchKernelGGL(k_rrqr_init, dim3(nd, tiles), dim3(WG), 0, s, d, st);
+template <class T>
+void rrqr_multi_go(const RrqrDesc* d, int nd, int tiles, int max_k, RrqrState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_rrqr_init<T>, dim3(nd, tiles), dim3(WG), 0, s, d, st);
   for (int j = 0; j < max_k; ++j) {
-    hipLaunchKernelGGL(k_rrqr_pivot, dim3(nd), dim3(WG), 0, s, d, st, j);
-    hipLaunchKernelGGL(k_rrqr_update, dim3(nd, tiles), dim3(WG), 0, s, d, st, j);
+    hipLaunchKernelGGL(k_rrqr_pivot<T>, dim3(nd), dim3(WG), 0, s, d, st, j);
+    hipLaunchKernelGGL(k_rrqr_update<T>, dim3(nd, tiles), dim3(WG), 0, s, d, st, j);
   }
 }
 
-void launch_formq(const FormQDesc* d, int nd, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL(k_formq, dim3(nd), dim3(WG), 0, s, d);
+// Raise the dynamic LDS limit of a kernel once (gfx950: 160 KiB per CU).
+void allow_lds(const void* fn, bool& done, size_t bytes) {
+  if (done) return;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  done = true;
 }
 
-void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
-  if (nd <= 0 || max_r <= 0) return;
-  const size_t rr = (size_t)max_r * max_r * sizeof(double);
-  const size_t row = sizeof(double) * max_r;
+template <class T>
+void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
+  const size_t rr = (size_t)max_r * max_r * sizeof(T);
+  const size_t row = sizeof(T) * max_r;
   // stay within 64 KiB when a 16-row chunk fits, else use up to 150 KiB of
   // the 160 KiB LDS of a gfx950 CU
   const size_t budget = rr + 16 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
@@ -872,13 +800,84 @@ void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hi
   const size_t lds = rr + (size_t)(chunk + 1) * row;
   if (lds > 64 * 1024) {
     static bool raised = false;
-    if (!raised) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_stackqr),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-      raised = true;
-    }
+    allow_lds(reinterpret_cast<const void*>(k_stackqr<T>), raised, 150 * 1024);
   }
-  hipLaunchKernelGGL(k_stackqr, dim3(nd), dim3(WG), lds, s, d, b, chunk);
+  hipLaunchKernelGGL(k_stackqr<T>, dim3(nd), dim3(WG), lds, s, d, b, chunk);
+}
+
+}  // namespace
+
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  switch (ty) {
+    case 0: gemm_go<double, double, double>(d, nd, tm, tn, s); break;
+    case 1: gemm_go<float, double, double>(d, nd, tm, tn, s); break;
+    case 2: gemm_go<double, float, double>(d, nd, tm, tn, s); break;
+    case 3: gemm_go<float, float, double>(d, nd, tm, tn, s); break;
+    case 4: gemm_go<double, double, float>(d, nd, tm, tn, s); break;
+    case 5: gemm_go<float, double, float>(d, nd, tm, tn, s); break;
+    case 6: gemm_go<double, float, float>(d, nd, tm, tn, s); break;
+    default: gemm_go<float, float, float>(d, nd, tm, tn, s); break;
+  }
+}
+
+void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  switch (ty) {
+    case 0: add_go<double, double>(d, nd, tm, tn, s); break;
+    case 1: add_go<float, double>(d, nd, tm, tn, s); break;
+    case 2: add_go<double, float>(d, nd, tm, tn, s); break;
+    default: add_go<float, float>(d, nd, tm, tn, s); break;
+  }
+}
+
+void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
+                  hipStream_t s) {
+  if (nd <= 0) return;
+  const dim3 grid(nd < nwg ? nd : nwg);
+  if (ty) hipLaunchKernelGGL(k_xform<float>, grid, dim3(WG), 0, s, d, nd, static_cast<float*>(scratch), ld_scratch);
+  else hipLaunchKernelGGL(k_xform<double>, grid, dim3(WG), 0, s, d, nd, static_cast<double*>(scratch), ld_scratch);
+}
+
+void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s) {
+  if (nd <= 0) return;
+  if (ty) hipLaunchKernelGGL(k_qr<float>, dim3(nd), dim3(WG), 0, s, d);
+  else hipLaunchKernelGGL(k_qr<double>, dim3(nd), dim3(WG), 0, s, d);
+}
+
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s) {
+  if (nd <= 0) return;
+  if (ty) {
+    static bool raised = false;
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<float>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL(k_rrqr<float>, dim3(nd), dim3(WG), lds, s, d);
+  } else {
+    static bool raised = false;
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<double>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL(k_rrqr<double>, dim3(nd), dim3(WG), lds, s, d);
+  }
+}
+
+void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st, int ty,
+                       hipStream_t s) {
+  if (nd <= 0) return;
+  const int tiles = cdiv(max_m, 4 * (WG / GRP));  // ~64 columns per workgroup
+  if (ty) rrqr_multi_go<float>(d, nd, tiles, max_k, st, s);
+  else rrqr_multi_go<double>(d, nd, tiles, max_k, st, s);
+}
+
+void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s) {
+  if (nd <= 0) return;
+  if (ty) hipLaunchKernelGGL(k_formq<float>, dim3(nd), dim3(WG), 0, s, d);
+  else hipLaunchKernelGGL(k_formq<double>, dim3(nd), dim3(WG), 0, s, d);
+}
+
+void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s) {
+  if (nd <= 0 || max_r <= 0) return;
+  if (ty) stackqr_go<float>(d, b, nd, max_r, s);
+  else stackqr_go<double>(d, b, nd, max_r, s);
 }
 
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
@@ -887,11 +886,7 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
   const size_t lds = sizeof(double) * (size_t)max_m * (nb + 1);
   if (lds <= 150 * 1024) {
     static bool raised = false;
-    if (!raised && lds > 64 * 1024) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-      raised = true;
-    }
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gj_panel<true>), raised, 150 * 1024);
     hipLaunchKernelGGL(k_gj_panel<true>, dim3(nd), dim3(WG), lds, s, d, j0, nb, piv, ldp, st);
   } else {
     hipLaunchKernelGGL(k_gj_panel<false>, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv,
@@ -908,12 +903,6 @@ void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const i
 void launch_gj_unpermute(const InvDesc* d, int nd, int max_m, const int* piv, int ldp, hipStream_t s) {
   if (nd <= 0) return;
   hipLaunchKernelGGL(k_gj_unpermute, dim3(nd, cdiv(max_m, WG)), dim3(WG), 0, s, d, piv, ldp);
-}
-
-void launch_inverse(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
-  if (nd <= 0 || max_m <= 0) return;
-  const size_t lds = sizeof(double) * 2 * max_m + sizeof(int) * max_m;
-  hipLaunchKernelGGL(k_inverse, dim3(nd), dim3(WG), lds, s, d, st);
 }
 
 }  // namespace ifmm

@@ -33,7 +33,8 @@ class _Kernel(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("r_max", C.c_int), ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
-                ("box_lo", C.c_double * 2), ("box_size", C.c_double), ("profile", C.c_int)]
+                ("box_lo", C.c_double * 2), ("box_size", C.c_double), ("profile", C.c_int),
+                ("precision", C.c_int)]
 
 
 class _SolveInfo(C.Structure):
@@ -46,12 +47,13 @@ class _Stats(C.Structure):
                 ("level_max_rank", C.c_int * 16), ("level_mean_rank", C.c_double * 16),
                 ("top_size", C.c_int), ("assembly_ms", C.c_double), ("factor_ms", C.c_double),
                 ("last_solve_ms", C.c_double), ("factor_bytes", C.c_double),
-                ("factor_flops", C.c_double), ("kernel_launches", C.c_int64 * 8),
-                ("kernel_ms", C.c_double * 8), ("kernel_flops", C.c_double * 8),
-                ("kernel_bytes", C.c_double * 8)]
+                ("factor_flops", C.c_double), ("kernel_launches", C.c_int64 * 16),
+                ("kernel_ms", C.c_double * 16), ("kernel_flops", C.c_double * 16),
+                ("kernel_bytes", C.c_double * 16), ("precision", C.c_int)]
 
 
 KERNEL_FAMILIES = ["gemm", "add", "xform", "qr", "rrqr", "formq", "stackqr", "inverse"]
+PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
 _LIBS: dict = {}
@@ -98,13 +100,17 @@ class IFMMSolver:
     """ifmm_factor(points, kernel, eps, leaf_size, rank) / ifmm_solve(b).
 
     points: torch float64 tensor [N, 2] on the GPU.  b for ``solve`` is [N]
-    or [N, nrhs] on the same device.
+    or [N, nrhs] on the same device.  precision "fp32" stores the factor's
+    blocks in FP32 (the mixed-precision factor; pivot inverses, the FMM
+    product, residuals and vectors stay FP64 and refinement recovers FP64
+    accuracy).
     """
 
     def __init__(self, points, kernel: str = "inv_r", ell: float = 0.0, diag: str = "rowsum",
                  c0: float = 1.0, eps: float = 1e-8, leaf_size: int = 64, rank: int = 36,
                  r_max: int = 0, refine_tol: float = 0.0, refine_maxit: int = 30,
-                 box=None, profile: bool = False, lib_path: str | None = None):
+                 box=None, profile: bool = False, precision: str = "fp64",
+                 lib_path: str | None = None):
         import torch
         self._lib = load(lib_path)
         if lib_path is None and not points.is_cuda:
@@ -118,6 +124,7 @@ class IFMMSolver:
         o.refine_tol = float(refine_tol)
         o.refine_maxit = int(refine_maxit)
         o.profile = 1 if profile else 0
+        o.precision = PRECISIONS[precision]
         if box is not None:
             o.box_lo[0], o.box_lo[1], o.box_size = float(box[0]), float(box[1]), float(box[2])
         h = C.c_void_p()
@@ -180,9 +187,13 @@ class IFMMSolver:
                 "top_size": s.top_size, "assembly_ms": s.assembly_ms, "factor_ms": s.factor_ms,
                 "last_solve_ms": s.last_solve_ms, "factor_bytes": s.factor_bytes,
                 "factor_flops": s.factor_flops,
-                "kernels": {name: {"launches": s.kernel_launches[i], "ms": s.kernel_ms[i],
-                                   "flops": s.kernel_flops[i], "bytes": s.kernel_bytes[i]}
-                            for i, name in enumerate(KERNEL_FAMILIES)}}
+                "precision": {v: k for k, v in PRECISIONS.items()}.get(s.precision, s.precision),
+                # "<family>" computes in FP64, "<family>_f32" in FP32
+                "kernels": {name + ("_f32" if q else ""):
+                            {"launches": s.kernel_launches[i + 8 * q], "ms": s.kernel_ms[i + 8 * q],
+                             "flops": s.kernel_flops[i + 8 * q], "bytes": s.kernel_bytes[i + 8 * q]}
+                            for q in (0, 1) for i, name in enumerate(KERNEL_FAMILIES)
+                            if q == 0 or s.kernel_launches[i + 8 * q] > 0}}
 
     def ranks(self, level: int) -> np.ndarray:
         out = (C.c_int * (4 ** level))()
