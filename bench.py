@@ -122,8 +122,9 @@ def run(prec, pts, b, steps, warmup, N):
     recs = []
     for k in range(steps):
         recs.append(step())
-        print(f"{prec} step {k}: t_f {recs[-1][0]['factor_ms']:.0f} ms  wall {recs[-1][0]['wall_ms']}",
-              file=sys.stderr, flush=True)
+        free_gb = torch.cuda.mem_get_info()[0] / 2**30
+        print(f"{prec} step {k}: t_a {recs[-1][0]['assembly_ms']:.0f} ms  t_f {recs[-1][0]['factor_ms']:.0f} ms  "
+              f"wall {recs[-1][0]['wall_ms']}  free {free_gb:.0f} GiB", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     fam = {}

@@ -162,7 +162,14 @@ ifmm_status ifmm_stats(ifmm_t h, ifmm_stats_t* s);
 /* Final rank of every cluster of `level` (Morton order) into host out[4^level]. */
 ifmm_status ifmm_ranks(ifmm_t h, int level, int* out, int count);
 
+/* Frees the handle and every device buffer it holds.  The buffers go to a
+ * process-wide cache that later ifmm_factor calls reuse (a block serves a
+ * request of at least 4/5 of its size; at most 60% of the device memory stays
+ * cached; a failed device allocation frees the cache and retries). */
 void ifmm_destroy(ifmm_t h);
+
+/* Returns the cached device memory of every device to the HIP runtime. */
+void ifmm_release_cached_memory(void);
 const char* ifmm_status_string(ifmm_status s);
 
 #ifdef __cplusplus

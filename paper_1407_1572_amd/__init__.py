@@ -1,6 +1,7 @@
-"""MI355X (gfx950) Inverse Fast Multipole Method: FP64 factor + solve.
+"""MI355X (gfx950) Inverse Fast Multipole Method: factor + solve, FP64 or
+mixed precision (FP32 factor, FP64 refinement).
 
 The numerical work runs in ``libifmm.so`` (HIP kernels + C-ABI, see
 include/ifmm.h); ``IFMMSolver`` is the Python face of that ABI.
 """
-from .ifmm import IFMMError, IFMMSolver, LIB_PATH, load  # noqa: F401
+from .ifmm import IFMMError, IFMMSolver, LIB_PATH, load, release_cached_memory  # noqa: F401

@@ -18,7 +18,9 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -41,19 +43,116 @@ struct BadArg {};
     if (e_ != hipSuccess) throw HipError{e_};          \
   } while (0)
 
+// Process-wide cache of device blocks.  A factorisation holds tens of GB in
+// a few hundred large blocks; a destroyed handle returns them here and the
+// next factorisation (typically the same problem sizes again: refactoring
+// with new hyperparameters, repeated solves in a loop) reuses them instead of
+// going back to hipMalloc / hipFree for every block.  A release waits for the
+// device like hipFree does, so a cached block is never reused while a kernel
+// still reads it.  A block is reused for a request of at least 4/5 of its
+// size; when hipMalloc fails the device's cache is freed and the allocation
+// retried; at most kPoolCapFrac of the device memory stays cached.
+class DevicePool {
+ public:
+  void* get(size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      size_t best = SIZE_MAX;
+      size_t bi = 0;
+      for (size_t i = 0; i < free_.size(); ++i) {
+        const Blk& b = free_[i];
+        if (b.dev == dev && b.bytes >= bytes && b.bytes - bytes <= b.bytes / 5 && b.bytes < best) {
+          best = b.bytes;
+          bi = i;
+        }
+      }
+      if (best != SIZE_MAX) {
+        Blk b = free_[bi];
+        free_[bi] = free_.back();
+        free_.pop_back();
+        cached_[dev] -= b.bytes;
+        live_[b.p] = b;
+        return b.p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(dev);
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw NoMem{};
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    live_[p] = Blk{p, bytes, dev};
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    const Blk b = it->second;
+    live_.erase(it);
+    if (cap_[b.dev] == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) (void)hipGetLastError();
+      cap_[b.dev] = (size_t)(kPoolCapFrac * (double)tot) + 1;
+    }
+    if (cached_[b.dev] + b.bytes > cap_[b.dev]) {
+      (void)hipFree(b.p);
+      return;
+    }
+    free_.push_back(b);
+    cached_[b.dev] += b.bytes;
+  }
+  // Frees the cached blocks of device dev (all devices when dev < 0).
+  void trim(int dev) {
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> g(mu_);
+    std::vector<Blk> keep;
+    for (const Blk& b : free_) {
+      if (dev < 0 || b.dev == dev) {
+        (void)hipFree(b.p);
+        cached_[b.dev] -= b.bytes;
+      } else {
+        keep.push_back(b);
+      }
+    }
+    free_.swap(keep);
+  }
+
+ private:
+  static constexpr double kPoolCapFrac = 0.6;
+  struct Blk {
+    void* p;
+    size_t bytes;
+    int dev;
+  };
+  std::mutex mu_;
+  std::vector<Blk> free_;
+  std::unordered_map<void*, Blk> live_;
+  std::unordered_map<int, size_t> cached_, cap_;
+};
+
+// Never destroyed: handles may be released after static destructors ran.
+DevicePool& pool() {
+  static DevicePool* p = new DevicePool();
+  return *p;
+}
+
 template <class T>
 T* dalloc(size_t n) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw NoMem{};
-  }
-  return static_cast<T*>(p);
+  return static_cast<T*>(pool().get(std::max<size_t>(n, 1) * sizeof(T)));
 }
 template <class T>
 void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) pool().put(p);
   p = nullptr;
 }
 
@@ -313,7 +412,7 @@ struct Arena {
   void release() {
     for (int i = 0; i < 2; ++i) {
       if (h[i]) (void)hipHostFree(h[i]);
-      if (d[i]) (void)hipFree(d[i]);
+      dfree(d[i]);
       if (ev[i]) (void)hipEventDestroy(ev[i]);
       h[i] = d[i] = nullptr;
       ev[i] = nullptr;
@@ -325,7 +424,7 @@ struct Arena {
     if (need > cap[cur]) {
       HIP_OK(hipStreamSynchronize(s));
       if (h[cur]) (void)hipHostFree(h[cur]);
-      if (d[cur]) (void)hipFree(d[cur]);
+      dfree(d[cur]);
       h[cur] = nullptr;
       d[cur] = nullptr;
       size_t c = std::max(need, 2 * cap[cur]);
@@ -1165,7 +1264,7 @@ struct Plan final : ifmm_plan {
     T* tauA = A + per * chunk;
     if (rank_cap < (size_t)2 * nt) {
       HIP_OK(hipStreamSynchronize(s));
-      if (d_rank) (void)hipFree(d_rank);
+      dfree(d_rank);
       rank_cap = (size_t)2 * nt;
       d_rank = dalloc<int>(rank_cap);
     }
@@ -1699,8 +1798,7 @@ struct Plan final : ifmm_plan {
     dfree(d_E);
     dfree(d_top);
     dfree(d_status);
-    if (d_rank) (void)hipFree(d_rank);
-    d_rank = nullptr;
+    dfree(d_rank);
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
                    &wsNrm, &wsSeg})
       b->release();
@@ -1839,6 +1937,8 @@ void ifmm_destroy(ifmm_t h) {
   h->release();
   delete h;
 }
+
+void ifmm_release_cached_memory(void) { pool().trim(-1); }
 
 const char* ifmm_status_string(ifmm_status s) {
   switch (s) {

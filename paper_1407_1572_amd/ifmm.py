@@ -83,10 +83,17 @@ def load(path: str | None = None):
     lib.ifmm_ranks.restype = C.c_int
     lib.ifmm_destroy.argtypes = [P]
     lib.ifmm_destroy.restype = None
+    lib.ifmm_release_cached_memory.argtypes = []
+    lib.ifmm_release_cached_memory.restype = None
     lib.ifmm_status_string.argtypes = [C.c_int]
     lib.ifmm_status_string.restype = C.c_char_p
     _LIBS[path] = lib
     return lib
+
+
+def release_cached_memory(lib_path: str | None = None):
+    """Return the device blocks cached by destroyed factors to the runtime."""
+    load(lib_path).ifmm_release_cached_memory()
 
 
 def _stream_handle(t):
