@@ -164,9 +164,10 @@ constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
 constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
-enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM };
+enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
+              OP_TXFORM };
 constexpr int kOpTypes = 8;  // profile families; the three blocked-inverse pieces count as 7
-inline int family(int t) { return t >= OP_GJPANEL ? 7 : t; }
+inline int family(int t) { return t == OP_TXFORM ? (int)OP_XFORM : t >= OP_GJPANEL ? 7 : t; }
 struct Op {
   OpType t;
   size_t off, off2;
@@ -323,6 +324,52 @@ struct Stage {
       flops += f;
       op({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
     });
+  }
+  // Touched-cluster basis change (geometry on the device).  The int arrays
+  // travel in the blob; the pointer fields of the stored TouchXform hold
+  // their blob offsets + 1 (0 = null) and are rebased at launch.  flops and
+  // bytes are the exact algorithmic counts, from the host's rank tables.
+  template <class T>
+  void touch_xform(TouchXform a, const std::vector<int>* touch_q, const std::vector<int>* tidx,
+                   const std::vector<int>& r_old, const std::vector<int>& r_new, const std::vector<int>* r_par,
+                   int ncl) {
+    if (a.nt <= 0) return;
+    auto arr = [&](const std::vector<int>* v) -> const int* {
+      if (!v) return nullptr;
+      return reinterpret_cast<const int*>(push(v->data(), std::max<size_t>(1, v->size()) * sizeof(int)) + 1);
+    };
+    a.touch_q = arr(touch_q);
+    a.tidx = arr(tidx);
+    a.r_old = arr(&r_old);
+    a.r_new = arr(&r_new);
+    a.r_par = arr(r_par);
+    double f = 0, by = 0;
+    const double es = sizeof(T);
+    auto blk = [&](int ro, int co, int rn, int cn, bool hasT, bool hasS) {
+      const int rz = hasT ? rn : ro;
+      f += 2.0 * (hasT ? (double)rn * ro * co : 0) + 2.0 * (hasS ? (double)rz * co * cn : 0);
+      by += es * ((double)ro * co + (hasT ? (double)rn * ro : 0) + (hasS ? (double)co * cn : 0) +
+                  (double)rz * (hasS ? cn : co));
+    };
+    for (int t = 0; t < a.nt; ++t) {
+      const int q = touch_q ? (*touch_q)[t] : t;
+      const int rq = r_old[q], rn = r_new[t];
+      if (rq == 0) continue;
+      if (a.UP && r_par && (*r_par)[q >> 2] > 0) blk(rq, (*r_par)[q >> 2], rn, 0, true, false);
+      const int qx = demorton_x(q), qy = demorton_y(q);
+      for (int sl = 0; sl < 36; ++sl) {
+        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+        if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+        const int l = morton2(jx, jy);
+        if (l >= ncl || r_old[l] == 0) continue;
+        const int tl = tidx ? (*tidx)[l] : l;
+        blk(rq, r_old[l], rn, tl >= 0 ? r_new[tl] : r_old[l], true, tl >= 0);
+        if (tl < 0 && a.col_blocks) blk(r_old[l], rq, r_old[l], rn, false, true);
+      }
+    }
+    flops += f;
+    op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
   }
   // All blocks of a stack have the type of its R.
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
@@ -699,6 +746,20 @@ struct Plan final : ifmm_plan {
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
                          op.count, op.a, op.ty, s);
           break;
+        case OP_TXFORM: {
+          TouchXform a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          auto rebase = [&](const int*& p) {
+            if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
+          };
+          rebase(a.touch_q);
+          rebase(a.tidx);
+          rebase(a.r_old);
+          rebase(a.r_new);
+          rebase(a.r_par);
+          launch_touch_xform(a, op.ty, s);
+          break;
+        }
         case OP_GJPANEL:
           launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
@@ -1320,31 +1381,20 @@ struct Plan final : ifmm_plan {
                    rpad, 1, 0, 1.0, 0.0});
     }
     st.gemm(g);
-    auto Tm = [&](int t) { return Tt + (size_t)t * rpad * rpad; };
-    std::vector<XformDesc> xf;
-    for (int t = 0; t < nt; ++t) {
-      const int q = touch[t].q;
-      const int qx = demorton_x(q), qy = demorton_y(q);
-      for (int sl = 0; sl < 36; ++sl) {
-        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
-        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
-        const int l = morton2(jx, jy);
-        if (L.r[l] == 0) continue;
-        const int tl = tidx[l];
-        // row block (q, l): T_q M T_l^T
-        xf.push_back({L.Mb(q, sl), Tm(t), tl >= 0 ? Tm(tl) : nullptr, L.r[q], L.r[l], rnew[t],
-                      tl >= 0 ? rnew[tl] : L.r[l], rpad, rpad, rpad, 1});
-        // column block (l, q) when l is not itself touched
-        if (tl < 0)
-          xf.push_back({L.Mb(l, slot36(l, q)), nullptr, Tm(t), L.r[l], L.r[q], L.r[l], rnew[t], rpad, rpad, rpad, 1});
-      }
-      if (k > 2 && lv[k - 1].r[q >> 2] > 0) {
-        const int rP = lv[k - 1].r[q >> 2];
-        xf.push_back({L.UPb(q), Tm(t), nullptr, L.r[q], rP, rnew[t], rP, rpad, rpad, rpad, 0});
-      }
+    {
+      TouchXform a{};
+      a.M = L.M;
+      a.UP = k > 2 ? L.UP : nullptr;
+      a.Tm = Tt;
+      a.nt = nt;
+      a.nside = L.nside;
+      a.rpad = rpad;
+      a.col_blocks = 1;
+      a.sM = L.sM;
+      std::vector<int> tq(nt);
+      for (int t = 0; t < nt; ++t) tq[t] = touch[t].q;
+      st.touch_xform<T>(a, &tq, &tidx, L.r, rnew, k > 2 ? &lv[k - 1].r : nullptr, L.nc);
     }
-    st.xform(xf);
     std::vector<AddDesc> cp;
     for (int t = 0; t < nt; ++t) {
       const int q = touch[t].q, nq = L.n[q];
@@ -1441,24 +1491,18 @@ struct Plan final : ifmm_plan {
       L.r[P] = std::min(L.n[P], rold[P]);
     }
     st.qr(q);
-    std::vector<XformDesc> xf;
-    for (int P = 0; P < L.nc; ++P) {
-      if (rold[P] == 0) continue;
-      const int px = demorton_x(P), py = demorton_y(P);
-      for (int sl = 0; sl < 36; ++sl) {
-        const int jx = 2 * (px >> 1) - 2 + sl / 6, jy = 2 * (py >> 1) - 2 + sl % 6;
-        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
-        if (std::abs(jx - px) <= 1 && std::abs(jy - py) <= 1) continue;
-        const int l = morton2(jx, jy);
-        if (rold[l] == 0) continue;
-        xf.push_back({L.Mb(P, sl), Rub(P), Rub(l), rold[P], rold[l], L.r[P], L.r[l], rpad, rpad, rpad, 1});
-      }
-      if (k - 1 > 2 && lv[k - 2].r[P >> 2] > 0) {
-        const int rG = lv[k - 2].r[P >> 2];
-        xf.push_back({L.UPb(P), Rub(P), nullptr, rold[P], rG, L.r[P], rG, rpad, rpad, rpad, 0});
-      }
+    {
+      TouchXform a{};
+      a.M = L.M;
+      a.UP = k - 1 > 2 ? L.UP : nullptr;
+      a.Tm = Ru;
+      a.nt = L.nc;
+      a.nside = L.nside;
+      a.rpad = rpad;
+      a.col_blocks = 0;
+      a.sM = L.sM;
+      st.touch_xform<T>(a, nullptr, nullptr, rold, L.r, k - 1 > 2 ? &lv[k - 2].r : nullptr, L.nc);
     }
-    st.xform(xf);
     run(st);
     HIP_OK(hipStreamSynchronize(s));
     C.free_work();

@@ -164,6 +164,27 @@ struct StackQrDesc {
       : R(R_), r(r_), ldr(ldr_), first(first_), nblk(nblk_), ty(tcode<U>()) {}
 };
 
+// Basis change of the far-field blocks of a set of clusters whose bases
+// changed ("touched"), with the block geometry resolved on the device.  For a
+// touched cluster q (touch t) with new-from-old basis map T_t (r_new x r_old,
+// ld rpad) and every far-field partner l in q's 6 x 6 window with r_old[l] > 0:
+//   M(q, l) <- T_t M(q, l) T_{tidx[l]}^T   (the right factor only if l is touched)
+//   M(l, q) <- M(l, q) T_t^T               (only if col_blocks and l is untouched)
+// and the parent transfer block UP(q) <- T_t UP(q) when r_par[q / 4] > 0.
+// touch_q / tidx null mean the identity (touch t is cluster t).
+struct TouchXform {
+  void* M;            // 36 blocks per cluster, sM elements each, ld rpad
+  void* UP;           // one block per cluster, sM elements, ld rpad (null: none)
+  const void* Tm;     // per touch, rpad x rpad
+  const int* touch_q; // [nt]
+  const int* tidx;    // [nc], -1 when untouched
+  const int* r_old;   // [nc] ranks before the change
+  const int* r_new;   // [nt]
+  const int* r_par;   // [nc / 4] parent ranks, or null
+  int nt, nside, rpad, col_blocks;
+  size_t sM;
+};
+
 // Inverse of a square FP64 matrix in place (Gauss-Jordan, partial pivoting).
 struct InvDesc {
   double* A;
@@ -209,6 +230,7 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
 // scratch: nwg * ld_scratch * kMaxRank elements of the descriptors' type.
 void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
                   hipStream_t s);
+void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s);
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
 // must fit in `lds` <= kRrqrLdsBytes.

@@ -194,6 +194,80 @@ __global__ __launch_bounds__(WG) void k_xform(const XformDesc* __restrict__ desc
   }
 }
 
+// X <- T X S (T: r_new x r_old or null; S: c_old x c_new, transposed when
+// transS, or null) by one workgroup, Z = T X staged in LDS (rpad x rpad).
+template <class T>
+__device__ void xform_block(T* X, const T* Tm, const T* Sm, int r_old, int c_old, int r_new, int c_new,
+                            int ldx, int ldt, int lds, int transS, T* Z, int ldz) {
+  const int rz = Tm ? r_new : r_old;
+  for (int e = threadIdx.x; e < rz * c_old; e += WG) {
+    const int i = e % rz, j = e / rz;
+    T v;
+    if (Tm) {
+      v = 0;
+      for (int k = 0; k < r_old; ++k) v = fma(Tm[i + (size_t)k * ldt], X[k + (size_t)j * ldx], v);
+    } else {
+      v = X[i + (size_t)j * ldx];
+    }
+    Z[i + j * ldz] = v;
+  }
+  __syncthreads();
+  const int cn = Sm ? c_new : c_old;
+  for (int e = threadIdx.x; e < rz * cn; e += WG) {
+    const int i = e % rz, j = e / rz;
+    T v;
+    if (Sm) {
+      v = 0;
+      for (int k = 0; k < c_old; ++k) {
+        const T s = transS ? Sm[j + (size_t)k * lds] : Sm[k + (size_t)j * lds];
+        v = fma(Z[i + k * ldz], s, v);
+      }
+    } else {
+      v = Z[i + j * ldz];
+    }
+    X[i + (size_t)j * ldx] = v;
+  }
+  __syncthreads();
+}
+
+// One workgroup per (touch, window slot); slot 36 is the parent transfer block.
+template <class T>
+__global__ __launch_bounds__(WG) void k_touch_xform(const TouchXform a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Z = reinterpret_cast<T*>(smem);
+  const int t = blockIdx.x, sl = blockIdx.y;
+  const int q = a.touch_q ? a.touch_q[t] : t;
+  const int rq = a.r_old[q];
+  if (rq == 0) return;
+  const int rn = a.r_new[t];
+  const T* Tq = static_cast<const T*>(a.Tm) + (size_t)t * a.rpad * a.rpad;
+  T* M = static_cast<T*>(a.M);
+  if (sl == 36) {
+    if (a.UP == nullptr || a.r_par == nullptr) return;
+    const int rP = a.r_par[q >> 2];
+    if (rP == 0) return;
+    xform_block<T>(static_cast<T*>(a.UP) + (size_t)q * a.sM, Tq, nullptr, rq, rP, rn, rP, a.rpad, a.rpad, a.rpad,
+                   0, Z, a.rpad);
+    return;
+  }
+  const int qx = demorton_x(q), qy = demorton_y(q);
+  const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+  if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) return;
+  if (abs(jx - qx) <= 1 && abs(jy - qy) <= 1) return;
+  const int l = morton2(jx, jy);
+  const int rl = a.r_old[l];
+  if (rl == 0) return;
+  const int tl = a.tidx ? a.tidx[l] : l;
+  const T* Tl = tl >= 0 ? static_cast<const T*>(a.Tm) + (size_t)tl * a.rpad * a.rpad : nullptr;
+  xform_block<T>(M + ((size_t)q * 36 + sl) * a.sM, Tq, Tl, rq, rl, rn, tl >= 0 ? a.r_new[tl] : rl, a.rpad, a.rpad,
+                 a.rpad, 1, Z, a.rpad);
+  if (tl < 0 && a.col_blocks) {
+    const int ls = win_slot(jx, jy, qx, qy);
+    xform_block<T>(M + ((size_t)l * 36 + ls) * a.sM, nullptr, Tq, rl, rq, rl, rn, a.rpad, a.rpad, a.rpad, 1, Z,
+                   a.rpad);
+  }
+}
+
 // --------------------------------------------------------------------- QR
 template <class T>
 __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
@@ -839,6 +913,21 @@ void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scr
   const dim3 grid(nd < nwg ? nd : nwg);
   if (ty) hipLaunchKernelGGL(k_xform<float>, grid, dim3(WG), 0, s, d, nd, static_cast<float*>(scratch), ld_scratch);
   else hipLaunchKernelGGL(k_xform<double>, grid, dim3(WG), 0, s, d, nd, static_cast<double*>(scratch), ld_scratch);
+}
+
+void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
+  if (a.nt <= 0) return;
+  const dim3 grid(a.nt, 37);
+  const size_t lds = (size_t)a.rpad * a.rpad * (ty ? sizeof(float) : sizeof(double));
+  if (ty) {
+    static bool raised = false;
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<float>), raised, 150 * 1024);
+    hipLaunchKernelGGL(k_touch_xform<float>, grid, dim3(WG), lds, s, a);
+  } else {
+    static bool raised = false;
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<double>), raised, 150 * 1024);
+    hipLaunchKernelGGL(k_touch_xform<double>, grid, dim3(WG), lds, s, a);
+  }
 }
 
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s) {
