@@ -34,9 +34,11 @@ WORKLOAD = ("1,048,576 uniform points in [0,1]^2, exp(-r/0.1) + 1e-2 I, leaf 64,
 # precision (the pivoted QR and the blocked inverse span several kernels).
 SINGLE_KERNEL = {
     "fp64": {"gemm": "k_gemm<double, double, double>", "add": "k_add<double, double>",
-             "xform": "k_xform<double>", "formq": "k_formq<double>", "stackqr": "k_stackqr<double>"},
-    "fp32": {"gemm_f32": "k_gemm<float, float, float>", "xform_f32": "k_xform<float>",
-             "qr_f32": "k_qr<float>", "formq_f32": "k_formq<float>", "stackqr_f32": "k_stackqr<float>"},
+             "formq": "k_formq<double>", "stackqr": "k_stackqr<double>", "elim": "k_elim<double>",
+             "touch_xform": "k_touch_xform<double>", "stack_win": "k_stackqr_win<double>"},
+    "fp32": {"gemm_f32": "k_gemm<float, float, float>", "qr_f32": "k_qr<float>",
+             "formq_f32": "k_formq<float>", "stackqr_f32": "k_stackqr<float>", "elim_f32": "k_elim<float>",
+             "touch_xform_f32": "k_touch_xform<float>", "stack_win_f32": "k_stackqr_win<float>"},
 }
 
 

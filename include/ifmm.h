@@ -110,15 +110,18 @@ typedef struct {
   double factor_bytes;     /* device bytes held by the factor */
   double factor_flops;     /* counted FP64 flops of the factorisation */
   /* With ifmm_options.profile: per batched-kernel family, accumulated over the
-     handle's life.  Slot f + 8 q: family f -- 0 gemm, 1 add/copy, 2 basis
-     transform, 3 Householder QR, 4 column-pivoted QR, 5 basis formation,
-     6 stacked R factor, 7 pivot inverse -- with q = 1 for launches computing
-     in FP32 (gemm: both operands FP32; add: FP32 destination).  flops / bytes
-     are the algorithmic counts of the launches (bytes at storage size). */
-  int64_t kernel_launches[16];
-  double kernel_ms[16];
-  double kernel_flops[16];
-  double kernel_bytes[16];
+     handle's life.  Slot f + 16 q: family f -- 0 gemm, 1 add/copy, 2 basis
+     transform (descriptor list), 3 Householder QR, 4 column-pivoted QR,
+     5 basis formation, 6 stacked R factor, 7 pivot inverse, 8 elimination
+     steps (pivot build, X = D^-1 B, Schur updates, M2L row), 9 basis change
+     of touched clusters, 10 far-field weight stacks; 11..15 unused -- with
+     q = 1 for launches whose blocks are FP32 (gemm: both operands FP32; add:
+     FP32 destination).  flops / bytes are the algorithmic counts of the
+     launches (bytes at storage size). */
+  int64_t kernel_launches[32];
+  double kernel_ms[32];
+  double kernel_flops[32];
+  double kernel_bytes[32];
   int precision;           /* ifmm_precision of the factor */
 } ifmm_stats_t;
 

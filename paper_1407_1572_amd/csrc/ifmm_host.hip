@@ -165,9 +165,23 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM };
-constexpr int kOpTypes = 8;  // profile families; the three blocked-inverse pieces count as 7
-inline int family(int t) { return t == OP_TXFORM ? (int)OP_XFORM : t >= OP_GJPANEL ? 7 : t; }
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS };
+// Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 xform, 3 qr,
+// 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse (its three pieces), 8 elim,
+// 9 touched-cluster transform, 10 window stacked R.
+constexpr int kOpTypes = 16;
+inline int family(int t) {
+  switch (t) {
+    case OP_GJPANEL:
+    case OP_GJREST:
+    case OP_GJUNPERM: return 7;
+    case OP_ELIM: return 8;
+    case OP_TXFORM: return 9;
+    case OP_WSTACK: return 10;
+    case OP_TRANS: return 1;
+    default: return t;
+  }
+}
 struct Op {
   OpType t;
   size_t off, off2;
@@ -329,15 +343,15 @@ struct Stage {
   // travel in the blob; the pointer fields of the stored TouchXform hold
   // their blob offsets + 1 (0 = null) and are rebased at launch.  flops and
   // bytes are the exact algorithmic counts, from the host's rank tables.
+  const int* arr(const std::vector<int>* v) {
+    if (!v) return nullptr;
+    return reinterpret_cast<const int*>(push(v->data(), std::max<size_t>(1, v->size()) * sizeof(int)) + 1);
+  }
   template <class T>
   void touch_xform(TouchXform a, const std::vector<int>* touch_q, const std::vector<int>* tidx,
                    const std::vector<int>& r_old, const std::vector<int>& r_new, const std::vector<int>* r_par,
                    int ncl) {
     if (a.nt <= 0) return;
-    auto arr = [&](const std::vector<int>* v) -> const int* {
-      if (!v) return nullptr;
-      return reinterpret_cast<const int*>(push(v->data(), std::max<size_t>(1, v->size()) * sizeof(int)) + 1);
-    };
     a.touch_q = arr(touch_q);
     a.tidx = arr(tidx);
     a.r_old = arr(&r_old);
@@ -370,6 +384,53 @@ struct Stage {
     }
     flops += f;
     op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
+  }
+  // Far-field weight stacks with device-side block lists (arrays as in
+  // touch_xform).
+  template <class T>
+  void win_stack(WinStack a, const std::vector<int>& ids, const std::vector<int>& r, const std::vector<int>* r_par) {
+    if (a.nt <= 0) return;
+    a.ids = arr(&ids);
+    a.r = arr(&r);
+    a.r_par = arr(r_par);
+    double f = 0, by = 0;
+    int rmax = 0;
+    const double es = sizeof(T);
+    for (int t = 0; t < a.nt; ++t) {
+      const int q = ids[t], rq = r[q];
+      if (rq == 0) continue;
+      rmax = std::max(rmax, rq);
+      double rows = (a.Z && r_par) ? (*r_par)[q >> 2] : 0;
+      const int qx = demorton_x(q), qy = demorton_y(q);
+      for (int sl = 0; sl < 36; ++sl) {
+        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+        if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+        rows += r[morton2(jx, jy)];
+      }
+      f += 2.0 * rows * rq * rq;
+      by += es * (rows * rq + (double)a.S * rq * rq);
+    }
+    flops += f;
+    op({OP_WSTACK, push(&a, sizeof(a)), 0, a.nt, rmax, 0, f, by}, tcode<T>());
+  }
+  // One step of the elimination kernels over a batch of records (the record
+  // array is pushed once per batch: rec_off = its blob offset + 1).
+  template <class T>
+  void elim(ElimArgs a, size_t rec_off, int step, int max_m, int max_n, double f, double by) {
+    if (a.nb <= 0) return;
+    a.rec = reinterpret_cast<const ElimRec*>(rec_off);
+    flops += f;
+    op({OP_ELIM, push(&a, sizeof(a)), 0, step, max_m, max_n, f, by}, tcode<T>());
+  }
+  // Level transition assembly (device-side geometry).
+  template <class T>
+  void transition(TransArgs a, const std::vector<int>& choff, const std::vector<int>& cr,
+                  const std::vector<int>& r_par, double by) {
+    a.choff = arr(&choff);
+    a.cr = arr(&cr);
+    a.r_par = arr(&r_par);
+    op({OP_TRANS, push(&a, sizeof(a)), 0, a.nc, 0, 0, 0.0, by}, tcode<T>());
   }
   // All blocks of a stack have the type of its R.
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
@@ -760,6 +821,37 @@ struct Plan final : ifmm_plan {
           launch_touch_xform(a, op.ty, s);
           break;
         }
+        case OP_TRANS: {
+          TransArgs a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          auto rebase = [&](const int*& p) {
+            if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
+          };
+          rebase(a.choff);
+          rebase(a.cr);
+          rebase(a.r_par);
+          launch_transition(a, op.ty, s);
+          break;
+        }
+        case OP_ELIM: {
+          ElimArgs a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          a.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(a.rec) - 1));
+          launch_elim(a, op.count, op.a, op.b, op.ty, s);
+          break;
+        }
+        case OP_WSTACK: {
+          WinStack a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          auto rebase = [&](const int*& p) {
+            if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
+          };
+          rebase(a.ids);
+          rebase(a.r);
+          rebase(a.r_par);
+          launch_stackqr_win(a, op.a, op.ty, s);
+          break;
+        }
         case OP_GJPANEL:
           launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
@@ -777,7 +869,7 @@ struct Plan final : ifmm_plan {
       HIP_OK(hipGetLastError());
       if (profile) {
         HIP_OK(hipEventRecord(eb, s));
-        const bool f32 = op.t == OP_GEMM ? (op.ty & 3) == 3 : op.t == OP_ADD ? (op.ty & 2) != 0 : op.ty != 0;
+        const bool f32 = op.t == OP_GEMM ? (op.ty & 3) == 3 : op.t == OP_ADD ? (op.ty & 2) != 0 : op.ty != 0;  // elim: block type
         pend.push_back({family(op.t) + (f32 ? kOpTypes : 0), ea, eb, op.flops, op.bytes});
         if (pend.size() > 4096) resolve_profile();
       }
@@ -1064,81 +1156,61 @@ struct Plan final : ifmm_plan {
       std::vector<int> ids;
       for (int i = 0; i < L.nc; ++i)
         if (L.r[i] > 0) ids.push_back(i);
-      weights(k, ids, [&](int t) { return L.Omb(ids[t]); });
+      weights(k, ids, L.Om, true);
     }
     HIP_OK(hipStreamSynchronize(s));
     t_assembly = now_ms() - t0;
   }
 
   // Omega of the clusters `ids` at level k: R factor of the stacked
-  // transposed far-field row (+ the parent chain UP Omega_parent^T).
-  template <class OutFn>
-  void weights(int k, const std::vector<int>& ids, OutFn out) {
+  // transposed far-field row (+ the parent chain UP Omega_parent^T), written
+  // to out + t * rpad^2 (or out + ids[t] * rpad^2 when by_id).
+  void weights(int k, const std::vector<int>& ids, T* out, bool by_id) {
     Level<T>& L = lv[k];
     const int nt = (int)ids.size();
     if (nt == 0) return;
+    const size_t so = (size_t)rpad * rpad;
     T* Z = nullptr;
-    if (k > 2) Z = wsZ.need<T>((size_t)nt * rpad * rpad, s);
     Stage st;
-    std::vector<GemmDesc> g;
-    std::vector<StackQrDesc> sd;
-    std::vector<BlkRef> br;
-    for (int t = 0; t < nt; ++t) {
-      const int q = ids[t];
-      const int rq = L.r[q];
-      StackQrDesc d{out(t), rq, rpad, (int)br.size(), 0};
-      const int qx = demorton_x(q), qy = demorton_y(q);
-      for (int sl = 0; sl < 36; ++sl) {
-        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-        if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
-        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
-        const int l = morton2(jx, jy);
-        if (L.r[l] == 0) continue;
-        br.push_back({L.Mb(q, sl), rpad, L.r[l], 1});
-        d.nblk++;
+    if (k > 2) {
+      Z = wsZ.need<T>((size_t)nt * so, s);
+      Level<T>& Pl = lv[k - 1];
+      std::vector<GemmDesc> g;
+      for (int t = 0; t < nt; ++t) {
+        const int q = ids[t], P = q >> 2, rP = Pl.r[P];
+        if (rP > 0 && L.r[q] > 0)
+          g.push_back({Pl.Omb(P), L.UPb(q), Z + (size_t)t * so, rP, L.r[q], rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
       }
-      if (k > 2) {
-        Level<T>& Pl = lv[k - 1];
-        const int P = q >> 2;
-        const int rP = Pl.r[P];
-        if (rP > 0) {
-          T* z = Z + (size_t)t * rpad * rpad;
-          g.push_back({Pl.Omb(P), L.UPb(q), z, rP, rq, rP, rpad, rpad, rpad, 0, 1, 1.0, 0.0});
-          br.push_back({z, rpad, rP, 0});
-          d.nblk++;
-        }
-      }
-      sd.push_back(d);
+      st.gemm(g);
     }
-    st.gemm(g);
     // Few clusters (coarse levels): split each stack into segments handled by
     // separate workgroups, then take the R factor of the stacked partial R's
     // (the same R up to rounding).
     const int S = std::max(1, std::min(8, (3072 + nt - 1) / nt));
-    if (S == 1) {
-      st.stackqr(sd, br);
-    } else {
-      T* part = wsSeg.need<T>((size_t)nt * S * rpad * rpad, s);
-      std::vector<StackQrDesc> s1, s2;
-      std::vector<BlkRef> b1, b2;
+    T* part = S > 1 ? wsSeg.need<T>((size_t)nt * S * so, s) : nullptr;
+    WinStack a{};
+    a.M = L.M;
+    a.Z = Z;
+    a.out = S > 1 ? part : out;
+    a.sM = L.sM;
+    a.so = so;
+    a.rpad = rpad;
+    a.nside = L.nside;
+    a.ldo = rpad;
+    a.nt = nt;
+    a.S = S;
+    a.out_by_id = by_id ? 1 : 0;
+    st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr);
+    if (S > 1) {
+      std::vector<StackQrDesc> s2;
+      std::vector<BlkRef> b2;
       for (int t = 0; t < nt; ++t) {
-        const StackQrDesc& d = sd[t];
-        StackQrDesc fin{static_cast<T*>(d.R), d.r, d.ldr, (int)b2.size(), 0};
-        const int per = (d.nblk + S - 1) / S;
-        for (int g0 = 0; g0 < d.nblk; g0 += per) {
-          T* pr = part + ((size_t)t * S + g0 / per) * rpad * rpad;
-          StackQrDesc ps{pr, d.r, rpad, (int)b1.size(), 0};
-          for (int x = g0; x < std::min(d.nblk, g0 + per); ++x) {
-            b1.push_back(br[d.first + x]);
-            ps.nblk++;
-          }
-          s1.push_back(ps);
-          b2.push_back({pr, rpad, d.r, 0});
-          fin.nblk++;
-        }
+        const int q = ids[t], rq = L.r[q];
+        if (rq == 0) continue;
+        StackQrDesc fin{out + (by_id ? (size_t)q : (size_t)t) * so, rq, rpad, (int)b2.size(), S};
+        for (int g0 = 0; g0 < S; ++g0) b2.push_back({part + ((size_t)t * S + g0) * so, rpad, rq, 0});
         s2.push_back(fin);
       }
-      st.stackqr(s1, b1);
       st.stackqr(s2, b2);
     }
     run(st);
@@ -1206,81 +1278,78 @@ struct Plan final : ifmm_plan {
     // ---- eliminate the batch: pivot inverse, X = D^-1 B, Schur updates
     {
       Stage st;
-      std::vector<AddDesc> dbuild;
+      std::vector<ElimRec> recs(nb);
+      int maxm = 0, maxu = 0;
+      double f1 = 0, b1 = 0, f2 = 0, b2 = 0, b3 = 0;
+      const double es = sizeof(T);
+      for (int b = 0; b < nb; ++b) {
+        const Elim& e = E[b];
+        ElimRec& r = recs[b];
+        r.i = e.i;
+        r.ni = e.ni;
+        r.ri = e.ri;
+        r.m = e.m;
+        maxm = std::max(maxm, e.m);
+        for (int sp = 0; sp < 9; ++sp) {
+          r.cl[sp] = e.u[sp].cl;
+          r.kind[sp] = e.u[sp].kind;
+          r.size[sp] = e.u[sp].size;
+          r.off[sp] = e.u[sp].off;
+          if (!e.u[sp].kind) continue;
+          maxu = std::max(maxu, e.u[sp].size);
+          if (sp != 4) {
+            f1 += 2.0 * e.m * e.u[sp].size * e.ni;
+            b1 += 8.0 * e.m * e.ni + es * (2.0 * e.ni * e.u[sp].size + (double)e.m * e.u[sp].size);
+          }
+          b3 += es * 3.0 * e.ri * e.u[sp].size;
+        }
+        for (int sa = 0; sa < 9; ++sa) {
+          if (sa == 4 || !e.u[sa].kind) continue;
+          for (int sb = 0; sb < 9; ++sb) {
+            if (!e.u[sb].kind) continue;
+            const double ma = e.u[sa].size, nbu = e.u[sb].size;
+            f2 += 2.0 * ma * nbu * e.ni;
+            b2 += es * (ma * e.ni + e.ni * nbu + (kPairs.idx[sa][sb] >= 0 && !(e.u[sa].kind == 2 && e.u[sb].kind == 2)
+                                                      ? 1.0 : 2.0) * ma * nbu);
+          }
+        }
+      }
+      ElimArgs a{};
+      a.P = L.P;
+      a.Qm = L.Qm;
+      a.L = L.L;
+      a.M = L.M;
+      a.U = L.U;
+      a.Dinv = L.Dinv;
+      a.X = X;
+      a.F = F;
+      a.sP = L.sP;
+      a.sQ = L.sQ;
+      a.sL = L.sL;
+      a.sM = L.sM;
+      a.sU = L.sU;
+      a.sD = L.sD;
+      a.sX = (size_t)L.mpad * wpad;
+      a.nb = nb;
+      a.npad = L.npad;
+      a.rpad = rpad;
+      a.mpad = L.mpad;
+      a.fpad = fpad;
+      a.npair = kPairs.count;
+      for (int sa = 0; sa < 9; ++sa)
+        for (int sb = 0; sb < 9; ++sb) a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
+      const size_t ro = st.push(recs.data(), recs.size() * sizeof(ElimRec)) + 1;
+      double bd = 0;
       std::vector<InvDesc> inv;
       for (const Elim& e : E) {
-        double* D = L.Db(e.i);
-        dbuild.push_back({L.Pb(e.i, 4), D, e.ni, e.ni, L.npad, L.mpad, 0, 1.0, 0.0});
-        dbuild.push_back({L.Ub(e.i), D + (size_t)e.ni * L.mpad, e.ni, e.ri, L.npad, L.mpad, 0, 1.0, 0.0});
-        dbuild.push_back({L.Ub(e.i), D + e.ni, e.ri, e.ni, L.npad, L.mpad, 1, 1.0, 0.0});
-        dbuild.push_back({nullptr, D + e.ni + (size_t)e.ni * L.mpad, e.ri, e.ri, 0, L.mpad, 0, 0.0, 0.0});
-        inv.push_back({D, e.m, L.mpad});
+        inv.push_back({L.Db(e.i), e.m, L.mpad});
+        bd += (es + 8.0) * e.m * (double)e.m;
       }
-      st.add(dbuild);
+      st.elim<T>(a, ro, 0, maxm, maxm, 0.0, bd);
       plan_inverse(st, inv);
-      std::vector<GemmDesc> gx;
-      std::vector<AddDesc> ax;
-      for (int b = 0; b < nb; ++b) {
-        const Elim& e = E[b];
-        const double* D = L.Db(e.i);
-        for (int sp = 0; sp < 9; ++sp) {
-          const UnitH& u = e.u[sp];
-          if (!u.kind) continue;
-          T* Xc = Xp(b) + (size_t)u.off * L.mpad;
-          if (sp == 4) {
-            ax.push_back({D + (size_t)e.ni * L.mpad, Xc, e.m, e.ri, L.mpad, L.mpad, 0, -1.0, 0.0});
-          } else {
-            const T* Bsrc = u.kind == 1 ? L.Pb(e.i, sp) : L.Qb(e.i, sp);
-            gx.push_back({D, Bsrc, Xc, e.m, u.size, e.ni, L.mpad, L.npad, L.mpad, 0, 0, 1.0, 0.0});
-          }
-        }
-      }
-      st.gemm(gx);
-      st.add(ax);
-      std::vector<GemmDesc> gs;
-      std::vector<AddDesc> am;
-      for (int b = 0; b < nb; ++b) {
-        const Elim& e = E[b];
-        for (int sa = 0; sa < 9; ++sa) {
-          const UnitH& ua = e.u[sa];
-          if (!ua.kind || sa == 4) continue;
-          const T* Ca = ua.kind == 1 ? L.Pb(ua.cl, 8 - sa) : L.Lb(ua.cl, 8 - sa);
-          const int lda = ua.kind == 1 ? L.npad : rpad;
-          for (int sb = 0; sb < 9; ++sb) {
-            const UnitH& ub = e.u[sb];
-            if (!ub.kind) continue;
-            const T* Xb = Xp(b) + (size_t)ub.off * L.mpad;
-            T* C;
-            int ldc;
-            double beta = 1.0;
-            const bool adj = pos_adjacent(sa, sb);
-            if (ua.kind == 2 && ub.kind == 2) {
-              C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
-              ldc = rpad;
-            } else if (!adj) {
-              C = Fp(b, sa, sb);
-              ldc = fpad;
-              beta = 0.0;
-            } else {
-              const int st9 = s9_of(s9_dx(sb) - s9_dx(sa), s9_dy(sb) - s9_dy(sa));
-              if (ua.kind == 1 && ub.kind == 1) { C = L.Pb(ua.cl, st9); ldc = L.npad; }
-              else if (ua.kind == 1) { C = L.Qb(ua.cl, st9); ldc = L.npad; }
-              else { C = L.Lb(ua.cl, st9); ldc = rpad; }
-            }
-            gs.push_back({Ca, Xb, C, ua.size, ub.size, e.ni, lda, L.mpad, ldc, 0, 0, -1.0, beta});
-          }
-        }
-        // row M2L(i) of the pivot: += X^z
-        for (int sb = 0; sb < 9; ++sb) {
-          const UnitH& ub = e.u[sb];
-          if (!ub.kind) continue;
-          const T* Xz = Xp(b) + e.ni + (size_t)ub.off * L.mpad;
-          if (ub.kind == 1) am.push_back({Xz, L.Lb(e.i, sb), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
-          else am.push_back({Xz, L.Mb(e.i, slot36(e.i, ub.cl)), e.ri, ub.size, L.mpad, rpad, 0, 1.0, 1.0});
-        }
-      }
-      st.gemm(gs);
-      st.add(am);
+      st.elim<T>(a, ro, 1, maxm, maxu, f1, b1);
+      st.elim<T>(a, ro, 2, maxu, maxu, f2, b2);
+      st.elim<T>(a, ro, 3, rpad, maxu, 0.0, b3);
       run(st);
     }
     compress(k, E, fpad, Fp);
@@ -1314,7 +1383,7 @@ struct Plan final : ifmm_plan {
     T* Om = wsB.need<T>((size_t)nt * rpad * rpad, s);
     std::vector<int> ids(nt);
     for (int t = 0; t < nt; ++t) ids[t] = touch[t].q;
-    weights(k, ids, [&](int t) { return Om + (size_t)t * rpad * rpad; });
+    weights(k, ids, Om, false);
     // new bases, chunk by chunk: pivoted QR of [U Omega^T | fill of the row]
     const int cmax = rpad + 5 * fpad;
     T* Uh = wsQ.need<T>((size_t)nt * L.sU, s);
@@ -1459,31 +1528,30 @@ struct Plan final : ifmm_plan {
     T* Ru = wsA.need<T>((size_t)L.nc * rpad * rpad, s);
     auto Rub = [&](int P) { return Ru + (size_t)P * rpad * rpad; };
     Stage st;
-    std::vector<AddDesc> a;
-    for (int P = 0; P < L.nc; ++P) {
-      if (L.n[P] == 0) continue;
-      for (int sp = 0; sp < 9; ++sp) {
-        const int Q = L.nbr9[(size_t)P * 9 + sp];
-        if (Q < 0 || L.n[Q] == 0) continue;
-        T* B = L.Pb(P, sp);
-        for (int c = 0; c < 4; ++c) {
-          const int ch = 4 * P + c;
-          if (C.r[ch] == 0) continue;
-          for (int c2 = 0; c2 < 4; ++c2) {
-            const int ch2 = 4 * Q + c2;
-            if (C.r[ch2] == 0) continue;
-            a.push_back({C.Mb(ch, slot36(ch, ch2)), B + L.choff[(size_t)P * 4 + c] + (size_t)L.choff[(size_t)Q * 4 + c2] * L.npad,
-                         C.r[ch], C.r[ch2], rpad, L.npad, 0, 1.0, 0.0});
-          }
+    {
+      TransArgs a{};
+      a.CM = C.M;
+      a.CUP = C.UP;
+      a.P = L.P;
+      a.U = L.U;
+      a.sM = C.sM;
+      a.sP = L.sP;
+      a.sU = L.sU;
+      a.npad = L.npad;
+      a.rpad = rpad;
+      a.nside = L.nside;
+      a.nc = L.nc;
+      double by = 0;
+      for (int P = 0; P < L.nc; ++P) {
+        if (L.n[P] == 0) continue;
+        for (int sp = 0; sp < 9; ++sp) {
+          const int Q = L.nbr9[(size_t)P * 9 + sp];
+          if (Q >= 0) by += 2.0 * sizeof(T) * (double)L.n[P] * L.n[Q];
         }
+        by += 2.0 * sizeof(T) * (double)L.n[P] * rold[P];
       }
-      for (int c = 0; c < 4; ++c) {
-        const int ch = 4 * P + c;
-        if (C.r[ch] == 0) continue;
-        a.push_back({C.UPb(ch), L.Ub(P) + L.choff[(size_t)P * 4 + c], C.r[ch], rold[P], rpad, L.npad, 0, 1.0, 0.0});
-      }
+      st.transition<T>(a, L.choff, C.r, rold, by);
     }
-    st.add(a);
     std::vector<QrDesc> q;
     std::vector<AddDesc> z;
     for (int P = 0; P < L.nc; ++P) {

@@ -185,29 +185,97 @@ struct TouchXform {
   size_t sM;
 };
 
+// Far-field weights with the block lists found on the device: for cluster
+// q = ids[t], R of the stack of M(q, l)^T over the far-field partners l of
+// q's 6 x 6 window (r[l] rows each) and of the parent term Z_t (r_par[q / 4]
+// rows, ld rpad) when Z and r_par are given.  The stack is split in S
+// segments of window slots (one workgroup each); segment s writes its R to
+// out + (t * S + s) * so, or to out + q * so when S == 1 and out_by_id.
+struct WinStack {
+  const void* M;
+  const void* Z;
+  void* out;
+  const int* ids;    // [nt]
+  const int* r;      // [nc]
+  const int* r_par;  // [nc / 4] or null
+  size_t sM, so;
+  int rpad, nside, ldo, nt, S, out_by_id;
+};
+
+// One eliminated cluster of a colour batch (Algorithm 1, one Schur step):
+// the units of its 3 x 3 neighbourhood, slot s = 3 (dx + 1) + (dy + 1),
+// slot 4 being the cluster's own multipoles.  kind 1: the particles of a
+// not yet eliminated neighbour; 2: the multipoles of an eliminated neighbour
+// (or of the cluster itself); 0: absent.  off: column offset of the unit in
+// the batch workspace X (X = D^-1 B, m x sum of unit sizes, ld mpad).
+struct ElimRec {
+  int i, ni, ri, m;
+  int cl[9], kind[9], size[9], off[9];
+};
+// Level blocks and batch workspaces of the elimination kernels.  Blocks are
+// in the factor's type, the pivot inverses in FP64.  F holds the fill of
+// the unit pairs at Chebyshev distance 2 (pair index pair[9 sa + sb] >= 0),
+// fpad x fpad each, npair per elimination.
+struct ElimArgs {
+  void* P;
+  void* Qm;
+  void* L;
+  void* M;
+  void* U;
+  double* Dinv;
+  void* X;
+  void* F;
+  const ElimRec* rec;
+  size_t sP, sQ, sL, sM, sU, sD, sX;
+  int nb, npad, rpad, mpad, fpad, npair;
+  signed char pair[81];
+};
+
+// Level transition k -> k-1 with device-side geometry: for parent P, its
+// neighbour Q in slot sp of P's 3 x 3 neighbourhood and children c of P, c2
+// of Q with nonzero ranks, P2P^(k-1)(P, Q) gets M^(k)(c, c2) at rows
+// choff[4P + c], columns choff[4Q + c2]; U^(k-1)(P) gets the children's
+// transfer blocks UP^(k)(4P + c) (cr x r_par[P]) at rows choff[4P + c].
+struct TransArgs {
+  const void* CM;    // child level M2L blocks, 36 per child, ld rpad
+  const void* CUP;   // child level transfer blocks, ld rpad
+  void* P;           // parent level near-field blocks, 9 per parent, ld npad
+  void* U;           // parent level bases, ld npad
+  const int* choff;  // [4 nc]
+  const int* cr;     // [4 nc] child ranks
+  const int* r_par;  // [nc] parent ranks before re-orthonormalisation
+  size_t sM, sP, sU;
+  int npad, rpad, nside, nc;
+};
+
 // Inverse of a square FP64 matrix in place (Gauss-Jordan, partial pivoting).
 struct InvDesc {
   double* A;
   int m, lda;
 };
 
-__host__ __device__ inline int demorton_x(int key) {
-  int x = 0;
-  for (int b = 0; b < 15; ++b) x |= ((key >> (2 * b)) & 1) << b;
+// Morton keys by bit interleaving with masks (bit b of x -> bit 2b, bit b
+// of y -> bit 2b + 1), for coordinates below 2^15.
+__host__ __device__ inline unsigned spread_bits(unsigned x) {
+  x &= 0x0000ffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
   return x;
 }
-__host__ __device__ inline int demorton_y(int key) {
-  int y = 0;
-  for (int b = 0; b < 15; ++b) y |= ((key >> (2 * b + 1)) & 1) << b;
-  return y;
+__host__ __device__ inline unsigned gather_bits(unsigned x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
 }
+__host__ __device__ inline int demorton_x(int key) { return (int)gather_bits((unsigned)key); }
+__host__ __device__ inline int demorton_y(int key) { return (int)gather_bits((unsigned)key >> 1); }
 __host__ __device__ inline int morton2(int x, int y) {
-  int key = 0;
-  for (int b = 0; b < 15; ++b) {
-    key |= ((x >> b) & 1) << (2 * b);
-    key |= ((y >> b) & 1) << (2 * b + 1);
-  }
-  return key;
+  return (int)(spread_bits((unsigned)x) | (spread_bits((unsigned)y) << 1));
 }
 // Slot of cluster (jx, jy) in the 6 x 6 window of cluster (ix, iy) -- the
 // children of the parent's 3 x 3 neighbourhood, which holds N_i and I_i --
@@ -231,6 +299,16 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
 void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
                   hipStream_t s);
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s);
+void launch_transition(const TransArgs& a, int ty, hipStream_t s);
+// The elimination steps of a colour batch (one record per eliminated
+// cluster, geometry resolved on the device):
+//   0 build the pivot blocks D = [[P_ii, U_i], [U_i^T, 0]] (FP64);
+//   1 X_u = D^-1 [B_u; 0] for every unit u (X_centre = -D^-1 [0; I]);
+//   2 Schur updates target(a, b) -= C_a X_b over all unit pairs (fill of
+//     pairs at distance 2 goes to F);
+//   3 M2L(i) row: L_iq / M_ip += X^z_u.
+// max_m / max_n bound the row / column sizes for the tiling.
+void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s);
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
 // must fit in `lds` <= kRrqrLdsBytes.
@@ -242,6 +320,7 @@ void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrStat
                        hipStream_t s);
 void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
+void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
 // Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s);

@@ -63,15 +63,12 @@ __device__ inline T grp_sum(T v) {
 }
 
 // ------------------------------------------------------------------- GEMM
-// 64 x 64 output tile per workgroup, 4 x 4 per thread, K staged by 16 in LDS.
+// 64 x 64 output tile (m0, n0) of one product, 4 x 4 per thread, K staged by
+// 16 in LDS.
 template <class TA, class TB, class TC>
-__global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs, int tiles_m) {
+__device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
   using Acc = typename std::conditional<std::is_same<TA, float>::value && std::is_same<TB, float>::value,
                                         float, double>::type;
-  const GemmDesc d = descs[blockIdx.x];
-  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
-  const int m0 = tm * 64, n0 = tn * 64;
-  if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
   const TA* __restrict__ Ap = static_cast<const TA*>(d.A);
   const TB* __restrict__ Bp = static_cast<const TB*>(d.B);
   TC* Cp = static_cast<TC*>(d.C);
@@ -127,6 +124,143 @@ __global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs,
         *c = (TC)(d.beta == 0.0 ? al * acc[i][j] : fma(al, acc[i][j], be * (Acc)*c));
       }
     }
+}
+
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs, int tiles_m) {
+  const GemmDesc d = descs[blockIdx.x];
+  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
+  const int m0 = tm * 64, n0 = tn * 64;
+  if (d.C == nullptr || m0 >= d.M || n0 >= d.N) return;
+  gemm_tile<TA, TB, TC>(d, m0, n0);
+}
+
+// --------------------------------------------------------- ELIMINATION
+__device__ inline int e9_dx(int s) { return s / 3 - 1; }
+__device__ inline int e9_dy(int s) { return s % 3 - 1; }
+
+// Descriptor of step 1 for unit u of record r (false: nothing to do).
+template <class T>
+__device__ bool elim_x_desc(const ElimArgs& a, const ElimRec& r, int b, int u, GemmDesc& g) {
+  if (!r.kind[u] || u == 4) return false;
+  T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[u] * a.mpad;
+  const T* B = r.kind[u] == 1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
+                              : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
+  g.A = a.Dinv + (size_t)r.i * a.sD;
+  g.B = B;
+  g.C = X;
+  g.M = r.m;
+  g.N = r.size[u];
+  g.K = r.ni;
+  g.lda = a.mpad;
+  g.ldb = a.npad;
+  g.ldc = a.mpad;
+  g.opA = 0;
+  g.opB = 0;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  return true;
+}
+
+// Descriptor of step 2 for the unit pair (sa, sb) of record r.
+template <class T>
+__device__ bool elim_schur_desc(const ElimArgs& a, const ElimRec& r, int b, int sa, int sb, GemmDesc& g) {
+  if (sa == 4 || !r.kind[sa] || !r.kind[sb]) return false;
+  const int ka = r.kind[sa], kb = r.kind[sb], ca = r.cl[sa];
+  g.A = ka == 1 ? static_cast<const T*>(a.P) + ((size_t)ca * 9 + (8 - sa)) * a.sP
+                : static_cast<const T*>(a.L) + ((size_t)ca * 9 + (8 - sa)) * a.sL;
+  g.lda = ka == 1 ? a.npad : a.rpad;
+  g.B = static_cast<const T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[sb] * a.mpad;
+  g.ldb = a.mpad;
+  const bool adj = abs(e9_dx(sa) - e9_dx(sb)) <= 1 && abs(e9_dy(sa) - e9_dy(sb)) <= 1;
+  g.beta = 1.0;
+  if (ka == 2 && kb == 2) {
+    const int cb = r.cl[sb];
+    const int sl = win_slot(demorton_x(ca), demorton_y(ca), demorton_x(cb), demorton_y(cb));
+    g.C = static_cast<T*>(a.M) + ((size_t)ca * 36 + sl) * a.sM;
+    g.ldc = a.rpad;
+  } else if (!adj) {
+    g.C = static_cast<T*>(a.F) + ((size_t)b * a.npair + a.pair[9 * sa + sb]) * a.fpad * a.fpad;
+    g.ldc = a.fpad;
+    g.beta = 0.0;
+  } else {
+    const int st9 = 3 * (e9_dx(sb) - e9_dx(sa) + 1) + (e9_dy(sb) - e9_dy(sa) + 1);
+    if (ka == 1 && kb == 1) {
+      g.C = static_cast<T*>(a.P) + ((size_t)ca * 9 + st9) * a.sP;
+      g.ldc = a.npad;
+    } else if (ka == 1) {
+      g.C = static_cast<T*>(a.Qm) + ((size_t)ca * 9 + st9) * a.sQ;
+      g.ldc = a.npad;
+    } else {
+      g.C = static_cast<T*>(a.L) + ((size_t)ca * 9 + st9) * a.sL;
+      g.ldc = a.rpad;
+    }
+  }
+  g.M = r.size[sa];
+  g.N = r.size[sb];
+  g.K = r.ni;
+  g.opA = 0;
+  g.opB = 0;
+  g.alpha = -1.0;
+  return true;
+}
+
+// grid (nb, units * tiles): step 0 and 3 are elementwise, 1 and 2 products.
+template <class T>
+__global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int step, int tiles_m, int tiles_n) {
+  const int b = blockIdx.x;
+  const ElimRec& r = a.rec[b];
+  const int per = tiles_m * tiles_n;
+  const int unit = blockIdx.y / per, tile = blockIdx.y % per;
+  const int m0 = (tile % tiles_m) * 64, n0 = (tile / tiles_m) * 64;
+  if (step == 0) {  // D = [[P_ii, U], [U^T, 0]]
+    double* D = a.Dinv + (size_t)r.i * a.sD;
+    const T* Pii = static_cast<const T*>(a.P) + ((size_t)r.i * 9 + 4) * a.sP;
+    const T* U = static_cast<const T*>(a.U) + (size_t)r.i * a.sU;
+    for (int e = threadIdx.x; e < 64 * 64; e += WG) {
+      const int row = m0 + e % 64, col = n0 + e / 64;
+      if (row >= r.m || col >= r.m) continue;
+      double v;
+      if (row < r.ni && col < r.ni) v = (double)Pii[row + (size_t)col * a.npad];
+      else if (row < r.ni) v = (double)U[row + (size_t)(col - r.ni) * a.npad];
+      else if (col < r.ni) v = (double)U[col + (size_t)(row - r.ni) * a.npad];
+      else v = 0.0;
+      D[row + (size_t)col * a.mpad] = v;
+    }
+  } else if (step == 1) {
+    if (unit == 4) {  // X_centre = -D^-1[:, ni:m]
+      if (!r.kind[4]) return;
+      const double* D = a.Dinv + (size_t)r.i * a.sD + (size_t)r.ni * a.mpad;
+      T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[4] * a.mpad;
+      for (int e = threadIdx.x; e < 64 * 64; e += WG) {
+        const int row = m0 + e % 64, col = n0 + e / 64;
+        if (row < r.m && col < r.ri) X[row + (size_t)col * a.mpad] = (T)(-D[row + (size_t)col * a.mpad]);
+      }
+      return;
+    }
+    GemmDesc g;
+    if (!elim_x_desc<T>(a, r, b, unit, g) || m0 >= g.M || n0 >= g.N) return;
+    gemm_tile<double, T, T>(g, m0, n0);
+  } else if (step == 2) {
+    GemmDesc g;
+    if (!elim_schur_desc<T>(a, r, b, unit / 9, unit % 9, g) || m0 >= g.M || n0 >= g.N) return;
+    gemm_tile<T, T, T>(g, m0, n0);
+  } else {  // M2L(i) row += X^z_u
+    if (!r.kind[unit]) return;
+    const T* Xz = static_cast<const T*>(a.X) + (size_t)b * a.sX + r.ni + (size_t)r.off[unit] * a.mpad;
+    T* C;
+    if (r.kind[unit] == 1) {
+      C = static_cast<T*>(a.L) + ((size_t)r.i * 9 + unit) * a.sL;
+    } else {
+      const int cb = r.cl[unit];
+      const int sl = win_slot(demorton_x(r.i), demorton_y(r.i), demorton_x(cb), demorton_y(cb));
+      C = static_cast<T*>(a.M) + ((size_t)r.i * 36 + sl) * a.sM;
+    }
+    for (int e = threadIdx.x; e < 64 * 64; e += WG) {
+      const int row = m0 + e % 64, col = n0 + e / 64;
+      if (row < r.ri && col < r.size[unit]) C[row + (size_t)col * a.rpad] += Xz[row + (size_t)col * a.mpad];
+    }
+  }
 }
 
 // -------------------------------------------------------------------- ADD
@@ -265,6 +399,42 @@ __global__ __launch_bounds__(WG) void k_touch_xform(const TouchXform a) {
     const int ls = win_slot(jx, jy, qx, qy);
     xform_block<T>(M + ((size_t)l * 36 + ls) * a.sM, nullptr, Tq, rl, rq, rl, rn, a.rpad, a.rpad, a.rpad, 1, Z,
                    a.rpad);
+  }
+}
+
+// grid (parent, 9 * 16 + 4): neighbour slot x child pair, then the 4 children's
+// transfer blocks.
+template <class T>
+__global__ __launch_bounds__(WG) void k_transition(const TransArgs a) {
+  const int P = blockIdx.x, y = blockIdx.y;
+  const T* src;
+  T* dst;
+  int rows, cols, lds = a.rpad;
+  if (y < 144) {
+    const int sp = y / 16, c = (y / 4) % 4, c2 = y % 4;
+    const int px = demorton_x(P), py = demorton_y(P);
+    const int qx = px + sp / 3 - 1, qy = py + sp % 3 - 1;
+    if (qx < 0 || qy < 0 || qx >= a.nside || qy >= a.nside) return;
+    const int Q = morton2(qx, qy);
+    const int ch = 4 * P + c, ch2 = 4 * Q + c2;
+    rows = a.cr[ch];
+    cols = a.cr[ch2];
+    if (rows == 0 || cols == 0) return;
+    const int sl = win_slot(demorton_x(ch), demorton_y(ch), demorton_x(ch2), demorton_y(ch2));
+    src = static_cast<const T*>(a.CM) + ((size_t)ch * 36 + sl) * a.sM;
+    dst = static_cast<T*>(a.P) + ((size_t)P * 9 + sp) * a.sP + a.choff[4 * P + c] +
+          (size_t)a.choff[4 * Q + c2] * a.npad;
+  } else {
+    const int c = y - 144, ch = 4 * P + c;
+    rows = a.cr[ch];
+    cols = a.r_par[P];
+    if (rows == 0 || cols == 0) return;
+    src = static_cast<const T*>(a.CUP) + (size_t)ch * a.sM;
+    dst = static_cast<T*>(a.U) + (size_t)P * a.sU + a.choff[4 * P + c];
+  }
+  for (int e = threadIdx.x; e < rows * cols; e += WG) {
+    const int i = e % rows, j = e / rows;
+    dst[i + (size_t)j * a.npad] = src[i + (size_t)j * lds];
   }
 }
 
@@ -626,22 +796,17 @@ __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ desc
 // only touches row j of R and the chunk rows.  Each trailing column is handled
 // by a 16-lane group (lanes over chunk rows, shuffle reductions), every group
 // forms the reflector of column j itself, so a step costs one barrier.
-template <class T>
-__global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
-                                                const BlkRef* __restrict__ blocks, int chunk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const StackQrDesc d = descs[blockIdx.x];
-  const int r = d.r;
-  if (d.R == nullptr || r == 0) return;
+template <class T, class BlockFn>
+__device__ void stackqr_body(T* lds, int r, int nblk, BlockFn block, int chunk, T* Rout, size_t ldr) {
   const int ldc = chunk + 1;
-  T* R = reinterpret_cast<T*>(smem);  // r x r, ld r
-  T* C = R + r * r;                    // chunk x r, ld chunk + 1
+  T* R = lds;          // r x r, ld r
+  T* C = R + r * r;    // chunk x r, ld chunk + 1
   const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
   constexpr int NSLOT = WG / GRP;
   for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0;
   __syncthreads();
-  for (int b = 0; b < d.nblk; ++b) {
-    const BlkRef B = blocks[d.first + b];
+  for (int b = 0; b < nblk; ++b) {
+    const BlkRef B = block(b);
     const T* Bp = static_cast<const T*>(B.p);
     for (int r0 = 0; r0 < B.rows; r0 += chunk) {
       const int cr = min(chunk, B.rows - r0);
@@ -682,13 +847,58 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
       __syncthreads();
     }
   }
-  T* Rout = static_cast<T*>(d.R);
   for (int e = threadIdx.x; e < r * r; e += WG) {
     const int i = e % r, j = e / r;
     T v = j < i ? T(0) : R[i + j * r];
     if (R[i + i * r] < 0) v = -v;
-    Rout[i + (size_t)j * d.ldr] = v;
+    Rout[i + (size_t)j * ldr] = v;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ descs,
+                                                const BlkRef* __restrict__ blocks, int chunk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const StackQrDesc d = descs[blockIdx.x];
+  if (d.R == nullptr || d.r == 0) return;
+  const BlkRef* bl = blocks + d.first;
+  stackqr_body<T>(reinterpret_cast<T*>(smem), d.r, d.nblk, [&](int b) { return bl[b]; }, chunk,
+                  static_cast<T*>(d.R), d.ldr);
+}
+
+// Far-field weight of cluster q = ids[t] with its blocks found on the device:
+// the stack of M(q, l)^T over the partners l of q's window (rows r[l]),
+// then the parent term z_t (rows r_par[q / 4], when given).  Segment s of
+// S takes window slots [36 s / S, 36 (s + 1) / S) (the last one also z_t) and
+// writes its R to out + (t * S + s) * so, or out + q * so when S == 1 and
+// out_by_id.
+template <class T>
+__global__ __launch_bounds__(WG) void k_stackqr_win(const WinStack a, int chunk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ BlkRef bl[37];
+  __shared__ int nb;
+  const int t = blockIdx.x, sg = blockIdx.y;
+  const int q = a.ids[t];
+  const int r = a.r[q];
+  if (r == 0) return;
+  if (threadIdx.x == 0) {
+    const int qx = demorton_x(q), qy = demorton_y(q);
+    int c = 0;
+    for (int sl = 36 * sg / a.S; sl < 36 * (sg + 1) / a.S; ++sl) {
+      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+      if (abs(jx - qx) <= 1 && abs(jy - qy) <= 1) continue;
+      const int l = morton2(jx, jy);
+      if (a.r[l] == 0) continue;
+      bl[c++] = BlkRef{static_cast<const T*>(a.M) + ((size_t)q * 36 + sl) * a.sM, a.rpad, a.r[l], 1};
+    }
+    if (sg == a.S - 1 && a.Z && a.r_par && a.r_par[q >> 2] > 0)
+      bl[c++] = BlkRef{static_cast<const T*>(a.Z) + (size_t)t * a.sM, a.rpad, a.r_par[q >> 2], 0};
+    nb = c;
+  }
+  __syncthreads();
+  T* out = static_cast<T*>(a.out) + (a.S == 1 && a.out_by_id ? (size_t)q : (size_t)t * a.S + sg) * a.so;
+  stackqr_body<T>(reinterpret_cast<T*>(smem), r, nb, [&](int b) { return bl[b]; }, chunk, out, a.ldo);
 }
 
 // ------------------------------------------------------- BLOCKED INVERSE
@@ -860,6 +1070,32 @@ void allow_lds(const void* fn, bool& done, size_t bytes) {
   done = true;
 }
 
+// Chunk rows of the stacked-R kernels and their LDS bytes for rank r.
+template <class T>
+size_t stackqr_lds(int max_r, int& chunk) {
+  const size_t rr = (size_t)max_r * max_r * sizeof(T);
+  const size_t row = sizeof(T) * max_r;
+  // stay within 64 KiB when a 16-row chunk fits, else use up to 150 KiB of
+  // the 160 KiB LDS of a gfx950 CU
+  const size_t budget = rr + 16 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
+  chunk = (int)((budget - rr) / row);
+  if (chunk > kMaxRank) chunk = kMaxRank;
+  if (chunk < 1) chunk = 1;
+  if (chunk > 1 && rr + (size_t)(chunk + 1) * row > budget) --chunk;
+  return rr + (size_t)(chunk + 1) * row;
+}
+
+template <class T>
+void stackqr_win_go(const WinStack& a, int max_r, hipStream_t s) {
+  int chunk;
+  const size_t lds = stackqr_lds<T>(max_r, chunk);
+  if (lds > 64 * 1024) {
+    static bool raised = false;
+    allow_lds(reinterpret_cast<const void*>(k_stackqr_win<T>), raised, 150 * 1024);
+  }
+  hipLaunchKernelGGL(k_stackqr_win<T>, dim3(a.nt, a.S), dim3(WG), lds, s, a, chunk);
+}
+
 template <class T>
 void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
   const size_t rr = (size_t)max_r * max_r * sizeof(T);
@@ -915,6 +1151,22 @@ void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scr
   else hipLaunchKernelGGL(k_xform<double>, grid, dim3(WG), 0, s, d, nd, static_cast<double*>(scratch), ld_scratch);
 }
 
+void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s) {
+  if (a.nb <= 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  const int units = step == 0 ? 1 : step == 2 ? 81 : 9;
+  const dim3 grid(a.nb, units * tm * tn);
+  if (ty) hipLaunchKernelGGL(k_elim<float>, grid, dim3(WG), 0, s, a, step, tm, tn);
+  else hipLaunchKernelGGL(k_elim<double>, grid, dim3(WG), 0, s, a, step, tm, tn);
+}
+
+void launch_transition(const TransArgs& a, int ty, hipStream_t s) {
+  if (a.nc <= 0) return;
+  const dim3 grid(a.nc, 148);
+  if (ty) hipLaunchKernelGGL(k_transition<float>, grid, dim3(WG), 0, s, a);
+  else hipLaunchKernelGGL(k_transition<double>, grid, dim3(WG), 0, s, a);
+}
+
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   if (a.nt <= 0) return;
   const dim3 grid(a.nt, 37);
@@ -961,6 +1213,12 @@ void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s) {
   if (nd <= 0) return;
   if (ty) hipLaunchKernelGGL(k_formq<float>, dim3(nd), dim3(WG), 0, s, d);
   else hipLaunchKernelGGL(k_formq<double>, dim3(nd), dim3(WG), 0, s, d);
+}
+
+void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
+  if (a.nt <= 0 || max_r <= 0) return;
+  if (ty) stackqr_win_go<float>(a, max_r, s);
+  else stackqr_win_go<double>(a, max_r, s);
 }
 
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s) {

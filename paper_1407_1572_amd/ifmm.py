@@ -47,12 +47,13 @@ class _Stats(C.Structure):
                 ("level_max_rank", C.c_int * 16), ("level_mean_rank", C.c_double * 16),
                 ("top_size", C.c_int), ("assembly_ms", C.c_double), ("factor_ms", C.c_double),
                 ("last_solve_ms", C.c_double), ("factor_bytes", C.c_double),
-                ("factor_flops", C.c_double), ("kernel_launches", C.c_int64 * 16),
-                ("kernel_ms", C.c_double * 16), ("kernel_flops", C.c_double * 16),
-                ("kernel_bytes", C.c_double * 16), ("precision", C.c_int)]
+                ("factor_flops", C.c_double), ("kernel_launches", C.c_int64 * 32),
+                ("kernel_ms", C.c_double * 32), ("kernel_flops", C.c_double * 32),
+                ("kernel_bytes", C.c_double * 32), ("precision", C.c_int)]
 
 
-KERNEL_FAMILIES = ["gemm", "add", "xform", "qr", "rrqr", "formq", "stackqr", "inverse"]
+KERNEL_FAMILIES = ["gemm", "add", "xform", "qr", "rrqr", "formq", "stackqr", "inverse", "elim",
+                   "touch_xform", "stack_win"]
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
@@ -197,10 +198,10 @@ class IFMMSolver:
                 "precision": {v: k for k, v in PRECISIONS.items()}.get(s.precision, s.precision),
                 # "<family>" computes in FP64, "<family>_f32" in FP32
                 "kernels": {name + ("_f32" if q else ""):
-                            {"launches": s.kernel_launches[i + 8 * q], "ms": s.kernel_ms[i + 8 * q],
-                             "flops": s.kernel_flops[i + 8 * q], "bytes": s.kernel_bytes[i + 8 * q]}
+                            {"launches": s.kernel_launches[i + 16 * q], "ms": s.kernel_ms[i + 16 * q],
+                             "flops": s.kernel_flops[i + 16 * q], "bytes": s.kernel_bytes[i + 16 * q]}
                             for q in (0, 1) for i, name in enumerate(KERNEL_FAMILIES)
-                            if q == 0 or s.kernel_launches[i + 8 * q] > 0}}
+                            if s.kernel_launches[i + 16 * q] > 0}}
 
     def ranks(self, level: int) -> np.ndarray:
         out = (C.c_int * (4 ** level))()
