@@ -165,7 +165,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 xform, 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse (its three pieces), 8 elim,
 // 9 touched-cluster transform, 10 window stacked R.
@@ -174,7 +174,8 @@ inline int family(int t) {
   switch (t) {
     case OP_GJPANEL:
     case OP_GJREST:
-    case OP_GJUNPERM: return 7;
+    case OP_GJUNPERM:
+    case OP_GJLDS: return 7;
     case OP_ELIM: return 8;
     case OP_TXFORM: return 9;
     case OP_WSTACK: return 10;
@@ -233,17 +234,20 @@ struct Stage {
   // operand read once and every output written once, at its storage size.
   void gemm(const std::vector<GemmDesc>& all) {
     by_type(all, [&](const std::vector<GemmDesc>& v, int ty) {
-      int mm = 0, nn = 0;
+      int mm = 0, nn = 0, plain = 1;
       double f = 0, by = 0;
       const double sa = esz(ty & 1), sb = esz(ty & 2), sc = esz(ty & 4);
       for (const auto& d : v) {
         mm = std::max(mm, d.M);
         nn = std::max(nn, d.N);
+        plain &= d.opA == 0 && d.opB == 0;
         f += 2.0 * d.M * d.N * d.K;
         by += sa * d.M * d.K + sb * (double)d.K * d.N + sc * (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N;
       }
       flops += f;
-      op({OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn, f, by}, ty);
+      Op o{OP_GEMM, push(v.data(), v.size() * sizeof(GemmDesc)), 0, (int)v.size(), mm, nn, f, by};
+      o.off2 = (size_t)plain;
+      op(o, ty);
     });
   }
   void add(const std::vector<AddDesc>& all) {
@@ -256,19 +260,6 @@ struct Stage {
         by += (double)d.M * d.N * ((d.A ? esz(ty & 1) : 0.0) + esz(ty & 2) * (d.beta != 0.0 ? 2.0 : 1.0));
       }
       op({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn, 0.0, by}, ty);
-    });
-  }
-  void xform(const std::vector<XformDesc>& all) {
-    by_type(all, [&](const std::vector<XformDesc>& v, int ty) {
-      double f = 0, by = 0;
-      for (const auto& d : v) {
-        const int rz = d.T ? d.r_new : d.r_old, cn = d.S ? d.c_new : d.c_old;
-        f += 2.0 * (d.T ? (double)d.r_new * d.r_old * d.c_old : 0) + 2.0 * (d.S ? (double)rz * d.c_old * d.c_new : 0);
-        by += esz(ty) * ((double)d.r_old * d.c_old + (d.T ? (double)d.r_new * d.r_old : 0) +
-                         (d.S ? (double)d.c_old * d.c_new : 0) + (double)rz * cn);
-      }
-      flops += f;
-      op({OP_XFORM, push(v.data(), v.size() * sizeof(XformDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
     });
   }
   void qr(const std::vector<QrDesc>& all) {
@@ -452,6 +443,19 @@ struct Stage {
     size_t o1 = push(v.data(), v.size() * sizeof(StackQrDesc));
     size_t o2 = push(b.data(), std::max<size_t>(1, b.size()) * sizeof(BlkRef));
     op({OP_STACKQR, o1, o2, (int)v.size(), rr, 0, f, by}, ty);
+  }
+  // Whole-matrix LDS Gauss-Jordan (FP64).
+  void inv_lds(const std::vector<InvDesc>& v) {
+    if (v.empty()) return;
+    int mm = 0;
+    double f = 0, by = 0;
+    for (const auto& d : v) {
+      mm = std::max(mm, d.m);
+      f += 2.0 * d.m * (double)d.m * d.m;
+      by += 16.0 * d.m * (double)d.m;
+    }
+    flops += f;
+    op({OP_GJLDS, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by}, 0);
   }
   // Blocked Gauss-Jordan inverse (FP64) of every matrix in v (panels of nb
   // columns); piv (nd x maxm ints) and tmp (nd x nb x maxm doubles) are
@@ -732,7 +736,7 @@ struct Plan final : ifmm_plan {
   double* d_top = nullptr;
   Status* d_status = nullptr;
   Arena arena;
-  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsXf, wsS1, wsS2, wsVec, wsNrm, wsSeg;
+  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsNrm, wsSeg;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
   // stats
@@ -787,14 +791,10 @@ struct Plan final : ifmm_plan {
         HIP_OK(hipEventRecord(ea, s));
       }
       switch (op.t) {
-        case OP_GEMM: launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
-        case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
-        case OP_XFORM: {
-          const int nwg = 2048;
-          double* z = wsXf.need<double>((size_t)nwg * kMaxRank * kMaxRank, s);
-          launch_xform(reinterpret_cast<XformDesc*>(d + op.off), op.count, z, nwg, kMaxRank, op.ty, s);
+        case OP_GEMM:
+          launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, op.ty, (int)op.off2, s);
           break;
-        }
+        case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
         case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_RRQR:
           if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
@@ -852,6 +852,7 @@ struct Plan final : ifmm_plan {
           launch_stackqr_win(a, op.a, op.ty, s);
           break;
         }
+        case OP_GJLDS: launch_gj_lds(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
         case OP_GJPANEL:
           launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
@@ -879,13 +880,19 @@ struct Plan final : ifmm_plan {
 
   // Inverse of the pivot blocks: blocked Gauss-Jordan.
   Buf wsInvT, wsInvP;
-  void plan_inverse(Stage& st, const std::vector<InvDesc>& v) {
-    if (v.empty()) return;
+  // Matrices that fit in LDS are inverted whole by one workgroup each; the
+  // rest by panels.
+  void plan_inverse(Stage& st, const std::vector<InvDesc>& all) {
+    if (all.empty()) return;
+    std::vector<InvDesc> small, big;
+    for (const auto& d : all) (gj_lds_bytes(d.m) <= kGjLdsBytes ? small : big).push_back(d);
+    st.inv_lds(small);
+    if (big.empty()) return;
     int mm = 0;
-    for (const auto& d : v) mm = std::max(mm, d.m);
-    double* tmp = wsInvT.need((size_t)v.size() * kInvNb * mm, s);
-    int* piv = wsInvP.need<int>((size_t)v.size() * mm + 1, s);
-    st.inv_blocked(v, piv, tmp, kInvNb);
+    for (const auto& d : big) mm = std::max(mm, d.m);
+    double* tmp = wsInvT.need((size_t)big.size() * kInvNb * mm, s);
+    int* piv = wsInvP.need<int>((size_t)big.size() * mm + 1, s);
+    st.inv_blocked(big, piv, tmp, kInvNb);
   }
 
   // ---------------------------------------------------------------- tree
@@ -1911,7 +1918,7 @@ struct Plan final : ifmm_plan {
     dfree(d_top);
     dfree(d_status);
     dfree(d_rank);
-    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsXf, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
+    for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
                    &wsNrm, &wsSeg})
       b->release();
     arena.release();

@@ -71,23 +71,6 @@ struct AddDesc {
         ty(tcode<TC>() | tcode<TC>() << 1) {}
 };
 
-// X <- T * X * S in place, X is r_old x c_old (ldx); T is r_new x r_old (ldt)
-// or null; S is c_old x c_new (lds), or its transpose when transS, or null.
-struct XformDesc {
-  void* X;
-  const void* T;
-  const void* S;
-  int r_old, c_old, r_new, c_new;
-  int ldx, ldt, lds, transS;
-  int ty;
-  XformDesc() = default;
-  template <class U>
-  __host__ XformDesc(U* x, typename nodeduce<const U*>::type t, typename nodeduce<const U*>::type s_, int ro,
-                     int co, int rn, int cn, int ldx_, int ldt_, int lds_, int ts)
-      : X(x), T(t), S(s_), r_old(ro), c_old(co), r_new(rn), c_new(cn), ldx(ldx_), ldt(ldt_), lds(lds_),
-        transS(ts), ty(tcode<U>()) {}
-};
-
 // Householder QR in place: Q (n x K, K = min(n, m)) overwrites A, R (K x m)
 // is written to R; sign-normalised so that R_jj >= 0.
 struct QrDesc {
@@ -293,11 +276,10 @@ struct Status {
 
 // ---------------------------------------------------------------- launchers
 // `ty` is the type code shared by the descriptors of the launch.
-void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
+// plain: every descriptor has opA = opB = 0 (then N <= 4 runs as batched
+// matrix-vector products).
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, int plain, hipStream_t s);
 void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
-// scratch: nwg * ld_scratch * kMaxRank elements of the descriptors' type.
-void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
-                  hipStream_t s);
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s);
 void launch_transition(const TransArgs& a, int ty, hipStream_t s);
 // The elimination steps of a colour batch (one record per eliminated
@@ -321,6 +303,11 @@ void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrStat
 void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
+// Whole-matrix FP64 Gauss-Jordan inverse in LDS for matrices with
+// gj_lds_bytes(m) <= kGjLdsBytes.
+constexpr size_t kGjLdsBytes = 159 * 1024;
+size_t gj_lds_bytes(int m);
+void launch_gj_lds(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
 // Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s);

@@ -135,6 +135,48 @@ __global__ __launch_bounds__(WG) void k_gemm(const GemmDesc* __restrict__ descs,
   gemm_tile<TA, TB, TC>(d, m0, n0);
 }
 
+// Products with few right-hand columns (N <= 4, A and B as stored): the
+// solve's matrix-vector work.  A 64-row tile per workgroup; the four waves
+// split K, each lane owns a row (coalesced column reads of A), and the
+// partial sums meet in LDS.
+constexpr int GEMV_N = 4;
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(WG) void k_gemv(const GemmDesc* __restrict__ descs) {
+  using Acc = typename std::conditional<std::is_same<TA, float>::value && std::is_same<TB, float>::value,
+                                        float, double>::type;
+  const GemmDesc d = descs[blockIdx.x];
+  const int m0 = blockIdx.y * WAVE;
+  if (d.C == nullptr || m0 >= d.M) return;
+  const TA* __restrict__ A = static_cast<const TA*>(d.A);
+  const TB* __restrict__ B = static_cast<const TB*>(d.B);
+  __shared__ Acc part[WG / WAVE][GEMV_N][WAVE];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int i = m0 + lane;
+  Acc acc[GEMV_N];
+#pragma unroll
+  for (int c = 0; c < GEMV_N; ++c) acc[c] = 0;
+  if (i < d.M) {
+    for (int k = w; k < d.K; k += WG / WAVE) {
+      const Acc a = (Acc)A[i + (size_t)k * d.lda];
+#pragma unroll
+      for (int c = 0; c < GEMV_N; ++c)
+        if (c < d.N) acc[c] = fma(a, (Acc)B[k + (size_t)c * d.ldb], acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < GEMV_N; ++c) part[w][c][lane] = acc[c];
+  __syncthreads();
+  if (w == 0 && i < d.M) {
+    TC* Cp = static_cast<TC*>(d.C);
+    for (int c = 0; c < d.N; ++c) {
+      Acc v = part[0][c][lane];
+      for (int q = 1; q < WG / WAVE; ++q) v += part[q][c][lane];
+      TC* cc = Cp + i + (size_t)c * d.ldc;
+      *cc = (TC)(d.beta == 0.0 ? (Acc)d.alpha * v : fma((Acc)d.alpha, v, (Acc)d.beta * (Acc)*cc));
+    }
+  }
+}
+
 // --------------------------------------------------------- ELIMINATION
 __device__ inline int e9_dx(int s) { return s / 3 - 1; }
 __device__ inline int e9_dy(int s) { return s % 3 - 1; }
@@ -284,55 +326,13 @@ __global__ __launch_bounds__(WG) void k_add(const AddDesc* __restrict__ descs, i
   }
 }
 
-// ------------------------------------------------------------------ XFORM
-// X <- T X S with Z = T X staged in a per-workgroup global scratch.
-template <class T>
-__global__ __launch_bounds__(WG) void k_xform(const XformDesc* __restrict__ descs, int nd, T* scratch,
-                                              int ldz) {
-  T* Z = scratch + (size_t)blockIdx.x * ldz * kMaxRank;
-  for (int di = blockIdx.x; di < nd; di += gridDim.x) {
-    const XformDesc d = descs[di];
-    if (d.X == nullptr || (d.T == nullptr && d.S == nullptr)) continue;
-    T* X = static_cast<T*>(d.X);
-    const T* Tm = static_cast<const T*>(d.T);
-    const T* Sm = static_cast<const T*>(d.S);
-    const int rz = Tm ? d.r_new : d.r_old;  // rows of Z
-    for (int e = threadIdx.x; e < rz * d.c_old; e += WG) {
-      const int i = e % rz, j = e / rz;
-      T v;
-      if (Tm) {
-        v = 0;
-        for (int k = 0; k < d.r_old; ++k) v = fma(Tm[i + (size_t)k * d.ldt], X[k + (size_t)j * d.ldx], v);
-      } else {
-        v = X[i + (size_t)j * d.ldx];
-      }
-      Z[i + (size_t)j * ldz] = v;
-    }
-    __syncthreads();
-    const int cn = Sm ? d.c_new : d.c_old;
-    for (int e = threadIdx.x; e < rz * cn; e += WG) {
-      const int i = e % rz, j = e / rz;
-      T v;
-      if (Sm) {
-        v = 0;
-        for (int k = 0; k < d.c_old; ++k) {
-          const T s = d.transS ? Sm[j + (size_t)k * d.lds] : Sm[k + (size_t)j * d.lds];
-          v = fma(Z[i + (size_t)k * ldz], s, v);
-        }
-      } else {
-        v = Z[i + (size_t)j * ldz];
-      }
-      X[i + (size_t)j * d.ldx] = v;
-    }
-    __syncthreads();
-  }
-}
-
 // X <- T X S (T: r_new x r_old or null; S: c_old x c_new, transposed when
 // transS, or null) by one workgroup, Z = T X staged in LDS (rpad x rpad).
 template <class T>
 __device__ void xform_block(T* X, const T* Tm, const T* Sm, int r_old, int c_old, int r_new, int c_new,
                             int ldx, int ldt, int lds, int transS, T* Z, int ldz) {
+  // flat element index over the block: the inner products amortise the
+  // index split, and every lane stays busy for any block height
   const int rz = Tm ? r_new : r_old;
   for (int e = threadIdx.x; e < rz * c_old; e += WG) {
     const int i = e % rz, j = e / rz;
@@ -432,10 +432,9 @@ __global__ __launch_bounds__(WG) void k_transition(const TransArgs a) {
     src = static_cast<const T*>(a.CUP) + (size_t)ch * a.sM;
     dst = static_cast<T*>(a.U) + (size_t)P * a.sU + a.choff[4 * P + c];
   }
-  for (int e = threadIdx.x; e < rows * cols; e += WG) {
-    const int i = e % rows, j = e / rows;
-    dst[i + (size_t)j * a.npad] = src[i + (size_t)j * lds];
-  }
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int j = w; j < cols; j += WG / WAVE)
+    for (int i = lane; i < rows; i += WAVE) dst[i + (size_t)j * a.npad] = src[i + (size_t)j * lds];
 }
 
 // --------------------------------------------------------------------- QR
@@ -925,10 +924,8 @@ __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ des
     A = f + m;
     lda = m;
     c0 = 0;
-    for (int e = threadIdx.x; e < m * nbe; e += WG) {
-      const int i = e % m, t = e / m;
-      A[i + t * lda] = d.A[i + (size_t)(j0 + t) * d.lda];
-    }
+    for (int t = threadIdx.x / WAVE; t < nbe; t += WG / WAVE)
+      for (int i = threadIdx.x % WAVE; i < m; i += WAVE) A[i + t * lda] = d.A[i + (size_t)(j0 + t) * d.lda];
     __syncthreads();
   } else {
     A = d.A + (size_t)j0 * d.lda;
@@ -977,19 +974,110 @@ __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ des
       rowj[c] = c == t ? inv : A[j + c * lda] * inv;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * nbe; e += WG) {
-      const int i = e % m, tc = e / m;
-      if (i == j) A[i + tc * lda] = rowj[tc];
-      else if (tc == t) A[i + tc * lda] = -fcol[i] * inv;
-      else A[i + tc * lda] -= fcol[i] * rowj[tc];
+    for (int tc = threadIdx.x / WAVE; tc < nbe; tc += WG / WAVE) {
+      double* col = A + tc * lda;
+      const double rc = rowj[tc];
+      for (int i = threadIdx.x % WAVE; i < m; i += WAVE) {
+        if (i == j) col[i] = rc;
+        else if (tc == t) col[i] = -fcol[i] * inv;
+        else col[i] = fma(-fcol[i], rc, col[i]);
+      }
     }
     __syncthreads();
   }
   if (kLds) {
-    for (int e = threadIdx.x; e < m * nbe; e += WG) {
-      const int i = e % m, t = e / m;
-      d.A[i + (size_t)(j0 + t) * d.lda] = A[i + t * lda];
+    for (int t = threadIdx.x / WAVE; t < nbe; t += WG / WAVE)
+      for (int i = threadIdx.x % WAVE; i < m; i += WAVE) d.A[i + (size_t)(j0 + t) * d.lda] = A[i + t * lda];
+  }
+  if (bad && threadIdx.x == 0 && st) {
+    if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
+  }
+}
+
+// Whole-matrix Gauss-Jordan in LDS (one 512-thread workgroup per matrix, for
+// matrices whose m (m + 1) doubles fit): per step one wave picks the pivot,
+// then rows j and p are swapped outside column j (that column is rewritten by
+// the step anyway), the pivot row is scaled and every other row eliminated.
+// The column permutation is undone while the result is written back.
+constexpr int GJ_WG = 512;
+__global__ __launch_bounds__(GJ_WG) void k_gj_lds(const InvDesc* __restrict__ descs, Status* st) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr || m == 0) return;
+  const int ld = m + 1;
+  double* A = reinterpret_cast<double*>(smem);
+  double* f = A + (size_t)m * ld;
+  double* rowj = f + m;
+  int* src = reinterpret_cast<int*>(rowj + m);
+  int* piv = src + m;
+  __shared__ int p_s;
+  __shared__ double inv_s;
+  // wave w owns columns w, w + 8, ...; its lanes run down the rows
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  constexpr int NW = GJ_WG / WAVE;
+  for (int c = w; c < m; c += NW)
+    for (int i = lane; i < m; i += WAVE) A[i + c * ld] = d.A[i + (size_t)c * d.lda];
+  __syncthreads();
+  bool bad = false;
+  for (int j = 0; j < m; ++j) {
+    if (threadIdx.x < WAVE) {  // pivot: largest |A(i, j)|, i >= j, first on ties
+      double bv = -1.0;
+      int bi = m;
+      for (int i = j + threadIdx.x; i < m; i += WAVE) {
+        const double a = fabs(A[i + j * ld]);
+        if (a > bv) { bv = a; bi = i; }
+      }
+      for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, WAVE);
+        const int oi = __shfl_xor(bi, o, WAVE);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (threadIdx.x == 0) {
+        p_s = bi;
+        piv[j] = bi;
+        inv_s = 1.0 / A[bi + j * ld];
+      }
     }
+    __syncthreads();
+    const int p = p_s;
+    const double inv = inv_s;
+    if (A[p + j * ld] == 0.0) bad = true;
+    for (int c = threadIdx.x; c < m; c += GJ_WG) {
+      if (c == j) {
+        rowj[c] = inv;
+        continue;
+      }
+      const double ap = A[p + c * ld];
+      if (p != j) A[p + c * ld] = A[j + c * ld];
+      A[j + c * ld] = ap;
+      rowj[c] = ap * inv;
+    }
+    for (int i = threadIdx.x; i < m; i += GJ_WG) f[i] = i == p ? A[j + j * ld] : A[i + j * ld];
+    __syncthreads();
+    for (int c = w; c < m; c += NW) {
+      double* col = A + c * ld;
+      if (c == j) {
+        for (int i = lane; i < m; i += WAVE) col[i] = i == j ? inv : -f[i] * inv;
+      } else {
+        const double rc = rowj[c];
+        for (int i = lane; i < m; i += WAVE) col[i] = i == j ? rc : fma(-f[i], rc, col[i]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < m; ++c) src[c] = c;
+    for (int j = m - 1; j >= 0; --j) {
+      const int t = src[j];
+      src[j] = src[piv[j]];
+      src[piv[j]] = t;
+    }
+  }
+  __syncthreads();
+  for (int c = w; c < m; c += NW) {
+    const double* col = A + src[c] * ld;
+    for (int i = lane; i < m; i += WAVE) d.A[i + (size_t)c * d.lda] = col[i];
   }
   if (bad && threadIdx.x == 0 && st) {
     if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
@@ -1045,8 +1133,9 @@ __global__ __launch_bounds__(WG) void k_gj_unpermute(const InvDesc* __restrict__
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 template <class TA, class TB, class TC>
-void gemm_go(const GemmDesc* d, int nd, int tm, int tn, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
+void gemm_go(const GemmDesc* d, int nd, int tm, int tn, int max_m, bool gemv, hipStream_t s) {
+  if (gemv) hipLaunchKernelGGL((k_gemv<TA, TB, TC>), dim3(nd, cdiv(max_m, WAVE)), dim3(WG), 0, s, d);
+  else hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
 }
 
 template <class TA, class TC>
@@ -1117,18 +1206,19 @@ void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStr
 
 }  // namespace
 
-void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s) {
+void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, int plain, hipStream_t s) {
   if (nd <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
+  const bool gemv = plain && max_n <= GEMV_N;
   switch (ty) {
-    case 0: gemm_go<double, double, double>(d, nd, tm, tn, s); break;
-    case 1: gemm_go<float, double, double>(d, nd, tm, tn, s); break;
-    case 2: gemm_go<double, float, double>(d, nd, tm, tn, s); break;
-    case 3: gemm_go<float, float, double>(d, nd, tm, tn, s); break;
-    case 4: gemm_go<double, double, float>(d, nd, tm, tn, s); break;
-    case 5: gemm_go<float, double, float>(d, nd, tm, tn, s); break;
-    case 6: gemm_go<double, float, float>(d, nd, tm, tn, s); break;
-    default: gemm_go<float, float, float>(d, nd, tm, tn, s); break;
+    case 0: gemm_go<double, double, double>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 1: gemm_go<float, double, double>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 2: gemm_go<double, float, double>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 3: gemm_go<float, float, double>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 4: gemm_go<double, double, float>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 5: gemm_go<float, double, float>(d, nd, tm, tn, max_m, gemv, s); break;
+    case 6: gemm_go<double, float, float>(d, nd, tm, tn, max_m, gemv, s); break;
+    default: gemm_go<float, float, float>(d, nd, tm, tn, max_m, gemv, s); break;
   }
 }
 
@@ -1141,14 +1231,6 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
     case 2: add_go<double, float>(d, nd, tm, tn, s); break;
     default: add_go<float, float>(d, nd, tm, tn, s); break;
   }
-}
-
-void launch_xform(const XformDesc* d, int nd, void* scratch, int nwg, int ld_scratch, int ty,
-                  hipStream_t s) {
-  if (nd <= 0) return;
-  const dim3 grid(nd < nwg ? nd : nwg);
-  if (ty) hipLaunchKernelGGL(k_xform<float>, grid, dim3(WG), 0, s, d, nd, static_cast<float*>(scratch), ld_scratch);
-  else hipLaunchKernelGGL(k_xform<double>, grid, dim3(WG), 0, s, d, nd, static_cast<double*>(scratch), ld_scratch);
 }
 
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s) {
@@ -1239,6 +1321,17 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
     hipLaunchKernelGGL(k_gj_panel<false>, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv,
                        ldp, st);
   }
+}
+
+size_t gj_lds_bytes(int m) {
+  return (size_t)m * (m + 1) * sizeof(double) + 2 * (size_t)m * sizeof(double) + 2 * (size_t)m * sizeof(int);
+}
+
+void launch_gj_lds(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0) return;
+  static bool raised = false;
+  allow_lds(reinterpret_cast<const void*>(k_gj_lds), raised, kGjLdsBytes);
+  hipLaunchKernelGGL(k_gj_lds, dim3(nd), dim3(GJ_WG), gj_lds_bytes(max_m), s, d, st);
 }
 
 void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const int* piv, int ldp,
