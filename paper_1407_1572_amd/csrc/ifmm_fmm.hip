@@ -21,10 +21,13 @@ __device__ inline void lagrange_all(int p, double s, double* out) {
   double t[kMaxP];
   for (int m = 0; m < p; ++m) t[m] = cheb_node(p, m);
   for (int m = 0; m < p; ++m) {
-    double v = 1.0;
+    double num = 1.0, den = 1.0;
     for (int k = 0; k < p; ++k)
-      if (k != m) v *= (s - t[k]) / (t[m] - t[k]);
-    out[m] = v;
+      if (k != m) {
+        num *= s - t[k];
+        den *= t[m] - t[k];
+      }
+    out[m] = num / den;
   }
 }
 
@@ -94,26 +97,56 @@ __global__ void k_m2l_table(KernelFn kf, int p, double h, double* dst) {
 
 // ---------------------------------------------------------------- FMM passes
 // Multipole/local node values are stored [cluster][rhs][p^2].
-__global__ void k_p2m(const double* __restrict__ pts, const int* __restrict__ start,
-                      const int* __restrict__ cnt, int kappa, double lox, double loy, double size,
-                      int p, const double* __restrict__ x, int ldx, int nrhs, double* W) {
+// P2M of every leaf: the Lagrange weights of a chunk of 64 points are
+// formed once (one point per lane) and staged in LDS with the point values,
+// then each lane accumulates one (node, column) coefficient over the chunk.
+constexpr int P2M_WG = 64;
+constexpr int P2M_RHS = 4;  // right-hand columns staged per pass
+__global__ __launch_bounds__(P2M_WG) void k_p2m(const double* __restrict__ pts, const int* __restrict__ start,
+                                                const int* __restrict__ cnt, int kappa, double lox, double loy,
+                                                double size, int p, const double* __restrict__ x, int ldx,
+                                                int nrhs, double* W) {
   const int i = blockIdx.x;
   const int p2 = p * p;
   const int n = cnt[i];
   double cx, cy, h;
   leaf_box(i, kappa, lox, loy, size, cx, cy, h);
-  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
-    const int m = e % p2, r = e / p2;
-    const int mx = m / p, my = m % p;
-    double acc = 0.0;
-    for (int a = 0; a < n; ++a) {
-      const int g = start[i] + a;
-      double lx[kMaxP], ly[kMaxP];
-      lagrange_all(p, (pts[2 * g] - cx) / h, lx);
-      lagrange_all(p, (pts[2 * g + 1] - cy) / h, ly);
-      acc = fma(lx[mx] * ly[my], x[g + (size_t)r * ldx], acc);
+  __shared__ double Lx[P2M_WG][kMaxP], Ly[P2M_WG][kMaxP], xs[P2M_RHS][P2M_WG];
+  for (int r0 = 0; r0 < nrhs; r0 += P2M_RHS) {
+    const int nr = min(P2M_RHS, nrhs - r0);
+    double acc[(kMaxP * kMaxP * P2M_RHS + P2M_WG - 1) / P2M_WG];
+    constexpr int NACC = (kMaxP * kMaxP * P2M_RHS + P2M_WG - 1) / P2M_WG;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
+    for (int a0 = 0; a0 < n; a0 += P2M_WG) {
+      const int a = a0 + threadIdx.x;
+      if (a < n) {
+        const int g = start[i] + a;
+        lagrange_all(p, (pts[2 * g] - cx) / h, Lx[threadIdx.x]);
+        lagrange_all(p, (pts[2 * g + 1] - cy) / h, Ly[threadIdx.x]);
+        for (int r = 0; r < nr; ++r) xs[r][threadIdx.x] = x[g + (size_t)(r0 + r) * ldx];
+      }
+      __syncthreads();
+      const int na = min(P2M_WG, n - a0);
+#pragma unroll
+      for (int q = 0; q < NACC; ++q) {
+        const int e = threadIdx.x + q * P2M_WG;
+        if (e >= p2 * nr) continue;
+        const int m = e % p2, r = e / p2;
+        const int mx = m / p, my = m % p;
+        double v = acc[q];
+        for (int b = 0; b < na; ++b) v = fma(Lx[b][mx] * Ly[b][my], xs[r][b], v);
+        acc[q] = v;
+      }
+      __syncthreads();
     }
-    W[((size_t)i * nrhs + r) * p2 + m] = acc;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+      const int e = threadIdx.x + q * P2M_WG;
+      if (e >= p2 * nr) continue;
+      const int m = e % p2, r = e / p2;
+      W[((size_t)i * nrhs + r0 + r) * p2 + m] = acc[q];
+    }
   }
 }
 
@@ -274,7 +307,7 @@ void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s) 
 void launch_p2m(const double* pts, const int* leaf_start, const int* leaf_n, int nleaf, int kappa,
                 double lox, double loy, double size, int p, const double* x, int ldx, int nrhs,
                 double* W, hipStream_t s) {
-  hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, kappa, lox, loy,
+  hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(P2M_WG), 0, s, pts, leaf_start, leaf_n, kappa, lox, loy,
                      size, p, x, ldx, nrhs, W);
 }
 

@@ -20,8 +20,9 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
-// Block-wide sum; every thread gets the result.  red must hold WG/WAVE values.
-template <class T>
+// Block-wide sum over NT threads; every thread gets the result.  red must
+// hold NT/WAVE values.
+template <class T, int NT = WG>
 __device__ inline T block_sum(T v, T* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -29,12 +30,12 @@ __device__ inline T block_sum(T v, T* red) {
   if (lane == 0) red[w] = v;
   __syncthreads();
   T t = 0;
-  for (int i = 0; i < WG / WAVE; ++i) t += red[i];
+  for (int i = 0; i < NT / WAVE; ++i) t += red[i];
   return t;
 }
 
 // Block-wide argmax of (value, index): largest value, smallest index on ties.
-template <class T>
+template <class T, int NT = WG>
 __device__ inline void block_argmax(T v, int idx, T* rv, int* ri, T& bv, int& bi) {
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     T ov = __shfl_xor(v, o, WAVE);
@@ -47,7 +48,7 @@ __device__ inline void block_argmax(T v, int idx, T* rv, int* ri, T& bv, int& bi
   __syncthreads();
   bv = rv[0];
   bi = ri[0];
-  for (int i = 1; i < WG / WAVE; ++i)
+  for (int i = 1; i < NT / WAVE; ++i)
     if (rv[i] > bv || (rv[i] == bv && ri[i] < bi)) { bv = rv[i]; bi = ri[i]; }
 }
 
@@ -514,8 +515,8 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
 // access), so a workgroup has 16 columns in flight; dot products and norms
 // reduce with shuffles inside the group.  Norms are recomputed exactly every
 // step.
-template <class T>
-__global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs) {
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RrqrDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m;
@@ -527,16 +528,16 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
   const size_t lda = n + 1;
   T* A = reinterpret_cast<T*>(smem);
   T* nrm = A + lda * m;
-  for (int e = threadIdx.x; e < n * m; e += WG) {
+  for (int e = threadIdx.x; e < n * m; e += NT) {
     const int i = e % n, c = e / n;
     A[i + c * lda] = gA[i + (size_t)c * d.lda];
   }
-  __shared__ T rv[WG / WAVE];
-  __shared__ int ri[WG / WAVE];
-  __shared__ T red[WG / WAVE];
+  __shared__ T rv[NT / WAVE];
+  __shared__ int ri[NT / WAVE];
+  __shared__ T red[NT / WAVE];
   const int rl = threadIdx.x % GRP;         // row lane inside the group
   const int slot = threadIdx.x / GRP;       // 0..15: column slot of the group
-  constexpr int NSLOT = WG / GRP;
+  constexpr int NSLOT = NT / GRP;
   __syncthreads();
   for (int c = slot; c < m; c += NSLOT) {
     const T* col = A + c * lda;
@@ -552,18 +553,18 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
   for (int j = 0; j < K; ++j) {
     T bv = -1;
     int bi = m;
-    for (int c = j + threadIdx.x; c < m; c += WG)
+    for (int c = j + threadIdx.x; c < m; c += NT)
       if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
     T piv;
     int cp;
-    block_argmax(bv, bi, rv, ri, piv, cp);
+    block_argmax<T, NT>(bv, bi, rv, ri, piv, cp);
     if (j == 0) first = piv;
     if (counting && first > 0 && (double)piv > d.eps * (double)first) rank = j + 1;
     else counting = false;
     if (!counting && d.stop_at_rank) {  // uniform: every thread holds the same pivot
       if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; }
       __syncthreads();
-      for (int e = threadIdx.x; e < n * j; e += WG) {
+      for (int e = threadIdx.x; e < n * j; e += NT) {
         const int i = e % n, c = e / n;
         gA[i + (size_t)c * d.lda] = A[i + c * lda];
       }
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
     if (cp != j) {
-      for (int i = threadIdx.x; i < n; i += WG) {
+      for (int i = threadIdx.x; i < n; i += NT) {
         const T t = A[i + j * lda];
         A[i + j * lda] = A[i + cp * lda];
         A[i + cp * lda] = t;
@@ -580,8 +581,8 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
     T part = 0;
-    for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
-    const T xn = sqrt(block_sum(part, red));
+    for (int i = j + threadIdx.x; i < n; i += NT) part = fma(A[i + j * lda], A[i + j * lda], part);
+    const T xn = sqrt(block_sum<T, NT>(part, red));
     const T x0 = A[j + j * lda];
     T alpha = 0, tau = 0, v0 = 1;
     if (xn > 0) {
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
       tau = -v0 / alpha;
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
+    for (int i = j + 1 + threadIdx.x; i < n; i += NT) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
     if (threadIdx.x == 0) { gtau[j] = tau; galpha[j] = alpha; A[j + j * lda] = alpha; }
     __syncthreads();
     const T* u = A + j * lda;
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(WG) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * K; e += WG) {
+  for (int e = threadIdx.x; e < n * K; e += NT) {
     const int i = e % n, c = e / n;
     gA[i + (size_t)c * d.lda] = A[i + c * lda];
   }
@@ -804,18 +805,30 @@ __device__ void stackqr_body(T* lds, int r, int nblk, BlockFn block, int chunk, 
   constexpr int NSLOT = WG / GRP;
   for (int e = threadIdx.x; e < r * r; e += WG) R[e] = 0;
   __syncthreads();
-  for (int b = 0; b < nblk; ++b) {
-    const BlkRef B = block(b);
-    const T* Bp = static_cast<const T*>(B.p);
-    for (int r0 = 0; r0 < B.rows; r0 += chunk) {
-      const int cr = min(chunk, B.rows - r0);
-      for (int e = threadIdx.x; e < cr * r; e += WG) {
+  // The chunk is filled with consecutive rows of the stack, across block
+  // boundaries, so each r-step Householder sweep covers up to `chunk` rows.
+  int b = 0, off = 0;
+  while (b < nblk) {
+    int cr = 0;
+    while (b < nblk && cr < chunk) {
+      const BlkRef B = block(b);
+      const T* Bp = static_cast<const T*>(B.p);
+      const int take = min(chunk - cr, B.rows - off);
+      for (int e = threadIdx.x; e < take * r; e += WG) {
         int i, j;
-        if (B.trans) { j = e % r; i = e / r; } else { i = e % cr; j = e / cr; }
-        const int gi = r0 + i;
-        C[i + j * ldc] = B.trans ? Bp[j + (size_t)gi * B.ld] : Bp[gi + (size_t)j * B.ld];
+        if (B.trans) { j = e % r; i = e / r; } else { i = e % take; j = e / take; }
+        const int gi = off + i;
+        C[cr + i + j * ldc] = B.trans ? Bp[j + (size_t)gi * B.ld] : Bp[gi + (size_t)j * B.ld];
       }
-      __syncthreads();
+      cr += take;
+      off += take;
+      if (off >= B.rows) {
+        ++b;
+        off = 0;
+      }
+    }
+    __syncthreads();
+    {
       for (int j = 0; j < r; ++j) {
         const T* cj = C + j * ldc;
         T s2 = 0;
@@ -1159,18 +1172,17 @@ void allow_lds(const void* fn, bool& done, size_t bytes) {
   done = true;
 }
 
-// Chunk rows of the stacked-R kernels and their LDS bytes for rank r.
+// Chunk rows of the stacked-R kernels and their LDS bytes for rank r: up to
+// 1024 rows, within 64 KiB when 128 rows fit there (several workgroups per
+// CU), else within 150 KiB of the 160 KiB LDS of a gfx950 CU.
 template <class T>
 size_t stackqr_lds(int max_r, int& chunk) {
   const size_t rr = (size_t)max_r * max_r * sizeof(T);
   const size_t row = sizeof(T) * max_r;
-  // stay within 64 KiB when a 16-row chunk fits, else use up to 150 KiB of
-  // the 160 KiB LDS of a gfx950 CU
-  const size_t budget = rr + 16 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
-  chunk = (int)((budget - rr) / row);
-  if (chunk > kMaxRank) chunk = kMaxRank;
+  const size_t budget = rr + 129 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
+  chunk = (int)((budget - rr) / row) - 1;
+  if (chunk > 1024) chunk = 1024;
   if (chunk < 1) chunk = 1;
-  if (chunk > 1 && rr + (size_t)(chunk + 1) * row > budget) --chunk;
   return rr + (size_t)(chunk + 1) * row;
 }
 
@@ -1187,16 +1199,8 @@ void stackqr_win_go(const WinStack& a, int max_r, hipStream_t s) {
 
 template <class T>
 void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
-  const size_t rr = (size_t)max_r * max_r * sizeof(T);
-  const size_t row = sizeof(T) * max_r;
-  // stay within 64 KiB when a 16-row chunk fits, else use up to 150 KiB of
-  // the 160 KiB LDS of a gfx950 CU
-  const size_t budget = rr + 16 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
-  int chunk = (int)((budget - rr) / row);
-  if (chunk > kMaxRank) chunk = kMaxRank;
-  if (chunk < 1) chunk = 1;
-  if (chunk > 1 && rr + (size_t)(chunk + 1) * row > budget) --chunk;
-  const size_t lds = rr + (size_t)(chunk + 1) * row;
+  int chunk;
+  const size_t lds = stackqr_lds<T>(max_r, chunk);
   if (lds > 64 * 1024) {
     static bool raised = false;
     allow_lds(reinterpret_cast<const void*>(k_stackqr<T>), raised, 150 * 1024);
@@ -1270,16 +1274,19 @@ void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s) {
   else hipLaunchKernelGGL(k_qr<double>, dim3(nd), dim3(WG), 0, s, d);
 }
 
+// The LDS pivoted QR runs 1024 threads per matrix: a staged matrix takes
+// most of a CU's LDS, so the CU's parallelism has to come from one workgroup.
+constexpr int RRQR_NT = 1024;
 void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s) {
   if (nd <= 0) return;
   if (ty) {
     static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<float>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL(k_rrqr<float>, dim3(nd), dim3(WG), lds, s, d);
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT>), dim3(nd), dim3(RRQR_NT), lds, s, d);
   } else {
     static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<double>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL(k_rrqr<double>, dim3(nd), dim3(WG), lds, s, d);
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT>), dim3(nd), dim3(RRQR_NT), lds, s, d);
   }
 }
 
