@@ -35,10 +35,12 @@ WORKLOAD = ("1,048,576 uniform points in [0,1]^2, exp(-r/0.1) + 1e-2 I, leaf 64,
 SINGLE_KERNEL = {
     "fp64": {"gemm": "k_gemm<double, double, double>", "add": "k_add<double, double>",
              "formq": "k_formq<double>", "stackqr": "k_stackqr<double>", "elim": "k_elim<double>",
-             "touch_xform": "k_touch_xform<double>", "stack_win": "k_stackqr_win<double>"},
+             "touch_xform": "k_touch_xform<double>", "stack_win": "k_stackqr_win<double>",
+             "solve": "k_solve<double>"},
     "fp32": {"gemm_f32": "k_gemm<float, float, float>", "qr_f32": "k_qr<float>",
              "formq_f32": "k_formq<float>", "stackqr_f32": "k_stackqr<float>", "elim_f32": "k_elim<float>",
-             "touch_xform_f32": "k_touch_xform<float>", "stack_win_f32": "k_stackqr_win<float>"},
+             "touch_xform_f32": "k_touch_xform<float>", "stack_win_f32": "k_stackqr_win<float>",
+             "solve_f32": "k_solve<float>"},
 }
 
 

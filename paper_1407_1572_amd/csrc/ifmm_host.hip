@@ -165,10 +165,10 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS };
-// Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 xform, 3 qr,
-// 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse (its three pieces), 8 elim,
-// 9 touched-cluster transform, 10 window stacked R.
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS, OP_SOLVE };
+// Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
+// 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 elim, 9 touched-cluster
+// transform, 10 window stacked R, 11 solve sweeps.
 constexpr int kOpTypes = 16;
 inline int family(int t) {
   switch (t) {
@@ -180,6 +180,7 @@ inline int family(int t) {
     case OP_TXFORM: return 9;
     case OP_WSTACK: return 10;
     case OP_TRANS: return 1;
+    case OP_SOLVE: return 11;
     default: return t;
   }
 }
@@ -276,10 +277,8 @@ struct Stage {
     });
   }
   // Pivoted QRs: matrices that fit in LDS go to the LDS kernel (b = 1); the
-  // rest run the multi-workgroup version (b = 0) with per-matrix norms in
-  // nrm_ws (sum of m doubles).
-  void rrqr(const std::vector<RrqrDesc>& all, double* nrm_ws) {
-    size_t nrm_off = 0;
+  // rest are worked on in place (b = 0).
+  void rrqr(const std::vector<RrqrDesc>& all) {
     by_type(all, [&](const std::vector<RrqrDesc>& byt, int ty) {
       const size_t es = ty ? sizeof(float) : sizeof(double);
       std::vector<RrqrDesc> grp[2];
@@ -290,32 +289,19 @@ struct Stage {
       for (int g = 0; g < 2; ++g) {
         const auto& v = grp[g];
         if (v.empty()) continue;
-        int mm = 0, kk = 0;
+        int mm = 0;
         size_t lds = 0;
         double f = 0, by = 0;
         for (const auto& d : v) {
           mm = std::max(mm, d.m);
           lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
           const int K = std::min(std::min(d.n, d.m), d.kmax);
-          kk = std::max(kk, K);
           for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
           by += 2.0 * es * d.n * (double)d.m;
         }
         flops += f;
         const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
-        if (g == 1) {
-          op({OP_RRQR, o, (size_t)lds, (int)v.size(), mm, 1, f, by}, ty);
-        } else {
-          std::vector<RrqrState> st(v.size());
-          for (size_t i = 0; i < v.size(); ++i) {
-            st[i] = RrqrState{nrm_ws + nrm_off, 0.0, 0, 1, 0, 0};
-            nrm_off += v[i].m;
-          }
-          const size_t o2 = push(st.data(), st.size() * sizeof(RrqrState));
-          Op x{OP_RRQR, o, o2, (int)v.size(), mm, 0, f, by};
-          x.off2b = (size_t)kk;
-          op(x, ty);
-        }
+        op({OP_RRQR, o, g == 1 ? (size_t)lds : 0, (int)v.size(), mm, g, f, by}, ty);
       }
     });
   }
@@ -422,6 +408,13 @@ struct Stage {
     a.cr = arr(&cr);
     a.r_par = arr(&r_par);
     op({OP_TRANS, push(&a, sizeof(a)), 0, a.nc, 0, 0, 0.0, by}, tcode<T>());
+  }
+  // One colour batch of the solve (dir 0 forward, 1 backward); bytes: the
+  // blocks read once plus the vectors.
+  template <class T>
+  void solve(const SolveArgs& a, int step, double* wk, int max_rows, double f, double by) {
+    if (a.nb <= 0) return;
+    op({OP_SOLVE, push(&a, sizeof(a)), (size_t)(uintptr_t)wk, step, max_rows, 0, f, by}, tcode<T>());
   }
   // All blocks of a stack have the type of its R.
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
@@ -730,13 +723,16 @@ struct Plan final : ifmm_plan {
   std::vector<double*> d_table;
   std::vector<Level<T>> lv;
   std::vector<std::vector<std::vector<Elim>>> plan;  // [k][colour] eliminations in order
+  std::vector<std::vector<std::vector<ElimRec>>> erec;  // their records, kept for the solve
+  ElimRec* d_erec = nullptr;                          // all records on the device
+  std::vector<std::vector<size_t>> erec_off;          // [k][colour] offset into d_erec
   // top
   std::vector<int> top_ids, top_off;
   int top_m = 0;
   double* d_top = nullptr;
   Status* d_status = nullptr;
   Arena arena;
-  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsNrm, wsSeg;
+  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
   // stats
@@ -798,9 +794,7 @@ struct Plan final : ifmm_plan {
         case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_RRQR:
           if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
-          else
-            launch_rrqr_multi(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2b,
-                              reinterpret_cast<RrqrState*>(d + op.off2), op.ty, s);
+          else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.ty, s);
           break;
         case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_STACKQR:
@@ -819,6 +813,12 @@ struct Plan final : ifmm_plan {
           rebase(a.r_new);
           rebase(a.r_par);
           launch_touch_xform(a, op.ty, s);
+          break;
+        }
+        case OP_SOLVE: {
+          SolveArgs a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          launch_solve(a, op.count, reinterpret_cast<double*>(op.off2), op.a, op.ty, s);
           break;
         }
         case OP_TRANS: {
@@ -1227,6 +1227,7 @@ struct Plan final : ifmm_plan {
   void factor() {
     const double t0 = now_ms();
     plan.assign(kappa + 1, std::vector<std::vector<Elim>>(9));
+    erec.assign(kappa + 1, std::vector<std::vector<ElimRec>>(9));
     for (int k = kappa; k >= 2; --k) {
       for (int c = 0; c < 9; ++c) phase(k, c);
       Level<T>& L = lv[k];
@@ -1234,6 +1235,16 @@ struct Plan final : ifmm_plan {
       if (k > 2) transition(k);
     }
     top();
+    // the records drive the solve sweeps
+    erec_off.assign(kappa + 1, std::vector<size_t>(9, 0));
+    std::vector<ElimRec> all;
+    for (int k = 2; k <= kappa; ++k)
+      for (int c = 0; c < 9; ++c) {
+        erec_off[k][c] = all.size();
+        all.insert(all.end(), erec[k][c].begin(), erec[k][c].end());
+      }
+    d_erec = dalloc<ElimRec>(all.size());
+    HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * all.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
     resolve_profile();
     Status hs{};
@@ -1346,6 +1357,7 @@ struct Plan final : ifmm_plan {
       for (int sa = 0; sa < 9; ++sa)
         for (int sb = 0; sb < 9; ++sb) a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
       const size_t ro = st.push(recs.data(), recs.size() * sizeof(ElimRec)) + 1;
+      erec[k][c] = recs;
       double bd = 0;
       std::vector<InvDesc> inv;
       for (const Elim& e : E) {
@@ -1430,9 +1442,7 @@ struct Plan final : ifmm_plan {
       }
       st.gemm(g);
       st.add(a);
-      size_t msum = 0;
-      for (const auto& d : rq) msum += d.m;
-      st.rrqr(rq, wsNrm.need(msum + 1, s));
+      st.rrqr(rq);
       run(st);
       HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
@@ -1624,23 +1634,61 @@ struct Plan final : ifmm_plan {
       oc[k] = tot;
       tot += (size_t)2 * L.nc * rpad * nrhs;
     }
-    int nbmax = 0, mmax = 0;
+    size_t wsz = 0;
     for (int k = 2; k <= kappa; ++k)
-      for (int c = 0; c < 9; ++c) {
-        nbmax = std::max(nbmax, (int)plan[k][c].size());
-        mmax = std::max(mmax, lv[k].mpad);
-      }
-    const size_t wsz = (size_t)nbmax * mmax * nrhs;
-    double* base = wsS1.need<double>(tot + 2 * wsz + 2 * (size_t)std::max(top_m, 1) * nrhs, s);
-    double* wv = base + tot;
-    double* rv = wv + wsz;
-    double* tv = rv + wsz;
+      for (int c = 0; c < 9; ++c) wsz = std::max(wsz, plan[k][c].size() * lv[k].mpad);
+    double* base = wsS1.need<double>(tot + 2 * (size_t)std::max(top_m, 1) * nrhs + wsz * nrhs, s);
+    double* tv = base + tot;
+    double* wk = tv + 2 * (size_t)std::max(top_m, 1) * nrhs;
     auto bvec = [&](int k, int i) { return base + ob[k] + (size_t)i * lv[k].npad * nrhs; };
-    auto snap = [&](int k, int i) { return base + ob[k] + ((size_t)lv[k].nc + i) * lv[k].npad * nrhs; };
     auto xvec = [&](int k, int i) { return base + ob[k] + ((size_t)2 * lv[k].nc + i) * lv[k].npad * nrhs; };
     auto cvec = [&](int k, int i) { return base + oc[k] + (size_t)i * rpad * nrhs; };
     auto yvec = [&](int k, int i) { return base + oc[k] + ((size_t)lv[k].nc + i) * rpad * nrhs; };
     HIP_OK(hipMemsetAsync(base, 0, sizeof(double) * tot, s));
+    auto args = [&](int k, int c) {
+      const Level<T>& L = lv[k];
+      SolveArgs a{};
+      a.rec = d_erec + erec_off[k][c];
+      a.P = L.P;
+      a.Qm = L.Qm;
+      a.L = L.L;
+      a.Dinv = L.Dinv;
+      a.bv = base + ob[k];
+      a.cv = base + oc[k];
+      a.sP = L.sP;
+      a.sQ = L.sQ;
+      a.sL = L.sL;
+      a.sD = L.sD;
+      a.nb = (int)plan[k][c].size();
+      a.nc = L.nc;
+      a.npad = L.npad;
+      a.rpad = rpad;
+      a.mpad = L.mpad;
+      a.nrhs = nrhs;
+      return a;
+    };
+    // algorithmic work of one step: every block it reads once, vectors read
+    // and written once; max_rows: largest row count of the step
+    auto work = [&](int k, int c, int step, double& f, double& by, int& rows) {
+      f = by = 0;
+      rows = 0;
+      for (const Elim& e : plan[k][c]) {
+        if (step == 0 || step == 3) {
+          const double kk = step == 0 ? e.ni : e.m, rr = step == 0 ? e.m : e.ni;
+          f += 2.0 * rr * kk * nrhs;
+          by += 8.0 * rr * kk + 8.0 * nrhs * (kk + rr);
+          rows = std::max(rows, (int)rr);
+          continue;
+        }
+        rows = std::max(rows, step == 1 ? e.ri : e.m);
+        for (int sp = 0; sp < 9; ++sp)
+          if (sp != 4 && e.u[sp].kind) {
+            f += 2.0 * e.u[sp].size * e.ni * nrhs;
+            by += sizeof(T) * (double)e.u[sp].size * e.ni + 8.0 * nrhs * (e.u[sp].size + e.ni);
+            if (step == 1) rows = std::max(rows, e.u[sp].size);
+          }
+      }
+    };
     Stage st;
     {
       std::vector<AddDesc> a;
@@ -1648,35 +1696,17 @@ struct Plan final : ifmm_plan {
       for (int i = 0; i < Lf.nc; ++i)
         if (Lf.n[i]) a.push_back({bt + leaf_start[i], bvec(kappa, i), Lf.n[i], nrhs, (int)N, Lf.npad, 0, 1.0, 0.0});
       st.add(a);
-      run(st);
     }
     for (int k = kappa; k >= 2; --k) {
       const Level<T>& L = lv[k];
       for (int c = 0; c < 9; ++c) {
-        const std::vector<Elim>& E = plan[k][c];
-        if (E.empty()) continue;
-        std::vector<AddDesc> a1, a2;
-        std::vector<GemmDesc> g1, g2;
-        for (int b = 0; b < (int)E.size(); ++b) {
-          const Elim& e = E[b];
-          double* w = wv + (size_t)b * L.mpad * nrhs;
-          a1.push_back({bvec(k, e.i), snap(k, e.i), e.ni, nrhs, L.npad, L.npad, 0, 1.0, 0.0});
-          g1.push_back({L.Db(e.i), bvec(k, e.i), w, e.m, nrhs, e.ni, L.mpad, L.npad, L.mpad, 0, 0, 1.0, 0.0});
-          for (int sp = 0; sp < 9; ++sp) {
-            const UnitH& u = e.u[sp];
-            if (!u.kind || sp == 4) continue;
-            if (u.kind == 1)
-              g2.push_back({L.Pb(u.cl, 8 - sp), w, bvec(k, u.cl), u.size, nrhs, e.ni, L.npad, L.mpad, L.npad, 0, 0, -1.0, 1.0});
-            else
-              g2.push_back({L.Lb(u.cl, 8 - sp), w, cvec(k, u.cl), u.size, nrhs, e.ni, rpad, L.mpad, rpad, 0, 0, -1.0, 1.0});
-          }
-          a2.push_back({w + e.ni, cvec(k, e.i), e.ri, nrhs, L.mpad, rpad, 0, 1.0, 1.0});
+        if (plan[k][c].empty()) continue;
+        for (int step = 0; step < 2; ++step) {
+          double f, by;
+          int rows;
+          work(k, c, step, f, by, rows);
+          st.solve<T>(args(k, c), step, wk, rows, f, by);
         }
-        st.add(a1);
-        st.gemm(g1);
-        st.gemm(g2);
-        st.add(a2);
-        run(st);
       }
       if (k > 2) {
         const Level<T>& Lp = lv[k - 1];
@@ -1687,7 +1717,6 @@ struct Plan final : ifmm_plan {
             if (L.r[ch]) a.push_back({cvec(k, ch), bvec(k - 1, P) + Lp.choff[(size_t)P * 4 + c], L.r[ch], nrhs, rpad, Lp.npad, 0, 1.0, 0.0});
           }
         st.add(a);
-        run(st);
       }
     }
     if (top_m > 0) {
@@ -1700,44 +1729,17 @@ struct Plan final : ifmm_plan {
       for (size_t x = 0; x < top_ids.size(); ++x)
         a2.push_back({yt + top_off[x], yvec(2, top_ids[x]), lv[2].r[top_ids[x]], nrhs, top_m, rpad, 0, 1.0, 0.0});
       st.add(a2);
-      run(st);
     }
     for (int k = 2; k <= kappa; ++k) {
       const Level<T>& L = lv[k];
       for (int c = 8; c >= 0; --c) {
-        const std::vector<Elim>& E = plan[k][c];
-        if (E.empty()) continue;
-        std::vector<AddDesc> a;
-        for (int b = 0; b < (int)E.size(); ++b) {
-          const Elim& e = E[b];
-          double* r = rv + (size_t)b * L.mpad * nrhs;
-          a.push_back({snap(k, e.i), r, e.ni, nrhs, L.npad, L.mpad, 0, 1.0, 0.0});
-          a.push_back({yvec(k, e.i), r + e.ni, e.ri, nrhs, rpad, L.mpad, 0, 1.0, 0.0});
+        if (plan[k][c].empty()) continue;
+        for (int step = 2; step < 4; ++step) {
+          double f, by;
+          int rows;
+          work(k, c, step, f, by, rows);
+          st.solve<T>(args(k, c), step, wk, rows, f, by);
         }
-        st.add(a);
-        for (int sp = 0; sp < 9; ++sp) {
-          if (sp == 4) continue;
-          std::vector<GemmDesc> g;
-          for (int b = 0; b < (int)E.size(); ++b) {
-            const Elim& e = E[b];
-            const UnitH& u = e.u[sp];
-            if (!u.kind) continue;
-            double* r = rv + (size_t)b * L.mpad * nrhs;
-            if (u.kind == 1)
-              g.push_back({L.Pb(e.i, sp), xvec(k, u.cl), r, e.ni, nrhs, u.size, L.npad, L.npad, L.mpad, 0, 0, -1.0, 1.0});
-            else
-              g.push_back({L.Qb(e.i, sp), yvec(k, u.cl), r, e.ni, nrhs, u.size, L.npad, rpad, L.mpad, 0, 0, -1.0, 1.0});
-          }
-          st.gemm(g);
-        }
-        std::vector<GemmDesc> gx;
-        for (int b = 0; b < (int)E.size(); ++b) {
-          const Elim& e = E[b];
-          gx.push_back({L.Db(e.i), rv + (size_t)b * L.mpad * nrhs, xvec(k, e.i), e.ni, nrhs, e.m, L.mpad, L.mpad,
-                        L.npad, 0, 0, 1.0, 0.0});
-        }
-        st.gemm(gx);
-        run(st);
       }
       if (k < kappa) {
         const Level<T>& Lc = lv[k + 1];
@@ -1748,7 +1750,6 @@ struct Plan final : ifmm_plan {
             if (Lc.r[ch]) a.push_back({xvec(k, P) + L.choff[(size_t)P * 4 + c], yvec(k + 1, ch), Lc.r[ch], nrhs, L.npad, rpad, 0, 1.0, 0.0});
           }
         st.add(a);
-        run(st);
       }
     }
     std::vector<AddDesc> a;
@@ -1756,6 +1757,7 @@ struct Plan final : ifmm_plan {
     for (int i = 0; i < Lf.nc; ++i)
       if (Lf.n[i]) a.push_back({xvec(kappa, i), xt + leaf_start[i], Lf.n[i], nrhs, Lf.npad, (int)N, 0, 1.0, 0.0});
     st.add(a);
+    st.flops = 0.0;  // solve work is not factorisation work
     run(st);
   }
 
@@ -1916,10 +1918,11 @@ struct Plan final : ifmm_plan {
     dfree(d_diag);
     dfree(d_E);
     dfree(d_top);
+    dfree(d_erec);
     dfree(d_status);
     dfree(d_rank);
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
-                   &wsNrm, &wsSeg})
+                   &wsSeg})
       b->release();
     arena.release();
     for (const Pending& p : pend) {

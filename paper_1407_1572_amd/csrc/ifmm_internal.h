@@ -107,13 +107,6 @@ struct RrqrDesc {
         eps(eps_), stop_at_rank(stop), ty(tcode<U>()) {}
 };
 
-// Per-matrix state of the multi-workgroup pivoted QR (nrm: m doubles).
-struct RrqrState {
-  double* nrm;
-  double first;
-  int rank, counting, done, apply;
-};
-
 // Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with
 // column j negated where alpha[j] < 0.
 struct FormQDesc {
@@ -231,6 +224,29 @@ struct TransArgs {
   int npad, rpad, nside, nc;
 };
 
+// One colour batch of Algorithm 2 with the elimination records of the
+// factorisation.  Vectors (FP64, nrhs columns) of level k, per cluster j:
+// b_j = bv + j sv, the snapshot of b_j taken at elimination bv + (nc + j) sv,
+// x_j = bv + (2 nc + j) sv (sv = npad nrhs, ld npad); c_j = cv + j svc and
+// y_j = cv + (nc + j) svc (svc = rpad nrhs, ld rpad).
+//  forward:  snapshot b_i; w = D_i^-1 [b_i; 0]; b_q -= P_qi w^x (uneliminated
+//            neighbours), c_p -= L_pi w^x (eliminated ones); c_i += w^z;
+//  backward: r = [snapshot_i - sum_q P_iq x_q - sum_p Q_ip y_p; y_i];
+//            x_i = (D_i^-1 r)^x.
+// Same-colour clusters have disjoint neighbourhoods, so no two records of a
+// batch write the same vector.
+struct SolveArgs {
+  const ElimRec* rec;
+  const void* P;
+  const void* Qm;
+  const void* L;
+  const double* Dinv;
+  double* bv;
+  double* cv;
+  size_t sP, sQ, sL, sD;
+  int nb, nc, npad, rpad, mpad, nrhs;
+};
+
 // Inverse of a square FP64 matrix in place (Gauss-Jordan, partial pivoting).
 struct InvDesc {
   double* A;
@@ -282,6 +298,9 @@ void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, int pl
 void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s);
 void launch_transition(const TransArgs& a, int ty, hipStream_t s);
+// Step 0..3 of a colour batch (0, 1: forward; 2, 3: backward); wk holds
+// mpad x nrhs doubles per record; max_rows bounds the rows of the step.
+void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty, hipStream_t s);
 // The elimination steps of a colour batch (one record per eliminated
 // cluster, geometry resolved on the device):
 //   0 build the pivot blocks D = [[P_ii, U_i], [U_i^T, 0]] (FP64);
@@ -296,10 +315,9 @@ void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
 // must fit in `lds` <= kRrqrLdsBytes.
 constexpr size_t kRrqrLdsBytes = 150 * 1024;
 void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
-// Same arithmetic with every step split in a pivot launch and a column-tiled
-// update launch (many workgroups per matrix); max_k = largest step count.
-void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st, int ty,
-                       hipStream_t s);
+// Same arithmetic on the matrix in place (one workgroup per matrix, the
+// matrix L2-resident, column norms in LDS): max_m columns at most.
+void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s);
 void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);

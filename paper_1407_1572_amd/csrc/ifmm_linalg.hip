@@ -438,6 +438,128 @@ __global__ __launch_bounds__(WG) void k_transition(const TransArgs a) {
     for (int i = lane; i < rows; i += WAVE) dst[i + (size_t)j * a.npad] = src[i + (size_t)j * lds];
 }
 
+// ------------------------------------------------------------------ SOLVE
+// Four launches per colour batch, each over (record, [unit,] 64-row tile):
+//   step 0: w = D_i^-1 [b_i; 0] into the work vector, b_i snapshotted;
+//   step 1: unit u != 4: b_q -= P_qi w^x or c_p -= L_pi w^x; unit 4:
+//           c_i += w^z;
+//   step 2: r = [snapshot_i - sum_u A_u v_u; y_i] into the work vector;
+//   step 3: x_i = (D_i^-1 r)^x.
+// Right-hand columns in groups of 4; the waves split the inner dimension
+// and meet in LDS.  wk: per record mpad x nrhs doubles.
+constexpr int SV_C = 4;
+
+// sum_k A(row, k) X(k, c) for this lane's row, the waves splitting k;
+// returns the full sums to wave 0 (acc valid there only).
+template <class TA, class XFn>
+__device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, bool live, int K, XFn X, int nc,
+                                double* part, double* acc) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  constexpr int NW = WG / WAVE;
+#pragma unroll
+  for (int c = 0; c < SV_C; ++c) acc[c] = 0.0;
+  if (live)
+    for (int k = w; k < K; k += NW) {
+      const double av = (double)A[row + (size_t)k * lda];
+#pragma unroll
+      for (int c = 0; c < SV_C; ++c)
+        if (c < nc) acc[c] = fma(av, X(k, c), acc[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < SV_C; ++c) part[(w * SV_C + c) * WAVE + lane] = acc[c];
+  __syncthreads();
+  if (w == 0)
+#pragma unroll
+    for (int c = 0; c < SV_C; ++c) {
+      double v = part[c * WAVE + lane];
+      for (int q = 1; q < NW; ++q) v += part[(q * SV_C + c) * WAVE + lane];
+      acc[c] = v;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, double* __restrict__ wk, int tiles) {
+  __shared__ double part[(WG / WAVE) * SV_C * WAVE];
+  const int b = blockIdx.x;
+  const ElimRec& r = a.rec[b];
+  const int unit = blockIdx.y / tiles, tile = blockIdx.y % tiles;
+  const int ni = r.ni, ri = r.ri, m = r.m;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int row = tile * WAVE + lane;
+  const size_t sv = (size_t)a.npad * a.nrhs, svc = (size_t)a.rpad * a.nrhs;
+  double* wb = wk + (size_t)b * a.mpad * a.nrhs;  // ld mpad
+  const double* D = a.Dinv + (size_t)r.i * a.sD;
+  double* snap = a.bv + ((size_t)a.nc + r.i) * sv;
+  double acc[SV_C];
+  for (int c0 = 0; c0 < a.nrhs; c0 += SV_C) {
+    const int nc = min(SV_C, a.nrhs - c0);
+    if (step == 0) {
+      if (tile * WAVE >= m) return;
+      const double* bi = a.bv + (size_t)r.i * sv + (size_t)c0 * a.npad;
+      tile_dot<double>(D, a.mpad, row, row < m, ni, [&](int k, int c) { return bi[k + (size_t)c * a.npad]; }, nc,
+                       part, acc);
+      if (w == 0 && row < m)
+        for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = acc[c];
+      if (tile == 0 && w == 1)
+        for (int k = lane; k < ni; k += WAVE)
+          for (int c = 0; c < nc; ++c) snap[k + (size_t)(c0 + c) * a.npad] = bi[k + (size_t)c * a.npad];
+    } else if (step == 1) {
+      if (!r.kind[unit]) return;
+      if (unit == 4) {
+        if (tile * WAVE >= ri) return;
+        double* ci = a.cv + (size_t)r.i * svc + (size_t)c0 * a.rpad;
+        if (w == 0 && row < ri)
+          for (int c = 0; c < nc; ++c) ci[row + (size_t)c * a.rpad] += wb[ni + row + (size_t)(c0 + c) * a.mpad];
+        continue;
+      }
+      const int cl = r.cl[unit], sz = r.size[unit];
+      if (tile * WAVE >= sz) return;
+      const bool part1 = r.kind[unit] == 1;
+      const T* A = part1 ? static_cast<const T*>(a.P) + ((size_t)cl * 9 + (8 - unit)) * a.sP
+                         : static_cast<const T*>(a.L) + ((size_t)cl * 9 + (8 - unit)) * a.sL;
+      const int ld = part1 ? a.npad : a.rpad;
+      tile_dot<T>(A, ld, row, row < sz, ni, [&](int k, int c) { return wb[k + (size_t)(c0 + c) * a.mpad]; }, nc,
+                  part, acc);
+      double* tg = part1 ? a.bv + (size_t)cl * sv + (size_t)c0 * a.npad : a.cv + (size_t)cl * svc + (size_t)c0 * a.rpad;
+      if (w == 0 && row < sz)
+        for (int c = 0; c < nc; ++c) tg[row + (size_t)c * ld] -= acc[c];
+    } else if (step == 2) {
+      if (tile * WAVE >= m) return;
+      if (w == 0 && row >= ni && row < m) {  // rows ni .. m-1: y_i
+        const double* yi = a.cv + ((size_t)a.nc + r.i) * svc + (size_t)c0 * a.rpad;
+        for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = yi[row - ni + (size_t)c * a.rpad];
+      }
+      if (tile * WAVE >= ni) continue;
+      double tot[SV_C] = {0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < 9; ++u) {
+        if (u == 4 || !r.kind[u]) continue;
+        const int cl = r.cl[u], sz = r.size[u];
+        const bool part1 = r.kind[u] == 1;
+        const double* src = part1 ? a.bv + ((size_t)2 * a.nc + cl) * sv + (size_t)c0 * a.npad
+                                  : a.cv + ((size_t)a.nc + cl) * svc + (size_t)c0 * a.rpad;
+        const int lds = part1 ? a.npad : a.rpad;
+        const T* A = part1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
+                           : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
+        tile_dot<T>(A, a.npad, row, row < ni, sz, [&](int k, int c) { return src[k + (size_t)c * lds]; }, nc, part,
+                    acc);
+        if (w == 0)
+          for (int c = 0; c < SV_C; ++c) tot[c] += acc[c];
+        __syncthreads();
+      }
+      if (w == 0 && row < ni)
+        for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = snap[row + (size_t)(c0 + c) * a.npad] - tot[c];
+    } else {
+      if (tile * WAVE >= ni) return;
+      tile_dot<double>(D, a.mpad, row, row < ni, m, [&](int k, int c) { return wb[k + (size_t)(c0 + c) * a.mpad]; },
+                       nc, part, acc);
+      double* xi = a.bv + ((size_t)2 * a.nc + r.i) * sv + (size_t)c0 * a.npad;
+      if (w == 0 && row < ni)
+        for (int c = 0; c < nc; ++c) xi[row + (size_t)c * a.npad] = acc[c];
+    }
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------------- QR
 template <class T>
 __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
@@ -515,7 +637,7 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
 // access), so a workgroup has 16 columns in flight; dot products and norms
 // reduce with shuffles inside the group.  Norms are recomputed exactly every
 // step.
-template <class T, int NT>
+template <class T, int NT, bool kLds>
 __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RrqrDesc d = descs[blockIdx.x];
@@ -525,13 +647,16 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
   T* gA = static_cast<T*>(d.A);
   T* gtau = static_cast<T*>(d.tau);
   T* galpha = static_cast<T*>(d.alpha);
-  const size_t lda = n + 1;
-  T* A = reinterpret_cast<T*>(smem);
-  T* nrm = A + lda * m;
-  for (int e = threadIdx.x; e < n * m; e += NT) {
-    const int i = e % n, c = e / n;
-    A[i + c * lda] = gA[i + (size_t)c * d.lda];
-  }
+  // staged in LDS (stride n + 1), or worked on in place (L2-resident) with
+  // only the column norms in LDS
+  const size_t lda = kLds ? (size_t)n + 1 : (size_t)d.lda;
+  T* A = kLds ? reinterpret_cast<T*>(smem) : gA;
+  T* nrm = kLds ? A + lda * m : reinterpret_cast<T*>(smem);
+  if (kLds)
+    for (int e = threadIdx.x; e < n * m; e += NT) {
+      const int i = e % n, c = e / n;
+      A[i + c * lda] = gA[i + (size_t)c * d.lda];
+    }
   __shared__ T rv[NT / WAVE];
   __shared__ int ri[NT / WAVE];
   __shared__ T red[NT / WAVE];
@@ -564,10 +689,11 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
     if (!counting && d.stop_at_rank) {  // uniform: every thread holds the same pivot
       if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; }
       __syncthreads();
-      for (int e = threadIdx.x; e < n * j; e += NT) {
-        const int i = e % n, c = e / n;
-        gA[i + (size_t)c * d.lda] = A[i + c * lda];
-      }
+      if (kLds)
+        for (int e = threadIdx.x; e < n * j; e += NT) {
+          const int i = e % n, c = e / n;
+          gA[i + (size_t)c * d.lda] = A[i + c * lda];
+        }
       return;
     }
     __syncthreads();
@@ -615,145 +741,12 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * K; e += NT) {
-    const int i = e % n, c = e / n;
-    gA[i + (size_t)c * d.lda] = A[i + c * lda];
-  }
+  if (kLds)
+    for (int e = threadIdx.x; e < n * K; e += NT) {
+      const int i = e % n, c = e / n;
+      gA[i + (size_t)c * d.lda] = A[i + c * lda];
+    }
   if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
-}
-
-// ------------------------------------------------ multi-workgroup RRQR
-// For large matrices (few per launch at the coarse levels) one Householder
-// step is two launches: k_rrqr_pivot (one workgroup per matrix: pivot choice,
-// column swap, reflector) and k_rrqr_update (column tiles of the trailing
-// matrix spread over many workgroups, 16-lane groups per column, exact norms).
-// Per-matrix state lives in RrqrState (norms kept in FP64); same arithmetic
-// as k_rrqr.
-template <class T>
-__global__ __launch_bounds__(WG) void k_rrqr_init(const RrqrDesc* __restrict__ descs,
-                                                  RrqrState* __restrict__ st) {
-  const RrqrDesc d = descs[blockIdx.x];
-  const int n = d.n, m = d.m;
-  RrqrState& S = st[blockIdx.x];
-  const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
-  constexpr int NSLOT = WG / GRP;
-  const T* A = static_cast<const T*>(d.A);
-  for (int c = blockIdx.y * NSLOT + slot; A != nullptr && c < m; c += gridDim.y * NSLOT) {
-    const T* col = A + (size_t)c * d.lda;
-    T q = 0;
-    for (int i = rl; i < n; i += GRP) q = fma(col[i], col[i], q);
-    q = grp_sum(q);
-    if (rl == 0) S.nrm[c] = (double)sqrt(q);
-  }
-  if (blockIdx.y == 0 && threadIdx.x == 0) {
-    S.done = d.A == nullptr ? 1 : 0;
-    S.apply = 0;
-    S.rank = 0;
-    S.counting = 1;
-    S.first = 0.0;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(WG) void k_rrqr_pivot(const RrqrDesc* __restrict__ descs,
-                                                   RrqrState* __restrict__ st, int j) {
-  const RrqrDesc d = descs[blockIdx.x];
-  RrqrState& S = st[blockIdx.x];
-  const int n = d.n, m = d.m;
-  const int K = min(min(n, m), d.kmax);
-  if (S.done) {
-    if (threadIdx.x == 0) S.apply = 0;
-    return;
-  }
-  if (j >= K) {
-    if (threadIdx.x == 0) { *d.rank = S.rank; *d.steps = K; S.done = 1; S.apply = 0; }
-    return;
-  }
-  __shared__ double rv[WG / WAVE];
-  __shared__ int ri[WG / WAVE];
-  __shared__ T red[WG / WAVE];
-  T* A = static_cast<T*>(d.A);
-  const size_t lda = d.lda;
-  double* nrm = S.nrm;
-  double bv = -1.0;
-  int bi = m;
-  for (int c = j + threadIdx.x; c < m; c += WG)
-    if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
-  double piv;
-  int cp;
-  block_argmax(bv, bi, rv, ri, piv, cp);
-  const double first = j == 0 ? piv : S.first;
-  int rank = S.rank;
-  bool counting = S.counting != 0;
-  if (counting && first > 0.0 && piv > d.eps * first) rank = j + 1;
-  else counting = false;
-  __syncthreads();
-  if (threadIdx.x == 0) { S.first = first; S.rank = rank; S.counting = counting ? 1 : 0; }
-  if (!counting && d.stop_at_rank) {
-    if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; S.done = 1; S.apply = 0; }
-    return;
-  }
-  if (cp != j) {
-    for (int i = threadIdx.x; i < n; i += WG) {
-      const T t = A[i + j * lda];
-      A[i + j * lda] = A[i + cp * lda];
-      A[i + cp * lda] = t;
-    }
-    if (threadIdx.x == 0) { const double t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
-  }
-  __syncthreads();
-  T part = 0;
-  for (int i = j + threadIdx.x; i < n; i += WG) part = fma(A[i + j * lda], A[i + j * lda], part);
-  const T xn = sqrt(block_sum(part, red));
-  const T x0 = A[j + j * lda];
-  T alpha = 0, tau = 0, v0 = 1;
-  if (xn > 0) {
-    alpha = x0 >= 0 ? -xn : xn;
-    v0 = x0 - alpha;
-    tau = -v0 / alpha;
-  }
-  __syncthreads();
-  for (int i = j + 1 + threadIdx.x; i < n; i += WG) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
-  if (threadIdx.x == 0) {
-    static_cast<T*>(d.tau)[j] = tau;
-    static_cast<T*>(d.alpha)[j] = alpha;
-    A[j + j * lda] = alpha;
-    // the trailing update of the last reflector is never read: skip it
-    if (j + 1 == K) { *d.rank = rank; *d.steps = K; S.done = 1; S.apply = 0; }
-    else S.apply = 1;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(WG) void k_rrqr_update(const RrqrDesc* __restrict__ descs,
-                                                    const RrqrState* __restrict__ st, int j) {
-  const RrqrDesc d = descs[blockIdx.x];
-  const RrqrState& S = st[blockIdx.x];
-  const int n = d.n, m = d.m;
-  if (!S.apply) return;  // no reflector formed at this step
-  T* A = static_cast<T*>(d.A);
-  const T tau = static_cast<const T*>(d.tau)[j];
-  const T* u = A + (size_t)j * d.lda;
-  const int rl = threadIdx.x % GRP, slot = threadIdx.x / GRP;
-  constexpr int NSLOT = WG / GRP;
-  for (int c = j + 1 + blockIdx.y * NSLOT + slot; c < m; c += gridDim.y * NSLOT) {
-    T* col = A + (size_t)c * d.lda;
-    T s = 0;
-    for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
-    s = grp_sum(s) + col[j];
-    const T ts = tau * s;
-    T q = 0;
-    for (int i = j + 1 + rl; i < n; i += GRP) {
-      const T v = fma(-ts, u[i], col[i]);
-      col[i] = v;
-      q = fma(v, v, q);
-    }
-    q = grp_sum(q);
-    if (rl == 0) {
-      col[j] -= ts;
-      S.nrm[c] = (double)sqrt(q);
-    }
-  }
 }
 
 // ------------------------------------------------------------------ FORMQ
@@ -1156,15 +1149,6 @@ void add_go(const AddDesc* d, int nd, int tm, int tn, hipStream_t s) {
   hipLaunchKernelGGL((k_add<TA, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
 }
 
-template <class T>
-void rrqr_multi_go(const RrqrDesc* d, int nd, int tiles, int max_k, RrqrState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_rrqr_init<T>, dim3(nd, tiles), dim3(WG), 0, s, d, st);
-  for (int j = 0; j < max_k; ++j) {
-    hipLaunchKernelGGL(k_rrqr_pivot<T>, dim3(nd), dim3(WG), 0, s, d, st, j);
-    hipLaunchKernelGGL(k_rrqr_update<T>, dim3(nd, tiles), dim3(WG), 0, s, d, st, j);
-  }
-}
-
 // Raise the dynamic LDS limit of a kernel once (gfx950: 160 KiB per CU).
 void allow_lds(const void* fn, bool& done, size_t bytes) {
   if (done) return;
@@ -1253,6 +1237,14 @@ void launch_transition(const TransArgs& a, int ty, hipStream_t s) {
   else hipLaunchKernelGGL(k_transition<double>, grid, dim3(WG), 0, s, a);
 }
 
+void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty, hipStream_t s) {
+  if (a.nb <= 0 || max_rows <= 0) return;
+  const int tiles = cdiv(max_rows, WAVE);
+  const dim3 grid(a.nb, (step == 1 ? 9 : 1) * tiles);
+  if (ty) hipLaunchKernelGGL(k_solve<float>, grid, dim3(WG), 0, s, a, step, wk, tiles);
+  else hipLaunchKernelGGL(k_solve<double>, grid, dim3(WG), 0, s, a, step, wk, tiles);
+}
+
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   if (a.nt <= 0) return;
   const dim3 grid(a.nt, 37);
@@ -1281,21 +1273,27 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t 
   if (nd <= 0) return;
   if (ty) {
     static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT>), dim3(nd), dim3(RRQR_NT), lds, s, d);
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT, true>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT, true>), dim3(nd), dim3(RRQR_NT), lds, s, d);
   } else {
     static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT>), dim3(nd), dim3(RRQR_NT), lds, s, d);
+    allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT, true>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT, true>), dim3(nd), dim3(RRQR_NT), lds, s, d);
   }
 }
 
-void launch_rrqr_multi(const RrqrDesc* d, int nd, int max_m, int max_k, RrqrState* st, int ty,
-                       hipStream_t s) {
-  if (nd <= 0) return;
-  const int tiles = cdiv(max_m, 4 * (WG / GRP));  // ~64 columns per workgroup
-  if (ty) rrqr_multi_go<float>(d, nd, tiles, max_k, st, s);
-  else rrqr_multi_go<double>(d, nd, tiles, max_k, st, s);
+void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0) return;
+  const size_t lds = (size_t)max_m * (ty ? sizeof(float) : sizeof(double));
+  if (ty) {
+    static bool raised = false;
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT, false>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT, false>), dim3(nd), dim3(RRQR_NT), lds, s, d);
+  } else {
+    static bool raised = false;
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT, false>), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT, false>), dim3(nd), dim3(RRQR_NT), lds, s, d);
+  }
 }
 
 void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s) {

@@ -52,8 +52,8 @@ class _Stats(C.Structure):
                 ("kernel_bytes", C.c_double * 32), ("precision", C.c_int)]
 
 
-KERNEL_FAMILIES = ["gemm", "add", "xform", "qr", "rrqr", "formq", "stackqr", "inverse", "elim",
-                   "touch_xform", "stack_win"]
+KERNEL_FAMILIES = ["gemm", "add", "unused2", "qr", "rrqr", "formq", "stackqr", "inverse", "elim",
+                   "touch_xform", "stack_win", "solve"]
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
