@@ -837,6 +837,7 @@ struct Plan final : ifmm_plan {
           ElimArgs a;
           std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
           a.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(a.rec) - 1));
+          if (a.rk) a.rk = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.rk) - 1));
           launch_elim(a, op.count, op.a, op.b, op.ty, s);
           break;
         }
@@ -1253,6 +1254,34 @@ struct Plan final : ifmm_plan {
     t_factor = now_ms() - t0;
   }
 
+  ElimArgs elim_args(const Level<T>& L, T* X, T* F, int wpad, int fpad, int nb) {
+    ElimArgs a{};
+    a.P = L.P;
+    a.Qm = L.Qm;
+    a.L = L.L;
+    a.M = L.M;
+    a.U = L.U;
+    a.Dinv = L.Dinv;
+    a.X = X;
+    a.F = F;
+    a.sP = L.sP;
+    a.sQ = L.sQ;
+    a.sL = L.sL;
+    a.sM = L.sM;
+    a.sU = L.sU;
+    a.sD = L.sD;
+    a.sX = (size_t)L.mpad * wpad;
+    a.nb = nb;
+    a.npad = L.npad;
+    a.rpad = rpad;
+    a.mpad = L.mpad;
+    a.fpad = fpad;
+    a.npair = kPairs.count;
+    for (int sa = 0; sa < 9; ++sa)
+      for (int sb = 0; sb < 9; ++sb) a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
+    return a;
+  }
+
   void phase(int k, int c) {
     Level<T>& L = lv[k];
     std::vector<Elim>& E = plan[k][c];
@@ -1332,30 +1361,7 @@ struct Plan final : ifmm_plan {
           }
         }
       }
-      ElimArgs a{};
-      a.P = L.P;
-      a.Qm = L.Qm;
-      a.L = L.L;
-      a.M = L.M;
-      a.U = L.U;
-      a.Dinv = L.Dinv;
-      a.X = X;
-      a.F = F;
-      a.sP = L.sP;
-      a.sQ = L.sQ;
-      a.sL = L.sL;
-      a.sM = L.sM;
-      a.sU = L.sU;
-      a.sD = L.sD;
-      a.sX = (size_t)L.mpad * wpad;
-      a.nb = nb;
-      a.npad = L.npad;
-      a.rpad = rpad;
-      a.mpad = L.mpad;
-      a.fpad = fpad;
-      a.npair = kPairs.count;
-      for (int sa = 0; sa < 9; ++sa)
-        for (int sb = 0; sb < 9; ++sb) a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
+      ElimArgs a = elim_args(L, X, F, wpad, fpad, nb);
       const size_t ro = st.push(recs.data(), recs.size() * sizeof(ElimRec)) + 1;
       erec[k][c] = recs;
       double bd = 0;
@@ -1371,11 +1377,11 @@ struct Plan final : ifmm_plan {
       st.elim<T>(a, ro, 3, rpad, maxu, 0.0, b3);
       run(st);
     }
-    compress(k, E, fpad, Fp);
+    compress(k, c, E, X, F, wpad, fpad, Fp);
   }
 
   template <class FpFn>
-  void compress(int k, const std::vector<Elim>& E, int fpad, FpFn Fp) {
+  void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, FpFn Fp) {
     Level<T>& L = lv[k];
     struct Touch {
       int q, b, sq;
@@ -1488,33 +1494,37 @@ struct Plan final : ifmm_plan {
     }
     st.add(cp);
     for (int t = 0; t < nt; ++t) L.r[touch[t].q] = rnew[t];
-    // project the compressed fill into M2L
-    std::vector<GemmDesc> g1, g2;
-    T* tmp = wsS2.need<T>((size_t)E.size() * kPairs.count * rpad * fpad, s);
-    for (int b = 0; b < (int)E.size(); ++b) {
-      const Elim& e = E[b];
-      for (int sa = 0; sa < 9; ++sa)
-        for (int sb = 0; sb < 9; ++sb) {
-          const int pi = kPairs.idx[sa][sb];
-          if (pi < 0) continue;
-          const UnitH& ua = e.u[sa];
-          const UnitH& ub = e.u[sb];
-          if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
-          const T* Fb = Fp(b, sa, sb);
-          T* C = L.Mb(ua.cl, slot36(ua.cl, ub.cl));
-          if (ua.kind == 1 && ub.kind == 1) {
-            T* tm = tmp + ((size_t)b * kPairs.count + pi) * rpad * fpad;
-            g1.push_back({L.Ub(ua.cl), Fb, tm, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 0.0});
-            g2.push_back({tm, L.Ub(ub.cl), C, L.r[ua.cl], L.r[ub.cl], ub.size, rpad, L.npad, rpad, 0, 0, 1.0, 1.0});
-          } else if (ua.kind == 1) {
-            g2.push_back({L.Ub(ua.cl), Fb, C, L.r[ua.cl], ub.size, ua.size, L.npad, fpad, rpad, 1, 0, 1.0, 1.0});
-          } else {
-            g2.push_back({Fb, L.Ub(ub.cl), C, ua.size, L.r[ub.cl], ub.size, fpad, L.npad, rpad, 0, 0, 1.0, 1.0});
+    // project the compressed fill into M2L (steps 4, 5 of the records)
+    {
+      ElimArgs a = elim_args(L, X, F, wpad, fpad, (int)E.size());
+      a.tmp = wsS2.need<T>((size_t)E.size() * kPairs.count * rpad * fpad, s);
+      a.rk = st.arr(&L.r);
+      const size_t ro = st.push(erec[k][c].data(), erec[k][c].size() * sizeof(ElimRec)) + 1;
+      double f4 = 0, f5 = 0, b4 = 0, b5 = 0;
+      int mx = rpad;
+      const double es = sizeof(T);
+      for (const Elim& e : E)
+        for (int sa = 0; sa < 9; ++sa)
+          for (int sb = 0; sb < 9; ++sb) {
+            if (kPairs.idx[sa][sb] < 0) continue;
+            const UnitH& ua = e.u[sa];
+            const UnitH& ub = e.u[sb];
+            if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
+            mx = std::max(mx, std::max(ua.size, ub.size));
+            const double ra = ua.kind == 1 ? L.r[ua.cl] : ua.size, rb = ub.kind == 1 ? L.r[ub.cl] : ub.size;
+            if (ua.kind == 1 && ub.kind == 1) {
+              f4 += 2.0 * ra * ub.size * ua.size;
+              b4 += es * (ua.size * ra + (double)ua.size * ub.size + ra * ub.size);
+              f5 += 2.0 * ra * rb * ub.size;
+              b5 += es * (ra * ub.size + (double)ub.size * rb + 2.0 * ra * rb);
+            } else {
+              f5 += 2.0 * ra * rb * (ua.kind == 1 ? ua.size : ub.size);
+              b5 += es * ((double)ua.size * ub.size + (ua.kind == 1 ? ua.size * ra : ub.size * rb) + 2.0 * ra * rb);
+            }
           }
-        }
+      st.elim<T>(a, ro, 4, mx, mx, f4, b4);
+      st.elim<T>(a, ro, 5, mx, mx, f5, b5);
     }
-    st.gemm(g1);
-    st.gemm(g2);
     run(st);
   }
 

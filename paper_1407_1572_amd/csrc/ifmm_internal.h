@@ -202,6 +202,8 @@ struct ElimArgs {
   void* X;
   void* F;
   const ElimRec* rec;
+  const int* rk;  // cluster ranks after the batch's compression (steps 4, 5)
+  void* tmp;      // r x fill products, rpad x fpad per (record, pair) (step 4)
   size_t sP, sQ, sL, sM, sU, sD, sX;
   int nb, npad, rpad, mpad, fpad, npair;
   signed char pair[81];
@@ -307,7 +309,10 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
 //   1 X_u = D^-1 [B_u; 0] for every unit u (X_centre = -D^-1 [0; I]);
 //   2 Schur updates target(a, b) -= C_a X_b over all unit pairs (fill of
 //     pairs at distance 2 goes to F);
-//   3 M2L(i) row: L_iq / M_ip += X^z_u.
+//   3 M2L(i) row: L_iq / M_ip += X^z_u;
+//   4, 5 projection of the compressed fill into M2L with the new bases:
+//     M_qq' += U_q^T F_qq' U_q' (step 4 forms U_q^T F_qq'), M_qp += U_q^T F_qp,
+//     M_pq += F_pq U_q.
 // max_m / max_n bound the row / column sizes for the tiling.
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s);
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);

@@ -248,7 +248,65 @@ __device__ bool elim_schur_desc(const ElimArgs& a, const ElimRec& r, int b, int 
   return true;
 }
 
-// grid (nb, units * tiles): step 0 and 3 are elementwise, 1 and 2 products.
+// Descriptor of projection step 4 or 5 for the pair (sa, sb) of record r.
+template <class T>
+__device__ bool elim_proj_desc(const ElimArgs& a, const ElimRec& r, int b, int sa, int sb, int step, GemmDesc& g) {
+  const int pi = a.pair[9 * sa + sb];
+  if (pi < 0) return false;
+  const int ka = r.kind[sa], kb = r.kind[sb];
+  if (!ka || !kb || (ka == 2 && kb == 2)) return false;
+  if (step == 4 && !(ka == 1 && kb == 1)) return false;
+  const int ca = r.cl[sa], cb = r.cl[sb];
+  const T* F = static_cast<const T*>(a.F) + ((size_t)b * a.npair + pi) * a.fpad * a.fpad;
+  T* tm = static_cast<T*>(a.tmp) + ((size_t)b * a.npair + pi) * a.rpad * a.fpad;
+  const T* U = static_cast<const T*>(a.U);
+  g.opA = 0;
+  g.opB = 0;
+  g.alpha = 1.0;
+  g.beta = 1.0;
+  g.ldc = a.rpad;
+  g.C = static_cast<T*>(a.M) + ((size_t)ca * 36 + win_slot(demorton_x(ca), demorton_y(ca), demorton_x(cb), demorton_y(cb))) * a.sM;
+  if (ka == 1 && kb == 1 && step == 4) {  // tm = U_a^T F
+    g.A = U + (size_t)ca * a.sU;
+    g.lda = a.npad;
+    g.opA = 1;
+    g.B = F;
+    g.ldb = a.fpad;
+    g.C = tm;
+    g.M = a.rk[ca];
+    g.N = r.size[sb];
+    g.K = r.size[sa];
+    g.beta = 0.0;
+  } else if (ka == 1 && kb == 1) {  // M += tm U_b
+    g.A = tm;
+    g.lda = a.rpad;
+    g.B = U + (size_t)cb * a.sU;
+    g.ldb = a.npad;
+    g.M = a.rk[ca];
+    g.N = a.rk[cb];
+    g.K = r.size[sb];
+  } else if (ka == 1) {  // M += U_a^T F
+    g.A = U + (size_t)ca * a.sU;
+    g.lda = a.npad;
+    g.opA = 1;
+    g.B = F;
+    g.ldb = a.fpad;
+    g.M = a.rk[ca];
+    g.N = r.size[sb];
+    g.K = r.size[sa];
+  } else {  // M += F U_b
+    g.A = F;
+    g.lda = a.fpad;
+    g.B = U + (size_t)cb * a.sU;
+    g.ldb = a.npad;
+    g.M = r.size[sa];
+    g.N = a.rk[cb];
+    g.K = r.size[sb];
+  }
+  return true;
+}
+
+// grid (nb, units * tiles): step 0 and 3 are elementwise, 1, 2, 4, 5 products.
 template <class T>
 __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int step, int tiles_m, int tiles_n) {
   const int b = blockIdx.x;
@@ -287,6 +345,10 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int step, int til
   } else if (step == 2) {
     GemmDesc g;
     if (!elim_schur_desc<T>(a, r, b, unit / 9, unit % 9, g) || m0 >= g.M || n0 >= g.N) return;
+    gemm_tile<T, T, T>(g, m0, n0);
+  } else if (step >= 4) {
+    GemmDesc g;
+    if (!elim_proj_desc<T>(a, r, b, unit / 9, unit % 9, step, g) || m0 >= g.M || n0 >= g.N) return;
     gemm_tile<T, T, T>(g, m0, n0);
   } else {  // M2L(i) row += X^z_u
     if (!r.kind[unit]) return;
@@ -1224,7 +1286,7 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s) {
   if (a.nb <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
-  const int units = step == 0 ? 1 : step == 2 ? 81 : 9;
+  const int units = step == 0 ? 1 : (step == 2 || step >= 4) ? 81 : 9;
   const dim3 grid(a.nb, units * tm * tn);
   if (ty) hipLaunchKernelGGL(k_elim<float>, grid, dim3(WG), 0, s, a, step, tm, tn);
   else hipLaunchKernelGGL(k_elim<double>, grid, dim3(WG), 0, s, a, step, tm, tn);
