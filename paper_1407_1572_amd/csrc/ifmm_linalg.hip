@@ -64,67 +64,76 @@ __device__ inline T grp_sum(T v) {
 }
 
 // ------------------------------------------------------------------- GEMM
-// 64 x 64 output tile (m0, n0) of one product, 4 x 4 per thread, K staged by
-// 16 in LDS.
+// 64 x 64 output tile (m0, n0) of one product on the matrix cores: K staged
+// by 16 in LDS, each of the four waves owns a 32 x 32 quarter as 2 x 2
+// blocks of 16 x 16, advanced by v_mfma_*_16x16x4 (FP32 operands with FP32
+// accumulation when A and B are FP32, else FP64 operands and accumulation).
+// Lane layouts of the 16x16x4 instructions (lane l, accumulator register r):
+// A(i, k) from lane i + 16 k, B(k, j) from lane j + 16 k; the FP32 result
+// D(4 (l / 16) + r, l % 16), the FP64 result D(4 r + l / 16, l % 16).
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+__device__ inline mf4 mfma16(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline md4 mfma16(double a, double b, md4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline int mfma_row(float, int l, int r) { return 4 * (l / 16) + r; }
+__device__ inline int mfma_row(double, int l, int r) { return 4 * r + l / 16; }
+
 template <class TA, class TB, class TC>
 __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
   using Acc = typename std::conditional<std::is_same<TA, float>::value && std::is_same<TB, float>::value,
                                         float, double>::type;
+  using V4 = typename std::conditional<std::is_same<Acc, float>::value, mf4, md4>::type;
   const TA* __restrict__ Ap = static_cast<const TA*>(d.A);
   const TB* __restrict__ Bp = static_cast<const TB*>(d.B);
   TC* Cp = static_cast<TC*>(d.C);
-  __shared__ Acc As[16][65];
-  __shared__ Acc Bs[16][65];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  Acc acc[4][4];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int wm = m0 + (w & 1) * 32, wn = n0 + (w >> 1) * 32;
+  if (wm >= d.M || wn >= d.N) return;  // no barrier below: a wave may leave
+  const int li = lane % 16, lk = lane / 16;
+  // this lane's rows / columns of the two 16-blocks, and their validity
+  const int r0 = wm + li, r1 = wm + 16 + li, c0 = wn + li, c1 = wn + 16 + li;
+  const bool vr0 = r0 < d.M, vr1 = r1 < d.M, vc0 = c0 < d.N, vc1 = c1 < d.N;
+  const size_t sa = d.opA ? 1 : (size_t)d.lda, ra = d.opA ? (size_t)d.lda : 1;  // A(i, k) = Ap[i ra + k sa]
+  const size_t sb = d.opB ? (size_t)d.ldb : 1, cb = d.opB ? 1 : (size_t)d.ldb;  // B(k, j) = Bp[k sb + j cb]
+  V4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V4{0, 0, 0, 0};
   for (int k0 = 0; k0 < d.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 1024; e += WG) {
-      int mm, kk;
-      if (d.opA == 0) { mm = e % 64; kk = e / 64; } else { kk = e % 16; mm = e / 16; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      Acc v = 0;
-      if (gm < d.M && gk < d.K)
-        v = (Acc)(d.opA == 0 ? Ap[gm + (size_t)gk * d.lda] : Ap[gk + (size_t)gm * d.lda]);
-      As[kk][mm] = v;
-      int nn;
-      if (d.opB == 0) { kk = e % 16; nn = e / 16; } else { nn = e % 64; kk = e / 64; }
-      const int gn = n0 + nn;
-      const int gk2 = k0 + kk;
-      Acc w = 0;
-      if (gn < d.N && gk2 < d.K)
-        w = (Acc)(d.opB == 0 ? Bp[gk2 + (size_t)gn * d.ldb] : Bp[gn + (size_t)gk2 * d.ldb]);
-      Bs[kk][nn] = w;
+    Acc a[4][2], b[4][2];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * s + lk;
+      const bool vk = k < d.K;
+      a[s][0] = vk && vr0 ? (Acc)Ap[r0 * ra + k * sa] : Acc(0);
+      a[s][1] = vk && vr1 ? (Acc)Ap[r1 * ra + k * sa] : Acc(0);
+      b[s][0] = vk && vc0 ? (Acc)Bp[k * sb + c0 * cb] : Acc(0);
+      b[s][1] = vk && vc1 ? (Acc)Bp[k * sb + c1 * cb] : Acc(0);
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      Acc a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    for (int s = 0; s < 4; ++s) {
+      acc[0][0] = mfma16(a[s][0], b[s][0], acc[0][0]);
+      acc[0][1] = mfma16(a[s][0], b[s][1], acc[0][1]);
+      acc[1][0] = mfma16(a[s][1], b[s][0], acc[1][0]);
+      acc[1][1] = mfma16(a[s][1], b[s][1], acc[1][1]);
     }
-    __syncthreads();
   }
   const Acc al = (Acc)d.alpha, be = (Acc)d.beta;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gm = m0 + tx + 16 * i, gn = n0 + ty + 16 * j;
-      if (gm < d.M && gn < d.N) {
-        TC* c = Cp + gm + (size_t)gn * d.ldc;
-        *c = (TC)(d.beta == 0.0 ? al * acc[i][j] : fma(al, acc[i][j], be * (Acc)*c));
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = wm + 16 * bi + mfma_row(Acc(0), lane, r), gn = wn + 16 * bj + li;
+        if (gm < d.M && gn < d.N) {
+          TC* c = Cp + gm + (size_t)gn * d.ldc;
+          const Acc v = acc[bi][bj][r];
+          *c = (TC)(d.beta == 0.0 ? al * v : fma(al, v, be * (Acc)*c));
+        }
       }
-    }
 }
 
 template <class TA, class TB, class TC>
