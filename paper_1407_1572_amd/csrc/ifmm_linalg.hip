@@ -398,40 +398,64 @@ __global__ __launch_bounds__(WG) void k_add(const AddDesc* __restrict__ descs, i
   }
 }
 
+// out(i, j, sum_k A(i, k) B(k, j)) for an M x N result, by 16 x 16 MFMA
+// blocks spread over the waves (k advanced 16 at a time, operands loaded for
+// four MFMA steps before they issue).  No barrier inside.
+template <class T, class AFn, class BFn, class OFn>
+__device__ void wg_mfma(int M, int N, int K, AFn A, BFn B, OFn out) {
+  using V4 = typename std::conditional<std::is_same<T, float>::value, mf4, md4>::type;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int li = lane % 16, lk = lane / 16;
+  const int bm = (M + 15) / 16, bn = (N + 15) / 16;
+  for (int blk = w; blk < bm * bn; blk += WG / WAVE) {
+    const int i0 = (blk % bm) * 16, j0 = (blk / bm) * 16;
+    const int i = i0 + li, j = j0 + li;
+    V4 acc = V4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * s + lk;
+        av[s] = (i < M && k < K) ? A(i, k) : T(0);
+        bv[s] = (j < N && k < K) ? B(k, j) : T(0);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma16(av[s], bv[s], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + mfma_row(T(0), lane, r);
+      if (row < M && j < N) out(row, j, acc[r]);
+    }
+  }
+}
+
 // X <- T X S (T: r_new x r_old or null; S: c_old x c_new, transposed when
-// transS, or null) by one workgroup, Z = T X staged in LDS (rpad x rpad).
+// transS, or null) by one workgroup, Z = T X staged in LDS (rpad x rpad),
+// both products on the matrix cores.
 template <class T>
 __device__ void xform_block(T* X, const T* Tm, const T* Sm, int r_old, int c_old, int r_new, int c_new,
                             int ldx, int ldt, int lds, int transS, T* Z, int ldz) {
-  // flat element index over the block: the inner products amortise the
-  // index split, and every lane stays busy for any block height
   const int rz = Tm ? r_new : r_old;
-  for (int e = threadIdx.x; e < rz * c_old; e += WG) {
-    const int i = e % rz, j = e / rz;
-    T v;
-    if (Tm) {
-      v = 0;
-      for (int k = 0; k < r_old; ++k) v = fma(Tm[i + (size_t)k * ldt], X[k + (size_t)j * ldx], v);
-    } else {
-      v = X[i + (size_t)j * ldx];
+  if (Tm) {
+    wg_mfma<T>(r_new, c_old, r_old, [&](int i, int k) { return Tm[i + (size_t)k * ldt]; },
+               [&](int k, int j) { return X[k + (size_t)j * ldx]; }, [&](int i, int j, T v) { Z[i + j * ldz] = v; });
+  } else {
+    for (int e = threadIdx.x; e < rz * c_old; e += WG) {
+      const int i = e % rz, j = e / rz;
+      Z[i + j * ldz] = X[i + (size_t)j * ldx];
     }
-    Z[i + j * ldz] = v;
   }
   __syncthreads();
-  const int cn = Sm ? c_new : c_old;
-  for (int e = threadIdx.x; e < rz * cn; e += WG) {
-    const int i = e % rz, j = e / rz;
-    T v;
-    if (Sm) {
-      v = 0;
-      for (int k = 0; k < c_old; ++k) {
-        const T s = transS ? Sm[j + (size_t)k * lds] : Sm[k + (size_t)j * lds];
-        v = fma(Z[i + k * ldz], s, v);
-      }
-    } else {
-      v = Z[i + j * ldz];
+  if (Sm) {
+    wg_mfma<T>(rz, c_new, c_old, [&](int i, int k) { return Z[i + k * ldz]; },
+               [&](int k, int j) { return transS ? Sm[j + (size_t)k * lds] : Sm[k + (size_t)j * lds]; },
+               [&](int i, int j, T v) { X[i + (size_t)j * ldx] = v; });
+  } else {
+    for (int e = threadIdx.x; e < rz * c_old; e += WG) {
+      const int i = e % rz, j = e / rz;
+      X[i + (size_t)j * ldx] = Z[i + j * ldz];
     }
-    X[i + (size_t)j * ldx] = v;
   }
   __syncthreads();
 }
