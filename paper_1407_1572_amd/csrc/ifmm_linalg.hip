@@ -919,9 +919,18 @@ __device__ void stackqr_body(T* lds, int r, int nblk, BlockFn block, int chunk, 
     {
       for (int j = 0; j < r; ++j) {
         const T* cj = C + j * ldc;
-        T s2 = 0;
-        for (int i = rl; i < cr; i += GRP) s2 = fma(cj[i], cj[i], s2);
-        s2 = grp_sum(s2);
+        // four independent partial sums per lane: the LDS loads of one
+        // iteration do not wait for the previous fma
+        T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        int i = rl;
+        for (; i + 3 * GRP < cr; i += 4 * GRP) {
+          p0 = fma(cj[i], cj[i], p0);
+          p1 = fma(cj[i + GRP], cj[i + GRP], p1);
+          p2 = fma(cj[i + 2 * GRP], cj[i + 2 * GRP], p2);
+          p3 = fma(cj[i + 3 * GRP], cj[i + 3 * GRP], p3);
+        }
+        for (; i < cr; i += GRP) p0 = fma(cj[i], cj[i], p0);
+        T s2 = grp_sum((p0 + p1) + (p2 + p3));
         const T rjj = R[j + j * r];
         const T nrm = sqrt(rjj * rjj + s2);
         if (s2 == 0 || nrm == 0) continue;  // nothing below the diagonal: H = I
@@ -934,11 +943,20 @@ __device__ void stackqr_body(T* lds, int r, int nblk, BlockFn block, int chunk, 
         const T iv0 = T(1) / v0;
         for (int c = j + 1 + slot; c < r; c += NSLOT) {
           T* cc = C + c * ldc;
-          T sc = 0;
-          for (int i = rl; i < cr; i += GRP) sc = fma(cj[i] * iv0, cc[i], sc);
+          T q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+          int i = rl;
+          for (; i + 3 * GRP < cr; i += 4 * GRP) {
+            q0 = fma(cj[i], cc[i], q0);
+            q1 = fma(cj[i + GRP], cc[i + GRP], q1);
+            q2 = fma(cj[i + 2 * GRP], cc[i + 2 * GRP], q2);
+            q3 = fma(cj[i + 3 * GRP], cc[i + 3 * GRP], q3);
+          }
+          for (; i < cr; i += GRP) q0 = fma(cj[i], cc[i], q0);
           const T rjc = R[j + c * r];
-          sc = tau * (grp_sum(sc) + rjc);
-          for (int i = rl; i < cr; i += GRP) cc[i] = fma(-sc, cj[i] * iv0, cc[i]);
+          const T sc = tau * (grp_sum((q0 + q1) + (q2 + q3)) * iv0 + rjc);
+          const T su = sc * iv0;
+#pragma unroll 4
+          for (int i2 = rl; i2 < cr; i2 += GRP) cc[i2] = fma(-su, cj[i2], cc[i2]);
           if (rl == 0) R[j + c * r] = rjc - sc;
         }
         __syncthreads();  // trailing columns final; R_jj and column j no longer read
