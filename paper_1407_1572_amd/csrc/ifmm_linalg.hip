@@ -818,17 +818,32 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
     const T* u = A + j * lda;
     for (int c = j + 1 + slot; c < m; c += NSLOT) {
       T* col = A + c * lda;
-      T s = 0;
-      for (int i = j + 1 + rl; i < n; i += GRP) s = fma(u[i], col[i], s);
-      s = grp_sum(s) + col[j];
-      const T ts = tau * s;
-      T q = 0;
-      for (int i = j + 1 + rl; i < n; i += GRP) {
-        const T v = fma(-ts, u[i], col[i]);
-        col[i] = v;
-        q = fma(v, v, q);
+      // two independent partial sums per lane (short, latency-bound loops)
+      T s0 = 0, s1 = 0;
+      int i = j + 1 + rl;
+      for (; i + GRP < n; i += 2 * GRP) {
+        s0 = fma(u[i], col[i], s0);
+        s1 = fma(u[i + GRP], col[i + GRP], s1);
       }
-      q = grp_sum(q);
+      if (i < n) s0 = fma(u[i], col[i], s0);
+      const T s = grp_sum(s0 + s1) + col[j];
+      const T ts = tau * s;
+      T q0 = 0, q1 = 0;
+      i = j + 1 + rl;
+      for (; i + GRP < n; i += 2 * GRP) {
+        const T v0 = fma(-ts, u[i], col[i]);
+        const T v1 = fma(-ts, u[i + GRP], col[i + GRP]);
+        col[i] = v0;
+        col[i + GRP] = v1;
+        q0 = fma(v0, v0, q0);
+        q1 = fma(v1, v1, q1);
+      }
+      if (i < n) {
+        const T v0 = fma(-ts, u[i], col[i]);
+        col[i] = v0;
+        q0 = fma(v0, v0, q0);
+      }
+      const T q = grp_sum(q0 + q1);
       if (rl == 0) {
         col[j] -= ts;
         nrm[c] = sqrt(q);
