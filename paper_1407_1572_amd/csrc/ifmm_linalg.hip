@@ -1134,6 +1134,7 @@ __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ des
 // the step anyway), the pivot row is scaled and every other row eliminated.
 // The column permutation is undone while the result is written back.
 constexpr int GJ_WG = 512;
+constexpr int kGjRows = 3;  // rows per lane: m <= 192 covers every LDS-sized matrix
 __global__ __launch_bounds__(GJ_WG) void k_gj_lds(const InvDesc* __restrict__ descs, Status* st) {
   extern __shared__ __align__(16) unsigned char smem[];
   const InvDesc d = descs[blockIdx.x];
@@ -1189,13 +1190,29 @@ __global__ __launch_bounds__(GJ_WG) void k_gj_lds(const InvDesc* __restrict__ de
     }
     for (int i = threadIdx.x; i < m; i += GJ_WG) f[i] = i == p ? A[j + j * ld] : A[i + j * ld];
     __syncthreads();
+    // each lane keeps the multipliers of its rows (lane, lane + 64, ...) in
+    // registers; per element one LDS read and one write remain
+    double fr[kGjRows];
+#pragma unroll
+    for (int t = 0; t < kGjRows; ++t) {
+      const int i = lane + WAVE * t;
+      fr[t] = i < m ? f[i] : 0.0;
+    }
     for (int c = w; c < m; c += NW) {
       double* col = A + c * ld;
       if (c == j) {
-        for (int i = lane; i < m; i += WAVE) col[i] = i == j ? inv : -f[i] * inv;
+#pragma unroll
+        for (int t = 0; t < kGjRows; ++t) {
+          const int i = lane + WAVE * t;
+          if (i < m) col[i] = i == j ? inv : -fr[t] * inv;
+        }
       } else {
         const double rc = rowj[c];
-        for (int i = lane; i < m; i += WAVE) col[i] = i == j ? rc : fma(-f[i], rc, col[i]);
+#pragma unroll
+        for (int t = 0; t < kGjRows; ++t) {
+          const int i = lane + WAVE * t;
+          if (i < m) col[i] = i == j ? rc : fma(-fr[t], rc, col[i]);
+        }
       }
     }
     __syncthreads();
