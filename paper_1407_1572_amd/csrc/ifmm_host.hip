@@ -165,7 +165,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS, OP_SOLVE };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS, OP_SOLVE, OP_M2LASM };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 elim, 9 touched-cluster
 // transform, 10 window stacked R, 11 solve sweeps.
@@ -181,6 +181,7 @@ inline int family(int t) {
     case OP_WSTACK: return 10;
     case OP_TRANS: return 1;
     case OP_SOLVE: return 11;
+    case OP_M2LASM: return 0;
     default: return t;
   }
 }
@@ -415,6 +416,12 @@ struct Stage {
   void solve(const SolveArgs& a, int step, double* wk, int max_rows, double f, double by) {
     if (a.nb <= 0) return;
     op({OP_SOLVE, push(&a, sizeof(a)), (size_t)(uintptr_t)wk, step, max_rows, 0, f, by}, tcode<T>());
+  }
+  // M2L assembly of one level (device-side interaction lists).
+  template <class T>
+  void m2l_assemble(M2LAssemble a, const std::vector<int>& r, double f, double by) {
+    a.r = arr(&r);
+    op({OP_M2LASM, push(&a, sizeof(a)), 0, a.nc, 0, 0, f, by}, tcode<T>());
   }
   // All blocks of a stack have the type of its R.
   void stackqr(const std::vector<StackQrDesc>& v, const std::vector<BlkRef>& b) {
@@ -821,6 +828,13 @@ struct Plan final : ifmm_plan {
           launch_solve(a, op.count, reinterpret_cast<double*>(op.off2), op.a, op.ty, s);
           break;
         }
+        case OP_M2LASM: {
+          M2LAssemble a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          a.r = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.r) - 1));
+          launch_m2l_assemble(a, op.ty, s);
+          break;
+        }
         case OP_TRANS: {
           TransArgs a;
           std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
@@ -1133,28 +1147,33 @@ struct Plan final : ifmm_plan {
       Level<T>& L = lv[k];
       L.M = dalloc<T>(L.sM * 36 * L.nc);
       HIP_OK(hipMemsetAsync(L.M, 0, sizeof(T) * L.sM * 36 * L.nc, s));
-      double* tmp = wsA.need((size_t)L.nc * rpad * p2, s);
-      for (int dx = -3; dx <= 3; ++dx)
-        for (int dy = -3; dy <= 3; ++dy) {
-          if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-          const double* Kt = d_table[k] + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
-          std::vector<GemmDesc> g1, g2;
-          for (int i = 0; i < L.nc; ++i) {
-            if (L.r[i] == 0) continue;
-            const int jx = demorton_x(i) + dx, jy = demorton_y(i) + dy;
-            if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
-            const int l = morton2(jx, jy);
-            if (L.r[l] == 0 || !in_ilist(i, l)) continue;
-            double* ti = tmp + (size_t)i * rpad * p2;
-            g1.push_back({Ra[k] + (size_t)i * rpad * p2, Kt, ti, L.r[i], p2, p2, rpad, p2, rpad, 0, 0, 1.0, 0.0});
-            g2.push_back({ti, Ra[k] + (size_t)l * rpad * p2, L.Mb(i, slot36(i, l)), L.r[i], L.r[l], p2, rpad,
-                          rpad, rpad, 0, 1, 1.0, 0.0});
-          }
-          Stage st;
-          st.gemm(g1);
-          st.gemm(g2);
-          run(st);
+      M2LAssemble a{};
+      a.R = Ra[k];
+      a.table = d_table[k];
+      a.M = L.M;
+      a.sR = (size_t)rpad * p2;
+      a.sM = L.sM;
+      a.nc = L.nc;
+      a.nside = L.nside;
+      a.rpad = rpad;
+      a.p2 = p2;
+      double f = 0, by = 0;
+      for (int i = 0; i < L.nc; ++i) {
+        if (L.r[i] == 0) continue;
+        const int ix = demorton_x(i), iy = demorton_y(i);
+        for (int sl = 0; sl < 36; ++sl) {
+          const int jx = 2 * (ix >> 1) - 2 + sl / 6, jy = 2 * (iy >> 1) - 2 + sl % 6;
+          if (jx < 0 || jy < 0 || jx >= L.nside || jy >= L.nside) continue;
+          if (std::abs(jx - ix) <= 1 && std::abs(jy - iy) <= 1) continue;
+          const double rl = L.r[morton2(jx, jy)];
+          if (rl == 0) continue;
+          f += 2.0 * L.r[i] * p2 * (p2 + rl);
+          by += 8.0 * ((double)L.r[i] * p2 + (double)p2 * p2 + rl * p2) + sizeof(T) * L.r[i] * rl;
         }
+      }
+      Stage st;
+      st.m2l_assemble<T>(a, L.r, f, by);
+      run(st);
     }
     for (int k = 2; k <= kappa; ++k) dfree(Ra[k]);
     // ---- far-field weights of the parent levels, top-down

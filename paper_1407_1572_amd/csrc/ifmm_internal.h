@@ -249,6 +249,20 @@ struct SolveArgs {
   int nb, nc, npad, rpad, mpad, nrhs;
 };
 
+// M2L blocks in orthonormal coordinates, M_il = R_i K(dx, dy) R_l^T, for every
+// cluster i and every l of its interaction list (window slot sl, offset
+// (dx, dy) = position of l minus position of i), FP64 products, stored in the
+// factor type.  R: per cluster rpad x p2 (ld rpad); table: 49 blocks p2 x p2
+// at offset index 7 (dx + 3) + (dy + 3).
+struct M2LAssemble {
+  const double* R;
+  const double* table;
+  void* M;
+  const int* r;
+  size_t sR, sM;
+  int nc, nside, rpad, p2;
+};
+
 // Inverse of a square FP64 matrix in place (Gauss-Jordan, partial pivoting).
 struct InvDesc {
   double* A;
@@ -300,6 +314,7 @@ void launch_gemm(const GemmDesc* d, int nd, int max_m, int max_n, int ty, int pl
 void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s);
 void launch_transition(const TransArgs& a, int ty, hipStream_t s);
+void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s);
 // Step 0..3 of a colour batch (0, 1: forward; 2, 3: backward); wk holds
 // mpad x nrhs doubles per record; max_rows bounds the rows of the step.
 void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty, hipStream_t s);

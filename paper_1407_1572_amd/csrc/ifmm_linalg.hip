@@ -460,6 +460,34 @@ __device__ void xform_block(T* X, const T* Tm, const T* Sm, int r_old, int c_old
   __syncthreads();
 }
 
+// One workgroup per (cluster, window slot).
+template <class T>
+__global__ __launch_bounds__(WG) void k_m2l_assemble(const M2LAssemble a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Z = reinterpret_cast<double*>(smem);  // r_i x p2, ld rpad
+  const int i = blockIdx.x, sl = blockIdx.y;
+  const int ri = a.r[i];
+  if (ri == 0) return;
+  const int ix = demorton_x(i), iy = demorton_y(i);
+  const int jx = 2 * (ix >> 1) - 2 + sl / 6, jy = 2 * (iy >> 1) - 2 + sl % 6;
+  if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) return;
+  const int dx = jx - ix, dy = jy - iy;
+  if (abs(dx) <= 1 && abs(dy) <= 1) return;
+  const int l = morton2(jx, jy);
+  const int rl = a.r[l];
+  if (rl == 0) return;
+  const double* Ri = a.R + (size_t)i * a.sR;
+  const double* Rl = a.R + (size_t)l * a.sR;
+  const double* K = a.table + (size_t)((dx + 3) * 7 + (dy + 3)) * a.p2 * a.p2;
+  const int p2 = a.p2, ld = a.rpad;
+  wg_mfma<double>(ri, p2, p2, [&](int x, int k) { return Ri[x + (size_t)k * ld]; },
+                  [&](int k, int y) { return K[k + (size_t)y * p2]; }, [&](int x, int y, double v) { Z[x + y * ld] = v; });
+  __syncthreads();
+  T* M = static_cast<T*>(a.M) + ((size_t)i * 36 + sl) * a.sM;
+  wg_mfma<double>(ri, rl, p2, [&](int x, int k) { return Z[x + k * ld]; },
+                  [&](int k, int y) { return Rl[y + (size_t)k * ld]; }, [&](int x, int y, double v) { M[x + y * ld] = (T)v; });
+}
+
 // One workgroup per (touch, window slot); slot 36 is the parent transfer block.
 template <class T>
 __global__ __launch_bounds__(WG) void k_touch_xform(const TouchXform a) {
@@ -1388,6 +1416,14 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
   const dim3 grid(a.nb, (step == 1 ? 9 : 1) * tiles);
   if (ty) hipLaunchKernelGGL(k_solve<float>, grid, dim3(WG), 0, s, a, step, wk, tiles);
   else hipLaunchKernelGGL(k_solve<double>, grid, dim3(WG), 0, s, a, step, wk, tiles);
+}
+
+void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s) {
+  if (a.nc <= 0) return;
+  const dim3 grid(a.nc, 36);
+  const size_t lds = (size_t)a.rpad * a.p2 * sizeof(double);
+  if (ty) hipLaunchKernelGGL(k_m2l_assemble<float>, grid, dim3(WG), lds, s, a);
+  else hipLaunchKernelGGL(k_m2l_assemble<double>, grid, dim3(WG), lds, s, a);
 }
 
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
