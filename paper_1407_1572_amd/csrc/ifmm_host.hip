@@ -786,6 +786,12 @@ struct Plan final : ifmm_plan {
     if (st.empty()) return;
     factor_flops += st.flops;
     char* d = arena.upload(st.blob, s);
+    launch_ops(st, d);
+    st.clear();
+  }
+
+  // Launches the ops of a stage whose blob is at device address d.
+  void launch_ops(const Stage& st, char* d) {
     for (const Op& op : st.ops) {
       hipEvent_t ea = nullptr, eb = nullptr;
       if (profile) {
@@ -890,7 +896,6 @@ struct Plan final : ifmm_plan {
         if (pend.size() > 4096) resolve_profile();
       }
     }
-    st.clear();
   }
 
   // Inverse of the pivot blocks: blocked Gauss-Jordan.
@@ -1652,6 +1657,18 @@ struct Plan final : ifmm_plan {
   struct SolveBufs {
     std::vector<double*> b, c, sn, x, y;
   };
+  // Plans of Algorithm 2 already uploaded, keyed by their vectors (the
+  // refinement alternates two): a repeated solve launches them as they are.
+  struct SolvePlan {
+    const double* bt;
+    double* xt;
+    double* base;
+    int nrhs;
+    Stage st;
+    char* d = nullptr;
+  };
+  std::vector<SolvePlan> splans;
+
   // x (tree order, ld N) = A^-1 b (tree order, ld N)
   void solve_tree(const double* bt, double* xt, int nrhs) {
     std::vector<size_t> ob(kappa + 1), oc(kappa + 1);
@@ -1674,6 +1691,11 @@ struct Plan final : ifmm_plan {
     auto cvec = [&](int k, int i) { return base + oc[k] + (size_t)i * rpad * nrhs; };
     auto yvec = [&](int k, int i) { return base + oc[k] + ((size_t)lv[k].nc + i) * rpad * nrhs; };
     HIP_OK(hipMemsetAsync(base, 0, sizeof(double) * tot, s));
+    for (SolvePlan& sp : splans)
+      if (sp.bt == bt && sp.xt == xt && sp.base == base && sp.nrhs == nrhs) {
+        launch_ops(sp.st, sp.d);
+        return;
+      }
     auto args = [&](int k, int c) {
       const Level<T>& L = lv[k];
       SolveArgs a{};
@@ -1787,7 +1809,15 @@ struct Plan final : ifmm_plan {
       if (Lf.n[i]) a.push_back({xvec(kappa, i), xt + leaf_start[i], Lf.n[i], nrhs, Lf.npad, (int)N, 0, 1.0, 0.0});
     st.add(a);
     st.flops = 0.0;  // solve work is not factorisation work
-    run(st);
+    if (splans.size() >= 4) {
+      dfree(splans.front().d);
+      splans.erase(splans.begin());
+    }
+    splans.push_back(SolvePlan{bt, xt, base, nrhs, std::move(st), nullptr});
+    SolvePlan& sp = splans.back();
+    sp.d = dalloc<char>(sp.st.blob.size());
+    HIP_OK(hipMemcpyAsync(sp.d, sp.st.blob.data(), sp.st.blob.size(), hipMemcpyHostToDevice, s));
+    launch_ops(sp.st, sp.d);
   }
 
   // ---------------------------------------------------------- entry points
@@ -1948,6 +1978,8 @@ struct Plan final : ifmm_plan {
     dfree(d_E);
     dfree(d_top);
     dfree(d_erec);
+    for (SolvePlan& sp : splans) dfree(sp.d);
+    splans.clear();
     dfree(d_status);
     dfree(d_rank);
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
