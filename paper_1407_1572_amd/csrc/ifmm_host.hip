@@ -1197,13 +1197,15 @@ struct Plan final : ifmm_plan {
   // Omega of the clusters `ids` at level k: R factor of the stacked
   // transposed far-field row (+ the parent chain UP Omega_parent^T), written
   // to out + t * rpad^2 (or out + ids[t] * rpad^2 when by_id).
-  void weights(int k, const std::vector<int>& ids, T* out, bool by_id) {
+  // With ext, the launches are appended to that stage (run by the caller).
+  void weights(int k, const std::vector<int>& ids, T* out, bool by_id, Stage* ext = nullptr) {
     Level<T>& L = lv[k];
     const int nt = (int)ids.size();
     if (nt == 0) return;
     const size_t so = (size_t)rpad * rpad;
     T* Z = nullptr;
-    Stage st;
+    Stage own;
+    Stage& st = ext ? *ext : own;
     if (k > 2) {
       Z = wsZ.need<T>((size_t)nt * so, s);
       Level<T>& Pl = lv[k - 1];
@@ -1245,7 +1247,7 @@ struct Plan final : ifmm_plan {
       }
       st.stackqr(s2, b2);
     }
-    run(st);
+    if (!ext) run(st);
   }
 
   // ------------------------------------------------------------ factorisation
@@ -1399,13 +1401,16 @@ struct Plan final : ifmm_plan {
       st.elim<T>(a, ro, 1, maxm, maxu, f1, b1);
       st.elim<T>(a, ro, 2, maxu, maxu, f2, b2);
       st.elim<T>(a, ro, 3, rpad, maxu, 0.0, b3);
-      run(st);
+      // the compression's work up to the rank read-back depends only on
+      // host-known shapes: it joins this stage, uploaded and launched at once
+      compress(k, c, E, X, F, wpad, fpad, Fp, st);
     }
-    compress(k, c, E, X, F, wpad, fpad, Fp);
   }
 
   template <class FpFn>
-  void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, FpFn Fp) {
+  // pre: launches not yet run (the batch's elimination); run before the first
+  // rank read-back.
+  void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, FpFn Fp, Stage& pre) {
     Level<T>& L = lv[k];
     struct Touch {
       int q, b, sq;
@@ -1426,13 +1431,16 @@ struct Plan final : ifmm_plan {
         touch.push_back({u.cl, b, sq});
       }
     const int nt = (int)touch.size();
-    if (nt == 0) return;
+    if (nt == 0) {
+      run(pre);
+      return;
+    }
     const double eps_c = kF32 ? std::max(eps, kF32EpsFloor) : eps;
     // Omega from the current state (before any basis change)
     T* Om = wsB.need<T>((size_t)nt * rpad * rpad, s);
     std::vector<int> ids(nt);
     for (int t = 0; t < nt; ++t) ids[t] = touch[t].q;
-    weights(k, ids, Om, false);
+    weights(k, ids, Om, false, &pre);
     // new bases, chunk by chunk: pivoted QR of [U Omega^T | fill of the row]
     const int cmax = rpad + 5 * fpad;
     T* Uh = wsQ.need<T>((size_t)nt * L.sU, s);
@@ -1450,7 +1458,8 @@ struct Plan final : ifmm_plan {
     std::vector<int> hr(2 * nt), rnew(nt);
     for (int t0 = 0; t0 < nt; t0 += chunk) {
       const int t1 = std::min(nt, t0 + chunk);
-      Stage st;
+      Stage own;
+      Stage& st = t0 == 0 ? pre : own;
       std::vector<GemmDesc> g;
       std::vector<AddDesc> a;
       std::vector<RrqrDesc> rq;
