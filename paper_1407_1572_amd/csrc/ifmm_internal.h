@@ -333,7 +333,7 @@ void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipS
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
 // must fit in `lds` <= kRrqrLdsBytes.
-constexpr size_t kRrqrLdsBytes = 150 * 1024;
+constexpr size_t kRrqrLdsBytes = 159 * 1024;
 void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
 // Same arithmetic on the matrix in place (one workgroup per matrix, the
 // matrix L2-resident, column norms in LDS): max_m columns at most.
