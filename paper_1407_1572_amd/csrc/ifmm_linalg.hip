@@ -1226,20 +1226,34 @@ __global__ __launch_bounds__(GJ_WG) void k_gj_lds(const InvDesc* __restrict__ de
       const int i = lane + WAVE * t;
       fr[t] = i < m ? f[i] : 0.0;
     }
-    for (int c = w; c < m; c += NW) {
-      double* col = A + c * ld;
-      if (c == j) {
+    // four columns per pass: all loads issue before the first store, so the
+    // LDS latency of one column overlaps the others
+    constexpr int CU4 = 4;
+    for (int c0 = w; c0 < m; c0 += CU4 * NW) {
+      double v[CU4][kGjRows], rc[CU4];
+#pragma unroll
+      for (int u = 0; u < CU4; ++u) {
+        const int c = c0 + u * NW;
+        rc[u] = c < m ? rowj[c] : 0.0;
 #pragma unroll
         for (int t = 0; t < kGjRows; ++t) {
           const int i = lane + WAVE * t;
-          if (i < m) col[i] = i == j ? inv : -fr[t] * inv;
+          v[u][t] = (c < m && i < m) ? A[i + c * ld] : 0.0;
         }
-      } else {
-        const double rc = rowj[c];
+      }
+#pragma unroll
+      for (int u = 0; u < CU4; ++u) {
+        const int c = c0 + u * NW;
+        if (c >= m) continue;
+        double* col = A + c * ld;
 #pragma unroll
         for (int t = 0; t < kGjRows; ++t) {
           const int i = lane + WAVE * t;
-          if (i < m) col[i] = i == j ? rc : fma(-fr[t], rc, col[i]);
+          if (i >= m) continue;
+          double x;
+          if (c == j) x = i == j ? inv : -fr[t] * inv;
+          else x = i == j ? rc[u] : fma(-fr[t], rc[u], v[u][t]);
+          col[i] = x;
         }
       }
     }
