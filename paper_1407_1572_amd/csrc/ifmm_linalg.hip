@@ -581,13 +581,27 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
   constexpr int NW = WG / WAVE;
 #pragma unroll
   for (int c = 0; c < SV_C; ++c) acc[c] = 0.0;
-  if (live)
-    for (int k = w; k < K; k += NW) {
+  if (live) {
+    // eight loads of A in flight per lane before their products
+    constexpr int U = 8;
+    int k = w;
+    for (; k + (U - 1) * NW < K; k += U * NW) {
+      double av[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) av[t] = (double)A[row + (size_t)(k + t * NW) * lda];
+#pragma unroll
+      for (int t = 0; t < U; ++t)
+#pragma unroll
+        for (int c = 0; c < SV_C; ++c)
+          if (c < nc) acc[c] = fma(av[t], X(k + t * NW, c), acc[c]);
+    }
+    for (; k < K; k += NW) {
       const double av = (double)A[row + (size_t)k * lda];
 #pragma unroll
       for (int c = 0; c < SV_C; ++c)
         if (c < nc) acc[c] = fma(av, X(k, c), acc[c]);
     }
+  }
 #pragma unroll
   for (int c = 0; c < SV_C; ++c) part[(w * SV_C + c) * WAVE + lane] = acc[c];
   __syncthreads();
