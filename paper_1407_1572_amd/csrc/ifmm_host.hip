@@ -22,6 +22,8 @@
 #include <new>
 #include <unordered_map>
 #include <string>
+#include <tuple>
+#include <functional>
 #include <vector>
 
 #include "../../include/ifmm.h"
@@ -43,18 +45,20 @@ struct BadArg {};
     if (e_ != hipSuccess) throw HipError{e_};          \
   } while (0)
 
-// Process-wide cache of device blocks.  A factorisation holds tens of GB in
-// a few hundred large blocks; a destroyed handle returns them here and the
-// next factorisation (typically the same problem sizes again: refactoring
-// with new hyperparameters, repeated solves in a loop) reuses them instead of
-// going back to hipMalloc / hipFree for every block.  A release waits for the
-// device like hipFree does, so a cached block is never reused while a kernel
-// still reads it.  A block is reused for a request of at least 4/5 of its
+// Process-wide, stream-ordered cache of device blocks.  A factorisation
+// holds tens of GB in a few hundred large blocks; a destroyed handle returns
+// them here and the next factorisation (typically the same problem sizes
+// again: refactoring with new hyperparameters, repeated solves in a loop)
+// reuses them instead of going back to hipMalloc / hipFree for every block.
+// A release records an event on the stream that last used the block and does
+// not wait; a later request makes its own stream wait for that event, so a
+// block is never handed out while earlier work still reads it and the host is
+// never blocked.  A block is reused for a request of at least 4/5 of its
 // size; when hipMalloc fails the device's cache is freed and the allocation
 // retried; at most kPoolCapFrac of the device memory stays cached.
 class DevicePool {
  public:
-  void* get(size_t bytes) {
+  void* get(size_t bytes, hipStream_t s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
@@ -71,6 +75,12 @@ class DevicePool {
       }
       if (best != SIZE_MAX) {
         Blk b = free_[bi];
+        if (hipStreamWaitEvent(s, b.ev, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipEventSynchronize(b.ev);
+        }
+        evfree_[dev].push_back(b.ev);
+        b.ev = nullptr;
         free_[bi] = free_.back();
         free_.pop_back();
         cached_[dev] -= b.bytes;
@@ -88,16 +98,16 @@ class DevicePool {
       }
     }
     std::lock_guard<std::mutex> g(mu_);
-    live_[p] = Blk{p, bytes, dev};
+    live_[p] = Blk{p, bytes, dev, nullptr};
     return p;
   }
-  void put(void* p) {
+  // s: the stream on which the block's last reader or writer was enqueued.
+  void put(void* p, hipStream_t s) {
     if (!p) return;
-    (void)hipDeviceSynchronize();
     std::lock_guard<std::mutex> g(mu_);
     auto it = live_.find(p);
     if (it == live_.end()) return;
-    const Blk b = it->second;
+    Blk b = it->second;
     live_.erase(it);
     if (cap_[b.dev] == 0) {
       size_t fr = 0, tot = 0;
@@ -105,6 +115,27 @@ class DevicePool {
       cap_[b.dev] = (size_t)(kPoolCapFrac * (double)tot) + 1;
     }
     if (cached_[b.dev] + b.bytes > cap_[b.dev]) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(b.p);
+      return;
+    }
+    std::vector<hipEvent_t>& ev = evfree_[b.dev];
+    if (ev.empty()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(b.p);
+        return;
+      }
+      ev.push_back(e);
+    }
+    b.ev = ev.back();
+    ev.pop_back();
+    if (hipEventRecord(b.ev, s) != hipSuccess) {
+      (void)hipGetLastError();
+      ev.push_back(b.ev);
+      (void)hipStreamSynchronize(s);
       (void)hipFree(b.p);
       return;
     }
@@ -119,6 +150,7 @@ class DevicePool {
     for (const Blk& b : free_) {
       if (dev < 0 || b.dev == dev) {
         (void)hipFree(b.p);
+        evfree_[b.dev].push_back(b.ev);
         cached_[b.dev] -= b.bytes;
       } else {
         keep.push_back(b);
@@ -133,11 +165,13 @@ class DevicePool {
     void* p;
     size_t bytes;
     int dev;
+    hipEvent_t ev;  // recorded at release (cached blocks only)
   };
   std::mutex mu_;
   std::vector<Blk> free_;
   std::unordered_map<void*, Blk> live_;
   std::unordered_map<int, size_t> cached_, cap_;
+  std::unordered_map<int, std::vector<hipEvent_t>> evfree_;
 };
 
 // Never destroyed: handles may be released after static destructors ran.
@@ -146,13 +180,56 @@ DevicePool& pool() {
   return *p;
 }
 
+// Pinned host buffers of the descriptor uploads, kept for the next handle.
+// A buffer is returned only once the copies out of it have completed.
+class PinnedPool {
+ public:
+  char* get(size_t bytes, size_t* got) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].second >= bytes) {
+          auto b = free_[i];
+          free_[i] = free_.back();
+          free_.pop_back();
+          *got = b.second;
+          return b.first;
+        }
+    }
+    char* p = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw NoMem{};
+    }
+    *got = bytes;
+    return p;
+  }
+  void put(char* p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    if (free_.size() >= 4) {
+      (void)hipHostFree(p);
+      return;
+    }
+    free_.push_back({p, bytes});
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<std::pair<char*, size_t>> free_;
+};
+PinnedPool& pinned() {
+  static PinnedPool* p = new PinnedPool();
+  return *p;
+}
+
 template <class T>
-T* dalloc(size_t n) {
-  return static_cast<T*>(pool().get(std::max<size_t>(n, 1) * sizeof(T)));
+T* dalloc(hipStream_t s, size_t n) {
+  return static_cast<T*>(pool().get(std::max<size_t>(n, 1) * sizeof(T), s));
 }
 template <class T>
-void dfree(T*& p) {
-  if (p) pool().put(p);
+void dfree(hipStream_t s, T*& p) {
+  if (p) pool().put(p, s);
   p = nullptr;
 }
 
@@ -216,6 +293,70 @@ void by_type(const std::vector<D>& v, F f) {
       if (d.ty == t) g.push_back(d);
     f(g, t);
   }
+}
+
+// Exact algorithmic work (flops, bytes at element size es) of a touched-
+// cluster basis change: per touched cluster, the parent transfer block and
+// every block of its M2L window (rows changed by T, columns by S = T^T when
+// the window partner is touched too, or the partner's row block when
+// col_blocks is set and it is not).
+inline std::pair<double, double> txform_work(const TouchXform& a, const std::vector<int>* touch_q,
+                                             const std::vector<int>* tidx, const std::vector<int>& r_old,
+                                             const std::vector<int>& r_new, const std::vector<int>* r_par,
+                                             int ncl, double es) {
+  double f = 0, by = 0;
+  auto blk = [&](int ro, int co, int rn, int cn, bool hasT, bool hasS) {
+    const int rz = hasT ? rn : ro;
+    f += 2.0 * (hasT ? (double)rn * ro * co : 0) + 2.0 * (hasS ? (double)rz * co * cn : 0);
+    by += es * ((double)ro * co + (hasT ? (double)rn * ro : 0) + (hasS ? (double)co * cn : 0) +
+                (double)rz * (hasS ? cn : co));
+  };
+  for (int t = 0; t < a.nt; ++t) {
+    const int q = touch_q ? (*touch_q)[t] : t;
+    const int rq = r_old[q], rn = r_new[t];
+    if (rq == 0) continue;
+    if (a.UP && r_par && (*r_par)[q >> 2] > 0) blk(rq, (*r_par)[q >> 2], rn, 0, true, false);
+    const int qx = demorton_x(q), qy = demorton_y(q);
+    for (int sl = 0; sl < 36; ++sl) {
+      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+      if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+      const int l = morton2(jx, jy);
+      if (l >= ncl || r_old[l] == 0) continue;
+      const int tl = tidx ? (*tidx)[l] : l;
+      blk(rq, r_old[l], rn, tl >= 0 ? r_new[tl] : r_old[l], true, tl >= 0);
+      if (tl < 0 && a.col_blocks) blk(r_old[l], rq, r_old[l], rn, false, true);
+    }
+  }
+  return {f, by};
+}
+
+// Exact work of the far-field weight stacks: per cluster, the R factor of its
+// stacked window column (plus the parent chain rows when a.Z is set).
+inline std::pair<double, double> winstack_work(const WinStack& a, const std::vector<int>& ids,
+                                               const std::vector<int>& r, const std::vector<int>* r_par,
+                                               double es) {
+  double f = 0, by = 0;
+  for (int t = 0; t < a.nt; ++t) {
+    const int q = ids[t], rq = r[q];
+    if (rq == 0) continue;
+    double rows = (a.Z && r_par) ? (*r_par)[q >> 2] : 0;
+    const int qx = demorton_x(q), qy = demorton_y(q);
+    for (int sl = 0; sl < 36; ++sl) {
+      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+      if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
+      rows += r[morton2(jx, jy)];
+    }
+    f += 2.0 * rows * rq * rq;
+    by += es * (rows * rq + (double)a.S * rq * rq);
+  }
+  return {f, by};
+}
+
+// sum_{j < K} (n - j) (m - j), exactly (integer-valued doubles).
+inline double tri_sum(double n, double m, double K) {
+  return K * n * m - (n + m) * K * (K - 1) / 2 + (K - 1) * K * (2 * K - 1) / 6;
 }
 
 struct Stage {
@@ -297,7 +438,7 @@ struct Stage {
           mm = std::max(mm, d.m);
           lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
           const int K = std::min(std::min(d.n, d.m), d.kmax);
-          for (int j = 0; j < K; ++j) f += 4.0 * (d.n - j) * (double)(d.m - j);
+          f += 4.0 * tri_sum(d.n, d.m, K);
           by += 2.0 * es * d.n * (double)d.m;
         }
         flops += f;
@@ -310,7 +451,7 @@ struct Stage {
     by_type(all, [&](const std::vector<FormQDesc>& v, int ty) {
       double f = 0, by = 0;
       for (const auto& d : v) {
-        for (int j = 0; j < d.kk; ++j) f += 4.0 * (d.n - j) * (double)(d.r - j);
+        f += 4.0 * tri_sum(d.n, d.r, d.kk);
         by += esz(ty) * ((double)d.n * d.kk + (double)d.n * d.r);
       }
       flops += f;
@@ -325,70 +466,36 @@ struct Stage {
     if (!v) return nullptr;
     return reinterpret_cast<const int*>(push(v->data(), std::max<size_t>(1, v->size()) * sizeof(int)) + 1);
   }
+  // count = false: the exact work counts are left to the caller (see
+  // txform_work), the launch carries zeros.
   template <class T>
   void touch_xform(TouchXform a, const std::vector<int>* touch_q, const std::vector<int>* tidx,
                    const std::vector<int>& r_old, const std::vector<int>& r_new, const std::vector<int>* r_par,
-                   int ncl) {
+                   int ncl, bool count = true) {
     if (a.nt <= 0) return;
+    double f = 0, by = 0;
+    if (count) std::tie(f, by) = txform_work(a, touch_q, tidx, r_old, r_new, r_par, ncl, sizeof(T));
     a.touch_q = arr(touch_q);
     a.tidx = arr(tidx);
     a.r_old = arr(&r_old);
     a.r_new = arr(&r_new);
     a.r_par = arr(r_par);
-    double f = 0, by = 0;
-    const double es = sizeof(T);
-    auto blk = [&](int ro, int co, int rn, int cn, bool hasT, bool hasS) {
-      const int rz = hasT ? rn : ro;
-      f += 2.0 * (hasT ? (double)rn * ro * co : 0) + 2.0 * (hasS ? (double)rz * co * cn : 0);
-      by += es * ((double)ro * co + (hasT ? (double)rn * ro : 0) + (hasS ? (double)co * cn : 0) +
-                  (double)rz * (hasS ? cn : co));
-    };
-    for (int t = 0; t < a.nt; ++t) {
-      const int q = touch_q ? (*touch_q)[t] : t;
-      const int rq = r_old[q], rn = r_new[t];
-      if (rq == 0) continue;
-      if (a.UP && r_par && (*r_par)[q >> 2] > 0) blk(rq, (*r_par)[q >> 2], rn, 0, true, false);
-      const int qx = demorton_x(q), qy = demorton_y(q);
-      for (int sl = 0; sl < 36; ++sl) {
-        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-        if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
-        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
-        const int l = morton2(jx, jy);
-        if (l >= ncl || r_old[l] == 0) continue;
-        const int tl = tidx ? (*tidx)[l] : l;
-        blk(rq, r_old[l], rn, tl >= 0 ? r_new[tl] : r_old[l], true, tl >= 0);
-        if (tl < 0 && a.col_blocks) blk(r_old[l], rq, r_old[l], rn, false, true);
-      }
-    }
     flops += f;
     op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
   }
   // Far-field weight stacks with device-side block lists (arrays as in
   // touch_xform).
   template <class T>
-  void win_stack(WinStack a, const std::vector<int>& ids, const std::vector<int>& r, const std::vector<int>* r_par) {
+  void win_stack(WinStack a, const std::vector<int>& ids, const std::vector<int>& r, const std::vector<int>* r_par,
+                 bool count = true) {
     if (a.nt <= 0) return;
+    double f = 0, by = 0;
+    if (count) std::tie(f, by) = winstack_work(a, ids, r, r_par, sizeof(T));
+    int rmax = 0;
+    for (int t = 0; t < a.nt; ++t) rmax = std::max(rmax, r[ids[t]]);
     a.ids = arr(&ids);
     a.r = arr(&r);
     a.r_par = arr(r_par);
-    double f = 0, by = 0;
-    int rmax = 0;
-    const double es = sizeof(T);
-    for (int t = 0; t < a.nt; ++t) {
-      const int q = ids[t], rq = r[q];
-      if (rq == 0) continue;
-      rmax = std::max(rmax, rq);
-      double rows = (a.Z && r_par) ? (*r_par)[q >> 2] : 0;
-      const int qx = demorton_x(q), qy = demorton_y(q);
-      for (int sl = 0; sl < 36; ++sl) {
-        const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-        if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
-        if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
-        rows += r[morton2(jx, jy)];
-      }
-      f += 2.0 * rows * rq * rq;
-      by += es * (rows * rq + (double)a.S * rq * rq);
-    }
     flops += f;
     op({OP_WSTACK, push(&a, sizeof(a)), 0, a.nt, rmax, 0, f, by}, tcode<T>());
   }
@@ -521,35 +628,34 @@ struct Arena {
   void init() {
     for (int i = 0; i < 2; ++i) HIP_OK(hipEventCreate(&ev[i]));
   }
-  void release() {
+  void release(hipStream_t s) {
     for (int i = 0; i < 2; ++i) {
-      if (h[i]) (void)hipHostFree(h[i]);
-      dfree(d[i]);
+      if (ev[i]) (void)hipEventSynchronize(ev[i]);
+      pinned().put(h[i], cap[i]);
+      dfree(s, d[i]);
       if (ev[i]) (void)hipEventDestroy(ev[i]);
       h[i] = d[i] = nullptr;
+      cap[i] = 0;
       ev[i] = nullptr;
     }
   }
   char* upload(const std::vector<char>& blob, hipStream_t s) {
     cur ^= 1;
     const size_t need = blob.size();
+    // the previous copy out of this buffer must be done before it is reused
+    HIP_OK(hipEventSynchronize(ev[cur]));
     if (need > cap[cur]) {
-      HIP_OK(hipStreamSynchronize(s));
-      if (h[cur]) (void)hipHostFree(h[cur]);
-      dfree(d[cur]);
+      pinned().put(h[cur], cap[cur]);
+      dfree(s, d[cur]);
+      size_t c = std::max(need, 2 * cap[cur]);
+      c = std::max<size_t>(c, (size_t)8 << 20);
       h[cur] = nullptr;
       d[cur] = nullptr;
-      size_t c = std::max(need, 2 * cap[cur]);
-      c = std::max<size_t>(c, 1 << 20);
-      if (hipHostMalloc(reinterpret_cast<void**>(&h[cur]), c) != hipSuccess) {
-        (void)hipGetLastError();
-        cap[cur] = 0;
-        throw NoMem{};
-      }
-      d[cur] = dalloc<char>(c);
-      cap[cur] = c;
-    } else {
-      HIP_OK(hipEventSynchronize(ev[cur]));
+      cap[cur] = 0;
+      size_t got = 0;
+      h[cur] = pinned().get(c, &got);
+      d[cur] = dalloc<char>(s, got);
+      cap[cur] = got;
     }
     std::memcpy(h[cur], blob.data(), need);
     HIP_OK(hipMemcpyAsync(d[cur], h[cur], need, hipMemcpyHostToDevice, s));
@@ -566,15 +672,14 @@ struct Buf {
   U* need(size_t m, hipStream_t s) {
     const size_t b = std::max<size_t>(m, 1) * sizeof(U);
     if (b > bytes) {
-      HIP_OK(hipStreamSynchronize(s));
-      dfree(p);
-      p = dalloc<char>(b);
+      dfree(s, p);
+      p = dalloc<char>(s, b);
       bytes = b;
     }
     return reinterpret_cast<U*>(p);
   }
-  void release() {
-    dfree(p);
+  void release(hipStream_t s) {
+    dfree(s, p);
     bytes = 0;
   }
 };
@@ -668,18 +773,18 @@ struct Level {
     sUP = (size_t)rpad * rpad;
     sD = (size_t)mpad * mpad;
   }
-  void free_work() {
-    dfree(M);
-    dfree(U);
-    dfree(UP);
-    dfree(Om);
+  void free_work(hipStream_t s) {
+    dfree(s, M);
+    dfree(s, U);
+    dfree(s, UP);
+    dfree(s, Om);
   }
-  void free_all() {
-    free_work();
-    dfree(P);
-    dfree(Qm);
-    dfree(L);
-    dfree(Dinv);
+  void free_all(hipStream_t s) {
+    free_work(s);
+    dfree(s, P);
+    dfree(s, Qm);
+    dfree(s, L);
+    dfree(s, Dinv);
   }
 };
 
@@ -744,6 +849,7 @@ struct Plan final : ifmm_plan {
   size_t rank_cap = 0;
   // stats
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
+  hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
   int max_rank = 0;
   // per-kernel profile (HIP events around each batched launch)
   struct Pending {
@@ -766,7 +872,28 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipEventCreate(&e));
     return e;
   }
+  // Exact work counts that take a pass over every cluster window feed only
+  // the statistics: they are computed later, while the host waits on the
+  // stream anyway.
+  std::vector<std::function<void()>> deferred;
+  template <class F>
+  void count_later(int op_t, F work) {
+    const int slot = family(op_t) + (kF32 ? kOpTypes : 0);
+    deferred.emplace_back([this, slot, work] {
+      const std::pair<double, double> w = work();
+      factor_flops += w.first;
+      if (profile) {
+        prof_flops[slot] += w.first;
+        prof_bytes[slot] += w.second;
+      }
+    });
+  }
+  void run_deferred() {
+    for (auto& f : deferred) f();
+    deferred.clear();
+  }
   void resolve_profile() {
+    run_deferred();
     if (pend.empty()) return;
     HIP_OK(hipStreamSynchronize(s));
     for (const Pending& p : pend) {
@@ -1002,7 +1129,6 @@ struct Plan final : ifmm_plan {
 
   // --------------------------------------------------------------- assembly
   void assemble(const double* d_points_in) {
-    const double t0 = now_ms();
     std::vector<double> pts(2 * N);
     HIP_OK(hipMemcpyAsync(pts.data(), d_points_in, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1013,13 +1139,13 @@ struct Plan final : ifmm_plan {
       spts[2 * a] = pts[2 * perm[a]];
       spts[2 * a + 1] = pts[2 * perm[a] + 1];
     }
-    d_pts = dalloc<double>(2 * N);
-    d_perm = dalloc<int>(N);
-    d_leaf_start = dalloc<int>(nleaf);
-    d_leaf_n = dalloc<int>(nleaf);
-    d_nbr9_leaf = dalloc<int>((size_t)nleaf * 9);
-    d_diag = dalloc<double>(N);
-    d_status = dalloc<Status>(1);
+    d_pts = dalloc<double>(s, 2 * N);
+    d_perm = dalloc<int>(s, N);
+    d_leaf_start = dalloc<int>(s, nleaf);
+    d_leaf_n = dalloc<int>(s, nleaf);
+    d_nbr9_leaf = dalloc<int>(s, (size_t)nleaf * 9);
+    d_diag = dalloc<double>(s, N);
+    d_status = dalloc<Status>(s, 1);
     HIP_OK(hipMemsetAsync(d_status, 0, sizeof(Status), s));
     HIP_OK(hipMemcpyAsync(d_pts, spts.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * N, hipMemcpyHostToDevice, s));
@@ -1027,11 +1153,11 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipMemcpyAsync(d_leaf_n, leaf_n.data(), sizeof(int) * nleaf, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(d_nbr9_leaf, lv[kappa].nbr9.data(), sizeof(int) * nleaf * 9, hipMemcpyHostToDevice, s));
     std::vector<double> E = transfer_host(p);
-    d_E = dalloc<double>(E.size());
+    d_E = dalloc<double>(s, E.size());
     HIP_OK(hipMemcpyAsync(d_E, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, s));
     d_table.assign(kappa + 1, nullptr);
     for (int k = 2; k <= kappa; ++k) {
-      d_table[k] = dalloc<double>((size_t)49 * p2 * p2);
+      d_table[k] = dalloc<double>(s, (size_t)49 * p2 * p2);
       launch_m2l_table(kf, p, 0.5 * size / (1 << k), d_table[k], s);
     }
     // diagonal
@@ -1059,11 +1185,11 @@ struct Plan final : ifmm_plan {
       Lf.r[i] = std::min(Lf.n[i], p2);
     }
     Lf.set_pads(rup(std::max(nmax, 1), 8));
-    Lf.P = dalloc<T>(Lf.sP * 9 * Lf.nc);
-    Lf.Qm = dalloc<T>(Lf.sQ * 9 * Lf.nc);
-    Lf.L = dalloc<T>(Lf.sL * 9 * Lf.nc);
-    Lf.U = dalloc<T>(Lf.sU * Lf.nc);
-    Lf.Dinv = dalloc<double>(Lf.sD * Lf.nc);
+    Lf.P = dalloc<T>(s, Lf.sP * 9 * Lf.nc);
+    Lf.Qm = dalloc<T>(s, Lf.sQ * 9 * Lf.nc);
+    Lf.L = dalloc<T>(s, Lf.sL * 9 * Lf.nc);
+    Lf.U = dalloc<T>(s, Lf.sU * Lf.nc);
+    Lf.Dinv = dalloc<double>(s, Lf.sD * Lf.nc);
     HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, s));
     HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, s));
     launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
@@ -1077,7 +1203,7 @@ struct Plan final : ifmm_plan {
                        Lf.npad, nmax, s);
     // R factors of every level at assembly (r x p^2), kept until M2L is built
     std::vector<double*> Ra(kappa + 1, nullptr);
-    for (int k = 2; k <= kappa; ++k) Ra[k] = dalloc<double>((size_t)lv[k].nc * rpad * p2);
+    for (int k = 2; k <= kappa; ++k) Ra[k] = dalloc<double>(s, (size_t)lv[k].nc * rpad * p2);
     {
       Stage st;
       std::vector<QrDesc> q;
@@ -1095,7 +1221,7 @@ struct Plan final : ifmm_plan {
     // ---- non-leaf levels at assembly: S_P = [R_c E_c], QR, transfer blocks
     for (int k = kappa; k >= 2; --k) {
       Level<T>& L = lv[k];
-      L.UP = dalloc<T>(L.sUP == 0 ? (size_t)rpad * rpad * L.nc : L.sUP * L.nc);
+      L.UP = dalloc<T>(s, L.sUP == 0 ? (size_t)rpad * rpad * L.nc : L.sUP * L.nc);
     }
     for (int k = kappa - 1; k >= 2; --k) {
       Level<T>& L = lv[k];
@@ -1150,7 +1276,7 @@ struct Plan final : ifmm_plan {
     // ---- M2L in orthonormal coordinates: M_il = R_i K(dx,dy) R_l^T
     for (int k = 2; k <= kappa; ++k) {
       Level<T>& L = lv[k];
-      L.M = dalloc<T>(L.sM * 36 * L.nc);
+      L.M = dalloc<T>(s, L.sM * 36 * L.nc);
       HIP_OK(hipMemsetAsync(L.M, 0, sizeof(T) * L.sM * 36 * L.nc, s));
       M2LAssemble a{};
       a.R = Ra[k];
@@ -1180,18 +1306,16 @@ struct Plan final : ifmm_plan {
       st.m2l_assemble<T>(a, L.r, f, by);
       run(st);
     }
-    for (int k = 2; k <= kappa; ++k) dfree(Ra[k]);
+    for (int k = 2; k <= kappa; ++k) dfree(s, Ra[k]);
     // ---- far-field weights of the parent levels, top-down
     for (int k = 2; k < kappa; ++k) {
       Level<T>& L = lv[k];
-      L.Om = dalloc<T>(L.sUP * L.nc);
+      L.Om = dalloc<T>(s, L.sUP * L.nc);
       std::vector<int> ids;
       for (int i = 0; i < L.nc; ++i)
         if (L.r[i] > 0) ids.push_back(i);
       weights(k, ids, L.Om, true);
     }
-    HIP_OK(hipStreamSynchronize(s));
-    t_assembly = now_ms() - t0;
   }
 
   // Omega of the clusters `ids` at level k: R factor of the stacked
@@ -1234,7 +1358,10 @@ struct Plan final : ifmm_plan {
     a.nt = nt;
     a.S = S;
     a.out_by_id = by_id ? 1 : 0;
-    st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr);
+    st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr, false);
+    count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2] {
+      return winstack_work(a, ids, r, par ? &rp : nullptr, sizeof(T));
+    });
     if (S > 1) {
       std::vector<StackQrDesc> s2;
       std::vector<BlkRef> b2;
@@ -1252,7 +1379,6 @@ struct Plan final : ifmm_plan {
 
   // ------------------------------------------------------------ factorisation
   void factor() {
-    const double t0 = now_ms();
     plan.assign(kappa + 1, std::vector<std::vector<Elim>>(9));
     erec.assign(kappa + 1, std::vector<std::vector<ElimRec>>(9));
     for (int k = kappa; k >= 2; --k) {
@@ -1270,14 +1396,14 @@ struct Plan final : ifmm_plan {
         erec_off[k][c] = all.size();
         all.insert(all.end(), erec[k][c].begin(), erec[k][c].end());
       }
-    d_erec = dalloc<ElimRec>(all.size());
+    d_erec = dalloc<ElimRec>(s, all.size());
     HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * all.size(), hipMemcpyHostToDevice, s));
+    run_deferred();
     HIP_OK(hipStreamSynchronize(s));
     resolve_profile();
     Status hs{};
     HIP_OK(hipMemcpy(&hs, d_status, sizeof(Status), hipMemcpyDeviceToHost));
     if (hs.singular) throw 3;
-    t_factor = now_ms() - t0;
   }
 
   ElimArgs elim_args(const Level<T>& L, T* X, T* F, int wpad, int fpad, int nb) {
@@ -1450,10 +1576,9 @@ struct Plan final : ifmm_plan {
     T* A = wsT.need<T>(per * chunk + (size_t)chunk * 2 * kMaxRank, s);
     T* tauA = A + per * chunk;
     if (rank_cap < (size_t)2 * nt) {
-      HIP_OK(hipStreamSynchronize(s));
-      dfree(d_rank);
+      dfree(s, d_rank);
       rank_cap = (size_t)2 * nt;
-      d_rank = dalloc<int>(rank_cap);
+      d_rank = dalloc<int>(s, rank_cap);
     }
     std::vector<int> hr(2 * nt), rnew(nt);
     for (int t0 = 0; t0 < nt; t0 += chunk) {
@@ -1483,6 +1608,7 @@ struct Plan final : ifmm_plan {
       st.add(a);
       st.rrqr(rq);
       run(st);
+      run_deferred();
       HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
       std::vector<FormQDesc> fq;
@@ -1518,7 +1644,11 @@ struct Plan final : ifmm_plan {
       a.sM = L.sM;
       std::vector<int> tq(nt);
       for (int t = 0; t < nt; ++t) tq[t] = touch[t].q;
-      st.touch_xform<T>(a, &tq, &tidx, L.r, rnew, k > 2 ? &lv[k - 1].r : nullptr, L.nc);
+      st.touch_xform<T>(a, &tq, &tidx, L.r, rnew, k > 2 ? &lv[k - 1].r : nullptr, L.nc, false);
+      count_later(OP_TXFORM, [a, tq, tidx, ro = L.r, rnew, rp = k > 2 ? lv[k - 1].r : std::vector<int>(),
+                              par = k > 2, ncl = L.nc] {
+        return txform_work(a, &tq, &tidx, ro, rnew, par ? &rp : nullptr, ncl, sizeof(T));
+      });
     }
     std::vector<AddDesc> cp;
     for (int t = 0; t < nt; ++t) {
@@ -1578,11 +1708,11 @@ struct Plan final : ifmm_plan {
       nm = std::max(nm, o);
     }
     L.set_pads(rup(std::max(nm, 1), 8));
-    L.P = dalloc<T>(L.sP * 9 * L.nc);
-    L.Qm = dalloc<T>(L.sQ * 9 * L.nc);
-    L.L = dalloc<T>(L.sL * 9 * L.nc);
-    L.U = dalloc<T>(L.sU * L.nc);
-    L.Dinv = dalloc<double>(L.sD * L.nc);
+    L.P = dalloc<T>(s, L.sP * 9 * L.nc);
+    L.Qm = dalloc<T>(s, L.sQ * 9 * L.nc);
+    L.L = dalloc<T>(s, L.sL * 9 * L.nc);
+    L.U = dalloc<T>(s, L.sU * L.nc);
+    L.Dinv = dalloc<double>(s, L.sD * L.nc);
     HIP_OK(hipMemsetAsync(L.Qm, 0, sizeof(T) * L.sQ * 9 * L.nc, s));
     HIP_OK(hipMemsetAsync(L.L, 0, sizeof(T) * L.sL * 9 * L.nc, s));
     T* Ru = wsA.need<T>((size_t)L.nc * rpad * rpad, s);
@@ -1629,11 +1759,14 @@ struct Plan final : ifmm_plan {
       a.rpad = rpad;
       a.col_blocks = 0;
       a.sM = L.sM;
-      st.touch_xform<T>(a, nullptr, nullptr, rold, L.r, k - 1 > 2 ? &lv[k - 2].r : nullptr, L.nc);
+      st.touch_xform<T>(a, nullptr, nullptr, rold, L.r, k - 1 > 2 ? &lv[k - 2].r : nullptr, L.nc, false);
+      count_later(OP_TXFORM, [a, rold, rn = L.r, rp = k - 1 > 2 ? lv[k - 2].r : std::vector<int>(),
+                              par = k - 1 > 2, ncl = L.nc] {
+        return txform_work(a, nullptr, nullptr, rold, rn, par ? &rp : nullptr, ncl, sizeof(T));
+      });
     }
     run(st);
-    HIP_OK(hipStreamSynchronize(s));
-    C.free_work();
+    C.free_work(s);
   }
 
   void top() {
@@ -1647,7 +1780,7 @@ struct Plan final : ifmm_plan {
       }
     top_m = top_off.back();
     if (top_m == 0) return;
-    d_top = dalloc<double>((size_t)top_m * top_m);
+    d_top = dalloc<double>(s, (size_t)top_m * top_m);
     Stage st;
     std::vector<AddDesc> a;
     for (size_t x = 0; x < top_ids.size(); ++x)
@@ -1659,7 +1792,7 @@ struct Plan final : ifmm_plan {
     st.add(a);
     plan_inverse(st, {InvDesc{d_top, top_m, top_m}});
     run(st);
-    L.free_work();
+    L.free_work(s);
   }
 
   // ------------------------------------------------------------------ solve
@@ -1819,12 +1952,12 @@ struct Plan final : ifmm_plan {
     st.add(a);
     st.flops = 0.0;  // solve work is not factorisation work
     if (splans.size() >= 4) {
-      dfree(splans.front().d);
+      dfree(s, splans.front().d);
       splans.erase(splans.begin());
     }
     splans.push_back(SolvePlan{bt, xt, base, nrhs, std::move(st), nullptr});
     SolvePlan& sp = splans.back();
-    sp.d = dalloc<char>(sp.st.blob.size());
+    sp.d = dalloc<char>(s, sp.st.blob.size());
     HIP_OK(hipMemcpyAsync(sp.d, sp.st.blob.data(), sp.st.blob.size(), hipMemcpyHostToDevice, s));
     launch_ops(sp.st, sp.d);
   }
@@ -1832,8 +1965,20 @@ struct Plan final : ifmm_plan {
   // ---------------------------------------------------------- entry points
   void build(const double* points) override {
     arena.init();
+    for (hipEvent_t& e : ev_t) HIP_OK(hipEventCreate(&e));
+    HIP_OK(hipEventRecord(ev_t[0], s));
     assemble(points);
+    HIP_OK(hipEventRecord(ev_t[1], s));
     factor();
+    HIP_OK(hipEventRecord(ev_t[2], s));
+    HIP_OK(hipStreamSynchronize(s));
+    // stream-timeline times: assembly ends when its last kernel does (the
+    // host plans the factorisation meanwhile)
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ev_t[0], ev_t[1]));
+    t_assembly = ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev_t[1], ev_t[2]));
+    t_factor = ms;
   }
 
   void matvec(const double* x, double* y, int nrhs) override {
@@ -1976,25 +2121,25 @@ struct Plan final : ifmm_plan {
   }
 
   void release() override {
-    for (auto& L : lv) L.free_all();
-    for (auto& t : d_table) dfree(t);
-    dfree(d_pts);
-    dfree(d_perm);
-    dfree(d_leaf_start);
-    dfree(d_leaf_n);
-    dfree(d_nbr9_leaf);
-    dfree(d_diag);
-    dfree(d_E);
-    dfree(d_top);
-    dfree(d_erec);
-    for (SolvePlan& sp : splans) dfree(sp.d);
+    for (auto& L : lv) L.free_all(s);
+    for (auto& t : d_table) dfree(s, t);
+    dfree(s, d_pts);
+    dfree(s, d_perm);
+    dfree(s, d_leaf_start);
+    dfree(s, d_leaf_n);
+    dfree(s, d_nbr9_leaf);
+    dfree(s, d_diag);
+    dfree(s, d_E);
+    dfree(s, d_top);
+    dfree(s, d_erec);
+    for (SolvePlan& sp : splans) dfree(s, sp.d);
     splans.clear();
-    dfree(d_status);
-    dfree(d_rank);
+    dfree(s, d_status);
+    dfree(s, d_rank);
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
                    &wsSeg})
-      b->release();
-    arena.release();
+      b->release(s);
+    arena.release(s);
     for (const Pending& p : pend) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -2002,6 +2147,10 @@ struct Plan final : ifmm_plan {
     pend.clear();
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     evpool.clear();
+    for (hipEvent_t& e : ev_t) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   }
 };
 
