@@ -85,7 +85,9 @@ typedef struct {
   int refine_maxit;    /* refinement sweeps (0 = 30) */
   double box_lo[2];    /* root box [lo, lo + size]^2 containing every point */
   double box_size;     /* 0 = unit square [0,1]^2 */
-  int profile;         /* 1: time every batched kernel launch with HIP events (ifmm_stats) */
+  int profile;         /* time batched kernel launches with HIP events (ifmm_stats): 0 off,
+                          1 every family, else bit f + 1 set times family f only (the
+                          families of ifmm_stats_t.kernel_*; e.g. 1 << 9: elimination steps) */
   int precision;       /* ifmm_precision of the factor (0 = FP64) */
 } ifmm_options;
 

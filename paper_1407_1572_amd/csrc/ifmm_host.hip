@@ -811,7 +811,9 @@ struct ifmm_plan {
   double lox = 0.0, loy = 0.0, size = 1.0;
   double refine_tol = 0.0;
   int refine_maxit = 30;
-  bool profile = false;
+  // 0: off; 1: every launch family; otherwise bit f + 1 times family f only
+  int profile = 0;
+  bool timed(int fam) const { return profile == 1 || ((profile >> (fam + 1)) & 1) != 0; }
   virtual ~ifmm_plan() = default;
   virtual void build(const double* points) = 0;  // assembly + Algorithm 1
   virtual ifmm_status solve(const double* b, double* x, int nrhs, ifmm_solve_info* info) = 0;
@@ -879,10 +881,11 @@ struct Plan final : ifmm_plan {
   template <class F>
   void count_later(int op_t, F work) {
     const int slot = family(op_t) + (kF32 ? kOpTypes : 0);
-    deferred.emplace_back([this, slot, work] {
+    const bool tm = profile && timed(family(op_t));
+    deferred.emplace_back([this, slot, tm, work] {
       const std::pair<double, double> w = work();
       factor_flops += w.first;
-      if (profile) {
+      if (tm) {
         prof_flops[slot] += w.first;
         prof_bytes[slot] += w.second;
       }
@@ -921,7 +924,8 @@ struct Plan final : ifmm_plan {
   void launch_ops(const Stage& st, char* d) {
     for (const Op& op : st.ops) {
       hipEvent_t ea = nullptr, eb = nullptr;
-      if (profile) {
+      const bool tm = profile && timed(family(op.t));
+      if (tm) {
         ea = get_event();
         eb = get_event();
         HIP_OK(hipEventRecord(ea, s));
@@ -1016,7 +1020,7 @@ struct Plan final : ifmm_plan {
           break;
       }
       HIP_OK(hipGetLastError());
-      if (profile) {
+      if (tm) {
         HIP_OK(hipEventRecord(eb, s));
         const bool f32 = op.t == OP_GEMM ? (op.ty & 3) == 3 : op.t == OP_ADD ? (op.ty & 2) != 0 : op.ty != 0;  // elim: block type
         pend.push_back({family(op.t) + (f32 ? kOpTypes : 0), ea, eb, op.flops, op.bytes});
@@ -2212,7 +2216,7 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
     h->size = opt->box_size;
   }
   if (opt) {
-    h->profile = opt->profile != 0;
+    h->profile = opt->profile;
     h->refine_tol = opt->refine_tol;
     h->refine_maxit = opt->refine_maxit > 0 ? opt->refine_maxit : 30;
   }

@@ -57,6 +57,17 @@ KERNEL_FAMILIES = ["gemm", "add", "unused2", "qr", "rrqr", "formq", "stackqr", "
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
+def profile_mask(profile) -> int:
+    """ifmm_options.profile from True/False (every family / off) or an
+    iterable of family names (KERNEL_FAMILIES): only those are timed."""
+    if profile is True or profile is False or profile is None:
+        return 1 if profile else 0
+    mask = 0
+    for name in profile:
+        mask |= 1 << (KERNEL_FAMILIES.index(name) + 1)
+    return mask
+
+
 _LIBS: dict = {}
 
 
@@ -117,7 +128,7 @@ class IFMMSolver:
     def __init__(self, points, kernel: str = "inv_r", ell: float = 0.0, diag: str = "rowsum",
                  c0: float = 1.0, eps: float = 1e-8, leaf_size: int = 64, rank: int = 36,
                  r_max: int = 0, refine_tol: float = 0.0, refine_maxit: int = 30,
-                 box=None, profile: bool = False, precision: str = "fp64",
+                 box=None, profile=False, precision: str = "fp64",
                  lib_path: str | None = None):
         import torch
         self._lib = load(lib_path)
@@ -131,7 +142,7 @@ class IFMMSolver:
         o.r_max = int(r_max)
         o.refine_tol = float(refine_tol)
         o.refine_maxit = int(refine_maxit)
-        o.profile = 1 if profile else 0
+        o.profile = profile_mask(profile)
         o.precision = PRECISIONS[precision]
         if box is not None:
             o.box_lo[0], o.box_lo[1], o.box_size = float(box[0]), float(box[1]), float(box[2])

@@ -135,3 +135,25 @@ def test_multi_rhs_refinement_and_empty_leaves(torch_dev):
         xj = s.solve(torch.from_numpy(B[:, j].copy()).to(dev)).cpu().numpy()
         assert _rel(xj, X[:, j]) < 1e-12
     s.close()
+
+
+def test_profile_family_mask(torch_dev):
+    _say("[gpu] profile: every family, then the elimination steps only")
+    torch, dev = torch_dev
+    from paper_1407_1572_amd import IFMMSolver
+    pts = workloads.uniform(4096, 1003)
+    tp = torch.from_numpy(pts).to(dev)
+    b = torch.from_numpy(workloads.rhs(4096, 1, 2001)[:, 0].copy()).to(dev)
+    counts = {}
+    for prof in (True, ["elim"]):
+        s = IFMMSolver(tp, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, profile=prof)
+        s.solve(b)
+        k = {n: v for n, v in s.stats()["kernels"].items() if v["launches"] > 0}
+        counts[str(prof)] = k
+        s.close()
+    full, only = counts["True"], counts["['elim']"]
+    assert {"elim", "inverse", "rrqr", "solve"} <= set(full)
+    assert set(only) == {"elim"}
+    # the same launches, with the same algorithmic counts
+    assert only["elim"]["launches"] == full["elim"]["launches"]
+    assert only["elim"]["flops"] == full["elim"]["flops"] and only["elim"]["bytes"] == full["elim"]["bytes"]
