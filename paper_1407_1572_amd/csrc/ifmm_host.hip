@@ -242,7 +242,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJLDS, OP_SOLVE, OP_M2LASM };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 elim, 9 touched-cluster
 // transform, 10 window stacked R, 11 solve sweeps.
@@ -252,7 +252,7 @@ inline int family(int t) {
     case OP_GJPANEL:
     case OP_GJREST:
     case OP_GJUNPERM:
-    case OP_GJLDS: return 7;
+    case OP_GJREG: return 7;
     case OP_ELIM: return 8;
     case OP_TXFORM: return 9;
     case OP_WSTACK: return 10;
@@ -552,7 +552,7 @@ struct Stage {
     op({OP_STACKQR, o1, o2, (int)v.size(), rr, 0, f, by}, ty);
   }
   // Whole-matrix LDS Gauss-Jordan (FP64).
-  void inv_lds(const std::vector<InvDesc>& v) {
+  void inv_reg(const std::vector<InvDesc>& v) {
     if (v.empty()) return;
     int mm = 0;
     double f = 0, by = 0;
@@ -562,7 +562,7 @@ struct Stage {
       by += 16.0 * d.m * (double)d.m;
     }
     flops += f;
-    op({OP_GJLDS, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by}, 0);
+    op({OP_GJREG, push(v.data(), v.size() * sizeof(InvDesc)), 0, (int)v.size(), mm, 0, f, by}, 0);
   }
   // Blocked Gauss-Jordan inverse (FP64) of every matrix in v (panels of nb
   // columns); piv (nd x maxm ints) and tmp (nd x nb x maxm doubles) are
@@ -1004,7 +1004,8 @@ struct Plan final : ifmm_plan {
           launch_stackqr_win(a, op.a, op.ty, s);
           break;
         }
-        case OP_GJLDS: launch_gj_lds(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
+        case OP_XFORM: break;  // family 2 has no launches
+        case OP_GJREG: launch_gj_reg(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
         case OP_GJPANEL:
           launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
@@ -1029,15 +1030,19 @@ struct Plan final : ifmm_plan {
     }
   }
 
-  // Inverse of the pivot blocks: blocked Gauss-Jordan.
+  // Inverse of the pivot blocks (Gauss-Jordan with partial pivoting).
   Buf wsInvT, wsInvP;
-  // Matrices that fit in LDS are inverted whole by one workgroup each; the
-  // rest by panels.
+  // Matrices up to kGjRegMax are inverted whole in registers, one workgroup
+  // each, in launches of one size class (the class sets the workgroup
+  // shape); larger ones by panels.
   void plan_inverse(Stage& st, const std::vector<InvDesc>& all) {
     if (all.empty()) return;
-    std::vector<InvDesc> small, big;
-    for (const auto& d : all) (gj_lds_bytes(d.m) <= kGjLdsBytes ? small : big).push_back(d);
-    st.inv_lds(small);
+    std::vector<InvDesc> cls[3], big;
+    for (const auto& d : all) {
+      if (d.m > kGjRegMax) big.push_back(d);
+      else cls[d.m <= 64 ? 0 : d.m <= 128 ? 1 : 2].push_back(d);
+    }
+    for (const auto& c : cls) st.inv_reg(c);
     if (big.empty()) return;
     int mm = 0;
     for (const auto& d : big) mm = std::max(mm, d.m);

@@ -341,11 +341,10 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_
 void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
-// Whole-matrix FP64 Gauss-Jordan inverse in LDS for matrices with
-// gj_lds_bytes(m) <= kGjLdsBytes.
-constexpr size_t kGjLdsBytes = 159 * 1024;
-size_t gj_lds_bytes(int m);
-void launch_gj_lds(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
+// Whole-matrix FP64 Gauss-Jordan inverse with the matrix in registers (one
+// workgroup per matrix), every m <= kGjRegMax.
+constexpr int kGjRegMax = 192;
+void launch_gj_reg(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
 // Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s);

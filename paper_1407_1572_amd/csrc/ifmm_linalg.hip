@@ -1170,121 +1170,124 @@ __global__ __launch_bounds__(WG) void k_gj_panel(const InvDesc* __restrict__ des
   }
 }
 
-// Whole-matrix Gauss-Jordan in LDS (one 512-thread workgroup per matrix, for
-// matrices whose m (m + 1) doubles fit): per step one wave picks the pivot,
-// then rows j and p are swapped outside column j (that column is rewritten by
-// the step anyway), the pivot row is scaled and every other row eliminated.
-// The column permutation is undone while the result is written back.
-constexpr int GJ_WG = 512;
-constexpr int kGjRows = 3;  // rows per lane: m <= 192 covers every LDS-sized matrix
-__global__ __launch_bounds__(GJ_WG) void k_gj_lds(const InvDesc* __restrict__ descs, Status* st) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// Whole-matrix Gauss-Jordan with the matrix in registers (one workgroup per
+// matrix, m <= min(TR RA, TC RB)): thread (tr, tc) of a TR x TC grid (rows
+// fastest) holds rows tr + TR a and columns tc + TC b.  Rows are never
+// swapped: step j takes as pivot the largest |M(i, j)| over the rows not yet
+// used (the smallest i on ties), publishes column j and the pivot row through
+// LDS (double-buffered, two barriers per step) and every thread updates its
+// tile.  With piv[j] the pivot row of step j and pinv its inverse, the
+// inverse is A^-1(pinv[i], piv[c]) = M(i, c), applied in the write-back.
+template <int TR, int TC, int RA, int RB>
+__global__ __launch_bounds__(TR * TC) void k_gj_reg(const InvDesc* __restrict__ descs, Status* st) {
+  static_assert(RA <= 32, "row-slot mask");
+  static_assert(TR <= WAVE && WAVE % TR == 0, "a column's owners share one wave");
+  __shared__ double fcol[2][TR * RA];
+  __shared__ double prow[2][TC * RB];
+  __shared__ int pbuf[2];
+  __shared__ int piv[TC * RB];
+  __shared__ int pinv[TR * RA];
   const InvDesc d = descs[blockIdx.x];
   const int m = d.m;
-  if (d.A == nullptr || m == 0) return;
-  const int ld = m + 1;
-  double* A = reinterpret_cast<double*>(smem);
-  double* f = A + (size_t)m * ld;
-  double* rowj = f + m;
-  int* src = reinterpret_cast<int*>(rowj + m);
-  int* piv = src + m;
-  __shared__ int p_s;
-  __shared__ double inv_s;
-  // wave w owns columns w, w + 8, ...; its lanes run down the rows
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  constexpr int NW = GJ_WG / WAVE;
-  for (int c = w; c < m; c += NW)
-    for (int i = lane; i < m; i += WAVE) A[i + c * ld] = d.A[i + (size_t)c * d.lda];
-  __syncthreads();
+  if (d.A == nullptr || m <= 0) return;
+  const int tr = threadIdx.x % TR, tc = threadIdx.x / TR;
+  const size_t lda = d.lda;
+  double M[RA][RB];
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = tr + TR * a, c = tc + TC * b;
+      M[a][b] = (i < m && c < m) ? d.A[i + c * lda] : 0.0;
+    }
+  unsigned used = 0;  // bit a: row tr + TR a has been a pivot
   bool bad = false;
-  for (int j = 0; j < m; ++j) {
-    if (threadIdx.x < WAVE) {  // pivot: largest |A(i, j)|, i >= j, first on ties
-      double bv = -1.0;
-      int bi = m;
-      for (int i = j + threadIdx.x; i < m; i += WAVE) {
-        const double a = fabs(A[i + j * ld]);
-        if (a > bv) { bv = a; bi = i; }
-      }
-      for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, WAVE);
-        const int oi = __shfl_xor(bi, o, WAVE);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (threadIdx.x == 0) {
-        p_s = bi;
-        piv[j] = bi;
-        inv_s = 1.0 / A[bi + j * ld];
-      }
-    }
-    __syncthreads();
-    const int p = p_s;
-    const double inv = inv_s;
-    if (A[p + j * ld] == 0.0) bad = true;
-    for (int c = threadIdx.x; c < m; c += GJ_WG) {
-      if (c == j) {
-        rowj[c] = inv;
-        continue;
-      }
-      const double ap = A[p + c * ld];
-      if (p != j) A[p + c * ld] = A[j + c * ld];
-      A[j + c * ld] = ap;
-      rowj[c] = ap * inv;
-    }
-    for (int i = threadIdx.x; i < m; i += GJ_WG) f[i] = i == p ? A[j + j * ld] : A[i + j * ld];
-    __syncthreads();
-    // each lane keeps the multipliers of its rows (lane, lane + 64, ...) in
-    // registers; per element one LDS read and one write remain
-    double fr[kGjRows];
 #pragma unroll
-    for (int t = 0; t < kGjRows; ++t) {
-      const int i = lane + WAVE * t;
-      fr[t] = i < m ? f[i] : 0.0;
-    }
-    // four columns per pass: all loads issue before the first store, so the
-    // LDS latency of one column overlaps the others
-    constexpr int CU4 = 4;
-    for (int c0 = w; c0 < m; c0 += CU4 * NW) {
-      double v[CU4][kGjRows], rc[CU4];
+  for (int bj = 0; bj < RB; ++bj) {
+    for (int jj = 0; jj < TC; ++jj) {
+      const int j = bj * TC + jj;
+      if (j >= m) break;
+      const int buf = j & 1;
+      // the TR lanes holding column j publish it and pick the pivot
+      if (tc == jj) {
+        double bv = -1.0;
+        int bi = 1 << 30;
 #pragma unroll
-      for (int u = 0; u < CU4; ++u) {
-        const int c = c0 + u * NW;
-        rc[u] = c < m ? rowj[c] : 0.0;
-#pragma unroll
-        for (int t = 0; t < kGjRows; ++t) {
-          const int i = lane + WAVE * t;
-          v[u][t] = (c < m && i < m) ? A[i + c * ld] : 0.0;
+        for (int a = 0; a < RA; ++a) {
+          const int i = tr + TR * a;
+          fcol[buf][i] = M[a][bj];
+          double v = fabs(M[a][bj]);
+          if (v != v) v = HUGE_VAL;  // NaN: a total order, and a valid index
+          if (i < m && !((used >> a) & 1u) && (v > bv || bi >= m)) {
+            bv = v;
+            bi = i;
+          }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < CU4; ++u) {
-        const int c = c0 + u * NW;
-        if (c >= m) continue;
-        double* col = A + c * ld;
-#pragma unroll
-        for (int t = 0; t < kGjRows; ++t) {
-          const int i = lane + WAVE * t;
-          if (i >= m) continue;
-          double x;
-          if (c == j) x = i == j ? inv : -fr[t] * inv;
-          else x = i == j ? rc[u] : fma(-fr[t], rc[u], v[u][t]);
-          col[i] = x;
+        for (int o = 1; o < TR; o <<= 1) {
+          const double ov = __shfl_xor(bv, o, WAVE);
+          const int oi = __shfl_xor(bi, o, WAVE);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
         }
+        if (tr == 0) pbuf[buf] = bi;
       }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < m; ++c) src[c] = c;
-    for (int j = m - 1; j >= 0; --j) {
-      const int t = src[j];
-      src[j] = src[piv[j]];
-      src[piv[j]] = t;
+      __syncthreads();
+      const int p = pbuf[buf];
+      const int tp = p % TR, ap = p / TR;
+      if (tr == tp) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == ap) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) prow[buf][tc + TC * b] = M[a][b];
+            used |= 1u << a;
+          }
+      }
+      if (threadIdx.x == 0) piv[j] = p;
+      __syncthreads();
+      const double pv = fcol[buf][p];
+      if (pv == 0.0) bad = true;
+      const double ip = 1.0 / pv;
+      double rb[RB], fa[RA];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) rb[b] = prow[buf][tc + TC * b] * ip;
+      if (tc == jj) rb[bj] = ip;
+#pragma unroll
+      for (int a = 0; a < RA; ++a) fa[a] = fcol[buf][tr + TR * a];
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) M[a][b] = fma(-fa[a], rb[b], M[a][b]);
+      if (tc == jj) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a) M[a][bj] = -fa[a] * ip;
+      }
+      if (tr == tp) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == ap) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) M[a][b] = rb[b];
+          }
+      }
     }
   }
   __syncthreads();
-  for (int c = w; c < m; c += NW) {
-    const double* col = A + src[c] * ld;
-    for (int i = lane; i < m; i += WAVE) d.A[i + (size_t)c * d.lda] = col[i];
+  for (int j = threadIdx.x; j < m; j += TR * TC) pinv[piv[j]] = j;
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int c = tc + TC * b;
+    if (c >= m) continue;
+    double* col = d.A + (size_t)piv[c] * lda;
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const int i = tr + TR * a;
+      if (i < m) col[pinv[i]] = M[a][b];
+    }
   }
   if (bad && threadIdx.x == 0 && st) {
     if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
@@ -1537,15 +1540,13 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
   }
 }
 
-size_t gj_lds_bytes(int m) {
-  return (size_t)m * (m + 1) * sizeof(double) + 2 * (size_t)m * sizeof(double) + 2 * (size_t)m * sizeof(int);
-}
-
-void launch_gj_lds(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
+// Register Gauss-Jordan by size class: m <= 64 one wave, m <= 128 four waves,
+// m <= 192 eight waves (kGjRegMax).
+void launch_gj_reg(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
   if (nd <= 0 || max_m <= 0) return;
-  static bool raised = false;
-  allow_lds(reinterpret_cast<const void*>(k_gj_lds), raised, kGjLdsBytes);
-  hipLaunchKernelGGL(k_gj_lds, dim3(nd), dim3(GJ_WG), gj_lds_bytes(max_m), s, d, st);
+  if (max_m <= 64) hipLaunchKernelGGL((k_gj_reg<8, 8, 8, 8>), dim3(nd), dim3(64), 0, s, d, st);
+  else if (max_m <= 128) hipLaunchKernelGGL((k_gj_reg<16, 16, 8, 8>), dim3(nd), dim3(256), 0, s, d, st);
+  else if (max_m <= kGjRegMax) hipLaunchKernelGGL((k_gj_reg<32, 16, 6, 12>), dim3(nd), dim3(512), 0, s, d, st);
 }
 
 void launch_gj_rest(const InvDesc* d, int nd, int max_m, int j0, int nb, const int* piv, int ldp,
