@@ -1294,6 +1294,138 @@ __global__ __launch_bounds__(TR * TC) void k_gj_reg(const InvDesc* __restrict__ 
   }
 }
 
+// The same panel steps with the panel in registers (m <= 64 RA, nb <= 8 RB):
+// thread (tr, tc), tr < 64 the lane of wave tc, holds rows tr + 64 a and panel
+// columns j0 + tc + 8 b.  Each step: the wave holding column j picks the pivot
+// (largest |A(i, j)| over i >= j, smallest i on ties) and publishes the column;
+// rows p and j are published; after one more barrier every thread updates its
+// tile and rows j and p take their swapped, scaled / eliminated contents.
+template <int RA, int RB>
+__global__ __launch_bounds__(512) void k_gj_panel_reg(const InvDesc* __restrict__ descs, int j0, int nb,
+                                                      int* __restrict__ piv_all, int ldp, Status* st) {
+  constexpr int TR = WAVE, TC = 8;
+  static_assert(TR * TC == 512, "eight waves");
+  __shared__ double fcol[2][TR * RA];
+  __shared__ double prow[2][TC * RB];
+  __shared__ double rowj[2][TC * RB];
+  __shared__ int pbuf[2];
+  const InvDesc d = descs[blockIdx.x];
+  const int m = d.m;
+  if (d.A == nullptr || j0 >= m) return;
+  const int nbe = min(nb, m - j0);
+  const int tr = threadIdx.x % TR, tc = threadIdx.x / TR;
+  const size_t lda = d.lda;
+  int* piv = piv_all + (size_t)blockIdx.x * ldp;
+  double M[RA][RB];
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = tr + TR * a, t = tc + TC * b;
+      M[a][b] = (i < m && t < nbe) ? d.A[i + (size_t)(j0 + t) * lda] : 0.0;
+    }
+  bool bad = false;
+#pragma unroll
+  for (int bt = 0; bt < RB; ++bt) {
+    for (int tt = 0; tt < TC; ++tt) {
+      const int t = bt * TC + tt;
+      if (t >= nbe) break;
+      const int j = j0 + t, buf = t & 1;
+      if (tc == tt) {
+        // key: |A(i, t)| as unsigned bits + 1 (NaN above inf), 0 for rows < j
+        unsigned long long bk = 0;
+        int bi = m;
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+          const int i = tr + TR * a;
+          fcol[buf][i] = M[a][bt];
+          const unsigned long long k =
+              (i >= j && i < m) ? ((unsigned long long)__double_as_longlong(M[a][bt]) & 0x7fffffffffffffffull) + 1 : 0;
+          if (k > bk) {
+            bk = k;
+            bi = i;
+          }
+        }
+#pragma unroll
+        for (int o = 1; o < TR; o <<= 1) {
+          const unsigned long long ok = __shfl_xor(bk, o, WAVE);
+          const int oi = __shfl_xor(bi, o, WAVE);
+          if (ok > bk || (ok == bk && oi < bi)) {
+            bk = ok;
+            bi = oi;
+          }
+        }
+        if (tr == 0) pbuf[buf] = bi < m ? bi : j;
+      }
+      __syncthreads();
+      const int p = pbuf[buf];
+      const int tp = p % TR, ap = p / TR, tj = j % TR, aj = j / TR;
+      if (tr == tp) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == ap) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) prow[buf][tc + TC * b] = M[a][b];
+          }
+      }
+      if (tr == tj) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == aj) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) rowj[buf][tc + TC * b] = M[a][b];
+          }
+      }
+      if (threadIdx.x == 0) piv[j] = p;
+      __syncthreads();
+      const double pv = fcol[buf][p], fj = fcol[buf][j];
+      if (pv == 0.0) bad = true;
+      const double ip = 1.0 / pv;
+      double rb[RB], fa[RA];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) rb[b] = prow[buf][tc + TC * b] * ip;
+      if (tc == tt) rb[bt] = ip;
+#pragma unroll
+      for (int a = 0; a < RA; ++a) fa[a] = fcol[buf][tr + TR * a];
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) M[a][b] = fma(-fa[a], rb[b], M[a][b]);
+      if (tc == tt) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a) M[a][bt] = -fa[a] * ip;
+      }
+      if (p != j && tr == tp) {  // row p takes the old row j, eliminated
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == ap) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) M[a][b] = fma(-fj, rb[b], rowj[buf][tc + TC * b]);
+            if (tc == tt) M[a][bt] = -fj * ip;
+          }
+      }
+      if (tr == tj) {  // row j takes the scaled pivot row
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          if (a == aj) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) M[a][b] = rb[b];
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = tr + TR * a, t = tc + TC * b;
+      if (i < m && t < nbe) d.A[i + (size_t)(j0 + t) * lda] = M[a][b];
+    }
+  if (bad && threadIdx.x == 0 && st) {
+    if (atomicExch(&st->singular, 1) == 0) st->bad_cluster = blockIdx.x;
+  }
+}
+
 // Row swaps of the panel applied to every other column, and rows j0..j0+nb-1
 // of those columns copied to tmp (nb x m, ld nb).
 __global__ __launch_bounds__(WG) void k_gj_rest(const InvDesc* __restrict__ descs, int j0, int nb,
@@ -1529,6 +1661,13 @@ void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, in
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s) {
   if (nd <= 0) return;
+  if (nb <= 32 && max_m <= 768) {
+    if (max_m <= 256) hipLaunchKernelGGL((k_gj_panel_reg<4, 4>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    else if (max_m <= 384) hipLaunchKernelGGL((k_gj_panel_reg<6, 4>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    else if (max_m <= 512) hipLaunchKernelGGL((k_gj_panel_reg<8, 4>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    else hipLaunchKernelGGL((k_gj_panel_reg<12, 4>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    return;
+  }
   const size_t lds = sizeof(double) * (size_t)max_m * (nb + 1);
   if (lds <= 150 * 1024) {
     static bool raised = false;
