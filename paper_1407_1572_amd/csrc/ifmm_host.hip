@@ -242,7 +242,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 elim, 9 touched-cluster
 // transform, 10 window stacked R, 11 solve sweeps.
@@ -259,6 +259,7 @@ inline int family(int t) {
     case OP_TRANS: return 1;
     case OP_SOLVE: return 11;
     case OP_M2LASM: return 0;
+    case OP_FORMQRR: return 5;
     default: return t;
   }
 }
@@ -418,46 +419,64 @@ struct Stage {
       op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
     });
   }
-  // Pivoted QRs: matrices that fit in LDS go to the LDS kernel (b = 1); the
-  // rest are worked on in place (b = 0).
+  // Pivoted QRs: matrices whose columns fit the registers of one thread each
+  // go to the register kernel (b = 2, which also forms Q), by row class;
+  // the rest to the LDS kernel (b = 1) or in place (b = 0), followed by the
+  // Q formation where Q is asked for.  Q's work is counted once the ranks
+  // are known (rrqr_q_work).
+  static bool rrqr_in_regs(const RrqrDesc& d) {
+    const int nr = rrqr_reg_rows(d.n, d.ty);
+    return nr > 0 && d.m <= kRrqrRegCols && rrqr_reg_lds(nr, d.kmax, d.ty) <= 144 * 1024;
+  }
   void rrqr(const std::vector<RrqrDesc>& all) {
     by_type(all, [&](const std::vector<RrqrDesc>& byt, int ty) {
       const size_t es = ty ? sizeof(float) : sizeof(double);
-      std::vector<RrqrDesc> grp[2];
+      std::vector<RrqrDesc> reg[5], grp[2];
       for (const auto& d : byt) {
-        const size_t need = es * ((size_t)(d.n + 1) * d.m + d.m);
-        grp[need <= kRrqrLdsBytes ? 1 : 0].push_back(d);
+        if (rrqr_in_regs(d)) {
+          reg[rrqr_reg_rows(d.n, ty) / 32].push_back(d);
+        } else {
+          const size_t need = es * ((size_t)(d.n + 1) * d.m + d.m);
+          grp[need <= kRrqrLdsBytes ? 1 : 0].push_back(d);
+        }
       }
-      for (int g = 0; g < 2; ++g) {
-        const auto& v = grp[g];
-        if (v.empty()) continue;
-        int mm = 0;
-        size_t lds = 0;
-        double f = 0, by = 0;
+      auto work = [&](const std::vector<RrqrDesc>& v, double& f, double& by, int& mm) {
         for (const auto& d : v) {
           mm = std::max(mm, d.m);
-          lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
           const int K = std::min(std::min(d.n, d.m), d.kmax);
           f += 4.0 * tri_sum(d.n, d.m, K);
           by += 2.0 * es * d.n * (double)d.m;
         }
         flops += f;
+      };
+      for (int c = 1; c <= 4; ++c) {
+        const auto& v = reg[c];
+        if (v.empty()) continue;
+        double f = 0, by = 0;
+        int mm = 0, km = 0;
+        work(v, f, by, mm);
+        for (const auto& d : v) km = std::max(km, d.kmax);
+        Op o{OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), (size_t)(32 * c), (int)v.size(), mm, 2, f, by};
+        o.off2b = (size_t)km;
+        op(o, ty);
+      }
+      for (int g = 0; g < 2; ++g) {
+        const auto& v = grp[g];
+        if (v.empty()) continue;
+        size_t lds = 0;
+        double f = 0, by = 0;
+        int mm = 0;
+        work(v, f, by, mm);
+        for (const auto& d : v) lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
         const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
         op({OP_RRQR, o, g == 1 ? (size_t)lds : 0, (int)v.size(), mm, g, f, by}, ty);
+        bool q = false;
+        for (const auto& d : v) q |= d.Q != nullptr;
+        if (q) op({OP_FORMQRR, o, 0, (int)v.size(), 0, 0, 0.0, 0.0}, ty);
       }
     });
   }
-  void formq(const std::vector<FormQDesc>& all) {
-    by_type(all, [&](const std::vector<FormQDesc>& v, int ty) {
-      double f = 0, by = 0;
-      for (const auto& d : v) {
-        f += 4.0 * tri_sum(d.n, d.r, d.kk);
-        by += esz(ty) * ((double)d.n * d.kk + (double)d.n * d.r);
-      }
-      flops += f;
-      op({OP_FORMQ, push(v.data(), v.size() * sizeof(FormQDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
-    });
-  }
+
   // Touched-cluster basis change (geometry on the device).  The int arrays
   // travel in the blob; the pointer fields of the stored TouchXform hold
   // their blob offsets + 1 (0 = null) and are rebased at launch.  flops and
@@ -891,6 +910,14 @@ struct Plan final : ifmm_plan {
       }
     });
   }
+  // Work counted after its launch (it depends on results read back).
+  void add_count(int fam, double f, double by) {
+    factor_flops += f;
+    if (profile && timed(fam)) {
+      prof_flops[fam + (kF32 ? kOpTypes : 0)] += f;
+      prof_bytes[fam + (kF32 ? kOpTypes : 0)] += by;
+    }
+  }
   void run_deferred() {
     for (auto& f : deferred) f();
     deferred.clear();
@@ -937,10 +964,14 @@ struct Plan final : ifmm_plan {
         case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
         case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.ty, s); break;
         case OP_RRQR:
-          if (op.b) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
+          if (op.b == 2)
+            launch_rrqr_reg(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2, (int)op.off2b,
+                            op.ty, s);
+          else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
           else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.ty, s);
           break;
-        case OP_FORMQ: launch_formq(reinterpret_cast<FormQDesc*>(d + op.off), op.count, op.ty, s); break;
+        case OP_FORMQRR: launch_formq_rr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.ty, s); break;
+        case OP_FORMQ: break;  // Q is formed with the pivoted QR (OP_RRQR / OP_FORMQRR)
         case OP_STACKQR:
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
                          op.count, op.a, op.ty, s);
@@ -1611,7 +1642,7 @@ struct Plan final : ifmm_plan {
         }
         T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
-                      std::min(nq, r_cap), eps_c, 1});
+                      std::min(nq, r_cap), eps_c, 1, Uh + (size_t)t * L.sU, L.npad});
       }
       st.gemm(g);
       st.add(a);
@@ -1620,17 +1651,15 @@ struct Plan final : ifmm_plan {
       run_deferred();
       HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
-      std::vector<FormQDesc> fq;
       for (int t = t0; t < t1; ++t) {
-        const int q = touch[t].q, nq = L.n[q];
+        const int nq = L.n[touch[t].q];
         rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
-        T* Aw = A + (size_t)(t - t0) * per;
-        T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
-        fq.push_back({Aw, tb, tb + kMaxRank, Uh + (size_t)t * L.sU, nq, rnew[t], std::min(rnew[t], hr[2 * t + 1]),
-                      L.npad, L.npad});
+        // Q of the pivoted steps, formed on the device: its work, now that
+        // the rank is known
+        const int kk = std::min(rnew[t], hr[2 * t + 1]);
+        add_count(Stage::rrqr_in_regs(rq[t - t0]) ? 4 : 5, 4.0 * tri_sum(nq, rnew[t], kk),
+                  sizeof(T) * ((double)nq * kk + (double)nq * rnew[t]));
       }
-      st.formq(fq);
-      run(st);
     }
     // basis change T = U^^T U (the column side uses S = T^T)
     Stage st;

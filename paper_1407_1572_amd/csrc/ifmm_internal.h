@@ -99,29 +99,17 @@ struct RrqrDesc {
   double eps;
   int stop_at_rank;
   int ty;
+  void* Q;  // optional: Q (n x r, r = min(rank, kmax)) of the pivoted steps, ld ldq
+  int ldq;
   RrqrDesc() = default;
   template <class U>
   __host__ RrqrDesc(U* a, typename nodeduce<U*>::type tau_, typename nodeduce<U*>::type alpha_, int* rank_,
-                    int* steps_, int n_, int m_, int lda_, int kmax_, double eps_, int stop)
+                    int* steps_, int n_, int m_, int lda_, int kmax_, double eps_, int stop,
+                    typename nodeduce<U*>::type q = nullptr, int ldq_ = 0)
       : A(a), tau(tau_), alpha(alpha_), rank(rank_), steps(steps_), n(n_), m(m_), lda(lda_), kmax(kmax_),
-        eps(eps_), stop_at_rank(stop), ty(tcode<U>()) {}
+        eps(eps_), stop_at_rank(stop), ty(tcode<U>()), Q(q), ldq(ldq_) {}
 };
 
-// Q = H_0 ... H_{kk-1} I[:, 0:r] (n x r) from reflectors of a RrqrDesc, with
-// column j negated where alpha[j] < 0.
-struct FormQDesc {
-  const void* A;
-  const void* tau;
-  const void* alpha;
-  void* Q;
-  int n, r, kk, lda, ldq;
-  int ty;
-  FormQDesc() = default;
-  template <class U>
-  __host__ FormQDesc(typename nodeduce<const U*>::type a, typename nodeduce<const U*>::type tau_,
-                     typename nodeduce<const U*>::type alpha_, U* q, int n_, int r_, int kk_, int lda_, int ldq_)
-      : A(a), tau(tau_), alpha(alpha_), Q(q), n(n_), r(r_), kk(kk_), lda(lda_), ldq(ldq_), ty(tcode<U>()) {}
-};
 
 // One block of a vertical stack whose R factor is wanted.
 struct BlkRef {
@@ -338,7 +326,16 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t 
 // Same arithmetic on the matrix in place (one workgroup per matrix, the
 // matrix L2-resident, column norms in LDS): max_m columns at most.
 void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s);
-void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s);
+// Pivoted QR with each column in the registers of one thread, and Q when
+// d.Q is set: every matrix has m <= kRrqrRegCols and n <= nr, with nr one of
+// rrqr_reg_rows(ty); LDS holds the kmax x nr reflectors.
+constexpr int kRrqrRegCols = 512;
+int rrqr_reg_rows(int n, int ty);  // smallest register row class >= n, 0 if none
+size_t rrqr_reg_lds(int nr, int kmax, int ty);
+void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, hipStream_t s);
+// Q of RrqrDescs whose pivoted QR ran in the LDS / in-place kernels (rank and
+// steps read on the device).
+void launch_formq_rr(const RrqrDesc* d, int nd, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
 // Whole-matrix FP64 Gauss-Jordan inverse with the matrix in registers (one

@@ -901,24 +901,193 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
   if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
 }
 
-// ------------------------------------------------------------------ FORMQ
+// Pivoted QR with each column of the matrix in the registers of one thread
+// (m <= blockDim.x columns, n <= NR rows), then Q.  Step j: the remaining
+// column with the largest norm over rows j..n-1 (the first on ties) is the
+// pivot; its thread publishes the column and its wave forms the reflector
+// u = (0, 1, x_{j+1:} / v0) with alpha = -sign(x_j) ||x_{j:}||, v0 = x_j - alpha,
+// tau = -v0 / alpha, keeps it in LDS (for the update and for Q) and writes it
+// to column j of A (alpha on the diagonal) with tau and alpha.  Every other
+// remaining column takes x - tau (u^T x) u and its new trailing norm.  The
+// steps stop at the first pivot norm <= eps times the first one (the rank).
+// Q = H_0 ... H_{kk-1} [I_r; 0] (kk = min(r, steps)), column j negated where
+// alpha_j < 0, is formed by the threads of its columns from the LDS
+// reflectors.
+template <class T, int NR>
+__global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ descs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ T xs[NR], mk[NR];
+  __shared__ T tau_s[kMaxRank], alpha_s[kMaxRank];
+  __shared__ T part_v[512 / WAVE];
+  __shared__ int part_i[512 / WAVE];
+  const RrqrDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m;
+  const int K = min(min(n, m), min(d.kmax, kMaxRank));
+  if (d.A == nullptr) return;
+  T* refl = reinterpret_cast<T*>(smem);  // [K][NR]
+  T* gA = static_cast<T*>(d.A);
+  T* gtau = static_cast<T*>(d.tau);
+  T* galpha = static_cast<T*>(d.alpha);
+  const size_t lda = d.lda;
+  const int c = threadIdx.x, lane = c % WAVE, w = c / WAVE, nw = blockDim.x / WAVE;
+  const bool live = c < m;
+  T col[NR];
+  T q0 = 0;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    col[i] = (live && i < n) ? gA[i + (size_t)c * lda] : T(0);
+    q0 = fma(col[i], col[i], q0);
+  }
+  T nrm = sqrt(q0);
+  bool done = !live;
+  int rank = 0, steps = K;
+  bool counting = true;
+  T first = 0;
+  for (int j = 0; j < K; ++j) {
+    T bv = done ? T(-1) : nrm;
+    int bi = done ? m : c;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const T ov = __shfl_xor(bv, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      part_v[w] = bv;
+      part_i[w] = bi;
+    }
+    __syncthreads();
+    T piv = part_v[0];
+    int cp = part_i[0];
+    for (int q = 1; q < nw; ++q) {
+      const T v = part_v[q];
+      const int i = part_i[q];
+      if (v > piv || (v == piv && i < cp)) {
+        piv = v;
+        cp = i;
+      }
+    }
+    if (j == 0) first = piv;
+    if (counting && first > 0 && (double)piv > d.eps * (double)first) rank = j + 1;
+    else counting = false;
+    if ((!counting && d.stop_at_rank) || cp >= m) {  // uniform
+      steps = j;
+      break;
+    }
+    if (w == cp / WAVE) {  // the pivot column's wave forms the reflector
+      if (c == cp) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) xs[i] = col[i];
+        done = true;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      T part = 0;
+      for (int i = lane; i < NR; i += WAVE)
+        if (i >= j && i < n) part = fma(xs[i], xs[i], part);
+      const T xn = sqrt(wave_sum(part));
+      const T x0 = xs[j];
+      T alpha = 0, tau = 0, iv = 0;
+      if (xn > 0) {
+        alpha = x0 >= 0 ? -xn : xn;
+        const T v0 = x0 - alpha;
+        tau = -v0 / alpha;
+        iv = T(1) / v0;
+      }
+      for (int i = lane; i < NR; i += WAVE) {
+        const T u = i < j ? T(0) : i == j ? T(1) : (i < n ? xs[i] * iv : T(0));
+        refl[j * NR + i] = u;
+        mk[i] = i > j ? T(1) : T(0);
+        if (i > j && i < n) gA[i + (size_t)j * lda] = u;
+      }
+      if (lane == 0) {
+        tau_s[j] = tau;
+        alpha_s[j] = alpha;
+        gA[j + (size_t)j * lda] = alpha;
+        gtau[j] = tau;
+        galpha[j] = alpha;
+      }
+    }
+    __syncthreads();
+    if (!done) {
+      const T* u = refl + j * NR;
+      const T tau = tau_s[j];
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int i = 0; i < NR; i += 2) {
+        sa = fma(u[i], col[i], sa);
+        if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+      }
+      const T ts = tau * (sa + sb);
+      // read u again from LDS below instead of holding NR more registers
+      asm volatile("" ::: "memory");
+      T qa = 0, qb = 0;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        col[i] = fma(-ts, u[i], col[i]);
+        const T v = col[i] * mk[i];
+        if (i & 1) qb = fma(v, col[i], qb);
+        else qa = fma(v, col[i], qa);
+      }
+      nrm = sqrt(qa + qb);
+    }
+  }
+  if (threadIdx.x == 0) {
+    *d.rank = rank;
+    *d.steps = steps;
+  }
+  if (d.Q == nullptr) return;
+  const int r = min(rank, d.kmax), kk = min(r, steps);
+  __syncthreads();
+  if (c < r) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) col[i] = i == c ? T(1) : T(0);
+    for (int jj = kk - 1; jj >= 0; --jj) {
+      const T* u = refl + jj * NR;
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int i = 0; i < NR; i += 2) {
+        sa = fma(u[i], col[i], sa);
+        if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+      }
+      const T ts = tau_s[jj] * (sa + sb);
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < NR; ++i) col[i] = fma(-ts, u[i], col[i]);
+      asm volatile("" ::: "memory");
+    }
+    const T sg = (c < kk && alpha_s[c] < 0) ? T(-1) : T(1);
+    T* Q = static_cast<T*>(d.Q) + (size_t)c * d.ldq;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+      if (i < n) Q[i] = sg * col[i];
+  }
+}
+
+// Q of a pivoted QR done by k_rrqr (rank and steps read on the device).
 template <class T>
-__global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ descs) {
-  const FormQDesc d = descs[blockIdx.x];
-  if (d.Q == nullptr || d.r == 0) return;
-  const int n = d.n, r = d.r;
-  const size_t lda = d.lda, ldq = d.ldq;
-  const T* A = static_cast<const T*>(d.A);
-  const T* tauv = static_cast<const T*>(d.tau);
-  const T* alphav = static_cast<const T*>(d.alpha);
-  T* Q = static_cast<T*>(d.Q);
+__global__ __launch_bounds__(WG) void k_formq_rr(const RrqrDesc* __restrict__ descs) {
+  const RrqrDesc dd = descs[blockIdx.x];
+  if (dd.Q == nullptr) return;
+  const int r = min(*dd.rank, dd.kmax), kk = min(r, *dd.steps);
+  if (r <= 0) return;
+  const int n = dd.n;
+  const size_t lda = dd.lda, ldq = dd.ldq;
+  const T* A = static_cast<const T*>(dd.A);
+  const T* tauv = static_cast<const T*>(dd.tau);
+  const T* alphav = static_cast<const T*>(dd.alpha);
+  T* Q = static_cast<T*>(dd.Q);
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
   for (int e = threadIdx.x; e < n * r; e += WG) {
     const int i = e % n, j = e / n;
     Q[i + j * ldq] = i == j ? T(1) : T(0);
   }
   __syncthreads();
-  for (int j = d.kk - 1; j >= 0; --j) {
+  for (int j = kk - 1; j >= 0; --j) {
     const T tau = tauv[j];
     for (int c = j + w; c < r; c += nw) {
       T s = 0;
@@ -930,7 +1099,7 @@ __global__ __launch_bounds__(WG) void k_formq(const FormQDesc* __restrict__ desc
     }
     __syncthreads();
   }
-  for (int j = 0; j < d.kk && j < r; ++j)
+  for (int j = 0; j < kk && j < r; ++j)
     if (alphav[j] < 0)
       for (int i = threadIdx.x; i < n; i += WG) Q[i + j * ldq] = -Q[i + j * ldq];
 }
@@ -1488,7 +1657,8 @@ void add_go(const AddDesc* d, int nd, int tm, int tn, hipStream_t s) {
 // Raise the dynamic LDS limit of a kernel once (gfx950: 160 KiB per CU).
 void allow_lds(const void* fn, bool& done, size_t bytes) {
   if (done) return;
-  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    (void)hipGetLastError();  // the launch reports a real shortfall
   done = true;
 }
 
@@ -1626,6 +1796,59 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t 
   }
 }
 
+int rrqr_reg_rows(int n, int ty) {
+  if (n <= 32) return 32;
+  if (n <= 64) return 64;
+  if (!ty) return 0;  // FP64 columns beyond 64 rows do not fit the register file
+  if (n <= 96) return 96;
+  if (n <= 128) return 128;
+  return 0;
+}
+
+size_t rrqr_reg_lds(int nr, int kmax, int ty) {
+  return (size_t)std::min(kmax, kMaxRank) * nr * (ty ? sizeof(float) : sizeof(double));
+}
+
+template <class T, int NR>
+void rrqr_reg_go(const RrqrDesc* d, int nd, int nt, size_t lds, hipStream_t s) {
+  // the kernel's static LDS is a few KiB: raise the dynamic limit to what
+  // this launch asks for, when above the default
+  static size_t raised = 64 * 1024;
+  if (lds > raised) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_rrqr_reg<T, NR>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+      raised = lds;
+    else
+      (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_rrqr_reg<T, NR>), dim3(nd), dim3(nt), lds, s, d);
+}
+
+void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, hipStream_t s) {
+  if (nd <= 0 || max_m <= 0) return;
+  const int nt = std::min(kRrqrRegCols, (max_m + WAVE - 1) / WAVE * WAVE);
+  const size_t lds = rrqr_reg_lds(nr, max_kmax, ty);
+  if (ty) {
+    switch (nr) {
+      case 32: rrqr_reg_go<float, 32>(d, nd, nt, lds, s); break;
+      case 64: rrqr_reg_go<float, 64>(d, nd, nt, lds, s); break;
+      case 96: rrqr_reg_go<float, 96>(d, nd, nt, lds, s); break;
+      case 128: rrqr_reg_go<float, 128>(d, nd, nt, lds, s); break;
+    }
+  } else {
+    switch (nr) {
+      case 32: rrqr_reg_go<double, 32>(d, nd, nt, lds, s); break;
+      case 64: rrqr_reg_go<double, 64>(d, nd, nt, lds, s); break;
+    }
+  }
+}
+
+void launch_formq_rr(const RrqrDesc* d, int nd, int ty, hipStream_t s) {
+  if (nd <= 0) return;
+  if (ty) hipLaunchKernelGGL(k_formq_rr<float>, dim3(nd), dim3(WG), 0, s, d);
+  else hipLaunchKernelGGL(k_formq_rr<double>, dim3(nd), dim3(WG), 0, s, d);
+}
+
 void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s) {
   if (nd <= 0 || max_m <= 0) return;
   const size_t lds = (size_t)max_m * (ty ? sizeof(float) : sizeof(double));
@@ -1640,11 +1863,6 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_
   }
 }
 
-void launch_formq(const FormQDesc* d, int nd, int ty, hipStream_t s) {
-  if (nd <= 0) return;
-  if (ty) hipLaunchKernelGGL(k_formq<float>, dim3(nd), dim3(WG), 0, s, d);
-  else hipLaunchKernelGGL(k_formq<double>, dim3(nd), dim3(WG), 0, s, d);
-}
 
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
   if (a.nt <= 0 || max_r <= 0) return;
