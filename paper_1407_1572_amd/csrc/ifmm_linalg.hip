@@ -64,13 +64,19 @@ __device__ inline T grp_sum(T v) {
 }
 
 // ------------------------------------------------------------------- GEMM
-// 64 x 64 output tile (m0, n0) of one product on the matrix cores: K staged
-// by 16 in LDS, each of the four waves owns a 32 x 32 quarter as 2 x 2
-// blocks of 16 x 16, advanced by v_mfma_*_16x16x4 (FP32 operands with FP32
-// accumulation when A and B are FP32, else FP64 operands and accumulation).
+// 64 x 64 output tile (m0, n0) of one product on the matrix cores, operands
+// loaded straight into registers: each of the four waves owns a 32 x 32
+// quarter as 2 x 2 blocks of 16 x 16, advanced by v_mfma_*_16x16x4 (FP32
+// operands with FP32 accumulation when A and B are FP32, else FP64 operands
+// and accumulation), K by 16 per iteration.
 // Lane layouts of the 16x16x4 instructions (lane l, accumulator register r):
 // A(i, k) from lane i + 16 k, B(k, j) from lane j + 16 k; the FP32 result
 // D(4 (l / 16) + r, l % 16), the FP64 result D(4 r + l / 16, l % 16).
+// Lane l feeds k = k0 + 4 (l / 16) + s to MFMA step s (s = 0..3): any
+// assignment of the 16 k values to (lane group, step) sums the same
+// products, and this one gives a lane four consecutive k, loaded as one
+// 16-byte access where the operand is contiguous in k (FP32 B as stored, FP32
+// A transposed).  FP32 results are stored four rows per lane at once.
 typedef float mf4 __attribute__((ext_vector_type(4)));
 typedef double md4 __attribute__((ext_vector_type(4)));
 
@@ -84,6 +90,7 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
   using Acc = typename std::conditional<std::is_same<TA, float>::value && std::is_same<TB, float>::value,
                                         float, double>::type;
   using V4 = typename std::conditional<std::is_same<Acc, float>::value, mf4, md4>::type;
+  constexpr bool kF = std::is_same<Acc, float>::value;
   const TA* __restrict__ Ap = static_cast<const TA*>(d.A);
   const TB* __restrict__ Bp = static_cast<const TB*>(d.B);
   TC* Cp = static_cast<TC*>(d.C);
@@ -96,21 +103,50 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
   const bool vr0 = r0 < d.M, vr1 = r1 < d.M, vc0 = c0 < d.N, vc1 = c1 < d.N;
   const size_t sa = d.opA ? 1 : (size_t)d.lda, ra = d.opA ? (size_t)d.lda : 1;  // A(i, k) = Ap[i ra + k sa]
   const size_t sb = d.opB ? (size_t)d.ldb : 1, cb = d.opB ? 1 : (size_t)d.ldb;  // B(k, j) = Bp[k sb + j cb]
+  const bool vecB = kF && d.opB == 0 && (d.ldb & 3) == 0 && (reinterpret_cast<uintptr_t>(Bp) & 15) == 0;
+  const bool vecA = kF && d.opA == 1 && (d.lda & 3) == 0 && (reinterpret_cast<uintptr_t>(Ap) & 15) == 0;
   V4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V4{0, 0, 0, 0};
   for (int k0 = 0; k0 < d.K; k0 += 16) {
+    const int kb = k0 + 4 * lk;
+    const bool full = kb + 3 < d.K;
     Acc a[4][2], b[4][2];
+    if (vecA && full) {
+      const mf4 x0 = vr0 ? *reinterpret_cast<const mf4*>(Ap + r0 * ra + kb) : mf4{0, 0, 0, 0};
+      const mf4 x1 = vr1 ? *reinterpret_cast<const mf4*>(Ap + r1 * ra + kb) : mf4{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int k = k0 + 4 * s + lk;
-      const bool vk = k < d.K;
-      a[s][0] = vk && vr0 ? (Acc)Ap[r0 * ra + k * sa] : Acc(0);
-      a[s][1] = vk && vr1 ? (Acc)Ap[r1 * ra + k * sa] : Acc(0);
-      b[s][0] = vk && vc0 ? (Acc)Bp[k * sb + c0 * cb] : Acc(0);
-      b[s][1] = vk && vc1 ? (Acc)Bp[k * sb + c1 * cb] : Acc(0);
+      for (int s = 0; s < 4; ++s) {
+        a[s][0] = (Acc)x0[s];
+        a[s][1] = (Acc)x1[s];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kb + s;
+        const bool vk = k < d.K;
+        a[s][0] = vk && vr0 ? (Acc)Ap[r0 * ra + k * sa] : Acc(0);
+        a[s][1] = vk && vr1 ? (Acc)Ap[r1 * ra + k * sa] : Acc(0);
+      }
+    }
+    if (vecB && full) {
+      const mf4 y0 = vc0 ? *reinterpret_cast<const mf4*>(Bp + kb + c0 * cb) : mf4{0, 0, 0, 0};
+      const mf4 y1 = vc1 ? *reinterpret_cast<const mf4*>(Bp + kb + c1 * cb) : mf4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        b[s][0] = (Acc)y0[s];
+        b[s][1] = (Acc)y1[s];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kb + s;
+        const bool vk = k < d.K;
+        b[s][0] = vk && vc0 ? (Acc)Bp[k * sb + c0 * cb] : Acc(0);
+        b[s][1] = vk && vc1 ? (Acc)Bp[k * sb + c1 * cb] : Acc(0);
+      }
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -121,19 +157,37 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
     }
   }
   const Acc al = (Acc)d.alpha, be = (Acc)d.beta;
+  const bool vecC = kF && std::is_same<TC, float>::value && (d.ldc & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(Cp) & 15) == 0;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < 2; ++bj) {
+      const int gm0 = wm + 16 * bi + mfma_row(Acc(0), lane, 0), gn = wn + 16 * bj + li;
+      if (gn >= d.N) continue;
+      if (vecC && gm0 + 3 < d.M) {  // four rows of one column at once
+        mf4* c = reinterpret_cast<mf4*>(Cp + gm0 + (size_t)gn * d.ldc);
+        mf4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = (float)(al * acc[bi][bj][r]);
+        if (d.beta != 0.0) {
+          const mf4 o = *c;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = (float)fma(al, (Acc)acc[bi][bj][r], be * (Acc)o[r]);
+        }
+        *c = v;
+        continue;
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = wm + 16 * bi + mfma_row(Acc(0), lane, r), gn = wn + 16 * bj + li;
-        if (gm < d.M && gn < d.N) {
+        const int gm = wm + 16 * bi + mfma_row(Acc(0), lane, r);
+        if (gm < d.M) {
           TC* c = Cp + gm + (size_t)gn * d.ldc;
           const Acc v = acc[bi][bj][r];
           *c = (TC)(d.beta == 0.0 ? al * v : fma(al, v, be * (Acc)*c));
         }
       }
+    }
 }
 
 template <class TA, class TB, class TC>
@@ -1663,15 +1717,17 @@ void allow_lds(const void* fn, bool& done, size_t bytes) {
 }
 
 // Chunk rows of the stacked-R kernels and their LDS bytes for rank r: up to
-// 1024 rows, within 64 KiB when 128 rows fit there (several workgroups per
-// CU), else within 150 KiB of the 160 KiB LDS of a gfx950 CU.
+// max_chunk rows, within 64 KiB when 128 rows fit there (several workgroups
+// per CU), else within 150 KiB of the 160 KiB LDS of a gfx950 CU.  The
+// window stacks of a whole level run as one launch: short chunks keep more
+// workgroups per CU in flight (measured: 128 rows beat 64, 256 and 1024).
 template <class T>
-size_t stackqr_lds(int max_r, int& chunk) {
+size_t stackqr_lds(int max_r, int& chunk, int max_chunk) {
   const size_t rr = (size_t)max_r * max_r * sizeof(T);
   const size_t row = sizeof(T) * max_r;
   const size_t budget = rr + 129 * row <= 64 * 1024 ? 64 * 1024 : 150 * 1024;
   chunk = (int)((budget - rr) / row) - 1;
-  if (chunk > 1024) chunk = 1024;
+  if (chunk > max_chunk) chunk = max_chunk;
   if (chunk < 1) chunk = 1;
   return rr + (size_t)(chunk + 1) * row;
 }
@@ -1679,7 +1735,7 @@ size_t stackqr_lds(int max_r, int& chunk) {
 template <class T>
 void stackqr_win_go(const WinStack& a, int max_r, hipStream_t s) {
   int chunk;
-  const size_t lds = stackqr_lds<T>(max_r, chunk);
+  const size_t lds = stackqr_lds<T>(max_r, chunk, 128);
   if (lds > 64 * 1024) {
     static bool raised = false;
     allow_lds(reinterpret_cast<const void*>(k_stackqr_win<T>), raised, 150 * 1024);
@@ -1690,7 +1746,7 @@ void stackqr_win_go(const WinStack& a, int max_r, hipStream_t s) {
 template <class T>
 void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStream_t s) {
   int chunk;
-  const size_t lds = stackqr_lds<T>(max_r, chunk);
+  const size_t lds = stackqr_lds<T>(max_r, chunk, 256);
   if (lds > 64 * 1024) {
     static bool raised = false;
     allow_lds(reinterpret_cast<const void*>(k_stackqr<T>), raised, 150 * 1024);
