@@ -471,8 +471,13 @@ struct Stage {
         const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
         op({OP_RRQR, o, g == 1 ? (size_t)lds : 0, (int)v.size(), mm, g, f, by}, ty);
         bool q = false;
-        for (const auto& d : v) q |= d.Q != nullptr;
-        if (q) op({OP_FORMQRR, o, 0, (int)v.size(), 0, 0, 0.0, 0.0}, ty);
+        int nn = 0, km = 0;
+        for (const auto& d : v) {
+          q |= d.Q != nullptr;
+          nn = std::max(nn, d.n);
+          km = std::max(km, d.kmax);
+        }
+        if (q) op({OP_FORMQRR, o, 0, (int)v.size(), nn, km, 0.0, 0.0}, ty);
       }
     });
   }
@@ -970,7 +975,9 @@ struct Plan final : ifmm_plan {
           else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
           else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.ty, s);
           break;
-        case OP_FORMQRR: launch_formq_rr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.ty, s); break;
+        case OP_FORMQRR:
+          launch_formq_rr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s);
+          break;
         case OP_FORMQ: break;  // Q is formed with the pivoted QR (OP_RRQR / OP_FORMQRR)
         case OP_STACKQR:
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),

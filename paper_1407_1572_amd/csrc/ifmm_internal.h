@@ -334,8 +334,8 @@ int rrqr_reg_rows(int n, int ty);  // smallest register row class >= n, 0 if non
 size_t rrqr_reg_lds(int nr, int kmax, int ty);
 void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, hipStream_t s);
 // Q of RrqrDescs whose pivoted QR ran in the LDS / in-place kernels (rank and
-// steps read on the device).
-void launch_formq_rr(const RrqrDesc* d, int nd, int ty, hipStream_t s);
+// steps read on the device); every n <= max_n <= 512, kmax <= max_kmax.
+void launch_formq_rr(const RrqrDesc* d, int nd, int max_n, int max_kmax, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
 // Whole-matrix FP64 Gauss-Jordan inverse with the matrix in registers (one

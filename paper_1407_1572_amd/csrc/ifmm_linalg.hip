@@ -1122,9 +1122,66 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
   }
 }
 
-// Q of a pivoted QR done by k_rrqr (rank and steps read on the device).
+// Q of a pivoted QR done by k_rrqr (rank and steps read on the device):
+// the kk reflectors are staged in LDS, then each column of Q is formed by G
+// consecutive lanes holding NR rows each (rows g NR .. g NR + NR - 1), the
+// products with the reflectors reduced over the G lanes.  No barrier after
+// the staging.
+template <class T, int NR, int G>
+__global__ __launch_bounds__(512) void k_formq_rr(const RrqrDesc* __restrict__ descs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* refl = reinterpret_cast<T*>(smem);  // [kk][G NR]
+  __shared__ T tau_s[kMaxRank];
+  __shared__ int neg_s[kMaxRank];
+  constexpr int LD = G * NR;
+  const RrqrDesc dd = descs[blockIdx.x];
+  if (dd.Q == nullptr) return;
+  const int r = min(min(*dd.rank, dd.kmax), kMaxRank), kk = min(r, *dd.steps);
+  if (r <= 0) return;
+  const int n = dd.n;
+  const size_t lda = dd.lda, ldq = dd.ldq;
+  const T* A = static_cast<const T*>(dd.A);
+  for (int e = threadIdx.x; e < kk * LD; e += blockDim.x) {
+    const int i = e % LD, j = e / LD;
+    refl[e] = i < j || i >= n ? T(0) : i == j ? T(1) : A[i + (size_t)j * lda];
+  }
+  for (int j = threadIdx.x; j < kk; j += blockDim.x) {
+    tau_s[j] = static_cast<const T*>(dd.tau)[j];
+    neg_s[j] = static_cast<const T*>(dd.alpha)[j] < 0;
+  }
+  __syncthreads();
+  const int g = threadIdx.x % G;
+  T* Q = static_cast<T*>(dd.Q);
+  for (int c = threadIdx.x / G; c < r; c += blockDim.x / G) {
+    T q[NR];
+#pragma unroll
+    for (int t = 0; t < NR; ++t) q[t] = g * NR + t == c ? T(1) : T(0);
+    for (int j = kk - 1; j >= 0; --j) {
+      const T* u = refl + (size_t)j * LD + g * NR;
+      T sa = 0;
+#pragma unroll
+      for (int t = 0; t < NR; ++t) sa = fma(u[t], q[t], sa);
+#pragma unroll
+      for (int o = 1; o < G; o <<= 1) sa += __shfl_xor(sa, o, WAVE);
+      const T ts = tau_s[j] * sa;
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int t = 0; t < NR; ++t) q[t] = fma(-ts, u[t], q[t]);
+      asm volatile("" ::: "memory");
+    }
+    const T sg = (c < kk && neg_s[c]) ? T(-1) : T(1);
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      const int i = g * NR + t;
+      if (i < n) Q[i + (size_t)c * ldq] = sg * q[t];
+    }
+  }
+}
+
+// The same for matrices whose reflectors do not fit in LDS: reflectors read
+// from the matrix in place, one wave per column.
 template <class T>
-__global__ __launch_bounds__(WG) void k_formq_rr(const RrqrDesc* __restrict__ descs) {
+__global__ __launch_bounds__(WG) void k_formq_rr_glb(const RrqrDesc* __restrict__ descs) {
   const RrqrDesc dd = descs[blockIdx.x];
   if (dd.Q == nullptr) return;
   const int r = min(*dd.rank, dd.kmax), kk = min(r, *dd.steps);
@@ -1899,10 +1956,38 @@ void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax,
   }
 }
 
-void launch_formq_rr(const RrqrDesc* d, int nd, int ty, hipStream_t s) {
-  if (nd <= 0) return;
-  if (ty) hipLaunchKernelGGL(k_formq_rr<float>, dim3(nd), dim3(WG), 0, s, d);
-  else hipLaunchKernelGGL(k_formq_rr<double>, dim3(nd), dim3(WG), 0, s, d);
+template <class T, int NR, int G>
+void formq_rr_go(const RrqrDesc* d, int nd, int max_kmax, hipStream_t s) {
+  const size_t lds = (size_t)std::min(max_kmax, kMaxRank) * G * NR * sizeof(T);
+  static size_t raised = 64 * 1024;
+  if (lds > raised) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_formq_rr<T, NR, G>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+      raised = lds;
+    else
+      (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_formq_rr<T, NR, G>), dim3(nd), dim3(512), lds, s, d);
+}
+
+// Q columns by groups of G lanes with NR rows each: G NR >= max_n.
+void launch_formq_rr(const RrqrDesc* d, int nd, int max_n, int max_kmax, int ty, hipStream_t s) {
+  if (nd <= 0 || max_n <= 0) return;
+  const int rows = max_n <= 128 ? 128 : max_n <= 256 ? 256 : 512;
+  if (max_n > 512 || (size_t)std::min(max_kmax, kMaxRank) * rows * (ty ? 4 : 8) > 144 * 1024) {
+    if (ty) hipLaunchKernelGGL(k_formq_rr_glb<float>, dim3(nd), dim3(WG), 0, s, d);
+    else hipLaunchKernelGGL(k_formq_rr_glb<double>, dim3(nd), dim3(WG), 0, s, d);
+    return;
+  }
+  if (ty) {
+    if (max_n <= 128) formq_rr_go<float, 32, 4>(d, nd, max_kmax, s);
+    else if (max_n <= 256) formq_rr_go<float, 32, 8>(d, nd, max_kmax, s);
+    else formq_rr_go<float, 64, 8>(d, nd, max_kmax, s);
+  } else {
+    if (max_n <= 128) formq_rr_go<double, 32, 4>(d, nd, max_kmax, s);
+    else if (max_n <= 256) formq_rr_go<double, 32, 8>(d, nd, max_kmax, s);
+    else formq_rr_go<double, 64, 8>(d, nd, max_kmax, s);
+  }
 }
 
 void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s) {
