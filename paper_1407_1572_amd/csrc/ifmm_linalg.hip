@@ -668,9 +668,22 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
     }
 }
 
+// The vector a product multiplies (K values per right-hand side column) is
+// staged in LDS first: every lane reads it there, not through the caches.
 template <class T>
 __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, double* __restrict__ wk, int tiles) {
   __shared__ double part[(WG / WAVE) * SV_C * WAVE];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* xs = reinterpret_cast<double*>(smem);  // [SV_C][mpad]
+  auto stage = [&](const double* src, size_t ld, int K, int ncol) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * ncol; e += WG) {
+      const int k = e % K, c = e / K;
+      xs[k + c * a.mpad] = src[k + c * ld];
+    }
+    __syncthreads();
+  };
+  auto XL = [&](int k, int c) { return xs[k + c * a.mpad]; };
   const int b = blockIdx.x;
   const ElimRec& r = a.rec[b];
   const int unit = blockIdx.y / tiles, tile = blockIdx.y % tiles;
@@ -687,8 +700,8 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, doubl
     if (step == 0) {
       if (tile * WAVE >= m) return;
       const double* bi = a.bv + (size_t)r.i * sv + (size_t)c0 * a.npad;
-      tile_dot<double>(D, a.mpad, row, row < m, ni, [&](int k, int c) { return bi[k + (size_t)c * a.npad]; }, nc,
-                       part, acc);
+      stage(bi, a.npad, ni, nc);
+      tile_dot<double>(D, a.mpad, row, row < m, ni, XL, nc, part, acc);
       if (w == 0 && row < m)
         for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = acc[c];
       if (tile == 0 && w == 1)
@@ -709,8 +722,8 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, doubl
       const T* A = part1 ? static_cast<const T*>(a.P) + ((size_t)cl * 9 + (8 - unit)) * a.sP
                          : static_cast<const T*>(a.L) + ((size_t)cl * 9 + (8 - unit)) * a.sL;
       const int ld = part1 ? a.npad : a.rpad;
-      tile_dot<T>(A, ld, row, row < sz, ni, [&](int k, int c) { return wb[k + (size_t)(c0 + c) * a.mpad]; }, nc,
-                  part, acc);
+      stage(wb + (size_t)c0 * a.mpad, a.mpad, ni, nc);
+      tile_dot<T>(A, ld, row, row < sz, ni, XL, nc, part, acc);
       double* tg = part1 ? a.bv + (size_t)cl * sv + (size_t)c0 * a.npad : a.cv + (size_t)cl * svc + (size_t)c0 * a.rpad;
       if (w == 0 && row < sz)
         for (int c = 0; c < nc; ++c) tg[row + (size_t)c * ld] -= acc[c];
@@ -731,8 +744,8 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, doubl
         const int lds = part1 ? a.npad : a.rpad;
         const T* A = part1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
                            : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
-        tile_dot<T>(A, a.npad, row, row < ni, sz, [&](int k, int c) { return src[k + (size_t)c * lds]; }, nc, part,
-                    acc);
+        stage(src, lds, sz, nc);
+        tile_dot<T>(A, a.npad, row, row < ni, sz, XL, nc, part, acc);
         if (w == 0)
           for (int c = 0; c < SV_C; ++c) tot[c] += acc[c];
         __syncthreads();
@@ -741,8 +754,8 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, doubl
         for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = snap[row + (size_t)(c0 + c) * a.npad] - tot[c];
     } else {
       if (tile * WAVE >= ni) return;
-      tile_dot<double>(D, a.mpad, row, row < ni, m, [&](int k, int c) { return wb[k + (size_t)(c0 + c) * a.mpad]; },
-                       nc, part, acc);
+      stage(wb + (size_t)c0 * a.mpad, a.mpad, m, nc);
+      tile_dot<double>(D, a.mpad, row, row < ni, m, XL, nc, part, acc);
       double* xi = a.bv + ((size_t)2 * a.nc + r.i) * sv + (size_t)c0 * a.npad;
       if (w == 0 && row < ni)
         for (int c = 0; c < nc; ++c) xi[row + (size_t)c * a.npad] = acc[c];
@@ -1860,8 +1873,9 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
   if (a.nb <= 0 || max_rows <= 0) return;
   const int tiles = cdiv(max_rows, WAVE);
   const dim3 grid(a.nb, (step == 1 ? 9 : 1) * tiles);
-  if (ty) hipLaunchKernelGGL(k_solve<float>, grid, dim3(WG), 0, s, a, step, wk, tiles);
-  else hipLaunchKernelGGL(k_solve<double>, grid, dim3(WG), 0, s, a, step, wk, tiles);
+  const size_t lds = sizeof(double) * SV_C * (size_t)a.mpad;
+  if (ty) hipLaunchKernelGGL(k_solve<float>, grid, dim3(WG), lds, s, a, step, wk, tiles);
+  else hipLaunchKernelGGL(k_solve<double>, grid, dim3(WG), lds, s, a, step, wk, tiles);
 }
 
 void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s) {
