@@ -114,9 +114,10 @@ typedef struct {
   /* With ifmm_options.profile: per batched-kernel family, accumulated over the
      handle's life.  Slot f + 16 q: family f -- 0 gemm, 1 add/copy, 2 basis
      (unused), 3 Householder QR, 4 column-pivoted QR, 5 basis formation,
-     6 stacked R factor, 7 pivot inverse, 8 elimination steps (pivot build,
-     X = D^-1 B, Schur updates, M2L row), 9 basis change of touched
-     clusters, 10 far-field weight stacks, 11 solve sweeps; 12..15 unused -- with
+     6 stacked R factor, 7 pivot inverse, 8 Schur updates of the
+     elimination, 9 basis change of touched clusters, 10 far-field weight
+     stacks, 11 solve sweeps, 12 the other elimination steps (pivot build,
+     X = D^-1 B, M2L row, fill projection); 13..15 unused -- with
      q = 1 for launches whose blocks are FP32 (gemm: both operands FP32; add:
      FP32 destination).  flops / bytes are the algorithmic counts of the
      launches (bytes at storage size). */

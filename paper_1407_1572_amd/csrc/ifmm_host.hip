@@ -244,8 +244,9 @@ constexpr double kF32EpsFloor = 2.5e-7;
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
               OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
-// 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 elim, 9 touched-cluster
-// transform, 10 window stacked R, 11 solve sweeps.
+// 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 Schur updates (elimination
+// step 2), 9 touched-cluster transform, 10 window stacked R, 11 solve sweeps,
+// 12 the other elimination steps.
 constexpr int kOpTypes = 16;
 inline int family(int t) {
   switch (t) {
@@ -271,6 +272,10 @@ struct Op {
   size_t off2b = 0;
   int ty = 0;  // scalar type code of the descriptors
 };
+
+// Profile family of a launch (the elimination steps other than the Schur
+// updates have a slot of their own).
+inline int op_family(const Op& o) { return o.t == OP_ELIM && o.count != 2 ? 12 : family(o.t); }
 
 inline double esz(int f32) { return f32 ? 4.0 : 8.0; }
 
@@ -956,7 +961,7 @@ struct Plan final : ifmm_plan {
   void launch_ops(const Stage& st, char* d) {
     for (const Op& op : st.ops) {
       hipEvent_t ea = nullptr, eb = nullptr;
-      const bool tm = profile && timed(family(op.t));
+      const bool tm = profile && timed(op_family(op));
       if (tm) {
         ea = get_event();
         eb = get_event();
@@ -1062,7 +1067,7 @@ struct Plan final : ifmm_plan {
       if (tm) {
         HIP_OK(hipEventRecord(eb, s));
         const bool f32 = op.t == OP_GEMM ? (op.ty & 3) == 3 : op.t == OP_ADD ? (op.ty & 2) != 0 : op.ty != 0;  // elim: block type
-        pend.push_back({family(op.t) + (f32 ? kOpTypes : 0), ea, eb, op.flops, op.bytes});
+        pend.push_back({op_family(op) + (f32 ? kOpTypes : 0), ea, eb, op.flops, op.bytes});
         if (pend.size() > 4096) resolve_profile();
       }
     }

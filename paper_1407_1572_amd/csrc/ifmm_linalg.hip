@@ -370,8 +370,11 @@ __device__ bool elim_proj_desc(const ElimArgs& a, const ElimRec& r, int b, int s
 }
 
 // grid (nb, units * tiles): step 0 and 3 are elementwise, 1, 2, 4, 5 products.
-template <class T>
-__global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int step, int tiles_m, int tiles_n) {
+// One instantiation per step: each gets the registers of its own step only
+// (the FP64-accumulating step 1 needs twice those of the FP32 products).
+template <class T, int STEP>
+__global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int tiles_m, int tiles_n) {
+  constexpr int step = STEP;
   const int b = blockIdx.x;
   const ElimRec& r = a.rec[b];
   const int per = tiles_m * tiles_n;
@@ -1858,8 +1861,18 @@ void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipS
   const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
   const int units = step == 0 ? 1 : (step == 2 || step >= 4) ? 81 : 9;
   const dim3 grid(a.nb, units * tm * tn);
-  if (ty) hipLaunchKernelGGL(k_elim<float>, grid, dim3(WG), 0, s, a, step, tm, tn);
-  else hipLaunchKernelGGL(k_elim<double>, grid, dim3(WG), 0, s, a, step, tm, tn);
+#define ELIM_GO(S)                                                                            \
+  if (ty) hipLaunchKernelGGL((k_elim<float, S>), grid, dim3(WG), 0, s, a, tm, tn);   \
+  else hipLaunchKernelGGL((k_elim<double, S>), grid, dim3(WG), 0, s, a, tm, tn);
+  switch (step) {
+    case 0: ELIM_GO(0) break;
+    case 1: ELIM_GO(1) break;
+    case 2: ELIM_GO(2) break;
+    case 3: ELIM_GO(3) break;
+    case 4: ELIM_GO(4) break;
+    default: ELIM_GO(5) break;
+  }
+#undef ELIM_GO
 }
 
 void launch_transition(const TransArgs& a, int ty, hipStream_t s) {

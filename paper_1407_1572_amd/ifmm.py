@@ -53,7 +53,7 @@ class _Stats(C.Structure):
 
 
 KERNEL_FAMILIES = ["gemm", "add", "unused2", "qr", "rrqr", "formq", "stackqr", "inverse", "elim",
-                   "touch_xform", "stack_win", "solve"]
+                   "touch_xform", "stack_win", "solve", "elim_other"]
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
