@@ -36,15 +36,13 @@ WORKLOAD = ("1,048,576 uniform points in [0,1]^2, exp(-r/0.1) + 1e-2 I, leaf 64,
             "value: mixed-precision factor (FP32 blocks), fp64 figures alongside")
 # Profile slots whose launches are all one kernel instantiation, per factor
 # precision (the pivoted QR, the inverse, the products slot (GEMMs and M2L
-# assembly), the copies slot (adds and transitions) and the other elimination
-# steps span several kernels).
+# assembly), the copies slot (adds and transitions), the other elimination
+# steps and the solve sweeps (one kernel per step) span several kernels).
 SINGLE_KERNEL = {
     "fp64": {"stackqr": "k_stackqr<double>", "elim": "k_elim<double, 2>",
-             "touch_xform": "k_touch_xform<double>", "stack_win": "k_stackqr_win<double>",
-             "solve": "k_solve<double>"},
+             "touch_xform": "k_touch_xform<double>", "stack_win": "k_stackqr_win<double>"},
     "fp32": {"qr_f32": "k_qr<float>", "stackqr_f32": "k_stackqr<float>", "elim_f32": "k_elim<float, 2>",
-             "touch_xform_f32": "k_touch_xform<float>", "stack_win_f32": "k_stackqr_win<float>",
-             "solve_f32": "k_solve<float>"},
+             "touch_xform_f32": "k_touch_xform<float>", "stack_win_f32": "k_stackqr_win<float>"},
 }
 
 

@@ -338,10 +338,12 @@ inline std::pair<double, double> txform_work(const TouchXform& a, const std::vec
 }
 
 // Exact work of the far-field weight stacks: per cluster, the R factor of its
-// stacked window column (plus the parent chain rows when a.Z is set).
+// stacked window column (plus the parent chain rows when a.Z is set), by
+// Householder steps or (gram) by the packed Gram matrix and its Cholesky
+// factor.
 inline std::pair<double, double> winstack_work(const WinStack& a, const std::vector<int>& ids,
                                                const std::vector<int>& r, const std::vector<int>* r_par,
-                                               double es) {
+                                               double es, bool gram = false) {
   double f = 0, by = 0;
   for (int t = 0; t < a.nt; ++t) {
     const int q = ids[t], rq = r[q];
@@ -354,7 +356,7 @@ inline std::pair<double, double> winstack_work(const WinStack& a, const std::vec
       if (std::abs(jx - qx) <= 1 && std::abs(jy - qy) <= 1) continue;
       rows += r[morton2(jx, jy)];
     }
-    f += 2.0 * rows * rq * rq;
+    f += gram ? rows * rq * (rq + 1.0) + rq * (double)rq * rq / 3.0 : 2.0 * rows * rq * rq;
     by += es * (rows * rq + (double)a.S * rq * rq);
   }
   return {f, by};
@@ -516,17 +518,17 @@ struct Stage {
   // touch_xform).
   template <class T>
   void win_stack(WinStack a, const std::vector<int>& ids, const std::vector<int>& r, const std::vector<int>* r_par,
-                 bool count = true) {
+                 bool count = true, bool gram = false) {
     if (a.nt <= 0) return;
     double f = 0, by = 0;
-    if (count) std::tie(f, by) = winstack_work(a, ids, r, r_par, sizeof(T));
+    if (count) std::tie(f, by) = winstack_work(a, ids, r, r_par, sizeof(T), gram);
     int rmax = 0;
     for (int t = 0; t < a.nt; ++t) rmax = std::max(rmax, r[ids[t]]);
     a.ids = arr(&ids);
     a.r = arr(&r);
     a.r_par = arr(r_par);
     flops += f;
-    op({OP_WSTACK, push(&a, sizeof(a)), 0, a.nt, rmax, 0, f, by}, tcode<T>());
+    op({OP_WSTACK, push(&a, sizeof(a)), 0, a.nt, rmax, gram ? 1 : 0, f, by}, tcode<T>());
   }
   // One step of the elimination kernels over a batch of records (the record
   // array is pushed once per batch: rec_off = its blob offset + 1).
@@ -1044,7 +1046,8 @@ struct Plan final : ifmm_plan {
           rebase(a.ids);
           rebase(a.r);
           rebase(a.r_par);
-          launch_stackqr_win(a, op.a, op.ty, s);
+          if (op.b) launch_gram_win(a, op.a, op.ty, s);
+          else launch_stackqr_win(a, op.a, op.ty, s);
           break;
         }
         case OP_XFORM: break;  // family 2 has no launches
@@ -1393,10 +1396,12 @@ struct Plan final : ifmm_plan {
       }
       st.gemm(g);
     }
-    // Few clusters (coarse levels): split each stack into segments handled by
-    // separate workgroups, then take the R factor of the stacked partial R's
-    // (the same R up to rounding).
-    const int S = std::max(1, std::min(8, (3072 + nt - 1) / nt));
+    // FP32 factor: R from the FP64 Gram matrix (one workgroup per cluster).
+    // FP64 factor: Householder steps; with few clusters (coarse levels) each
+    // stack is split into segments handled by separate workgroups, then the R
+    // factor of the stacked partial R's is taken (the same R up to rounding).
+    const bool gram = kF32;
+    const int S = gram ? 1 : std::max(1, std::min(8, (3072 + nt - 1) / nt));
     T* part = S > 1 ? wsSeg.need<T>((size_t)nt * S * so, s) : nullptr;
     WinStack a{};
     a.M = L.M;
@@ -1410,9 +1415,9 @@ struct Plan final : ifmm_plan {
     a.nt = nt;
     a.S = S;
     a.out_by_id = by_id ? 1 : 0;
-    st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr, false);
-    count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2] {
-      return winstack_work(a, ids, r, par ? &rp : nullptr, sizeof(T));
+    st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr, false, gram);
+    count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2, gram] {
+      return winstack_work(a, ids, r, par ? &rp : nullptr, sizeof(T), gram);
     });
     if (S > 1) {
       std::vector<StackQrDesc> s2;

@@ -338,6 +338,9 @@ void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax,
 void launch_formq_rr(const RrqrDesc* d, int nd, int max_n, int max_kmax, int ty, hipStream_t s);
 void launch_stackqr(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, int ty, hipStream_t s);
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s);
+// The same weights (S == 1) from the FP64 Gram matrix of the stack and its
+// Cholesky factor; max_r <= rpad <= kMaxRank.
+void launch_gram_win(const WinStack& a, int max_r, int ty, hipStream_t s);
 // Whole-matrix FP64 Gauss-Jordan inverse with the matrix in registers (one
 // workgroup per matrix), every m <= kGjRegMax.
 constexpr int kGjRegMax = 192;

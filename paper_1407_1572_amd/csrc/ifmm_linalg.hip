@@ -673,8 +673,10 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
 
 // The vector a product multiplies (K values per right-hand side column) is
 // staged in LDS first: every lane reads it there, not through the caches.
-template <class T>
-__global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, int step, double* __restrict__ wk, int tiles) {
+// One instantiation per step (each with the registers of its own step).
+template <class T, int STEP>
+__global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restrict__ wk, int tiles) {
+  constexpr int step = STEP;
   __shared__ double part[(WG / WAVE) * SV_C * WAVE];
   extern __shared__ __align__(16) unsigned char smem[];
   double* xs = reinterpret_cast<double*>(smem);  // [SV_C][mpad]
@@ -1372,6 +1374,120 @@ __global__ __launch_bounds__(WG) void k_stackqr_win(const WinStack a, int chunk)
   stackqr_body<T>(reinterpret_cast<T*>(smem), r, nb, [&](int b) { return bl[b]; }, chunk, out, a.ldo);
 }
 
+// Far-field weight of cluster q = ids[t] from the Gram matrix of its stack:
+// G = sum_l M(q, l) M(q, l)^T (+ z^T z for the parent term) accumulated in
+// FP64 from the stored blocks, then R with R^T R = G by Cholesky (a pivot at
+// or below 8 r eps_64 max_i G_ii, a direction the stack does not reach above
+// FP64 rounding, gives a zero row).  R equals the R factor of the stack
+// (positive diagonal) up to rounding in every direction above sqrt(eps_64)
+// of the largest; used for the FP32 factor, where those below are FP32
+// noise.  Output as k_stackqr_win with S == 1.
+template <class T, int MAXE>
+__global__ __launch_bounds__(WG) void k_gram_win(const WinStack a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ BlkRef bl[37];
+  __shared__ int nb;
+  __shared__ double rjj_s;
+  const int t = blockIdx.x;
+  const int q = a.ids[t];
+  const int r = a.r[q];
+  if (r == 0) return;
+  const int rp1 = a.rpad + 1;
+  double* Bs = reinterpret_cast<double*>(smem);  // staged block, [col][row], ld rpad + 1
+  double* G = Bs + (size_t)r * rp1;               // r x r
+  if (threadIdx.x == 0) {
+    const int qx = demorton_x(q), qy = demorton_y(q);
+    int c = 0;
+    for (int sl = 0; sl < 36; ++sl) {
+      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
+      if (abs(jx - qx) <= 1 && abs(jy - qy) <= 1) continue;
+      const int l = morton2(jx, jy);
+      if (a.r[l] == 0) continue;
+      bl[c++] = BlkRef{static_cast<const T*>(a.M) + ((size_t)q * 36 + sl) * a.sM, a.rpad, a.r[l], 1};
+    }
+    if (a.Z && a.r_par && a.r_par[q >> 2] > 0)
+      bl[c++] = BlkRef{static_cast<const T*>(a.Z) + (size_t)t * a.sM, a.rpad, a.r_par[q >> 2], 0};
+    nb = c;
+  }
+  // upper-triangle entries (j <= k) owned by each thread, in registers
+  const int ne = r * (r + 1) / 2;  // <= MAXE WG
+  double g[MAXE];
+  int jj[MAXE], kk[MAXE];
+#pragma unroll
+  for (int u = 0; u < MAXE; ++u) {
+    g[u] = 0.0;
+    const int e = threadIdx.x + u * WG;
+    int j = 0, rem = e;  // row j of the packed upper triangle: entries j..r-1
+    while (j < r && rem >= r - j) {
+      rem -= r - j;
+      ++j;
+    }
+    jj[u] = e < ne ? j : -1;
+    kk[u] = e < ne ? j + rem : -1;
+  }
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    const BlkRef B = bl[b];
+    const T* Bp = static_cast<const T*>(B.p);
+    __syncthreads();
+    for (int e = threadIdx.x; e < B.rows * r; e += WG) {
+      int i, j;
+      if (B.trans) { j = e % r; i = e / r; } else { i = e % B.rows; j = e / B.rows; }
+      Bs[i + j * rp1] = (double)(B.trans ? Bp[j + (size_t)i * B.ld] : Bp[i + (size_t)j * B.ld]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) {
+      if (jj[u] < 0) continue;
+      const double* cj = Bs + jj[u] * rp1;
+      const double* ck = Bs + kk[u] * rp1;
+      double s0 = 0.0, s1 = 0.0;
+      int i = 0;
+      for (; i + 1 < B.rows; i += 2) {
+        s0 = fma(cj[i], ck[i], s0);
+        s1 = fma(cj[i + 1], ck[i + 1], s1);
+      }
+      if (i < B.rows) s0 = fma(cj[i], ck[i], s0);
+      g[u] += s0 + s1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < MAXE; ++u)
+    if (jj[u] >= 0) {
+      G[jj[u] + kk[u] * r] = g[u];
+      G[kk[u] + jj[u] * r] = g[u];
+    }
+  __syncthreads();
+  double gmax = 0.0;
+  for (int j = 0; j < r; ++j) gmax = fmax(gmax, G[j + j * r]);
+  const double tol = 8.0 * r * 2.220446049250313e-16 * gmax;
+  // right-looking Cholesky: row j of G becomes row j of R
+  for (int j = 0; j < r; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = G[j + j * r];
+      rjj_s = d > tol ? sqrt(d) : 0.0;
+      G[j + j * r] = rjj_s;
+    }
+    __syncthreads();
+    const double rjj = rjj_s;
+    for (int c = j + 1 + threadIdx.x; c < r; c += WG) G[j + c * r] = rjj > 0.0 ? G[j + c * r] / rjj : 0.0;
+    __syncthreads();
+    const int w = r - j - 1;
+    for (int e = threadIdx.x; e < w * w; e += WG) {
+      const int aa = j + 1 + e % w, bb = j + 1 + e / w;
+      if (aa <= bb) G[aa + bb * r] -= G[j + aa * r] * G[j + bb * r];
+    }
+    __syncthreads();
+  }
+  T* out = static_cast<T*>(a.out) + (a.out_by_id ? (size_t)q : (size_t)t) * a.so;
+  for (int e = threadIdx.x; e < r * r; e += WG) {
+    const int i = e % r, j = e / r;
+    out[i + (size_t)j * a.ldo] = j < i ? T(0) : (T)G[i + j * r];
+  }
+}
+
 // ------------------------------------------------------- BLOCKED INVERSE
 // Gauss-Jordan by panels of nb columns.  The panel kernel runs the nb
 // unblocked steps restricted to the panel columns (pivot search over the
@@ -1887,8 +2003,16 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
   const int tiles = cdiv(max_rows, WAVE);
   const dim3 grid(a.nb, (step == 1 ? 9 : 1) * tiles);
   const size_t lds = sizeof(double) * SV_C * (size_t)a.mpad;
-  if (ty) hipLaunchKernelGGL(k_solve<float>, grid, dim3(WG), lds, s, a, step, wk, tiles);
-  else hipLaunchKernelGGL(k_solve<double>, grid, dim3(WG), lds, s, a, step, wk, tiles);
+#define SOLVE_GO(S)                                                                           \
+  if (ty) hipLaunchKernelGGL((k_solve<float, S>), grid, dim3(WG), lds, s, a, wk, tiles);   \
+  else hipLaunchKernelGGL((k_solve<double, S>), grid, dim3(WG), lds, s, a, wk, tiles);
+  switch (step) {
+    case 0: SOLVE_GO(0) break;
+    case 1: SOLVE_GO(1) break;
+    case 2: SOLVE_GO(2) break;
+    default: SOLVE_GO(3) break;
+  }
+#undef SOLVE_GO
 }
 
 void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s) {
@@ -2031,6 +2155,35 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_
   }
 }
 
+
+template <class T, int MAXE>
+void gram_win_go(const WinStack& a, size_t lds, hipStream_t s) {
+  static size_t raised = 64 * 1024;
+  if (lds > raised) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_win<T, MAXE>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+      raised = lds;
+    else
+      (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_gram_win<T, MAXE>), dim3(a.nt), dim3(WG), lds, s, a);
+}
+
+// Entries of the packed upper triangle per thread: r (r + 1) / 2 <= MAXE WG.
+void launch_gram_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
+  if (a.nt <= 0 || max_r <= 0) return;
+  const size_t lds = sizeof(double) * ((size_t)max_r * (a.rpad + 1) + (size_t)max_r * max_r);
+  const int ne = max_r * (max_r + 1) / 2;
+  if (ty) {
+    if (ne <= 4 * WG) gram_win_go<float, 4>(a, lds, s);
+    else if (ne <= 11 * WG) gram_win_go<float, 11>(a, lds, s);
+    else gram_win_go<float, (kMaxRank * (kMaxRank + 1) / 2 + WG - 1) / WG>(a, lds, s);
+  } else {
+    if (ne <= 4 * WG) gram_win_go<double, 4>(a, lds, s);
+    else if (ne <= 11 * WG) gram_win_go<double, 11>(a, lds, s);
+    else gram_win_go<double, (kMaxRank * (kMaxRank + 1) / 2 + WG - 1) / WG>(a, lds, s);
+  }
+}
 
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
   if (a.nt <= 0 || max_r <= 0) return;
