@@ -1415,6 +1415,9 @@ struct Plan final : ifmm_plan {
     a.nt = nt;
     a.S = S;
     a.out_by_id = by_id ? 1 : 0;
+    a.max_rows = *std::max_element(L.r.begin(), L.r.end());
+    if (k > 2) a.max_rows = std::max(a.max_rows, *std::max_element(lv[k - 1].r.begin(), lv[k - 1].r.end()));
+    a.max_rows = std::max(a.max_rows, 1);
     st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr, false, gram);
     count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2, gram] {
       return winstack_work(a, ids, r, par ? &rp : nullptr, sizeof(T), gram);

@@ -164,6 +164,7 @@ struct WinStack {
   const int* r_par;  // [nc / 4] or null
   size_t sM, so;
   int rpad, nside, ldo, nt, S, out_by_id;
+  int max_rows;  // largest block of a stack (the ranks of the level and of z)
 };
 
 // One eliminated cluster of a colour batch (Algorithm 1, one Schur step):

@@ -1339,6 +1339,34 @@ __global__ __launch_bounds__(WG) void k_stackqr(const StackQrDesc* __restrict__ 
                   static_cast<T*>(d.R), d.ldr);
 }
 
+// The blocks of cluster q's stack in segment sg of S (window slots
+// [36 sg / S, 36 (sg + 1) / S), the last segment also the parent term z_t),
+// listed by the first wave: lane sl tests slot sl, and a ballot compacts the
+// list in slot order (no lane waits on another's loads).
+template <class T>
+__device__ void win_blocks(const WinStack& a, int q, int t, int sg, int S, BlkRef* bl, int& nb) {
+  const int lane = threadIdx.x % WAVE;
+  const int qx = demorton_x(q), qy = demorton_y(q);
+  const int s0 = 36 * sg / S, s1 = 36 * (sg + 1) / S;
+  const int sl = s0 + lane;
+  int rows = 0;
+  if (sl < s1) {
+    const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
+    if (jx >= 0 && jy >= 0 && jx < a.nside && jy < a.nside && (abs(jx - qx) > 1 || abs(jy - qy) > 1))
+      rows = a.r[morton2(jx, jy)];
+  }
+  const unsigned long long mask = __ballot(rows > 0);
+  const int pos = __popcll(mask & ((1ull << lane) - 1));
+  if (rows > 0) bl[pos] = BlkRef{static_cast<const T*>(a.M) + ((size_t)q * 36 + sl) * a.sM, a.rpad, rows, 1};
+  const int c = __popcll(mask);
+  if (lane == 0) {
+    int n = c;
+    if (sg == S - 1 && a.Z && a.r_par && a.r_par[q >> 2] > 0)
+      bl[n++] = BlkRef{static_cast<const T*>(a.Z) + (size_t)t * a.sM, a.rpad, a.r_par[q >> 2], 0};
+    nb = n;
+  }
+}
+
 // Far-field weight of cluster q = ids[t] with its blocks found on the device:
 // the stack of M(q, l)^T over the partners l of q's window (rows r[l]),
 // then the parent term z_t (rows r_par[q / 4], when given).  Segment s of
@@ -1354,135 +1382,125 @@ __global__ __launch_bounds__(WG) void k_stackqr_win(const WinStack a, int chunk)
   const int q = a.ids[t];
   const int r = a.r[q];
   if (r == 0) return;
-  if (threadIdx.x == 0) {
-    const int qx = demorton_x(q), qy = demorton_y(q);
-    int c = 0;
-    for (int sl = 36 * sg / a.S; sl < 36 * (sg + 1) / a.S; ++sl) {
-      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
-      if (abs(jx - qx) <= 1 && abs(jy - qy) <= 1) continue;
-      const int l = morton2(jx, jy);
-      if (a.r[l] == 0) continue;
-      bl[c++] = BlkRef{static_cast<const T*>(a.M) + ((size_t)q * 36 + sl) * a.sM, a.rpad, a.r[l], 1};
-    }
-    if (sg == a.S - 1 && a.Z && a.r_par && a.r_par[q >> 2] > 0)
-      bl[c++] = BlkRef{static_cast<const T*>(a.Z) + (size_t)t * a.sM, a.rpad, a.r_par[q >> 2], 0};
-    nb = c;
-  }
+  if (threadIdx.x < WAVE) win_blocks<T>(a, q, t, sg, a.S, bl, nb);
   __syncthreads();
   T* out = static_cast<T*>(a.out) + (a.S == 1 && a.out_by_id ? (size_t)q : (size_t)t * a.S + sg) * a.so;
   stackqr_body<T>(reinterpret_cast<T*>(smem), r, nb, [&](int b) { return bl[b]; }, chunk, out, a.ldo);
 }
 
 // Far-field weight of cluster q = ids[t] from the Gram matrix of its stack:
-// G = sum_l M(q, l) M(q, l)^T (+ z^T z for the parent term) accumulated in
-// FP64 from the stored blocks, then R with R^T R = G by Cholesky (a pivot at
-// or below 8 r eps_64 max_i G_ii, a direction the stack does not reach above
-// FP64 rounding, gives a zero row).  R equals the R factor of the stack
-// (positive diagonal) up to rounding in every direction above sqrt(eps_64)
-// of the largest; used for the FP32 factor, where those below are FP32
-// noise.  Output as k_stackqr_win with S == 1.
-template <class T, int MAXE>
+// G = sum_l M(q, l) M(q, l)^T (+ z^T z for the parent term), the blocks
+// staged GRAM_NB at a time in LDS and multiplied on the FP64 matrix cores
+// (16 x 16 blocks of the upper triangle of G spread over the waves, four rows
+// of the stack per v_mfma_f64_16x16x4), then R with R^T R = G by Cholesky
+// in one wave (a pivot at or below 8 r eps_64 max_i G_ii, a direction the
+// stack does not reach above FP64 rounding, gives a zero row).  R equals the
+// R factor of the stack (positive diagonal) up to rounding in every
+// direction above sqrt(eps_64) of the largest; used for the FP32 factor,
+// where those below are FP32 noise.  Output as k_stackqr_win with S == 1.
+constexpr int GRAM_NB = 4;
+template <class T, int MAXP>
 __global__ __launch_bounds__(WG) void k_gram_win(const WinStack a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BlkRef bl[37];
   __shared__ int nb;
-  __shared__ double rjj_s;
   const int t = blockIdx.x;
   const int q = a.ids[t];
   const int r = a.r[q];
   if (r == 0) return;
-  const int rp1 = a.rpad + 1;
-  double* Bs = reinterpret_cast<double*>(smem);  // staged block, [col][row], ld rpad + 1
-  double* G = Bs + (size_t)r * rp1;               // r x r
-  if (threadIdx.x == 0) {
-    const int qx = demorton_x(q), qy = demorton_y(q);
-    int c = 0;
-    for (int sl = 0; sl < 36; ++sl) {
-      const int jx = 2 * (qx >> 1) - 2 + sl / 6, jy = 2 * (qy >> 1) - 2 + sl % 6;
-      if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) continue;
-      if (abs(jx - qx) <= 1 && abs(jy - qy) <= 1) continue;
-      const int l = morton2(jx, jy);
-      if (a.r[l] == 0) continue;
-      bl[c++] = BlkRef{static_cast<const T*>(a.M) + ((size_t)q * 36 + sl) * a.sM, a.rpad, a.r[l], 1};
-    }
-    if (a.Z && a.r_par && a.r_par[q >> 2] > 0)
-      bl[c++] = BlkRef{static_cast<const T*>(a.Z) + (size_t)t * a.sM, a.rpad, a.r_par[q >> 2], 0};
-    nb = c;
-  }
-  // upper-triangle entries (j <= k) owned by each thread, in registers
-  const int ne = r * (r + 1) / 2;  // <= MAXE WG
-  double g[MAXE];
-  int jj[MAXE], kk[MAXE];
+  const int rp1 = a.max_rows + 1;
+  const size_t bsz = (size_t)r * rp1;                // one staged block, [col][row]
+  double* G = reinterpret_cast<double*>(smem);       // r x r
+  T* Bs = reinterpret_cast<T*>(G + (size_t)r * r);   // GRAM_NB blocks
+  if (threadIdx.x < WAVE) win_blocks<T>(a, q, t, 0, 1, bl, nb);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int li = lane % 16, lk = lane / 16;
+  const int nbk = (r + 15) / 16, npair = nbk * (nbk + 1) / 2;
+  constexpr int NW = WG / WAVE;
+  // this wave's upper blocks (bi <= bj) of G: pair index w, w + NW, ... (< MAXP NW)
+  int pbi[MAXP], pbj[MAXP];
 #pragma unroll
-  for (int u = 0; u < MAXE; ++u) {
-    g[u] = 0.0;
-    const int e = threadIdx.x + u * WG;
-    int j = 0, rem = e;  // row j of the packed upper triangle: entries j..r-1
-    while (j < r && rem >= r - j) {
-      rem -= r - j;
-      ++j;
+  for (int u = 0; u < MAXP; ++u) {
+    int pidx = w + u * NW, bi = 0;
+    while (bi < nbk && pidx >= nbk - bi) {
+      pidx -= nbk - bi;
+      ++bi;
     }
-    jj[u] = e < ne ? j : -1;
-    kk[u] = e < ne ? j + rem : -1;
+    pbi[u] = w + u * NW < npair ? bi : -1;
+    pbj[u] = bi + pidx;
   }
+  md4 acc[MAXP];
+#pragma unroll
+  for (int u = 0; u < MAXP; ++u) acc[u] = md4{0, 0, 0, 0};
   __syncthreads();
-  for (int b = 0; b < nb; ++b) {
-    const BlkRef B = bl[b];
-    const T* Bp = static_cast<const T*>(B.p);
+  for (int b0 = 0; b0 < nb; b0 += GRAM_NB) {
+    const int b1 = min(nb, b0 + GRAM_NB);
     __syncthreads();
-    for (int e = threadIdx.x; e < B.rows * r; e += WG) {
-      int i, j;
-      if (B.trans) { j = e % r; i = e / r; } else { i = e % B.rows; j = e / B.rows; }
-      Bs[i + j * rp1] = (double)(B.trans ? Bp[j + (size_t)i * B.ld] : Bp[i + (size_t)j * B.ld]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MAXE; ++u) {
-      if (jj[u] < 0) continue;
-      const double* cj = Bs + jj[u] * rp1;
-      const double* ck = Bs + kk[u] * rp1;
-      double s0 = 0.0, s1 = 0.0;
-      int i = 0;
-      for (; i + 1 < B.rows; i += 2) {
-        s0 = fma(cj[i], ck[i], s0);
-        s1 = fma(cj[i + 1], ck[i + 1], s1);
+    for (int b = b0; b < b1; ++b) {
+      const BlkRef B = bl[b];
+      const T* Bp = static_cast<const T*>(B.p);
+      T* dst = Bs + (b - b0) * bsz;
+      for (int e = threadIdx.x; e < B.rows * r; e += WG) {
+        int i, j;
+        if (B.trans) { j = e % r; i = e / r; } else { i = e % B.rows; j = e / B.rows; }
+        dst[i + j * rp1] = B.trans ? Bp[j + (size_t)i * B.ld] : Bp[i + (size_t)j * B.ld];
       }
-      if (i < B.rows) s0 = fma(cj[i], ck[i], s0);
-      g[u] += s0 + s1;
+    }
+    __syncthreads();
+    for (int b = b0; b < b1; ++b) {
+      const int rows = bl[b].rows;
+      const T* src = Bs + (b - b0) * bsz;
+      for (int k0 = 0; k0 < rows; k0 += 4) {
+        const int row = k0 + lk;
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u) {
+          if (pbi[u] < 0) continue;
+          const int ca = 16 * pbi[u] + li, cb = 16 * pbj[u] + li;
+          const double xa = row < rows && ca < r ? (double)src[row + ca * rp1] : 0.0;
+          const double xb = row < rows && cb < r ? (double)src[row + cb * rp1] : 0.0;
+          acc[u] = mfma16(xa, xb, acc[u]);
+        }
+      }
     }
   }
   __syncthreads();
+  // G(16 bi + i, 16 bj + j) = acc(i, j): lane j + 16 (i % 4), register i / 4
 #pragma unroll
-  for (int u = 0; u < MAXE; ++u)
-    if (jj[u] >= 0) {
-      G[jj[u] + kk[u] * r] = g[u];
-      G[kk[u] + jj[u] * r] = g[u];
+  for (int u = 0; u < MAXP; ++u) {
+    if (pbi[u] < 0) continue;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int gi = 16 * pbi[u] + mfma_row(0.0, lane, rr), gj = 16 * pbj[u] + li;
+      if (gi < r && gj < r) {
+        G[gi + gj * r] = acc[u][rr];
+        G[gj + gi * r] = acc[u][rr];
+      }
     }
+  }
   __syncthreads();
+  if (threadIdx.x >= WAVE) return;
+  // right-looking Cholesky by one wave (lane c owns columns c, c + 64, ...):
+  // row j of G becomes row j of R
   double gmax = 0.0;
   for (int j = 0; j < r; ++j) gmax = fmax(gmax, G[j + j * r]);
   const double tol = 8.0 * r * 2.220446049250313e-16 * gmax;
-  // right-looking Cholesky: row j of G becomes row j of R
   for (int j = 0; j < r; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = G[j + j * r];
-      rjj_s = d > tol ? sqrt(d) : 0.0;
-      G[j + j * r] = rjj_s;
+    const double d = G[j + j * r];
+    const double rjj = d > tol ? sqrt(d) : 0.0;
+    for (int c = j + lane; c < r; c += WAVE) G[j + c * r] = c == j ? rjj : (rjj > 0.0 ? G[j + c * r] / rjj : 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = j + 1 + lane; c < r; c += WAVE) {
+      const double rjc = G[j + c * r];
+      for (int aa = j + 1; aa <= c; ++aa) G[aa + c * r] -= G[j + aa * r] * rjc;
     }
-    __syncthreads();
-    const double rjj = rjj_s;
-    for (int c = j + 1 + threadIdx.x; c < r; c += WG) G[j + c * r] = rjj > 0.0 ? G[j + c * r] / rjj : 0.0;
-    __syncthreads();
-    const int w = r - j - 1;
-    for (int e = threadIdx.x; e < w * w; e += WG) {
-      const int aa = j + 1 + e % w, bb = j + 1 + e / w;
-      if (aa <= bb) G[aa + bb * r] -= G[j + aa * r] * G[j + bb * r];
-    }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   T* out = static_cast<T*>(a.out) + (a.out_by_id ? (size_t)q : (size_t)t) * a.so;
-  for (int e = threadIdx.x; e < r * r; e += WG) {
+  for (int e = lane; e < r * r; e += WAVE) {
     const int i = e % r, j = e / r;
     out[i + (size_t)j * a.ldo] = j < i ? T(0) : (T)G[i + j * r];
   }
@@ -2156,33 +2174,34 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_
 }
 
 
-template <class T, int MAXE>
+template <class T, int MAXP>
 void gram_win_go(const WinStack& a, size_t lds, hipStream_t s) {
   static size_t raised = 64 * 1024;
   if (lds > raised) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_win<T, MAXE>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_win<T, MAXP>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
       raised = lds;
     else
       (void)hipGetLastError();
   }
-  hipLaunchKernelGGL((k_gram_win<T, MAXE>), dim3(a.nt), dim3(WG), lds, s, a);
+  hipLaunchKernelGGL((k_gram_win<T, MAXP>), dim3(a.nt), dim3(WG), lds, s, a);
 }
 
-// Entries of the packed upper triangle per thread: r (r + 1) / 2 <= MAXE WG.
+template <class T>
+void gram_win_by_rank(const WinStack& a, int max_r, size_t lds, hipStream_t s) {
+  const int nbk = (max_r + 15) / 16, np = nbk * (nbk + 1) / 2, per = (np + WG / WAVE - 1) / (WG / WAVE);
+  if (per <= 1) gram_win_go<T, 1>(a, lds, s);
+  else if (per <= 2) gram_win_go<T, 2>(a, lds, s);
+  else if (per <= 4) gram_win_go<T, 4>(a, lds, s);
+  else gram_win_go<T, 9>(a, lds, s);  // max_r <= kMaxRank = 128: 36 blocks
+}
+
 void launch_gram_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
   if (a.nt <= 0 || max_r <= 0) return;
-  const size_t lds = sizeof(double) * ((size_t)max_r * (a.rpad + 1) + (size_t)max_r * max_r);
-  const int ne = max_r * (max_r + 1) / 2;
-  if (ty) {
-    if (ne <= 4 * WG) gram_win_go<float, 4>(a, lds, s);
-    else if (ne <= 11 * WG) gram_win_go<float, 11>(a, lds, s);
-    else gram_win_go<float, (kMaxRank * (kMaxRank + 1) / 2 + WG - 1) / WG>(a, lds, s);
-  } else {
-    if (ne <= 4 * WG) gram_win_go<double, 4>(a, lds, s);
-    else if (ne <= 11 * WG) gram_win_go<double, 11>(a, lds, s);
-    else gram_win_go<double, (kMaxRank * (kMaxRank + 1) / 2 + WG - 1) / WG>(a, lds, s);
-  }
+  const size_t lds = sizeof(double) * (size_t)max_r * max_r +
+                     (ty ? sizeof(float) : sizeof(double)) * GRAM_NB * (size_t)max_r * (a.max_rows + 1);
+  if (ty) gram_win_by_rank<float>(a, max_r, lds, s);
+  else gram_win_by_rank<double>(a, max_r, lds, s);
 }
 
 void launch_stackqr_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
