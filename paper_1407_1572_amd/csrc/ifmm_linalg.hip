@@ -1058,10 +1058,8 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      T part = 0;
-      for (int i = lane; i < NR; i += WAVE)
-        if (i >= j && i < n) part = fma(xs[i], xs[i], part);
-      const T xn = sqrt(wave_sum(part));
+      // the pivot's norm over rows j.. is the pivot value itself
+      const T xn = piv;
       const T x0 = xs[j];
       T alpha = 0, tau = 0, iv = 0;
       if (xn > 0) {
