@@ -860,7 +860,7 @@ namespace {
 template <class T>
 struct Plan final : ifmm_plan {
   static constexpr bool kF32 = std::is_same<T, float>::value;
-  std::vector<int> perm, leaf_start, leaf_n;
+  std::vector<int> leaf_start, leaf_n;
   double* d_pts = nullptr;
   int *d_perm = nullptr, *d_leaf_start = nullptr, *d_leaf_n = nullptr, *d_nbr9_leaf = nullptr;
   double* d_diag = nullptr;
@@ -1098,41 +1098,35 @@ struct Plan final : ifmm_plan {
   }
 
   // ---------------------------------------------------------------- tree
-  void build_tree(const std::vector<double>& pts) {
+  // Points (original order, device) -> tree order on the device; the leaf
+  // populations come back to the host for planning.
+  void build_tree(const double* d_points_in) {
     kappa = 2;
     while ((int64_t)leaf * (1LL << (2 * kappa)) < N) ++kappa;
     if (kappa > 12) throw BadArg{};
     const int nb = 1 << kappa;
     const int nleaf = nb * nb;
-    std::vector<int> key(N);
-    for (int64_t a = 0; a < N; ++a) {
-      const double x = pts[2 * a], y = pts[2 * a + 1];
-      if (!std::isfinite(x) || !std::isfinite(y)) throw BadArg{};
-      if (x < lox || y < loy || x > lox + size || y > loy + size) throw BadArg{};
-      int ix = (int)std::floor((x - lox) / size * nb), iy = (int)std::floor((y - loy) / size * nb);
-      ix = std::min(std::max(ix, 0), nb - 1);
-      iy = std::min(std::max(iy, 0), nb - 1);
-      key[a] = morton2(ix, iy);
-    }
-    leaf_n.assign(nleaf, 0);
-    for (int64_t a = 0; a < N; ++a) leaf_n[key[a]]++;
+    const int n = (int)N;
+    d_pts = dalloc<double>(s, 2 * N);
+    d_perm = dalloc<int>(s, N);
+    d_leaf_start = dalloc<int>(s, nleaf);
+    d_leaf_n = dalloc<int>(s, nleaf + 1);  // + the rejection flag
+    int* bad = d_leaf_n + nleaf;
+    size_t tmp_bytes = 0;
+    HIP_OK(tree_scratch_bytes(n, nleaf, 2 * kappa, &tmp_bytes));
+    int* ki = wsS1.need<int>(3 * N, s);
+    void* tmp = wsS2.need<char>(tmp_bytes, s);
+    HIP_OK(hipMemsetAsync(d_leaf_n, 0, sizeof(int) * (nleaf + 1), s));
+    HIP_OK(launch_tree_build(d_points_in, n, lox, loy, size, kappa, ki, ki + N, ki + 2 * N, d_perm, d_leaf_n,
+                             d_leaf_start, bad, d_pts, tmp, tmp_bytes, s));
+    if (kf.kind == 0) launch_tree_distinct(d_pts, d_leaf_start, d_leaf_n, nleaf, bad, s);  // 1/r: distinct
+    leaf_n.assign(nleaf + 1, 0);
+    HIP_OK(hipMemcpyAsync(leaf_n.data(), d_leaf_n, sizeof(int) * (nleaf + 1), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (leaf_n[nleaf]) throw BadArg{};
+    leaf_n.resize(nleaf);
     leaf_start.assign(nleaf, 0);
     for (int i = 1; i < nleaf; ++i) leaf_start[i] = leaf_start[i - 1] + leaf_n[i - 1];
-    perm.assign(N, 0);
-    std::vector<int> fillp(leaf_start);
-    for (int64_t a = 0; a < N; ++a) perm[fillp[key[a]]++] = (int)a;  // stable
-    if (kf.kind == 0) {  // 1/r needs distinct points
-      for (int i = 0; i < nleaf; ++i) {
-        std::vector<std::pair<double, double>> v;
-        for (int a = 0; a < leaf_n[i]; ++a) {
-          const int g = perm[leaf_start[i] + a];
-          v.emplace_back(pts[2 * g], pts[2 * g + 1]);
-        }
-        std::sort(v.begin(), v.end());
-        for (size_t a = 1; a < v.size(); ++a)
-          if (v[a] == v[a - 1]) throw BadArg{};
-      }
-    }
     lv.assign(kappa + 1, Level<T>());
     for (int k = 2; k <= kappa; ++k) {
       Level<T>& L = lv[k];
@@ -1184,28 +1178,12 @@ struct Plan final : ifmm_plan {
 
   // --------------------------------------------------------------- assembly
   void assemble(const double* d_points_in) {
-    std::vector<double> pts(2 * N);
-    HIP_OK(hipMemcpyAsync(pts.data(), d_points_in, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    build_tree(pts);
+    build_tree(d_points_in);
     const int nleaf = 1 << (2 * kappa);
-    std::vector<double> spts(2 * N);
-    for (int64_t a = 0; a < N; ++a) {
-      spts[2 * a] = pts[2 * perm[a]];
-      spts[2 * a + 1] = pts[2 * perm[a] + 1];
-    }
-    d_pts = dalloc<double>(s, 2 * N);
-    d_perm = dalloc<int>(s, N);
-    d_leaf_start = dalloc<int>(s, nleaf);
-    d_leaf_n = dalloc<int>(s, nleaf);
     d_nbr9_leaf = dalloc<int>(s, (size_t)nleaf * 9);
     d_diag = dalloc<double>(s, N);
     d_status = dalloc<Status>(s, 1);
     HIP_OK(hipMemsetAsync(d_status, 0, sizeof(Status), s));
-    HIP_OK(hipMemcpyAsync(d_pts, spts.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * N, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d_leaf_start, leaf_start.data(), sizeof(int) * nleaf, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(d_leaf_n, leaf_n.data(), sizeof(int) * nleaf, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(d_nbr9_leaf, lv[kappa].nbr9.data(), sizeof(int) * nleaf * 9, hipMemcpyHostToDevice, s));
     std::vector<double> E = transfer_host(p);
     d_E = dalloc<double>(s, E.size());
@@ -1218,19 +1196,13 @@ struct Plan final : ifmm_plan {
     // diagonal
     if (diag_mode == IFMM_DIAG_ROWSUM) {
       double* ones = wsS1.need(N, s);
-      std::vector<double> h1(N, 1.0);
-      HIP_OK(hipMemcpyAsync(ones, h1.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+      launch_fill(ones, N, 1.0, s);
       fmm_apply_tree(ones, d_diag, 1, nullptr);
-      std::vector<double> hd(N);
-      HIP_OK(hipMemcpyAsync(hd.data(), d_diag, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
-      for (auto& v : hd) v += c0;
-      HIP_OK(hipMemcpyAsync(d_diag, hd.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-      HIP_OK(hipStreamSynchronize(s));
+      launch_add_const(d_diag, N, c0, s);
     } else {
-      std::vector<double> hd(N, c0);
-      HIP_OK(hipMemcpyAsync(d_diag, hd.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+      launch_fill(d_diag, N, c0, s);
     }
+    HIP_OK(hipGetLastError());
 
     // ---- leaf level: interpolation, orthonormal bases, near field
     Level<T>& Lf = lv[kappa];

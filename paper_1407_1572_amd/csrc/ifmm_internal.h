@@ -399,4 +399,21 @@ void launch_gather_rows(const double* src, int ld_src, const int* idx, int n, in
 void launch_scatter_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
                          double* dst, int ld_dst, hipStream_t s);
 
+// Quadtree of n points (x, y interleaved, any order) at depth kappa, on the
+// stream: key_in / key_out / idx are n-int scratch, tmp holds
+// tree_scratch_bytes(n, 4^kappa, 2 kappa); leaf_n (4^kappa ints) must be
+// zeroed.  Out: perm (tree position -> original index, stable within a leaf),
+// leaf_n, leaf_start (exclusive prefix sum), spts (coordinates in tree order),
+// *bad = 1 for a point not finite or outside [lo, lo + size]^2.
+hipError_t tree_scratch_bytes(int n, int nleaf, int bits, size_t* bytes);
+hipError_t launch_tree_build(const double* pts, int n, double lox, double loy, double size, int kappa,
+                             int* key_in, int* key_out, int* idx, int* perm, int* leaf_n,
+                             int* leaf_start, int* bad, double* spts, void* tmp, size_t tmp_bytes,
+                             hipStream_t s);
+// *bad = 1 when two points of one leaf coincide.
+void launch_tree_distinct(const double* spts, const int* leaf_start, const int* leaf_n, int nleaf,
+                          int* bad, hipStream_t s);
+void launch_fill(double* x, size_t n, double v, hipStream_t s);
+void launch_add_const(double* x, size_t n, double v, hipStream_t s);
+
 }  // namespace ifmm

@@ -1,0 +1,126 @@
+// Quadtree of the points on gfx950 (Section 2: the hierarchical subdivision of
+// the square domain that the FMM and its inverse share).  Every point gets the
+// Morton index of its leaf box; a stable radix sort by that index gives the
+// tree order (points of one leaf contiguous, original order kept within a
+// leaf); a histogram gives the leaf populations.  Validation (finite, inside
+// the box, distinct within a leaf for the singular kernel) sets a flag that the
+// host reads back with the populations.
+#include "ifmm_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+namespace ifmm {
+
+namespace {
+
+// key[a] = Morton index of the leaf box of point a, idx[a] = a, leaf_n[key]++.
+// A point outside the box or not finite sets *bad and is filed in box 0.
+__global__ void __launch_bounds__(256) k_tree_keys(const double* __restrict__ pts, int n, double lox,
+                                                   double loy, double size, int nb, int* __restrict__ key,
+                                                   int* __restrict__ idx, int* __restrict__ leaf_n,
+                                                   int* __restrict__ bad) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= n) return;
+  const double x = pts[2 * a], y = pts[2 * a + 1];
+  int k = 0;
+  if (!isfinite(x) || !isfinite(y) || x < lox || y < loy || x > lox + size || y > loy + size) {
+    *bad = 1;
+  } else {
+    int ix = (int)floor((x - lox) / size * nb), iy = (int)floor((y - loy) / size * nb);
+    ix = min(max(ix, 0), nb - 1);
+    iy = min(max(iy, 0), nb - 1);
+    k = morton2(ix, iy);
+  }
+  key[a] = k;
+  idx[a] = a;
+  atomicAdd(leaf_n + k, 1);
+}
+
+// Sorted coordinates: dst[i] = src[perm[i]] for the (x, y) pairs.
+__global__ void __launch_bounds__(256) k_tree_gather(const double* __restrict__ src,
+                                                     const int* __restrict__ perm, int n,
+                                                     double2* __restrict__ dst) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const int a = perm[i];
+    dst[i] = make_double2(src[2 * a], src[2 * a + 1]);
+  }
+}
+
+// Two equal points in one leaf set *bad (the 1/r kernel is singular there).
+// One workgroup per leaf, all pairs compared.
+__global__ void __launch_bounds__(256) k_tree_distinct(const double2* __restrict__ pts,
+                                                       const int* __restrict__ leaf_start,
+                                                       const int* __restrict__ leaf_n,
+                                                       int* __restrict__ bad) {
+  const int i = blockIdx.x, n = leaf_n[i];
+  if (n < 2) return;
+  const double2* p = pts + leaf_start[i];
+  int hit = 0;
+  for (int a = threadIdx.x; a < n; a += 256) {
+    const double2 u = p[a];
+    for (int b = a + 1; b < n; ++b) {
+      const double2 v = p[b];
+      hit |= (u.x == v.x) & (u.y == v.y);
+    }
+  }
+  if (hit) *bad = 1;
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* __restrict__ x, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_add_const(double* __restrict__ x, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] += v;
+}
+
+}  // namespace
+
+hipError_t tree_scratch_bytes(int n, int nleaf, int bits, size_t* bytes) {
+  size_t a = 0, b = 0;
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, a, (int*)nullptr, (int*)nullptr, (int*)nullptr, (int*)nullptr,
+                                           (size_t)n, 0u, (unsigned)bits);
+  if (e != hipSuccess) return e;
+  e = rocprim::exclusive_scan(nullptr, b, (int*)nullptr, (int*)nullptr, 0, (size_t)nleaf, rocprim::plus<int>());
+  *bytes = a > b ? a : b;
+  return e;
+}
+
+hipError_t launch_tree_build(const double* pts, int n, double lox, double loy, double size, int kappa,
+                       int* key_in, int* key_out, int* idx, int* perm, int* leaf_n, int* leaf_start,
+                       int* bad, double* spts, void* tmp, size_t tmp_bytes, hipStream_t s) {
+  const int nb = 1 << kappa, nleaf = nb * nb;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_tree_keys, dim3(g), dim3(256), 0, s, pts, n, lox, loy, size, nb, key_in, idx,
+                     leaf_n, bad);
+  size_t t = tmp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(tmp, t, key_in, key_out, idx, perm, (size_t)n, 0u, (unsigned)(2 * kappa), s);
+  if (e != hipSuccess) return e;
+  t = tmp_bytes;
+  e = rocprim::exclusive_scan(tmp, t, leaf_n, leaf_start, 0, (size_t)nleaf, rocprim::plus<int>(), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tree_gather, dim3(g), dim3(256), 0, s, pts, perm, n, reinterpret_cast<double2*>(spts));
+  return hipGetLastError();
+}
+
+void launch_tree_distinct(const double* spts, const int* leaf_start, const int* leaf_n, int nleaf,
+                          int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_distinct, dim3(nleaf), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(spts), leaf_start, leaf_n, bad);
+}
+
+void launch_fill(double* x, size_t n, double v, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+}
+
+void launch_add_const(double* x, size_t n, double v, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_add_const, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+}
+
+}  // namespace ifmm

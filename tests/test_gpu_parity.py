@@ -157,3 +157,28 @@ def test_profile_family_mask(torch_dev):
     # the same launches, with the same algorithmic counts
     assert only["elim"]["launches"] == full["elim"]["launches"]
     assert only["elim"]["flops"] == full["elim"]["flops"] and only["elim"]["bytes"] == full["elim"]["bytes"]
+
+
+def test_rejected_points(torch_dev):
+    """Points the tree build refuses (not finite, outside the box, two equal
+    points of the singular kernel) give 'invalid argument'; equal points are
+    fine for the smooth kernel, and a point on the box's far edge is inside."""
+    _say("[gpu] tree build: rejected points")
+    from paper_1407_1572_amd import IFMMError
+    base = workloads.uniform(600, 1007)
+    bad = []
+    p = base.copy(); p[17] = (1.25, 0.5); bad.append(("outside", p, "exp"))
+    p = base.copy(); p[301, 1] = np.nan; bad.append(("nan", p, "exp"))
+    p = base.copy(); p[5] = p[444]; bad.append(("equal, 1/r", p, "inv_r"))
+    for name, pts, kern in bad:
+        _say(f"  {name}")
+        with pytest.raises(IFMMError) as e:
+            _gpu(torch_dev, pts, kern, 0.1, "rowsum", 1.0, 1e-8, 8, 3, box=(0.0, 0.0, 1.0))
+        assert e.value.code == 1
+    p = base.copy(); p[5] = p[444]; p[9] = (1.0, 1.0)
+    s = _gpu(torch_dev, p, "exp", 0.1, "const", 1.01, 0.0, 8, 3, r_max=64, box=(0.0, 0.0, 1.0))
+    b = workloads.rhs(600, 1, 2003)[:, 0].copy()
+    x = s.solve(torch_dev[0].from_numpy(b).to(torch_dev[1])).cpu().numpy()
+    o = IFMM(p, Kernel("exp", 0.1), 0.0, 8, 3, "const", 1.01, r_cap=64)
+    assert _rel(x, _dense(o, b)) < 1e-9
+    s.close()
