@@ -2066,10 +2066,18 @@ struct Plan final : ifmm_plan {
         HIP_OK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         double worst = 0.0;
-        for (int r = 0; r < nrhs; ++r) worst = std::max(worst, std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300));
+        for (int r = 0; r < nrhs; ++r) {
+          const double rel = std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300);
+          worst = std::isfinite(rel) ? std::max(worst, rel) : HUGE_VAL;  // a NaN column is not converged
+        }
         hist.push_back(worst);
         if (worst <= refine_tol) {
           xout = xt;
+          break;
+        }
+        if (worst == HUGE_VAL) {  // non-finite residual: stop with the best finite iterate (else x as is)
+          result = IFMM_ENOTCONV;
+          xout = best < 1e300 ? xbest : xt;
           break;
         }
         if (worst < best) {  // keep the best iterate for a non-converged return

@@ -1386,12 +1386,44 @@ __global__ __launch_bounds__(WG) void k_stackqr_win(const WinStack a, int chunk)
   stackqr_body<T>(reinterpret_cast<T*>(smem), r, nb, [&](int b) { return bl[b]; }, chunk, out, a.ldo);
 }
 
+// R with R^T R = G (r x r in LDS, overwritten) by a right-looking Cholesky
+// over the workgroup: row j of R goes to rowj, then (once every thread has
+// read G_jj) into row j of G while the trailing upper triangle takes the
+// rank-1 update, lane on rows j + 1 + lane (+ 64 ...), wave w on columns
+// j + 1 + w (+ NW ...).  A pivot at or below 8 r eps_64 max_i G_ii gives a
+// zero row.  R goes to the weight slot of cluster q (or of stack t).
+template <class T>
+__device__ void gram_chol(const WinStack& a, int q, int t, int r, double* G, double* rowj) {
+  constexpr int NW = WG / WAVE;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  double gmax = 0.0;
+  for (int j = 0; j < r; ++j) gmax = fmax(gmax, G[j + j * r]);
+  const double tol = 8.0 * r * 2.220446049250313e-16 * gmax;
+  for (int j = 0; j < r; ++j) {
+    const double d = G[j + j * r];
+    const double rjj = d > tol ? sqrt(d) : 0.0;
+    for (int c = j + threadIdx.x; c < r; c += WG) rowj[c] = c == j ? rjj : (rjj > 0.0 ? G[j + c * r] / rjj : 0.0);
+    __syncthreads();  // every thread has read G_jj
+    for (int c = j + threadIdx.x; c < r; c += WG) G[j + c * r] = rowj[c];
+    for (int c = j + 1 + w; c < r; c += NW) {
+      const double rjc = rowj[c];
+      for (int aa = j + 1 + lane; aa <= c; aa += WAVE) G[aa + c * r] -= rowj[aa] * rjc;
+    }
+    __syncthreads();
+  }
+  T* out = static_cast<T*>(a.out) + (a.out_by_id ? (size_t)q : (size_t)t) * a.so;
+  for (int e = threadIdx.x; e < r * r; e += WG) {
+    const int i = e % r, j = e / r;
+    out[i + (size_t)j * a.ldo] = j < i ? T(0) : (T)G[i + j * r];
+  }
+}
+
 // Far-field weight of cluster q = ids[t] from the Gram matrix of its stack:
 // G = sum_l M(q, l) M(q, l)^T (+ z^T z for the parent term), the blocks
 // staged GRAM_NB at a time in LDS and multiplied on the FP64 matrix cores
 // (16 x 16 blocks of the upper triangle of G spread over the waves, four rows
 // of the stack per v_mfma_f64_16x16x4), then R with R^T R = G by Cholesky
-// in one wave (a pivot at or below 8 r eps_64 max_i G_ii, a direction the
+// over the workgroup (a pivot at or below 8 r eps_64 max_i G_ii, a direction the
 // stack does not reach above FP64 rounding, gives a zero row).  R equals the
 // R factor of the stack (positive diagonal) up to rounding in every
 // direction above sqrt(eps_64) of the largest; used for the FP32 factor,
@@ -1402,6 +1434,7 @@ __global__ __launch_bounds__(WG) void k_gram_win(const WinStack a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BlkRef bl[37];
   __shared__ int nb;
+  __shared__ double rowj[kMaxRank];
   const int t = blockIdx.x;
   const int q = a.ids[t];
   const int r = a.r[q];
@@ -1476,32 +1509,80 @@ __global__ __launch_bounds__(WG) void k_gram_win(const WinStack a) {
     }
   }
   __syncthreads();
-  if (threadIdx.x >= WAVE) return;
-  // right-looking Cholesky by one wave (lane c owns columns c, c + 64, ...):
-  // row j of G becomes row j of R
-  double gmax = 0.0;
-  for (int j = 0; j < r; ++j) gmax = fmax(gmax, G[j + j * r]);
-  const double tol = 8.0 * r * 2.220446049250313e-16 * gmax;
-  for (int j = 0; j < r; ++j) {
-    const double d = G[j + j * r];
-    const double rjj = d > tol ? sqrt(d) : 0.0;
-    for (int c = j + lane; c < r; c += WAVE) G[j + c * r] = c == j ? rjj : (rjj > 0.0 ? G[j + c * r] / rjj : 0.0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int c = j + 1 + lane; c < r; c += WAVE) {
-      const double rjc = G[j + c * r];
-      for (int aa = j + 1; aa <= c; ++aa) G[aa + c * r] -= G[j + aa * r] * rjc;
+  gram_chol<T>(a, q, t, r, G, rowj);
+}
+
+// The same weight with the stack's blocks read straight from memory: wave w
+// takes blocks w, w + NW, ... and accumulates every upper 16 x 16 block pair
+// of G over its rows (NBK column blocks, r <= 16 NBK; four rows of the stack
+// per v_mfma_f64_16x16x4, NBK loads feeding NBK (NBK + 1) / 2 independent
+// accumulators); the waves' partial G are added in wave order (the same
+// result on every run), then the Cholesky above.
+template <class T, int NBK>
+__global__ __launch_bounds__(WG) void k_gram_rows(const WinStack a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ BlkRef bl[37];
+  __shared__ int nb;
+  __shared__ double rowj[kMaxRank];
+  constexpr int NW = WG / WAVE, NP = NBK * (NBK + 1) / 2;
+  const int t = blockIdx.x;
+  const int q = a.ids[t];
+  const int r = a.r[q];
+  if (r == 0) return;
+  double* G = reinterpret_cast<double*>(smem);  // r x r
+  if (threadIdx.x < WAVE) win_blocks<T>(a, q, t, 0, 1, bl, nb);
+  for (int e = threadIdx.x; e < r * r; e += WG) G[e] = 0.0;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int li = lane % 16, lk = lane / 16;
+  const int nbk = (r + 15) / 16;
+  md4 acc[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) acc[u] = md4{0, 0, 0, 0};
+  __syncthreads();
+  const int nbl = nb;
+  for (int b = w; b < nbl; b += NW) {
+    const BlkRef B = bl[b];
+    const T* Bp = static_cast<const T*>(B.p);
+    // stack row k, column c: B^T (k, c) = p[c + k ld] or B (k, c) = p[k + c ld]
+    const size_t sr = B.trans ? (size_t)B.ld : 1, sc = B.trans ? 1 : (size_t)B.ld;
+#pragma unroll 2
+    for (int k0 = 0; k0 < B.rows; k0 += 4) {
+      const int row = k0 + lk;
+      double x[NBK];
+#pragma unroll
+      for (int c = 0; c < NBK; ++c) {
+        const int col = 16 * c + li;
+        x[c] = row < B.rows && col < r ? (double)Bp[row * sr + col * sc] : 0.0;
+      }
+      int u = 0;
+#pragma unroll
+      for (int bi = 0; bi < NBK; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NBK; ++bj, ++u)
+          if (bj < nbk) acc[u] = mfma16(x[bi], x[bj], acc[u]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  T* out = static_cast<T*>(a.out) + (a.out_by_id ? (size_t)q : (size_t)t) * a.so;
-  for (int e = lane; e < r * r; e += WAVE) {
-    const int i = e % r, j = e / r;
-    out[i + (size_t)j * a.ldo] = j < i ? T(0) : (T)G[i + j * r];
+  // G(16 bi + i, 16 bj + j) += acc(i, j): lane j + 16 (i % 4), register i / 4
+  for (int ww = 0; ww < NW; ++ww) {
+    if (w == ww) {
+      int u = 0;
+#pragma unroll
+      for (int bi = 0; bi < NBK; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NBK; ++bj, ++u) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int gi = 16 * bi + mfma_row(0.0, lane, rr), gj = 16 * bj + li;
+            if (gi < r && gj < r) {
+              G[gi + gj * r] += acc[u][rr];
+              if (bi != bj) G[gj + gi * r] += acc[u][rr];
+            }
+          }
+        }
+    }
+    __syncthreads();
   }
+  gram_chol<T>(a, q, t, r, G, rowj);
 }
 
 // ------------------------------------------------------- BLOCKED INVERSE
@@ -2194,8 +2275,36 @@ void gram_win_by_rank(const WinStack& a, int max_r, size_t lds, hipStream_t s) {
   else gram_win_go<T, 9>(a, lds, s);  // max_r <= kMaxRank = 128: 36 blocks
 }
 
+template <class T, int NBK>
+void gram_rows_go(const WinStack& a, size_t lds, hipStream_t s) {
+  static size_t raised = 64 * 1024;
+  if (lds > raised) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_rows<T, NBK>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+      raised = lds;
+    else
+      (void)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_gram_rows<T, NBK>), dim3(a.nt), dim3(WG), lds, s, a);
+}
+
 void launch_gram_win(const WinStack& a, int max_r, int ty, hipStream_t s) {
   if (a.nt <= 0 || max_r <= 0) return;
+  if (max_r <= 80) {  // blocks read in place, all block pairs per wave
+    const size_t lds = sizeof(double) * (size_t)max_r * max_r;
+    const int nbk = (max_r + 15) / 16;
+#define GRAM_ROWS(T)                                  \
+  switch (nbk) {                                      \
+    case 1: gram_rows_go<T, 1>(a, lds, s); break;     \
+    case 2: gram_rows_go<T, 2>(a, lds, s); break;     \
+    case 3: gram_rows_go<T, 3>(a, lds, s); break;     \
+    case 4: gram_rows_go<T, 4>(a, lds, s); break;     \
+    default: gram_rows_go<T, 5>(a, lds, s); break;    \
+  }
+    if (ty) GRAM_ROWS(float) else GRAM_ROWS(double)
+#undef GRAM_ROWS
+    return;
+  }
   const size_t lds = sizeof(double) * (size_t)max_r * max_r +
                      (ty ? sizeof(float) : sizeof(double)) * GRAM_NB * (size_t)max_r * (a.max_rows + 1);
   if (ty) gram_win_by_rank<float>(a, max_r, lds, s);

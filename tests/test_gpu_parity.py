@@ -182,3 +182,21 @@ def test_rejected_points(torch_dev):
     o = IFMM(p, Kernel("exp", 0.1), 0.0, 8, 3, "const", 1.01, r_cap=64)
     assert _rel(x, _dense(o, b)) < 1e-9
     s.close()
+
+
+def test_nonfinite_rhs_is_not_converged(torch_dev):
+    """A right-hand side with a NaN gives a NaN residual: refinement stops at
+    once with 'did not converge' instead of reporting success."""
+    _say("[gpu] refinement: NaN right-hand side")
+    torch, dev = torch_dev
+    pts = workloads.uniform(1024, 1009)
+    s = _gpu(torch_dev, pts, "exp", 0.1, "const", 1.01, 1e-8, 16, 4, refine_tol=1e-10)
+    b = workloads.rhs(1024, 1, 2005)[:, 0].copy()
+    b[100] = np.nan
+    s.solve(torch.from_numpy(b).to(dev), check=False)
+    info = s.last_info
+    assert info["status"] == 4 and info["iterations"] == 0 and not np.isfinite(info["residual"])
+    b[100] = 0.5  # the same handle still solves a finite system
+    s.solve(torch.from_numpy(b).to(dev))
+    assert s.last_info["status"] == 0 and s.last_info["residual"] <= 1e-10
+    s.close()
