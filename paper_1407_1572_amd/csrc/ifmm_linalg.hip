@@ -625,48 +625,46 @@ __global__ __launch_bounds__(WG) void k_transition(const TransArgs a) {
 //           c_i += w^z;
 //   step 2: r = [snapshot_i - sum_u A_u v_u; y_i] into the work vector;
 //   step 3: x_i = (D_i^-1 r)^x.
-// Right-hand columns in groups of 4; the waves split the inner dimension
+// Right-hand columns in groups of SV_C (one at a time for a single right-hand
+// side: NC = 1 keeps the registers of one column); the waves split the inner dimension
 // and meet in LDS.  wk: per record mpad x nrhs doubles.
 constexpr int SV_C = 4;
 
 // sum_k A(row, k) X(k, c) for this lane's row, the waves splitting k;
 // returns the full sums to wave 0 (acc valid there only).
-template <class TA, class XFn>
+template <int NC, class TA, class XFn>
 __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, bool live, int K, XFn X, int nc,
                                 double* part, double* acc) {
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   constexpr int NW = WG / WAVE;
 #pragma unroll
-  for (int c = 0; c < SV_C; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if (live) {
-    // eight loads of A in flight per lane before their products
-    constexpr int U = 8;
-    int k = w;
-    for (; k + (U - 1) * NW < K; k += U * NW) {
-      double av[U];
+    // sixteen loads of A in flight per lane before their products (the last
+    // round predicated): one memory round trip per 16 NW columns
+    constexpr int U = 16;
+    for (int k = w; k < K; k += U * NW) {
+      TA av[U];
 #pragma unroll
-      for (int t = 0; t < U; ++t) av[t] = (double)A[row + (size_t)(k + t * NW) * lda];
+      for (int t = 0; t < U; ++t) av[t] = A[row + (size_t)min(k + t * NW, K - 1) * lda];
 #pragma unroll
-      for (int t = 0; t < U; ++t)
+      for (int t = 0; t < U; ++t) {
+        const int kk = min(k + t * NW, K - 1);
+        const double v = k + t * NW < K ? (double)av[t] : 0.0;
 #pragma unroll
-        for (int c = 0; c < SV_C; ++c)
-          if (c < nc) acc[c] = fma(av[t], X(k + t * NW, c), acc[c]);
-    }
-    for (; k < K; k += NW) {
-      const double av = (double)A[row + (size_t)k * lda];
-#pragma unroll
-      for (int c = 0; c < SV_C; ++c)
-        if (c < nc) acc[c] = fma(av, X(k, c), acc[c]);
+        for (int c = 0; c < NC; ++c)
+          if (c < nc) acc[c] = fma(v, X(kk, c), acc[c]);
+      }
     }
   }
 #pragma unroll
-  for (int c = 0; c < SV_C; ++c) part[(w * SV_C + c) * WAVE + lane] = acc[c];
+  for (int c = 0; c < NC; ++c) part[(w * NC + c) * WAVE + lane] = acc[c];
   __syncthreads();
   if (w == 0)
 #pragma unroll
-    for (int c = 0; c < SV_C; ++c) {
+    for (int c = 0; c < NC; ++c) {
       double v = part[c * WAVE + lane];
-      for (int q = 1; q < NW; ++q) v += part[(q * SV_C + c) * WAVE + lane];
+      for (int q = 1; q < NW; ++q) v += part[(q * NC + c) * WAVE + lane];
       acc[c] = v;
     }
 }
@@ -674,12 +672,12 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
 // The vector a product multiplies (K values per right-hand side column) is
 // staged in LDS first: every lane reads it there, not through the caches.
 // One instantiation per step (each with the registers of its own step).
-template <class T, int STEP>
+template <class T, int STEP, int NC>
 __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restrict__ wk, int tiles) {
   constexpr int step = STEP;
-  __shared__ double part[(WG / WAVE) * SV_C * WAVE];
+  __shared__ double part[(WG / WAVE) * NC * WAVE];
   extern __shared__ __align__(16) unsigned char smem[];
-  double* xs = reinterpret_cast<double*>(smem);  // [SV_C][mpad]
+  double* xs = reinterpret_cast<double*>(smem);  // [NC][mpad]
   auto stage = [&](const double* src, size_t ld, int K, int ncol) {
     __syncthreads();
     for (int e = threadIdx.x; e < K * ncol; e += WG) {
@@ -699,14 +697,14 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
   double* wb = wk + (size_t)b * a.mpad * a.nrhs;  // ld mpad
   const double* D = a.Dinv + (size_t)r.i * a.sD;
   double* snap = a.bv + ((size_t)a.nc + r.i) * sv;
-  double acc[SV_C];
-  for (int c0 = 0; c0 < a.nrhs; c0 += SV_C) {
-    const int nc = min(SV_C, a.nrhs - c0);
+  double acc[NC];
+  for (int c0 = 0; c0 < a.nrhs; c0 += NC) {
+    const int nc = min(NC, a.nrhs - c0);
     if (step == 0) {
       if (tile * WAVE >= m) return;
       const double* bi = a.bv + (size_t)r.i * sv + (size_t)c0 * a.npad;
       stage(bi, a.npad, ni, nc);
-      tile_dot<double>(D, a.mpad, row, row < m, ni, XL, nc, part, acc);
+      tile_dot<NC, double>(D, a.mpad, row, row < m, ni, XL, nc, part, acc);
       if (w == 0 && row < m)
         for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = acc[c];
       if (tile == 0 && w == 1)
@@ -728,7 +726,7 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
                          : static_cast<const T*>(a.L) + ((size_t)cl * 9 + (8 - unit)) * a.sL;
       const int ld = part1 ? a.npad : a.rpad;
       stage(wb + (size_t)c0 * a.mpad, a.mpad, ni, nc);
-      tile_dot<T>(A, ld, row, row < sz, ni, XL, nc, part, acc);
+      tile_dot<NC, T>(A, ld, row, row < sz, ni, XL, nc, part, acc);
       double* tg = part1 ? a.bv + (size_t)cl * sv + (size_t)c0 * a.npad : a.cv + (size_t)cl * svc + (size_t)c0 * a.rpad;
       if (w == 0 && row < sz)
         for (int c = 0; c < nc; ++c) tg[row + (size_t)c * ld] -= acc[c];
@@ -739,28 +737,63 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
         for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = yi[row - ni + (size_t)c * a.rpad];
       }
       if (tile * WAVE >= ni) continue;
-      double tot[SV_C] = {0.0, 0.0, 0.0, 0.0};
-      for (int u = 0; u < 9; ++u) {
+      // every neighbour's vector staged at once (unit order, column stride kst),
+      // then one pass over all neighbour blocks and one reduction
+      const int kst = 8 * max(a.npad, a.rpad);
+      __syncthreads();
+      for (int u = 0, off = 0; u < 9; ++u) {
         if (u == 4 || !r.kind[u]) continue;
         const int cl = r.cl[u], sz = r.size[u];
         const bool part1 = r.kind[u] == 1;
         const double* src = part1 ? a.bv + ((size_t)2 * a.nc + cl) * sv + (size_t)c0 * a.npad
                                   : a.cv + ((size_t)a.nc + cl) * svc + (size_t)c0 * a.rpad;
         const int lds = part1 ? a.npad : a.rpad;
-        const T* A = part1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
-                           : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
-        stage(src, lds, sz, nc);
-        tile_dot<T>(A, a.npad, row, row < ni, sz, XL, nc, part, acc);
-        if (w == 0)
-          for (int c = 0; c < SV_C; ++c) tot[c] += acc[c];
-        __syncthreads();
+        for (int e = threadIdx.x; e < sz * nc; e += WG) {
+          const int k = e % sz, c = e / sz;
+          xs[off + k + c * kst] = src[k + (size_t)c * lds];
+        }
+        off += sz;
       }
+      __syncthreads();
+      double tot[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) tot[c] = 0.0;
+      if (row < ni) {
+        for (int u = 0, off = 0; u < 9; ++u) {
+          if (u == 4 || !r.kind[u]) continue;
+          const int sz = r.size[u];
+          const T* A = r.kind[u] == 1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
+                                      : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
+          constexpr int U = 16, NW = WG / WAVE;
+          for (int k = w; k < sz; k += U * NW) {
+            T av[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) av[t] = A[row + (size_t)min(k + t * NW, sz - 1) * a.npad];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+              const int kk = min(k + t * NW, sz - 1);
+              const double v = k + t * NW < sz ? (double)av[t] : 0.0;
+#pragma unroll
+              for (int c = 0; c < NC; ++c)
+                if (c < nc) tot[c] = fma(v, xs[off + kk + c * kst], tot[c]);
+            }
+          }
+          off += sz;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) part[(w * NC + c) * WAVE + lane] = tot[c];
+      __syncthreads();
       if (w == 0 && row < ni)
-        for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = snap[row + (size_t)(c0 + c) * a.npad] - tot[c];
+        for (int c = 0; c < nc; ++c) {
+          double v = part[c * WAVE + lane];
+          for (int q = 1; q < WG / WAVE; ++q) v += part[(q * NC + c) * WAVE + lane];
+          wb[row + (size_t)(c0 + c) * a.mpad] = snap[row + (size_t)(c0 + c) * a.npad] - v;
+        }
     } else {
       if (tile * WAVE >= ni) return;
       stage(wb + (size_t)c0 * a.mpad, a.mpad, m, nc);
-      tile_dot<double>(D, a.mpad, row, row < ni, m, XL, nc, part, acc);
+      tile_dot<NC, double>(D, a.mpad, row, row < ni, m, XL, nc, part, acc);
       double* xi = a.bv + ((size_t)2 * a.nc + r.i) * sv + (size_t)c0 * a.npad;
       if (w == 0 && row < ni)
         for (int c = 0; c < nc; ++c) xi[row + (size_t)c * a.npad] = acc[c];
@@ -2099,10 +2132,18 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
   if (a.nb <= 0 || max_rows <= 0) return;
   const int tiles = cdiv(max_rows, WAVE);
   const dim3 grid(a.nb, (step == 1 ? 9 : 1) * tiles);
-  const size_t lds = sizeof(double) * SV_C * (size_t)a.mpad;
-#define SOLVE_GO(S)                                                                           \
-  if (ty) hipLaunchKernelGGL((k_solve<float, S>), grid, dim3(WG), lds, s, a, wk, tiles);   \
-  else hipLaunchKernelGGL((k_solve<double, S>), grid, dim3(WG), lds, s, a, wk, tiles);
+  // staged vectors: min(SV_C, nrhs) columns of mpad (step 2: of every
+  // neighbour block, 8 max(npad, rpad))
+  const size_t lds = sizeof(double) * std::min(SV_C, a.nrhs) *
+                     (step == 2 ? (size_t)8 * std::max(a.npad, a.rpad) : (size_t)a.mpad);
+#define SOLVE_GO(S)                                                                              \
+  if (a.nrhs == 1) {                                                                          \
+    if (ty) hipLaunchKernelGGL((k_solve<float, S, 1>), grid, dim3(WG), lds, s, a, wk, tiles);    \
+    else hipLaunchKernelGGL((k_solve<double, S, 1>), grid, dim3(WG), lds, s, a, wk, tiles);      \
+  } else {                                                                                    \
+    if (ty) hipLaunchKernelGGL((k_solve<float, S, SV_C>), grid, dim3(WG), lds, s, a, wk, tiles); \
+    else hipLaunchKernelGGL((k_solve<double, S, SV_C>), grid, dim3(WG), lds, s, a, wk, tiles);   \
+  }
   switch (step) {
     case 0: SOLVE_GO(0) break;
     case 1: SOLVE_GO(1) break;
