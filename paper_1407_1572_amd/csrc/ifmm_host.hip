@@ -476,7 +476,6 @@ struct Stage {
         work(v, f, by, mm);
         for (const auto& d : v) lds = std::max(lds, es * ((size_t)(d.n + 1) * d.m + d.m));
         const size_t o = push(v.data(), v.size() * sizeof(RrqrDesc));
-        op({OP_RRQR, o, g == 1 ? (size_t)lds : 0, (int)v.size(), mm, g, f, by}, ty);
         bool q = false;
         int nn = 0, km = 0;
         for (const auto& d : v) {
@@ -484,6 +483,9 @@ struct Stage {
           nn = std::max(nn, d.n);
           km = std::max(km, d.kmax);
         }
+        Op r{OP_RRQR, o, g == 1 ? (size_t)lds : 0, (int)v.size(), mm, g, f, by};
+        r.off2b = (size_t)nn;
+        op(r, ty);
         if (q) op({OP_FORMQRR, o, 0, (int)v.size(), nn, km, 0.0, 0.0}, ty);
       }
     });
@@ -979,8 +981,8 @@ struct Plan final : ifmm_plan {
           if (op.b == 2)
             launch_rrqr_reg(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2, (int)op.off2b,
                             op.ty, s);
-          else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
-          else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.ty, s);
+          else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, (int)op.off2b, op.ty, s);
+          else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2b, op.ty, s);
           break;
         case OP_FORMQRR:
           launch_formq_rr(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s);

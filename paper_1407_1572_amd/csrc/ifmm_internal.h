@@ -321,12 +321,12 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s);
 void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
-// must fit in `lds` <= kRrqrLdsBytes.
+// must fit in `lds` <= kRrqrLdsBytes.  max_n: the largest row count.
 constexpr size_t kRrqrLdsBytes = 159 * 1024;
-void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int max_n, int ty, hipStream_t s);
 // Same arithmetic on the matrix in place (one workgroup per matrix, the
 // matrix L2-resident, column norms in LDS): max_m columns at most.
-void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s);
+void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s);
 // Pivoted QR with each column in the registers of one thread, and Q when
 // d.Q is set: every matrix has m <= kRrqrRegCols and n <= nr, with nr one of
 // rrqr_reg_rows(ty); LDS holds the kmax x nr reflectors.

@@ -879,7 +879,7 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
 // access), so a workgroup has 16 columns in flight; dot products and norms
 // reduce with shuffles inside the group.  Norms are recomputed exactly every
 // step.
-template <class T, int NT, bool kLds>
+template <class T, int NT, bool kLds, int NV>
 __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RrqrDesc d = descs[blockIdx.x];
@@ -963,6 +963,52 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
     if (threadIdx.x == 0) { gtau[j] = tau; galpha[j] = alpha; A[j + j * lda] = alpha; }
     __syncthreads();
     const T* u = A + j * lda;
+    if constexpr (NV > 0) {
+      // n <= GRP NV: this lane's rows of u and of each column it updates
+      // stay in registers (one read and one write of the trailing matrix per
+      // step); the same partial sums, in the same order, as below
+      T ur[NV];
+#pragma unroll
+      for (int t = 0; t < NV; ++t) {
+        const int i = j + 1 + rl + GRP * t;
+        ur[t] = i < n ? u[i] : T(0);
+      }
+      for (int c = j + 1 + slot; c < m; c += NSLOT) {
+        T* col = A + c * lda;
+        T cv[NV];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+          const int i = j + 1 + rl + GRP * t;
+          cv[t] = i < n ? col[i] : T(0);
+        }
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int t = 0; t < NV; t += 2) {
+          s0 = fma(ur[t], cv[t], s0);
+          s1 = fma(ur[t + 1], cv[t + 1], s1);
+        }
+        const T s = grp_sum(s0 + s1) + col[j];
+        const T ts = tau * s;
+        T q0 = 0, q1 = 0;
+#pragma unroll
+        for (int t = 0; t < NV; t += 2) {
+          const int i0 = j + 1 + rl + GRP * t, i1 = i0 + GRP;
+          const T v0 = fma(-ts, ur[t], cv[t]);
+          const T v1 = fma(-ts, ur[t + 1], cv[t + 1]);
+          if (i0 < n) col[i0] = v0;
+          if (i1 < n) col[i1] = v1;
+          q0 = fma(v0, v0, q0);
+          q1 = fma(v1, v1, q1);
+        }
+        const T q = grp_sum(q0 + q1);
+        if (rl == 0) {
+          col[j] -= ts;
+          nrm[c] = sqrt(q);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (int c = j + 1 + slot; c < m; c += NSLOT) {
       T* col = A + c * lda;
       // two independent partial sums per lane (short, latency-bound loops)
@@ -2185,17 +2231,27 @@ void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s) {
 // The LDS pivoted QR runs 1024 threads per matrix: a staged matrix takes
 // most of a CU's LDS, so the CU's parallelism has to come from one workgroup.
 constexpr int RRQR_NT = 1024;
-void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int ty, hipStream_t s) {
+// Rows per lane of the register-held update (even, 16 NV >= max_n), 0 for
+// the loop form.
+template <class T, bool kLds>
+void rrqr_go(const RrqrDesc* d, int nd, size_t lds, int max_n, hipStream_t s) {
+  auto go = [&](auto kern) {
+    static bool raised = false;
+    if (kLds || lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(kern), raised, kRrqrLdsBytes);
+    hipLaunchKernelGGL(kern, dim3(nd), dim3(RRQR_NT), lds, s, d);
+  };
+  constexpr bool f32 = sizeof(T) == 4;  // registers: up to 24 FP32 or 18 FP64 rows per lane
+  if (max_n <= 128) go(k_rrqr<T, RRQR_NT, kLds, 8>);
+  else if (max_n <= 192) go(k_rrqr<T, RRQR_NT, kLds, 12>);
+  else if (max_n <= 288) go(k_rrqr<T, RRQR_NT, kLds, 18>);
+  else if (f32 && max_n <= 384) go(k_rrqr<T, RRQR_NT, kLds, f32 ? 24 : 0>);
+  else go(k_rrqr<T, RRQR_NT, kLds, 0>);
+}
+
+void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int max_n, int ty, hipStream_t s) {
   if (nd <= 0) return;
-  if (ty) {
-    static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT, true>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT, true>), dim3(nd), dim3(RRQR_NT), lds, s, d);
-  } else {
-    static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT, true>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT, true>), dim3(nd), dim3(RRQR_NT), lds, s, d);
-  }
+  if (ty) rrqr_go<float, true>(d, nd, lds, max_n, s);
+  else rrqr_go<double, true>(d, nd, lds, max_n, s);
 }
 
 int rrqr_reg_rows(int n, int ty) {
@@ -2279,18 +2335,11 @@ void launch_formq_rr(const RrqrDesc* d, int nd, int max_n, int max_kmax, int ty,
   }
 }
 
-void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int ty, hipStream_t s) {
+void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int max_n, int ty, hipStream_t s) {
   if (nd <= 0 || max_m <= 0) return;
   const size_t lds = (size_t)max_m * (ty ? sizeof(float) : sizeof(double));
-  if (ty) {
-    static bool raised = false;
-    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr<float, RRQR_NT, false>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<float, RRQR_NT, false>), dim3(nd), dim3(RRQR_NT), lds, s, d);
-  } else {
-    static bool raised = false;
-    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr<double, RRQR_NT, false>), raised, kRrqrLdsBytes);
-    hipLaunchKernelGGL((k_rrqr<double, RRQR_NT, false>), dim3(nd), dim3(RRQR_NT), lds, s, d);
-  }
+  if (ty) rrqr_go<float, false>(d, nd, lds, max_n, s);
+  else rrqr_go<double, false>(d, nd, lds, max_n, s);
 }
 
 
