@@ -57,25 +57,40 @@ __global__ void k_leaf_interp(const double* __restrict__ pts, const int* __restr
   }
 }
 
+// Near-field blocks of the factor; optionally also the FP64 near field of
+// the product: leaf i's row block (n_i x the sources of its 3 x 3 neighbours
+// in slot order, ld n_i) at near + near_off[i], zero on the self pairs.
 template <class T>
 __global__ void k_near(const double* __restrict__ pts, const int* __restrict__ start,
                        const int* __restrict__ cnt, const int* __restrict__ nbr9, KernelFn kf,
-                       const double* __restrict__ d, T* P, size_t slot_stride, int ld) {
+                       const double* __restrict__ d, T* P, size_t slot_stride, int ld,
+                       double* __restrict__ near, const size_t* __restrict__ near_off) {
   const int i = blockIdx.x, s = blockIdx.y;
   const int j = nbr9[i * 9 + s];
   if (j < 0) return;
   const int ni = cnt[i], nj = cnt[j];
   T* B = P + ((size_t)i * 9 + s) * slot_stride;
   const int si = start[i], sj = start[j];
+  double* Nb = nullptr;
+  if (near) {
+    int coff = 0;
+    for (int u = 0; u < s; ++u) {
+      const int ju = nbr9[i * 9 + u];
+      if (ju >= 0) coff += cnt[ju];
+    }
+    Nb = near + near_off[i] + (size_t)coff * ni;
+  }
   for (int e = threadIdx.x; e < ni * nj; e += blockDim.x) {
     const int a = e % ni, b = e / ni;
     double v;
     if (s == 4 && a == b) {
       v = d[si + a];
+      if (Nb) Nb[e] = 0.0;
     } else {
       const double dx = pts[2 * (si + a)] - pts[2 * (sj + b)];
       const double dy = pts[2 * (si + a) + 1] - pts[2 * (sj + b) + 1];
       v = kval(kf, sqrt(dx * dx + dy * dy));
+      if (Nb) Nb[e] = v;
     }
     B[a + (size_t)b * ld] = (T)v;
   }
@@ -242,6 +257,55 @@ __global__ void k_l2p_p2p(const double* __restrict__ pts, const int* __restrict_
   }
 }
 
+// The same product with the near field read from its stored FP64 blocks
+// (k_near): the terms in the same order, the self pairs skipped.
+__global__ void k_l2p_near(const double* __restrict__ pts, const int* __restrict__ start,
+                           const int* __restrict__ cnt, const int* __restrict__ nbr9, int kappa,
+                           double lox, double loy, double size, int p, const double* __restrict__ near,
+                           const size_t* __restrict__ near_off, const double* __restrict__ G,
+                           const double* __restrict__ x, int ldx, const double* __restrict__ d, double* y,
+                           int ldy, int nrhs) {
+  const int i = blockIdx.x;
+  const int p2 = p * p;
+  const int n = cnt[i];
+  double cx, cy, h;
+  leaf_box(i, kappa, lox, loy, size, cx, cy, h);
+  const double* B = near + near_off[i];
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    const int g = start[i] + a;
+    const double xa = pts[2 * g], ya = pts[2 * g + 1];
+    double lx[kMaxP], ly[kMaxP];
+    lagrange_all(p, (xa - cx) / h, lx);
+    lagrange_all(p, (ya - cy) / h, ly);
+    for (int r = 0; r < nrhs; ++r) {
+      const double* gl = G + ((size_t)i * nrhs + r) * p2;
+      const double* xr = x + (size_t)r * ldx;
+      double acc = 0.0;
+      for (int m = 0; m < p2; ++m) acc = fma(lx[m / p] * ly[m % p], gl[m], acc);
+      const double* Ba = B + a;
+      for (int s = 0; s < 9; ++s) {
+        const int j = nbr9[i * 9 + s];
+        if (j < 0) continue;
+        const int nj = cnt[j], sj = start[j];
+        int b = 0;
+        for (; b + 4 <= nj; b += 4) {  // four loads in flight
+          const double v0 = Ba[(size_t)b * n], v1 = Ba[(size_t)(b + 1) * n];
+          const double v2 = Ba[(size_t)(b + 2) * n], v3 = Ba[(size_t)(b + 3) * n];
+          if (sj + b != g) acc = fma(v0, xr[sj + b], acc);
+          if (sj + b + 1 != g) acc = fma(v1, xr[sj + b + 1], acc);
+          if (sj + b + 2 != g) acc = fma(v2, xr[sj + b + 2], acc);
+          if (sj + b + 3 != g) acc = fma(v3, xr[sj + b + 3], acc);
+        }
+        for (; b < nj; ++b)
+          if (sj + b != g) acc = fma(Ba[(size_t)b * n], xr[sj + b], acc);
+        Ba += (size_t)nj * n;
+      }
+      if (d) acc = fma(d[g], xr[g], acc);
+      y[g + (size_t)r * ldy] = acc;
+    }
+  }
+}
+
 __global__ void k_gather_rows(const double* __restrict__ src, int ld_src, const int* __restrict__ idx,
                               int n, int nrhs, double* dst, int ld_dst) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,14 +354,15 @@ void launch_leaf_interp(const double* pts, const int* leaf_start, const int* lea
 
 void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
                        const int* nbr9, int nleaf, KernelFn kf, const double* d, void* P, int f32,
-                       size_t slot_stride, int ld, int max_n, hipStream_t s) {
+                       size_t slot_stride, int ld, int max_n, double* near, const size_t* near_off,
+                       hipStream_t s) {
   (void)max_n;
   if (f32)
     hipLaunchKernelGGL(k_near<float>, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
-                       d, static_cast<float*>(P), slot_stride, ld);
+                       d, static_cast<float*>(P), slot_stride, ld, near, near_off);
   else
     hipLaunchKernelGGL(k_near<double>, dim3(nleaf, 9), dim3(256), 0, s, pts, leaf_start, leaf_n, nbr9, kf,
-                       d, static_cast<double*>(P), slot_stride, ld);
+                       d, static_cast<double*>(P), slot_stride, ld, near, near_off);
 }
 
 void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s) {
@@ -332,6 +397,14 @@ void launch_l2p_p2p(const double* pts, const int* leaf_start, const int* leaf_n,
                     int ldy, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_l2p_p2p, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, nbr9, kappa,
                      lox, loy, size, p, kf, G, x, ldx, d, y, ldy, nrhs);
+}
+
+void launch_l2p_near(const double* pts, const int* leaf_start, const int* leaf_n, const int* nbr9,
+                     int nleaf, int kappa, double lox, double loy, double size, int p, const double* near,
+                     const size_t* near_off, const double* G, const double* x, int ldx, const double* d,
+                     double* y, int ldy, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_l2p_near, dim3(nleaf), dim3(64), 0, s, pts, leaf_start, leaf_n, nbr9, kappa, lox, loy,
+                     size, p, near, near_off, G, x, ldx, d, y, ldy, nrhs);
 }
 
 void launch_gather_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,

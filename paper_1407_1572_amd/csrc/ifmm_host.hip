@@ -235,6 +235,10 @@ void dfree(hipStream_t s, T*& p) {
 
 inline int rup(int a, int b) { return (a + b - 1) / b * b; }
 constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
+// Largest stored near field of the FMM product (bytes); beyond it the
+// product evaluates the near-field kernel on the fly.
+constexpr size_t kNearStoreMax = (size_t)16 << 30;
+
 // Relative threshold floor of the fill compression in an FP32 factor: pivot
 // norms below a few FP32 rounding units of the first are rounding noise
 // there, so a smaller eps would only keep noise directions up to the cap.
@@ -866,6 +870,9 @@ struct Plan final : ifmm_plan {
   double* d_pts = nullptr;
   int *d_perm = nullptr, *d_leaf_start = nullptr, *d_leaf_n = nullptr, *d_nbr9_leaf = nullptr;
   double* d_diag = nullptr;
+  double* d_near = nullptr;      // FP64 near field of the product (null: evaluated on the fly)
+  size_t* d_near_off = nullptr;  // per leaf: offset of its block in d_near
+  std::vector<size_t> near_off_h;
   double* d_E = nullptr;
   std::vector<double*> d_table;
   std::vector<Level<T>> lv;
@@ -1173,8 +1180,12 @@ struct Plan final : ifmm_plan {
     for (int k = kappa - 1; k >= 2; --k) launch_m2m(d_E, p, 1 << (2 * k), W[k + 1], W[k], nrhs, s);
     for (int k = 2; k <= kappa; ++k) launch_m2l(p, k, d_table[k], W[k], G[k], nrhs, s);
     for (int k = 2; k < kappa; ++k) launch_l2l(d_E, p, 1 << (2 * k), G[k], G[k + 1], nrhs, s);
-    launch_l2p_p2p(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, kf,
-                   G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
+    if (d_near)
+      launch_l2p_near(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, d_near,
+                      d_near_off, G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
+    else
+      launch_l2p_p2p(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, kf,
+                     G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
     HIP_OK(hipGetLastError());
   }
 
@@ -1221,8 +1232,30 @@ struct Plan final : ifmm_plan {
     Lf.Dinv = dalloc<double>(s, Lf.sD * Lf.nc);
     HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, s));
     HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, s));
+    // The product's near field is stored once (FP64, every leaf's row block
+    // over its neighbours' points) when it fits kNearStoreMax; the refinement
+    // sweeps then read it instead of evaluating the kernel again.
+    {
+      std::vector<size_t>& off = near_off_h;
+      off.assign(nleaf, 0);
+      size_t tot = 0;
+      for (int i = 0; i < nleaf; ++i) {
+        size_t c = 0;
+        for (int q = 0; q < 9; ++q) {
+          const int j = Lf.nbr9[(size_t)i * 9 + q];
+          if (j >= 0) c += (size_t)leaf_n[j];
+        }
+        off[i] = tot;
+        tot += c * (size_t)leaf_n[i];
+      }
+      if (tot * sizeof(double) <= kNearStoreMax) {
+        d_near = dalloc<double>(s, std::max<size_t>(tot, 1));
+        d_near_off = dalloc<size_t>(s, nleaf);
+        HIP_OK(hipMemcpyAsync(d_near_off, off.data(), sizeof(size_t) * nleaf, hipMemcpyHostToDevice, s));
+      }
+    }
     launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
-                      Lf.sP, Lf.npad, nmax, s);
+                      Lf.sP, Lf.npad, nmax, d_near, d_near_off, s);
     // Interpolation and orthonormalisation in FP64; an FP32 factor takes the
     // rounded bases.
     double* U64;
@@ -2163,6 +2196,8 @@ struct Plan final : ifmm_plan {
   void release() override {
     for (auto& L : lv) L.free_all(s);
     for (auto& t : d_table) dfree(s, t);
+    dfree(s, d_near);
+    dfree(s, d_near_off);
     dfree(s, d_pts);
     dfree(s, d_perm);
     dfree(s, d_leaf_start);

@@ -364,10 +364,14 @@ void launch_leaf_interp(const double* pts, const int* leaf_start, const int* lea
                         int nleaf, int kappa, double lox, double loy, double size, int p,
                         double* dst, size_t stride, int ld, int max_n, hipStream_t s);
 // Near-field blocks of the leaves: dst[i][slot] = K(x_i, x_j), diagonal of the
-// self block replaced by d; P is FP64 (f32 = 0) or FP32 (f32 = 1).
+// self block replaced by d; P is FP64 (f32 = 0) or FP32 (f32 = 1).  When near
+// is given, the same values also go to the FP64 near field of the product:
+// leaf i's n_i x c_i block (c_i = the points of its 3 x 3 neighbours in slot
+// order, ld n_i, self pairs 0) at near + near_off[i].
 void launch_near_field(const double* pts, const int* leaf_start, const int* leaf_n,
                        const int* nbr9, int nleaf, KernelFn kf, const double* d,
-                       void* P, int f32, size_t slot_stride, int ld, int max_n, hipStream_t s);
+                       void* P, int f32, size_t slot_stride, int ld, int max_n, double* near,
+                       const size_t* near_off, hipStream_t s);
 // Kernel between the Chebyshev nodes of two boxes of half-width h whose
 // centres differ by (dx, dy) * 2h, for the 49 offsets dx, dy in [-3, 3].
 void launch_m2l_table(KernelFn kf, int p, double h, double* dst, hipStream_t s);
@@ -392,6 +396,11 @@ void launch_l2p_p2p(const double* pts, const int* leaf_start, const int* leaf_n,
                     int nleaf, int kappa, double lox, double loy, double size, int p,
                     KernelFn kf, const double* G, const double* x, int ldx, const double* d,
                     double* y, int ldy, int nrhs, hipStream_t s);
+// L2P + near field from the stored blocks (launch_near_field), + d x when d.
+void launch_l2p_near(const double* pts, const int* leaf_start, const int* leaf_n, const int* nbr9,
+                     int nleaf, int kappa, double lox, double loy, double size, int p, const double* near,
+                     const size_t* near_off, const double* G, const double* x, int ldx, const double* d,
+                     double* y, int ldy, int nrhs, hipStream_t s);
 // out[r] += sum_i x[i + r*ld]^2 (out must be zeroed first).
 void launch_colnorm2(const double* x, int n, int nrhs, int ld, double* out, hipStream_t s);
 void launch_gather_rows(const double* src, int ld_src, const int* idx, int n, int nrhs,
