@@ -417,17 +417,27 @@ struct Stage {
       op({OP_ADD, push(v.data(), v.size() * sizeof(AddDesc)), 0, (int)v.size(), mm, nn, 0.0, by}, ty);
     });
   }
+  // Unpivoted QRs, staged in LDS (off2 = bytes) when the matrix fits
+  // kQrLdsBytes, else in place.
   void qr(const std::vector<QrDesc>& all) {
-    by_type(all, [&](const std::vector<QrDesc>& v, int ty) {
-      double f = 0, by = 0;
-      for (const auto& d : v) {
-        const double K = std::min(d.n, d.m);
-        f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
-             + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
-        by += esz(ty) * (2.0 * d.n * d.m + K * d.m);
+    by_type(all, [&](const std::vector<QrDesc>& byt, int ty) {
+      std::vector<QrDesc> grp[2];
+      for (const auto& d : byt) grp[qr_lds_bytes(d.n, d.m, ty) <= kQrLdsBytes ? 1 : 0].push_back(d);
+      for (int g = 0; g < 2; ++g) {
+        const auto& v = grp[g];
+        if (v.empty()) continue;
+        double f = 0, by = 0;
+        size_t lds = 0;
+        for (const auto& d : v) {
+          const double K = std::min(d.n, d.m);
+          f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
+               + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
+          by += esz(ty) * (2.0 * d.n * d.m + K * d.m);
+          lds = std::max(lds, qr_lds_bytes(d.n, d.m, ty));
+        }
+        flops += f;
+        op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), g ? lds : 0, (int)v.size(), 0, 0, f, by}, ty);
       }
-      flops += f;
-      op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), 0, 0, f, by}, ty);
     });
   }
   // Pivoted QRs: matrices whose columns fit the registers of one thread each
@@ -983,7 +993,7 @@ struct Plan final : ifmm_plan {
           launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, op.ty, (int)op.off2, s);
           break;
         case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
-        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.ty, s); break;
+        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.off2, op.ty, s); break;
         case OP_RRQR:
           if (op.b == 2)
             launch_rrqr_reg(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2, (int)op.off2b,

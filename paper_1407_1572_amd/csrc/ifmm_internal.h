@@ -319,7 +319,11 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
 //     M_pq += F_pq U_q.
 // max_m / max_n bound the row / column sizes for the tiling.
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s);
-void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s);
+// Unpivoted Householder QR (Q in place, R out), one workgroup per matrix;
+// lds > 0: every matrix staged in LDS ((n + 1) m elements, lds bytes at most).
+constexpr size_t kQrLdsBytes = 64 * 1024;
+inline size_t qr_lds_bytes(int n, int m, int ty) { return (ty ? 4 : 8) * (size_t)(n + 1) * m; }
+void launch_qr(const QrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
 // must fit in `lds` <= kRrqrLdsBytes.  max_n: the largest row count.
 constexpr size_t kRrqrLdsBytes = 159 * 1024;

@@ -803,14 +803,24 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
 }
 
 // --------------------------------------------------------------------- QR
-template <class T>
+template <class T, bool kLds>
 __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const QrDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m, K = min(n, m);
   if (d.A == nullptr || K == 0 || K > kMaxRank) return;
-  T* A = static_cast<T*>(d.A);
+  T* gA = static_cast<T*>(d.A);
   T* R = static_cast<T*>(d.R);
-  const size_t lda = d.lda;
+  // staged in LDS (stride n + 1) or worked on in place
+  const size_t lda = kLds ? (size_t)n + 1 : (size_t)d.lda;
+  T* A = kLds ? reinterpret_cast<T*>(smem) : gA;
+  if (kLds) {
+    for (int e = threadIdx.x; e < n * m; e += WG) {
+      const int i = e % n, c = e / n;
+      A[i + c * lda] = gA[i + (size_t)c * d.lda];
+    }
+    __syncthreads();
+  }
   __shared__ T red[WG / WAVE];
   __shared__ T tau_s[kMaxRank], alpha_s[kMaxRank];
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE, nw = WG / WAVE;
@@ -869,6 +879,13 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
     if (alpha_s[j] < 0) {
       for (int i = threadIdx.x; i < n; i += WG) A[i + j * lda] = -A[i + j * lda];
       for (int c = j + threadIdx.x; c < m; c += WG) R[j + (size_t)c * d.ldr] = -R[j + (size_t)c * d.ldr];
+    }
+  }
+  if (kLds) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * K; e += WG) {
+      const int i = e % n, c = e / n;
+      gA[i + (size_t)c * d.lda] = A[i + c * lda];
     }
   }
 }
@@ -2222,10 +2239,16 @@ void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   }
 }
 
-void launch_qr(const QrDesc* d, int nd, int ty, hipStream_t s) {
+void launch_qr(const QrDesc* d, int nd, size_t lds, int ty, hipStream_t s) {
   if (nd <= 0) return;
-  if (ty) hipLaunchKernelGGL(k_qr<float>, dim3(nd), dim3(WG), 0, s, d);
-  else hipLaunchKernelGGL(k_qr<double>, dim3(nd), dim3(WG), 0, s, d);
+  if (lds > kQrLdsBytes) return;
+  if (lds) {
+    if (ty) hipLaunchKernelGGL((k_qr<float, true>), dim3(nd), dim3(WG), lds, s, d);
+    else hipLaunchKernelGGL((k_qr<double, true>), dim3(nd), dim3(WG), lds, s, d);
+  } else {
+    if (ty) hipLaunchKernelGGL((k_qr<float, false>), dim3(nd), dim3(WG), 0, s, d);
+    else hipLaunchKernelGGL((k_qr<double, false>), dim3(nd), dim3(WG), 0, s, d);
+  }
 }
 
 // The LDS pivoted QR runs 1024 threads per matrix: a staged matrix takes
