@@ -640,9 +640,10 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if (live) {
-    // sixteen loads of A in flight per lane before their products (the last
-    // round predicated): one memory round trip per 16 NW columns
-    constexpr int U = 16;
+    // eight loads of A in flight per lane before their products, the last
+    // round's indices clamped and its values zeroed (no remainder loop):
+    // one memory round trip per 8 NW columns
+    constexpr int U = 8;
     for (int k = w; k < K; k += U * NW) {
       TA av[U];
 #pragma unroll
@@ -764,7 +765,7 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
           const int sz = r.size[u];
           const T* A = r.kind[u] == 1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
                                       : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
-          constexpr int U = 16, NW = WG / WAVE;
+          constexpr int U = 8, NW = WG / WAVE;
           for (int k = w; k < sz; k += U * NW) {
             T av[U];
 #pragma unroll
