@@ -1475,6 +1475,7 @@ struct Plan final : ifmm_plan {
       }
     d_erec = dalloc<ElimRec>(s, all.size());
     HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * all.size(), hipMemcpyHostToDevice, s));
+    solve_plan(1);  // planned while the last launches run
     run_deferred();
     HIP_OK(hipStreamSynchronize(s));
     resolve_profile();
@@ -1876,18 +1877,21 @@ struct Plan final : ifmm_plan {
   };
   // Plans of Algorithm 2 already uploaded, keyed by their vectors (the
   // refinement alternates two): a repeated solve launches them as they are.
+  // The launches of one solve sweep for nrhs columns (every level, colour
+  // and step, the level transitions and the top solve) on the workspace at
+  // base; the right-hand side and the solution enter and leave through the
+  // leaf blocks, so one plan serves every vector pair.
   struct SolvePlan {
-    const double* bt;
-    double* xt;
     double* base;
     int nrhs;
+    size_t tot, bleaf, xleaf;  // zeroed length; leaf b and x blocks (offsets)
     Stage st;
     char* d = nullptr;
   };
   std::vector<SolvePlan> splans;
 
   // x (tree order, ld N) = A^-1 b (tree order, ld N)
-  void solve_tree(const double* bt, double* xt, int nrhs) {
+  SolvePlan& solve_plan(int nrhs) {
     std::vector<size_t> ob(kappa + 1), oc(kappa + 1);
     size_t tot = 0;
     for (int k = 2; k <= kappa; ++k) {
@@ -1907,12 +1911,8 @@ struct Plan final : ifmm_plan {
     auto xvec = [&](int k, int i) { return base + ob[k] + ((size_t)2 * lv[k].nc + i) * lv[k].npad * nrhs; };
     auto cvec = [&](int k, int i) { return base + oc[k] + (size_t)i * rpad * nrhs; };
     auto yvec = [&](int k, int i) { return base + oc[k] + ((size_t)lv[k].nc + i) * rpad * nrhs; };
-    HIP_OK(hipMemsetAsync(base, 0, sizeof(double) * tot, s));
     for (SolvePlan& sp : splans)
-      if (sp.bt == bt && sp.xt == xt && sp.base == base && sp.nrhs == nrhs) {
-        launch_ops(sp.st, sp.d);
-        return;
-      }
+      if (sp.base == base && sp.nrhs == nrhs) return sp;
     auto args = [&](int k, int c) {
       const Level<T>& L = lv[k];
       SolveArgs a{};
@@ -1958,13 +1958,6 @@ struct Plan final : ifmm_plan {
       }
     };
     Stage st;
-    {
-      std::vector<AddDesc> a;
-      const Level<T>& Lf = lv[kappa];
-      for (int i = 0; i < Lf.nc; ++i)
-        if (Lf.n[i]) a.push_back({bt + leaf_start[i], bvec(kappa, i), Lf.n[i], nrhs, (int)N, Lf.npad, 0, 1.0, 0.0});
-      st.add(a);
-    }
     for (int k = kappa; k >= 2; --k) {
       const Level<T>& L = lv[k];
       for (int c = 0; c < 9; ++c) {
@@ -2020,21 +2013,29 @@ struct Plan final : ifmm_plan {
         st.add(a);
       }
     }
-    std::vector<AddDesc> a;
-    const Level<T>& Lf = lv[kappa];
-    for (int i = 0; i < Lf.nc; ++i)
-      if (Lf.n[i]) a.push_back({xvec(kappa, i), xt + leaf_start[i], Lf.n[i], nrhs, Lf.npad, (int)N, 0, 1.0, 0.0});
-    st.add(a);
     st.flops = 0.0;  // solve work is not factorisation work
     if (splans.size() >= 4) {
       dfree(s, splans.front().d);
       splans.erase(splans.begin());
     }
-    splans.push_back(SolvePlan{bt, xt, base, nrhs, std::move(st), nullptr});
+    splans.push_back(SolvePlan{base, nrhs, tot, (size_t)(bvec(kappa, 0) - base), (size_t)(xvec(kappa, 0) - base),
+                               std::move(st), nullptr});
     SolvePlan& sp = splans.back();
     sp.d = dalloc<char>(s, sp.st.blob.size());
     HIP_OK(hipMemcpyAsync(sp.d, sp.st.blob.data(), sp.st.blob.size(), hipMemcpyHostToDevice, s));
+    return sp;
+  }
+
+  // One sweep: x = A_f^-1 b (tree order, ld N).
+  void solve_tree(const double* bt, double* xt, int nrhs) {
+    SolvePlan& sp = solve_plan(nrhs);
+    const Level<T>& Lf = lv[kappa];
+    const size_t bs = (size_t)Lf.npad * nrhs;
+    HIP_OK(hipMemsetAsync(sp.base, 0, sizeof(double) * sp.tot, s));
+    launch_leaf_gather(bt, (int)N, sp.base + sp.bleaf, bs, Lf.npad, d_leaf_start, d_leaf_n, Lf.nc, nrhs, s);
     launch_ops(sp.st, sp.d);
+    launch_leaf_scatter(sp.base + sp.xleaf, bs, Lf.npad, xt, (int)N, d_leaf_start, d_leaf_n, Lf.nc, nrhs, s);
+    HIP_OK(hipGetLastError());
   }
 
   // ---------------------------------------------------------- entry points

@@ -426,6 +426,12 @@ hipError_t launch_tree_build(const double* pts, int n, double lox, double loy, d
 // *bad = 1 when two points of one leaf coincide.
 void launch_tree_distinct(const double* spts, const int* leaf_start, const int* leaf_n, int nleaf,
                           int* bad, hipStream_t s);
+// Rows of each leaf of a tree-order vector (ld ldv, nrhs columns) into the
+// leaf's block (blk + i bstride, ld ldb), and back.
+void launch_leaf_gather(const double* v, int ldv, double* blk, size_t bstride, int ldb, const int* leaf_start,
+                        const int* leaf_n, int nleaf, int nrhs, hipStream_t s);
+void launch_leaf_scatter(const double* blk, size_t bstride, int ldb, double* v, int ldv, const int* leaf_start,
+                         const int* leaf_n, int nleaf, int nrhs, hipStream_t s);
 void launch_fill(double* x, size_t n, double v, hipStream_t s);
 void launch_add_const(double* x, size_t n, double v, hipStream_t s);
 

@@ -68,6 +68,22 @@ __global__ void __launch_bounds__(256) k_tree_distinct(const double2* __restrict
   if (hit) *bad = 1;
 }
 
+// Leaf rows of a tree-order vector (ld ldv, nrhs columns) to / from the
+// per-leaf blocks of the solve (leaf i at blk + i bstride, ld ldb).
+template <bool kToBlocks>
+__global__ void __launch_bounds__(256) k_leaf_copy(double* __restrict__ v, int ldv, double* __restrict__ blk,
+                                                   size_t bstride, int ldb, const int* __restrict__ start,
+                                                   const int* __restrict__ cnt, int nrhs) {
+  const int i = blockIdx.x, n = cnt[i];
+  double* b = blk + (size_t)i * bstride;
+  double* x = v + start[i];
+  for (int e = threadIdx.x; e < n * nrhs; e += 256) {
+    const int a = e % n, r = e / n;
+    if (kToBlocks) b[a + (size_t)r * ldb] = x[a + (size_t)r * ldv];
+    else x[a + (size_t)r * ldv] = b[a + (size_t)r * ldb];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ x, size_t n, double v) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) x[i] = v;
@@ -111,6 +127,20 @@ void launch_tree_distinct(const double* spts, const int* leaf_start, const int* 
                           int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k_tree_distinct, dim3(nleaf), dim3(256), 0, s,
                      reinterpret_cast<const double2*>(spts), leaf_start, leaf_n, bad);
+}
+
+void launch_leaf_gather(const double* v, int ldv, double* blk, size_t bstride, int ldb, const int* leaf_start,
+                        const int* leaf_n, int nleaf, int nrhs, hipStream_t s) {
+  if (nleaf <= 0) return;
+  hipLaunchKernelGGL(k_leaf_copy<true>, dim3(nleaf), dim3(256), 0, s, const_cast<double*>(v), ldv, blk, bstride,
+                     ldb, leaf_start, leaf_n, nrhs);
+}
+
+void launch_leaf_scatter(const double* blk, size_t bstride, int ldb, double* v, int ldv, const int* leaf_start,
+                         const int* leaf_n, int nleaf, int nrhs, hipStream_t s) {
+  if (nleaf <= 0) return;
+  hipLaunchKernelGGL(k_leaf_copy<false>, dim3(nleaf), dim3(256), 0, s, v, ldv, const_cast<double*>(blk), bstride,
+                     ldb, leaf_start, leaf_n, nrhs);
 }
 
 void launch_fill(double* x, size_t n, double v, hipStream_t s) {
