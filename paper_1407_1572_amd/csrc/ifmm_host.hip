@@ -207,7 +207,7 @@ class PinnedPool {
   void put(char* p, size_t bytes) {
     if (!p) return;
     std::lock_guard<std::mutex> g(mu_);
-    if (free_.size() >= 4) {
+    if (free_.size() >= 32) {
       (void)hipHostFree(p);
       return;
     }
@@ -246,7 +246,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR, OP_FILLCP };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 Schur updates (elimination
 // step 2), 9 touched-cluster transform, 10 window stacked R, 11 solve sweeps,
@@ -265,6 +265,7 @@ inline int family(int t) {
     case OP_SOLVE: return 11;
     case OP_M2LASM: return 0;
     case OP_FORMQRR: return 5;
+    case OP_FILLCP: return 1;
     default: return t;
   }
 }
@@ -530,6 +531,15 @@ struct Stage {
     flops += f;
     op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
   }
+  // Fill copies into the pivoted-QR inputs (records and touches travel in
+  // the blob; their pointer fields hold blob offsets + 1, rebased at launch).
+  template <class T>
+  void fill_copy(FillCopy a, const std::vector<ElimRec>& rec, const std::vector<int>& touch, double bytes) {
+    if (a.nt <= 0) return;
+    a.rec = reinterpret_cast<const ElimRec*>(push(rec.data(), std::max<size_t>(1, rec.size()) * sizeof(ElimRec)) + 1);
+    a.touch = arr(&touch);
+    op({OP_FILLCP, push(&a, sizeof(a)), 0, a.nt, 0, 0, 0.0, bytes}, tcode<T>());
+  }
   // Far-field weight stacks with device-side block lists (arrays as in
   // touch_xform).
   template <class T>
@@ -665,18 +675,23 @@ struct Stage {
   }
 };
 
-// Pinned host + device buffers for descriptor upload, double-buffered.
+// Pinned host + device buffers for descriptor upload, a ring of kSlots: an
+// upload waits only for the copy out of the slot it reuses (kSlots uploads
+// back), so the host can plan that many stages ahead of the device.  The
+// device copy of a slot is rewritten only by a later copy on the same
+// stream, after the kernels that read it.
 struct Arena {
-  char* h[2] = {nullptr, nullptr};
-  char* d[2] = {nullptr, nullptr};
-  size_t cap[2] = {0, 0};
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  static constexpr int kSlots = 16;
+  char* h[kSlots] = {};
+  char* d[kSlots] = {};
+  size_t cap[kSlots] = {};
+  hipEvent_t ev[kSlots] = {};
   int cur = 0;
   void init() {
-    for (int i = 0; i < 2; ++i) HIP_OK(hipEventCreate(&ev[i]));
+    for (int i = 0; i < kSlots; ++i) HIP_OK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
   }
   void release(hipStream_t s) {
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kSlots; ++i) {
       if (ev[i]) (void)hipEventSynchronize(ev[i]);
       pinned().put(h[i], cap[i]);
       dfree(s, d[i]);
@@ -687,7 +702,7 @@ struct Arena {
     }
   }
   char* upload(const std::vector<char>& blob, hipStream_t s) {
-    cur ^= 1;
+    cur = (cur + 1) % kSlots;
     const size_t need = blob.size();
     // the previous copy out of this buffer must be done before it is reused
     HIP_OK(hipEventSynchronize(ev[cur]));
@@ -695,7 +710,7 @@ struct Arena {
       pinned().put(h[cur], cap[cur]);
       dfree(s, d[cur]);
       size_t c = std::max(need, 2 * cap[cur]);
-      c = std::max<size_t>(c, (size_t)8 << 20);
+      c = std::max<size_t>(c, (size_t)1 << 20);
       h[cur] = nullptr;
       d[cur] = nullptr;
       cap[cur] = 0;
@@ -1009,6 +1024,14 @@ struct Plan final : ifmm_plan {
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
                          op.count, op.a, op.ty, s);
           break;
+        case OP_FILLCP: {
+          FillCopy a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          a.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(a.rec) - 1));
+          a.touch = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.touch) - 1));
+          launch_fill_copy(a, op.ty, s);
+          break;
+        }
         case OP_TXFORM: {
           TouchXform a;
           std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
@@ -1664,7 +1687,8 @@ struct Plan final : ifmm_plan {
       Stage own;
       Stage& st = t0 == 0 ? pre : own;
       std::vector<GemmDesc> g;
-      std::vector<AddDesc> a;
+      std::vector<int> fc;  // fill copies on the device: (b, sq, nq, col0) per touch
+      double fcb = 0;
       std::vector<RrqrDesc> rq;
       for (int t = t0; t < t1; ++t) {
         const Touch& tc = touch[t];
@@ -1674,16 +1698,27 @@ struct Plan final : ifmm_plan {
         int col = rq0;
         for (int s2 = 0; s2 < 9; ++s2) {
           if (kPairs.idx[tc.sq][s2] < 0 || !E[tc.b].u[s2].kind) continue;
-          const int w = E[tc.b].u[s2].size;
-          a.push_back({Fp(tc.b, tc.sq, s2), Aw + (size_t)col * L.npad, nq, w, fpad, L.npad, 0, 1.0, 0.0});
-          col += w;
+          col += E[tc.b].u[s2].size;
         }
+        fc.insert(fc.end(), {tc.b, tc.sq, nq, rq0});
+        fcb += 2.0 * sizeof(T) * nq * (double)(col - rq0);
         T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
                       std::min(nq, r_cap), eps_c, 1, Uh + (size_t)t * L.sU, L.npad});
       }
       st.gemm(g);
-      st.add(a);
+      {
+        FillCopy f{};
+        f.F = F;
+        f.A = A;
+        f.per = per;
+        f.fpad = fpad;
+        f.npad = L.npad;
+        f.npair = kPairs.count;
+        f.nt = t1 - t0;
+        for (int x = 0; x < 81; ++x) f.pair[x] = (signed char)kPairs.idx[x / 9][x % 9];
+        st.fill_copy<T>(f, erec[k][c], fc, fcb);
+      }
       st.rrqr(rq);
       run(st);
       run_deferred();

@@ -350,6 +350,20 @@ void launch_gram_win(const WinStack& a, int max_r, int ty, hipStream_t s);
 // workgroup per matrix), every m <= kGjRegMax.
 constexpr int kGjRegMax = 192;
 void launch_gj_reg(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s);
+// Fill of the touched clusters into their pivoted-QR inputs: touch t = (b,
+// sq, nq, col0) takes, for every unit s2 of record b whose unit pair (sq, s2)
+// carries fill, the nq x size[s2] block F(b, pair) (ld fpad) into columns
+// col0 + (sizes of the earlier such units) of A + t per (ld npad).
+struct FillCopy {
+  const ElimRec* rec;
+  const int* touch;  // 4 ints per touch
+  const void* F;
+  void* A;
+  size_t per;
+  int fpad, npad, npair, nt;
+  signed char pair[81];
+};
+void launch_fill_copy(const FillCopy& a, int ty, hipStream_t s);
 // Blocked Gauss-Jordan pieces (panel of nb <= 64 columns starting at j0).
 void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* piv, int ldp,
                      Status* st, hipStream_t s);

@@ -545,6 +545,26 @@ __global__ __launch_bounds__(WG) void k_m2l_assemble(const M2LAssemble a) {
                   [&](int k, int y) { return Rl[y + (size_t)k * ld]; }, [&](int x, int y, double v) { M[x + y * ld] = (T)v; });
 }
 
+// One workgroup per (touch, unit of its elimination record).
+template <class T>
+__global__ __launch_bounds__(WG) void k_fill_copy(const FillCopy a) {
+  const int t = blockIdx.x, s2 = blockIdx.y;
+  const int b = a.touch[4 * t], sq = a.touch[4 * t + 1], nq = a.touch[4 * t + 2], col0 = a.touch[4 * t + 3];
+  const ElimRec& r = a.rec[b];
+  const int pidx = a.pair[9 * sq + s2];
+  if (pidx < 0 || !r.kind[s2]) return;
+  int col = col0;
+  for (int u = 0; u < s2; ++u)
+    if (a.pair[9 * sq + u] >= 0 && r.kind[u]) col += r.size[u];
+  const int w = r.size[s2];
+  const T* src = static_cast<const T*>(a.F) + ((size_t)b * a.npair + pidx) * a.fpad * a.fpad;
+  T* dst = static_cast<T*>(a.A) + (size_t)t * a.per + (size_t)col * a.npad;
+  for (int e = threadIdx.x; e < nq * w; e += WG) {
+    const int i = e % nq, j = e / nq;
+    dst[i + (size_t)j * a.npad] = src[i + (size_t)j * a.fpad];
+  }
+}
+
 // One workgroup per (touch, window slot); slot 36 is the parent transfer block.
 template <class T>
 __global__ __launch_bounds__(WG) void k_touch_xform(const TouchXform a) {
@@ -2223,6 +2243,12 @@ void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s) {
   const size_t lds = (size_t)a.rpad * a.p2 * sizeof(double);
   if (ty) hipLaunchKernelGGL(k_m2l_assemble<float>, grid, dim3(WG), lds, s, a);
   else hipLaunchKernelGGL(k_m2l_assemble<double>, grid, dim3(WG), lds, s, a);
+}
+
+void launch_fill_copy(const FillCopy& a, int ty, hipStream_t s) {
+  if (a.nt <= 0) return;
+  if (ty) hipLaunchKernelGGL(k_fill_copy<float>, dim3(a.nt, 9), dim3(WG), 0, s, a);
+  else hipLaunchKernelGGL(k_fill_copy<double>, dim3(a.nt, 9), dim3(WG), 0, s, a);
 }
 
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
