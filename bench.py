@@ -85,6 +85,33 @@ def dominant(fam, prec):
     return max(single, key=lambda k: fam[k]["ms"])
 
 
+# HBM traffic per launch of the roofline kernel, from two rocprofv3 counter
+# runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64` (pass 1
+# FETCH_SIZE, pass 2 WRITE_SIZE; KiB per dispatch, averaged over its 108
+# dispatches), each scaled by what the same counter reads for the known-size
+# copy of `bench.py --copy-cal` (1 GiB read: FETCH_SIZE 524,300 KiB, factor
+# 2.000; 1 GiB written: WRITE_SIZE 1,048,576 KiB, factor 1.000); summary in
+# profiles/ifmm_c3_1m_exp_mixed_pmc_traffic.md.  Valid only for the kernel
+# sources the counters were taken on (their SHA-256 below): traffic is null
+# after any change to them.
+PMC_TRAFFIC = {"kernel": "k_elim<float, 2>", "fetch_bytes": 1.4827e9, "write_bytes": 2.7076e8,
+               "sources": ("paper_1407_1572_amd/csrc/ifmm_linalg.hip", "paper_1407_1572_amd/csrc/ifmm_internal.h"),
+               "sha256": "2f201818a9e9625102cf45749df20e81e0e0ce88a815b68b5d21481598042977"}
+
+
+def pmc_traffic(kernel):
+    import hashlib
+    if kernel != PMC_TRAFFIC["kernel"]:
+        return None
+    h = hashlib.sha256()
+    for f in PMC_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != PMC_TRAFFIC["sha256"]:
+        return None
+    return PMC_TRAFFIC["fetch_bytes"] + PMC_TRAFFIC["write_bytes"]
+
+
 def roofline(fam, dom, nrec, prec):
     d = fam[dom]
     t_s = d["ms"] / 1e3
@@ -97,7 +124,14 @@ def roofline(fam, dom, nrec, prec):
     else:
         roof = {"bound": "alu", "achieved": flops_rate, "peak": peak_f, "unit": "TFLOP/s",
                 "frac": flops_rate / peak_f, "traffic": None}
-    roof.update({"kernel": SINGLE_KERNEL[prec][dom], "launches_per_step": d["launches"] / nrec,
+    kern = SINGLE_KERNEL[prec][dom]
+    traffic = pmc_traffic(kern)
+    if traffic is not None and roof["bound"] == "hbm":
+        roof["traffic"] = traffic
+        roof["traffic_GBs"] = traffic / (d["ms"] / max(1, d["launches"]) / 1e3) / 1e9
+        roof["traffic_over_algorithmic"] = traffic / (d["bytes"] / max(1, d["launches"]))
+        roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof.update({"kernel": kern, "launches_per_step": d["launches"] / nrec,
                  "avg_launch_ms": d["ms"] / max(1, d["launches"]),
                  "algorithmic_flops_per_launch": d["flops"] / max(1, d["launches"]),
                  "algorithmic_bytes_per_launch": d["bytes"] / max(1, d["launches"]),
@@ -185,6 +219,9 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-cal", action="store_true",
+                    help="only run a plain 1 GiB read + 1 GiB write kernel (3 times): the known-size reference "
+                         "for scaling the HBM counters (FETCH_SIZE / WRITE_SIZE) of a counter run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the IFMM factor+solve of one problem runs on a "
@@ -195,6 +232,14 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.copy_cal:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print("copy-cal: 3 x (read 1 GiB, write 1 GiB) by torch.mul", flush=True)
+        return
     N = args.n
     pts = torch.from_numpy(workloads.points_for("c3_exp_1m", N)).to(dev)
     b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", N)[:, 0].copy()).to(dev)
