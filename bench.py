@@ -17,7 +17,11 @@ events (the per-family breakdown in the output); the timed steps put HIP
 events around the launches of the dominant single-kernel family only (the
 roofline's live launch duration), so the other launches run back to back.
 
-Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects).  The
+roofline's "traffic" is the HBM traffic per launch of its kernel from the
+committed rocprofv3 counter runs (null once the kernel sources differ from the
+ones measured); `--copy-cal` runs only the known-size copy those counter runs
+are scaled by.
 """
 import argparse
 import json
