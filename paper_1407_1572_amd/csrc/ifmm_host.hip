@@ -956,6 +956,20 @@ struct Plan final : ifmm_plan {
       }
     });
   }
+  // The same for a launch whose profile family is given directly.
+  template <class F>
+  void count_later_family(int fam, F work) {
+    const int slot = fam + (kF32 ? kOpTypes : 0);
+    const bool tm = profile && timed(fam);
+    deferred.emplace_back([this, slot, tm, work] {
+      const std::pair<double, double> w = work();
+      factor_flops += w.first;
+      if (tm) {
+        prof_flops[slot] += w.first;
+        prof_bytes[slot] += w.second;
+      }
+    });
+  }
   // Work counted after its launch (it depends on results read back).
   void add_count(int fam, double f, double by) {
     factor_flops += f;
@@ -1774,30 +1788,40 @@ struct Plan final : ifmm_plan {
       a.tmp = wsS2.need<T>((size_t)E.size() * kPairs.count * rpad * fpad, s);
       a.rk = st.arr(&L.r);
       const size_t ro = st.push(erec[k][c].data(), erec[k][c].size() * sizeof(ElimRec)) + 1;
-      double f4 = 0, f5 = 0, b4 = 0, b5 = 0;
       int mx = rpad;
-      const double es = sizeof(T);
       for (const Elim& e : E)
         for (int sa = 0; sa < 9; ++sa)
           for (int sb = 0; sb < 9; ++sb) {
-            if (kPairs.idx[sa][sb] < 0) continue;
             const UnitH& ua = e.u[sa];
             const UnitH& ub = e.u[sb];
-            if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
+            if (kPairs.idx[sa][sb] < 0 || !ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
             mx = std::max(mx, std::max(ua.size, ub.size));
-            const double ra = ua.kind == 1 ? L.r[ua.cl] : ua.size, rb = ub.kind == 1 ? L.r[ub.cl] : ub.size;
-            if (ua.kind == 1 && ub.kind == 1) {
-              f4 += 2.0 * ra * ub.size * ua.size;
-              b4 += es * (ua.size * ra + (double)ua.size * ub.size + ra * ub.size);
-              f5 += 2.0 * ra * rb * ub.size;
-              b5 += es * (ra * ub.size + (double)ub.size * rb + 2.0 * ra * rb);
-            } else {
-              f5 += 2.0 * ra * rb * (ua.kind == 1 ? ua.size : ub.size);
-              b5 += es * ((double)ua.size * ub.size + (ua.kind == 1 ? ua.size * ra : ub.size * rb) + 2.0 * ra * rb);
-            }
           }
-      st.elim<T>(a, ro, 4, mx, mx, f4, b4);
-      st.elim<T>(a, ro, 5, mx, mx, f5, b5);
+      // the work of the two launches is counted while the host next waits
+      st.elim<T>(a, ro, 4, mx, mx, 0.0, 0.0);
+      st.elim<T>(a, ro, 5, mx, mx, 0.0, 0.0);
+      count_later_family(12, [E, r = L.r] {
+        double f = 0, by = 0;
+        const double es = sizeof(T);
+        for (const Elim& e : E)
+          for (int sa = 0; sa < 9; ++sa)
+            for (int sb = 0; sb < 9; ++sb) {
+              if (kPairs.idx[sa][sb] < 0) continue;
+              const UnitH& ua = e.u[sa];
+              const UnitH& ub = e.u[sb];
+              if (!ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
+              const double ra = ua.kind == 1 ? r[ua.cl] : ua.size, rb = ub.kind == 1 ? r[ub.cl] : ub.size;
+              if (ua.kind == 1 && ub.kind == 1) {
+                f += 2.0 * ra * ub.size * ua.size + 2.0 * ra * rb * ub.size;
+                by += es * (ua.size * ra + (double)ua.size * ub.size + ra * ub.size) +
+                      es * (ra * ub.size + (double)ub.size * rb + 2.0 * ra * rb);
+              } else {
+                f += 2.0 * ra * rb * (ua.kind == 1 ? ua.size : ub.size);
+                by += es * ((double)ua.size * ub.size + (ua.kind == 1 ? ua.size * ra : ub.size * rb) + 2.0 * ra * rb);
+              }
+            }
+        return std::make_pair(f, by);
+      });
     }
     run(st);
   }
