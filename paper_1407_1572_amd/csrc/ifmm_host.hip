@@ -1057,6 +1057,7 @@ struct Plan final : ifmm_plan {
           rebase(a.r_old);
           rebase(a.r_new);
           rebase(a.r_par);
+          rebase(a.n);
           launch_touch_xform(a, op.ty, s);
           break;
         }
@@ -1769,18 +1770,22 @@ struct Plan final : ifmm_plan {
       a.sM = L.sM;
       std::vector<int> tq(nt);
       for (int t = 0; t < nt; ++t) tq[t] = touch[t].q;
+      // the new bases replace U inside the same launch (after the product
+      // T = U^^T U above has read the old ones)
+      a.Unew = Uh;
+      a.U = L.U;
+      a.n = st.arr(&L.n);
+      a.sU = L.sU;
+      a.npad = L.npad;
+      double ucb = 0;
+      for (int t = 0; t < nt; ++t) ucb += 2.0 * sizeof(T) * L.n[tq[t]] * (double)rnew[t];
+      add_count(9, 0.0, ucb);
       st.touch_xform<T>(a, &tq, &tidx, L.r, rnew, k > 2 ? &lv[k - 1].r : nullptr, L.nc, false);
       count_later(OP_TXFORM, [a, tq, tidx, ro = L.r, rnew, rp = k > 2 ? lv[k - 1].r : std::vector<int>(),
                               par = k > 2, ncl = L.nc] {
         return txform_work(a, &tq, &tidx, ro, rnew, par ? &rp : nullptr, ncl, sizeof(T));
       });
     }
-    std::vector<AddDesc> cp;
-    for (int t = 0; t < nt; ++t) {
-      const int q = touch[t].q, nq = L.n[q];
-      cp.push_back({Uh + (size_t)t * L.sU, L.Ub(q), nq, rnew[t], L.npad, L.npad, 0, 1.0, 0.0});
-    }
-    st.add(cp);
     for (int t = 0; t < nt; ++t) L.r[touch[t].q] = rnew[t];
     // project the compressed fill into M2L (steps 4, 5 of the records)
     {

@@ -147,6 +147,13 @@ struct TouchXform {
   const int* r_par;   // [nc / 4] parent ranks, or null
   int nt, nside, rpad, col_blocks;
   size_t sM;
+  // optional: the new bases Unew (per touch, sU elements, ld npad) replace
+  // U of their clusters (n[q] x r_new[t]), one more workgroup per touch
+  const void* Unew;
+  void* U;
+  const int* n;       // [nc] cluster sizes
+  size_t sU;
+  int npad;
 };
 
 // Far-field weights with the block lists found on the device: for cluster

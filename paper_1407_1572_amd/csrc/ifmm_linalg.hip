@@ -565,13 +565,24 @@ __global__ __launch_bounds__(WG) void k_fill_copy(const FillCopy a) {
   }
 }
 
-// One workgroup per (touch, window slot); slot 36 is the parent transfer block.
+// One workgroup per (touch, window slot); slot 36 is the parent transfer
+// block, slot 37 (when Unew is given) the copy of the new basis into U.
 template <class T>
 __global__ __launch_bounds__(WG) void k_touch_xform(const TouchXform a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* Z = reinterpret_cast<T*>(smem);
   const int t = blockIdx.x, sl = blockIdx.y;
   const int q = a.touch_q ? a.touch_q[t] : t;
+  if (sl == 37) {  // U(q) <- Unew(t)
+    const int nq = a.n[q], rn = a.r_new[t];
+    const T* src = static_cast<const T*>(a.Unew) + (size_t)t * a.sU;
+    T* dst = static_cast<T*>(a.U) + (size_t)q * a.sU;
+    for (int e = threadIdx.x; e < nq * rn; e += WG) {
+      const int i = e % nq, j = e / nq;
+      dst[i + (size_t)j * a.npad] = src[i + (size_t)j * a.npad];
+    }
+    return;
+  }
   const int rq = a.r_old[q];
   if (rq == 0) return;
   const int rn = a.r_new[t];
@@ -2253,7 +2264,7 @@ void launch_fill_copy(const FillCopy& a, int ty, hipStream_t s) {
 
 void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   if (a.nt <= 0) return;
-  const dim3 grid(a.nt, 37);
+  const dim3 grid(a.nt, a.Unew ? 38 : 37);
   const size_t lds = (size_t)a.rpad * a.rpad * (ty ? sizeof(float) : sizeof(double));
   if (ty) {
     static bool raised = false;
