@@ -200,3 +200,25 @@ def test_nonfinite_rhs_is_not_converged(torch_dev):
     s.solve(torch.from_numpy(b).to(dev))
     assert s.last_info["status"] == 0 and s.last_info["residual"] <= 1e-10
     s.close()
+
+
+def test_five_rhs_and_plan_reuse(torch_dev):
+    """Five right-hand sides (column groups of four and one in the solve
+    kernels), then one column, then five again on the same handle: every
+    solve matches the dense solve, and the single-column solve matches the
+    corresponding column of the five-column one."""
+    _say("[gpu] 5 rhs, then 1, then 5 on one handle")
+    torch, dev = torch_dev
+    pts = workloads.uniform(1500, 1011)
+    B = workloads.rhs(1500, 5, 2007)
+    # eps = 0 with a rank cap that never binds: lossless compression
+    s = _gpu(torch_dev, pts, "exp", 0.1, "const", 1.01, 0.0, 8, 3, r_max=128)
+    o = IFMM(pts, Kernel("exp", 0.1), 0.0, 8, 3, "const", 1.01, r_cap=128)
+    xd = _dense(o, B)
+    X = s.solve(torch.from_numpy(np.ascontiguousarray(B)).to(dev)).cpu().numpy()
+    assert _rel(X, xd) < 1e-10
+    x2 = s.solve(torch.from_numpy(B[:, 2].copy()).to(dev)).cpu().numpy()
+    assert _rel(x2, X[:, 2]) < 1e-12
+    X2 = s.solve(torch.from_numpy(np.ascontiguousarray(B)).to(dev)).cpu().numpy()
+    assert _rel(X2, X) < 1e-13
+    s.close()
