@@ -246,7 +246,7 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR, OP_FILLCP };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR, OP_FILLCP, OP_ROWCP };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 Schur updates (elimination
 // step 2), 9 touched-cluster transform, 10 window stacked R, 11 solve sweeps,
@@ -266,6 +266,7 @@ inline int family(int t) {
     case OP_M2LASM: return 0;
     case OP_FORMQRR: return 5;
     case OP_FILLCP: return 1;
+    case OP_ROWCP: return 1;
     default: return t;
   }
 }
@@ -530,6 +531,26 @@ struct Stage {
     a.r_par = arr(r_par);
     flops += f;
     op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
+  }
+  // Row blocks between a vector of blocks (item i at blk + i bstride, ld ldb)
+  // and a long vector (item i at v + start[i], ld ldv), cnt[i] rows x nrhs
+  // each: to_blocks = gather into the blocks, else scatter out of them.  The
+  // start / cnt arrays travel in the blob (rebased at launch).
+  struct RowCopy {
+    double* v;
+    double* blk;
+    const int* start;
+    const int* cnt;
+    size_t bstride;
+    int ldv, ldb, n, nrhs, to_blocks;
+  };
+  void row_copy(RowCopy a, const std::vector<int>& start, const std::vector<int>& cnt) {
+    if (a.n <= 0) return;
+    double by = 0;
+    for (int c : cnt) by += 16.0 * c * a.nrhs;
+    a.start = arr(&start);
+    a.cnt = arr(&cnt);
+    op({OP_ROWCP, push(&a, sizeof(a)), 0, a.n, 0, 0, 0.0, by}, 0);
   }
   // Fill copies into the pivoted-QR inputs (records and touches travel in
   // the blob; their pointer fields hold blob offsets + 1, rebased at launch).
@@ -1038,6 +1059,17 @@ struct Plan final : ifmm_plan {
           launch_stackqr(reinterpret_cast<StackQrDesc*>(d + op.off), reinterpret_cast<BlkRef*>(d + op.off2),
                          op.count, op.a, op.ty, s);
           break;
+        case OP_ROWCP: {
+          Stage::RowCopy a;
+          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          a.start = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.start) - 1));
+          a.cnt = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.cnt) - 1));
+          if (a.to_blocks)
+            launch_leaf_gather(a.v, a.ldv, a.blk, a.bstride, a.ldb, a.start, a.cnt, a.n, a.nrhs, s);
+          else
+            launch_leaf_scatter(a.blk, a.bstride, a.ldb, a.v, a.ldv, a.start, a.cnt, a.n, a.nrhs, s);
+          break;
+        }
         case OP_FILLCP: {
           FillCopy a;
           std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
@@ -2033,15 +2065,12 @@ struct Plan final : ifmm_plan {
           st.solve<T>(args(k, c), step, wk, rows, f, by);
         }
       }
-      if (k > 2) {
+      if (k > 2) {  // children's c into the parents' b at the children's offsets
         const Level<T>& Lp = lv[k - 1];
-        std::vector<AddDesc> a;
-        for (int P = 0; P < Lp.nc; ++P)
-          for (int c = 0; c < 4; ++c) {
-            const int ch = 4 * P + c;
-            if (L.r[ch]) a.push_back({cvec(k, ch), bvec(k - 1, P) + Lp.choff[(size_t)P * 4 + c], L.r[ch], nrhs, rpad, Lp.npad, 0, 1.0, 0.0});
-          }
-        st.add(a);
+        std::vector<int> start(L.nc);
+        for (int ch = 0; ch < L.nc; ++ch) start[ch] = (ch >> 2) * Lp.npad * nrhs + Lp.choff[ch];
+        st.row_copy({bvec(k - 1, 0), cvec(k, 0), nullptr, nullptr, (size_t)rpad * nrhs, Lp.npad, rpad, L.nc, nrhs, 0},
+                    start, L.r);
       }
     }
     if (top_m > 0) {
@@ -2066,15 +2095,12 @@ struct Plan final : ifmm_plan {
           st.solve<T>(args(k, c), step, wk, rows, f, by);
         }
       }
-      if (k < kappa) {
+      if (k < kappa) {  // the parents' x at the children's offsets into the children's y
         const Level<T>& Lc = lv[k + 1];
-        std::vector<AddDesc> a;
-        for (int P = 0; P < L.nc; ++P)
-          for (int c = 0; c < 4; ++c) {
-            const int ch = 4 * P + c;
-            if (Lc.r[ch]) a.push_back({xvec(k, P) + L.choff[(size_t)P * 4 + c], yvec(k + 1, ch), Lc.r[ch], nrhs, L.npad, rpad, 0, 1.0, 0.0});
-          }
-        st.add(a);
+        std::vector<int> start(Lc.nc);
+        for (int ch = 0; ch < Lc.nc; ++ch) start[ch] = (ch >> 2) * L.npad * nrhs + L.choff[ch];
+        st.row_copy({xvec(k, 0), yvec(k + 1, 0), nullptr, nullptr, (size_t)rpad * nrhs, L.npad, rpad, Lc.nc, nrhs, 1},
+                    start, Lc.r);
       }
     }
     st.flops = 0.0;  // solve work is not factorisation work
