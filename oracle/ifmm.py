@@ -76,6 +76,11 @@ class IFMM:
         self.c0 = float(c0)
         self.r_cap = int(r_cap) if r_cap is not None else 2 * p * p
         self.stats = {"max_rank": 0, "ranks": {}}
+        # counted FP64 flops of the factorisation by part (leading terms of the
+        # dense primitives: LU (2/3) m^3, triangular solves 2 m^2 w, products
+        # 2 m k n, Householder QR 2 m n^2 - (2/3) n^3, pivoted QR and basis
+        # formation 4 m n k); counting only, no effect on the arithmetic
+        self.work = {"elim": 0.0, "compress": 0.0, "transition": 0.0, "top": 0.0}
         self.assemble()
 
     # ------------------------------------------------------------------ assembly
@@ -207,6 +212,7 @@ class IFMM:
                     Mt[offs[a]:offs[a + 1], offs[b]:offs[b + 1]] = blk
         self.top_offs = offs
         self.top_lu = sla.lu_factor(Mt) if offs[-1] > 0 else None
+        self.work["top"] += 2.0 / 3.0 * float(offs[-1]) ** 3
         return self
 
     def _eliminate(self, k, i, fills):
@@ -240,6 +246,8 @@ class IFMM:
         lu = sla.lu_factor(D)
         X = sla.lu_solve(lu, B)
         Xx, Xz = X[:ni], X[ni:]
+        h = sum(int(n[q]) for q in Qs) + sum(int(r[p]) for p in Es)
+        self.work["elim"] += 2.0 / 3.0 * m ** 3 + 2.0 * m * m * w + 2.0 * h * ni * w
         rows = [("p2p", q, P[(q, i)]) for q in Qs] + \
                [("m2l", p, L.get((p, i), _z(int(r[p]), ni))) for p in Es]
         for rk, a, Ca in rows:
@@ -294,6 +302,10 @@ class IFMM:
         for q in touched:
             Om, Omp = self._weights(k, q)
             AU = np.hstack([self.U[k][q] @ Om.T] + rowf[q])
+            nq, rq = int(n[q]), int(r[q])
+            rows_w = sum(int(r[l]) for l in self.tree.interaction_list(k, q)) + rq
+            self.work["compress"] += (2.0 * rows_w * rq * rq + 2.0 * nq * rq * Om.shape[0]
+                                      + 4.0 * nq * AU.shape[1] * min(nq, self.r_cap))
             kmax = min(int(n[q]), self.r_cap)
             kU, vU, aU = hh.pivoted_qr(AU, self.eps, kmax)
             if self.symmetric:
@@ -309,14 +321,17 @@ class IFMM:
             Tq[q] = Uh.T @ self.U[k][q]
             Sq[q] = self.V[k][q].T @ Vh
             new[q] = (Uh, Vh, rh)
+            self.work["compress"] += 4.0 * nq * rh * min(nq, self.r_cap) + 2.0 * rh * nq * rq
         M = self.M[k]
         for key in list(M.keys()):
             a, b = key
             if a in Tq or b in Sq:
                 blk = M[key]
                 if a in Tq:
+                    self.work["compress"] += 2.0 * Tq[a].shape[0] * blk.shape[0] * blk.shape[1]
                     blk = Tq[a] @ blk
                 if b in Sq:
+                    self.work["compress"] += 2.0 * blk.shape[0] * blk.shape[1] * Sq[b].shape[1]
                     blk = blk @ Sq[b]
                 M[key] = blk
         for q in touched:
@@ -363,6 +378,8 @@ class IFMM:
                 self.P[kp][(P_, Q_)] = np.vstack(rows)
             Qu, Ru = hh.qr(np.vstack([self.UP[k][c] for c in chP]))
             Qv, Rv = hh.qr(np.vstack([self.VP[k][c] for c in chP]))
+            mq, nq = Qu.shape[0], Ru.shape[1]
+            self.work["transition"] += 2.0 * (2.0 * mq * nq * nq - 2.0 / 3.0 * nq ** 3)
             self.U[kp][P_], self.V[kp][P_] = Qu, Qv
             self.r[kp][P_] = Qu.shape[1]
             Rt[P_] = (Ru, Rv)
