@@ -50,10 +50,13 @@ SINGLE_KERNEL = {
 }
 
 
-def cpu_baseline(n_full):
-    """The oracle, untuned, on sub-squares of the same point set (same density
-    and leaf-box width as the full problem), one BLAS thread."""
-    import numpy as np
+SUB_SIDE = 1.0 / 16  # sub-squares of the 1M point set: 16 x 16 of them
+
+
+def _oracle_subsquare(args):
+    """Factor + refined solve of one sub-square of the point set by the
+    oracle on one core (one BLAS thread); returns (points, seconds)."""
+    n_full, ix, iy = args
     from threadpoolctl import threadpool_limits
 
     import workloads
@@ -62,24 +65,57 @@ def cpu_baseline(n_full):
 
     pts = workloads.points_for("c3_exp_1m", n_full)
     b = workloads.rhs_for("c3_exp_1m", n_full)[:, 0]
-    side = 1.0 / 16
-    tot_n, tot_t = 0, 0.0
-    subs = [(0.0, 0.0), (side, 0.0), (0.0, side)]
+    lo = (ix * SUB_SIDE, iy * SUB_SIDE)
+    m = ((pts[:, 0] >= lo[0]) & (pts[:, 0] < lo[0] + SUB_SIDE) &
+         (pts[:, 1] >= lo[1]) & (pts[:, 1] < lo[1] + SUB_SIDE))
+    p, bb = pts[m], b[m]
     with threadpool_limits(limits=1):
-        for lo in subs:
-            m = ((pts[:, 0] >= lo[0]) & (pts[:, 0] < lo[0] + side) &
-                 (pts[:, 1] >= lo[1]) & (pts[:, 1] < lo[1] + side))
-            p, bb = pts[m], b[m]
-            t0 = time.perf_counter()
-            o = IFMM(p, Kernel("exp", 0.1), 1e-8, 64, 6, "const", 1.01, lo=lo, size=side)
-            o.factor()
-            o.solve_refined(bb, 1e-8)
-            tot_t += time.perf_counter() - t0
-            tot_n += len(p)
-    return {"value": tot_n / tot_t, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(subs)} sub-squares of side 1/16 of the same 1M point set "
-                      f"({tot_n} points, leaf boxes of the full problem's width), same kernel, "
-                      f"p, eps, FP64, refinement to 1e-8; {tot_t:.1f} s on 1 thread"}
+        t0 = time.perf_counter()
+        o = IFMM(p, Kernel("exp", 0.1), 1e-8, 64, 6, "const", 1.01, lo=lo, size=SUB_SIDE)
+        o.factor()
+        o.solve_refined(bb, 1e-8)
+        dt = time.perf_counter() - t0
+    return len(p), dt
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_full):
+    """The oracle, untuned, on sub-squares of the same point set (same density
+    and leaf-box width as the full problem): one core, then every usable core
+    (one process per core, one sub-square at a time each).  Run before the GPU
+    is touched, so the worker processes are plain forks."""
+    import multiprocessing as mp
+
+    single = [(n_full, 0, 0), (n_full, 1, 0), (n_full, 0, 1)]
+    n1, t1 = 0, 0.0
+    for a in single:
+        n, dt = _oracle_subsquare(a)
+        n1, t1 = n1 + n, t1 + dt
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    many = [(n_full, 2 + j % 14, 2 + j // 14) for j in range(2 * cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_subsquare, many, chunksize=1)
+    tw = time.perf_counter() - t0
+    nm = sum(n for n, _ in res)
+    return {"value": nm / tw, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(many)} sub-squares of side 1/16 of the same 1M point set ({nm} points, "
+                      f"leaf boxes of the full problem's width), same kernel, p, eps, FP64, refinement to "
+                      f"1e-8, one process per core (one BLAS thread each); {tw:.1f} s wall",
+            "single_core": {"value": n1 / t1, "unit": "unknowns/s", "cores": 1,
+                            "sample": f"{len(single)} sub-squares ({n1} points), {t1:.1f} s on 1 thread"},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+                     "usable_cpus": len(os.sched_getaffinity(0))}}
 
 
 def dominant(fam, prec):
@@ -135,6 +171,9 @@ def roofline(fam, dom, nrec, prec):
         roof["traffic_GBs"] = traffic / (d["ms"] / max(1, d["launches"]) / 1e3) / 1e9
         roof["traffic_over_algorithmic"] = traffic / (d["bytes"] / max(1, d["launches"]))
         roof["traffic_unit"] = "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    # both fractions of the Schur-update kernel (memory and matrix-core side)
+    roof["frac_hbm"] = bw / PEAK["hbm_GBs"]
+    roof["frac_mfma"] = flops_rate / peak_f
     roof.update({"kernel": kern, "launches_per_step": d["launches"] / nrec,
                  "avg_launch_ms": d["ms"] / max(1, d["launches"]),
                  "algorithmic_flops_per_launch": d["flops"] / max(1, d["launches"]),
@@ -215,6 +254,83 @@ def run(prec, pts, b, steps, warmup, N):
     return summary, roofline(fam, dom, len(recs), prec)
 
 
+def accuracy(pts, b, N):
+    """Outside the timed region, one factor of each precision: the refined
+    solution's residual against the FMM matrix, against the true kernel on
+    1,000 sampled rows, the paper's error (b = A~ x_exact, x_exact ~ N(0,1);
+    the notation table of the numerical section), and the mixed solution
+    against the FP64 one."""
+    import numpy as np
+    import torch
+
+    from paper_1407_1572_amd import IFMMSolver
+
+    gen = np.random.default_rng(3003)
+    rows = torch.from_numpy(np.sort(gen.choice(N, 1000, replace=False))).to(pts.device)
+    x_exact = torch.from_numpy(np.random.default_rng(3004).standard_normal(N)).to(pts.device)
+    c0, ell = 1.01, 0.1
+
+    def true_rows(x):
+        """(A x)[rows] with the exact kernel exp(-r/ell), A_ii = c0 (FP64, plain torch ops)."""
+        out = torch.empty(len(rows), dtype=torch.float64, device=pts.device)
+        for a in range(0, len(rows), 50):
+            rr = rows[a:a + 50]
+            d = torch.cdist(pts[rr], pts)
+            K = torch.exp(-d / ell)
+            K[torch.arange(len(rr), device=pts.device), rr] = c0
+            out[a:a + 50] = K @ x
+        return out
+
+    res, xs = {}, {}
+    for prec in ("fp32", "fp64"):
+        s = IFMMSolver(pts, "exp", ell, "const", c0, 1e-8, 64, 36, refine_tol=1e-8, precision=prec)
+        x = s.solve(b)
+        info = s.last_info
+        r_fmm = (b - s.matvec(x)).norm() / b.norm()
+        r_true = (b[rows] - true_rows(x)).norm() / b[rows].norm()
+        r_fmm_rows = (b - s.matvec(x))[rows].norm() / b[rows].norm()
+        be = s.matvec(x_exact)
+        xe = s.solve(be)
+        err = (xe - x_exact).norm() / x_exact.norm()
+        xs[prec] = x
+        res["mixed" if prec == "fp32" else "fp64"] = {
+            "direct_residual": info["history"][0], "refined_residual": float(r_fmm),
+            "sweeps": info["iterations"], "residual_fmm_sampled_rows": float(r_fmm_rows),
+            "residual_true_kernel_sampled_rows": float(r_true),
+            "paper_error_x_exact": float(err)}
+        s.close()
+        torch.cuda.synchronize()
+    res["mixed_vs_fp64"] = float((xs["fp32"] - xs["fp64"]).norm() / xs["fp64"].norm())
+    res["note"] = ("residual_true_kernel_sampled_rows: ||b - A x|| / ||b|| over 1,000 seeded rows with the exact "
+                   "kernel (the FMM matrix A~ at p = 6 differs from it by its interpolation error); "
+                   "paper_error_x_exact: ||x - x_exact|| / ||x_exact|| for b = A~ x_exact, refined to 1e-8")
+    return res
+
+
+def scaling(prec):
+    """Factor and solve time per unknown and the largest rank at N = 4^k * 64
+    (same parameters, uniform points of the same seed), second of two runs."""
+    import torch
+
+    import workloads
+    from paper_1407_1572_amd import IFMMSolver
+
+    out = {}
+    for n in (16384, 65536, 262144):
+        pts = torch.from_numpy(workloads.points_for("c3_exp_1m", n)).to("cuda:0")
+        b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", n)[:, 0].copy()).to("cuda:0")
+        for _ in range(2):
+            s = IFMMSolver(pts, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, refine_tol=1e-8, precision=prec)
+            s.solve(b)
+            st = s.stats()
+            s.close()
+        out[str(n)] = {"t_factor_ns_per_unknown": st["factor_ms"] * 1e6 / n,
+                       "t_assembly_ns_per_unknown": st["assembly_ms"] * 1e6 / n,
+                       "t_solve_ns_per_unknown": st["last_solve_ms"] * 1e6 / n,
+                       "max_rank": st["max_rank"], "level_max_rank": st["level_max_rank"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +339,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the untimed accuracy figures and the factor-time-per-unknown sweep over N")
     ap.add_argument("--copy-cal", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (3 times): the known-size reference "
                          "for scaling the HBM counters (FETCH_SIZE / WRITE_SIZE) of a counter run")
@@ -245,12 +363,25 @@ def main():
         print("copy-cal: 3 x (read 1 GiB, write 1 GiB) by torch.mul", flush=True)
         return
     N = args.n
+    cpu = None if args.no_cpu_baseline else cpu_baseline(N)
     pts = torch.from_numpy(workloads.points_for("c3_exp_1m", N)).to(dev)
     b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", N)[:, 0].copy()).to(dev)
     torch.cuda.synchronize()
 
     mixed, roof = run("fp32", pts, b, args.steps, args.warmup, N)
     fp64, roof64 = (None, None) if args.no_fp64 else run("fp64", pts, b, args.steps, args.warmup, N)
+    acc = None if args.no_fp64 or args.no_extra else accuracy(pts, b, N)
+    print(f"accuracy: {acc}", file=sys.stderr, flush=True)
+    scal = None
+    if not args.no_extra:
+        scal = {"fp32": scaling("fp32"), "fp64": None if args.no_fp64 else scaling("fp64")}
+        for prec, rec in (("fp32", mixed), ("fp64", fp64)):
+            if rec is not None and scal[prec] is not None:
+                scal[prec][str(N)] = {"t_factor_ns_per_unknown": rec["t_factor_ms"] * 1e6 / N,
+                                      "t_assembly_ns_per_unknown": rec["t_assembly_ms"] * 1e6 / N,
+                                      "t_solve_ns_per_unknown": rec["t_solve_ms"] * 1e6 / N,
+                                      "max_rank": rec["max_rank"], "level_max_rank": rec["level_max_rank"]}
+        print(f"scaling: {scal}", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC, "value": mixed["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -258,11 +389,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N, "mixed": mixed, "fp64": fp64,
                    "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
-                   "roofline_fp64": roof64},
+                   "roofline_fp64": roof64, "accuracy": acc, "scaling_in_n": scal},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(N)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

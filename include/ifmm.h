@@ -54,14 +54,18 @@ typedef enum {
 
 typedef enum {
   IFMM_DIAG_ROWSUM = 0, /* A_ii = c0 + sum_{j != i} A_ij over the FMM matrix */
-  IFMM_DIAG_CONST = 1   /* A_ii = c0 (e.g. K(0) + sigma^2 for exp, 1 for Section 5) */
+  IFMM_DIAG_CONST = 1,  /* A_ii = c0 (e.g. K(0) + sigma^2 for exp, 1 for Section 5) */
+  IFMM_DIAG_VECTOR = 2  /* A_ii = diag[i], a caller-supplied device array (c0 unused) */
 } ifmm_diag_mode;
 
 typedef struct {
-  int kind;       /* ifmm_kernel_kind */
-  double ell;     /* length scale of IFMM_K_EXP (> 0) */
-  int diag_mode;  /* ifmm_diag_mode */
+  int kind;            /* ifmm_kernel_kind */
+  double ell;          /* length scale of IFMM_K_EXP (> 0) */
+  int diag_mode;       /* ifmm_diag_mode */
   double c0;
+  const double* diag;  /* IFMM_DIAG_VECTOR only: device [n], caller's point order, finite
+                          (a non-finite entry gives EINVAL); read during ifmm_factor only,
+                          the library keeps its own copy */
 } ifmm_kernel;
 
 /*
@@ -126,6 +130,8 @@ typedef struct {
   double kernel_flops[32];
   double kernel_bytes[32];
   int precision;           /* ifmm_precision of the factor */
+  int level_cap_hits[16];  /* compressions per level whose rank reached r_max while the
+                              cluster had more rows (the cap may have truncated there) */
 } ifmm_stats_t;
 
 /*
@@ -133,14 +139,16 @@ typedef struct {
  *   points     device [n][2], inside the root box (default [0,1]^2)
  *   k          kernel and diagonal rule
  *   eps        relative truncation tolerance of the fill compression (>= 0;
- *              eps = 0 keeps every direction up to the rank cap)
+ *              eps = 0 keeps every direction up to the rank cap and needs an
+ *              explicit opt->r_max: the default cap would truncate silently)
  *   leaf_size  mean leaf occupancy bound: depth = max(2, ceil(log4(n / leaf_size)))
  *   rank       p^2, the Chebyshev interpolation rank, 1 <= p <= 8
  *   opt        NULL for defaults
  *   out        receives the handle (owns all factor memory; free with ifmm_destroy)
  * Errors: EINVAL (n < 16, rank not a perfect square, p > 8, leaf_size < 1,
- * eps < 0 or NaN, kernel parameters, unknown precision, non-finite or
- * out-of-box or duplicate points), ENOMEM, ESINGULAR, EDEVICE.
+ * eps < 0 or NaN, eps = 0 without opt->r_max, kernel parameters, a null or
+ * non-finite diagonal vector, unknown precision, non-finite or out-of-box or
+ * duplicate points), ENOMEM, ESINGULAR, EDEVICE.
  */
 ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, double eps,
                         int leaf_size, int rank, const ifmm_options* opt, void* stream,

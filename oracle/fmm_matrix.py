@@ -12,7 +12,8 @@ Diagonal (readings listed in the design doc):
   the sum runs over the FMM matrix so that oracle and solver factor the same
   matrix);
 * "const":  A_ii = c0  (exp(-r/ell) + sigma^2 I: c0 = K(0) + sigma^2; the
-  paper's benchmark equation of Section 5 has c0 = 1).
+  paper's benchmark equation of Section 5 has c0 = 1);
+* "vector": A_ii = a given vector (tree order here).
 
 Everything here is in tree order (the order of ``Tree.points``).
 """
@@ -82,17 +83,20 @@ def dense_offdiag(tree: Tree, kernel, p: int) -> np.ndarray:
     return A
 
 
-def diagonal(offdiag_rowsum: np.ndarray, mode: str, c0: float) -> np.ndarray:
+def diagonal(offdiag_rowsum: np.ndarray, mode: str, c0: float, values=None) -> np.ndarray:
     if mode == "rowsum":
         return c0 + offdiag_rowsum
     if mode == "const":
         return np.full_like(offdiag_rowsum, c0)
+    if mode == "vector":
+        return np.array(values, dtype=np.float64, copy=True)
     raise ValueError(mode)
 
 
-def dense_matrix(tree: Tree, kernel, p: int, mode: str, c0: float) -> np.ndarray:
+def dense_matrix(tree: Tree, kernel, p: int, mode: str, c0: float, values=None) -> np.ndarray:
+    """values: the diagonal of mode "vector" in tree order."""
     A = dense_offdiag(tree, kernel, p)
-    d = diagonal(A.sum(axis=1), mode, c0)
+    d = diagonal(A.sum(axis=1), mode, c0, values)
     A[np.diag_indices_from(A)] = d
     return A
 

@@ -66,8 +66,12 @@ def _z(a, b):
 class IFMM:
     def __init__(self, points, kernel: Kernel, eps: float, leaf_size: int, p: int,
                  diag_mode: str = "rowsum", c0: float = 1.0, r_cap: int | None = None,
-                 lo=(0.0, 0.0), size: float = 1.0, symmetric: bool | None = None):
+                 lo=(0.0, 0.0), size: float = 1.0, symmetric: bool | None = None,
+                 diag_values=None):
+        """diag_mode "rowsum" (A_ii = c0 + the FMM row sum), "const" (A_ii =
+        c0) or "vector" (A_ii = diag_values[i], caller's point order)."""
         self.tree = Tree(points, leaf_size, lo, size)
+        self.diag_values = None if diag_values is None else np.asarray(diag_values, dtype=np.float64)[self.tree.perm]
         self.symmetric = (kernel.kind != "callable") if symmetric is None else bool(symmetric)
         self.kernel = kernel
         self.eps = float(eps)
@@ -143,7 +147,7 @@ class IFMM:
             rs = fmm_apply_offdiag(T, self.kernel, p, np.ones(T.N))
         else:
             rs = np.zeros(T.N)
-        self.d = diagonal(rs, self.diag_mode, self.c0)
+        self.d = diagonal(rs, self.diag_mode, self.c0, self.diag_values)
         self.P = {k: {} for k in range(2, kap + 1)}
         for i in range(4 ** kap):
             if self.n[kap][i] == 0:

@@ -890,6 +890,7 @@ struct ifmm_plan {
   int kappa = 0, p = 0, p2 = 0, leaf = 0, r_cap = 0, rpad = 0;
   KernelFn kf{};
   int diag_mode = 0;
+  const double* d_diag_user = nullptr;  // IFMM_DIAG_VECTOR: the caller's A_ii (device, caller order)
   double c0 = 0.0, eps = 0.0;
   double lox = 0.0, loy = 0.0, size = 1.0;
   double refine_tol = 0.0;
@@ -939,6 +940,7 @@ struct Plan final : ifmm_plan {
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
   hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
   int max_rank = 0;
+  int cap_hits[16] = {};  // compressions per level whose rank reached the cap with more rows left
   // per-kernel profile (HIP events around each batched launch)
   struct Pending {
     int t;
@@ -1209,6 +1211,7 @@ struct Plan final : ifmm_plan {
     HIP_OK(launch_tree_build(d_points_in, n, lox, loy, size, kappa, ki, ki + N, ki + 2 * N, d_perm, d_leaf_n,
                              d_leaf_start, bad, d_pts, tmp, tmp_bytes, s));
     if (kf.kind == 0) launch_tree_distinct(d_pts, d_leaf_start, d_leaf_n, nleaf, bad, s);  // 1/r: distinct
+    if (diag_mode == IFMM_DIAG_VECTOR) launch_check_finite(d_diag_user, n, bad, s);
     leaf_n.assign(nleaf + 1, 0);
     HIP_OK(hipMemcpyAsync(leaf_n.data(), d_leaf_n, sizeof(int) * (nleaf + 1), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1292,6 +1295,8 @@ struct Plan final : ifmm_plan {
       launch_fill(ones, N, 1.0, s);
       fmm_apply_tree(ones, d_diag, 1, nullptr);
       launch_add_const(d_diag, N, c0, s);
+    } else if (diag_mode == IFMM_DIAG_VECTOR) {
+      launch_gather_rows(d_diag_user, (int)N, d_perm, (int)N, 1, d_diag, (int)N, s);
     } else {
       launch_fill(d_diag, N, c0, s);
     }
@@ -1650,14 +1655,24 @@ struct Plan final : ifmm_plan {
           }
           b3 += es * 3.0 * e.ri * e.u[sp].size;
         }
+        // Schur updates, counted per elimination GEMM: the pivot column C
+        // (h x n_i) and X (n_i x w) read once, every target block read and
+        // written once (a fill block between well-separated units is only
+        // written)
+        double h = 0, wcols = 0;
+        for (int sa = 0; sa < 9; ++sa) {
+          if (!e.u[sa].kind) continue;
+          wcols += e.u[sa].size;
+          if (sa != 4) h += e.u[sa].size;
+        }
+        b2 += es * (h * e.ni + e.ni * wcols);
         for (int sa = 0; sa < 9; ++sa) {
           if (sa == 4 || !e.u[sa].kind) continue;
           for (int sb = 0; sb < 9; ++sb) {
             if (!e.u[sb].kind) continue;
             const double ma = e.u[sa].size, nbu = e.u[sb].size;
             f2 += 2.0 * ma * nbu * e.ni;
-            b2 += es * (ma * e.ni + e.ni * nbu + (kPairs.idx[sa][sb] >= 0 && !(e.u[sa].kind == 2 && e.u[sb].kind == 2)
-                                                      ? 1.0 : 2.0) * ma * nbu);
+            b2 += es * (kPairs.idx[sa][sb] >= 0 && !(e.u[sa].kind == 2 && e.u[sb].kind == 2) ? 1.0 : 2.0) * ma * nbu;
           }
         }
       }
@@ -1774,6 +1789,7 @@ struct Plan final : ifmm_plan {
       for (int t = t0; t < t1; ++t) {
         const int nq = L.n[touch[t].q];
         rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
+        if (rnew[t] == r_cap && nq > r_cap) ++cap_hits[k];
         // Q of the pivoted steps, formed on the device: its work, now that
         // the rank is known
         const int kk = std::min(rnew[t], hr[2 * t + 1]);
@@ -2269,6 +2285,7 @@ struct Plan final : ifmm_plan {
         }
       st->level_max_rank[k] = mx;
       st->level_mean_rank[k] = cnt ? sum / cnt : 0.0;
+      st->level_cap_hits[k] = cap_hits[k];
       bytes += (double)L.nc * (sizeof(T) * 9.0 * (L.sP + L.sQ + L.sL) + sizeof(double) * L.sD);
     }
     st->top_size = top_m;
@@ -2360,8 +2377,13 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
   if (rank < 1 || p * p != rank || p > kMaxP) return IFMM_EINVAL;
   if (k->kind != IFMM_K_INV_R && k->kind != IFMM_K_EXP) return IFMM_EINVAL;
   if (k->kind == IFMM_K_EXP && !(k->ell > 0.0)) return IFMM_EINVAL;
-  if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST) return IFMM_EINVAL;
-  if (!std::isfinite(k->c0)) return IFMM_EINVAL;
+  if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST && k->diag_mode != IFMM_DIAG_VECTOR)
+    return IFMM_EINVAL;
+  if (k->diag_mode == IFMM_DIAG_VECTOR && !k->diag) return IFMM_EINVAL;
+  if (k->diag_mode != IFMM_DIAG_VECTOR && !std::isfinite(k->c0)) return IFMM_EINVAL;
+  // eps = 0 asks for lossless compression: only with an explicit rank cap
+  // (ranks grow with every elimination; the default cap would truncate)
+  if (eps == 0.0 && !(opt && opt->r_max > 0)) return IFMM_EINVAL;
   int r_cap = opt && opt->r_max > 0 ? opt->r_max : 2 * rank;
   if (r_cap > kMaxRank) r_cap = opt && opt->r_max > 0 ? -1 : kMaxRank;
   if (r_cap < rank || r_cap > kMaxRank) return IFMM_EINVAL;
@@ -2380,7 +2402,8 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
   h->rpad = rup(r_cap, 8);
   h->kf = KernelFn{k->kind, k->ell};
   h->diag_mode = k->diag_mode;
-  h->c0 = k->c0;
+  h->d_diag_user = k->diag_mode == IFMM_DIAG_VECTOR ? k->diag : nullptr;
+  h->c0 = k->diag_mode == IFMM_DIAG_VECTOR ? 0.0 : k->c0;
   h->eps = eps;
   if (opt && opt->box_size > 0.0) {
     h->lox = opt->box_lo[0];

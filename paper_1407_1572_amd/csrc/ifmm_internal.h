@@ -447,6 +447,8 @@ hipError_t launch_tree_build(const double* pts, int n, double lox, double loy, d
 // *bad = 1 when two points of one leaf coincide.
 void launch_tree_distinct(const double* spts, const int* leaf_start, const int* leaf_n, int nleaf,
                           int* bad, hipStream_t s);
+// Sets *bad when an entry of v[0..n) is not finite.
+void launch_check_finite(const double* v, int n, int* bad, hipStream_t s);
 // Rows of each leaf of a tree-order vector (ld ldv, nrhs columns) into the
 // leaf's block (blk + i bstride, ld ldb), and back.
 void launch_leaf_gather(const double* v, int ldv, double* blk, size_t bstride, int ldb, const int* leaf_start,

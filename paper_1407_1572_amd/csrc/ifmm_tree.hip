@@ -37,6 +37,12 @@ __global__ void __launch_bounds__(256) k_tree_keys(const double* __restrict__ pt
   atomicAdd(leaf_n + k, 1);
 }
 
+// A non-finite entry of v sets *bad (the caller's diagonal).
+__global__ void __launch_bounds__(256) k_check_finite(const double* __restrict__ v, int n, int* __restrict__ bad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && !isfinite(v[i])) *bad = 1;
+}
+
 // Sorted coordinates: dst[i] = src[perm[i]] for the (x, y) pairs.
 __global__ void __launch_bounds__(256) k_tree_gather(const double* __restrict__ src,
                                                      const int* __restrict__ perm, int n,
@@ -141,6 +147,11 @@ void launch_leaf_scatter(const double* blk, size_t bstride, int ldb, double* v, 
   if (nleaf <= 0) return;
   hipLaunchKernelGGL(k_leaf_copy<false>, dim3(nleaf), dim3(256), 0, s, v, ldv, const_cast<double*>(blk), bstride,
                      ldb, leaf_start, leaf_n, nrhs);
+}
+
+void launch_check_finite(const double* v, int n, int* bad, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, bad);
 }
 
 void launch_fill(double* x, size_t n, double v, hipStream_t s) {

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libifmm.so")
 
 KERNELS = {"inv_r": 0, "exp": 1}
-DIAG = {"rowsum": 0, "const": 1}
+DIAG = {"rowsum": 0, "const": 1, "vector": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "singular pivot block",
           4: "refinement did not converge", 5: "HIP device error"}
 
@@ -28,7 +28,8 @@ class IFMMError(RuntimeError):
 
 
 class _Kernel(C.Structure):
-    _fields_ = [("kind", C.c_int), ("ell", C.c_double), ("diag_mode", C.c_int), ("c0", C.c_double)]
+    _fields_ = [("kind", C.c_int), ("ell", C.c_double), ("diag_mode", C.c_int), ("c0", C.c_double),
+                ("diag", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -49,7 +50,8 @@ class _Stats(C.Structure):
                 ("last_solve_ms", C.c_double), ("factor_bytes", C.c_double),
                 ("factor_flops", C.c_double), ("kernel_launches", C.c_int64 * 32),
                 ("kernel_ms", C.c_double * 32), ("kernel_flops", C.c_double * 32),
-                ("kernel_bytes", C.c_double * 32), ("precision", C.c_int)]
+                ("kernel_bytes", C.c_double * 32), ("precision", C.c_int),
+                ("level_cap_hits", C.c_int * 16)]
 
 
 KERNEL_FAMILIES = ["gemm", "add", "unused2", "qr", "rrqr", "formq", "stackqr", "inverse", "elim",
@@ -119,7 +121,9 @@ class IFMMSolver:
     """ifmm_factor(points, kernel, eps, leaf_size, rank) / ifmm_solve(b).
 
     points: torch float64 tensor [N, 2] on the GPU.  b for ``solve`` is [N]
-    or [N, nrhs] on the same device.  precision "fp32" stores the factor's
+    or [N, nrhs] on the same device.  diag "vector" takes A_ii from
+    ``diag_values`` ([N] on the same device, caller's order; c0 unused).
+    precision "fp32" stores the factor's
     blocks in FP32 (the mixed-precision factor; pivot inverses, the FMM
     product, residuals and vectors stay FP64 and refinement recovers FP64
     accuracy).
@@ -129,7 +133,7 @@ class IFMMSolver:
                  c0: float = 1.0, eps: float = 1e-8, leaf_size: int = 64, rank: int = 36,
                  r_max: int = 0, refine_tol: float = 0.0, refine_maxit: int = 30,
                  box=None, profile=False, precision: str = "fp64",
-                 lib_path: str | None = None):
+                 lib_path: str | None = None, diag_values=None):
         import torch
         self._lib = load(lib_path)
         if lib_path is None and not points.is_cuda:
@@ -137,7 +141,15 @@ class IFMMSolver:
         pts = points.to(torch.float64).contiguous()
         self.n = int(pts.shape[0])
         self.device = pts.device
-        k = _Kernel(KERNELS[kernel], float(ell), DIAG[diag], float(c0))
+        dv = None
+        if diag == "vector":
+            if diag_values is None:
+                raise ValueError('diag="vector" needs diag_values')
+            dv = diag_values.to(device=pts.device, dtype=torch.float64).contiguous()
+            if dv.shape != (self.n,):
+                raise ValueError("diag_values must have shape [N]")
+        k = _Kernel(KERNELS[kernel], float(ell), DIAG[diag], float(c0),
+                    C.c_void_p(dv.data_ptr()) if dv is not None else C.c_void_p(0))
         o = _Options()
         o.r_max = int(r_max)
         o.refine_tol = float(refine_tol)
@@ -203,6 +215,7 @@ class IFMMSolver:
         return {"n": s.n, "kappa": k, "p": s.p, "max_rank": s.max_rank,
                 "level_max_rank": {l: s.level_max_rank[l] for l in range(2, k + 1)},
                 "level_mean_rank": {l: s.level_mean_rank[l] for l in range(2, k + 1)},
+                "level_cap_hits": {l: s.level_cap_hits[l] for l in range(2, k + 1)},
                 "top_size": s.top_size, "assembly_ms": s.assembly_ms, "factor_ms": s.factor_ms,
                 "last_solve_ms": s.last_solve_ms, "factor_bytes": s.factor_bytes,
                 "factor_flops": s.factor_flops,

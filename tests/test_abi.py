@@ -39,9 +39,9 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
 
     class K(ctypes.Structure):
         _fields_ = [("kind", ctypes.c_int), ("ell", ctypes.c_double), ("diag_mode", ctypes.c_int),
-                    ("c0", ctypes.c_double)]
+                    ("c0", ctypes.c_double), ("diag", ctypes.c_void_p)]
 
-    k = K(0, 0.0, 0, 1.0)
+    k = K(0, 0.0, 0, 1.0, None)
     f = lib.ifmm_factor
     f.restype = ctypes.c_int
     P = ctypes.c_void_p
@@ -53,7 +53,13 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     assert f(dummy, 4096, ctypes.byref(k), 1e-6, 0, 16, None, None, ctypes.byref(h)) == 1   # leaf size
     assert f(dummy, 8, ctypes.byref(k), 1e-6, 32, 16, None, None, ctypes.byref(h)) == 1     # too small
     assert f(dummy, 4096, ctypes.byref(k), 1e-6, 32, 81, None, None, ctypes.byref(h)) == 1  # p > 8
-    k2 = K(1, 0.0, 1, 1.0)  # exp with ell = 0
+    k2 = K(1, 0.0, 1, 1.0, None)  # exp with ell = 0
     assert f(dummy, 4096, ctypes.byref(k2), 1e-6, 32, 16, None, None, ctypes.byref(h)) == 1
+    k3 = K(1, 0.1, 2, 0.0, None)  # diagonal vector without the vector
+    assert f(dummy, 4096, ctypes.byref(k3), 1e-6, 32, 16, None, None, ctypes.byref(h)) == 1
+    k4 = K(1, 0.1, 7, 1.0, None)  # unknown diagonal rule
+    assert f(dummy, 4096, ctypes.byref(k4), 1e-6, 32, 16, None, None, ctypes.byref(h)) == 1
+    # eps = 0 (lossless) without an explicit rank cap
+    assert f(dummy, 4096, ctypes.byref(k), 0.0, 32, 16, None, None, ctypes.byref(h)) == 1
     lib.ifmm_solve.restype = ctypes.c_int
     assert lib.ifmm_solve(None, None, None, 1, None, None) == 1

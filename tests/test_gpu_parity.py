@@ -6,7 +6,9 @@ Every case is seeded and synthetic.  Bars:
   eliminations;
 * eps > 0: same ranks as the oracle cluster by cluster (+-1 tolerated where a
   pivot norm sits at the threshold) and x within 50 eps of the oracle's x
-  (relative 2-norm); residual against the FMM matrix <= 10 eps;
+  (relative 2-norm) and within 100 eps element by element (largest
+  |x_i - xo_i| over the largest |xo_i|, so an error confined to a few clusters
+  cannot hide in the norm); residual against the FMM matrix <= 10 eps;
 * the FMM product and the assembled diagonal agree with the oracle to 1e-12;
 * refinement reaches 1e-12.
 """
@@ -53,6 +55,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _elem(a, b):
+    """Largest entry-wise difference relative to the largest entry."""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 CASES_EXACT = [
     # name, points, kernel, ell, diag, c0, leaf, p, r_max
     ("invr_512_p3_3lev", lambda: workloads.jittered_grid(512, 1001), "inv_r", 0.0, "rowsum", 1.0, 8, 3, 64),
@@ -71,7 +78,7 @@ def test_eps0_matches_dense_solve(torch_dev, case):
     x = s.solve(torch.from_numpy(b).to(dev)).cpu().numpy()
     o = IFMM(pts, Kernel(kind, ell), 0.0, leaf, p, diag, c0, r_cap=rmax)
     xd = _dense(o, b)
-    assert _rel(x, xd) < 1e-11
+    assert _rel(x, xd) < 1e-11 and _elem(x, xd) < 1e-11
     o.factor()
     for k in range(2, o.tree.kappa + 1):
         assert np.array_equal(s.ranks(k), o.r[k]), k
@@ -104,12 +111,14 @@ def test_eps_matches_oracle(torch_dev, case):
     for k in range(2, o.tree.kappa + 1):
         d = np.abs(s.ranks(k) - o.r[k])
         assert d.max() <= 1 and (d > 0).mean() < 0.02, (k, d.max(), (d > 0).mean())
-    assert _rel(x, xo) < 50 * eps
+    _say(f"  x vs oracle: 2-norm {_rel(x, xo):.2e}, element-wise {_elem(x, xo):.2e}")
+    assert _rel(x, xo) < 50 * eps and _elem(x, xo) < 100 * eps
     res = np.linalg.norm(b - o.apply(x)) / np.linalg.norm(b)
     assert res < res_bound
     # FMM product and diagonal
     y = s.matvec(torch.from_numpy(b).to(dev)).cpu().numpy()
-    assert _rel(y, o.apply(b)) < 1e-12
+    yo = o.apply(b)
+    assert _rel(y, yo) < 1e-12 and _elem(y, yo) < 1e-12
     dg = s.diagonal().cpu().numpy()
     do = np.empty(len(pts))
     do[o.tree.perm] = o.d
@@ -130,7 +139,7 @@ def test_multi_rhs_refinement_and_empty_leaves(torch_dev):
     assert info["residual"] <= 1e-12 and info["iterations"] >= 1
     o = IFMM(pts, Kernel("exp", 0.1), 1e-8, 16, 4, "const", 1.01)
     xd = _dense(o, B)
-    assert _rel(X, xd) < 1e-9
+    assert _rel(X, xd) < 1e-9 and _elem(X, xd) < 1e-9
     for j in range(3):  # column-wise agreement with single-rhs solves
         xj = s.solve(torch.from_numpy(B[:, j].copy()).to(dev)).cpu().numpy()
         assert _rel(xj, X[:, j]) < 1e-12
@@ -216,7 +225,7 @@ def test_five_rhs_and_plan_reuse(torch_dev):
     o = IFMM(pts, Kernel("exp", 0.1), 0.0, 8, 3, "const", 1.01, r_cap=128)
     xd = _dense(o, B)
     X = s.solve(torch.from_numpy(np.ascontiguousarray(B)).to(dev)).cpu().numpy()
-    assert _rel(X, xd) < 1e-10
+    assert _rel(X, xd) < 1e-10 and _elem(X, xd) < 1e-10
     x2 = s.solve(torch.from_numpy(B[:, 2].copy()).to(dev)).cpu().numpy()
     assert _rel(x2, X[:, 2]) < 1e-12
     X2 = s.solve(torch.from_numpy(np.ascontiguousarray(B)).to(dev)).cpu().numpy()

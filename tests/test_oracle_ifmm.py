@@ -218,3 +218,19 @@ def test_symmetric_mode_agrees_with_two_sided_compression():
     og = IFMM(pts, Kernel("inv_r"), 1e-7, 16, 4, "rowsum", 1.0, symmetric=False).factor()
     xg = og.solve(b)
     assert np.linalg.norm(xs - xg) / np.linalg.norm(xg) < 1e-7
+
+
+def test_eps0_with_a_diagonal_vector_equals_dense_solve():
+    # A_ii given per point (caller's order): the lossless factor solves the
+    # dense FMM matrix with that diagonal
+    pts = workloads.uniform(1500, 77)
+    d = 1.01 + np.random.default_rng(79).uniform(size=1500)
+    o = IFMM(pts, Kernel("exp", 0.1), 0.0, 8, 3, "vector", 0.0, r_cap=10 ** 6, diag_values=d).factor()
+    A = fm.dense_matrix(o.tree, o.kernel, o.p, "vector", 0.0, d[o.tree.perm])
+    assert np.array_equal(np.diag(A), d[o.tree.perm])
+    b = workloads.rhs(1500, 1, 80)[:, 0]
+    xt = np.linalg.solve(A, b[o.tree.perm])
+    xd = np.empty_like(xt)
+    xd[o.tree.perm] = xt
+    x = o.solve(b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-11
