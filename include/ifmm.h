@@ -30,6 +30,7 @@
 #ifndef IFMM_H_
 #define IFMM_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -44,12 +45,21 @@ typedef enum {
   IFMM_ENOMEM = 2,     /* device or pinned-host allocation failed */
   IFMM_ESINGULAR = 3,  /* a pivot block was exactly singular */
   IFMM_ENOTCONV = 4,   /* refinement did not reach refine_tol (x holds the best iterate) */
-  IFMM_EDEVICE = 5     /* a HIP runtime error */
+  IFMM_EDEVICE = 5,    /* a HIP runtime error */
+  IFMM_ESIZE = 6       /* ifmm_matvec_noalloc: the product needs more than its fixed workspace */
 } ifmm_status;
 
 typedef enum {
-  IFMM_K_INV_R = 0, /* K(r) = 1/r   (Section 1, Green's functions table) */
-  IFMM_K_EXP = 1    /* K(r) = exp(-r/ell) (Section 1, covariance functions table) */
+  IFMM_K_INV_R = 0,    /* K(r) = 1/r   (Section 1, Green's functions table) */
+  IFMM_K_EXP = 1,      /* K(r) = exp(-r/ell) (Section 1, covariance functions table) */
+  /* The three singular kernels of Section 5 (numerical benchmarks), parameter
+     a = ell (> 0, != 1), each continuous at r = a with K(a) = 1, K(0) = 0: */
+  IFMM_K_LOG_A = 2,    /* (i)   r (log r - 1) / (a (log a - 1)) for r < a, log r / log a else */
+  IFMM_K_INV_R_A = 3,  /* (ii)  r / a for r < a, a / r else */
+  IFMM_K_R2LOG_A = 4,  /* (iii) r^3 (3 log r - 1) / (a^3 (3 log a - 1)) for r < a,
+                                r^2 log r / (a^2 log a) else */
+  IFMM_K_EXP_DELL = 5  /* d/d ell exp(-r/ell) = (r / ell^2) exp(-r/ell): entries of dA/d ell
+                          of the exp kernel (for ifmm_matvec_kernel) */
 } ifmm_kernel_kind;
 
 typedef enum {
@@ -60,7 +70,7 @@ typedef enum {
 
 typedef struct {
   int kind;            /* ifmm_kernel_kind */
-  double ell;          /* length scale of IFMM_K_EXP (> 0) */
+  double ell;          /* length scale of IFMM_K_EXP / _EXP_DELL, parameter a of kinds 2-4 (> 0) */
   int diag_mode;       /* ifmm_diag_mode */
   double c0;
   const double* diag;  /* IFMM_DIAG_VECTOR only: device [n], caller's point order, finite
@@ -166,6 +176,28 @@ ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* str
 
 /* y = A x with the FMM product in FP64 (the matrix that is factored). */
 ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* stream);
+
+/*
+ * y = A x like ifmm_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): every intermediate (x and y in tree order, the multipole and
+ * local coefficients of every level) lives in a fixed 64 MiB device array
+ * that the library holds on each device it runs on until the process ends;
+ * no device memory is allocated or freed.  The work is only enqueued on
+ * `stream` (no wait).  The fixed array is shared by every call on a device:
+ * calls that overlap on one device (different streams, threads or handles)
+ * race and must be ordered by the caller.  Nothing in it needs clearing
+ * between calls (each pass writes its output before it is read).
+ * Needs ifmm_matvec_noalloc_bytes(h, nrhs) <= 64 MiB, i.e.
+ * 8 (2 n nrhs + 2 p^2 nrhs sum_{k=2..kappa} 4^k) bytes (n = 2^20, p = 6:
+ * 29.4 MB per column, so up to 2 columns).
+ * Errors: EINVAL (null handle or pointers, nrhs < 1 or > 64), ESIZE (beyond
+ * the fixed workspace), EDEVICE.
+ */
+ifmm_status ifmm_matvec_noalloc(ifmm_t h, const double* x, double* y, int nrhs, void* stream);
+
+/* Bytes of fixed workspace ifmm_matvec_noalloc needs for nrhs columns (0 for a null handle). */
+size_t ifmm_matvec_noalloc_bytes(ifmm_t h, int nrhs);
 
 /* Copy the diagonal of A (caller's point order) into device array d[n]. */
 ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream);

@@ -8,8 +8,25 @@ namespace ifmm {
 
 namespace {
 
+// K(r) of the built-in kernels (kind: ifmm_kernel_kind; ell is the length
+// scale of the exp kernels and the parameter a of the numerical section's
+// three singular kernels, each continuous at r = a with K(a) = 1 and with the
+// limit 0 at r = 0).
 __device__ inline double kval(KernelFn kf, double r) {
-  return kf.kind == 0 ? 1.0 / r : exp(-r / kf.ell);
+  const double a = kf.ell;
+  switch (kf.kind) {
+    case 0: return 1.0 / r;
+    case 1: return exp(-r / a);
+    case 2:  // r (log r - 1) / (a (log a - 1)) below a, log r / log a above
+      if (r == 0.0) return 0.0;
+      return r < a ? r * (log(r) - 1.0) / (a * (log(a) - 1.0)) : log(r) / log(a);
+    case 3: return r < a ? r / a : a / r;
+    case 4:  // r^3 (3 log r - 1) / (a^3 (3 log a - 1)) below a, r^2 log r / (a^2 log a) above
+      if (r == 0.0) return 0.0;
+      return r < a ? r * r * r * (3.0 * log(r) - 1.0) / (a * a * a * (3.0 * log(a) - 1.0))
+                   : r * r * log(r) / (a * a * log(a));
+    default: return r / (a * a) * exp(-r / a);  // 5: d/d ell of exp(-r / ell)
+  }
 }
 
 __device__ inline double cheb_node(int p, int m) {

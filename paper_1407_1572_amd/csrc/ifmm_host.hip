@@ -238,6 +238,7 @@ constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
 // Largest stored near field of the FMM product (bytes); beyond it the
 // product evaluates the near-field kernel on the fly.
 constexpr size_t kNearStoreMax = (size_t)16 << 30;
+constexpr int kMaxLevels = 12;  // deepest tree (4^12 leaves)
 
 // Relative threshold floor of the fill compression in an FP32 factor: pivot
 // norms below a few FP32 rounding units of the first are rounding noise
@@ -902,6 +903,8 @@ struct ifmm_plan {
   virtual void build(const double* points) = 0;  // assembly + Algorithm 1
   virtual ifmm_status solve(const double* b, double* x, int nrhs, ifmm_solve_info* info) = 0;
   virtual void matvec(const double* x, double* y, int nrhs) = 0;
+  virtual size_t matvec_scratch_bytes(int nrhs) const = 0;
+  virtual void matvec_into(const double* x, double* y, int nrhs, double* ws) = 0;
   virtual void diagonal(double* d) = 0;
   virtual void stats(ifmm_stats_t* st) = 0;
   virtual int ranks(int level, int* out, int count) = 0;
@@ -1194,7 +1197,7 @@ struct Plan final : ifmm_plan {
   void build_tree(const double* d_points_in) {
     kappa = 2;
     while ((int64_t)leaf * (1LL << (2 * kappa)) < N) ++kappa;
-    if (kappa > 12) throw BadArg{};
+    if (kappa > kMaxLevels) throw BadArg{};
     const int nb = 1 << kappa;
     const int nleaf = nb * nb;
     const int n = (int)N;
@@ -1244,12 +1247,18 @@ struct Plan final : ifmm_plan {
 
   // ------------------------------------------------------------- FMM product
   // y = A x (tree order, column-major ld N); diag null = off-diagonal part only.
-  void fmm_apply_tree(const double* xs, double* ys, int nrhs, const double* diag) {
-    const int nleaf = 1 << (2 * kappa);
-    std::vector<double*> W(kappa + 1, nullptr), G(kappa + 1, nullptr);
+  // coeff: the multipole / local coefficients (fmm_coeff_count doubles), null =
+  // the handle's own workspace.
+  size_t fmm_coeff_count(int nrhs) const {
     size_t tot = 0;
     for (int k = 2; k <= kappa; ++k) tot += (size_t)(1 << (2 * k)) * p2 * nrhs;
-    double* base = wsVec.need(2 * tot, s);
+    return 2 * tot;
+  }
+  void fmm_apply_tree(const double* xs, double* ys, int nrhs, const double* diag, double* coeff = nullptr) {
+    const int nleaf = 1 << (2 * kappa);
+    double* W[kMaxLevels + 1] = {};
+    double* G[kMaxLevels + 1] = {};
+    double* base = coeff ? coeff : wsVec.need(fmm_coeff_count(nrhs), s);
     size_t off = 0;
     for (int k = 2; k <= kappa; ++k) {
       W[k] = base + off;
@@ -1583,7 +1592,10 @@ struct Plan final : ifmm_plan {
     a.fpad = fpad;
     a.npair = kPairs.count;
     for (int sa = 0; sa < 9; ++sa)
-      for (int sb = 0; sb < 9; ++sb) a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
+      for (int sb = 0; sb < 9; ++sb) {
+        a.pair[9 * sa + sb] = (signed char)kPairs.idx[sa][sb];
+        if (kPairs.idx[sa][sb] >= 0) a.plist[kPairs.idx[sa][sb]] = (unsigned char)(9 * sa + sb);
+      }
     return a;
   }
 
@@ -2173,6 +2185,22 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipStreamSynchronize(s));
   }
 
+  size_t matvec_scratch_bytes(int nrhs) const override {
+    return sizeof(double) * (2 * (size_t)N * nrhs + fmm_coeff_count(nrhs));
+  }
+
+  // The product with every intermediate in ws (matvec_scratch_bytes): the
+  // tree-order x and y, then the coefficients.  Enqueued only (no wait).
+  void matvec_into(const double* x, double* y, int nrhs, double* ws) override {
+    const int n = (int)N;
+    double* xt = ws;
+    double* yt = ws + (size_t)n * nrhs;
+    launch_gather_rows(x, n, d_perm, n, nrhs, xt, n, s);
+    fmm_apply_tree(xt, yt, nrhs, d_diag, yt + (size_t)n * nrhs);
+    launch_scatter_rows(yt, n, d_perm, n, nrhs, y, n, s);
+    HIP_OK(hipGetLastError());
+  }
+
   void diagonal(double* d) override {
     launch_scatter_rows(d_diag, (int)N, d_perm, (int)N, 1, d, (int)N, s);
     HIP_OK(hipGetLastError());
@@ -2347,6 +2375,38 @@ struct Plan final : ifmm_plan {
   }
 };
 
+// ------------------------------------------------ fixed device workspace
+// The workspace of ifmm_matvec_noalloc: one copy per device, held by the
+// process from the library's first use of the device until it ends.  Its
+// device address is looked up once per device (hipGetSymbolAddress); host
+// code only ever passes that address on, never the array's own name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+std::mutex scratch_mu;
+void* scratch_addr[64] = {};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of the current device's workspace (resolved on first use).
+hipError_t scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
+  return hipSuccess;
+}
+
 ifmm_status map_exc() {
   try {
     throw;
@@ -2375,8 +2435,9 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
   if (n < 16 || n > (int64_t)1 << 30 || leaf_size < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return IFMM_EINVAL;
   int p = (int)std::lround(std::sqrt((double)rank));
   if (rank < 1 || p * p != rank || p > kMaxP) return IFMM_EINVAL;
-  if (k->kind != IFMM_K_INV_R && k->kind != IFMM_K_EXP) return IFMM_EINVAL;
-  if (k->kind == IFMM_K_EXP && !(k->ell > 0.0)) return IFMM_EINVAL;
+  if (k->kind < IFMM_K_INV_R || k->kind > IFMM_K_EXP_DELL) return IFMM_EINVAL;
+  if (k->kind != IFMM_K_INV_R && !(k->ell > 0.0 && std::isfinite(k->ell))) return IFMM_EINVAL;
+  if ((k->kind == IFMM_K_LOG_A || k->kind == IFMM_K_R2LOG_A) && k->ell == 1.0) return IFMM_EINVAL;
   if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST && k->diag_mode != IFMM_DIAG_VECTOR)
     return IFMM_EINVAL;
   if (k->diag_mode == IFMM_DIAG_VECTOR && !k->diag) return IFMM_EINVAL;
@@ -2425,6 +2486,10 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
     return st;
   }
   *out = h;
+  // set-up of the device's fixed workspace (ifmm_matvec_noalloc); a failure
+  // here is reported by that entry point, not by the factorisation
+  void* ws = nullptr;
+  (void)scratch_ptr(&ws);
   return IFMM_OK;
 }
 
@@ -2437,6 +2502,25 @@ ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* st
     return map_exc();
   }
   return IFMM_OK;
+}
+
+ifmm_status ifmm_matvec_noalloc(ifmm_t h, const double* x, double* y, int nrhs, void* stream) {
+  if (!h || !x || !y || nrhs < 1 || nrhs > 64) return IFMM_EINVAL;
+  if (h->matvec_scratch_bytes(nrhs) > kScratchBytes) return IFMM_ESIZE;
+  void* ws = nullptr;
+  if (scratch_ptr(&ws) != hipSuccess) return IFMM_EDEVICE;
+  try {
+    h->s = static_cast<hipStream_t>(stream);
+    h->matvec_into(x, y, nrhs, static_cast<double*>(ws));
+  } catch (...) {
+    return map_exc();
+  }
+  return IFMM_OK;
+}
+
+size_t ifmm_matvec_noalloc_bytes(ifmm_t h, int nrhs) {
+  if (!h || nrhs < 1) return 0;
+  return h->matvec_scratch_bytes(nrhs);
 }
 
 ifmm_status ifmm_diagonal(ifmm_t h, double* d, void* stream) {
@@ -2484,6 +2568,7 @@ const char* ifmm_status_string(ifmm_status s) {
   switch (s) {
     case IFMM_OK: return "ok";
     case IFMM_EINVAL: return "invalid argument";
+    case IFMM_ESIZE: return "problem exceeds the fixed device workspace";
     case IFMM_ENOMEM: return "out of memory";
     case IFMM_ESINGULAR: return "singular pivot block";
     case IFMM_ENOTCONV: return "refinement did not converge";

@@ -203,6 +203,7 @@ struct ElimArgs {
   size_t sP, sQ, sL, sM, sU, sD, sX;
   int nb, npad, rpad, mpad, fpad, npair;
   signed char pair[81];
+  unsigned char plist[81];  // 9 sa + sb of pair index 0 .. npair - 1
 };
 
 // Level transition k -> k-1 with device-side geometry: for parent P, its
@@ -380,7 +381,8 @@ void launch_gj_unpermute(const InvDesc* d, int nd, int max_m, const int* piv, in
 
 // ---------------------------------------------------------- problem kernels
 struct KernelFn {
-  int kind;   // 0: 1/r, 1: exp(-r/ell)
+  int kind;   // ifmm_kernel_kind: 0 1/r, 1 exp(-r/ell), 2-4 the numerical section's kernels (a = ell),
+              // 5 d/d ell exp(-r/ell)
   double ell;
 };
 

@@ -369,12 +369,60 @@ __device__ bool elim_proj_desc(const ElimArgs& a, const ElimRec& r, int b, int s
   return true;
 }
 
-// grid (nb, units * tiles): step 0 and 3 are elementwise, 1, 2, 4, 5 products.
-// One instantiation per step: each gets the registers of its own step only
-// (the FP64-accumulating step 1 needs twice those of the FP32 products).
+// The products (steps 1, 2, 4, 5) run one workgroup per (record, item) --
+// step 1: the nine column units; step 2: the 72 unit pairs with row unit
+// != 4; steps 4, 5: the pairs at Chebyshev distance 2 -- looping over the
+// item's 64 x 64 output tiles.  The order is XCD-aware: a launch's
+// workgroups go round-robin to the 8 XCDs (linear id mod 8), so record b's
+// items take the linear ids congruent to b mod 8 and run back to back on one
+// XCD, where the record's operand blocks (pivot column, X, D^-1, bases) stay
+// in that XCD's L2 for all its products instead of being fetched from HBM
+// once per product.
+constexpr int kXcd = 8;
+__host__ __device__ constexpr int elim_items(int step, int npair) {
+  return step == 1 ? 9 : step == 2 ? 72 : npair;
+}
+
+// grid (nb, units * tiles): step 0 and 3 are elementwise; 1, 2, 4, 5
+// products over the XCD-aware linear grid above.  One instantiation per
+// step: each gets the registers of its own step only (the FP64-accumulating
+// step 1 needs twice those of the FP32 products).
 template <class T, int STEP>
 __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int tiles_m, int tiles_n) {
   constexpr int step = STEP;
+  if (step == 1 || step == 2 || step >= 4) {
+    const int items = elim_items(step, a.npair);
+    const int L = blockIdx.x, j = L / kXcd;
+    const int b = (j / items) * kXcd + L % kXcd, y = j % items;
+    if (b >= a.nb) return;
+    const ElimRec& r = a.rec[b];
+    GemmDesc g;
+    if (step == 1) {
+      if (y == 4) {  // X_centre = -D^-1[:, ni:m]
+        if (!r.kind[4]) return;
+        const double* D = a.Dinv + (size_t)r.i * a.sD + (size_t)r.ni * a.mpad;
+        T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[4] * a.mpad;
+        for (int col = 0; col < r.ri; ++col)
+          for (int row = threadIdx.x; row < r.m; row += WG)
+            X[row + (size_t)col * a.mpad] = (T)(-D[row + (size_t)col * a.mpad]);
+        return;
+      }
+      if (!elim_x_desc<T>(a, r, b, y, g)) return;
+      for (int n0 = 0; n0 < g.N; n0 += 64)
+        for (int m0 = 0; m0 < g.M; m0 += 64) gemm_tile<double, T, T>(g, m0, n0);
+    } else if (step == 2) {
+      const int sa = y / 9 + (y / 9 >= 4 ? 1 : 0), sb = y % 9;
+      if (!elim_schur_desc<T>(a, r, b, sa, sb, g)) return;
+      for (int n0 = 0; n0 < g.N; n0 += 64)
+        for (int m0 = 0; m0 < g.M; m0 += 64) gemm_tile<T, T, T>(g, m0, n0);
+    } else {
+      const int sa = a.plist[y] / 9, sb = a.plist[y] % 9;
+      if (!elim_proj_desc<T>(a, r, b, sa, sb, step, g)) return;
+      for (int n0 = 0; n0 < g.N; n0 += 64)
+        for (int m0 = 0; m0 < g.M; m0 += 64) gemm_tile<T, T, T>(g, m0, n0);
+    }
+    return;
+  }
   const int b = blockIdx.x;
   const ElimRec& r = a.rec[b];
   const int per = tiles_m * tiles_n;
@@ -394,29 +442,7 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int tiles_m, int 
       else v = 0.0;
       D[row + (size_t)col * a.mpad] = v;
     }
-  } else if (step == 1) {
-    if (unit == 4) {  // X_centre = -D^-1[:, ni:m]
-      if (!r.kind[4]) return;
-      const double* D = a.Dinv + (size_t)r.i * a.sD + (size_t)r.ni * a.mpad;
-      T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[4] * a.mpad;
-      for (int e = threadIdx.x; e < 64 * 64; e += WG) {
-        const int row = m0 + e % 64, col = n0 + e / 64;
-        if (row < r.m && col < r.ri) X[row + (size_t)col * a.mpad] = (T)(-D[row + (size_t)col * a.mpad]);
-      }
-      return;
-    }
-    GemmDesc g;
-    if (!elim_x_desc<T>(a, r, b, unit, g) || m0 >= g.M || n0 >= g.N) return;
-    gemm_tile<double, T, T>(g, m0, n0);
-  } else if (step == 2) {
-    GemmDesc g;
-    if (!elim_schur_desc<T>(a, r, b, unit / 9, unit % 9, g) || m0 >= g.M || n0 >= g.N) return;
-    gemm_tile<T, T, T>(g, m0, n0);
-  } else if (step >= 4) {
-    GemmDesc g;
-    if (!elim_proj_desc<T>(a, r, b, unit / 9, unit % 9, step, g) || m0 >= g.M || n0 >= g.N) return;
-    gemm_tile<T, T, T>(g, m0, n0);
-  } else {  // M2L(i) row += X^z_u
+  } else {  // step 3: M2L(i) row += X^z_u
     if (!r.kind[unit]) return;
     const T* Xz = static_cast<const T*>(a.X) + (size_t)b * a.sX + r.ni + (size_t)r.off[unit] * a.mpad;
     T* C;
@@ -2200,8 +2226,9 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s) {
   if (a.nb <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
-  const int units = step == 0 ? 1 : (step == 2 || step >= 4) ? 81 : 9;
-  const dim3 grid(a.nb, units * tm * tn);
+  const bool product = step == 1 || step == 2 || step >= 4;
+  const dim3 grid = product ? dim3((unsigned)(cdiv(a.nb, kXcd) * kXcd * elim_items(step, a.npair)))
+                            : dim3(a.nb, (step == 0 ? 1 : 9) * tm * tn);
 #define ELIM_GO(S)                                                                            \
   if (ty) hipLaunchKernelGGL((k_elim<float, S>), grid, dim3(WG), 0, s, a, tm, tn);   \
   else hipLaunchKernelGGL((k_elim<double, S>), grid, dim3(WG), 0, s, a, tm, tn);

@@ -15,10 +15,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libifmm.so")
 
-KERNELS = {"inv_r": 0, "exp": 1}
+KERNELS = {"inv_r": 0, "exp": 1, "log_a": 2, "inv_r_a": 3, "r2log_a": 4, "dexp_dell": 5}
 DIAG = {"rowsum": 0, "const": 1, "vector": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "singular pivot block",
-          4: "refinement did not converge", 5: "HIP device error"}
+          4: "refinement did not converge", 5: "HIP device error",
+          6: "problem exceeds the fixed device workspace"}
 
 
 class IFMMError(RuntimeError):
@@ -89,6 +90,10 @@ def load(path: str | None = None):
     lib.ifmm_solve.restype = C.c_int
     lib.ifmm_matvec.argtypes = [P, P, P, C.c_int, P]
     lib.ifmm_matvec.restype = C.c_int
+    lib.ifmm_matvec_noalloc.argtypes = [P, P, P, C.c_int, P]
+    lib.ifmm_matvec_noalloc.restype = C.c_int
+    lib.ifmm_matvec_noalloc_bytes.argtypes = [P, C.c_int]
+    lib.ifmm_matvec_noalloc_bytes.restype = C.c_size_t
     lib.ifmm_diagonal.argtypes = [P, P, P]
     lib.ifmm_diagonal.restype = C.c_int
     lib.ifmm_stats.argtypes = [P, C.POINTER(_Stats)]
@@ -197,6 +202,26 @@ class IFMMSolver:
         if st != 0:
             raise IFMMError(st, "ifmm_matvec")
         return yt[0] if one else yt.t()
+
+    def matvec_noalloc(self, x, out):
+        """y = A x into ``out`` ([N] or [N, nrhs] float64, contiguous in the
+        ABI's [nrhs][N] layout: a 1-D tensor, or the transpose of a
+        contiguous [nrhs, N] tensor) with the library's fixed device
+        workspace: no device memory is allocated by the library.  Enqueued on
+        the current stream."""
+        import torch
+        xt, one = self._cols(x)
+        yt = out.reshape(1, -1) if one else out.t()
+        if not (yt.is_contiguous() and yt.dtype == torch.float64 and yt.shape == xt.shape):
+            raise ValueError("out must match x, float64, [nrhs][N] contiguous")
+        st = self._lib.ifmm_matvec_noalloc(self._h, C.c_void_p(xt.data_ptr()), C.c_void_p(yt.data_ptr()),
+                                           int(xt.shape[0]), _stream_handle(xt))
+        if st != 0:
+            raise IFMMError(st, "ifmm_matvec_noalloc")
+        return out
+
+    def matvec_noalloc_bytes(self, nrhs: int = 1) -> int:
+        return int(self._lib.ifmm_matvec_noalloc_bytes(self._h, int(nrhs)))
 
     def diagonal(self):
         import torch
