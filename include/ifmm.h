@@ -178,6 +178,21 @@ ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* str
 ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* stream);
 
 /*
+ * y = A_k x: the FMM matrix of another kernel k (with k's own diagonal rule)
+ * on the tree and Chebyshev bases of h, in FP64 (near field evaluated, not
+ * stored).  The Chebyshev interpolation is linear in the kernel, so with
+ * k = IFMM_K_EXP_DELL (ell of the factored exp kernel), IFMM_DIAG_CONST and
+ * c0 = 0 this is exactly dA/d ell of the factored matrix exp(-r/ell) +
+ * sigma^2 I (the products a gradient with respect to the kernel's
+ * hyperparameters needs; Section 1's covariance kernels).
+ * Errors: EINVAL (null pointers, nrhs < 1 or > 64, invalid kernel; 1/r on a
+ * handle whose kernel is not 1/r: equal points were not ruled out), ENOMEM,
+ * EDEVICE.
+ */
+ifmm_status ifmm_matvec_kernel(ifmm_t h, const ifmm_kernel* k, const double* x, double* y, int nrhs,
+                               void* stream);
+
+/*
  * y = A x like ifmm_matvec, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): every intermediate (x and y in tree order, the multipole and

@@ -903,6 +903,8 @@ struct ifmm_plan {
   virtual void build(const double* points) = 0;  // assembly + Algorithm 1
   virtual ifmm_status solve(const double* b, double* x, int nrhs, ifmm_solve_info* info) = 0;
   virtual void matvec(const double* x, double* y, int nrhs) = 0;
+  virtual void matvec_kernel(const KernelFn& kk, int dmode, double c0k, const double* dvec, const double* x,
+                             double* y, int nrhs) = 0;
   virtual size_t matvec_scratch_bytes(int nrhs) const = 0;
   virtual void matvec_into(const double* x, double* y, int nrhs, double* ws) = 0;
   virtual void diagonal(double* d) = 0;
@@ -936,7 +938,7 @@ struct Plan final : ifmm_plan {
   double* d_top = nullptr;
   Status* d_status = nullptr;
   Arena arena;
-  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg;
+  Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg, wsTab;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
   // stats
@@ -1254,7 +1256,10 @@ struct Plan final : ifmm_plan {
     for (int k = 2; k <= kappa; ++k) tot += (size_t)(1 << (2 * k)) * p2 * nrhs;
     return 2 * tot;
   }
-  void fmm_apply_tree(const double* xs, double* ys, int nrhs, const double* diag, double* coeff = nullptr) {
+  // tables / kov: the M2L tables and kernel of another kernel on the same
+  // tree (its near field evaluated on the fly); null = the factored kernel.
+  void fmm_apply_tree(const double* xs, double* ys, int nrhs, const double* diag, double* coeff = nullptr,
+                      double* const* tables = nullptr, const KernelFn* kov = nullptr) {
     const int nleaf = 1 << (2 * kappa);
     double* W[kMaxLevels + 1] = {};
     double* G[kMaxLevels + 1] = {};
@@ -1270,9 +1275,12 @@ struct Plan final : ifmm_plan {
     }
     launch_p2m(d_pts, d_leaf_start, d_leaf_n, nleaf, kappa, lox, loy, size, p, xs, (int)N, nrhs, W[kappa], s);
     for (int k = kappa - 1; k >= 2; --k) launch_m2m(d_E, p, 1 << (2 * k), W[k + 1], W[k], nrhs, s);
-    for (int k = 2; k <= kappa; ++k) launch_m2l(p, k, d_table[k], W[k], G[k], nrhs, s);
+    for (int k = 2; k <= kappa; ++k) launch_m2l(p, k, tables ? tables[k] : d_table[k], W[k], G[k], nrhs, s);
     for (int k = 2; k < kappa; ++k) launch_l2l(d_E, p, 1 << (2 * k), G[k], G[k + 1], nrhs, s);
-    if (d_near)
+    if (kov)
+      launch_l2p_p2p(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, *kov,
+                     G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
+    else if (d_near)
       launch_l2p_near(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kappa, lox, loy, size, p, d_near,
                       d_near_off, G[kappa], xs, (int)N, diag, ys, (int)N, nrhs, s);
     else
@@ -2201,6 +2209,38 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipGetLastError());
   }
 
+  // y = A_k x for another kernel kk on this tree and these bases, with its
+  // own diagonal rule (dmode / c0k / dvec as in ifmm_kernel).
+  void matvec_kernel(const KernelFn& kk, int dmode, double c0k, const double* dvec, const double* x, double* y,
+                     int nrhs) override {
+    const int n = (int)N;
+    const size_t tsz = (size_t)49 * p2 * p2;
+    double* tb = wsTab.need<double>((size_t)(kappa + 1) * tsz, s);
+    double* tab[kMaxLevels + 1] = {};
+    for (int k = 2; k <= kappa; ++k) {
+      tab[k] = tb + (size_t)k * tsz;
+      launch_m2l_table(kk, p, 0.5 * size / (1 << k), tab[k], s);
+    }
+    double* buf = wsS2.need<double>((size_t)2 * n * nrhs + n, s);
+    double* xt = buf;
+    double* yt = buf + (size_t)n * nrhs;
+    double* dg = buf + (size_t)2 * n * nrhs;
+    if (dmode == IFMM_DIAG_ROWSUM) {  // c0 + the row sums of the off-diagonal part
+      launch_fill(xt, n, 1.0, s);
+      fmm_apply_tree(xt, dg, 1, nullptr, nullptr, tab, &kk);
+      launch_add_const(dg, n, c0k, s);
+    } else if (dmode == IFMM_DIAG_VECTOR) {
+      launch_gather_rows(dvec, n, d_perm, n, 1, dg, n, s);
+    } else {
+      launch_fill(dg, n, c0k, s);
+    }
+    launch_gather_rows(x, n, d_perm, n, nrhs, xt, n, s);
+    fmm_apply_tree(xt, yt, nrhs, dg, nullptr, tab, &kk);
+    launch_scatter_rows(yt, n, d_perm, n, nrhs, y, n, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+  }
+
   void diagonal(double* d) override {
     launch_scatter_rows(d_diag, (int)N, d_perm, (int)N, 1, d, (int)N, s);
     HIP_OK(hipGetLastError());
@@ -2358,7 +2398,7 @@ struct Plan final : ifmm_plan {
     dfree(s, d_status);
     dfree(s, d_rank);
     for (Buf* b : {&wsX, &wsF, &wsT, &wsA, &wsB, &wsQ, &wsR, &wsZ, &wsS1, &wsS2, &wsVec, &wsInvT, &wsInvP,
-                   &wsSeg})
+                   &wsSeg, &wsTab})
       b->release(s);
     arena.release(s);
     for (const Pending& p : pend) {
@@ -2429,19 +2469,27 @@ ifmm_status map_exc() {
 
 extern "C" {
 
+namespace {
+// The kernel description is usable: known kind and diagonal rule, valid parameters.
+bool kernel_ok(const ifmm_kernel* k) {
+  if (k->kind < IFMM_K_INV_R || k->kind > IFMM_K_EXP_DELL) return false;
+  if (k->kind != IFMM_K_INV_R && !(k->ell > 0.0 && std::isfinite(k->ell))) return false;
+  if ((k->kind == IFMM_K_LOG_A || k->kind == IFMM_K_R2LOG_A) && k->ell == 1.0) return false;
+  if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST && k->diag_mode != IFMM_DIAG_VECTOR)
+    return false;
+  if (k->diag_mode == IFMM_DIAG_VECTOR && !k->diag) return false;
+  if (k->diag_mode != IFMM_DIAG_VECTOR && !std::isfinite(k->c0)) return false;
+  return true;
+}
+}  // namespace
+
 ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, double eps, int leaf_size,
                         int rank, const ifmm_options* opt, void* stream, ifmm_t* out) {
   if (!out || !points || !k) return IFMM_EINVAL;
   if (n < 16 || n > (int64_t)1 << 30 || leaf_size < 1 || !(eps >= 0.0) || !std::isfinite(eps)) return IFMM_EINVAL;
   int p = (int)std::lround(std::sqrt((double)rank));
   if (rank < 1 || p * p != rank || p > kMaxP) return IFMM_EINVAL;
-  if (k->kind < IFMM_K_INV_R || k->kind > IFMM_K_EXP_DELL) return IFMM_EINVAL;
-  if (k->kind != IFMM_K_INV_R && !(k->ell > 0.0 && std::isfinite(k->ell))) return IFMM_EINVAL;
-  if ((k->kind == IFMM_K_LOG_A || k->kind == IFMM_K_R2LOG_A) && k->ell == 1.0) return IFMM_EINVAL;
-  if (k->diag_mode != IFMM_DIAG_ROWSUM && k->diag_mode != IFMM_DIAG_CONST && k->diag_mode != IFMM_DIAG_VECTOR)
-    return IFMM_EINVAL;
-  if (k->diag_mode == IFMM_DIAG_VECTOR && !k->diag) return IFMM_EINVAL;
-  if (k->diag_mode != IFMM_DIAG_VECTOR && !std::isfinite(k->c0)) return IFMM_EINVAL;
+  if (!kernel_ok(k)) return IFMM_EINVAL;
   // eps = 0 asks for lossless compression: only with an explicit rank cap
   // (ranks grow with every elimination; the default cap would truncate)
   if (eps == 0.0 && !(opt && opt->r_max > 0)) return IFMM_EINVAL;
@@ -2498,6 +2546,20 @@ ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* st
   try {
     h->s = static_cast<hipStream_t>(stream);
     h->matvec(x, y, nrhs);
+  } catch (...) {
+    return map_exc();
+  }
+  return IFMM_OK;
+}
+
+ifmm_status ifmm_matvec_kernel(ifmm_t h, const ifmm_kernel* k, const double* x, double* y, int nrhs,
+                               void* stream) {
+  if (!h || !k || !x || !y || nrhs < 1 || nrhs > 64 || !kernel_ok(k)) return IFMM_EINVAL;
+  // 1/r is singular at equal points: only on a tree whose points were checked distinct
+  if (k->kind == IFMM_K_INV_R && h->kf.kind != IFMM_K_INV_R) return IFMM_EINVAL;
+  try {
+    h->s = static_cast<hipStream_t>(stream);
+    h->matvec_kernel(KernelFn{k->kind, k->ell}, k->diag_mode, k->c0, k->diag, x, y, nrhs);
   } catch (...) {
     return map_exc();
   }

@@ -90,6 +90,8 @@ def load(path: str | None = None):
     lib.ifmm_solve.restype = C.c_int
     lib.ifmm_matvec.argtypes = [P, P, P, C.c_int, P]
     lib.ifmm_matvec.restype = C.c_int
+    lib.ifmm_matvec_kernel.argtypes = [P, C.POINTER(_Kernel), P, P, C.c_int, P]
+    lib.ifmm_matvec_kernel.restype = C.c_int
     lib.ifmm_matvec_noalloc.argtypes = [P, P, P, C.c_int, P]
     lib.ifmm_matvec_noalloc.restype = C.c_int
     lib.ifmm_matvec_noalloc_bytes.argtypes = [P, C.c_int]
@@ -201,6 +203,24 @@ class IFMMSolver:
                                    int(xt.shape[0]), _stream_handle(xt))
         if st != 0:
             raise IFMMError(st, "ifmm_matvec")
+        return yt[0] if one else yt.t()
+
+    def matvec_kernel(self, x, kernel: str, ell: float = 0.0, diag: str = "const", c0: float = 0.0,
+                      diag_values=None):
+        """y = A_k x for another kernel on this factor's tree and bases (e.g.
+        kernel "dexp_dell", diag "const", c0 = 0: dA/d ell of the exp kernel)."""
+        import torch
+        xt, one = self._cols(x)
+        dv = None
+        if diag == "vector":
+            dv = diag_values.to(device=self.device, dtype=torch.float64).contiguous()
+        k = _Kernel(KERNELS[kernel], float(ell), DIAG[diag], float(c0),
+                    C.c_void_p(dv.data_ptr()) if dv is not None else C.c_void_p(0))
+        yt = torch.empty_like(xt)
+        st = self._lib.ifmm_matvec_kernel(self._h, C.byref(k), C.c_void_p(xt.data_ptr()),
+                                          C.c_void_p(yt.data_ptr()), int(xt.shape[0]), _stream_handle(xt))
+        if st != 0:
+            raise IFMMError(st, "ifmm_matvec_kernel")
         return yt[0] if one else yt.t()
 
     def matvec_noalloc(self, x, out):

@@ -61,3 +61,20 @@ def test_eps0_factor_of_the_numerical_section_kernels(kind):
     xd[o.tree.perm] = xt
     x = o.solve(b)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10 * max(1.0, np.linalg.cond(Ad)) ** 0.5
+
+
+def test_fmm_matrix_derivative_is_the_fmm_matrix_of_the_kernel_derivative():
+    # the Chebyshev FMM matrix is linear in the kernel, so d/d ell of the
+    # matrix of exp(-r/ell) is the matrix of (r/ell^2) exp(-r/ell): checked
+    # against a central difference of the dense matrices
+    from oracle.geometry import Tree
+    pts = workloads.uniform(600, 95)
+    T = Tree(pts, 16)
+    ell, h = 0.08, 1e-6
+    dA = fm.dense_offdiag(T, Kernel("dexp_dell", ell), 4)
+    fd = (fm.dense_offdiag(T, Kernel("exp", ell + h), 4) - fm.dense_offdiag(T, Kernel("exp", ell - h), 4)) / (2 * h)
+    assert np.abs(dA - fd).max() <= 1e-7 * np.abs(dA).max()
+    # and the FMM passes reproduce it
+    x = workloads.rhs(600, 1, 96)[:, 0]
+    assert np.allclose(fm.fmm_apply_offdiag(T, Kernel("dexp_dell", ell), 4, x), dA @ x, rtol=0,
+                       atol=1e-12 * np.abs(dA @ x).max())
