@@ -101,6 +101,10 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
   // this lane's rows / columns of the two 16-blocks, and their validity
   const int r0 = wm + li, r1 = wm + 16 + li, c0 = wn + li, c1 = wn + 16 + li;
   const bool vr0 = r0 < d.M, vr1 = r1 < d.M, vc0 = c0 < d.N, vc1 = c1 < d.N;
+  // the wave's second 16-row / 16-column block lies (partly) inside the
+  // product: else its MFMAs are skipped (wave-uniform; padded blocks of the
+  // many 36- to 100-wide operands would otherwise double the MFMA work)
+  const bool two_m = wm + 16 < d.M, two_n = wn + 16 < d.N;
   const size_t sa = d.opA ? 1 : (size_t)d.lda, ra = d.opA ? (size_t)d.lda : 1;  // A(i, k) = Ap[i ra + k sa]
   const size_t sb = d.opB ? (size_t)d.ldb : 1, cb = d.opB ? 1 : (size_t)d.ldb;  // B(k, j) = Bp[k sb + j cb]
   const bool vecB = kF && d.opB == 0 && (d.ldb & 3) == 0 && (reinterpret_cast<uintptr_t>(Bp) & 15) == 0;
@@ -151,9 +155,9 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       acc[0][0] = mfma16(a[s][0], b[s][0], acc[0][0]);
-      acc[0][1] = mfma16(a[s][0], b[s][1], acc[0][1]);
-      acc[1][0] = mfma16(a[s][1], b[s][0], acc[1][0]);
-      acc[1][1] = mfma16(a[s][1], b[s][1], acc[1][1]);
+      if (two_n) acc[0][1] = mfma16(a[s][0], b[s][1], acc[0][1]);
+      if (two_m) acc[1][0] = mfma16(a[s][1], b[s][0], acc[1][0]);
+      if (two_m && two_n) acc[1][1] = mfma16(a[s][1], b[s][1], acc[1][1]);
     }
   }
   const Acc al = (Acc)d.alpha, be = (Acc)d.beta;
@@ -185,128 +189,6 @@ __device__ void gemm_tile(const GemmDesc& d, int m0, int n0) {
           TC* c = Cp + gm + (size_t)gn * d.ldc;
           const Acc v = acc[bi][bj][r];
           *c = (TC)(d.beta == 0.0 ? al * v : fma(al, v, be * (Acc)*c));
-        }
-      }
-    }
-}
-
-// 64 x 64 output tile (m0, n0) of C += alpha A B (A, B, C of one type T,
-// as stored, column-major, leading dimensions multiples of 16 bytes / T),
-// K staged through LDS in chunks of KC: the 256 threads load a chunk of A
-// (64 x KC) and of B (KC x 64) with 16-byte loads, all in flight at once
-// (one memory round trip per chunk instead of one per 16 k), and store them
-// k-contiguous (A row by row, B column by column, stride KC + pad) so that a
-// lane reads its four consecutive k of each MFMA step as one 16-byte LDS
-// access.  Entries with k >= K are zero in both operands; rows >= M and
-// columns >= N are loaded (inside the blocks' padding) but never stored.
-// The MFMA lane layouts and the wave quarters are those of gemm_tile.
-template <class T>
-struct alignas(16) LdsTile {
-  static constexpr int KC = 256 / (int)sizeof(T);  // 64 FP32, 32 FP64
-  static constexpr int LD = KC + 16 / (int)sizeof(T);
-  static constexpr int V = 16 / (int)sizeof(T);     // values per 16-byte access
-  T a[64 * LD];
-  T b[64 * LD];
-};
-
-template <class T>
-__device__ void gemm_tile_lds(const GemmDesc& d, int m0, int n0, LdsTile<T>& sm) {
-  using Tl = LdsTile<T>;
-  constexpr int KC = Tl::KC, LD = Tl::LD, V = Tl::V;
-  using V4 = typename std::conditional<std::is_same<T, float>::value, mf4, md4>::type;
-  typedef T tv __attribute__((ext_vector_type(V)));
-  const T* __restrict__ Ap = static_cast<const T*>(d.A);
-  const T* __restrict__ Bp = static_cast<const T*>(d.B);
-  T* Cp = static_cast<T*>(d.C);
-  const int t = threadIdx.x;
-  const int lane = t % WAVE, w = t / WAVE;
-  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;  // this wave's quarter inside the tile
-  const int li = lane % 16, lk = lane / 16;
-  V4 acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V4{0, 0, 0, 0};
-  // chunk loads: A as (64 / V) vectors down each of the KC columns, B as
-  // (KC / V) vectors down each of the 64 columns; NL per thread of each
-  constexpr int NL = 64 * KC / V / WG;
-  for (int k0 = 0; k0 < d.K; k0 += KC) {
-    tv av[NL], bv[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + q * WG;
-      const int iv = e % (64 / V), kk = e / (64 / V);  // A: rows V iv .. + V - 1 of column k0 + kk
-      const int row = m0 + V * iv, k = k0 + kk;
-      av[q] = (row < d.M && k < d.K) ? *reinterpret_cast<const tv*>(Ap + row + (size_t)k * d.lda) : tv{};
-      const int kv = e % (KC / V), j = e / (KC / V);  // B: rows k0 + V kv .. of column n0 + j
-      const int kb = k0 + V * kv, col = n0 + j;
-      bv[q] = (col < d.N && kb < d.K) ? *reinterpret_cast<const tv*>(Bp + kb + (size_t)col * d.ldb) : tv{};
-#pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (kb + v >= d.K) bv[q][v] = T(0);
-    }
-    __syncthreads();  // the previous chunk's reads are done
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = t + q * WG;
-      const int iv = e % (64 / V), kk = e / (64 / V);
-#pragma unroll
-      for (int v = 0; v < V; ++v) sm.a[(V * iv + v) * LD + kk] = av[q][v];
-      const int kv = e % (KC / V), j = e / (KC / V);
-      *reinterpret_cast<tv*>(&sm.b[j * LD + V * kv]) = bv[q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 16) {
-      const int kb = kk + 4 * lk;
-      T a[2][4], b[2][4];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          a[x][s4] = sm.a[(wm + 16 * x + li) * LD + kb + s4];
-          b[x][s4] = sm.b[(wn + 16 * x + li) * LD + kb + s4];
-        }
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        acc[0][0] = mfma16(a[0][s4], b[0][s4], acc[0][0]);
-        acc[0][1] = mfma16(a[0][s4], b[1][s4], acc[0][1]);
-        acc[1][0] = mfma16(a[1][s4], b[0][s4], acc[1][0]);
-        acc[1][1] = mfma16(a[1][s4], b[1][s4], acc[1][1]);
-      }
-    }
-  }
-  __syncthreads();  // the LDS is free for the next tile
-  const T al = (T)d.alpha, be = (T)d.beta;
-  constexpr bool kF = std::is_same<T, float>::value;
-  const bool vecC = kF && (d.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(Cp) & 15) == 0;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int gn = n0 + wn + 16 * bj + li;
-      if (gn >= d.N) continue;
-      const int gm0 = m0 + wm + 16 * bi + mfma_row(T(0), lane, 0);
-      if (kF && vecC && gm0 + 3 < d.M) {  // FP32: four consecutive rows of one column at once
-        mf4* c = reinterpret_cast<mf4*>(Cp + gm0 + (size_t)gn * d.ldc);
-        mf4 v;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = (float)(al * acc[bi][bj][r]);
-        if (d.beta != 0.0) {
-          const mf4 o = *c;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = (float)fma(al, acc[bi][bj][r], be * (T)o[r]);
-        }
-        *c = v;
-        continue;
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * bi + mfma_row(T(0), lane, r);
-        if (gm < d.M) {
-          T* c = Cp + gm + (size_t)gn * d.ldc;
-          const T v = acc[bi][bj][r];
-          *c = d.beta == 0.0 ? al * v : fma(al, v, be * *c);
         }
       }
     }
@@ -491,21 +373,20 @@ __device__ bool elim_proj_desc(const ElimArgs& a, const ElimRec& r, int b, int s
   return true;
 }
 
-// The products (steps 1, 2, 4, 5) run one workgroup per (record, item) --
-// step 1: a 64 x 64 output tile of one of the nine column units (the FP64
-// D^-1 operand makes these tiles the slow ones: one per workgroup keeps more
-// of them in flight); step 2: one of the 72 unit pairs with row unit != 4;
-// steps 4, 5: one of the pairs at Chebyshev distance 2 -- steps 2, 4, 5
-// looping over the item's 64 x 64 output tiles.  The order is XCD-aware: a launch's
-// workgroups go round-robin to the 8 XCDs (linear id mod 8), so record b's
-// items take the linear ids congruent to b mod 8 and run back to back on one
-// XCD, where the record's operand blocks (pivot column, X, D^-1, bases) stay
-// in that XCD's L2 for all its products instead of being fetched from HBM
-// once per product.
+// The products of steps 2, 4 and 5 run one workgroup per (record, item) --
+// step 2: one of the 72 unit pairs with row unit != 4; steps 4, 5: one of
+// the pairs at Chebyshev distance 2 -- looping over the item's 64 x 64
+// output tiles.  The order is XCD-aware: a launch's workgroups go
+// round-robin to the 8 XCDs (linear id mod 8), so record b's items take the
+// linear ids congruent to b mod 8 and run back to back on one XCD, where the
+// record's operand blocks (pivot column, X, bases, fill) stay in that XCD's
+// L2 for all its products instead of being fetched from HBM once per
+// product (measured: the Schur updates' HBM fetches fall 4.4x).  Step 1
+// (X = D^-1 B) keeps the record-fastest 2D grid (nb, units x tiles): with
+// its FP64 D^-1 operand the XCD-aware order measured slower (each record's
+// 54 tiles then read the same D^-1 lines at the same time).
 constexpr int kXcd = 8;
-__host__ __device__ constexpr int elim_items(int step, int npair, int tiles) {
-  return step == 1 ? 9 * tiles : step == 2 ? 72 : npair;
-}
+__host__ __device__ constexpr int elim_items(int step, int npair) { return step == 2 ? 72 : npair; }
 
 // grid (nb, units * tiles): step 0 and 3 are elementwise; 1, 2, 4, 5
 // products over the XCD-aware linear grid above.  One instantiation per
@@ -514,34 +395,18 @@ __host__ __device__ constexpr int elim_items(int step, int npair, int tiles) {
 template <class T, int STEP>
 __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int tiles_m, int tiles_n) {
   constexpr int step = STEP;
-  if (step == 1 || step == 2 || step >= 4) {
-    const int items = elim_items(step, a.npair, tiles_m * tiles_n);
+  if (step == 2 || step >= 4) {
+    const int items = elim_items(step, a.npair);
     const int L = blockIdx.x, j = L / kXcd;
     const int b = (j / items) * kXcd + L % kXcd, y = j % items;
     if (b >= a.nb) return;
     const ElimRec& r = a.rec[b];
     GemmDesc g;
-    if (step == 1) {
-      const int per = tiles_m * tiles_n, unit = y / per, tile = y % per;
-      const int m0 = (tile % tiles_m) * 64, n0 = (tile / tiles_m) * 64;
-      if (unit == 4) {  // X_centre = -D^-1[:, ni:m]
-        if (!r.kind[4]) return;
-        const double* D = a.Dinv + (size_t)r.i * a.sD + (size_t)r.ni * a.mpad;
-        T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[4] * a.mpad;
-        for (int e = threadIdx.x; e < 64 * 64; e += WG) {
-          const int row = m0 + e % 64, col = n0 + e / 64;
-          if (row < r.m && col < r.ri) X[row + (size_t)col * a.mpad] = (T)(-D[row + (size_t)col * a.mpad]);
-        }
-        return;
-      }
-      if (!elim_x_desc<T>(a, r, b, unit, g) || m0 >= g.M || n0 >= g.N) return;
-      gemm_tile<double, T, T>(g, m0, n0);
-    } else if (step == 2) {
-      __shared__ LdsTile<T> sm;
+    if (step == 2) {
       const int sa = y / 9 + (y / 9 >= 4 ? 1 : 0), sb = y % 9;
-      if (!elim_schur_desc<T>(a, r, b, sa, sb, g)) return;  // uniform over the workgroup
+      if (!elim_schur_desc<T>(a, r, b, sa, sb, g)) return;
       for (int n0 = 0; n0 < g.N; n0 += 64)
-        for (int m0 = 0; m0 < g.M; m0 += 64) gemm_tile_lds<T>(g, m0, n0, sm);
+        for (int m0 = 0; m0 < g.M; m0 += 64) gemm_tile<T, T, T>(g, m0, n0);
     } else {
       const int sa = a.plist[y] / 9, sb = a.plist[y] % 9;
       if (!elim_proj_desc<T>(a, r, b, sa, sb, step, g)) return;
@@ -555,7 +420,21 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimArgs a, int tiles_m, int 
   const int per = tiles_m * tiles_n;
   const int unit = blockIdx.y / per, tile = blockIdx.y % per;
   const int m0 = (tile % tiles_m) * 64, n0 = (tile / tiles_m) * 64;
-  if (step == 0) {  // D = [[P_ii, U], [U^T, 0]]
+  if (step == 1) {
+    if (unit == 4) {  // X_centre = -D^-1[:, ni:m]
+      if (!r.kind[4]) return;
+      const double* D = a.Dinv + (size_t)r.i * a.sD + (size_t)r.ni * a.mpad;
+      T* X = static_cast<T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[4] * a.mpad;
+      for (int e = threadIdx.x; e < 64 * 64; e += WG) {
+        const int row = m0 + e % 64, col = n0 + e / 64;
+        if (row < r.m && col < r.ri) X[row + (size_t)col * a.mpad] = (T)(-D[row + (size_t)col * a.mpad]);
+      }
+      return;
+    }
+    GemmDesc g;
+    if (!elim_x_desc<T>(a, r, b, unit, g) || m0 >= g.M || n0 >= g.N) return;
+    gemm_tile<double, T, T>(g, m0, n0);
+  } else if (step == 0) {  // D = [[P_ii, U], [U^T, 0]]
     double* D = a.Dinv + (size_t)r.i * a.sD;
     const T* Pii = static_cast<const T*>(a.P) + ((size_t)r.i * 9 + 4) * a.sP;
     const T* U = static_cast<const T*>(a.U) + (size_t)r.i * a.sU;
@@ -2353,9 +2232,9 @@ void launch_add(const AddDesc* d, int nd, int max_m, int max_n, int ty, hipStrea
 void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipStream_t s) {
   if (a.nb <= 0 || max_m <= 0 || max_n <= 0) return;
   const int tm = cdiv(max_m, 64), tn = cdiv(max_n, 64);
-  const bool product = step == 1 || step == 2 || step >= 4;
-  const dim3 grid = product ? dim3((unsigned)(cdiv(a.nb, kXcd) * kXcd * elim_items(step, a.npair, tm * tn)))
-                            : dim3(a.nb, (step == 0 ? 1 : 9) * tm * tn);
+  const bool xcd = step == 2 || step >= 4;
+  const dim3 grid = xcd ? dim3((unsigned)(cdiv(a.nb, kXcd) * kXcd * elim_items(step, a.npair)))
+                        : dim3(a.nb, (step == 0 ? 1 : 9) * tm * tn);
 #define ELIM_GO(S)                                                                            \
   if (ty) hipLaunchKernelGGL((k_elim<float, S>), grid, dim3(WG), 0, s, a, tm, tn);   \
   else hipLaunchKernelGGL((k_elim<double, S>), grid, dim3(WG), 0, s, a, tm, tn);
