@@ -126,17 +126,17 @@ def dominant(fam, prec):
 
 
 # HBM traffic per launch of the roofline kernel, from two rocprofv3 counter
-# runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64` (pass 1
-# FETCH_SIZE, pass 2 WRITE_SIZE; KiB per dispatch, averaged over its 108
-# dispatches), each scaled by what the same counter reads for the known-size
-# copy of `bench.py --copy-cal` (1 GiB read: FETCH_SIZE 524,303 KiB, factor
-# 2.000; 1 GiB written: WRITE_SIZE 1,048,576 KiB, factor 1.000); summary in
-# profiles/ifmm_c3_1m_exp_mixed_pmc_traffic.md.  Valid only for the kernel
-# sources the counters were taken on (their SHA-256 below): traffic is null
-# after any change to them.
-PMC_TRAFFIC = {"kernel": "k_elim<float, 2>", "fetch_bytes": 1.4827e9, "write_bytes": 2.7078e8,
+# runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp64
+# --no-extra` (pass 1 FETCH_SIZE, pass 2 WRITE_SIZE; KiB per dispatch,
+# averaged over its 108 dispatches), each scaled by what the same counter
+# reads for the known-size copy of `bench.py --copy-cal` (1 GiB read:
+# FETCH_SIZE 524,303 KiB, factor 2.000; 1 GiB written: WRITE_SIZE 1,048,576
+# KiB, factor 1.000); summary in profiles/ifmm_c3_1m_exp_mixed_pmc_traffic.md.
+# Valid only for the kernel sources the counters were taken on (their
+# SHA-256 below): traffic is null after any change to them.
+PMC_TRAFFIC = {"kernel": "k_elim<float, 2>", "fetch_bytes": 3.4017e8, "write_bytes": 2.6275e8,
                "sources": ("paper_1407_1572_amd/csrc/ifmm_linalg.hip", "paper_1407_1572_amd/csrc/ifmm_internal.h"),
-               "sha256": "1d8a7f21954cf3f5b8e97c879f98b05cf925819a5b67fe151c15b2604eb76cc3"}
+               "sha256": "196dab498a87452b22f909b49f0ff0541ce53391a07596e5b014455fbaaa485c"}
 
 
 def pmc_traffic(kernel):
