@@ -331,6 +331,63 @@ def scaling(prec):
     return out
 
 
+# The numerical section's benchmark: sigma_i + sum_{j != i} K(r_ij) sigma_j =
+# f_i with its three singular kernels (a = 1e-3), points uniform in
+# [-1, 1]^2, 8 x 8 Chebyshev nodes, tolerance 1e-14 (FP64 factor, direct solve);
+# N in thousands as in its tables.  The paper's own figures (one CPU at
+# 2.1 GHz, its C++ code): t_f seconds and r_m per N.
+PAPER_SIZES_K = (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000)
+PAPER_TABLES = {
+    "log_a": {"t_f": (0.35, 0.71, 1.68, 3.21, 6.78, 16.79, 34.93, 73.87, 189.63, 412.48),
+              "t_s": (0.007, 0.009, 0.026, 0.06, 0.13, 0.32, 0.72, 1.54, 4.09, 8.87),
+              "r_m": (29, 31, 30, 37, 36, 40, 44, 48, 47, 51)},
+    "inv_r_a": {"t_f": (0.42, 1.00, 2.37, 4.94, 9.92, 27.39, 61.34, 142.38, 398.23, 803.85),
+                "t_s": (0.005, 0.015, 0.035, 0.092, 0.192, 0.567, 1.213, 2.492, 5.781, 12.436),
+                "r_m": (45, 43, 49, 51, 57, 54, 59, 65, 68, 67)},
+    "r2log_a": {"t_f": (0.11, 0.27, 0.64, 1.42, 2.76, 5.34, 10.89, 26.47, 72.37, 153.93),
+                "t_s": (0.003, 0.007, 0.017, 0.041, 0.091, 0.262, 0.554, 1.192, 2.873, 6.121),
+                "r_m": (22, 21, 25, 24, 27, 26, 28, 31, 30, 32)},
+}
+
+
+def paper_kernels(max_k):
+    """Factor time, solve time, largest rank and the error ||x - x_exact|| /
+    ||x_exact|| (b = A~ x_exact) of the three kernels over the paper's sizes."""
+    import numpy as np
+    import torch
+
+    from paper_1407_1572_amd import IFMMError, IFMMSolver
+
+    out = {}
+    for kind in ("log_a", "inv_r_a", "r2log_a"):
+        rows = []
+        for j, nk in enumerate(PAPER_SIZES_K):
+            if nk > max_k:
+                break
+            n = nk * 1000
+            pts = torch.from_numpy(2.0 * np.random.default_rng(6000 + nk).uniform(size=(n, 2)) - 1.0).to("cuda:0")
+            xe = torch.from_numpy(np.random.default_rng(7000 + nk).standard_normal(n)).to("cuda:0")
+            rec = {"n": n, "paper": {q: PAPER_TABLES[kind][q][j] for q in ("t_f", "t_s", "r_m")}}
+            try:
+                for _ in range(2):  # the second run is reported (the first warms the block cache)
+                    s = IFMMSolver(pts, kind, 1e-3, "const", 1.0, 1e-14, 128, 64, box=(-1.0, -1.0, 2.0))
+                    b = s.matvec(xe)
+                    x = s.solve(b)
+                    st = s.stats()
+                    s.close()
+                rec.update(t_a=st["assembly_ms"] / 1e3, t_f=st["factor_ms"] / 1e3, t_s=st["last_solve_ms"] / 1e3,
+                           r_m=st["max_rank"], level_max_rank=st["level_max_rank"],
+                           cap_hits=sum(st["level_cap_hits"].values()),
+                           error=float((x - xe).norm() / xe.norm()), kappa=st["kappa"])
+            except IFMMError as e:
+                rec["status"] = str(e)
+            torch.cuda.synchronize()
+            print(f"paper kernel {kind} N={n}: {rec}", file=sys.stderr, flush=True)
+            rows.append(rec)
+        out[kind] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +398,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the untimed accuracy figures and the factor-time-per-unknown sweep over N")
+    ap.add_argument("--paper-kernels", type=int, default=0, metavar="MAX_K",
+                    help="only sweep the numerical section's three kernels up to N = MAX_K thousand "
+                         "(p = 8, tolerance 1e-14, [-1,1]^2, FP64) and print that table as one JSON line")
     ap.add_argument("--copy-cal", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (3 times): the known-size reference "
                          "for scaling the HBM counters (FETCH_SIZE / WRITE_SIZE) of a counter run")
@@ -361,6 +421,12 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print("copy-cal: 3 x (read 1 GiB, write 1 GiB) by torch.mul", flush=True)
+        return
+    if args.paper_kernels:
+        res = paper_kernels(args.paper_kernels)
+        print(json.dumps({"workload": "numerical-section kernels (i)-(iii), a = 1e-3, uniform points in [-1,1]^2, "
+                          "unit diagonal, p = 8 (rank 64), leaf 128, tolerance 1e-14, FP64 factor, direct solve; "
+                          "paper: one 2.1 GHz CPU", "results": res}))
         return
     N = args.n
     cpu = None if args.no_cpu_baseline else cpu_baseline(N)
