@@ -307,6 +307,51 @@ def accuracy(pts, b, N):
     return res
 
 
+def gradients():
+    """Gradients of L = 1/2 y^T A^-1 y, A = exp(-r/0.08) + 5e-3 I, on 262,144
+    uniform points (eps 1e-10, FP64 factor refined to 1e-12): forward (factor +
+    solve) and backward (transposed solve + FMM of dK/d ell) times, and the
+    gradients in ell and sigma^2 against central finite differences of the
+    loss (step 1e-5)."""
+    import numpy as np
+    import torch
+
+    from paper_1407_1572_amd.autograd import gp_loss
+
+    n, ell0, s20 = 262144, 0.08, 5e-3
+    pts = torch.from_numpy(np.random.default_rng(1005).uniform(size=(n, 2))).to("cuda:0")
+    y = torch.from_numpy(np.random.default_rng(2005).standard_normal(n)).to("cuda:0")
+    kw = dict(eps=1e-10, leaf_size=64, rank=36, refine_tol=1e-12)
+    out = {}
+    for rep in range(2):  # the second run is reported (the first warms the block cache)
+        yy = y.clone().requires_grad_(True)
+        ell = torch.tensor(ell0, dtype=torch.float64, requires_grad=True)
+        s2 = torch.tensor(s20, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = gp_loss(pts, yy, ell, s2, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"n": n, "loss": float(L.detach()), "d_ell": float(ell.grad), "d_sigma2": float(s2.grad),
+               "dy_norm": float(yy.grad.norm()), "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3}
+    h = 1e-5
+
+    def loss(e, q):
+        with torch.no_grad():
+            return float(gp_loss(pts, y, e, q, **kw))
+
+    fd_ell = (loss(ell0 + h, s20) - loss(ell0 - h, s20)) / (2 * h)
+    fd_s2 = (loss(ell0, s20 + h) - loss(ell0, s20 - h)) / (2 * h)
+    out.update(fd_d_ell=fd_ell, fd_d_sigma2=fd_s2, rel_err_d_ell=abs(out["d_ell"] - fd_ell) / abs(fd_ell),
+               rel_err_d_sigma2=abs(out["d_sigma2"] - fd_s2) / abs(fd_s2),
+               workload="262,144 uniform points, exp(-r/0.08) + 5e-3 I, leaf 64, p = 6, eps 1e-10, FP64 factor, "
+                        "solve refined to 1e-12; central differences with step 1e-5")
+    return out
+
+
 def scaling(prec):
     """Factor and solve time per unknown and the largest rank at N = 4^k * 64
     (same parameters, uniform points of the same seed), second of two runs."""
@@ -448,6 +493,8 @@ def main():
                                       "t_solve_ns_per_unknown": rec["t_solve_ms"] * 1e6 / N,
                                       "max_rank": rec["max_rank"], "level_max_rank": rec["level_max_rank"]}
         print(f"scaling: {scal}", file=sys.stderr, flush=True)
+    grads = None if args.no_extra else gradients()
+    print(f"gradients: {grads}", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC, "value": mixed["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -455,7 +502,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": N, "mixed": mixed, "fp64": fp64,
                    "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
-                   "roofline_fp64": roof64, "accuracy": acc, "scaling_in_n": scal},
+                   "roofline_fp64": roof64, "accuracy": acc, "scaling_in_n": scal,
+                   "gradients": grads},
         "roofline": roof,
     }
     if cpu is not None:

@@ -272,14 +272,29 @@ __device__ bool elim_x_desc(const ElimArgs& a, const ElimRec& r, int b, int u, G
   return true;
 }
 
-// Descriptor of step 2 for the unit pair (sa, sb) of record r.
+// Descriptor of step 2 for the unit pair (sa, sb) of record r.  The pivot
+// column block of row unit sa -- P_qi (particles q) or L_pi (multipoles of an
+// eliminated p) -- is read as the transpose of its symmetric partner in the
+// pivot row, P_iq or Qm_ip (the reordered extended system is symmetric, and
+// the elimination keeps both partners equal up to rounding): the record's
+// own blocks, just read by X = D^-1 B, with each lane's four consecutive k
+// contiguous in memory (one 16-byte load).  FP32 only: FP64 operands take
+// one 8-byte load per k either way, and the stored orientation keeps the
+// lanes of a load on consecutive rows.
 template <class T>
 __device__ bool elim_schur_desc(const ElimArgs& a, const ElimRec& r, int b, int sa, int sb, GemmDesc& g) {
   if (sa == 4 || !r.kind[sa] || !r.kind[sb]) return false;
   const int ka = r.kind[sa], kb = r.kind[sb], ca = r.cl[sa];
-  g.A = ka == 1 ? static_cast<const T*>(a.P) + ((size_t)ca * 9 + (8 - sa)) * a.sP
-                : static_cast<const T*>(a.L) + ((size_t)ca * 9 + (8 - sa)) * a.sL;
-  g.lda = ka == 1 ? a.npad : a.rpad;
+  constexpr bool kT = std::is_same<T, float>::value;
+  if (kT) {
+    g.A = ka == 1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + sa) * a.sP
+                  : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + sa) * a.sQ;
+    g.lda = a.npad;
+  } else {
+    g.A = ka == 1 ? static_cast<const T*>(a.P) + ((size_t)ca * 9 + (8 - sa)) * a.sP
+                  : static_cast<const T*>(a.L) + ((size_t)ca * 9 + (8 - sa)) * a.sL;
+    g.lda = ka == 1 ? a.npad : a.rpad;
+  }
   g.B = static_cast<const T*>(a.X) + (size_t)b * a.sX + (size_t)r.off[sb] * a.mpad;
   g.ldb = a.mpad;
   const bool adj = abs(e9_dx(sa) - e9_dx(sb)) <= 1 && abs(e9_dy(sa) - e9_dy(sb)) <= 1;
@@ -309,7 +324,7 @@ __device__ bool elim_schur_desc(const ElimArgs& a, const ElimRec& r, int b, int 
   g.M = r.size[sa];
   g.N = r.size[sb];
   g.K = r.ni;
-  g.opA = 0;
+  g.opA = kT ? 1 : 0;
   g.opB = 0;
   g.alpha = -1.0;
   return true;
@@ -1904,7 +1919,10 @@ __global__ __launch_bounds__(TR * TC) void k_gj_reg(const InvDesc* __restrict__ 
         if (tr == 0) pbuf[buf] = bi;
       }
       __syncthreads();
-      const int p = pbuf[buf];
+      // the pivot row is the same for every thread: read as a scalar, so the
+      // selection of its register slot below compiles to scalar branches
+      // (not a chain of per-lane selects over every slot and column)
+      const int p = __builtin_amdgcn_readfirstlane(pbuf[buf]);
       const int tp = p % TR, ap = p / TR;
       if (tr == tp) {
 #pragma unroll
@@ -2027,7 +2045,7 @@ __global__ __launch_bounds__(512) void k_gj_panel_reg(const InvDesc* __restrict_
         if (tr == 0) pbuf[buf] = bi < m ? bi : j;
       }
       __syncthreads();
-      const int p = pbuf[buf];
+      const int p = __builtin_amdgcn_readfirstlane(pbuf[buf]);  // uniform: scalar slot selection below
       const int tp = p % TR, ap = p / TR, tj = j % TR, aj = j / TR;
       if (tr == tp) {
 #pragma unroll
