@@ -352,6 +352,49 @@ def gradients():
     return out
 
 
+def batched():
+    """256 independent problems of uneven size (N_j log-uniform in [1,024,
+    32,768], points seed 4000 + j), kernels alternating between 1/r with the
+    row-sum diagonal and exp(-r/0.1) + 1e-2 I, leaf 64, p = 6, eps 1e-8, 8
+    right-hand sides each (seed 5000 + j), FP32 factor with FP64 refinement
+    to 1e-10: ifmm_factor_batched + ifmm_solve_batched in chunks of 64
+    problems (factor, solve, free), with 1, 4 and 8 host threads (streams)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1407_1572_amd import factor_batched, solve_batched
+
+    count, chunk = 256, 64
+    ns = [int(round(np.exp(np.random.default_rng(3000 + j).uniform(np.log(1024), np.log(32768)))))
+          for j in range(count)]
+    pts = [torch.from_numpy(workloads.uniform(n, 4000 + j)).to("cuda:0") for j, n in enumerate(ns)]
+    rhs = [torch.from_numpy(workloads.rhs(n, 8, 5000 + j)).to("cuda:0") for j, n in enumerate(ns)]
+    kern = [{"kind": "inv_r", "ell": 0.0, "diag": "rowsum", "c0": 1.0} if j % 2 == 0 else
+            {"kind": "exp", "ell": 0.1, "diag": "const", "c0": 1.01} for j in range(count)]
+    kw = dict(eps=1e-8, leaf_size=64, rank=36, refine_tol=1e-10, precision="fp32")
+    out = {"problems": count, "unknowns": int(sum(ns)), "nrhs": 8, "chunk": chunk, "min_n": min(ns),
+           "max_n": max(ns)}
+    for threads in (1, 4, 8):
+        for rep in range(2):  # the second pass is reported (the first warms the block cache)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            worst, sweeps = 0.0, 0
+            for c0 in range(0, count, chunk):
+                sv = factor_batched(pts[c0:c0 + chunk], kern[c0:c0 + chunk], threads=threads, **kw)
+                solve_batched(sv, rhs[c0:c0 + chunk], threads=threads)
+                for s in sv:
+                    worst = max(worst, s.last_info["residual"])
+                    sweeps = max(sweeps, s.last_info["iterations"])
+                    s.close()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out[f"threads_{threads}"] = {"seconds": dt, "unknowns_per_s": sum(ns) / dt,
+                                     "worst_residual": worst, "max_sweeps": sweeps}
+        print(f"batched, {threads} threads: {out[f'threads_{threads}']}", file=sys.stderr, flush=True)
+    return out
+
+
 def scaling(prec):
     """Factor and solve time per unknown and the largest rank at N = 4^k * 64
     (same parameters, uniform points of the same seed), second of two runs."""
@@ -495,6 +538,7 @@ def main():
         print(f"scaling: {scal}", file=sys.stderr, flush=True)
     grads = None if args.no_extra else gradients()
     print(f"gradients: {grads}", file=sys.stderr, flush=True)
+    batch = None if args.no_extra else batched()
     out = {
         "metric": METRIC, "value": mixed["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -503,7 +547,7 @@ def main():
         "config": {"workload": WORKLOAD, "n": N, "mixed": mixed, "fp64": fp64,
                    "speedup_mixed_vs_fp64": (fp64["ms_per_step"] / mixed["ms_per_step"]) if fp64 else None,
                    "roofline_fp64": roof64, "accuracy": acc, "scaling_in_n": scal,
-                   "gradients": grads},
+                   "gradients": grads, "batched": batch},
         "roofline": roof,
     }
     if cpu is not None:

@@ -174,6 +174,39 @@ ifmm_status ifmm_factor(const double* points, int64_t n, const ifmm_kernel* k, d
 ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* stream,
                        ifmm_solve_info* info);
 
+/*
+ * Batched factorisation of `count` independent problems, each exactly as
+ * ifmm_factor(points[i], n[i], &kernels[i], eps, leaf_size, rank, opt, ...)
+ * would factor it (uneven sizes and different kernels allowed; Section
+ * 4.2.2's decoupling of factor and solve).  `threads` host threads (0 = 4)
+ * each drive problems in turn on a HIP stream of their own, so the launches
+ * of different problems run concurrently on the device (each problem's
+ * factorisation reads its new ranks back to the host once per colour phase;
+ * concurrent problems fill the device while one waits).  The inputs must be
+ * ready on `stream`; on return every factorisation is complete and the
+ * handles use `stream`.  Results equal those of ifmm_factor bit for bit.
+ *   out[i], status[i]: host arrays of count entries (out[i] = NULL where
+ *   status[i] != IFMM_OK).
+ * Returns IFMM_OK if every problem succeeded, else the status of a failed
+ * one (EINVAL for null arrays or count < 1, EDEVICE if a worker stream could
+ * not be created).
+ */
+ifmm_status ifmm_factor_batched(int count, const double* const* points, const int64_t* n,
+                                const ifmm_kernel* kernels, double eps, int leaf_size, int rank,
+                                const ifmm_options* opt, int threads, void* stream, ifmm_t* out,
+                                ifmm_status* status);
+
+/*
+ * Batched solve: ifmm_solve(h[i], b[i], x[i], nrhs, ...) for i < count,
+ * concurrently on `threads` host threads with a stream each (as above).  The
+ * handles must be distinct; info (optional) and status are host arrays of
+ * count entries.  Returns IFMM_OK if every solve succeeded, else the status
+ * of a failed one.
+ */
+ifmm_status ifmm_solve_batched(int count, const ifmm_t* h, const double* const* b, double* const* x,
+                               int nrhs, int threads, void* stream, ifmm_solve_info* info,
+                               ifmm_status* status);
+
 /* y = A x with the FMM product in FP64 (the matrix that is factored). */
 ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* stream);
 

@@ -4,4 +4,5 @@ mixed precision (FP32 factor, FP64 refinement).
 The numerical work runs in ``libifmm.so`` (HIP kernels + C-ABI, see
 include/ifmm.h); ``IFMMSolver`` is the Python face of that ABI.
 """
-from .ifmm import IFMMError, IFMMSolver, LIB_PATH, load, release_cached_memory  # noqa: F401
+from .ifmm import (IFMMError, IFMMSolver, LIB_PATH, factor_batched, load,  # noqa: F401
+                   release_cached_memory, solve_batched)

@@ -18,7 +18,9 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <unordered_map>
 #include <string>
@@ -2467,6 +2469,45 @@ ifmm_status map_exc() {
 
 }  // namespace
 
+namespace {
+// Runs job(i, stream) for i = 0 .. count-1 on `threads` host threads, each
+// with its own non-blocking HIP stream (default priority), problems taken
+// in order from a shared counter.  Every job ends with its stream
+// synchronised (ifmm_factor / ifmm_solve do), so the handles it touched are
+// handed back on `caller` once the worker is done with them.
+template <class Job>
+ifmm_status run_batched(int count, int threads, Job job) {
+  if (threads <= 0) threads = 4;
+  threads = std::min(threads, count);
+  std::atomic<int> next{0};
+  std::atomic<int> dev_err{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return IFMM_EDEVICE;
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) {
+      dev_err = 1;
+      return;
+    }
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      dev_err = 1;
+      return;
+    }
+    for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) job(i, st);
+    (void)hipStreamDestroy(st);
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < threads; ++t) pool.emplace_back(worker);
+  } catch (...) {
+    // fewer threads: the ones started and this one take every problem
+  }
+  worker();
+  for (auto& t : pool) t.join();
+  return dev_err ? IFMM_EDEVICE : IFMM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 namespace {
@@ -2550,6 +2591,46 @@ ifmm_status ifmm_matvec(ifmm_t h, const double* x, double* y, int nrhs, void* st
     return map_exc();
   }
   return IFMM_OK;
+}
+
+
+ifmm_status ifmm_factor_batched(int count, const double* const* points, const int64_t* n, const ifmm_kernel* kernels,
+                                double eps, int leaf_size, int rank, const ifmm_options* opt, int threads,
+                                void* stream, ifmm_t* out, ifmm_status* status) {
+  if (count < 1 || !points || !n || !kernels || !out || !status) return IFMM_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    out[i] = nullptr;
+    status[i] = IFMM_EINVAL;
+  }
+  const hipStream_t caller = static_cast<hipStream_t>(stream);
+  // the problems' inputs are the caller's: they are ready once its stream is
+  if (hipStreamSynchronize(caller) != hipSuccess) return IFMM_EDEVICE;
+  const ifmm_status r = run_batched(count, threads, [&](int i, hipStream_t st) {
+    status[i] = ifmm_factor(points[i], n[i], &kernels[i], eps, leaf_size, rank, opt, st, &out[i]);
+    if (status[i] == IFMM_OK) out[i]->s = caller;
+  });
+  if (r != IFMM_OK) return r;
+  ifmm_status worst = IFMM_OK;
+  for (int i = 0; i < count; ++i)
+    if (status[i] != IFMM_OK) worst = status[i];
+  return worst;
+}
+
+ifmm_status ifmm_solve_batched(int count, const ifmm_t* h, const double* const* b, double* const* x, int nrhs,
+                               int threads, void* stream, ifmm_solve_info* info, ifmm_status* status) {
+  if (count < 1 || !h || !b || !x || !status) return IFMM_EINVAL;
+  for (int i = 0; i < count; ++i) status[i] = IFMM_EINVAL;
+  const hipStream_t caller = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(caller) != hipSuccess) return IFMM_EDEVICE;
+  const ifmm_status r = run_batched(count, threads, [&](int i, hipStream_t st) {
+    status[i] = ifmm_solve(h[i], b[i], x[i], nrhs, st, info ? &info[i] : nullptr);
+    if (h[i]) h[i]->s = caller;
+  });
+  if (r != IFMM_OK) return r;
+  ifmm_status worst = IFMM_OK;
+  for (int i = 0; i < count; ++i)
+    if (status[i] != IFMM_OK) worst = status[i];
+  return worst;
 }
 
 ifmm_status ifmm_matvec_kernel(ifmm_t h, const ifmm_kernel* k, const double* x, double* y, int nrhs,

@@ -7,6 +7,9 @@
 // over the scalar type of their operands; the pivot inverse is FP64 only.
 #include "ifmm_internal.h"
 
+#include <mutex>
+#include <unordered_set>
+
 namespace ifmm {
 
 namespace {
@@ -2173,11 +2176,19 @@ void add_go(const AddDesc* d, int nd, int tm, int tn, hipStream_t s) {
 }
 
 // Raise the dynamic LDS limit of a kernel once (gfx950: 160 KiB per CU).
-void allow_lds(const void* fn, bool& done, size_t bytes) {
-  if (done) return;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+// Raise a kernel's dynamic-LDS limit to the CU's 160 KiB once, before its
+// first launch that needs more than the default 64 KiB.  Thread-safe (batched
+// factorisations launch from several host threads) and monotonic: the limit
+// only bounds what a launch may ask for, the LDS actually allocated (and the
+// occupancy) is the launch's own request.
+constexpr size_t kLdsLimit = 160 * 1024;
+void allow_lds(const void* fn) {
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!done.insert(fn).second) return;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit) != hipSuccess)
     (void)hipGetLastError();  // the launch reports a real shortfall
-  done = true;
 }
 
 // Chunk rows of the stacked-R kernels and their LDS bytes for rank r: up to
@@ -2201,8 +2212,7 @@ void stackqr_win_go(const WinStack& a, int max_r, hipStream_t s) {
   int chunk;
   const size_t lds = stackqr_lds<T>(max_r, chunk, 128);
   if (lds > 64 * 1024) {
-    static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_stackqr_win<T>), raised, 150 * 1024);
+    allow_lds(reinterpret_cast<const void*>(k_stackqr_win<T>));
   }
   hipLaunchKernelGGL(k_stackqr_win<T>, dim3(a.nt, a.S), dim3(WG), lds, s, a, chunk);
 }
@@ -2212,8 +2222,7 @@ void stackqr_go(const StackQrDesc* d, const BlkRef* b, int nd, int max_r, hipStr
   int chunk;
   const size_t lds = stackqr_lds<T>(max_r, chunk, 256);
   if (lds > 64 * 1024) {
-    static bool raised = false;
-    allow_lds(reinterpret_cast<const void*>(k_stackqr<T>), raised, 150 * 1024);
+    allow_lds(reinterpret_cast<const void*>(k_stackqr<T>));
   }
   hipLaunchKernelGGL(k_stackqr<T>, dim3(nd), dim3(WG), lds, s, d, b, chunk);
 }
@@ -2318,12 +2327,10 @@ void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   const dim3 grid(a.nt, a.Unew ? 38 : 37);
   const size_t lds = (size_t)a.rpad * a.rpad * (ty ? sizeof(float) : sizeof(double));
   if (ty) {
-    static bool raised = false;
-    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<float>), raised, 150 * 1024);
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<float>));
     hipLaunchKernelGGL(k_touch_xform<float>, grid, dim3(WG), lds, s, a);
   } else {
-    static bool raised = false;
-    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<double>), raised, 150 * 1024);
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<double>));
     hipLaunchKernelGGL(k_touch_xform<double>, grid, dim3(WG), lds, s, a);
   }
 }
@@ -2348,8 +2355,7 @@ constexpr int RRQR_NT = 1024;
 template <class T, bool kLds>
 void rrqr_go(const RrqrDesc* d, int nd, size_t lds, int max_n, hipStream_t s) {
   auto go = [&](auto kern) {
-    static bool raised = false;
-    if (kLds || lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(kern), raised, kRrqrLdsBytes);
+    if (kLds || lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(kern));
     hipLaunchKernelGGL(kern, dim3(nd), dim3(RRQR_NT), lds, s, d);
   };
   constexpr bool f32 = sizeof(T) == 4;  // registers: up to 24 FP32 or 18 FP64 rows per lane
@@ -2383,14 +2389,7 @@ template <class T, int NR>
 void rrqr_reg_go(const RrqrDesc* d, int nd, int nt, size_t lds, hipStream_t s) {
   // the kernel's static LDS is a few KiB: raise the dynamic limit to what
   // this launch asks for, when above the default
-  static size_t raised = 64 * 1024;
-  if (lds > raised) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_rrqr_reg<T, NR>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
-      raised = lds;
-    else
-      (void)hipGetLastError();
-  }
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr_reg<T, NR>));
   hipLaunchKernelGGL((k_rrqr_reg<T, NR>), dim3(nd), dim3(nt), lds, s, d);
 }
 
@@ -2416,14 +2415,7 @@ void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax,
 template <class T, int NR, int G>
 void formq_rr_go(const RrqrDesc* d, int nd, int max_kmax, hipStream_t s) {
   const size_t lds = (size_t)std::min(max_kmax, kMaxRank) * G * NR * sizeof(T);
-  static size_t raised = 64 * 1024;
-  if (lds > raised) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_formq_rr<T, NR, G>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
-      raised = lds;
-    else
-      (void)hipGetLastError();
-  }
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_formq_rr<T, NR, G>));
   hipLaunchKernelGGL((k_formq_rr<T, NR, G>), dim3(nd), dim3(512), lds, s, d);
 }
 
@@ -2457,14 +2449,7 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int max_n, int ty,
 
 template <class T, int MAXP>
 void gram_win_go(const WinStack& a, size_t lds, hipStream_t s) {
-  static size_t raised = 64 * 1024;
-  if (lds > raised) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_win<T, MAXP>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
-      raised = lds;
-    else
-      (void)hipGetLastError();
-  }
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gram_win<T, MAXP>));
   hipLaunchKernelGGL((k_gram_win<T, MAXP>), dim3(a.nt), dim3(WG), lds, s, a);
 }
 
@@ -2479,14 +2464,7 @@ void gram_win_by_rank(const WinStack& a, int max_r, size_t lds, hipStream_t s) {
 
 template <class T, int NBK>
 void gram_rows_go(const WinStack& a, size_t lds, hipStream_t s) {
-  static size_t raised = 64 * 1024;
-  if (lds > raised) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_rows<T, NBK>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
-      raised = lds;
-    else
-      (void)hipGetLastError();
-  }
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gram_rows<T, NBK>));
   hipLaunchKernelGGL((k_gram_rows<T, NBK>), dim3(a.nt), dim3(WG), lds, s, a);
 }
 
@@ -2537,8 +2515,7 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
   }
   const size_t lds = sizeof(double) * (size_t)max_m * (nb + 1);
   if (lds <= 150 * 1024) {
-    static bool raised = false;
-    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gj_panel<true>), raised, 150 * 1024);
+    if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gj_panel<true>));
     hipLaunchKernelGGL(k_gj_panel<true>, dim3(nd), dim3(WG), lds, s, d, j0, nb, piv, ldp, st);
   } else {
     hipLaunchKernelGGL(k_gj_panel<false>, dim3(nd), dim3(WG), sizeof(double) * max_m, s, d, j0, nb, piv,

@@ -90,6 +90,13 @@ def load(path: str | None = None):
     lib.ifmm_solve.restype = C.c_int
     lib.ifmm_matvec.argtypes = [P, P, P, C.c_int, P]
     lib.ifmm_matvec.restype = C.c_int
+    lib.ifmm_factor_batched.argtypes = [C.c_int, C.POINTER(P), C.POINTER(C.c_int64), C.POINTER(_Kernel),
+                                        C.c_double, C.c_int, C.c_int, C.POINTER(_Options), C.c_int, P,
+                                        C.POINTER(P), C.POINTER(C.c_int)]
+    lib.ifmm_factor_batched.restype = C.c_int
+    lib.ifmm_solve_batched.argtypes = [C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.c_int, C.c_int, P,
+                                       C.POINTER(_SolveInfo), C.POINTER(C.c_int)]
+    lib.ifmm_solve_batched.restype = C.c_int
     lib.ifmm_matvec_kernel.argtypes = [P, C.POINTER(_Kernel), P, P, C.c_int, P]
     lib.ifmm_matvec_kernel.restype = C.c_int
     lib.ifmm_matvec_noalloc.argtypes = [P, P, P, C.c_int, P]
@@ -173,6 +180,12 @@ class IFMMSolver:
             raise IFMMError(st, "ifmm_factor")
         self._h = h
         self.last_info = None
+
+    @classmethod
+    def _from_handle(cls, lib, h, n, device):
+        s = cls.__new__(cls)
+        s._lib, s._h, s.n, s.device, s.last_info = lib, h, n, device, None
+        return s
 
     def _cols(self, v):
         import torch
@@ -289,3 +302,60 @@ class IFMMSolver:
             self.close()
         except Exception:
             pass
+
+
+def factor_batched(points, kernels, eps: float = 1e-8, leaf_size: int = 64, rank: int = 36,
+                   r_max: int = 0, refine_tol: float = 0.0, refine_maxit: int = 30,
+                   precision: str = "fp64", threads: int = 0, lib_path: str | None = None):
+    """ifmm_factor_batched: factor independent problems concurrently.
+
+    points: list of [N_i, 2] float64 GPU tensors; kernels: list of dicts
+    {kind, ell, diag, c0} (one per problem).  Returns a list of IFMMSolver.
+    Raises IFMMError if any factorisation failed (the others are freed)."""
+    import torch
+    lib = load(lib_path)
+    cnt = len(points)
+    pts = [p.to(torch.float64).contiguous() for p in points]
+    P = (C.c_void_p * cnt)(*[p.data_ptr() for p in pts])
+    N = (C.c_int64 * cnt)(*[int(p.shape[0]) for p in pts])
+    K = (_Kernel * cnt)(*[_Kernel(KERNELS[k["kind"]], float(k.get("ell", 0.0)), DIAG[k.get("diag", "const")],
+                                  float(k.get("c0", 1.0)), C.c_void_p(0)) for k in kernels])
+    o = _Options()
+    o.r_max, o.refine_tol, o.refine_maxit = int(r_max), float(refine_tol), int(refine_maxit)
+    o.precision = PRECISIONS[precision]
+    H = (C.c_void_p * cnt)()
+    S = (C.c_int * cnt)()
+    st = lib.ifmm_factor_batched(cnt, P, N, K, float(eps), int(leaf_size), int(rank), C.byref(o), int(threads),
+                                 _stream_handle(pts[0]), H, S)
+    solvers = [IFMMSolver._from_handle(lib, C.c_void_p(H[i]), int(N[i]), pts[i].device) if H[i] else None
+               for i in range(cnt)]
+    if st != 0:
+        for s in solvers:
+            if s is not None:
+                s.close()
+        raise IFMMError(st, "ifmm_factor_batched")
+    return solvers
+
+
+def solve_batched(solvers, rhs, threads: int = 0):
+    """ifmm_solve_batched: x_i = A_i^-1 b_i for every solver concurrently;
+    rhs: list of [N_i, nrhs] (or [N_i]) GPU tensors, one nrhs for all.
+    Returns the list of solutions; each solver's last_info is set."""
+    import torch
+    cnt = len(solvers)
+    cols = [s._cols(b) for s, b in zip(solvers, rhs)]
+    nrhs = int(cols[0][0].shape[0])
+    xs = [torch.empty_like(bt) for bt, _ in cols]
+    H = (C.c_void_p * cnt)(*[s._h.value for s in solvers])
+    B = (C.c_void_p * cnt)(*[bt.data_ptr() for bt, _ in cols])
+    X = (C.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+    I = (_SolveInfo * cnt)()
+    S = (C.c_int * cnt)()
+    st = solvers[0]._lib.ifmm_solve_batched(cnt, H, B, X, nrhs, int(threads), _stream_handle(cols[0][0]), I, S)
+    for i, s in enumerate(solvers):
+        s.last_info = {"iterations": I[i].iterations, "residual": I[i].residual,
+                       "history": list(I[i].history[:max(1, I[i].iterations + 1)]),
+                       "solve_ms": I[i].solve_ms, "status": S[i]}
+    if st != 0 and st != 4:
+        raise IFMMError(st, "ifmm_solve_batched")
+    return [x[0] if one else x.t() for x, (_, one) in zip(xs, cols)]

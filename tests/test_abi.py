@@ -63,3 +63,17 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     assert f(dummy, 4096, ctypes.byref(k), 0.0, 32, 16, None, None, ctypes.byref(h)) == 1
     lib.ifmm_solve.restype = ctypes.c_int
     assert lib.ifmm_solve(None, None, None, 1, None, None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_batched_entry_points_reject_bad_arguments():
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    f = lib.ifmm_factor_batched
+    f.restype = ctypes.c_int
+    assert f(0, None, None, None, ctypes.c_double(1e-8), 64, 36, None, 4, None, None, None) == 1  # count 0
+    assert f(3, None, None, None, ctypes.c_double(1e-8), 64, 36, None, 4, None, None, None) == 1  # null arrays
+    g = lib.ifmm_solve_batched
+    g.restype = ctypes.c_int
+    assert g(0, None, None, None, 1, 4, None, None, None) == 1
+    assert g(2, None, None, None, 1, 4, None, None, None) == 1
