@@ -489,6 +489,8 @@ def main():
     ap.add_argument("--paper-kernels", type=int, default=0, metavar="MAX_K",
                     help="only sweep the numerical section's three kernels up to N = MAX_K thousand "
                          "(p = 8, tolerance 1e-14, [-1,1]^2, FP64) and print that table as one JSON line")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 256-problem batched factor + solve and print its JSON")
     ap.add_argument("--copy-cal", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (3 times): the known-size reference "
                          "for scaling the HBM counters (FETCH_SIZE / WRITE_SIZE) of a counter run")
@@ -509,6 +511,9 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print("copy-cal: 3 x (read 1 GiB, write 1 GiB) by torch.mul", flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched()}))
         return
     if args.paper_kernels:
         res = paper_kernels(args.paper_kernels)

@@ -37,6 +37,7 @@ namespace {
 
 struct HipError {
   hipError_t e;
+  int line;  // where in this file the failing call is
 };
 struct NoMem {};
 struct BadArg {};
@@ -44,7 +45,7 @@ struct BadArg {};
 #define HIP_OK(x)                                      \
   do {                                                 \
     hipError_t e_ = (x);                               \
-    if (e_ != hipSuccess) throw HipError{e_};          \
+    if (e_ != hipSuccess) throw HipError{e_, __LINE__};          \
   } while (0)
 
 // Process-wide, stream-ordered cache of device blocks.  A factorisation
@@ -2452,7 +2453,10 @@ hipError_t scratch_ptr(void** out) {
 ifmm_status map_exc() {
   try {
     throw;
-  } catch (const HipError&) {
+  } catch (const HipError& h) {
+    // a HIP runtime error has no other way out through the status codes:
+    // name it on stderr (the call's line in this file and the runtime's text)
+    std::fprintf(stderr, "ifmm: HIP error %d (%s) at ifmm_host.hip:%d\n", (int)h.e, hipGetErrorString(h.e), h.line);
     return IFMM_EDEVICE;
   } catch (const NoMem&) {
     return IFMM_ENOMEM;
@@ -2489,7 +2493,9 @@ ifmm_status run_batched(int count, int threads, Job job) {
       return;
     }
     hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      std::fprintf(stderr, "ifmm: batched worker stream: HIP error %d (%s)\n", (int)e, hipGetErrorString(e));
       dev_err = 1;
       return;
     }
