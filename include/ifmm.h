@@ -22,7 +22,10 @@
  *  - b, x, y: [nrhs][n] column-major (leading dimension n), FP64, in the
  *    caller's point order.
  *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
- *    ifmm_factor and ifmm_solve synchronise that stream before returning.
+ *    ifmm_factor and ifmm_solve synchronise that stream before returning;
+ *    a caller may destroy a stream once the call that used it returned and
+ *    use the handle on other streams (ifmm_destroy releases the handle's
+ *    blocks on the stream of its last call: that one must still exist).
  *  - Every call returns a status; no exception crosses the ABI.  On error the
  *    outputs are left untouched except where stated.
  *  - A handle is not thread-safe; distinct handles are independent.
@@ -178,13 +181,16 @@ ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* str
  * Batched factorisation of `count` independent problems, each exactly as
  * ifmm_factor(points[i], n[i], &kernels[i], eps, leaf_size, rank, opt, ...)
  * would factor it (uneven sizes and different kernels allowed; Section
- * 4.2.2's decoupling of factor and solve).  `threads` host threads (0 = 4)
- * each drive problems in turn on a HIP stream of their own, so the launches
- * of different problems run concurrently on the device (each problem's
- * factorisation reads its new ranks back to the host once per colour phase;
- * concurrent problems fill the device while one waits).  The inputs must be
- * ready on `stream`; on return every factorisation is complete and the
- * handles use `stream`.  Results equal those of ifmm_factor bit for bit.
+ * 4.2.2's decoupling of factor and solve).  `threads` host threads (0 = 4,
+ * at most 64) each drive problems in turn on a worker stream of their own
+ * (created by the library once per device and worker, kept until the
+ * process ends), so the launches of different problems run concurrently on
+ * the device (each problem's factorisation reads its new ranks back to the
+ * host once per colour phase; concurrent problems fill the device while one
+ * waits).  The inputs must be ready on `stream`; on return every
+ * factorisation is complete and the handles use `stream`.  Results equal
+ * those of ifmm_factor bit for bit.  Concurrent batched calls share the
+ * worker streams.
  *   out[i], status[i]: host arrays of count entries (out[i] = NULL where
  *   status[i] != IFMM_OK).
  * Returns IFMM_OK if every problem succeeded, else the status of a failed

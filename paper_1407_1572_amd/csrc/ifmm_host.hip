@@ -80,7 +80,13 @@ class DevicePool {
         Blk b = free_[bi];
         if (hipStreamWaitEvent(s, b.ev, 0) != hipSuccess) {
           (void)hipGetLastError();
-          (void)hipEventSynchronize(b.ev);
+          // the event cannot be waited on (e.g. its stream was destroyed by
+          // its owner since): wait for the device instead
+          if (hipEventSynchronize(b.ev) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipDeviceSynchronize();
+            (void)hipGetLastError();
+          }
         }
         evfree_[dev].push_back(b.ev);
         b.ev = nullptr;
@@ -711,13 +717,20 @@ struct Arena {
   char* d[kSlots] = {};
   size_t cap[kSlots] = {};
   hipEvent_t ev[kSlots] = {};
+  bool pending[kSlots] = {};  // a copy out of the slot may still be in flight
   int cur = 0;
   void init() {
     for (int i = 0; i < kSlots; ++i) HIP_OK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
   }
+  // The stream the copies went to has been synchronised: no slot is in
+  // flight, and no later upload needs to query an event recorded on it (the
+  // caller may destroy that stream).
+  void settle() {
+    for (int i = 0; i < kSlots; ++i) pending[i] = false;
+  }
   void release(hipStream_t s) {
     for (int i = 0; i < kSlots; ++i) {
-      if (ev[i]) (void)hipEventSynchronize(ev[i]);
+      if (ev[i] && pending[i]) (void)hipEventSynchronize(ev[i]);
       pinned().put(h[i], cap[i]);
       dfree(s, d[i]);
       if (ev[i]) (void)hipEventDestroy(ev[i]);
@@ -730,7 +743,7 @@ struct Arena {
     cur = (cur + 1) % kSlots;
     const size_t need = blob.size();
     // the previous copy out of this buffer must be done before it is reused
-    HIP_OK(hipEventSynchronize(ev[cur]));
+    if (pending[cur]) HIP_OK(hipEventSynchronize(ev[cur]));
     if (need > cap[cur]) {
       pinned().put(h[cur], cap[cur]);
       dfree(s, d[cur]);
@@ -747,6 +760,7 @@ struct Arena {
     std::memcpy(h[cur], blob.data(), need);
     HIP_OK(hipMemcpyAsync(d[cur], h[cur], need, hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(ev[cur], s));
+    pending[cur] = true;
     return d[cur];
   }
 };
@@ -2177,6 +2191,7 @@ struct Plan final : ifmm_plan {
     factor();
     HIP_OK(hipEventRecord(ev_t[2], s));
     HIP_OK(hipStreamSynchronize(s));
+    arena.settle();
     // stream-timeline times: assembly ends when its last kernel does (the
     // host plans the factorisation meanwhile)
     float ms = 0.f;
@@ -2324,6 +2339,7 @@ struct Plan final : ifmm_plan {
     launch_scatter_rows(xout, n, d_perm, n, nrhs, x, n, s);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));
+    arena.settle();
     t_solve = now_ms() - t0;
     resolve_profile();
     if (info) {
@@ -2479,36 +2495,57 @@ namespace {
 // in order from a shared counter.  Every job ends with its stream
 // synchronised (ifmm_factor / ifmm_solve do), so the handles it touched are
 // handed back on `caller` once the worker is done with them.
+// Worker stream `idx` of device `dev`, created on first use and kept until
+// the process ends: block releases and descriptor uploads record events on
+// the stream a call ran on, and later calls may wait on those events; an
+// event must not outlive the stream it was last recorded on.
+hipError_t worker_stream(int dev, int idx, hipStream_t* out) {
+  static std::mutex mu;
+  static std::unordered_map<int, std::vector<hipStream_t>>* all =
+      new std::unordered_map<int, std::vector<hipStream_t>>();  // never destroyed
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<hipStream_t>& v = (*all)[dev];
+  while ((int)v.size() <= idx) {
+    hipStream_t st = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    v.push_back(st);
+  }
+  *out = v[idx];
+  return hipSuccess;
+}
+
+// Runs job(i, stream) for i = 0 .. count-1 on `threads` host threads, each
+// on a worker stream of its own (non-blocking, default priority), problems
+// taken in order from a shared counter.  Every job ends with its stream
+// synchronised (ifmm_factor / ifmm_solve do), so the handles it touched can
+// be handed back to the caller's stream.
 template <class Job>
 ifmm_status run_batched(int count, int threads, Job job) {
   if (threads <= 0) threads = 4;
-  threads = std::min(threads, count);
+  threads = std::min(std::min(threads, count), 64);
   std::atomic<int> next{0};
   std::atomic<int> dev_err{0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return IFMM_EDEVICE;
-  auto worker = [&]() {
-    if (hipSetDevice(dev) != hipSuccess) {
-      dev_err = 1;
-      return;
-    }
+  auto worker = [&](int t) {
     hipStream_t st = nullptr;
-    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    hipError_t e = hipSetDevice(dev);
+    if (e == hipSuccess) e = worker_stream(dev, t, &st);
     if (e != hipSuccess) {
-      std::fprintf(stderr, "ifmm: batched worker stream: HIP error %d (%s)\n", (int)e, hipGetErrorString(e));
+      std::fprintf(stderr, "ifmm: batched worker %d: HIP error %d (%s)\n", t, (int)e, hipGetErrorString(e));
       dev_err = 1;
       return;
     }
     for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) job(i, st);
-    (void)hipStreamDestroy(st);
   };
   std::vector<std::thread> pool;
   try {
-    for (int t = 1; t < threads; ++t) pool.emplace_back(worker);
+    for (int t = 1; t < threads; ++t) pool.emplace_back(worker, t);
   } catch (...) {
     // fewer threads: the ones started and this one take every problem
   }
-  worker();
+  worker(0);
   for (auto& t : pool) t.join();
   return dev_err ? IFMM_EDEVICE : IFMM_OK;
 }

@@ -78,3 +78,64 @@ def test_batched_equals_single_and_matches_oracle():
         assert res <= 2e-10 and err <= 1e-6
     for s in sv:
         s.close()
+
+
+def test_handles_outlive_the_streams_they_ran_on():
+    """A factor built on a stream the caller then destroys is solved, used
+    and destroyed on other streams (the library keeps no event of that
+    stream alive across calls); batched calls back to back reuse their
+    worker streams.  Regression: events recorded on a destroyed stream made
+    later calls fail with a HIP error."""
+    import ctypes
+
+    import torch
+    from paper_1407_1572_amd import IFMMSolver, factor_batched, solve_batched
+    from paper_1407_1572_amd.ifmm import _Kernel, _Options, _SolveInfo, load
+    _say("[gpu] handles outliving their streams")
+    dev = torch.device("cuda:0")
+    hip = ctypes.CDLL("libamdhip64.so")
+    lib = load()
+    pts = torch.from_numpy(workloads.uniform(4096, 1017)).to(dev)
+    b = torch.from_numpy(workloads.rhs(4096, 1, 2017)[:, 0].copy()).to(dev)
+    ref = IFMMSolver(pts, "exp", 0.1, "const", 1.01, 1e-8, 64, 36, refine_tol=1e-10)
+    xr = ref.solve(b)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        st = ctypes.c_void_p()
+        assert hip.hipStreamCreate(ctypes.byref(st)) == 0
+        k = _Kernel(1, 0.1, 1, 1.01, ctypes.c_void_p(0))
+        o = _Options()
+        o.refine_tol = 1e-10
+        h = ctypes.c_void_p()
+        assert lib.ifmm_factor(ctypes.c_void_p(pts.data_ptr()), 4096, ctypes.byref(k), 1e-8, 64, 36, ctypes.byref(o),
+                               st, ctypes.byref(h)) == 0
+        x = torch.empty_like(b)
+        info = _SolveInfo()
+        assert lib.ifmm_solve(h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), 1, st,
+                              ctypes.byref(info)) == 0
+        assert hip.hipStreamDestroy(st) == 0
+        x2 = torch.empty_like(b)
+        assert lib.ifmm_solve(h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x2.data_ptr()), 1, None,
+                              ctypes.byref(info)) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(x, xr) and torch.equal(x2, xr)
+        lib.ifmm_destroy(h)
+    ref.close()
+    # batched calls back to back
+    probs = _problems()[:6]
+    tp = [torch.from_numpy(p[0]).to(dev) for p in probs]
+    tb = [torch.from_numpy(p[1][:, :2].copy()).to(dev) for p in probs]
+    kw = dict(eps=1e-8, leaf_size=64, rank=36, refine_tol=1e-10, precision="fp32")
+    first = None
+    for rep in range(3):
+        sv = factor_batched(tp, [p[2] for p in probs], threads=3, **kw)
+        X = solve_batched(sv, tb, threads=3)
+        X2 = solve_batched(sv, tb, threads=2)
+        for a, c in zip(X, X2):
+            assert torch.equal(a, c)
+        if first is None:
+            first = [x.clone() for x in X]
+        for a, c in zip(X, first):
+            assert torch.equal(a, c)
+        for s in sv:
+            s.close()
