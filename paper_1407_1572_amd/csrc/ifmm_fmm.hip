@@ -4,8 +4,6 @@
 // row-sum diagonal and for refinement residuals.  Points are in tree order.
 #include "ifmm_internal.h"
 
-#include <algorithm>
-
 namespace ifmm {
 
 namespace {
@@ -200,75 +198,28 @@ __global__ void k_m2m(const double* __restrict__ E, int p, const double* __restr
   }
 }
 
-// M2L of one level for a tile of TS x TS clusters (one workgroup; TS = 4, or
-// the level's side at level 2): the multipole values of the tile's window
-// (the clusters whose children-of-parent's-neighbours lists reach into the
-// tile: TS + 4 on a side) are staged in LDS once per right-hand column; each
-// of the four waves takes the clusters of one parity class (ix mod 2,
-// iy mod 2), for which a window slot has the same offset (dx, dy) on every
-// lane, so a wave reads one node-to-node kernel block per slot; a lane holds
-// rows m = g, g + 16, ... of one cluster (g = lane / 4).  Each local value is
-// written once, summed over the slots in a fixed order.
-constexpr int M2L_TS = 4;
-constexpr int M2L_WAVE = 64;
-__global__ __launch_bounds__(256) void k_m2l_tile(int p, int k, const double* __restrict__ table,
-                                                  const double* __restrict__ W, double* __restrict__ G,
-                                                  int nrhs) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* win = reinterpret_cast<double*>(smem);  // [(TS + 4)^2][p2]
+__global__ void k_m2l(int p, int k, const double* __restrict__ table, const double* __restrict__ W,
+                      double* G, int nrhs) {
+  const int i = blockIdx.x;
   const int p2 = p * p;
+  const int ix = demorton_x(i), iy = demorton_y(i);
   const int nside = 1 << k;
-  const int ts = min(M2L_TS, nside), ws = ts + 4;
-  const int tiles_side = nside / ts;
-  const int tx = (int)blockIdx.x % tiles_side, ty = (int)blockIdx.x / tiles_side;
-  const int bx = tx * ts, by = ty * ts;
-  const int lane = threadIdx.x % M2L_WAVE, w = threadIdx.x / M2L_WAVE;
-  // this lane's cluster: parity class w, cluster q of the class, row group g
-  const int px = w & 1, py = w >> 1;
-  const int per = (ts / 2) * (ts / 2);  // clusters of one parity class in the tile
-  const int q = lane % 4, g = lane / 4;  // g: 0..15
-  const bool has = q < per;
-  const int ix = bx + px + 2 * (q % (ts / 2)), iy = by + py + 2 * (q / (ts / 2));
-  const int i = has ? morton2(ix, iy) : 0;
-  constexpr int RM = (kMaxP * kMaxP + 15) / 16;  // rows per lane, at most
-  for (int r = 0; r < nrhs; ++r) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < ws * ws * p2; e += blockDim.x) {
-      const int n = e % p2, cell = e / p2;
-      const int jx = bx - 2 + cell % ws, jy = by - 2 + cell / ws;
-      win[e] = (jx >= 0 && jy >= 0 && jx < nside && jy < nside)
-                   ? W[((size_t)morton2(jx, jy) * nrhs + r) * p2 + n] : 0.0;
-    }
-    __syncthreads();
-    double acc[RM];
-#pragma unroll
-    for (int j = 0; j < RM; ++j) acc[j] = 0.0;
-    // slots of the 6 x 6 window of the parent's neighbours' children,
-    // relative to this parity class: jx = ix + dx with dx = sx - 2 - px
+  const int x0 = 2 * (ix >> 1) - 2, y0 = 2 * (iy >> 1) - 2;
+  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
+    const int m = e % p2, r = e / p2;
+    double acc = 0.0;
     for (int sx = 0; sx < 6; ++sx)
       for (int sy = 0; sy < 6; ++sy) {
-        const int dx = sx - 2 - px, dy = sy - 2 - py;
-        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;  // near field: not M2L
+        const int jx = x0 + sx, jy = y0 + sy;
+        if (jx < 0 || jy < 0 || jx >= nside || jy >= nside) continue;
+        const int dx = jx - ix, dy = jy - iy;
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+        const int l = morton2(jx, jy);
         const double* T = table + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
-        const int jx = ix + dx, jy = iy + dy;
-        const bool ok = has && jx >= 0 && jy >= 0 && jx < nside && jy < nside;
-        const double* wl = win + ((jy - (by - 2)) * ws + (jx - (bx - 2))) * p2;
-        if (!ok) continue;
-        for (int n = 0; n < p2; ++n) {
-          const double v = wl[n];
-#pragma unroll
-          for (int j = 0; j < RM; ++j) {
-            const int m = g + 16 * j;
-            if (m < p2) acc[j] = fma(T[m + (size_t)n * p2], v, acc[j]);
-          }
-        }
+        const double* w = W + ((size_t)l * nrhs + r) * p2;
+        for (int n = 0; n < p2; ++n) acc = fma(T[m + (size_t)n * p2], w[n], acc);
       }
-    if (has)
-#pragma unroll
-      for (int j = 0; j < RM; ++j) {
-        const int m = g + 16 * j;
-        if (m < p2) G[((size_t)i * nrhs + r) * p2 + m] = acc[j];
-      }
+    G[((size_t)i * nrhs + r) * p2 + m] = acc;
   }
 }
 
@@ -449,10 +400,7 @@ void launch_m2m(const double* E, int p, int nc_parent, const double* Wc, double*
 
 void launch_m2l(int p, int k, const double* table, const double* W, double* G, int nrhs,
                 hipStream_t s) {
-  const int nside = 1 << k, ts = std::min(M2L_TS, nside), ws = ts + 4;
-  const int tiles = (nside / ts) * (nside / ts);
-  const size_t lds = sizeof(double) * (size_t)ws * ws * p * p;
-  hipLaunchKernelGGL(k_m2l_tile, dim3(tiles), dim3(256), lds, s, p, k, table, W, G, nrhs);
+  hipLaunchKernelGGL(k_m2l, dim3(1 << (2 * k)), dim3(64), 0, s, p, k, table, W, G, nrhs);
 }
 
 void launch_l2l(const double* E, int p, int nc_parent, const double* Gp, double* Gc, int nrhs,
