@@ -2528,7 +2528,7 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
 void launch_gj_reg(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t s) {
   if (nd <= 0 || max_m <= 0) return;
   if (max_m <= 64) hipLaunchKernelGGL((k_gj_reg<8, 8, 8, 8>), dim3(nd), dim3(64), 0, s, d, st);
-  else if (max_m <= 128) hipLaunchKernelGGL((k_gj_reg<16, 16, 8, 8>), dim3(nd), dim3(256), 0, s, d, st);
+  else if (max_m <= 128) hipLaunchKernelGGL((k_gj_reg<32, 16, 4, 8>), dim3(nd), dim3(512), 0, s, d, st);
   else if (max_m <= kGjRegMax) hipLaunchKernelGGL((k_gj_reg<32, 16, 6, 12>), dim3(nd), dim3(512), 0, s, d, st);
 }
 
