@@ -8,6 +8,8 @@ namespace ifmm {
 
 namespace {
 
+typedef double md4 __attribute__((ext_vector_type(4)));
+
 // K(r) of the built-in kernels (kind: ifmm_kernel_kind; ell is the length
 // scale of the exp kernels and the parameter a of the numerical section's
 // three singular kernels, each continuous at r = a with K(a) = 1 and with the
@@ -198,28 +200,118 @@ __global__ void k_m2m(const double* __restrict__ E, int p, const double* __restr
   }
 }
 
-__global__ void k_m2l(int p, int k, const double* __restrict__ table, const double* __restrict__ W,
-                      double* G, int nrhs) {
-  const int i = blockIdx.x;
-  const int p2 = p * p;
-  const int ix = demorton_x(i), iy = demorton_y(i);
-  const int nside = 1 << k;
-  const int x0 = 2 * (ix >> 1) - 2, y0 = 2 * (iy >> 1) - 2;
-  for (int e = threadIdx.x; e < p2 * nrhs; e += blockDim.x) {
-    const int m = e % p2, r = e / p2;
-    double acc = 0.0;
-    for (int sx = 0; sx < 6; ++sx)
-      for (int sy = 0; sy < 6; ++sy) {
-        const int jx = x0 + sx, jy = y0 + sy;
-        if (jx < 0 || jy < 0 || jx >= nside || jy >= nside) continue;
-        const int dx = jx - ix, dy = jy - iy;
-        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-        const int l = morton2(jx, jy);
-        const double* T = table + (size_t)((dx + 3) * 7 + (dy + 3)) * p2 * p2;
-        const double* w = W + ((size_t)l * nrhs + r) * p2;
-        for (int n = 0; n < p2; ++n) acc = fma(T[m + (size_t)n * p2], w[n], acc);
+// M2L of one level on the matrix cores (FP64): G_i = sum over the far-field
+// slots of the 6 x 6 window of T(dx, dy) W_l, with T the node-to-node kernel
+// block of offset (dx, dy) = (jx - ix, jy - iy).  One workgroup per 8 x 8
+// block of clusters; wave w takes the 16 clusters of parity class
+// (w & 1, w >> 1), laid out 4 x 4 with stride 2, so that every slot has the
+// same offset for all 16 and the slot is one product (p^2 x p^2) x (p^2 x 16)
+// by v_mfma_f64_16x16x4 (A: T read from global memory, L2-resident; B: the
+// multipoles of the block's 12 x 12 window, staged in LDS with zeros outside
+// the grid).  Output rows are split in 16-row tiles (RT of them), the inner
+// dimension in steps of 4.  The A operand of the next far-field slot is
+// loaded into a second register set while the current slot's products run
+// (DB; for p <= 7, where two sets fit the registers).
+template <int P, bool DB>
+__device__ inline void m2l_wave(const double* __restrict__ table, const double* __restrict__ win, int px, int py,
+                                int c, int kq, md4 (&acc)[(P * P + 15) / 16]) {
+  constexpr int P2 = P * P, RT = (P2 + 15) / 16, KS = (P2 + 3) / 4, PS = P2 + 1;
+  // this lane's cluster in the window: (2 + px + 2 (c % 4), 2 + py + 2 (c / 4))
+  const double* w0 = win + ((2 + py + 2 * (c / 4)) * 12 + (2 + px + 2 * (c % 4))) * PS;
+  auto near = [&](int s) {
+    const int dx = s / 6 - 2 - px, dy = s % 6 - 2 - py;
+    return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+  };
+  auto next_far = [&](int s) {  // 36 when none is left
+    do ++s;
+    while (s < 36 && near(s));
+    return s;
+  };
+  auto load = [&](double (&buf)[RT][KS], int s) {
+    const int dx = s / 6 - 2 - px, dy = s % 6 - 2 - py;
+    const double* T = table + (size_t)((dx + 3) * 7 + (dy + 3)) * P2 * P2;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int m = 16 * t + c, n = 4 * ks + kq;
+        buf[t][ks] = (m < P2 && n < P2) ? T[m + n * P2] : 0.0;
       }
-    G[((size_t)i * nrhs + r) * p2 + m] = acc;
+  };
+  auto comp = [&](const double (&buf)[RT][KS], int s) {
+    const int dx = s / 6 - 2 - px, dy = s % 6 - 2 - py;
+    const double* wl = w0 + (dy * 12 + dx) * PS;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int n = 4 * ks + kq;
+      const double b = n < P2 ? wl[n] : 0.0;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[t][ks], b, acc[t], 0, 0, 0);
+    }
+  };
+  int s = next_far(-1);
+  if constexpr (DB) {
+    double ta[RT][KS], tb[RT][KS];
+    load(ta, s);
+    while (true) {
+      const int s1 = next_far(s);
+      load(tb, s1 < 36 ? s1 : s);  // unconditional: no branch between the loads and their use
+      comp(ta, s);
+      if (s1 >= 36) break;
+      const int s2 = next_far(s1);
+      load(ta, s2 < 36 ? s2 : s1);
+      comp(tb, s1);
+      if (s2 >= 36) break;
+      s = s2;
+    }
+  } else {
+    for (; s < 36; s = next_far(s)) {
+      double ta[RT][KS];
+      load(ta, s);
+      comp(ta, s);
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l(int k, const double* __restrict__ table,
+                                             const double* __restrict__ W, double* __restrict__ G,
+                                             int nrhs) {
+  constexpr int P2 = P * P, RT = (P2 + 15) / 16, PS = P2 + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* win = reinterpret_cast<double*>(smem);  // [12 * 12][PS]
+  const int nside = 1 << k;
+  const int nbs = nside >= 8 ? nside / 8 : 1;
+  const int bx = 8 * ((int)blockIdx.x % nbs), by = 8 * ((int)blockIdx.x / nbs);
+  const int lane = threadIdx.x % 64;  // 64-wide waves
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int px = w & 1, py = w >> 1;
+  const int c = lane % 16, kq = lane / 16;
+  const int ix = bx + px + 2 * (c % 4), iy = by + py + 2 * (c / 4);
+  const bool live = ix < nside && iy < nside;
+  for (int r = 0; r < nrhs; ++r) {
+    if (r) __syncthreads();
+    for (int e = threadIdx.x; e < 144 * P2; e += blockDim.x) {
+      const int n = e % P2, cell = e / P2;
+      const int jx = bx - 2 + cell % 12, jy = by - 2 + cell / 12;
+      win[cell * PS + n] = (jx >= 0 && jy >= 0 && jx < nside && jy < nside)
+                               ? W[((size_t)morton2(jx, jy) * nrhs + r) * P2 + n] : 0.0;
+    }
+    __syncthreads();
+    md4 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = md4{0, 0, 0, 0};
+    m2l_wave<P, (P <= 7)>(table, win, px, py, c, kq, acc);
+    if (live) {
+      double* g = G + ((size_t)morton2(ix, iy) * nrhs + r) * P2;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * t + 4 * v + kq;  // row of output value v of this lane
+          if (m < P2) g[m] = acc[t][v];
+        }
+    }
   }
 }
 
@@ -398,9 +490,27 @@ void launch_m2m(const double* E, int p, int nc_parent, const double* Wc, double*
   hipLaunchKernelGGL(k_m2m, dim3(nc_parent), dim3(64), 0, s, E, p, Wc, Wp, nrhs);
 }
 
+template <int P>
+void m2l_go(int k, const double* table, const double* W, double* G, int nrhs, hipStream_t s) {
+  const int nside = 1 << k, nbs = nside >= 8 ? nside / 8 : 1;
+  const size_t lds = (size_t)144 * (P * P + 1) * sizeof(double);
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_m2l<P>));
+  hipLaunchKernelGGL(k_m2l<P>, dim3(nbs * nbs), dim3(256), lds, s, k, table, W, G, nrhs);
+}
+
 void launch_m2l(int p, int k, const double* table, const double* W, double* G, int nrhs,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_m2l, dim3(1 << (2 * k)), dim3(64), 0, s, p, k, table, W, G, nrhs);
+  if (k < 2 || nrhs <= 0) return;
+  switch (p) {
+    case 1: m2l_go<1>(k, table, W, G, nrhs, s); break;
+    case 2: m2l_go<2>(k, table, W, G, nrhs, s); break;
+    case 3: m2l_go<3>(k, table, W, G, nrhs, s); break;
+    case 4: m2l_go<4>(k, table, W, G, nrhs, s); break;
+    case 5: m2l_go<5>(k, table, W, G, nrhs, s); break;
+    case 6: m2l_go<6>(k, table, W, G, nrhs, s); break;
+    case 7: m2l_go<7>(k, table, W, G, nrhs, s); break;
+    default: m2l_go<8>(k, table, W, G, nrhs, s); break;
+  }
 }
 
 void launch_l2l(const double* E, int p, int nc_parent, const double* Gp, double* Gc, int nrhs,

@@ -415,6 +415,9 @@ void launch_p2m(const double* pts, const int* leaf_start, const int* leaf_n, int
                 int nrhs, double* W, hipStream_t s);
 void launch_m2m(const double* E, int p, int nc_parent, const double* Wc, double* Wp, int nrhs,
                 hipStream_t s);
+// Raise a kernel's dynamic LDS limit to the 160 KiB of a gfx950 CU (once per
+// kernel; thread-safe).
+void allow_lds(const void* fn);
 void launch_m2l(int p, int k, const double* table, const double* W, double* G, int nrhs,
                 hipStream_t s);
 void launch_l2l(const double* E, int p, int nc_parent, const double* Gp, double* Gc, int nrhs,

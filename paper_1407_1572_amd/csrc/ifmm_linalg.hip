@@ -2175,13 +2175,13 @@ void add_go(const AddDesc* d, int nd, int tm, int tn, hipStream_t s) {
   hipLaunchKernelGGL((k_add<TA, TC>), dim3(nd, tm * tn), dim3(WG), 0, s, d, tm);
 }
 
-// Raise the dynamic LDS limit of a kernel once (gfx950: 160 KiB per CU).
 // Raise a kernel's dynamic-LDS limit to the CU's 160 KiB once, before its
 // first launch that needs more than the default 64 KiB.  Thread-safe (batched
 // factorisations launch from several host threads) and monotonic: the limit
 // only bounds what a launch may ask for, the LDS actually allocated (and the
 // occupancy) is the launch's own request.
 constexpr size_t kLdsLimit = 160 * 1024;
+}  // namespace
 void allow_lds(const void* fn) {
   static std::mutex mu;
   static std::unordered_set<const void*> done;
@@ -2190,6 +2190,7 @@ void allow_lds(const void* fn) {
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit) != hipSuccess)
     (void)hipGetLastError();  // the launch reports a real shortfall
 }
+namespace {
 
 // Chunk rows of the stacked-R kernels and their LDS bytes for rank r: up to
 // max_chunk rows, within 64 KiB when 128 rows fit there (several workgroups
