@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <atomic>
@@ -196,14 +197,16 @@ class PinnedPool {
   char* get(size_t bytes, size_t* got) {
     {
       std::lock_guard<std::mutex> g(mu_);
-      for (size_t i = 0; i < free_.size(); ++i)
-        if (free_[i].second >= bytes) {
-          auto b = free_[i];
-          free_[i] = free_.back();
-          free_.pop_back();
-          *got = b.second;
-          return b.first;
-        }
+      size_t best = free_.size();
+      for (size_t i = 0; i < free_.size(); ++i)  // the smallest that fits
+        if (free_[i].second >= bytes && (best == free_.size() || free_[i].second < free_[best].second)) best = i;
+      if (best < free_.size()) {
+        auto b = free_[best];
+        free_[best] = free_.back();
+        free_.pop_back();
+        *got = b.second;
+        return b.first;
+      }
     }
     char* p = nullptr;
     if (hipHostMalloc(reinterpret_cast<void**>(&p), bytes) != hipSuccess) {
@@ -216,7 +219,7 @@ class PinnedPool {
   void put(char* p, size_t bytes) {
     if (!p) return;
     std::lock_guard<std::mutex> g(mu_);
-    if (free_.size() >= 32) {
+    if (free_.size() >= 96) {
       (void)hipHostFree(p);
       return;
     }
@@ -243,6 +246,71 @@ void dfree(hipStream_t s, T*& p) {
 }
 
 inline int rup(int a, int b) { return (a + b - 1) / b * b; }
+// Host-side phase clock of the factorisation (IFMM_TRACE_HOST=1 in the
+// environment): exclusive wall time per planning phase, a nested phase
+// pausing the one that encloses it, printed to stderr when the factorisation
+// ends.  Off, it costs one branch per scope.
+constexpr int kHcLevels = 13;  // tree levels 0..12
+enum HostPhase { HP_TREE, HP_ASSEMBLY, HP_RECORDS, HP_INVPLAN, HP_COMPRESS_PRE, HP_WEIGHTS, HP_RUN, HP_WAIT,
+                 HP_COMPRESS_POST, HP_DEFERRED, HP_TRANSITION, HP_TOP, HP_SOLVE_PLAN, HP_COUNT };
+struct HostClock {
+  using Clock = std::chrono::steady_clock;
+  bool on = false;
+  int cur = -1;
+  Clock::time_point last;
+  int level = 0;  // tree level being factored (0: outside the levels)
+  double sec[HP_COUNT][kHcLevels] = {};
+  long calls[HP_COUNT] = {};
+  double upload_bytes[kHcLevels] = {};
+  void charge(Clock::time_point t) {
+    if (cur >= 0) sec[cur][level] += std::chrono::duration<double>(t - last).count();
+    last = t;
+  }
+  int enter(int id) {
+    const int prev = cur;
+    if (!on) return prev;
+    charge(Clock::now());
+    cur = id;
+    ++calls[id];
+    return prev;
+  }
+  void leave(int prev) {
+    if (!on) return;
+    charge(Clock::now());
+    cur = prev;
+  }
+  void print(int64_t n) const {
+    if (!on) return;
+    static const char* names[HP_COUNT] = {"tree",        "assembly",     "records",    "inverse-plan", "compress-pre",
+                                          "weights",     "upload+launch", "rank-wait", "compress-post", "work-counts",
+                                          "transition",  "top",          "solve-plan"};
+    double tot = 0;
+    for (const auto& row : sec)
+      for (double v : row) tot += v;
+    std::fprintf(stderr, "ifmm host phases (N = %lld): %.2f ms; per level (0: outside the levels)\n", (long long)n,
+                 1e3 * tot);
+    for (int i = 0; i < HP_COUNT; ++i) {
+      if (!calls[i]) continue;
+      double t = 0;
+      for (double v : sec[i]) t += v;
+      std::fprintf(stderr, "  %-14s %9.3f ms %6ld |", names[i], 1e3 * t, calls[i]);
+      for (int k = 0; k < kHcLevels; ++k)
+        if (sec[i][k] > 0) std::fprintf(stderr, " %d:%.2f", k, 1e3 * sec[i][k]);
+      std::fprintf(stderr, "\n");
+    }
+    std::fprintf(stderr, "  descriptor MB  |");
+    for (int k = 0; k < kHcLevels; ++k)
+      if (upload_bytes[k] > 0) std::fprintf(stderr, " %d:%.2f", k, upload_bytes[k] / 1e6);
+    std::fprintf(stderr, "\n");
+  }
+};
+struct PhaseScope {
+  HostClock& c;
+  int prev;
+  PhaseScope(HostClock& hc, int id) : c(hc), prev(hc.enter(id)) {}
+  ~PhaseScope() { c.leave(prev); }
+};
+
 constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
 // Largest stored near field of the FMM product (bytes); beyond it the
 // product evaluates the near-field kernel on the fly.
@@ -383,14 +451,51 @@ inline double tri_sum(double n, double m, double K) {
   return K * n * m - (n + m) * K * (K - 1) / 2 + (K - 1) * K * (2 * K - 1) / 6;
 }
 
+// Descriptor bytes of a stage, written straight into pinned host memory from
+// the pool (no staging copy before the upload; growth keeps the contents,
+// new bytes are not initialised).  Upload hands the buffer to the arena
+// slot that copies it, taking the slot's previous (idle) buffer in exchange.
+struct Blob {
+  char* p = nullptr;
+  size_t n = 0, cap = 0;
+  Blob() = default;
+  Blob(const Blob&) = delete;
+  Blob& operator=(const Blob&) = delete;
+  Blob(Blob&& o) noexcept : p(o.p), n(o.n), cap(o.cap) { o.p = nullptr, o.n = o.cap = 0; }
+  Blob& operator=(Blob&& o) noexcept {
+    std::swap(p, o.p);
+    std::swap(n, o.n);
+    std::swap(cap, o.cap);
+    return *this;
+  }
+  ~Blob() {
+    if (p) pinned().put(p, cap);
+  }
+  size_t size() const { return n; }
+  char* data() { return p; }
+  const char* data() const { return p; }
+  void clear() { n = 0; }
+  void resize(size_t m) {
+    if (m > cap) {
+      size_t got = 0;
+      char* q = pinned().get(std::max(m, std::max(2 * cap, (size_t)64 << 10)), &got);
+      if (n) std::memcpy(q, p, n);
+      if (p) pinned().put(p, cap);
+      p = q;
+      cap = got;
+    }
+    n = m;
+  }
+};
+
 struct Stage {
-  std::vector<char> blob;
+  Blob blob;
   std::vector<Op> ops;
   double flops = 0.0;
   size_t push(const void* p, size_t n) {
     size_t off = (blob.size() + 63) & ~size_t(63);
     blob.resize(off + n);
-    std::memcpy(blob.data() + off, p, n);
+    if (n) std::memcpy(blob.data() + off, p, n);
     return off;
   }
   void op(Op o, int ty) {
@@ -715,7 +820,7 @@ struct Arena {
   static constexpr int kSlots = 16;
   char* h[kSlots] = {};
   char* d[kSlots] = {};
-  size_t cap[kSlots] = {};
+  size_t hcap[kSlots] = {}, dcap[kSlots] = {};
   hipEvent_t ev[kSlots] = {};
   bool pending[kSlots] = {};  // a copy out of the slot may still be in flight
   int cur = 0;
@@ -731,36 +836,38 @@ struct Arena {
   void release(hipStream_t s) {
     for (int i = 0; i < kSlots; ++i) {
       if (ev[i] && pending[i]) (void)hipEventSynchronize(ev[i]);
-      pinned().put(h[i], cap[i]);
+      pinned().put(h[i], hcap[i]);
       dfree(s, d[i]);
       if (ev[i]) (void)hipEventDestroy(ev[i]);
       h[i] = d[i] = nullptr;
-      cap[i] = 0;
+      hcap[i] = dcap[i] = 0;
       ev[i] = nullptr;
     }
   }
-  char* upload(const std::vector<char>& blob, hipStream_t s) {
-    cur = (cur + 1) % kSlots;
+  // Copies the blob to the device; returns the device address and, in
+  // *host, where the bytes now are on the host (the slot took the blob's
+  // buffer; the blob is left empty, holding the slot's previous buffer).
+  char* upload(Blob& blob, hipStream_t s, const char** host) {
     const size_t need = blob.size();
-    // the previous copy out of this buffer must be done before it is reused
+    *host = blob.data();
+    if (need == 0) return nullptr;
+    cur = (cur + 1) % kSlots;
+    // the previous copy out of this slot must be done before it is reused
     if (pending[cur]) HIP_OK(hipEventSynchronize(ev[cur]));
-    if (need > cap[cur]) {
-      pinned().put(h[cur], cap[cur]);
+    if (need > dcap[cur]) {
+      const size_t c = std::max(std::max(need, 2 * dcap[cur]), (size_t)1 << 20);
       dfree(s, d[cur]);
-      size_t c = std::max(need, 2 * cap[cur]);
-      c = std::max<size_t>(c, (size_t)1 << 20);
-      h[cur] = nullptr;
-      d[cur] = nullptr;
-      cap[cur] = 0;
-      size_t got = 0;
-      h[cur] = pinned().get(c, &got);
-      d[cur] = dalloc<char>(s, got);
-      cap[cur] = got;
+      dcap[cur] = 0;
+      d[cur] = dalloc<char>(s, c);
+      dcap[cur] = c;
     }
-    std::memcpy(h[cur], blob.data(), need);
+    std::swap(h[cur], blob.p);
+    std::swap(hcap[cur], blob.cap);
+    blob.n = 0;
     HIP_OK(hipMemcpyAsync(d[cur], h[cur], need, hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(ev[cur], s));
     pending[cur] = true;
+    *host = h[cur];
     return d[cur];
   }
 };
@@ -955,6 +1062,7 @@ struct Plan final : ifmm_plan {
   double* d_top = nullptr;
   Status* d_status = nullptr;
   Arena arena;
+  HostClock hc;
   Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg, wsTab;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
@@ -1024,6 +1132,7 @@ struct Plan final : ifmm_plan {
     }
   }
   void run_deferred() {
+    PhaseScope ps_(hc, HP_DEFERRED);
     for (auto& f : deferred) f();
     deferred.clear();
   }
@@ -1045,15 +1154,20 @@ struct Plan final : ifmm_plan {
   }
 
   void run(Stage& st) {
+    PhaseScope ps_(hc, HP_RUN);
     if (st.empty()) return;
+    if (hc.on) hc.upload_bytes[hc.level] += (double)st.blob.size();
     factor_flops += st.flops;
-    char* d = arena.upload(st.blob, s);
-    launch_ops(st, d);
+    const char* hb = nullptr;
+    char* d = arena.upload(st.blob, s, &hb);
+    launch_ops(st, d, hb);
     st.clear();
   }
 
-  // Launches the ops of a stage whose blob is at device address d.
-  void launch_ops(const Stage& st, char* d) {
+  // Launches the ops of a stage whose blob is at device address d and host
+  // address hb (default: the stage's own blob).
+  void launch_ops(const Stage& st, char* d, const char* hb = nullptr) {
+    if (!hb) hb = st.blob.data();
     for (const Op& op : st.ops) {
       hipEvent_t ea = nullptr, eb = nullptr;
       const bool tm = profile && timed(op_family(op));
@@ -1085,7 +1199,7 @@ struct Plan final : ifmm_plan {
           break;
         case OP_ROWCP: {
           Stage::RowCopy a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           a.start = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.start) - 1));
           a.cnt = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.cnt) - 1));
           if (a.to_blocks)
@@ -1096,7 +1210,7 @@ struct Plan final : ifmm_plan {
         }
         case OP_FILLCP: {
           FillCopy a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           a.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(a.rec) - 1));
           a.touch = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.touch) - 1));
           launch_fill_copy(a, op.ty, s);
@@ -1104,7 +1218,7 @@ struct Plan final : ifmm_plan {
         }
         case OP_TXFORM: {
           TouchXform a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           auto rebase = [&](const int*& p) {
             if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
           };
@@ -1119,20 +1233,20 @@ struct Plan final : ifmm_plan {
         }
         case OP_SOLVE: {
           SolveArgs a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           launch_solve(a, op.count, reinterpret_cast<double*>(op.off2), op.a, op.ty, s);
           break;
         }
         case OP_M2LASM: {
           M2LAssemble a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           a.r = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.r) - 1));
           launch_m2l_assemble(a, op.ty, s);
           break;
         }
         case OP_TRANS: {
           TransArgs a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           auto rebase = [&](const int*& p) {
             if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
           };
@@ -1144,7 +1258,7 @@ struct Plan final : ifmm_plan {
         }
         case OP_ELIM: {
           ElimArgs a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           a.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(a.rec) - 1));
           if (a.rk) a.rk = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(a.rk) - 1));
           launch_elim(a, op.count, op.a, op.b, op.ty, s);
@@ -1152,7 +1266,7 @@ struct Plan final : ifmm_plan {
         }
         case OP_WSTACK: {
           WinStack a;
-          std::memcpy(&a, st.blob.data() + op.off, sizeof(a));
+          std::memcpy(&a, hb + op.off, sizeof(a));
           auto rebase = [&](const int*& p) {
             if (p) p = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(p) - 1));
           };
@@ -1195,6 +1309,7 @@ struct Plan final : ifmm_plan {
   // each, in launches of one size class (the class sets the workgroup
   // shape); larger ones by panels.
   void plan_inverse(Stage& st, const std::vector<InvDesc>& all) {
+    PhaseScope ps_(hc, HP_INVPLAN);
     if (all.empty()) return;
     std::vector<InvDesc> cls[3], big;
     for (const auto& d : all) {
@@ -1214,6 +1329,7 @@ struct Plan final : ifmm_plan {
   // Points (original order, device) -> tree order on the device; the leaf
   // populations come back to the host for planning.
   void build_tree(const double* d_points_in) {
+    PhaseScope ps_(hc, HP_TREE);
     kappa = 2;
     while ((int64_t)leaf * (1LL << (2 * kappa)) < N) ++kappa;
     if (kappa > kMaxLevels) throw BadArg{};
@@ -1308,6 +1424,7 @@ struct Plan final : ifmm_plan {
 
   // --------------------------------------------------------------- assembly
   void assemble(const double* d_points_in) {
+    PhaseScope ps_(hc, HP_ASSEMBLY);
     build_tree(d_points_in);
     const int nleaf = 1 << (2 * kappa);
     d_nbr9_leaf = dalloc<int>(s, (size_t)nleaf * 9);
@@ -1504,6 +1621,7 @@ struct Plan final : ifmm_plan {
   // to out + t * rpad^2 (or out + ids[t] * rpad^2 when by_id).
   // With ext, the launches are appended to that stage (run by the caller).
   void weights(int k, const std::vector<int>& ids, T* out, bool by_id, Stage* ext = nullptr) {
+    PhaseScope ps_(hc, HP_WEIGHTS);
     Level<T>& L = lv[k];
     const int nt = (int)ids.size();
     if (nt == 0) return;
@@ -1568,10 +1686,18 @@ struct Plan final : ifmm_plan {
     plan.assign(kappa + 1, std::vector<std::vector<Elim>>(9));
     erec.assign(kappa + 1, std::vector<std::vector<ElimRec>>(9));
     for (int k = kappa; k >= 2; --k) {
+      if (hc.on) {
+        hc.charge(HostClock::Clock::now());
+        hc.level = k;
+      }
       for (int c = 0; c < 9; ++c) phase(k, c);
       Level<T>& L = lv[k];
       for (int i = 0; i < L.nc; ++i) max_rank = std::max(max_rank, L.r[i]);
       if (k > 2) transition(k);
+    }
+    if (hc.on) {
+      hc.charge(HostClock::Clock::now());
+      hc.level = 0;
     }
     top();
     // the records drive the solve sweeps
@@ -1625,6 +1751,7 @@ struct Plan final : ifmm_plan {
   }
 
   void phase(int k, int c) {
+    PhaseScope ps_(hc, HP_RECORDS);
     Level<T>& L = lv[k];
     std::vector<Elim>& E = plan[k][c];
     for (int i = 0; i < L.nc; ++i) {
@@ -1737,6 +1864,7 @@ struct Plan final : ifmm_plan {
   // pre: launches not yet run (the batch's elimination); run before the first
   // rank read-back.
   void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, FpFn Fp, Stage& pre) {
+    PhaseScope ps_(hc, HP_COMPRESS_PRE);
     Level<T>& L = lv[k];
     struct Touch {
       int q, b, sq;
@@ -1821,8 +1949,12 @@ struct Plan final : ifmm_plan {
       st.rrqr(rq);
       run(st);
       run_deferred();
-      HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
+      {
+        PhaseScope w(hc, HP_WAIT);
+        HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost,
+                              s));
+        HIP_OK(hipStreamSynchronize(s));
+      }
       for (int t = t0; t < t1; ++t) {
         const int nq = L.n[touch[t].q];
         rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
@@ -1835,6 +1967,7 @@ struct Plan final : ifmm_plan {
       }
     }
     // basis change T = U^^T U (the column side uses S = T^T)
+    PhaseScope post(hc, HP_COMPRESS_POST);
     Stage st;
     std::vector<GemmDesc> g;
     for (int t = 0; t < nt; ++t) {
@@ -1919,6 +2052,7 @@ struct Plan final : ifmm_plan {
   // Level k -> k-1: particles are the children's multipoles; P2P from their
   // M2L; parent bases re-orthonormalised (z_P -> Ru z_P, y_P = Rv^T y^_P).
   void transition(int k) {
+    PhaseScope ps_(hc, HP_TRANSITION);
     Level<T>& C = lv[k];
     Level<T>& L = lv[k - 1];
     int nm = 0;
@@ -1995,6 +2129,7 @@ struct Plan final : ifmm_plan {
   }
 
   void top() {
+    PhaseScope ps_(hc, HP_TOP);
     Level<T>& L = lv[2];
     top_ids.clear();
     top_off.assign(1, 0);
@@ -2041,6 +2176,7 @@ struct Plan final : ifmm_plan {
 
   // x (tree order, ld N) = A^-1 b (tree order, ld N)
   SolvePlan& solve_plan(int nrhs) {
+    PhaseScope ps_(hc, HP_SOLVE_PLAN);
     std::vector<size_t> ob(kappa + 1), oc(kappa + 1);
     size_t tot = 0;
     for (int k = 2; k <= kappa; ++k) {
@@ -2183,6 +2319,8 @@ struct Plan final : ifmm_plan {
 
   // ---------------------------------------------------------- entry points
   void build(const double* points) override {
+    const char* tr = std::getenv("IFMM_TRACE_HOST");
+    hc.on = tr && tr[0] && tr[0] != '0';
     arena.init();
     for (hipEvent_t& e : ev_t) HIP_OK(hipEventCreate(&e));
     HIP_OK(hipEventRecord(ev_t[0], s));
@@ -2199,6 +2337,7 @@ struct Plan final : ifmm_plan {
     t_assembly = ms;
     HIP_OK(hipEventElapsedTime(&ms, ev_t[1], ev_t[2]));
     t_factor = ms;
+    hc.print(N);
   }
 
   void matvec(const double* x, double* y, int nrhs) override {
