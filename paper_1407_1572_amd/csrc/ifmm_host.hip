@@ -536,23 +536,44 @@ struct Stage {
   }
   // Unpivoted QRs, staged in LDS (off2 = bytes) when the matrix fits
   // kQrLdsBytes, else in place.
+  // Matrices of at most 64 columns whose rows fit one lane's registers go to
+  // the one-wave kernel (op.b = row class), by row class; the rest to the
+  // workgroup kernel, staged in LDS where they fit (op.off2 = LDS bytes).
   void qr(const std::vector<QrDesc>& all) {
     by_type(all, [&](const std::vector<QrDesc>& byt, int ty) {
-      std::vector<QrDesc> grp[2];
-      for (const auto& d : byt) grp[qr_lds_bytes(d.n, d.m, ty) <= kQrLdsBytes ? 1 : 0].push_back(d);
-      for (int g = 0; g < 2; ++g) {
-        const auto& v = grp[g];
-        if (v.empty()) continue;
-        double f = 0, by = 0;
-        size_t lds = 0;
+      std::vector<QrDesc> grp[2], wave[5];
+      for (const auto& d : byt) {
+        const int nr = qr_wave_rows(d.n, d.m, ty);
+        if (nr > 0) wave[nr / 32].push_back(d);
+        else grp[qr_lds_bytes(d.n, d.m, ty) <= kQrLdsBytes ? 1 : 0].push_back(d);
+      }
+      auto work = [&](const std::vector<QrDesc>& v, double& f, double& by, size_t& lds, int& kmax) {
         for (const auto& d : v) {
           const double K = std::min(d.n, d.m);
           f += 4.0 * d.n * d.m * K - 2.0 * K * K * (d.n + d.m) + 4.0 / 3.0 * K * K * K  // factor
                + 4.0 * d.n * K * K - 2.0 * K * K * K;                                   // form Q
           by += esz(ty) * (2.0 * d.n * d.m + K * d.m);
           lds = std::max(lds, qr_lds_bytes(d.n, d.m, ty));
+          kmax = std::max(kmax, std::min(d.n, d.m));
         }
         flops += f;
+      };
+      for (int c = 1; c <= 4; ++c) {
+        const auto& v = wave[c];
+        if (v.empty()) continue;
+        double f = 0, by = 0;
+        size_t lds = 0;
+        int kmax = 0;
+        work(v, f, by, lds, kmax);
+        op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), 0, (int)v.size(), kmax, 32 * c, f, by}, ty);
+      }
+      for (int g = 0; g < 2; ++g) {
+        const auto& v = grp[g];
+        if (v.empty()) continue;
+        double f = 0, by = 0;
+        size_t lds = 0;
+        int kmax = 0;
+        work(v, f, by, lds, kmax);
         op({OP_QR, push(v.data(), v.size() * sizeof(QrDesc)), g ? lds : 0, (int)v.size(), 0, 0, f, by}, ty);
       }
     });
@@ -1181,7 +1202,10 @@ struct Plan final : ifmm_plan {
           launch_gemm(reinterpret_cast<GemmDesc*>(d + op.off), op.count, op.a, op.b, op.ty, (int)op.off2, s);
           break;
         case OP_ADD: launch_add(reinterpret_cast<AddDesc*>(d + op.off), op.count, op.a, op.b, op.ty, s); break;
-        case OP_QR: launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.off2, op.ty, s); break;
+        case OP_QR:
+          if (op.b) launch_qr_wave(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.b, op.a, op.ty, s);
+          else launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
+          break;
         case OP_RRQR:
           if (op.b == 2)
             launch_rrqr_reg(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2, (int)op.off2b,

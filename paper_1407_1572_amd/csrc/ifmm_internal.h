@@ -332,6 +332,12 @@ void launch_elim(const ElimArgs& a, int step, int max_m, int max_n, int ty, hipS
 constexpr size_t kQrLdsBytes = 64 * 1024;
 inline size_t qr_lds_bytes(int n, int m, int ty) { return (ty ? 4 : 8) * (size_t)(n + 1) * m; }
 void launch_qr(const QrDesc* d, int nd, size_t lds, int ty, hipStream_t s);
+// The same QR by one wave per matrix (m <= 64, n <= nr rows in registers;
+// nr = qr_wave_rows(n, m, ty): 32, 64 or 96 rows, and 128 in FP32; 0 when
+// the matrix does not fit).  max_k bounds min(n, m) over the batch (LDS of
+// the reflectors: max_k nr elements).
+int qr_wave_rows(int n, int m, int ty);
+void launch_qr_wave(const QrDesc* d, int nd, int nr, int max_k, int ty, hipStream_t s);
 // Pivoted QR with the whole matrix staged in LDS: (n + 1) * m + m elements
 // must fit in `lds` <= kRrqrLdsBytes.  max_n: the largest row count.
 constexpr size_t kRrqrLdsBytes = 159 * 1024;

@@ -972,6 +972,104 @@ __global__ __launch_bounds__(WG) void k_qr(const QrDesc* __restrict__ descs) {
   }
 }
 
+// The same factorisation with one wave per matrix for m <= 64 columns and
+// n <= NR rows: lane c holds column c in registers.  Step j: lane j publishes
+// its column; the wave forms the reflector (the norm by a butterfly sum, so
+// every lane holds the same value) and keeps it in LDS for Q; every column
+// right of j takes x - tau (u^T x) u.  Row j of column c is final after step
+// j, so R is written from the registers at the end; Q = H_0 ... H_{K-1}
+// [I_K; 0] is formed column by column from the LDS reflectors.  Same
+// reflector convention and sign normalisation as k_qr.
+template <class T, int NR>
+__global__ __launch_bounds__(WAVE) void k_qr_wave(const QrDesc* __restrict__ descs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* refl = reinterpret_cast<T*>(smem);  // [K][NR]
+  __shared__ T xs[NR];
+  __shared__ T tau_s[WAVE], alpha_s[WAVE];
+  const QrDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m, K = min(n, m);
+  if (d.A == nullptr || K == 0 || m > WAVE || n > NR) return;
+  T* gA = static_cast<T*>(d.A);
+  T* R = static_cast<T*>(d.R);
+  const size_t lda = d.lda;
+  const int c = threadIdx.x;
+  const bool live = c < m;
+  T col[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) col[i] = (live && i < n) ? gA[i + (size_t)c * lda] : T(0);
+  for (int j = 0; j < K; ++j) {
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) xs[i] = col[i];
+    }
+    __syncthreads();
+    T part = 0;
+    for (int i = c; i < n; i += WAVE)
+      if (i >= j) part = fma(xs[i], xs[i], part);
+    const T nrm = sqrt(wave_sum(part));
+    const T x0 = xs[j];
+    T alpha = 0, tau = 0, v0 = 1;
+    if (nrm > 0) {
+      alpha = x0 >= 0 ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tau = -v0 / alpha;
+    }
+    for (int i = c; i < NR; i += WAVE)
+      refl[j * NR + i] = i < j ? T(0) : i == j ? T(1) : (i < n && nrm > 0 ? xs[i] / v0 : T(0));
+    if (c == 0) {
+      tau_s[j] = tau;
+      alpha_s[j] = alpha;
+    }
+    __syncthreads();
+    if (live && c > j) {
+      const T* u = refl + j * NR;
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int i = 0; i < NR; i += 2) {
+        sa = fma(u[i], col[i], sa);
+        if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+      }
+      const T ts = tau * (sa + sb);
+      asm volatile("" ::: "memory");  // read u again below instead of holding NR more registers
+#pragma unroll
+      for (int i = 0; i < NR; ++i) col[i] = fma(-ts, u[i], col[i]);
+    }
+  }
+  // R (K x m), rows with a negative alpha negated
+  if (live) {
+    T* Rc = R + (size_t)c * d.ldr;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      if (i < K) {
+        const T v = i < c ? col[i] : (i == c ? alpha_s[c] : T(0));
+        Rc[i] = alpha_s[i] < 0 ? -v : v;
+      }
+    }
+  }
+  if (c >= K) return;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) col[i] = i == c ? T(1) : T(0);
+  for (int jj = K - 1; jj >= 0; --jj) {
+    const T* u = refl + jj * NR;
+    T sa = 0, sb = 0;
+#pragma unroll
+    for (int i = 0; i < NR; i += 2) {
+      sa = fma(u[i], col[i], sa);
+      if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+    }
+    const T ts = tau_s[jj] * (sa + sb);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < NR; ++i) col[i] = fma(-ts, u[i], col[i]);
+    asm volatile("" ::: "memory");
+  }
+  const T sg = alpha_s[c] < 0 ? T(-1) : T(1);
+  T* Qc = gA + (size_t)c * lda;
+#pragma unroll
+  for (int i = 0; i < NR; ++i)
+    if (i < n) Qc[i] = sg * col[i];
+}
+
 // ------------------------------------------------------------------- RRQR
 // The whole matrix is staged in LDS (stride n + 1).  Each column of the
 // trailing matrix is handled by a group of 16 lanes (16 consecutive rows per
@@ -2333,6 +2431,40 @@ void launch_touch_xform(const TouchXform& a, int ty, hipStream_t s) {
   } else {
     if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_touch_xform<double>));
     hipLaunchKernelGGL(k_touch_xform<double>, grid, dim3(WG), lds, s, a);
+  }
+}
+
+int qr_wave_rows(int n, int m, int ty) {
+  if (m > WAVE || n <= 0) return 0;
+  if (n <= 32) return 32;
+  if (n <= 64) return 64;
+  if (n <= 96) return 96;
+  if (ty && n <= 128) return 128;
+  return 0;
+}
+
+template <class T, int NR>
+void qr_wave_go(const QrDesc* d, int nd, int max_k, hipStream_t s) {
+  const size_t lds = (size_t)std::max(max_k, 1) * NR * sizeof(T);
+  if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_qr_wave<T, NR>));
+  hipLaunchKernelGGL((k_qr_wave<T, NR>), dim3(nd), dim3(WAVE), lds, s, d);
+}
+
+void launch_qr_wave(const QrDesc* d, int nd, int nr, int max_k, int ty, hipStream_t s) {
+  if (nd <= 0) return;
+  if (ty) {
+    switch (nr) {
+      case 32: qr_wave_go<float, 32>(d, nd, max_k, s); break;
+      case 64: qr_wave_go<float, 64>(d, nd, max_k, s); break;
+      case 96: qr_wave_go<float, 96>(d, nd, max_k, s); break;
+      default: qr_wave_go<float, 128>(d, nd, max_k, s); break;
+    }
+  } else {
+    switch (nr) {
+      case 32: qr_wave_go<double, 32>(d, nd, max_k, s); break;
+      case 64: qr_wave_go<double, 64>(d, nd, max_k, s); break;
+      default: qr_wave_go<double, 96>(d, nd, max_k, s); break;
+    }
   }
 }
 
