@@ -324,7 +324,8 @@ constexpr double kF32EpsFloor = 2.5e-7;
 
 // ------------------------------------------------------------ descriptor stages
 enum OpType { OP_GEMM, OP_ADD, OP_XFORM, OP_QR, OP_RRQR, OP_FORMQ, OP_STACKQR, OP_GJPANEL, OP_GJREST, OP_GJUNPERM,
-              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR, OP_FILLCP, OP_ROWCP };
+              OP_TXFORM, OP_WSTACK, OP_ELIM, OP_TRANS, OP_GJREG, OP_SOLVE, OP_M2LASM, OP_FORMQRR, OP_FILLCP, OP_ROWCP,
+              OP_RANKFIN };
 // Profile families (slots of ifmm_stats_t): 0 gemm, 1 add, 2 (unused), 3 qr,
 // 4 rrqr, 5 formq, 6 stackqr, 7 pivot inverse, 8 Schur updates (elimination
 // step 2), 9 touched-cluster transform, 10 window stacked R, 11 solve sweeps,
@@ -345,6 +346,7 @@ inline int family(int t) {
     case OP_FORMQRR: return 5;
     case OP_FILLCP: return 1;
     case OP_ROWCP: return 1;
+    case OP_RANKFIN: return 1;
     default: return t;
   }
 }
@@ -578,6 +580,12 @@ struct Stage {
       }
     });
   }
+  // Ranks finished on the device (RankFin; pointer fields other than rank
+  // are arr()-style blob pointers).
+  void rank_finalize(RankFin a) {
+    if (a.nt <= 0) return;
+    op({OP_RANKFIN, push(&a, sizeof(a)), 0, a.nt, 0, 0, 0.0, 0.0}, 0);
+  }
   // Pivoted QRs: matrices whose columns fit the registers of one thread each
   // go to the register kernel (b = 2, which also forms Q), by row class;
   // the rest to the LDS kernel (b = 1) or in place (b = 0), followed by the
@@ -652,18 +660,20 @@ struct Stage {
     return reinterpret_cast<const int*>(push(v->data(), std::max<size_t>(1, v->size()) * sizeof(int)) + 1);
   }
   // count = false: the exact work counts are left to the caller (see
-  // txform_work), the launch carries zeros.
+  // txform_work), the launch carries zeros.  r_new_at: an int array already
+  // in the blob (its arr() pointer) used as r_new instead of pushing r_new
+  // (its values are then written on the device; no work is counted here).
   template <class T>
   void touch_xform(TouchXform a, const std::vector<int>* touch_q, const std::vector<int>* tidx,
                    const std::vector<int>& r_old, const std::vector<int>& r_new, const std::vector<int>* r_par,
-                   int ncl, bool count = true) {
+                   int ncl, bool count = true, const int* r_new_at = nullptr) {
     if (a.nt <= 0) return;
     double f = 0, by = 0;
-    if (count) std::tie(f, by) = txform_work(a, touch_q, tidx, r_old, r_new, r_par, ncl, sizeof(T));
+    if (count && !r_new_at) std::tie(f, by) = txform_work(a, touch_q, tidx, r_old, r_new, r_par, ncl, sizeof(T));
     a.touch_q = arr(touch_q);
     a.tidx = arr(tidx);
     a.r_old = arr(&r_old);
-    a.r_new = arr(&r_new);
+    a.r_new = r_new_at ? r_new_at : arr(&r_new);
     a.r_par = arr(r_par);
     flops += f;
     op({OP_TXFORM, push(&a, sizeof(a)), 0, a.nt, 0, 0, f, by}, tcode<T>());
@@ -1087,6 +1097,10 @@ struct Plan final : ifmm_plan {
   Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg, wsTab;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
+  // the ranks' pinned copy on the host, and the event after its copy
+  int* h_rank = nullptr;
+  size_t h_rank_bytes = 0;
+  hipEvent_t ev_rank = nullptr;
   // stats
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
   hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
@@ -1299,6 +1313,21 @@ struct Plan final : ifmm_plan {
           rebase(a.r_par);
           if (op.b) launch_gram_win(a, op.a, op.ty, s);
           else launch_stackqr_win(a, op.a, op.ty, s);
+          break;
+        }
+        case OP_RANKFIN: {
+          RankFin a;
+          std::memcpy(&a, hb + op.off, sizeof(a));
+          auto rebase = [&](auto*& p) {
+            using P = typename std::remove_reference<decltype(p)>::type;
+            if (p) p = reinterpret_cast<P>(d + (reinterpret_cast<uintptr_t>(p) - 1));
+          };
+          rebase(a.q);
+          rebase(a.n);
+          rebase(a.r_new);
+          rebase(a.r_lvl);
+          rebase(a.g);
+          launch_rank_finalize(a, s);
           break;
         }
         case OP_XFORM: break;  // family 2 has no launches
@@ -1932,7 +1961,8 @@ struct Plan final : ifmm_plan {
       rank_cap = (size_t)2 * nt;
       d_rank = dalloc<int>(s, rank_cap);
     }
-    std::vector<int> hr(2 * nt), rnew(nt);
+    std::vector<int> rnew(nt);
+    std::vector<char> in_regs(nt);
     for (int t0 = 0; t0 < nt; t0 += chunk) {
       const int t1 = std::min(nt, t0 + chunk);
       Stage own;
@@ -1971,35 +2001,65 @@ struct Plan final : ifmm_plan {
         st.fill_copy<T>(f, erec[k][c], fc, fcb);
       }
       st.rrqr(rq);
+      for (int t = t0; t < t1; ++t) in_regs[t] = Stage::rrqr_in_regs(rq[t - t0]);
       run(st);
       run_deferred();
-      {
-        PhaseScope w(hc, HP_WAIT);
-        HIP_OK(hipMemcpyAsync(hr.data() + 2 * t0, d_rank + 2 * t0, sizeof(int) * 2 * (t1 - t0), hipMemcpyDeviceToHost,
-                              s));
-        HIP_OK(hipStreamSynchronize(s));
-      }
-      for (int t = t0; t < t1; ++t) {
-        const int nq = L.n[touch[t].q];
-        rnew[t] = std::min(std::min(hr[2 * t], nq), r_cap);
-        if (rnew[t] == r_cap && nq > r_cap) ++cap_hits[k];
-        // Q of the pivoted steps, formed on the device: its work, now that
-        // the rank is known
-        const int kk = std::min(rnew[t], hr[2 * t + 1]);
-        add_count(Stage::rrqr_in_regs(rq[t - t0]) ? 4 : 5, 4.0 * tri_sum(nq, rnew[t], kk),
-                  sizeof(T) * ((double)nq * kk + (double)nq * rnew[t]));
-      }
     }
-    // basis change T = U^^T U (the column side uses S = T^T)
+    // The ranks go to the host (pinned buffer, event) while the basis change
+    // is queued at once: its launches take the new ranks from the device
+    // (RankFin), so the device does not wait for the host's planning.
+    const size_t rb = sizeof(int) * 2 * (size_t)nt;
+    if (h_rank_bytes < rb) {
+      pinned().put(reinterpret_cast<char*>(h_rank), h_rank_bytes);
+      h_rank = nullptr;
+      h_rank_bytes = 0;
+      size_t got = 0;
+      h_rank = reinterpret_cast<int*>(pinned().get(std::max(rb, (size_t)64 << 10), &got));
+      h_rank_bytes = got;
+    }
+    HIP_OK(hipMemcpyAsync(h_rank, d_rank, rb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipEventRecord(ev_rank, s));
+    // basis change T = U^^T U (the column side uses S = T^T); row counts
+    // r_new written on the device before the launches read them
     PhaseScope post(hc, HP_COMPRESS_POST);
     Stage st;
+    std::vector<int> tq(nt), rbound(nt);
+    for (int t = 0; t < nt; ++t) {
+      tq[t] = touch[t].q;
+      rbound[t] = std::min(L.n[tq[t]], r_cap);
+    }
     std::vector<GemmDesc> g;
     for (int t = 0; t < nt; ++t) {
       const int q = touch[t].q, nq = L.n[q];
-      g.push_back({Uh + (size_t)t * L.sU, L.Ub(q), Tt + (size_t)t * rpad * rpad, rnew[t], L.r[q], nq, L.npad, L.npad,
-                   rpad, 1, 0, 1.0, 0.0});
+      g.push_back({Uh + (size_t)t * L.sU, L.Ub(q), Tt + (size_t)t * rpad * rpad, rbound[t], L.r[q], nq, L.npad,
+                   L.npad, rpad, 1, 0, 1.0, 0.0});
     }
-    st.gemm(g);
+    RankFin fin{};
+    fin.rank = d_rank;
+    fin.q = st.arr(&tq);
+    fin.n = st.arr(&L.n);
+    fin.r_new = const_cast<int*>(st.arr(&rbound));
+    fin.nt = nt;
+    fin.r_cap = r_cap;
+    const int* rk_blob = st.arr(&L.r);  // the level's ranks, touched entries patched on the device
+    fin.r_lvl = const_cast<int*>(rk_blob);
+    GemmDesc* gT = nullptr;
+    // descriptor array pushed first, its op queued after the finalize op
+    {
+      const size_t goff = st.push(g.data(), g.size() * sizeof(GemmDesc));
+      gT = reinterpret_cast<GemmDesc*>(goff + 1);
+      fin.g = gT;
+      st.rank_finalize(fin);
+      int mm = 0, nn = 0;
+      for (const auto& d : g) {
+        mm = std::max(mm, d.M);
+        nn = std::max(nn, d.N);
+      }
+      Op o{OP_GEMM, goff, 0, (int)g.size(), mm, nn, 0.0, 0.0};
+      o.off2 = 0;  // opA = 1
+      st.op(o, g[0].ty);
+    }
+    TouchXform txa{};
     {
       TouchXform a{};
       a.M = L.M;
@@ -2010,30 +2070,21 @@ struct Plan final : ifmm_plan {
       a.rpad = rpad;
       a.col_blocks = 1;
       a.sM = L.sM;
-      std::vector<int> tq(nt);
-      for (int t = 0; t < nt; ++t) tq[t] = touch[t].q;
       // the new bases replace U inside the same launch (after the product
       // T = U^^T U above has read the old ones)
       a.Unew = Uh;
       a.U = L.U;
-      a.n = st.arr(&L.n);
+      a.n = fin.n;
       a.sU = L.sU;
       a.npad = L.npad;
-      double ucb = 0;
-      for (int t = 0; t < nt; ++t) ucb += 2.0 * sizeof(T) * L.n[tq[t]] * (double)rnew[t];
-      add_count(9, 0.0, ucb);
-      st.touch_xform<T>(a, &tq, &tidx, L.r, rnew, k > 2 ? &lv[k - 1].r : nullptr, L.nc, false);
-      count_later(OP_TXFORM, [a, tq, tidx, ro = L.r, rnew, rp = k > 2 ? lv[k - 1].r : std::vector<int>(),
-                              par = k > 2, ncl = L.nc] {
-        return txform_work(a, &tq, &tidx, ro, rnew, par ? &rp : nullptr, ncl, sizeof(T));
-      });
+      st.touch_xform<T>(a, &tq, &tidx, L.r, rbound, k > 2 ? &lv[k - 1].r : nullptr, L.nc, false, fin.r_new);
+      txa = a;
     }
-    for (int t = 0; t < nt; ++t) L.r[touch[t].q] = rnew[t];
     // project the compressed fill into M2L (steps 4, 5 of the records)
     {
       ElimArgs a = elim_args(L, X, F, wpad, fpad, (int)E.size());
       a.tmp = wsS2.need<T>((size_t)E.size() * kPairs.count * rpad * fpad, s);
-      a.rk = st.arr(&L.r);
+      a.rk = rk_blob;
       const size_t ro = st.push(erec[k][c].data(), erec[k][c].size() * sizeof(ElimRec)) + 1;
       int mx = rpad;
       for (const Elim& e : E)
@@ -2044,9 +2095,37 @@ struct Plan final : ifmm_plan {
             if (kPairs.idx[sa][sb] < 0 || !ua.kind || !ub.kind || (ua.kind == 2 && ub.kind == 2)) continue;
             mx = std::max(mx, std::max(ua.size, ub.size));
           }
-      // the work of the two launches is counted while the host next waits
       st.elim<T>(a, ro, 4, mx, mx, 0.0, 0.0);
       st.elim<T>(a, ro, 5, mx, mx, 0.0, 0.0);
+    }
+    run(st);
+    // the host's copy of the ranks, and the work counts that depend on them
+    {
+      PhaseScope w(hc, HP_WAIT);
+      HIP_OK(hipEventSynchronize(ev_rank));
+    }
+    const double es = sizeof(T);
+    double gf = 0, gb = 0, ucb = 0;
+    for (int t = 0; t < nt; ++t) {
+      const int q = tq[t], nq = L.n[q];
+      rnew[t] = std::min(std::min(h_rank[2 * t], nq), r_cap);
+      if (rnew[t] == r_cap && nq > r_cap) ++cap_hits[k];
+      // Q of the pivoted steps, formed on the device
+      const int kk = std::min(rnew[t], h_rank[2 * t + 1]);
+      add_count(in_regs[t] ? 4 : 5, 4.0 * tri_sum(nq, rnew[t], kk), es * ((double)nq * kk + (double)nq * rnew[t]));
+      // T = U^^T U (r_new x r_old, inner n_q)
+      gf += 2.0 * rnew[t] * (double)L.r[q] * nq;
+      gb += es * ((double)rnew[t] * nq + (double)nq * L.r[q] + (double)rnew[t] * L.r[q]);
+      ucb += 2.0 * es * nq * (double)rnew[t];
+    }
+    add_count(0, gf, gb);
+    add_count(9, 0.0, ucb);
+    count_later(OP_TXFORM, [a = txa, tq, tidx, ro = L.r, rnew, rp = k > 2 ? lv[k - 1].r : std::vector<int>(),
+                            par = k > 2, ncl = L.nc] {
+      return txform_work(a, &tq, &tidx, ro, rnew, par ? &rp : nullptr, ncl, sizeof(T));
+    });
+    for (int t = 0; t < nt; ++t) L.r[tq[t]] = rnew[t];
+    {
       count_later_family(12, [E, r = L.r] {
         double f = 0, by = 0;
         const double es = sizeof(T);
@@ -2070,7 +2149,6 @@ struct Plan final : ifmm_plan {
         return std::make_pair(f, by);
       });
     }
-    run(st);
   }
 
   // Level k -> k-1: particles are the children's multipoles; P2P from their
@@ -2347,6 +2425,7 @@ struct Plan final : ifmm_plan {
     hc.on = tr && tr[0] && tr[0] != '0';
     arena.init();
     for (hipEvent_t& e : ev_t) HIP_OK(hipEventCreate(&e));
+    HIP_OK(hipEventCreateWithFlags(&ev_rank, hipEventDisableTiming));
     HIP_OK(hipEventRecord(ev_t[0], s));
     assemble(points);
     HIP_OK(hipEventRecord(ev_t[1], s));
@@ -2594,6 +2673,11 @@ struct Plan final : ifmm_plan {
       if (e) (void)hipEventDestroy(e);
       e = nullptr;
     }
+    if (ev_rank) (void)hipEventDestroy(ev_rank);
+    ev_rank = nullptr;
+    pinned().put(reinterpret_cast<char*>(h_rank), h_rank_bytes);
+    h_rank = nullptr;
+    h_rank_bytes = 0;
   }
 };
 

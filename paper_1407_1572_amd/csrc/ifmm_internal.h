@@ -156,6 +156,21 @@ struct TouchXform {
   int npad;
 };
 
+// Ranks of a compression, finished on the device so that the basis change
+// can be queued before the host reads them: for touch t (cluster q[t]),
+// r_new[t] = min(rank[2 t], n[q[t]], r_cap), also written to r_lvl[q[t]] and
+// to the row count M of the t-th descriptor of g when those are given.
+struct RankFin {
+  const int* rank;  // pivoted-QR ranks, two ints per touch (rank, steps)
+  const int* q;     // [nt] touched clusters
+  const int* n;     // [nc] cluster sizes
+  int* r_new;       // [nt] out
+  int* r_lvl;       // [nc] level ranks to patch, or null
+  GemmDesc* g;      // [nt] descriptors whose M is the new rank, or null
+  int nt, r_cap;
+};
+void launch_rank_finalize(const RankFin& a, hipStream_t s);
+
 // Far-field weights with the block lists found on the device: for cluster
 // q = ids[t], R of the stack of M(q, l)^T over the far-field partners l of
 // q's 6 x 6 window (r[l] rows each) and of the parent term Z_t (r_par[q / 4]

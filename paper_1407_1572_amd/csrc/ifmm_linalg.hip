@@ -595,6 +595,17 @@ __global__ __launch_bounds__(WG) void k_m2l_assemble(const M2LAssemble a) {
                   [&](int k, int y) { return Rl[y + (size_t)k * ld]; }, [&](int x, int y, double v) { M[x + y * ld] = (T)v; });
 }
 
+// One thread per touched cluster (RankFin).
+__global__ __launch_bounds__(WG) void k_rank_finalize(const RankFin a) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (t >= a.nt) return;
+  const int q = a.q[t];
+  const int rn = min(min(a.rank[2 * t], a.n[q]), a.r_cap);
+  a.r_new[t] = rn;
+  if (a.r_lvl) a.r_lvl[q] = rn;
+  if (a.g) a.g[t].M = rn;
+}
+
 // One workgroup per (touch, unit of its elimination record).
 template <class T>
 __global__ __launch_bounds__(WG) void k_fill_copy(const FillCopy a) {
@@ -2413,6 +2424,11 @@ void launch_m2l_assemble(const M2LAssemble& a, int ty, hipStream_t s) {
   const size_t lds = (size_t)a.rpad * a.p2 * sizeof(double);
   if (ty) hipLaunchKernelGGL(k_m2l_assemble<float>, grid, dim3(WG), lds, s, a);
   else hipLaunchKernelGGL(k_m2l_assemble<double>, grid, dim3(WG), lds, s, a);
+}
+
+void launch_rank_finalize(const RankFin& a, hipStream_t s) {
+  if (a.nt <= 0) return;
+  hipLaunchKernelGGL(k_rank_finalize, dim3(cdiv(a.nt, WG)), dim3(WG), 0, s, a);
 }
 
 void launch_fill_copy(const FillCopy& a, int ty, hipStream_t s) {
