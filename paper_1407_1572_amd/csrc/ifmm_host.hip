@@ -1754,15 +1754,24 @@ struct Plan final : ifmm_plan {
     }
     top();
     // the records drive the solve sweeps
+    // (gathered in pinned memory: the copy is queued without waiting for the
+    // launches ahead of it, and the solve plan is built meanwhile)
     erec_off.assign(kappa + 1, std::vector<size_t>(9, 0));
-    std::vector<ElimRec> all;
+    size_t nrec = 0;
     for (int k = 2; k <= kappa; ++k)
       for (int c = 0; c < 9; ++c) {
-        erec_off[k][c] = all.size();
-        all.insert(all.end(), erec[k][c].begin(), erec[k][c].end());
+        erec_off[k][c] = nrec;
+        nrec += erec[k][c].size();
       }
-    d_erec = dalloc<ElimRec>(s, all.size());
-    HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * all.size(), hipMemcpyHostToDevice, s));
+    Blob all;
+    all.resize(std::max<size_t>(nrec, 1) * sizeof(ElimRec));
+    for (int k = 2; k <= kappa; ++k)
+      for (int c = 0; c < 9; ++c)
+        if (!erec[k][c].empty())
+          std::memcpy(all.data() + erec_off[k][c] * sizeof(ElimRec), erec[k][c].data(),
+                      erec[k][c].size() * sizeof(ElimRec));
+    d_erec = dalloc<ElimRec>(s, std::max<size_t>(nrec, 1));
+    HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * nrec, hipMemcpyHostToDevice, s));
     solve_plan(1);  // planned while the last launches run
     run_deferred();
     HIP_OK(hipStreamSynchronize(s));
@@ -1849,7 +1858,6 @@ struct Plan final : ifmm_plan {
       Stage st;
       std::vector<ElimRec> recs(nb);
       int maxm = 0, maxu = 0;
-      double f1 = 0, b1 = 0, f2 = 0, b2 = 0, b3 = 0;
       const double es = sizeof(T);
       for (int b = 0; b < nb; ++b) {
         const Elim& e = E[b];
@@ -1864,35 +1872,54 @@ struct Plan final : ifmm_plan {
           r.kind[sp] = e.u[sp].kind;
           r.size[sp] = e.u[sp].size;
           r.off[sp] = e.u[sp].off;
-          if (!e.u[sp].kind) continue;
-          maxu = std::max(maxu, e.u[sp].size);
-          if (sp != 4) {
-            f1 += 2.0 * e.m * e.u[sp].size * e.ni;
-            b1 += 8.0 * e.m * e.ni + es * (2.0 * e.ni * e.u[sp].size + (double)e.m * e.u[sp].size);
-          }
-          b3 += es * 3.0 * e.ri * e.u[sp].size;
-        }
-        // Schur updates, counted per elimination GEMM: the pivot column C
-        // (h x n_i) and X (n_i x w) read once, every target block read and
-        // written once (a fill block between well-separated units is only
-        // written)
-        double h = 0, wcols = 0;
-        for (int sa = 0; sa < 9; ++sa) {
-          if (!e.u[sa].kind) continue;
-          wcols += e.u[sa].size;
-          if (sa != 4) h += e.u[sa].size;
-        }
-        b2 += es * (h * e.ni + e.ni * wcols);
-        for (int sa = 0; sa < 9; ++sa) {
-          if (sa == 4 || !e.u[sa].kind) continue;
-          for (int sb = 0; sb < 9; ++sb) {
-            if (!e.u[sb].kind) continue;
-            const double ma = e.u[sa].size, nbu = e.u[sb].size;
-            f2 += 2.0 * ma * nbu * e.ni;
-            b2 += es * (kPairs.idx[sa][sb] >= 0 && !(e.u[sa].kind == 2 && e.u[sb].kind == 2) ? 1.0 : 2.0) * ma * nbu;
-          }
+          if (e.u[sp].kind) maxu = std::max(maxu, e.u[sp].size);
         }
       }
+      // algorithmic work of steps 1-3, counted while the host next waits
+      // (E is plan[k][c], kept until the factorisation ends)
+      auto work = [&E, es](int step) {
+        double f = 0, by = 0;
+        for (const Elim& e : E) {
+          if (step == 2) {
+            // Schur updates, counted per elimination GEMM: the pivot column
+            // C (h x n_i) and X (n_i x w) read once, every target block read
+            // and written once (a fill block between well-separated units is
+            // only written)
+            double h = 0, wcols = 0;
+            for (int sa = 0; sa < 9; ++sa) {
+              if (!e.u[sa].kind) continue;
+              wcols += e.u[sa].size;
+              if (sa != 4) h += e.u[sa].size;
+            }
+            by += es * (h * e.ni + e.ni * wcols);
+            for (int sa = 0; sa < 9; ++sa) {
+              if (sa == 4 || !e.u[sa].kind) continue;
+              for (int sb = 0; sb < 9; ++sb) {
+                if (!e.u[sb].kind) continue;
+                const double ma = e.u[sa].size, nbu = e.u[sb].size;
+                f += 2.0 * ma * nbu * e.ni;
+                by += es * (kPairs.idx[sa][sb] >= 0 && !(e.u[sa].kind == 2 && e.u[sb].kind == 2) ? 1.0 : 2.0) * ma *
+                      nbu;
+              }
+            }
+            continue;
+          }
+          for (int sp = 0; sp < 9; ++sp) {
+            if (!e.u[sp].kind) continue;
+            if (step == 1 && sp != 4) {
+              f += 2.0 * e.m * e.u[sp].size * e.ni;
+              by += 8.0 * e.m * e.ni + es * (2.0 * e.ni * e.u[sp].size + (double)e.m * e.u[sp].size);
+            }
+            if (step == 3) by += es * 3.0 * e.ri * e.u[sp].size;
+          }
+        }
+        return std::make_pair(f, by);
+      };
+      count_later_family(12, [work] {
+        const auto a = work(1), b = work(3);
+        return std::make_pair(a.first + b.first, a.second + b.second);
+      });
+      count_later_family(8, [work] { return work(2); });
       ElimArgs a = elim_args(L, X, F, wpad, fpad, nb);
       const size_t ro = st.push(recs.data(), recs.size() * sizeof(ElimRec)) + 1;
       erec[k][c] = recs;
@@ -1904,9 +1931,9 @@ struct Plan final : ifmm_plan {
       }
       st.elim<T>(a, ro, 0, maxm, maxm, 0.0, bd);
       plan_inverse(st, inv);
-      st.elim<T>(a, ro, 1, maxm, maxu, f1, b1);
-      st.elim<T>(a, ro, 2, maxu, maxu, f2, b2);
-      st.elim<T>(a, ro, 3, rpad, maxu, 0.0, b3);
+      st.elim<T>(a, ro, 1, maxm, maxu, 0.0, 0.0);
+      st.elim<T>(a, ro, 2, maxu, maxu, 0.0, 0.0);
+      st.elim<T>(a, ro, 3, rpad, maxu, 0.0, 0.0);
       // the compression's work up to the rank read-back depends only on
       // host-known shapes: it joins this stage, uploaded and launched at once
       compress(k, c, E, X, F, wpad, fpad, Fp, st);
