@@ -1094,6 +1094,7 @@ struct Plan final : ifmm_plan {
   Status* d_status = nullptr;
   Arena arena;
   HostClock hc;
+  Blob up_E, up_nbr9;  // pinned sources of assembly uploads, kept until build() has synchronised
   Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg, wsTab;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
@@ -1478,21 +1479,33 @@ struct Plan final : ifmm_plan {
   // --------------------------------------------------------------- assembly
   void assemble(const double* d_points_in) {
     PhaseScope ps_(hc, HP_ASSEMBLY);
+    // the kernel tables and the transfer matrices depend on the depth only:
+    // queued ahead of the tree, in pinned memory, so the device works while
+    // the host reads the leaf populations back and plans
+    kappa = 2;
+    while ((int64_t)leaf * (1LL << (2 * kappa)) < N) ++kappa;
+    if (kappa > kMaxLevels) throw BadArg{};
+    d_table.assign(kappa + 1, nullptr);
+    for (int k = 2; k <= kappa; ++k) {
+      d_table[k] = dalloc<double>(s, (size_t)49 * p2 * p2);
+      launch_m2l_table(kf, p, 0.5 * size / (1 << k), d_table[k], s);
+    }
+    {
+      const std::vector<double> E = transfer_host(p);
+      up_E.resize(E.size() * sizeof(double));
+      std::memcpy(up_E.data(), E.data(), up_E.size());
+      d_E = dalloc<double>(s, E.size());
+      HIP_OK(hipMemcpyAsync(d_E, up_E.data(), up_E.size(), hipMemcpyHostToDevice, s));
+    }
     build_tree(d_points_in);
     const int nleaf = 1 << (2 * kappa);
     d_nbr9_leaf = dalloc<int>(s, (size_t)nleaf * 9);
     d_diag = dalloc<double>(s, N);
     d_status = dalloc<Status>(s, 1);
     HIP_OK(hipMemsetAsync(d_status, 0, sizeof(Status), s));
-    HIP_OK(hipMemcpyAsync(d_nbr9_leaf, lv[kappa].nbr9.data(), sizeof(int) * nleaf * 9, hipMemcpyHostToDevice, s));
-    std::vector<double> E = transfer_host(p);
-    d_E = dalloc<double>(s, E.size());
-    HIP_OK(hipMemcpyAsync(d_E, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, s));
-    d_table.assign(kappa + 1, nullptr);
-    for (int k = 2; k <= kappa; ++k) {
-      d_table[k] = dalloc<double>(s, (size_t)49 * p2 * p2);
-      launch_m2l_table(kf, p, 0.5 * size / (1 << k), d_table[k], s);
-    }
+    up_nbr9.resize(sizeof(int) * nleaf * 9);
+    std::memcpy(up_nbr9.data(), lv[kappa].nbr9.data(), up_nbr9.size());
+    HIP_OK(hipMemcpyAsync(d_nbr9_leaf, up_nbr9.data(), up_nbr9.size(), hipMemcpyHostToDevice, s));
     // diagonal
     if (diag_mode == IFMM_DIAG_ROWSUM) {
       double* ones = wsS1.need(N, s);
@@ -2460,6 +2473,8 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipEventRecord(ev_t[2], s));
     HIP_OK(hipStreamSynchronize(s));
     arena.settle();
+    up_E = Blob();
+    up_nbr9 = Blob();
     // stream-timeline times: assembly ends when its last kernel does (the
     // host plans the factorisation meanwhile)
     float ms = 0.f;
