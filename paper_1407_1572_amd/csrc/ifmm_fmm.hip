@@ -391,24 +391,29 @@ __global__ void k_l2p_near(const double* __restrict__ pts, const int* __restrict
       const double* xr = x + (size_t)r * ldx;
       double acc = 0.0;
       for (int m = 0; m < p2; ++m) acc = fma(lx[m / p] * ly[m % p], gl[m], acc);
+      // the stored block holds 0 for the point itself (the diagonal is d)
       const double* Ba = B + a;
+      double acc1 = 0.0;
       for (int s = 0; s < 9; ++s) {
         const int j = nbr9[i * 9 + s];
         if (j < 0) continue;
-        const int nj = cnt[j], sj = start[j];
+        const int nj = cnt[j];
+        const double* xs = xr + start[j];
         int b = 0;
-        for (; b + 4 <= nj; b += 4) {  // four loads in flight
-          const double v0 = Ba[(size_t)b * n], v1 = Ba[(size_t)(b + 1) * n];
-          const double v2 = Ba[(size_t)(b + 2) * n], v3 = Ba[(size_t)(b + 3) * n];
-          if (sj + b != g) acc = fma(v0, xr[sj + b], acc);
-          if (sj + b + 1 != g) acc = fma(v1, xr[sj + b + 1], acc);
-          if (sj + b + 2 != g) acc = fma(v2, xr[sj + b + 2], acc);
-          if (sj + b + 3 != g) acc = fma(v3, xr[sj + b + 3], acc);
+        for (; b + 8 <= nj; b += 8) {  // eight loads in flight, two sums
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = Ba[(size_t)(b + u) * n];
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {
+            acc = fma(v[u], xs[b + u], acc);
+            acc1 = fma(v[u + 1], xs[b + u + 1], acc1);
+          }
         }
-        for (; b < nj; ++b)
-          if (sj + b != g) acc = fma(Ba[(size_t)b * n], xr[sj + b], acc);
+        for (; b < nj; ++b) acc = fma(Ba[(size_t)b * n], xs[b], acc);
         Ba += (size_t)nj * n;
       }
+      acc += acc1;
       if (d) acc = fma(d[g], xr[g], acc);
       y[g + (size_t)r * ldy] = acc;
     }
