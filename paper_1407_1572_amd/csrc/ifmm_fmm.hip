@@ -391,29 +391,26 @@ __global__ void k_l2p_near(const double* __restrict__ pts, const int* __restrict
       const double* xr = x + (size_t)r * ldx;
       double acc = 0.0;
       for (int m = 0; m < p2; ++m) acc = fma(lx[m / p] * ly[m % p], gl[m], acc);
-      // the stored block holds 0 for the point itself (the diagonal is d)
+      // the stored block holds 0 for the point itself (the diagonal is d);
+      // one running sum in column order (the refinement's residual floor
+      // depends on this rounding order)
       const double* Ba = B + a;
-      double acc1 = 0.0;
       for (int s = 0; s < 9; ++s) {
         const int j = nbr9[i * 9 + s];
         if (j < 0) continue;
         const int nj = cnt[j];
         const double* xs = xr + start[j];
         int b = 0;
-        for (; b + 8 <= nj; b += 8) {  // eight loads in flight, two sums
+        for (; b + 8 <= nj; b += 8) {  // eight loads in flight
           double v[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) v[u] = Ba[(size_t)(b + u) * n];
 #pragma unroll
-          for (int u = 0; u < 8; u += 2) {
-            acc = fma(v[u], xs[b + u], acc);
-            acc1 = fma(v[u + 1], xs[b + u + 1], acc1);
-          }
+          for (int u = 0; u < 8; ++u) acc = fma(v[u], xs[b + u], acc);
         }
         for (; b < nj; ++b) acc = fma(Ba[(size_t)b * n], xs[b], acc);
         Ba += (size_t)nj * n;
       }
-      acc += acc1;
       if (d) acc = fma(d[g], xr[g], acc);
       y[g + (size_t)r * ldy] = acc;
     }
