@@ -530,27 +530,31 @@ def main():
 
     mixed, roof = run("fp32", pts, b, args.steps, args.warmup, N)
     fp64, roof64 = (None, None) if args.no_fp64 else run("fp64", pts, b, args.steps, args.warmup, N)
-    acc = None if args.no_fp64 or args.no_extra else accuracy(pts, b, N)
-    print(f"accuracy: {acc}", file=sys.stderr, flush=True)
+    def extra(name, fn):
+        """An extra section of the line; an error in it is reported there and
+        the headline figures above stand."""
+        try:
+            r = fn()
+        except Exception as e:
+            r = {"error": f"{type(e).__name__}: {e}"}
+        print(f"{name}: {r}", file=sys.stderr, flush=True)
+        return r
+
+    acc = None if args.no_fp64 or args.no_extra else extra("accuracy", lambda: accuracy(pts, b, N))
     scal = None
     if not args.no_extra:
-        scal = {"fp32": scaling("fp32"), "fp64": None if args.no_fp64 else scaling("fp64")}
-        for prec, rec in (("fp32", mixed), ("fp64", fp64)):
-            if rec is not None and scal[prec] is not None:
-                scal[prec][str(N)] = {"t_factor_ns_per_unknown": rec["t_factor_ms"] * 1e6 / N,
-                                      "t_assembly_ns_per_unknown": rec["t_assembly_ms"] * 1e6 / N,
-                                      "t_solve_ns_per_unknown": rec["t_solve_ms"] * 1e6 / N,
-                                      "max_rank": rec["max_rank"], "level_max_rank": rec["level_max_rank"]}
-        print(f"scaling: {scal}", file=sys.stderr, flush=True)
-    grads = None if args.no_extra else gradients()
-    print(f"gradients: {grads}", file=sys.stderr, flush=True)
-    batch = None
-    if not args.no_extra:
-        try:
-            batch = batched()
-        except Exception as e:  # reported in the line; the headline figures above stand
-            batch = {"error": str(e)}
-            print(f"batched: {e}", file=sys.stderr, flush=True)
+        def scaling_all():
+            sc = {"fp32": scaling("fp32"), "fp64": None if args.no_fp64 else scaling("fp64")}
+            for prec, rec in (("fp32", mixed), ("fp64", fp64)):
+                if rec is not None and sc[prec] is not None:
+                    sc[prec][str(N)] = {"t_factor_ns_per_unknown": rec["t_factor_ms"] * 1e6 / N,
+                                        "t_assembly_ns_per_unknown": rec["t_assembly_ms"] * 1e6 / N,
+                                        "t_solve_ns_per_unknown": rec["t_solve_ms"] * 1e6 / N,
+                                        "max_rank": rec["max_rank"], "level_max_rank": rec["level_max_rank"]}
+            return sc
+        scal = extra("scaling", scaling_all)
+    grads = None if args.no_extra else extra("gradients", gradients)
+    batch = None if args.no_extra else extra("batched", batched)
     out = {
         "metric": METRIC, "value": mixed["unknowns_per_s"], "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
