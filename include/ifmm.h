@@ -187,7 +187,10 @@ ifmm_status ifmm_solve(ifmm_t h, const double* b, double* x, int nrhs, void* str
  * process ends), so the launches of different problems run concurrently on
  * the device (each problem's factorisation reads its new ranks back to the
  * host once per colour phase; concurrent problems fill the device while one
- * waits).  The inputs must be ready on `stream`; on return every
+ * waits).  The worker streams overlap best when the process's HIP runtime
+ * opens at least `threads` hardware queues (GPU_MAX_HW_QUEUES, read when the
+ * runtime starts; its default 4 makes the streams of more threads share 4
+ * queues).  The inputs must be ready on `stream`; on return every
  * factorisation is complete and the handles use `stream`.  Results equal
  * those of ifmm_factor bit for bit.  Concurrent batched calls share the
  * worker streams.
