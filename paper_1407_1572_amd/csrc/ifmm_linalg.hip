@@ -765,15 +765,19 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
 // The vector a product multiplies (K values per right-hand side column) is
 // staged in LDS first: every lane reads it there, not through the caches.
 // One instantiation per step (each with the registers of its own step).
-template <class T, int STEP, int NC>
-__global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restrict__ wk, int tiles) {
+// NT threads per workgroup: WG, or 4 WG for step 2 (the residual gather over
+// every neighbour block) on batches of few records, where its row tile's
+// columns split four times finer give each record more loads in flight.
+template <class T, int STEP, int NC, int NT = WG>
+__global__ __launch_bounds__(NT) void k_solve(const SolveArgs a, double* __restrict__ wk, int tiles) {
   constexpr int step = STEP;
-  __shared__ double part[(WG / WAVE) * NC * WAVE];
+  static_assert(NT == WG || STEP == 2, "wide workgroups for the gather only");
+  __shared__ double part[(NT / WAVE) * NC * WAVE];
   extern __shared__ __align__(16) unsigned char smem[];
   double* xs = reinterpret_cast<double*>(smem);  // [NC][mpad]
   auto stage = [&](const double* src, size_t ld, int K, int ncol) {
     __syncthreads();
-    for (int e = threadIdx.x; e < K * ncol; e += WG) {
+    for (int e = threadIdx.x; e < K * ncol; e += NT) {
       const int k = e % K, c = e / K;
       xs[k + c * a.mpad] = src[k + c * ld];
     }
@@ -841,7 +845,7 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
         const double* src = part1 ? a.bv + ((size_t)2 * a.nc + cl) * sv + (size_t)c0 * a.npad
                                   : a.cv + ((size_t)a.nc + cl) * svc + (size_t)c0 * a.rpad;
         const int lds = part1 ? a.npad : a.rpad;
-        for (int e = threadIdx.x; e < sz * nc; e += WG) {
+        for (int e = threadIdx.x; e < sz * nc; e += NT) {
           const int k = e % sz, c = e / sz;
           xs[off + k + c * kst] = src[k + (size_t)c * lds];
         }
@@ -857,7 +861,7 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
           const int sz = r.size[u];
           const T* A = r.kind[u] == 1 ? static_cast<const T*>(a.P) + ((size_t)r.i * 9 + u) * a.sP
                                       : static_cast<const T*>(a.Qm) + ((size_t)r.i * 9 + u) * a.sQ;
-          constexpr int U = 8, NW = WG / WAVE;
+          constexpr int U = 8, NW = NT / WAVE;
           for (int k = w; k < sz; k += U * NW) {
             T av[U];
 #pragma unroll
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(WG) void k_solve(const SolveArgs a, double* __restr
       if (w == 0 && row < ni)
         for (int c = 0; c < nc; ++c) {
           double v = part[c * WAVE + lane];
-          for (int q = 1; q < WG / WAVE; ++q) v += part[(q * NC + c) * WAVE + lane];
+          for (int q = 1; q < NT / WAVE; ++q) v += part[(q * NC + c) * WAVE + lane];
           wb[row + (size_t)(c0 + c) * a.mpad] = snap[row + (size_t)(c0 + c) * a.npad] - v;
         }
     } else {
@@ -2393,6 +2397,11 @@ void launch_transition(const TransArgs& a, int ty, hipStream_t s) {
   else hipLaunchKernelGGL(k_transition<double>, grid, dim3(WG), 0, s, a);
 }
 
+// Colour batches of fewer records than this run the residual gather with 16
+// waves per workgroup (measured: the coarse levels' gathers 4.9 -> 3.9 ms per
+// 1M-point step; batches of 450+ records lose with it).
+constexpr int kSolveWideRecords = 256;
+
 void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty, hipStream_t s) {
   if (a.nb <= 0 || max_rows <= 0) return;
   const int tiles = cdiv(max_rows, WAVE);
@@ -2401,19 +2410,25 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
   // neighbour block, 8 max(npad, rpad))
   const size_t lds = sizeof(double) * std::min(SV_C, a.nrhs) *
                      (step == 2 ? (size_t)8 * std::max(a.npad, a.rpad) : (size_t)a.mpad);
-#define SOLVE_GO(S)                                                                              \
-  if (a.nrhs == 1) {                                                                          \
-    if (ty) hipLaunchKernelGGL((k_solve<float, S, 1>), grid, dim3(WG), lds, s, a, wk, tiles);    \
-    else hipLaunchKernelGGL((k_solve<double, S, 1>), grid, dim3(WG), lds, s, a, wk, tiles);      \
-  } else {                                                                                    \
-    if (ty) hipLaunchKernelGGL((k_solve<float, S, SV_C>), grid, dim3(WG), lds, s, a, wk, tiles); \
-    else hipLaunchKernelGGL((k_solve<double, S, SV_C>), grid, dim3(WG), lds, s, a, wk, tiles);   \
+#define SOLVE_GO(S, NT)                                                                                       \
+  if (a.nrhs == 1) {                                                                                        \
+    if (ty) hipLaunchKernelGGL((k_solve<float, S, 1, NT>), grid, dim3(NT), lds, s, a, wk, tiles);             \
+    else hipLaunchKernelGGL((k_solve<double, S, 1, NT>), grid, dim3(NT), lds, s, a, wk, tiles);               \
+  } else {                                                                                                  \
+    if (ty) hipLaunchKernelGGL((k_solve<float, S, SV_C, NT>), grid, dim3(NT), lds, s, a, wk, tiles);          \
+    else hipLaunchKernelGGL((k_solve<double, S, SV_C, NT>), grid, dim3(NT), lds, s, a, wk, tiles);            \
   }
   switch (step) {
-    case 0: SOLVE_GO(0) break;
-    case 1: SOLVE_GO(1) break;
-    case 2: SOLVE_GO(2) break;
-    default: SOLVE_GO(3) break;
+    case 0: SOLVE_GO(0, WG) break;
+    case 1: SOLVE_GO(1, WG) break;
+    case 2:
+      if (a.nb < kSolveWideRecords) {
+        SOLVE_GO(2, 4 * WG)
+      } else {
+        SOLVE_GO(2, WG)
+      }
+      break;
+    default: SOLVE_GO(3, WG) break;
   }
 #undef SOLVE_GO
 }
