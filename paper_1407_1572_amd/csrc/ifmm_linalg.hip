@@ -724,11 +724,11 @@ constexpr int SV_C = 4;
 
 // sum_k A(row, k) X(k, c) for this lane's row, the waves splitting k;
 // returns the full sums to wave 0 (acc valid there only).
-template <int NC, class TA, class XFn>
+template <int NC, class TA, int NT = WG, class XFn>
 __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, bool live, int K, XFn X, int nc,
                                 double* part, double* acc) {
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  constexpr int NW = WG / WAVE;
+  constexpr int NW = NT / WAVE;
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
   if (live) {
@@ -765,13 +765,12 @@ __device__ inline void tile_dot(const TA* __restrict__ A, size_t lda, int row, b
 // The vector a product multiplies (K values per right-hand side column) is
 // staged in LDS first: every lane reads it there, not through the caches.
 // One instantiation per step (each with the registers of its own step).
-// NT threads per workgroup: WG, or 4 WG for step 2 (the residual gather over
-// every neighbour block) on batches of few records, where its row tile's
-// columns split four times finer give each record more loads in flight.
+// NT threads per workgroup: WG, or 4 WG on colour batches of few records,
+// where a row tile's inner dimension split four times finer gives each
+// record more loads in flight.
 template <class T, int STEP, int NC, int NT = WG>
 __global__ __launch_bounds__(NT) void k_solve(const SolveArgs a, double* __restrict__ wk, int tiles) {
   constexpr int step = STEP;
-  static_assert(NT == WG || STEP == 2, "wide workgroups for the gather only");
   __shared__ double part[(NT / WAVE) * NC * WAVE];
   extern __shared__ __align__(16) unsigned char smem[];
   double* xs = reinterpret_cast<double*>(smem);  // [NC][mpad]
@@ -801,7 +800,7 @@ __global__ __launch_bounds__(NT) void k_solve(const SolveArgs a, double* __restr
       if (tile * WAVE >= m) return;
       const double* bi = a.bv + (size_t)r.i * sv + (size_t)c0 * a.npad;
       stage(bi, a.npad, ni, nc);
-      tile_dot<NC, double>(D, a.mpad, row, row < m, ni, XL, nc, part, acc);
+      tile_dot<NC, double, NT>(D, a.mpad, row, row < m, ni, XL, nc, part, acc);
       if (w == 0 && row < m)
         for (int c = 0; c < nc; ++c) wb[row + (size_t)(c0 + c) * a.mpad] = acc[c];
       if (tile == 0 && w == 1)
@@ -823,7 +822,7 @@ __global__ __launch_bounds__(NT) void k_solve(const SolveArgs a, double* __restr
                          : static_cast<const T*>(a.L) + ((size_t)cl * 9 + (8 - unit)) * a.sL;
       const int ld = part1 ? a.npad : a.rpad;
       stage(wb + (size_t)c0 * a.mpad, a.mpad, ni, nc);
-      tile_dot<NC, T>(A, ld, row, row < sz, ni, XL, nc, part, acc);
+      tile_dot<NC, T, NT>(A, ld, row, row < sz, ni, XL, nc, part, acc);
       double* tg = part1 ? a.bv + (size_t)cl * sv + (size_t)c0 * a.npad : a.cv + (size_t)cl * svc + (size_t)c0 * a.rpad;
       if (w == 0 && row < sz)
         for (int c = 0; c < nc; ++c) tg[row + (size_t)c * ld] -= acc[c];
@@ -890,7 +889,7 @@ __global__ __launch_bounds__(NT) void k_solve(const SolveArgs a, double* __restr
     } else {
       if (tile * WAVE >= ni) return;
       stage(wb + (size_t)c0 * a.mpad, a.mpad, m, nc);
-      tile_dot<NC, double>(D, a.mpad, row, row < ni, m, XL, nc, part, acc);
+      tile_dot<NC, double, NT>(D, a.mpad, row, row < ni, m, XL, nc, part, acc);
       double* xi = a.bv + ((size_t)2 * a.nc + r.i) * sv + (size_t)c0 * a.npad;
       if (w == 0 && row < ni)
         for (int c = 0; c < nc; ++c) xi[row + (size_t)c * a.npad] = acc[c];
@@ -2397,9 +2396,10 @@ void launch_transition(const TransArgs& a, int ty, hipStream_t s) {
   else hipLaunchKernelGGL(k_transition<double>, grid, dim3(WG), 0, s, a);
 }
 
-// Colour batches of fewer records than this run the residual gather with 16
-// waves per workgroup (measured: the coarse levels' gathers 4.9 -> 3.9 ms per
-// 1M-point step; batches of 450+ records lose with it).
+// Colour batches of fewer records than this run solve steps 0, 2 and 3 with
+// 16 waves per workgroup (measured at the coarse levels of a 1M-point step:
+// residual gathers 4.9 -> 3.9 ms, steps 0 and 3 2.5 -> 2.3 ms; batches of
+// 450+ records lose with it).
 constexpr int kSolveWideRecords = 256;
 
 void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty, hipStream_t s) {
@@ -2418,17 +2418,32 @@ void launch_solve(const SolveArgs& a, int step, double* wk, int max_rows, int ty
     if (ty) hipLaunchKernelGGL((k_solve<float, S, SV_C, NT>), grid, dim3(NT), lds, s, a, wk, tiles);          \
     else hipLaunchKernelGGL((k_solve<double, S, SV_C, NT>), grid, dim3(NT), lds, s, a, wk, tiles);            \
   }
+  const bool wide = a.nb < kSolveWideRecords;
   switch (step) {
-    case 0: SOLVE_GO(0, WG) break;
-    case 1: SOLVE_GO(1, WG) break;
+    case 0:
+      if (wide) {
+        SOLVE_GO(0, 4 * WG)
+      } else {
+        SOLVE_GO(0, WG)
+      }
+      break;
+    case 1:  // a workgroup per (record, unit, tile) already: no wide form (measured slower)
+      SOLVE_GO(1, WG)
+      break;
     case 2:
-      if (a.nb < kSolveWideRecords) {
+      if (wide) {
         SOLVE_GO(2, 4 * WG)
       } else {
         SOLVE_GO(2, WG)
       }
       break;
-    default: SOLVE_GO(3, WG) break;
+    default:
+      if (wide) {
+        SOLVE_GO(3, 4 * WG)
+      } else {
+        SOLVE_GO(3, WG)
+      }
+      break;
   }
 #undef SOLVE_GO
 }
