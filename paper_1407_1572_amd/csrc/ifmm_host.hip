@@ -926,17 +926,8 @@ struct Buf {
 // ------------------------------------------------------------ geometry helpers
 inline int s9_dx(int s) { return s / 3 - 1; }
 inline int s9_dy(int s) { return s % 3 - 1; }
-inline int s9_of(int dx, int dy) { return (dx + 1) * 3 + (dy + 1); }
-inline bool pos_adjacent(int sa, int sb) {
-  return std::abs(s9_dx(sa) - s9_dx(sb)) <= 1 && std::abs(s9_dy(sa) - s9_dy(sb)) <= 1;
-}
 inline int slot36(int a, int b) {
   return win_slot(demorton_x(a), demorton_y(a), demorton_x(b), demorton_y(b));
-}
-inline bool in_ilist(int a, int b) {
-  const int ax = demorton_x(a), ay = demorton_y(a), bx = demorton_x(b), by = demorton_y(b);
-  if (win_slot(ax, ay, bx, by) < 0) return false;
-  return std::abs(ax - bx) > 1 || std::abs(ay - by) > 1;
 }
 // compact index of an ordered pair of 3x3 positions at Chebyshev distance 2
 struct PairTable {
@@ -1729,7 +1720,7 @@ struct Plan final : ifmm_plan {
     if (k > 2) a.max_rows = std::max(a.max_rows, *std::max_element(lv[k - 1].r.begin(), lv[k - 1].r.end()));
     a.max_rows = std::max(a.max_rows, 1);
     st.win_stack<T>(a, ids, L.r, k > 2 ? &lv[k - 1].r : nullptr, false, gram);
-    count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2, gram] {
+    count_later(OP_WSTACK, [a, ids, r = L.r, rp = k > 2 ? lv[k - 1].r : std::vector<int>(), par = k > 2] {
       return winstack_work(a, ids, r, par ? &rp : nullptr, sizeof(T), gram);
     });
     if (S > 1) {
@@ -1862,10 +1853,6 @@ struct Plan final : ifmm_plan {
     const int wpad = 8 * fpad + rpad;
     T* X = wsX.need<T>((size_t)nb * L.mpad * wpad, s);
     T* F = wsF.need<T>((size_t)nb * kPairs.count * fpad * fpad, s);
-    auto Xp = [&](int b) { return X + (size_t)b * L.mpad * wpad; };
-    auto Fp = [&](int b, int sa, int sb) {
-      return F + ((size_t)b * kPairs.count + kPairs.idx[sa][sb]) * fpad * fpad;
-    };
     // ---- eliminate the batch: pivot inverse, X = D^-1 B, Schur updates
     {
       Stage st;
@@ -1949,14 +1936,13 @@ struct Plan final : ifmm_plan {
       st.elim<T>(a, ro, 3, rpad, maxu, 0.0, 0.0);
       // the compression's work up to the rank read-back depends only on
       // host-known shapes: it joins this stage, uploaded and launched at once
-      compress(k, c, E, X, F, wpad, fpad, Fp, st);
+      compress(k, c, E, X, F, wpad, fpad, st);
     }
   }
 
-  template <class FpFn>
-  // pre: launches not yet run (the batch's elimination); run before the first
-  // rank read-back.
-  void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, FpFn Fp, Stage& pre) {
+  // pre: launches not yet run (the batch's elimination); run with the first
+  // chunk of the compression.
+  void compress(int k, int c, const std::vector<Elim>& E, T* X, T* F, int wpad, int fpad, Stage& pre) {
     PhaseScope ps_(hc, HP_COMPRESS_PRE);
     Level<T>& L = lv[k];
     struct Touch {
@@ -2083,12 +2069,10 @@ struct Plan final : ifmm_plan {
     fin.r_cap = r_cap;
     const int* rk_blob = st.arr(&L.r);  // the level's ranks, touched entries patched on the device
     fin.r_lvl = const_cast<int*>(rk_blob);
-    GemmDesc* gT = nullptr;
     // descriptor array pushed first, its op queued after the finalize op
     {
       const size_t goff = st.push(g.data(), g.size() * sizeof(GemmDesc));
-      gT = reinterpret_cast<GemmDesc*>(goff + 1);
-      fin.g = gT;
+      fin.g = reinterpret_cast<GemmDesc*>(goff + 1);
       st.rank_finalize(fin);
       int mm = 0, nn = 0;
       for (const auto& d : g) {
