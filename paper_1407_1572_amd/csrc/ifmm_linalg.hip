@@ -1294,6 +1294,10 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
   const int c = threadIdx.x, lane = c % WAVE, w = c / WAVE, nw = blockDim.x / WAVE;
   const bool live = c < m;
   T col[NR];
+  // FP64 columns of more than 64 rows leave few registers beside them: a
+  // compiler barrier every CH rows keeps the LDS reads of u from being
+  // hoisted ahead of their FMAs all at once
+  constexpr int CH = (sizeof(T) == 8 && NR > 64) ? 16 : NR;
   T q0 = 0;
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
@@ -1381,6 +1385,7 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
       for (int i = 0; i < NR; i += 2) {
         sa = fma(u[i], col[i], sa);
         if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+        if ((i + 2) % CH == 0 && i + 2 < NR) asm volatile("" ::: "memory");
       }
       const T ts = tau * (sa + sb);
       // read u again from LDS below instead of holding NR more registers
@@ -1392,6 +1397,7 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
         const T v = col[i] * mk[i];
         if (i & 1) qb = fma(v, col[i], qb);
         else qa = fma(v, col[i], qa);
+        if ((i + 1) % CH == 0 && i + 1 < NR) asm volatile("" ::: "memory");
       }
       nrm = sqrt(qa + qb);
     }
@@ -1413,11 +1419,15 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
       for (int i = 0; i < NR; i += 2) {
         sa = fma(u[i], col[i], sa);
         if (i + 1 < NR) sb = fma(u[i + 1], col[i + 1], sb);
+        if ((i + 2) % CH == 0 && i + 2 < NR) asm volatile("" ::: "memory");
       }
       const T ts = tau_s[jj] * (sa + sb);
       asm volatile("" ::: "memory");
 #pragma unroll
-      for (int i = 0; i < NR; ++i) col[i] = fma(-ts, u[i], col[i]);
+      for (int i = 0; i < NR; ++i) {
+        col[i] = fma(-ts, u[i], col[i]);
+        if ((i + 1) % CH == 0 && i + 1 < NR) asm volatile("" ::: "memory");
+      }
       asm volatile("" ::: "memory");
     }
     const T sg = (c < kk && alpha_s[c] < 0) ? T(-1) : T(1);
@@ -2554,8 +2564,8 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int max_n, int ty, h
 int rrqr_reg_rows(int n, int ty) {
   if (n <= 32) return 32;
   if (n <= 64) return 64;
-  if (!ty) return 0;  // FP64 columns beyond 64 rows do not fit the register file
   if (n <= 96) return 96;
+  if (!ty) return 0;  // FP64 columns beyond 96 rows do not fit the register file
   if (n <= 128) return 128;
   return 0;
 }
@@ -2587,6 +2597,7 @@ void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax,
     switch (nr) {
       case 32: rrqr_reg_go<double, 32>(d, nd, nt, lds, s); break;
       case 64: rrqr_reg_go<double, 64>(d, nd, nt, lds, s); break;
+      case 96: rrqr_reg_go<double, 96>(d, nd, nt, lds, s); break;
     }
   }
 }
