@@ -1085,11 +1085,110 @@ __global__ __launch_bounds__(WAVE) void k_qr_wave(const QrDesc* __restrict__ des
 }
 
 // ------------------------------------------------------------------- RRQR
-// The whole matrix is staged in LDS (stride n + 1).  Each column of the
-// trailing matrix is handled by a group of 16 lanes (16 consecutive rows per
-// access), so a workgroup has 16 columns in flight; dot products and norms
-// reduce with shuffles inside the group.  Norms are recomputed exactly every
-// step.
+// The whole matrix is staged in LDS (stride n + 1), or worked on in place.
+// Each column of the trailing matrix is handled by a group of 16 lanes (16
+// consecutive rows per access), two columns at a time where registers
+// allow, so a workgroup has 64 or more columns in flight; dot products and
+// norms reduce with shuffles inside the group.  Norms are recomputed exactly
+// every step, so the pivot's norm over rows j.. is the pivot value itself.
+// A step costs three barriers: the pivot search, the column swap (with the
+// previous reflector's column scaled to u = x / v0 and alpha put on its
+// diagonal: no thread reads it any more), and the update, which works from
+// the unscaled x with 1 / v0 folded into its scalars.
+template <class T, int IL, int NV>
+__device__ inline void rrqr_update_cols(T* A, size_t lda, T* nrm, int n, int m, int j, T tau, T iv0, int rl,
+                                        int slot, int nslot) {
+  const T* x = A + j * lda;
+  T ur[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const int i = j + 1 + rl + GRP * t;
+    ur[t] = i < n ? x[i] : T(0);
+  }
+  int c = j + 1 + slot;
+  for (; IL == 2 && c + nslot < m; c += 2 * nslot) {
+    T* ca = A + c * lda;
+    T* cb = A + (c + nslot) * lda;
+    T va[NV], vb[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int i = j + 1 + rl + GRP * t;
+      va[t] = i < n ? ca[i] : T(0);
+      vb[t] = i < n ? cb[i] : T(0);
+    }
+    T sa0 = 0, sa1 = 0, sb0 = 0, sb1 = 0;
+#pragma unroll
+    for (int t = 0; t < NV; t += 2) {
+      sa0 = fma(ur[t], va[t], sa0);
+      sa1 = fma(ur[t + 1], va[t + 1], sa1);
+      sb0 = fma(ur[t], vb[t], sb0);
+      sb1 = fma(ur[t + 1], vb[t + 1], sb1);
+    }
+    const T tsa = tau * fma(grp_sum(sa0 + sa1), iv0, ca[j]);
+    const T tsb = tau * fma(grp_sum(sb0 + sb1), iv0, cb[j]);
+    const T ua = tsa * iv0, ub = tsb * iv0;
+    T qa0 = 0, qa1 = 0, qb0 = 0, qb1 = 0;
+#pragma unroll
+    for (int t = 0; t < NV; t += 2) {
+      const int i0 = j + 1 + rl + GRP * t, i1 = i0 + GRP;
+      const T a0 = fma(-ua, ur[t], va[t]), a1 = fma(-ua, ur[t + 1], va[t + 1]);
+      const T b0 = fma(-ub, ur[t], vb[t]), b1 = fma(-ub, ur[t + 1], vb[t + 1]);
+      if (i0 < n) {
+        ca[i0] = a0;
+        cb[i0] = b0;
+      }
+      if (i1 < n) {
+        ca[i1] = a1;
+        cb[i1] = b1;
+      }
+      qa0 = fma(a0, a0, qa0);
+      qa1 = fma(a1, a1, qa1);
+      qb0 = fma(b0, b0, qb0);
+      qb1 = fma(b1, b1, qb1);
+    }
+    const T qa = grp_sum(qa0 + qa1), qb = grp_sum(qb0 + qb1);
+    if (rl == 0) {
+      ca[j] -= tsa;
+      cb[j] -= tsb;
+      nrm[c] = sqrt(qa);
+      nrm[c + nslot] = sqrt(qb);
+    }
+  }
+  for (; c < m; c += nslot) {
+    T* col = A + c * lda;
+    T cv[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int i = j + 1 + rl + GRP * t;
+      cv[t] = i < n ? col[i] : T(0);
+    }
+    T s0 = 0, s1 = 0;
+#pragma unroll
+    for (int t = 0; t < NV; t += 2) {
+      s0 = fma(ur[t], cv[t], s0);
+      s1 = fma(ur[t + 1], cv[t + 1], s1);
+    }
+    const T ts = tau * fma(grp_sum(s0 + s1), iv0, col[j]);
+    const T us = ts * iv0;
+    T q0 = 0, q1 = 0;
+#pragma unroll
+    for (int t = 0; t < NV; t += 2) {
+      const int i0 = j + 1 + rl + GRP * t, i1 = i0 + GRP;
+      const T v0 = fma(-us, ur[t], cv[t]);
+      const T v1 = fma(-us, ur[t + 1], cv[t + 1]);
+      if (i0 < n) col[i0] = v0;
+      if (i1 < n) col[i1] = v1;
+      q0 = fma(v0, v0, q0);
+      q1 = fma(v1, v1, q1);
+    }
+    const T q = grp_sum(q0 + q1);
+    if (rl == 0) {
+      col[j] -= ts;
+      nrm[c] = sqrt(q);
+    }
+  }
+}
+
 template <class T, int NT, bool kLds, int NV>
 __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1110,12 +1209,13 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
       const int i = e % n, c = e / n;
       A[i + c * lda] = gA[i + (size_t)c * d.lda];
     }
-  __shared__ T rv[NT / WAVE];
-  __shared__ int ri[NT / WAVE];
-  __shared__ T red[NT / WAVE];
+  constexpr int NW = NT / WAVE;
+  __shared__ T rv[2][NW];
+  __shared__ int ri[2][NW];
   const int rl = threadIdx.x % GRP;         // row lane inside the group
-  const int slot = threadIdx.x / GRP;       // 0..15: column slot of the group
+  const int slot = threadIdx.x / GRP;       // column slot of the group
   constexpr int NSLOT = NT / GRP;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   __syncthreads();
   for (int c = slot; c < m; c += NSLOT) {
     const T* col = A + c * lda;
@@ -1125,31 +1225,47 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
     if (rl == 0) nrm[c] = sqrt(q);
   }
   __syncthreads();
-  int rank = 0;
+  int rank = 0, steps = K;
   bool counting = true;
   T first = 0;
+  // column j - 1 below its diagonal still holds x: scaled by 1 / v0 (0 for
+  // a zero column), alpha on the diagonal
+  auto finish = [&](int jp, T v0, T alpha, bool zero) {
+    T* col = A + jp * lda;
+    for (int i = jp + 1 + threadIdx.x; i < n; i += NT) col[i] = zero ? T(0) : col[i] / v0;
+    if (threadIdx.x == 0) col[jp] = alpha;
+  };
+  T pv0 = 1, palpha = 0;
+  bool pzero = true;
   for (int j = 0; j < K; ++j) {
     T bv = -1;
     int bi = m;
     for (int c = j + threadIdx.x; c < m; c += NT)
       if (nrm[c] > bv || (nrm[c] == bv && c < bi)) { bv = nrm[c]; bi = c; }
-    T piv;
-    int cp;
-    block_argmax<T, NT>(bv, bi, rv, ri, piv, cp);
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const T ov = __shfl_xor(bv, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    // the buffers alternate between steps: the previous step's readers are
+    // past the barrier that ended that step
+    if (lane == 0) { rv[j & 1][w] = bv; ri[j & 1][w] = bi; }
+    __syncthreads();
+    T piv = rv[j & 1][0];
+    int cp = ri[j & 1][0];
+    for (int q = 1; q < NW; ++q) {
+      const T v = rv[j & 1][q];
+      const int i = ri[j & 1][q];
+      if (v > piv || (v == piv && i < cp)) { piv = v; cp = i; }
+    }
     if (j == 0) first = piv;
     if (counting && first > 0 && (double)piv > d.eps * (double)first) rank = j + 1;
     else counting = false;
     if (!counting && d.stop_at_rank) {  // uniform: every thread holds the same pivot
-      if (threadIdx.x == 0) { *d.rank = rank; *d.steps = j; }
-      __syncthreads();
-      if (kLds)
-        for (int e = threadIdx.x; e < n * j; e += NT) {
-          const int i = e % n, c = e / n;
-          gA[i + (size_t)c * d.lda] = A[i + c * lda];
-        }
-      return;
+      steps = j;
+      break;
     }
-    __syncthreads();
+    if (j > 0) finish(j - 1, pv0, palpha, pzero);
     if (cp != j) {
       for (int i = threadIdx.x; i < n; i += NT) {
         const T t = A[i + j * lda];
@@ -1159,57 +1275,50 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
       if (threadIdx.x == 0) { const T t = nrm[j]; nrm[j] = nrm[cp]; nrm[cp] = t; }
     }
     __syncthreads();
-    T part = 0;
-    for (int i = j + threadIdx.x; i < n; i += NT) part = fma(A[i + j * lda], A[i + j * lda], part);
-    const T xn = sqrt(block_sum<T, NT>(part, red));
+    const T xn = piv;
     const T x0 = A[j + j * lda];
-    T alpha = 0, tau = 0, v0 = 1;
+    T alpha = 0, tau = 0, v0 = 1, iv0 = 0;
     if (xn > 0) {
       alpha = x0 >= 0 ? -xn : xn;
       v0 = x0 - alpha;
       tau = -v0 / alpha;
+      iv0 = T(1) / v0;
     }
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += NT) A[i + j * lda] = xn > 0 ? A[i + j * lda] / v0 : T(0);
-    if (threadIdx.x == 0) { gtau[j] = tau; galpha[j] = alpha; A[j + j * lda] = alpha; }
-    __syncthreads();
-    const T* u = A + j * lda;
+    if (threadIdx.x == 0) { gtau[j] = tau; galpha[j] = alpha; }
     if constexpr (NV > 0) {
-      // n <= GRP NV: this lane's rows of u and of each column it updates
+      // n <= GRP NV: this lane's rows of x and of each column it updates
       // stay in registers (one read and one write of the trailing matrix per
-      // step); the same partial sums, in the same order, as below
-      T ur[NV];
-#pragma unroll
-      for (int t = 0; t < NV; ++t) {
-        const int i = j + 1 + rl + GRP * t;
-        ur[t] = i < n ? u[i] : T(0);
-      }
+      // step)
+      constexpr int IL = sizeof(T) * NV <= 64 ? 2 : 1;  // two columns' rows and addresses fit the registers
+      rrqr_update_cols<T, IL, NV>(A, lda, nrm, n, m, j, tau, iv0, rl, slot, NSLOT);
+    } else {
+      const T* x = A + j * lda;
       for (int c = j + 1 + slot; c < m; c += NSLOT) {
         T* col = A + c * lda;
-        T cv[NV];
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-          const int i = j + 1 + rl + GRP * t;
-          cv[t] = i < n ? col[i] : T(0);
-        }
+        // two independent partial sums per lane (short, latency-bound loops)
         T s0 = 0, s1 = 0;
-#pragma unroll
-        for (int t = 0; t < NV; t += 2) {
-          s0 = fma(ur[t], cv[t], s0);
-          s1 = fma(ur[t + 1], cv[t + 1], s1);
+        int i = j + 1 + rl;
+        for (; i + GRP < n; i += 2 * GRP) {
+          s0 = fma(x[i], col[i], s0);
+          s1 = fma(x[i + GRP], col[i + GRP], s1);
         }
-        const T s = grp_sum(s0 + s1) + col[j];
-        const T ts = tau * s;
+        if (i < n) s0 = fma(x[i], col[i], s0);
+        const T ts = tau * fma(grp_sum(s0 + s1), iv0, col[j]);
+        const T us = ts * iv0;
         T q0 = 0, q1 = 0;
-#pragma unroll
-        for (int t = 0; t < NV; t += 2) {
-          const int i0 = j + 1 + rl + GRP * t, i1 = i0 + GRP;
-          const T v0 = fma(-ts, ur[t], cv[t]);
-          const T v1 = fma(-ts, ur[t + 1], cv[t + 1]);
-          if (i0 < n) col[i0] = v0;
-          if (i1 < n) col[i1] = v1;
+        i = j + 1 + rl;
+        for (; i + GRP < n; i += 2 * GRP) {
+          const T v0 = fma(-us, x[i], col[i]);
+          const T v1 = fma(-us, x[i + GRP], col[i + GRP]);
+          col[i] = v0;
+          col[i + GRP] = v1;
           q0 = fma(v0, v0, q0);
           q1 = fma(v1, v1, q1);
+        }
+        if (i < n) {
+          const T v0 = fma(-us, x[i], col[i]);
+          col[i] = v0;
+          q0 = fma(v0, v0, q0);
         }
         const T q = grp_sum(q0 + q1);
         if (rl == 0) {
@@ -1217,50 +1326,21 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
           nrm[c] = sqrt(q);
         }
       }
-      __syncthreads();
-      continue;
     }
-    for (int c = j + 1 + slot; c < m; c += NSLOT) {
-      T* col = A + c * lda;
-      // two independent partial sums per lane (short, latency-bound loops)
-      T s0 = 0, s1 = 0;
-      int i = j + 1 + rl;
-      for (; i + GRP < n; i += 2 * GRP) {
-        s0 = fma(u[i], col[i], s0);
-        s1 = fma(u[i + GRP], col[i + GRP], s1);
-      }
-      if (i < n) s0 = fma(u[i], col[i], s0);
-      const T s = grp_sum(s0 + s1) + col[j];
-      const T ts = tau * s;
-      T q0 = 0, q1 = 0;
-      i = j + 1 + rl;
-      for (; i + GRP < n; i += 2 * GRP) {
-        const T v0 = fma(-ts, u[i], col[i]);
-        const T v1 = fma(-ts, u[i + GRP], col[i + GRP]);
-        col[i] = v0;
-        col[i + GRP] = v1;
-        q0 = fma(v0, v0, q0);
-        q1 = fma(v1, v1, q1);
-      }
-      if (i < n) {
-        const T v0 = fma(-ts, u[i], col[i]);
-        col[i] = v0;
-        q0 = fma(v0, v0, q0);
-      }
-      const T q = grp_sum(q0 + q1);
-      if (rl == 0) {
-        col[j] -= ts;
-        nrm[c] = sqrt(q);
-      }
-    }
+    pv0 = v0;
+    palpha = alpha;
+    pzero = !(xn > 0);
     __syncthreads();
   }
-  if (kLds)
-    for (int e = threadIdx.x; e < n * K; e += NT) {
+  if (steps > 0) finish(steps - 1, pv0, palpha, pzero);
+  if (kLds) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * steps; e += NT) {
       const int i = e % n, c = e / n;
       gA[i + (size_t)c * d.lda] = A[i + c * lda];
     }
-  if (threadIdx.x == 0) { *d.rank = rank; *d.steps = K; }
+  }
+  if (threadIdx.x == 0) { *d.rank = rank; *d.steps = steps; }
 }
 
 // Pivoted QR with each column of the matrix in the registers of one thread
