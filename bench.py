@@ -513,6 +513,9 @@ def main():
                          "(p = 8, tolerance 1e-14, [-1,1]^2, FP64) and print that table as one JSON line")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 256-problem batched factor + solve and print its JSON")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="only run the FP64 factor + solve of the workload (for profiling that path) and print "
+                         "its figures as one JSON line")
     ap.add_argument("--copy-cal", action="store_true",
                     help="only run a plain 1 GiB read + 1 GiB write kernel (3 times): the known-size reference "
                          "for scaling the HBM counters (FETCH_SIZE / WRITE_SIZE) of a counter run")
@@ -549,6 +552,10 @@ def main():
     b = torch.from_numpy(workloads.rhs_for("c3_exp_1m", N)[:, 0].copy()).to(dev)
     torch.cuda.synchronize()
 
+    if args.fp64_only:
+        fp64, roof64 = run("fp64", pts, b, args.steps, args.warmup, N)
+        print(json.dumps({"workload": WORKLOAD, "n": N, "fp64": fp64, "roofline_fp64": roof64}))
+        return
     mixed, roof = run("fp32", pts, b, args.steps, args.warmup, N)
     fp64, roof64 = (None, None) if args.no_fp64 else run("fp64", pts, b, args.steps, args.warmup, N)
     def extra(name, fn):
