@@ -42,6 +42,10 @@ struct HipError {
 };
 struct NoMem {};
 struct BadArg {};
+struct Broken {  // an internal invariant failed
+  const char* what;
+  int line;
+};
 
 #define HIP_OK(x)                                      \
   do {                                                 \
@@ -895,7 +899,10 @@ struct Arena {
     std::swap(h[cur], blob.p);
     std::swap(hcap[cur], blob.cap);
     blob.n = 0;
-    HIP_OK(hipMemcpyAsync(d[cur], h[cur], need, hipMemcpyHostToDevice, s));
+    void* hd = nullptr;  // the slot's host buffer, as the device addresses it
+    HIP_OK(hipHostGetDevicePointer(&hd, h[cur], 0));
+    launch_copy_from_host(hd, d[cur], need, s);
+    HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(ev[cur], s));
     pending[cur] = true;
     *host = h[cur];
@@ -1075,6 +1082,8 @@ struct Plan final : ifmm_plan {
   std::vector<double*> d_table;
   std::vector<Level<T>> lv;
   std::vector<std::vector<std::vector<Elim>>> plan;  // [k][colour] eliminations in order
+  std::vector<unsigned> batch_mark;  // per cluster: stamp of the last colour batch whose neighbourhood holds it
+  unsigned batch_stamp = 0;
   std::vector<std::vector<std::vector<ElimRec>>> erec;  // their records, kept for the solve
   ElimRec* d_erec = nullptr;                          // all records on the device
   std::vector<std::vector<size_t>> erec_off;          // [k][colour] offset into d_erec
@@ -1091,7 +1100,22 @@ struct Plan final : ifmm_plan {
   size_t rank_cap = 0;
   // the ranks' pinned copy on the host, and the event after its copy
   int* h_rank = nullptr;
+  int* h_rank_dev = nullptr;  // h_rank's device address
   size_t h_rank_bytes = 0;
+  double* h_nrm = nullptr;  // the solve's residual norms (pinned, 64 columns at most)
+  double* h_nrm_dev = nullptr;
+  size_t h_nrm_bytes = 0;
+  // The nrhs column norms at d (device) on the host, read back by a kernel.
+  void norms_to_host(const double* d, int nrhs, double* out) {
+    if (!h_nrm) {
+      h_nrm = reinterpret_cast<double*>(pinned().get(64 * sizeof(double), &h_nrm_bytes));
+      HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h_nrm_dev), h_nrm, 0));
+    }
+    launch_copy_to_host(d, h_nrm_dev, sizeof(double) * nrhs, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    std::memcpy(out, h_nrm, sizeof(double) * nrhs);
+  }
   hipEvent_t ev_rank = nullptr;
   // stats
   double t_assembly = 0, t_factor = 0, t_solve = 0, factor_flops = 0;
@@ -1847,6 +1871,18 @@ struct Plan final : ifmm_plan {
       }
       E.push_back(e);
     }
+    // The batch's eliminations run concurrently: their 3 x 3 neighbourhoods
+    // (every block an elimination reads or writes, and every cluster it
+    // recompresses) must be disjoint.  The colouring gives it; checked here.
+    if (batch_mark.size() < (size_t)L.nc) batch_mark.assign(L.nc, 0);
+    ++batch_stamp;
+    for (const Elim& e : E)
+      for (int sp = 0; sp < 9; ++sp) {
+        const int j = sp == 4 ? e.i : L.nbr9[(size_t)e.i * 9 + sp];
+        if (j < 0) continue;
+        if (batch_mark[j] == batch_stamp) throw Broken{"a colour batch with overlapping neighbourhoods", __LINE__};
+        batch_mark[j] = batch_stamp;
+      }
     const int nb = (int)E.size();
     if (nb == 0) return;
     const int fpad = std::max(L.npad, rpad);
@@ -2029,21 +2065,23 @@ struct Plan final : ifmm_plan {
       st.rrqr(rq);
       for (int t = t0; t < t1; ++t) in_regs[t] = Stage::rrqr_in_regs(rq[t - t0]);
       run(st);
-      run_deferred();
     }
-    // The ranks go to the host (pinned buffer, event) while the basis change
-    // is queued at once: its launches take the new ranks from the device
-    // (RankFin), so the device does not wait for the host's planning.
+    // The ranks go to the host (a kernel writes them into a pinned buffer;
+    // event) while the basis change is queued at once: its launches take the
+    // new ranks from the device (RankFin), so the device does not wait for
+    // the host's planning.
     const size_t rb = sizeof(int) * 2 * (size_t)nt;
     if (h_rank_bytes < rb) {
       pinned().put(reinterpret_cast<char*>(h_rank), h_rank_bytes);
       h_rank = nullptr;
+      h_rank_dev = nullptr;
       h_rank_bytes = 0;
       size_t got = 0;
       h_rank = reinterpret_cast<int*>(pinned().get(std::max(rb, (size_t)64 << 10), &got));
       h_rank_bytes = got;
+      HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h_rank_dev), h_rank, 0));
     }
-    HIP_OK(hipMemcpyAsync(h_rank, d_rank, rb, hipMemcpyDeviceToHost, s));
+    launch_copy_to_host(d_rank, h_rank_dev, rb, s);
     HIP_OK(hipEventRecord(ev_rank, s));
     // basis change T = U^^T U (the column side uses S = T^T); row counts
     // r_new written on the device before the launches read them
@@ -2123,7 +2161,10 @@ struct Plan final : ifmm_plan {
       st.elim<T>(a, ro, 5, mx, mx, 0.0, 0.0);
     }
     run(st);
-    // the host's copy of the ranks, and the work counts that depend on them
+    // the deferred work counts while the device runs the compression (after
+    // every launch of it is queued), then the host's copy of the ranks and
+    // the work counts that depend on them
+    run_deferred();
     {
       PhaseScope w(hc, HP_WAIT);
       HIP_OK(hipEventSynchronize(ev_rank));
@@ -2558,8 +2599,7 @@ struct Plan final : ifmm_plan {
       std::vector<double> bn(nrhs), rn(nrhs);
       HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
       launch_colnorm2(bt, n, nrhs, n, nrm, s);
-      HIP_OK(hipMemcpyAsync(bn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
+      norms_to_host(nrm, nrhs, bn.data());
       double best = 1e300;
       while (true) {
         fmm_apply_tree(xt, yt, nrhs, d_diag);
@@ -2569,8 +2609,7 @@ struct Plan final : ifmm_plan {
         run(st);
         HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
         launch_colnorm2(rt, n, nrhs, n, nrm, s);
-        HIP_OK(hipMemcpyAsync(rn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
+        norms_to_host(nrm, nrhs, rn.data());
         double worst = 0.0;
         for (int r = 0; r < nrhs; ++r) {
           const double rel = std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300);
@@ -2703,7 +2742,12 @@ struct Plan final : ifmm_plan {
     ev_rank = nullptr;
     pinned().put(reinterpret_cast<char*>(h_rank), h_rank_bytes);
     h_rank = nullptr;
+    h_rank_dev = nullptr;
     h_rank_bytes = 0;
+    pinned().put(reinterpret_cast<char*>(h_nrm), h_nrm_bytes);
+    h_nrm = nullptr;
+    h_nrm_dev = nullptr;
+    h_nrm_bytes = 0;
   }
 };
 
@@ -2751,6 +2795,9 @@ ifmm_status map_exc() {
     return IFMM_ENOMEM;
   } catch (const BadArg&) {
     return IFMM_EINVAL;
+  } catch (const Broken& b) {
+    std::fprintf(stderr, "ifmm: internal check failed at ifmm_host.hip:%d: %s\n", b.line, b.what);
+    return IFMM_EDEVICE;
   } catch (int code) {
     return (ifmm_status)code;
   } catch (const std::bad_alloc&) {

@@ -483,5 +483,11 @@ void launch_leaf_scatter(const double* blk, size_t bstride, int ldb, double* v, 
                          const int* leaf_n, int nleaf, int nrhs, hipStream_t s);
 void launch_fill(double* x, size_t n, double v, hipStream_t s);
 void launch_add_const(double* x, size_t n, double v, hipStream_t s);
+// bytes (a multiple of 4) from device memory into pinned host memory given
+// by its device address, by a kernel (see ifmm_tree.hip).
+void launch_copy_to_host(const void* src, void* dst_dev, size_t bytes, hipStream_t s);
+// bytes from pinned host memory given by its device address (16-byte
+// aligned, as is dst) into device memory, by a kernel.
+void launch_copy_from_host(const void* src_dev, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace ifmm

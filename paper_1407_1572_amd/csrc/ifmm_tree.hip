@@ -7,6 +7,8 @@
 // host reads back with the populations.
 #include "ifmm_internal.h"
 
+#include <algorithm>
+
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -152,6 +154,46 @@ void launch_leaf_scatter(const double* blk, size_t bstride, int ldb, double* v, 
 void launch_check_finite(const double* v, int n, int* bad, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, bad);
+}
+
+// n 32-bit words into pinned host memory (dst: its device address), then a
+// system-scope fence: the host reads them once a later event on the stream
+// has completed.  One short launch in place of a DMA copy, whose start-up
+// would otherwise stall the stream on a read-back the host waits for.
+__global__ void __launch_bounds__(256) k_copy_to_host(const unsigned* __restrict__ src, unsigned* dst, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+  __threadfence_system();
+}
+
+void launch_copy_to_host(const void* src, void* dst_dev, size_t bytes, hipStream_t s) {
+  const int n = (int)(bytes / 4);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_to_host, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const unsigned*>(src), static_cast<unsigned*>(dst_dev), n);
+}
+
+// bytes from pinned host memory (src: its device address) into device
+// memory, 16 bytes per lane and step: an upload that stays on the stream's
+// compute queue (a DMA copy between two launches costs the hand-over
+// between the copy engine and the compute queue, twice).
+__global__ void __launch_bounds__(256) k_copy_from_host(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                        size_t n16, const unsigned char* __restrict__ src_tail,
+                                                        unsigned char* __restrict__ dst_tail, int tail) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  if (blockIdx.x == 0 && (int)threadIdx.x < tail) dst_tail[threadIdx.x] = src_tail[threadIdx.x];
+}
+
+void launch_copy_from_host(const void* src_dev, void* dst, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  const size_t n16 = bytes / 16;
+  const int tail = (int)(bytes % 16);
+  const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((n16 + 255) / 256, 1024));
+  const unsigned char* st = static_cast<const unsigned char*>(src_dev) + n16 * 16;
+  unsigned char* dt = static_cast<unsigned char*>(dst) + n16 * 16;
+  hipLaunchKernelGGL(k_copy_from_host, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src_dev),
+                     static_cast<uint4*>(dst), n16, st, dt, tail);
 }
 
 void launch_fill(double* x, size_t n, double v, hipStream_t s) {
