@@ -1094,7 +1094,7 @@ struct Plan final : ifmm_plan {
   Status* d_status = nullptr;
   Arena arena;
   HostClock hc;
-  Blob up_E, up_nbr9;  // pinned sources of assembly uploads, kept until build() has synchronised
+  Blob up_E, up_nbr9, up_near_off;  // pinned sources of assembly uploads, kept until build() has synchronised
   Buf wsX, wsF, wsT, wsA, wsB, wsQ, wsR, wsZ, wsS1, wsS2, wsVec, wsSeg, wsTab;
   int* d_rank = nullptr;
   size_t rank_cap = 0;
@@ -1102,19 +1102,33 @@ struct Plan final : ifmm_plan {
   int* h_rank = nullptr;
   int* h_rank_dev = nullptr;  // h_rank's device address
   size_t h_rank_bytes = 0;
-  double* h_nrm = nullptr;  // the solve's residual norms (pinned, 64 columns at most)
-  double* h_nrm_dev = nullptr;
-  size_t h_nrm_bytes = 0;
-  // The nrhs column norms at d (device) on the host, read back by a kernel.
-  void norms_to_host(const double* d, int nrhs, double* out) {
-    if (!h_nrm) {
-      h_nrm = reinterpret_cast<double*>(pinned().get(64 * sizeof(double), &h_nrm_bytes));
-      HIP_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h_nrm_dev), h_nrm, 0));
+  char* h_small = nullptr;  // pinned scratch of the small read-backs (leaf counts, norms, status)
+  size_t h_small_bytes = 0;
+  // A pinned pool buffer as the device addresses it.
+  static void* dev_view(const void* h) {
+    void* d = nullptr;
+    HIP_OK(hipHostGetDevicePointer(&d, const_cast<void*>(h), 0));
+    return d;
+  }
+  // The first `bytes` of a pinned blob into device memory, queued on the
+  // stream (the blob must outlive the copy).
+  void upload_pinned(void* d, const Blob& b, size_t bytes) {
+    launch_copy_from_host(dev_view(b.data()), d, bytes, s);
+    HIP_OK(hipGetLastError());
+  }
+  // bytes (a multiple of 4) of device data into out: a kernel writes them
+  // into the pinned scratch, then the stream is waited for.
+  void to_host(const void* d, size_t bytes, void* out) {
+    if (h_small_bytes < bytes) {
+      pinned().put(h_small, h_small_bytes);
+      h_small = nullptr;
+      h_small_bytes = 0;
+      h_small = pinned().get(std::max(bytes, (size_t)4096), &h_small_bytes);
     }
-    launch_copy_to_host(d, h_nrm_dev, sizeof(double) * nrhs, s);
+    launch_copy_to_host(d, dev_view(h_small), bytes, s);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));
-    std::memcpy(out, h_nrm, sizeof(double) * nrhs);
+    std::memcpy(out, h_small, bytes);
   }
   hipEvent_t ev_rank = nullptr;
   // stats
@@ -1420,8 +1434,7 @@ struct Plan final : ifmm_plan {
     if (kf.kind == 0) launch_tree_distinct(d_pts, d_leaf_start, d_leaf_n, nleaf, bad, s);  // 1/r: distinct
     if (diag_mode == IFMM_DIAG_VECTOR) launch_check_finite(d_diag_user, n, bad, s);
     leaf_n.assign(nleaf + 1, 0);
-    HIP_OK(hipMemcpyAsync(leaf_n.data(), d_leaf_n, sizeof(int) * (nleaf + 1), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    to_host(d_leaf_n, sizeof(int) * (nleaf + 1), leaf_n.data());
     if (leaf_n[nleaf]) throw BadArg{};
     leaf_n.resize(nleaf);
     leaf_start.assign(nleaf, 0);
@@ -1510,7 +1523,7 @@ struct Plan final : ifmm_plan {
       up_E.resize(E.size() * sizeof(double));
       std::memcpy(up_E.data(), E.data(), up_E.size());
       d_E = dalloc<double>(s, E.size());
-      HIP_OK(hipMemcpyAsync(d_E, up_E.data(), up_E.size(), hipMemcpyHostToDevice, s));
+      upload_pinned(d_E, up_E, up_E.size());
     }
     build_tree(d_points_in);
     const int nleaf = 1 << (2 * kappa);
@@ -1520,7 +1533,7 @@ struct Plan final : ifmm_plan {
     HIP_OK(hipMemsetAsync(d_status, 0, sizeof(Status), s));
     up_nbr9.resize(sizeof(int) * nleaf * 9);
     std::memcpy(up_nbr9.data(), lv[kappa].nbr9.data(), up_nbr9.size());
-    HIP_OK(hipMemcpyAsync(d_nbr9_leaf, up_nbr9.data(), up_nbr9.size(), hipMemcpyHostToDevice, s));
+    upload_pinned(d_nbr9_leaf, up_nbr9, up_nbr9.size());
     // diagonal
     if (diag_mode == IFMM_DIAG_ROWSUM) {
       double* ones = wsS1.need(N, s);
@@ -1568,7 +1581,9 @@ struct Plan final : ifmm_plan {
       if (tot * sizeof(double) <= kNearStoreMax) {
         d_near = dalloc<double>(s, std::max<size_t>(tot, 1));
         d_near_off = dalloc<size_t>(s, nleaf);
-        HIP_OK(hipMemcpyAsync(d_near_off, off.data(), sizeof(size_t) * nleaf, hipMemcpyHostToDevice, s));
+        up_near_off.resize(sizeof(size_t) * nleaf);
+        std::memcpy(up_near_off.data(), off.data(), up_near_off.size());
+        upload_pinned(d_near_off, up_near_off, up_near_off.size());
       }
     }
     launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
@@ -1799,13 +1814,13 @@ struct Plan final : ifmm_plan {
           std::memcpy(all.data() + erec_off[k][c] * sizeof(ElimRec), erec[k][c].data(),
                       erec[k][c].size() * sizeof(ElimRec));
     d_erec = dalloc<ElimRec>(s, std::max<size_t>(nrec, 1));
-    HIP_OK(hipMemcpyAsync(d_erec, all.data(), sizeof(ElimRec) * nrec, hipMemcpyHostToDevice, s));
+    upload_pinned(d_erec, all, sizeof(ElimRec) * nrec);
     solve_plan(1);  // planned while the last launches run
     run_deferred();
     HIP_OK(hipStreamSynchronize(s));
     resolve_profile();
     Status hs{};
-    HIP_OK(hipMemcpy(&hs, d_status, sizeof(Status), hipMemcpyDeviceToHost));
+    to_host(d_status, sizeof(Status), &hs);
     if (hs.singular) throw 3;
   }
 
@@ -2388,10 +2403,24 @@ struct Plan final : ifmm_plan {
       return a;
     };
     // algorithmic work of one step: every block it reads once, vectors read
-    // and written once; max_rows: largest row count of the step
+    // and written once (counted for the profile only); max_rows: largest row
+    // count of the step
     auto work = [&](int k, int c, int step, double& f, double& by, int& rows) {
       f = by = 0;
       rows = 0;
+      if (!(profile && timed(family(OP_SOLVE)))) {
+        for (const Elim& e : plan[k][c]) {
+          if (step == 0 || step == 3) {
+            rows = std::max(rows, step == 0 ? e.m : e.ni);
+            continue;
+          }
+          rows = std::max(rows, step == 1 ? e.ri : e.m);
+          if (step == 1)
+            for (int sp = 0; sp < 9; ++sp)
+              if (sp != 4 && e.u[sp].kind) rows = std::max(rows, e.u[sp].size);
+        }
+        return;
+      }
       for (const Elim& e : plan[k][c]) {
         if (step == 0 || step == 3) {
           const double kk = step == 0 ? e.ni : e.m, rr = step == 0 ? e.m : e.ni;
@@ -2468,7 +2497,7 @@ struct Plan final : ifmm_plan {
                                std::move(st), nullptr});
     SolvePlan& sp = splans.back();
     sp.d = dalloc<char>(s, sp.st.blob.size());
-    HIP_OK(hipMemcpyAsync(sp.d, sp.st.blob.data(), sp.st.blob.size(), hipMemcpyHostToDevice, s));
+    upload_pinned(sp.d, sp.st.blob, sp.st.blob.size());
     return sp;
   }
 
@@ -2500,6 +2529,7 @@ struct Plan final : ifmm_plan {
     arena.settle();
     up_E = Blob();
     up_nbr9 = Blob();
+    up_near_off = Blob();
     // stream-timeline times: assembly ends when its last kernel does (the
     // host plans the factorisation meanwhile)
     float ms = 0.f;
@@ -2599,7 +2629,7 @@ struct Plan final : ifmm_plan {
       std::vector<double> bn(nrhs), rn(nrhs);
       HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
       launch_colnorm2(bt, n, nrhs, n, nrm, s);
-      norms_to_host(nrm, nrhs, bn.data());
+      to_host(nrm, sizeof(double) * nrhs, bn.data());
       double best = 1e300;
       while (true) {
         fmm_apply_tree(xt, yt, nrhs, d_diag);
@@ -2609,7 +2639,7 @@ struct Plan final : ifmm_plan {
         run(st);
         HIP_OK(hipMemsetAsync(nrm, 0, sizeof(double) * nrhs, s));
         launch_colnorm2(rt, n, nrhs, n, nrm, s);
-        norms_to_host(nrm, nrhs, rn.data());
+        to_host(nrm, sizeof(double) * nrhs, rn.data());
         double worst = 0.0;
         for (int r = 0; r < nrhs; ++r) {
           const double rel = std::sqrt(rn[r]) / std::max(std::sqrt(bn[r]), 1e-300);
@@ -2744,10 +2774,9 @@ struct Plan final : ifmm_plan {
     h_rank = nullptr;
     h_rank_dev = nullptr;
     h_rank_bytes = 0;
-    pinned().put(reinterpret_cast<char*>(h_nrm), h_nrm_bytes);
-    h_nrm = nullptr;
-    h_nrm_dev = nullptr;
-    h_nrm_bytes = 0;
+    pinned().put(h_small, h_small_bytes);
+    h_small = nullptr;
+    h_small_bytes = 0;
   }
 };
 
