@@ -1670,8 +1670,10 @@ struct Plan final : ifmm_plan {
     // ---- M2L in orthonormal coordinates: M_il = R_i K(dx,dy) R_l^T
     for (int k = 2; k <= kappa; ++k) {
       Level<T>& L = lv[k];
+      // the assembly writes every far-field block (its partner's rank wide)
+      // and zeroes the neighbours' slots, where fill-in accumulates; no other
+      // part of a slot is ever read
       L.M = dalloc<T>(s, L.sM * 36 * L.nc);
-      HIP_OK(hipMemsetAsync(L.M, 0, sizeof(T) * L.sM * 36 * L.nc, s));
       M2LAssemble a{};
       a.R = Ra[k];
       a.table = d_table[k];

@@ -579,7 +579,11 @@ __global__ __launch_bounds__(WG) void k_m2l_assemble(const M2LAssemble a) {
   const int jx = 2 * (ix >> 1) - 2 + sl / 6, jy = 2 * (iy >> 1) - 2 + sl % 6;
   if (jx < 0 || jy < 0 || jx >= a.nside || jy >= a.nside) return;
   const int dx = jx - ix, dy = jy - iy;
-  if (abs(dx) <= 1 && abs(dy) <= 1) return;
+  T* M = static_cast<T*>(a.M) + ((size_t)i * 36 + sl) * a.sM;
+  if (abs(dx) <= 1 && abs(dy) <= 1) {  // a neighbour's slot: the fill-in accumulates there from zero
+    for (size_t e = threadIdx.x; e < a.sM; e += WG) M[e] = T(0);
+    return;
+  }
   const int l = morton2(jx, jy);
   const int rl = a.r[l];
   if (rl == 0) return;
@@ -590,7 +594,6 @@ __global__ __launch_bounds__(WG) void k_m2l_assemble(const M2LAssemble a) {
   wg_mfma<double>(ri, p2, p2, [&](int x, int k) { return Ri[x + (size_t)k * ld]; },
                   [&](int k, int y) { return K[k + (size_t)y * p2]; }, [&](int x, int y, double v) { Z[x + y * ld] = v; });
   __syncthreads();
-  T* M = static_cast<T*>(a.M) + ((size_t)i * 36 + sl) * a.sM;
   wg_mfma<double>(ri, rl, p2, [&](int x, int k) { return Z[x + k * ld]; },
                   [&](int k, int y) { return Rl[y + (size_t)k * ld]; }, [&](int x, int y, double v) { M[x + y * ld] = (T)v; });
 }
