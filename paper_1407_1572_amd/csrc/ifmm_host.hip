@@ -361,6 +361,7 @@ struct Op {
   double flops, bytes;  // algorithmic work of the launch
   size_t off2b = 0;
   int ty = 0;  // scalar type code of the descriptors
+  size_t off3 = 0;  // register pivoted QR: blob offset + 1 of the FillCopy whose fills it reads in place
 };
 
 // Profile family of a launch (the elimination steps other than the Schur
@@ -599,7 +600,7 @@ struct Stage {
     const int nr = rrqr_reg_rows(d.n, d.ty);
     return nr > 0 && d.m <= kRrqrRegCols && rrqr_reg_lds(nr, d.kmax, d.ty) <= 144 * 1024;
   }
-  void rrqr(const std::vector<RrqrDesc>& all) {
+  void rrqr(const std::vector<RrqrDesc>& all, size_t fill_off = 0) {
     by_type(all, [&](const std::vector<RrqrDesc>& byt, int ty) {
       const size_t es = ty ? sizeof(float) : sizeof(double);
       std::vector<RrqrDesc> reg[5], grp[2];
@@ -629,6 +630,7 @@ struct Stage {
         for (const auto& d : v) km = std::max(km, d.kmax);
         Op o{OP_RRQR, push(v.data(), v.size() * sizeof(RrqrDesc)), (size_t)(32 * c), (int)v.size(), mm, 2, f, by};
         o.off2b = (size_t)km;
+        o.off3 = fill_off;
         op(o, ty);
       }
       for (int g = 0; g < 2; ++g) {
@@ -704,12 +706,16 @@ struct Stage {
   }
   // Fill copies into the pivoted-QR inputs (records and touches travel in
   // the blob; their pointer fields hold blob offsets + 1, rebased at launch).
+  // Returns the FillCopy's blob offset + 1 (0: none), for the register
+  // pivoted QRs that read the fills of their touches in place.
   template <class T>
-  void fill_copy(FillCopy a, const std::vector<ElimRec>& rec, const std::vector<int>& touch, double bytes) {
-    if (a.nt <= 0) return;
+  size_t fill_copy(FillCopy a, const std::vector<ElimRec>& rec, const std::vector<int>& touch, double bytes) {
+    if (a.nt <= 0) return 0;
     a.rec = reinterpret_cast<const ElimRec*>(push(rec.data(), std::max<size_t>(1, rec.size()) * sizeof(ElimRec)) + 1);
     a.touch = arr(&touch);
-    op({OP_FILLCP, push(&a, sizeof(a)), 0, a.nt, 0, 0, 0.0, bytes}, tcode<T>());
+    const size_t off = push(&a, sizeof(a));
+    op({OP_FILLCP, off, 0, a.nt, 0, 0, 0.0, bytes}, tcode<T>());
+    return off + 1;
   }
   // Far-field weight stacks with device-side block lists (arrays as in
   // touch_xform).
@@ -1251,10 +1257,16 @@ struct Plan final : ifmm_plan {
           else launch_qr(reinterpret_cast<QrDesc*>(d + op.off), op.count, op.off2, op.ty, s);
           break;
         case OP_RRQR:
-          if (op.b == 2)
+          if (op.b == 2) {
+            FillCopy fc{};
+            if (op.off3) {
+              std::memcpy(&fc, hb + (op.off3 - 1), sizeof(fc));
+              fc.rec = reinterpret_cast<const ElimRec*>(d + (reinterpret_cast<uintptr_t>(fc.rec) - 1));
+              fc.touch = reinterpret_cast<const int*>(d + (reinterpret_cast<uintptr_t>(fc.touch) - 1));
+            }
             launch_rrqr_reg(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2, (int)op.off2b,
-                            op.ty, s);
-          else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, (int)op.off2b, op.ty, s);
+                            op.ty, op.off3 ? &fc : nullptr, s);
+          } else if (op.b == 1) launch_rrqr_lds(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.off2, (int)op.off2b, op.ty, s);
           else launch_rrqr_global(reinterpret_cast<RrqrDesc*>(d + op.off), op.count, op.a, (int)op.off2b, op.ty, s);
           break;
         case OP_FORMQRR:
@@ -2047,7 +2059,7 @@ struct Plan final : ifmm_plan {
       Stage own;
       Stage& st = t0 == 0 ? pre : own;
       std::vector<GemmDesc> g;
-      std::vector<int> fc;  // fill copies on the device: (b, sq, nq, col0) per touch
+      std::vector<int> fc;  // fill copies on the device: (b, sq, nq, col0, read in place) per touch
       double fcb = 0;
       std::vector<RrqrDesc> rq;
       for (int t = t0; t < t1; ++t) {
@@ -2060,13 +2072,17 @@ struct Plan final : ifmm_plan {
           if (kPairs.idx[tc.sq][s2] < 0 || !E[tc.b].u[s2].kind) continue;
           col += E[tc.b].u[s2].size;
         }
-        fc.insert(fc.end(), {tc.b, tc.sq, nq, rq0});
-        fcb += 2.0 * sizeof(T) * nq * (double)(col - rq0);
         T* tb = tauA + (size_t)(t - t0) * 2 * kMaxRank;
         rq.push_back({Aw, tb, tb + kMaxRank, d_rank + 2 * t, d_rank + 2 * t + 1, nq, col, L.npad,
                       std::min(nq, r_cap), eps_c, 1, Uh + (size_t)t * L.sU, L.npad});
+        // a register pivoted QR reads this touch's fill blocks in place: no copy
+        const bool in_place = Stage::rrqr_in_regs(rq.back()) && rrqr_reg_reads_fill(rrqr_reg_rows(nq, rq.back().ty), rq.back().ty);
+        if (in_place) rq.back().fill_t = t - t0;
+        else fcb += 2.0 * sizeof(T) * nq * (double)(col - rq0);
+        fc.insert(fc.end(), {tc.b, tc.sq, nq, rq0, in_place ? 1 : 0});
       }
       st.gemm(g);
+      size_t fill_off = 0;
       {
         FillCopy f{};
         f.F = F;
@@ -2077,9 +2093,9 @@ struct Plan final : ifmm_plan {
         f.npair = kPairs.count;
         f.nt = t1 - t0;
         for (int x = 0; x < 81; ++x) f.pair[x] = (signed char)kPairs.idx[x / 9][x % 9];
-        st.fill_copy<T>(f, erec[k][c], fc, fcb);
+        fill_off = st.fill_copy<T>(f, erec[k][c], fc, fcb);
       }
-      st.rrqr(rq);
+      st.rrqr(rq, fill_off);
       for (int t = t0; t < t1; ++t) in_regs[t] = Stage::rrqr_in_regs(rq[t - t0]);
       run(st);
     }

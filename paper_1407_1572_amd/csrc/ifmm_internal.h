@@ -101,6 +101,7 @@ struct RrqrDesc {
   int ty;
   void* Q;  // optional: Q (n x r, r = min(rank, kmax)) of the pivoted steps, ld ldq
   int ldq;
+  int fill_t = -1;  // register kernel: touch t of the launch's FillCopy whose fill columns are read in place
   RrqrDesc() = default;
   template <class U>
   __host__ RrqrDesc(U* a, typename nodeduce<U*>::type tau_, typename nodeduce<U*>::type alpha_, int* rank_,
@@ -365,8 +366,13 @@ void launch_rrqr_global(const RrqrDesc* d, int nd, int max_m, int max_n, int ty,
 // rrqr_reg_rows(ty); LDS holds the kmax x nr reflectors.
 constexpr int kRrqrRegCols = 512;
 int rrqr_reg_rows(int n, int ty);  // smallest register row class >= n, 0 if none
+bool rrqr_reg_reads_fill(int nr, int ty);  // the row class's kernel can read fills in place (fill_t)
 size_t rrqr_reg_lds(int nr, int kmax, int ty);
-void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, hipStream_t s);
+// fc (host copy, pointers rebased; or null): the fills of descriptors with
+// fill_t >= 0 are read from their blocks (columns from col0 on) instead of A.
+struct FillCopy;
+void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, const FillCopy* fc,
+                     hipStream_t s);
 // Q of RrqrDescs whose pivoted QR ran in the LDS / in-place kernels (rank and
 // steps read on the device); every n <= max_n <= 512, kmax <= max_kmax.
 void launch_formq_rr(const RrqrDesc* d, int nd, int max_n, int max_kmax, int ty, hipStream_t s);
@@ -385,7 +391,7 @@ void launch_gj_reg(const InvDesc* d, int nd, int max_m, Status* st, hipStream_t 
 // col0 + (sizes of the earlier such units) of A + t per (ld npad).
 struct FillCopy {
   const ElimRec* rec;
-  const int* touch;  // 4 ints per touch
+  const int* touch;  // 5 ints per touch: b, sq, nq, col0, and 1 where its pivoted QR reads the fills in place
   const void* F;
   void* A;
   size_t per;

@@ -613,7 +613,8 @@ __global__ __launch_bounds__(WG) void k_rank_finalize(const RankFin a) {
 template <class T>
 __global__ __launch_bounds__(WG) void k_fill_copy(const FillCopy a) {
   const int t = blockIdx.x, s2 = blockIdx.y;
-  const int b = a.touch[4 * t], sq = a.touch[4 * t + 1], nq = a.touch[4 * t + 2], col0 = a.touch[4 * t + 3];
+  if (a.touch[5 * t + 4]) return;  // its pivoted QR reads the fill blocks in place
+  const int b = a.touch[5 * t], sq = a.touch[5 * t + 1], nq = a.touch[5 * t + 2], col0 = a.touch[5 * t + 3];
   const ElimRec& r = a.rec[b];
   const int pidx = a.pair[9 * sq + s2];
   if (pidx < 0 || !r.kind[s2]) return;
@@ -1358,8 +1359,15 @@ __global__ __launch_bounds__(NT) void k_rrqr(const RrqrDesc* __restrict__ descs)
 // Q = H_0 ... H_{kk-1} [I_r; 0] (kk = min(r, steps)), column j negated where
 // alpha_j < 0, is formed by the threads of its columns from the LDS
 // reflectors.
+// FILL: the instantiations that may read a touch's fill columns in place
+// (FP32 columns of up to 96 rows; the others keep the plain column loads,
+// whose register allocation their main loop runs best with).  FP32 columns
+// of 96 rows are held to 168 registers, three waves per SIMD.
 template <class T, int NR>
-__global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ descs) {
+constexpr bool kRrqrFill = sizeof(T) == 4 && NR <= 96;
+template <class T, int NR>
+__global__ __launch_bounds__(512, (sizeof(T) == 4 && NR == 96) ? 3 : 1) void k_rrqr_reg(
+    const RrqrDesc* __restrict__ descs, const FillCopy fc) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ T xs[NR], mk[NR];
   __shared__ T tau_s[kMaxRank], alpha_s[kMaxRank];
@@ -1381,10 +1389,32 @@ __global__ __launch_bounds__(512) void k_rrqr_reg(const RrqrDesc* __restrict__ d
   // compiler barrier every CH rows keeps the LDS reads of u from being
   // hoisted ahead of their FMAs all at once
   constexpr int CH = (sizeof(T) == 8 && NR > 64) ? 16 : NR;
+  // column c: from A, or (fill_t >= 0, c >= col0) from the fill block of the
+  // unit it belongs to, as the fill copy would have placed it
+  const T* src = gA + (size_t)c * lda;
+  if (kRrqrFill<T, NR> && live && d.fill_t >= 0 && fc.touch) {
+    const int* tc = fc.touch + 5 * d.fill_t;
+    const int b = tc[0], sq = tc[1], col0 = tc[3];
+    if (c >= col0) {
+      const ElimRec& r = fc.rec[b];
+      src = nullptr;
+      int cs = col0;
+      for (int u = 0; u < 9; ++u) {
+        const int pidx = fc.pair[9 * sq + u];
+        if (pidx < 0 || !r.kind[u]) continue;
+        if (c < cs + r.size[u]) {
+          src = static_cast<const T*>(fc.F) + ((size_t)b * fc.npair + pidx) * fc.fpad * fc.fpad +
+                (size_t)(c - cs) * fc.fpad;
+          break;
+        }
+        cs += r.size[u];
+      }
+    }
+  }
   T q0 = 0;
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
-    col[i] = (live && i < n) ? gA[i + (size_t)c * lda] : T(0);
+    col[i] = (live && src && i < n) ? src[i] : T(0);
     q0 = fma(col[i], col[i], q0);
   }
   T nrm = sqrt(q0);
@@ -2644,6 +2674,8 @@ void launch_rrqr_lds(const RrqrDesc* d, int nd, size_t lds, int max_n, int ty, h
   else rrqr_go<double, true>(d, nd, lds, max_n, s);
 }
 
+bool rrqr_reg_reads_fill(int nr, int ty) { return ty && nr <= 96; }
+
 int rrqr_reg_rows(int n, int ty) {
   if (n <= 32) return 32;
   if (n <= 64) return 64;
@@ -2658,29 +2690,32 @@ size_t rrqr_reg_lds(int nr, int kmax, int ty) {
 }
 
 template <class T, int NR>
-void rrqr_reg_go(const RrqrDesc* d, int nd, int nt, size_t lds, hipStream_t s) {
+void rrqr_reg_go(const RrqrDesc* d, int nd, int nt, size_t lds, const FillCopy& fc, hipStream_t s) {
   // the kernel's static LDS is a few KiB: raise the dynamic limit to what
   // this launch asks for, when above the default
   if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_rrqr_reg<T, NR>));
-  hipLaunchKernelGGL((k_rrqr_reg<T, NR>), dim3(nd), dim3(nt), lds, s, d);
+  hipLaunchKernelGGL((k_rrqr_reg<T, NR>), dim3(nd), dim3(nt), lds, s, d, fc);
 }
 
-void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, hipStream_t s) {
+void launch_rrqr_reg(const RrqrDesc* d, int nd, int max_m, int nr, int max_kmax, int ty, const FillCopy* fcp,
+                     hipStream_t s) {
   if (nd <= 0 || max_m <= 0) return;
   const int nt = std::min(kRrqrRegCols, (max_m + WAVE - 1) / WAVE * WAVE);
   const size_t lds = rrqr_reg_lds(nr, max_kmax, ty);
+  FillCopy fc{};
+  if (fcp) fc = *fcp;
   if (ty) {
     switch (nr) {
-      case 32: rrqr_reg_go<float, 32>(d, nd, nt, lds, s); break;
-      case 64: rrqr_reg_go<float, 64>(d, nd, nt, lds, s); break;
-      case 96: rrqr_reg_go<float, 96>(d, nd, nt, lds, s); break;
-      case 128: rrqr_reg_go<float, 128>(d, nd, nt, lds, s); break;
+      case 32: rrqr_reg_go<float, 32>(d, nd, nt, lds, fc, s); break;
+      case 64: rrqr_reg_go<float, 64>(d, nd, nt, lds, fc, s); break;
+      case 96: rrqr_reg_go<float, 96>(d, nd, nt, lds, fc, s); break;
+      case 128: rrqr_reg_go<float, 128>(d, nd, nt, lds, fc, s); break;
     }
   } else {
     switch (nr) {
-      case 32: rrqr_reg_go<double, 32>(d, nd, nt, lds, s); break;
-      case 64: rrqr_reg_go<double, 64>(d, nd, nt, lds, s); break;
-      case 96: rrqr_reg_go<double, 96>(d, nd, nt, lds, s); break;
+      case 32: rrqr_reg_go<double, 32>(d, nd, nt, lds, fc, s); break;
+      case 64: rrqr_reg_go<double, 64>(d, nd, nt, lds, fc, s); break;
+      case 96: rrqr_reg_go<double, 96>(d, nd, nt, lds, fc, s); break;
     }
   }
 }
