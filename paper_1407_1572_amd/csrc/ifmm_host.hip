@@ -1074,6 +1074,32 @@ struct ifmm_plan {
 
 namespace {
 
+// A second stream forked from s (it starts after the work queued on s so
+// far) and joined back into s when the scope ends: s then waits for it, and
+// the stream is released (its queued work still runs).
+struct SideStream {
+  hipStream_t main, s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  explicit SideStream(hipStream_t m) : main(m) {
+    HIP_OK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_OK(hipEventRecord(fork, main));
+    HIP_OK(hipStreamWaitEvent(s, fork, 0));
+  }
+  ~SideStream() {
+    if (s) {
+      (void)hipEventRecord(join, s);
+      (void)hipStreamWaitEvent(main, join, 0);
+      (void)hipStreamDestroy(s);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+};
+
 template <class T>
 struct Plan final : ifmm_plan {
   static constexpr bool kF32 = std::is_same<T, float>::value;
@@ -1572,8 +1598,6 @@ struct Plan final : ifmm_plan {
     Lf.L = dalloc<T>(s, Lf.sL * 9 * Lf.nc);
     Lf.U = dalloc<T>(s, Lf.sU * Lf.nc);
     Lf.Dinv = dalloc<double>(s, Lf.sD * Lf.nc);
-    HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, s));
-    HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, s));
     // The product's near field is stored once (FP64, every leaf's row block
     // over its neighbours' points) when it fits kNearStoreMax; the refinement
     // sweeps then read it instead of evaluating the kernel again.
@@ -1598,8 +1622,16 @@ struct Plan final : ifmm_plan {
         upload_pinned(d_near_off, up_near_off, up_near_off.size());
       }
     }
+    // The clearing of the leaf fill slots and the near field (P blocks and
+    // the stored FP64 near field) run on a second stream beside the basis
+    // QRs and the M2L assembly below, whose latency-bound launches leave
+    // most of the GPU idle; the factorisation starts after both.
+    SideStream side(s);
+    HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, side.s));
+    HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, side.s));
     launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
-                      Lf.sP, Lf.npad, nmax, d_near, d_near_off, s);
+                      Lf.sP, Lf.npad, nmax, d_near, d_near_off, side.s);
+    HIP_OK(hipGetLastError());
     // Interpolation and orthonormalisation in FP64; an FP32 factor takes the
     // rounded bases.
     double* U64;
