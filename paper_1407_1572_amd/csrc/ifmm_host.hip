@@ -1075,26 +1075,41 @@ struct ifmm_plan {
 namespace {
 
 // A second stream forked from s (it starts after the work queued on s so
-// far) and joined back into s when the scope ends: s then waits for it, and
-// the stream is released (its queued work still runs).
+// far) and joined back into s when the scope ends (s then waits for it).
+// The stream is one per device, created on first use and kept until the
+// process ends (creating one per factorisation cost ~0.3 ms of host time);
+// calls that share it stay correct (their forks and joins are events), only
+// their side work serialises.  enabled = false: everything stays on s.
 struct SideStream {
-  hipStream_t main, s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  explicit SideStream(hipStream_t m) : main(m) {
+  hipStream_t main, s;
+  hipEvent_t join = nullptr;
+  SideStream(hipStream_t m, bool enabled) : main(m), s(m) {
+    if (!enabled) return;
+    static std::mutex mu;
+    static std::unordered_map<int, hipStream_t>* per_dev = new std::unordered_map<int, hipStream_t>();  // never destroyed
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    hipStream_t side = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      hipStream_t& st = (*per_dev)[dev];
+      if (!st) HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      side = st;
+    }
+    hipEvent_t fork = nullptr;
     HIP_OK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    const hipError_t e1 = hipEventRecord(fork, main);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(side, fork, 0) : e1;
+    (void)hipEventDestroy(fork);
+    HIP_OK(e2);
     HIP_OK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    HIP_OK(hipEventRecord(fork, main));
-    HIP_OK(hipStreamWaitEvent(s, fork, 0));
+    s = side;
   }
   ~SideStream() {
-    if (s) {
-      (void)hipEventRecord(join, s);
-      (void)hipStreamWaitEvent(main, join, 0);
-      (void)hipStreamDestroy(s);
-    }
-    if (fork) (void)hipEventDestroy(fork);
-    if (join) (void)hipEventDestroy(join);
+    if (!join) return;
+    (void)hipEventRecord(join, s);
+    (void)hipStreamWaitEvent(main, join, 0);
+    (void)hipEventDestroy(join);
   }
   SideStream(const SideStream&) = delete;
   SideStream& operator=(const SideStream&) = delete;
@@ -1625,8 +1640,9 @@ struct Plan final : ifmm_plan {
     // The clearing of the leaf fill slots and the near field (P blocks and
     // the stored FP64 near field) run on a second stream beside the basis
     // QRs and the M2L assembly below, whose latency-bound launches leave
-    // most of the GPU idle; the factorisation starts after both.
-    SideStream side(s);
+    // most of the GPU idle, for problems large enough to fill both; the
+    // factorisation starts after both.
+    SideStream side(s, N >= ((int64_t)1 << 18));
     HIP_OK(hipMemsetAsync(Lf.Qm, 0, sizeof(T) * Lf.sQ * 9 * Lf.nc, side.s));
     HIP_OK(hipMemsetAsync(Lf.L, 0, sizeof(T) * Lf.sL * 9 * Lf.nc, side.s));
     launch_near_field(d_pts, d_leaf_start, d_leaf_n, d_nbr9_leaf, nleaf, kf, d_diag, Lf.P, kF32 ? 1 : 0,
