@@ -315,7 +315,11 @@ struct PhaseScope {
   ~PhaseScope() { c.leave(prev); }
 };
 
-constexpr int kInvNb = 32;  // panel width of the blocked pivot inverse
+// Panel width of the blocked pivot inverse: 64 columns (half the panel,
+// row-swap and update launches of 32) while the panel fits the registers
+// of the panel kernel (m <= 512), else 32.
+constexpr int kInvNb = 64;
+inline int inv_panel_width(int max_m) { return max_m <= 512 ? 64 : 32; }
 // Largest stored near field of the FMM product (bytes); beyond it the
 // product evaluates the near-field kernel on the fly.
 constexpr size_t kNearStoreMax = (size_t)16 << 30;
@@ -818,8 +822,10 @@ struct Stage {
         }
       flops += fp;
       op({OP_GJPANEL, o, (size_t)(uintptr_t)piv, nd, mm, j0, fp, bp}, 0);
+      ops.back().off3 = (size_t)nb;
       op({OP_GJREST, o, (size_t)(uintptr_t)tmp, nd, mm, j0, 0.0, 0.0}, 0);
       ops.back().off2b = (size_t)(uintptr_t)piv;
+      ops.back().off3 = (size_t)nb;
       std::vector<GemmDesc> g;
       for (int b = 0; b < nd; ++b) {
         const InvDesc& d = v[b];
@@ -1415,14 +1421,14 @@ struct Plan final : ifmm_plan {
         }
         case OP_XFORM: break;  // family 2 has no launches
         case OP_GJREG: launch_gj_reg(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, d_status, s); break;
-        case OP_GJPANEL:
-          launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
+        case OP_GJPANEL:  // off3: the panel width
+          launch_gj_panel(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, (int)op.off3,
                           reinterpret_cast<int*>(op.off2), op.a, d_status, s);
           break;
         case OP_GJREST:
-          launch_gj_rest(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, kInvNb,
+          launch_gj_rest(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a, op.b, (int)op.off3,
                          reinterpret_cast<int*>(op.off2b), op.a, reinterpret_cast<double*>(op.off2),
-                         (size_t)kInvNb * op.a, s);
+                         op.off3 * (size_t)op.a, s);
           break;
         case OP_GJUNPERM:
           launch_gj_unpermute(reinterpret_cast<InvDesc*>(d + op.off), op.count, op.a,
@@ -1458,7 +1464,7 @@ struct Plan final : ifmm_plan {
     for (const auto& d : big) mm = std::max(mm, d.m);
     double* tmp = wsInvT.need((size_t)big.size() * kInvNb * mm, s);
     int* piv = wsInvP.need<int>((size_t)big.size() * mm + 1, s);
-    st.inv_blocked(big, piv, tmp, kInvNb);
+    st.inv_blocked(big, piv, tmp, inv_panel_width(mm));
   }
 
   // ---------------------------------------------------------------- tree

@@ -2821,6 +2821,12 @@ void launch_gj_panel(const InvDesc* d, int nd, int max_m, int j0, int nb, int* p
     else hipLaunchKernelGGL((k_gj_panel_reg<12, 4>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
     return;
   }
+  if (nb <= 64 && max_m <= 512) {
+    if (max_m <= 256) hipLaunchKernelGGL((k_gj_panel_reg<4, 8>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    else if (max_m <= 384) hipLaunchKernelGGL((k_gj_panel_reg<6, 8>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    else hipLaunchKernelGGL((k_gj_panel_reg<8, 8>), dim3(nd), dim3(512), 0, s, d, j0, nb, piv, ldp, st);
+    return;
+  }
   const size_t lds = sizeof(double) * (size_t)max_m * (nb + 1);
   if (lds <= 150 * 1024) {
     if (lds > 64 * 1024) allow_lds(reinterpret_cast<const void*>(k_gj_panel<true>));
