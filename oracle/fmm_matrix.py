@@ -7,7 +7,7 @@ bases, taken at the unique level where the two ancestor clusters are well
 separated while their parents are neighbours (i.e. where one lies in the
 other's interaction list).  The bases are the Chebyshev ones of Section 5.
 
-Diagonal (readings listed in the design doc):
+Diagonal (readings where the paper is silent):
 * "rowsum": A_ii = c0 + sum_{j != i} A~_ij  (diagonally dominant 1/r systems;
   the sum runs over the FMM matrix so that oracle and solver factor the same
   matrix);

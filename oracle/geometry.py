@@ -5,7 +5,7 @@ cluster i at level k": N_i = neighbours including self, I_i = children of the
 parent's neighbours that are well separated); Section 2.2 figure of the 2D
 FMM matrix (Morton / Z ordering).
 
-Readings taken where the paper is silent (listed in the design doc):
+Readings taken where the paper is silent:
 * depth: kappa = max(2, ceil(log4(N / leaf_size))), i.e. the mean leaf
   occupancy is at most leaf_size;
 * a point's box index is floor((x - lo) / size * 2^k) clamped to 2^k - 1;

@@ -25,7 +25,7 @@ Block names used below (level k, clusters i, j):
   (row M2L(i) carries UP[i] z_parent; y_parent = sum_c VP[c]^T y_c).
 Row M2L(i) reads  -z_i + sum_l M[i,l] y_l + sum_j L[i,j] x_j + UP[i] z_par = c_i.
 
-Readings where the paper is silent (all listed in the design doc):
+Readings where the paper is silent:
 * bases are Chebyshev interpolation orthonormalised exactly by Householder QR
   (A~ unchanged); non-leaf ranks start at min(n_i, p^2);
 * elimination order: 9 colours, and inside a level each colour runs three
